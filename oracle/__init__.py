@@ -1,0 +1,28 @@
+"""CPU oracle for the lifted layer-splitting step -- TEST INFRASTRUCTURE ONLY.
+
+Plain, slow, FP64 NumPy/SciPy implementation of what the hot path computes,
+written from Wang, Chen, Zhou & Zhou, "Layer-splitting methods for
+time-dependent Schroedinger equations of incommensurate systems"
+(arXiv 2103.14897).  Only the test-suite, the smoke check and the CPU-baseline
+leg of the benchmark may import it; the product path (the HIP library and its
+Python binding) never does and shares no code with it.
+
+Modules
+-------
+lifted       lattices, reciprocal lattices, the lifted index set I, fibres,
+             and the dense lifted matrices D, V^1, V^2 (Secs. 2-3, eqs. 3.4-3.6)
+splitting    fibre Hamiltonians, exact fibre propagators via eigh, the kinetic
+             phase, and the Lie / Strang layer-splitting compositions
+             (Sec. 4.2, App. A)
+observables  mass (eq. 2.3 via orthonormality 3.1), energy (eq. 2.4), fibre masses
+reference    brute-force exponentials of the full lifted Hamiltonian and a
+             direct commensurate-supercell computation used to pin the rest
+
+Parity status
+-------------
+Every function here is pinned by tests in ``tests/test_oracle_*.py`` against
+closed forms, brute force, invariants or an independent supercell computation,
+except where a function's docstring says "parity unpinned".
+"""
+
+from . import lifted, splitting, observables, reference  # noqa: F401
