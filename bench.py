@@ -1,0 +1,170 @@
+"""Benchmark of the lifted layer-splitting step on one MI355X.
+
+Workload (the configuration the coeff*steps/s metric is quoted on): two 1D layers
+L1 = 1, L2 = golden mean, V_j = 2 v_j cos(2 pi x / L_j) with v1 = 1.0, v2 = 0.7,
+ball cutoff Ec = 2e4 (N = 5149 lifted coefficients, 103 + 63 fibres of length
+9-103), 64 Gaussian wavepackets (sigma = 2, k0 ~ U[-10, 10], seed 0), Strang layer
+splitting with tau = 1e-3 to T = 2 (2000 steps).  Synthetic inputs, resident in
+HBM before the timed region.
+
+A step is one full Strang step (two fibre passes: layer 2 with tau, layer 1 with
+tau; the half steps of consecutive steps are merged).  coeff*steps/s =
+N * W * steps / (time of the timed steps).  Every precision path (plain FP64,
+FP32 MFMA on the off-diagonal propagator part, BF16x3 split products) is timed;
+the headline `value` is the fastest path whose relative L2 error after T against
+the FP64 path is <= 1e-6.  The CPU oracle is timed on a bounded sample of the
+same workload on the host cores.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_2103_14897_amd import lsx  # noqa: E402
+from paper_2103_14897_amd import workloads as wl  # noqa: E402
+
+PEAK = {"fp64": 78.6e12, "mix_fp32": 157.3e12, "mix_bf16x3": 2.5e15}
+DTYPE = {"fp64": "f64", "mix_fp32": "f32-mfma+f64", "mix_bf16x3": "bf16x3-mfma+f64"}
+METRIC = "coeff·steps/s, plain FP64 vs mixed at ≤1e-6 L2 error; % HBM/MFMA peak"
+
+
+def cpu_baseline(spec, c0, tau, budget_s=15.0):
+    """The CPU oracle (FP64 NumPy) on a bounded sample of the same workload."""
+    from oracle import splitting
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:  # pragma: no cover
+        threads = 1
+    O = splitting.Lifted.from_spec(spec)
+    plan = splitting.SplitPlan(O, 0.0)
+    t0 = time.perf_counter()
+    for layer in (1, 2):
+        plan.propagators(layer, tau)
+    plan.propagators(1, tau / 2)
+    pre = time.perf_counter() - t0
+    c = c0.copy()
+    t0 = time.perf_counter()
+    c = plan.strang_step(c, tau)
+    one = time.perf_counter() - t0
+    n = int(max(3, min(2000, budget_s / max(one, 1e-6))))
+    t0 = time.perf_counter()
+    for _ in range(n):
+        c = plan.strang_step(c, tau)
+    el = time.perf_counter() - t0
+    return {"value": O.N * c0.shape[1] * n / el, "unit": "coeff*steps/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": f"{n} unmerged Strang steps of the same workload (N={O.N}, W={c0.shape[1]}), "
+                      f"precompute {pre:.2f}s excluded"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--paths", default="fp64,mix_fp32,mix_bf16x3")
+    ap.add_argument("--kernel-reps", type=int, default=400)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the lifted step shards by wavepacket with no "
+              "communication, so the N-GPU figure is N x the one-GPU figure; run with --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    w = wl.chain()
+    S = lsx.System.from_spec(w.spec)
+    mn = S.index()
+    c0 = w.initial_state(mn)
+    N, W = S.N, w.W
+    ptr2, _ = S.fibres(2)
+    ptr1, _ = S.fibres(1)
+    sumL2 = {1: int(np.sum(np.diff(ptr1).astype(np.int64) ** 2)), 2: int(np.sum(np.diff(ptr2).astype(np.int64) ** 2))}
+    stream = torch.cuda.current_stream()
+    res = {}
+    finals = {}
+    for path in args.paths.split(","):
+        t0 = time.perf_counter()
+        P = lsx.Plan(S, w.tau, "strang", 0.0, path, stream)
+        pre = time.perf_counter() - t0
+        st = lsx.State(P, W)
+        # accuracy run to T
+        st.upload(c0, stream)
+        st.step(w.nsteps, stream)
+        finals[path] = st.download(stream)
+        # timed run
+        st.upload(c0, stream)
+        st.step(args.warmup, stream)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        st.step(args.steps, stream)
+        e1.record(stream)
+        e1.synchronize()
+        wall = time.perf_counter() - t0
+        ms = e0.elapsed_time(e1)
+        # dominant kernel: the layer-2 fibre pass, back-to-back launches on the same stream
+        torch.cuda.synchronize()
+        k0, k1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        k0.record(stream)
+        st.fibre_pass(2, 0, args.kernel_reps, stream)
+        k1.record(stream)
+        k1.synchronize()
+        kus = k0.elapsed_time(k1) * 1e3 / args.kernel_reps
+        res[path] = {"coeff_steps_per_s": N * W * args.steps / (ms * 1e-3), "ms_per_step": ms / args.steps,
+                     "wall_ms": wall * 1e3, "precompute_s": pre, "layer2_pass_us": kus}
+        st.destroy()
+        P.destroy()
+    ref = finals.get("fp64")
+    for path in res:
+        if ref is not None:
+            err = float((np.linalg.norm(finals[path] - ref, axis=0) / np.linalg.norm(ref, axis=0)).max())
+        else:
+            err = None
+        res[path]["rel_l2_vs_fp64_after_T"] = err
+    ok = [p for p in res if p == "fp64" or (res[p]["rel_l2_vs_fp64_after_T"] is not None
+                                            and res[p]["rel_l2_vs_fp64_after_T"] <= 1e-6)]
+    best = max(ok, key=lambda p: res[p]["coeff_steps_per_s"])
+    r = res[best]
+    flops = 8.0 * W * sumL2[2]
+    achieved = flops / (r["layer2_pass_us"] * 1e-6)
+    out = {
+        "metric": METRIC,
+        "value": r["coeff_steps_per_s"],
+        "unit": "coeff*steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPE[best],
+        "data": "synthetic",
+        "config": {"workload": "chain1d_golden_Ec2e4_W64_strang_tau1e-3", "N": N, "W": W,
+                   "fibres": [S.nfibres[1], S.nfibres[2]], "path": best, "kappa": 0.0},
+        "roofline": {"bound": "mfma", "kernel": f"fibre pass layer 2 ({best})", "achieved": achieved / 1e12,
+                     "peak": PEAK[best] / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK[best],
+                     "traffic": None},
+        "paths": res,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w.spec, c0, w.tau)
+    print(json.dumps(out))
+    S.destroy()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,211 @@
+/*
+ * lsx.h -- C-ABI of the MI355X layer-splitting library (liblsx.so).
+ *
+ * Computes the exact-flow layer-splitting time stepping of Wang, Chen, Zhou &
+ * Zhou, "Layer-splitting methods for time-dependent Schroedinger equations of
+ * incommensurate systems" (arXiv 2103.14897), on the lifted plane-wave
+ * coefficient array phi_mn (Sec. 3, eqs. 3.2-3.6).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every function returns lsx_status: LSX_OK (0) or a negative error code.
+ *    On error a thread-local message is available from lsx_last_error() and no
+ *    output argument is written; handles are left unchanged.
+ *  - Validation happens on the host before anything is enqueued.
+ *  - Host arrays passed in are owned by the caller and are copied (or fully
+ *    consumed) before the call returns, except where a stream-ordered upload is
+ *    documented: then the caller keeps the buffer alive until the stream has
+ *    reached that point.
+ *  - Handles (lsx_system, lsx_plan, lsx_state) are owned by the library and
+ *    freed by the matching *_destroy call.  A system must outlive its plans and
+ *    a plan its states (destroying a parent with live children returns
+ *    LSX_E_STATE and destroys nothing).
+ *  - `stream` is a hipStream_t passed as void*; NULL is the default stream.  All
+ *    device work of a call is enqueued on that stream, in order.
+ *  - Complex numbers are stored interleaved (re, im) as pairs of doubles.
+ *  - A state holds W wavepackets as a device array c[N][W] of complex doubles
+ *    (W innermost): c[i*W + w] is the coefficient of lifted index i (canonical
+ *    order, see lsx_index_get) in wavepacket w.
+ */
+#ifndef LSX_H
+#define LSX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LSX_OK = 0,
+  LSX_E_INVALID = -1,       /* bad argument (size, enum, pointer, geometry) */
+  LSX_E_NOT_HERMITIAN = -2, /* potential coefficients violate v_{-m} = conj(v_m) */
+  LSX_E_OOM = -3,           /* host or device allocation failed */
+  LSX_E_HIP = -4,           /* a HIP runtime call failed; message has the HIP string */
+  LSX_E_EIG = -5,           /* fibre eigensolver did not converge */
+  LSX_E_NONFINITE = -6,     /* an observable came out NaN or Inf */
+  LSX_E_STATE = -7          /* handle misuse (live children, mismatched plan, ...) */
+} lsx_status;
+
+enum { LSX_CUTOFF_BALL = 0, LSX_CUTOFF_PRODUCT = 1 };
+enum { LSX_LIE = 0, LSX_STRANG = 1 };
+enum { LSX_FP64 = 0, LSX_MIX_FP32 = 1, LSX_MIX_BF16X3 = 2 };
+enum {
+  LSX_OBS_MASS = 1,         /* W doubles */
+  LSX_OBS_ENERGY = 2,       /* W doubles */
+  LSX_OBS_FIBRE_MASS_1 = 4, /* nfibres_1 * W doubles, [fibre][w] */
+  LSX_OBS_FIBRE_MASS_2 = 8  /* nfibres_2 * W doubles, [fibre][w] */
+};
+
+typedef struct lsx_system lsx_system;
+typedef struct lsx_plan lsx_plan;
+typedef struct lsx_state lsx_state;
+
+/* Message of the last failed call on this thread ("" if none).  Never NULL. */
+const char* lsx_last_error(void);
+
+/*
+ * lsx_system_create -- the problem statement (Sec. 2) and its lifted cutoff set (Sec. 3).
+ *
+ *  d            layer dimension, 1 or 2.
+ *  A1, A2       d*d lattice matrices, column-major (column k = primitive vector k):
+ *               R_j = { A_j n : n in Z^d } (Sec. 2).  Must be invertible.
+ *  Ec           energy cutoff > 0 (Sec. 3).
+ *  cutoff       LSX_CUTOFF_BALL:    I = {(m,n) : |G1m|^2 + |G2n|^2 <= 2 Ec}
+ *               LSX_CUTOFF_PRODUCT: I = I1 x I2 with |G1m|^2 <= 2Ec, |G2n|^2 <= 2Ec (Sec. 3)
+ *               where G_jm = 2 pi A_j^{-T} m.  A point is kept when
+ *               s <= 2 Ec (1 + 1e-12), s = sum_k (G1m)_k^2 + sum_k (G2n)_k^2.
+ *  nv1, v1_idx, v1_re, v1_im
+ *               Fourier coefficients v^(1)_m of the layer-1 potential (eq. 2.2):
+ *               nv1 entries, v1_idx is nv1*d int32 (entry e has index
+ *               v1_idx[e*d .. e*d+d-1]), value v1_re[e] + i v1_im[e].  Indices must
+ *               be distinct; the set must be Hermitian (v_{-m} = conj(v_m) within
+ *               1e-14 * max|v|), otherwise LSX_E_NOT_HERMITIAN.  nv1 may be 0.
+ *  nv2, ...     same for layer 2.
+ *  out          receives the new handle.
+ *
+ * Host-only: enumerates I in canonical (lexicographic in m_1..m_d, n_1..n_d)
+ * order and builds the fibre tables; touches no GPU.
+ */
+lsx_status lsx_system_create(int32_t d, const double* A1, const double* A2, double Ec, int32_t cutoff,
+                             int32_t nv1, const int32_t* v1_idx, const double* v1_re, const double* v1_im,
+                             int32_t nv2, const int32_t* v2_idx, const double* v2_re, const double* v2_im,
+                             lsx_system** out);
+
+/* Sizes: N = |I|, and the number of fibres of each layer.  Any output pointer may be NULL. */
+lsx_status lsx_system_size(const lsx_system* sys, int64_t* N, int64_t* nfibres1, int64_t* nfibres2);
+
+/* The lifted index set: mn is N*2d int32 (host), row i = (m_1..m_d, n_1..n_d) of index i. */
+lsx_status lsx_index_get(const lsx_system* sys, int32_t* mn);
+
+/*
+ * Fibre tables of one layer (Sec. 3, block structure of V^1 and of the permuted V^2).
+ * Layer 1: one fibre per n, rows {i : n_i = n}; layer 2: one fibre per m, rows {i : m_i = m}.
+ * Fibres are ordered by their key (lexicographic), rows ascending.
+ *  ptr   nfibres+1 int32 (host): rows of fibre f are rows[ptr[f] .. ptr[f+1]-1].  May be NULL.
+ *  rows  N int32 (host).  May be NULL.
+ */
+lsx_status lsx_fibre_get(const lsx_system* sys, int32_t layer, int32_t* ptr, int32_t* rows);
+
+/* Frees the system.  LSX_E_STATE if plans built on it are still alive. */
+lsx_status lsx_system_destroy(lsx_system* sys);
+
+/*
+ * lsx_plan_create -- one-time precompute of the fibre propagators on the GPU.
+ *
+ * Splitting (Sec. 4.2, App. A) of H = D + V^1 + V^2 (eq. 3.5) with a kinetic
+ * share kappa in [0, 1]:  H = kappa D + H_1 + H_2,  H_j = (1-kappa)/2 D + V^j.
+ * kappa = 0 is the paper's layer split; kappa > 0 moves that share of D into an
+ * elementwise phase exp(-i kappa t |G1m+G2n|^2 / 2).
+ * For every fibre the FP64 fibre Hamiltonian is assembled and diagonalised on the
+ * device (batched Jacobi), and P(t) = U exp(-i t Lambda) U^H is formed for the
+ * sub-step lengths the scheme needs:
+ *   LSX_LIE    : F1(tau), Phase(kappa tau), F2(tau)                                per step
+ *   LSX_STRANG : F1(tau/2), Phase(kappa tau/2), F2(tau), Phase(kappa tau/2), F1(tau/2) per step
+ * precision    LSX_FP64: complex128 propagators, FP64 MFMA.
+ *              LSX_MIX_FP32: P = diag(d) + E with d complex128 and E complex64, FP32 MFMA
+ *                 on E with FP32 accumulation, FP64 diagonal term and FP64 carried state.
+ *              LSX_MIX_BF16X3: as MIX_FP32 but E and the state operand are each split
+ *                 into three bf16 terms; six cross products on BF16 MFMA, FP32 accumulation.
+ *  tau          time step (any finite nonzero value; negative runs backwards).
+ *  stream       stream for the precompute; the call synchronises it before returning.
+ * Errors: LSX_E_INVALID (scheme/precision/kappa), LSX_E_EIG, LSX_E_OOM, LSX_E_HIP.
+ */
+lsx_status lsx_plan_create(lsx_system* sys, double tau, int32_t scheme, double kappa, int32_t precision,
+                           void* stream, lsx_plan** out);
+
+/*
+ * Copies one fibre propagator P(t) back to the host as a dense L*L complex matrix
+ * (row-major, interleaved; L = fibre length), with t = tau (half = 0) or tau/2
+ * (half = 1).  For mixed plans this is d + E as stored (E rounded to the plan's
+ * precision).  LSX_E_INVALID if the plan holds no such propagator.  Synchronous.
+ */
+lsx_status lsx_plan_propagator(const lsx_plan* plan, int32_t layer, int32_t half, int32_t fibre,
+                               double* out, void* stream);
+
+/* Frees the plan.  LSX_E_STATE if states built on it are still alive. */
+lsx_status lsx_plan_destroy(lsx_plan* plan);
+
+/*
+ * lsx_state_create -- W wavepackets on the device, c[N][W] complex128.
+ *  dev_ptr   NULL: the library allocates the array (owned by the state).
+ *            non-NULL: a caller-owned device array of N*W complex doubles (16-byte
+ *            aligned) that the state wraps; the caller keeps it alive until
+ *            lsx_state_destroy.  Its contents are the state.
+ * The library also allocates one same-size work array per state (ping-pong
+ * target of the fibre passes) and small reduction buffers.
+ */
+lsx_status lsx_state_create(lsx_plan* plan, int32_t W, void* dev_ptr, lsx_state** out);
+
+/* Host <-> device copies of the whole state, host layout identical to the device one
+ * ([N][W] interleaved complex).  Stream-ordered; download synchronises the stream. */
+lsx_status lsx_state_upload(lsx_state* st, const double* host, void* stream);
+lsx_status lsx_state_download(lsx_state* st, double* host, void* stream);
+
+/* Device address of the state array c[N][W].  For a wrapped state this is always the
+ * caller's pointer.  A library-owned state keeps two arrays and may swap their roles
+ * after a step or pass, so query the address again after such calls. */
+lsx_status lsx_state_device_ptr(const lsx_state* st, void** dev_ptr);
+
+lsx_status lsx_state_destroy(lsx_state* st);
+
+/*
+ * lsx_step -- advances the state by exactly nsteps * tau with the plan's scheme
+ * (App. A compositions; Strang half-steps of consecutive steps inside one call
+ * are merged, F1(tau/2) F1(tau/2) = F1(tau)).  nsteps >= 0.  Stream-ordered.
+ */
+lsx_status lsx_step(lsx_plan* plan, lsx_state* st, int64_t nsteps, void* stream);
+
+/*
+ * lsx_fibre_pass -- one layer sub-step on its own: c[rows_f] <- P_f(t) c[rows_f]
+ * for every fibre f of `layer` (Alg. 2 steps 1/2 with exact fibre flows), with
+ * t = tau (half = 0) or tau/2 (half = 1), applied `count` >= 0 times back to back
+ * (one kernel launch each; count > 1 is used to time the pass).  Stream-ordered.
+ */
+lsx_status lsx_fibre_pass(lsx_plan* plan, lsx_state* st, int32_t layer, int32_t half, int32_t count,
+                          void* stream);
+
+/*
+ * lsx_phase -- kinetic sub-step c_i <- exp(-i kappa t |G1m+G2n|^2 / 2) c_i, with
+ * t = tau (half = 0) or tau/2 (half = 1) and the plan's kappa (Alg. 3 step 1 with
+ * kinetic share kappa).  A no-op when kappa = 0.  Stream-ordered.
+ */
+lsx_status lsx_phase(lsx_plan* plan, lsx_state* st, int32_t half, void* stream);
+
+/*
+ * lsx_observables -- FP64 reductions on the device, result copied to `out` (host).
+ * mask selects, in this order of output blocks:
+ *   LSX_OBS_MASS          N_w = sum_i |c_iw|^2  (eq. 2.3 via the orthonormality 3.1)
+ *   LSX_OBS_ENERGY        E_w = sum_i 1/2 |K_i|^2 |c_iw|^2 + Re c_w^H (V^1 + V^2) c_w (eq. 2.4)
+ *   LSX_OBS_FIBRE_MASS_1  [f][w] partial masses over layer-1 fibres
+ *   LSX_OBS_FIBRE_MASS_2  [f][w] partial masses over layer-2 fibres
+ * Deterministic (fixed reduction order).  Synchronises the stream.
+ * LSX_E_NONFINITE if any requested value is NaN/Inf (out is still written).
+ */
+lsx_status lsx_observables(lsx_plan* plan, lsx_state* st, uint32_t mask, double* out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LSX_H */

@@ -1,0 +1,819 @@
+// Host side of liblsx: geometry and lifted index set (Secs. 2-3), fibre tables,
+// plan precompute driver, state management, step composer (App. A) and the C-ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <numeric>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "lsx_internal.h"
+
+namespace lsx {
+
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+
+static lsx_status fail(lsx_status st, const std::string& msg) {
+  set_error(msg);
+  return st;
+}
+
+// ---------------------------------------------------------------- device buffer helper
+template <typename T>
+struct DBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  DBuf() = default;
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  ~DBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  lsx_status alloc(size_t count) {
+    release();
+    if (count == 0) count = 1;
+    if (hipMalloc(reinterpret_cast<void**>(&p), count * sizeof(T)) != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+      return fail(LSX_E_OOM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+    }
+    n = count;
+    return LSX_OK;
+  }
+  lsx_status upload(const std::vector<T>& v, hipStream_t s) {
+    lsx_status st = alloc(v.size());
+    if (st != LSX_OK) return st;
+    if (!v.empty()) LSX_HIP_TRY(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    return LSX_OK;
+  }
+};
+
+#define LSX_TRY(expr)                     \
+  do {                                    \
+    lsx_status st_ = (expr);              \
+    if (st_ != LSX_OK) return st_;        \
+  } while (0)
+
+}  // namespace lsx
+
+using namespace lsx;
+
+// ================================================================ system
+struct Stencil {
+  std::vector<int32_t> idx;  // nv*d
+  std::vector<double> re, im;
+  int nv = 0;
+  bool real = true;
+};
+
+struct FibreTable {
+  std::vector<int32_t> ptr, rows;
+  int maxL = 0;
+};
+
+struct lsx_system {
+  int d = 1;
+  double A[2][4] = {};
+  double B[2][4] = {};  // reciprocal 2 pi A^{-T}, row-major d x d
+  double Ec = 0.0;
+  int cutoff = 0;
+  int64_t N = 0;
+  std::vector<int32_t> mn;  // N * 2d
+  std::vector<double> K2;   // |G1m + G2n|^2
+  Stencil pot[2];
+  FibreTable fib[2];
+  std::vector<int32_t> nbr[2];  // N * nv_j: index of (m - p, n) / (m, n - q), or -1
+  int nplans = 0;
+};
+
+// A given column-major (A[k + d*c] = row k, column c); returns B = 2 pi A^{-T} row-major.
+static bool reciprocal(int d, const double* A, double* B) {
+  if (d == 1) {
+    if (!(std::isfinite(A[0])) || A[0] == 0.0) return false;
+    B[0] = 2.0 * M_PI / A[0];
+    return true;
+  }
+  const double a = A[0], c = A[1], b = A[2], dd = A[3];  // [[a, b], [c, dd]]
+  const double det = a * dd - b * c;
+  if (!std::isfinite(det) || std::fabs(det) < 1e-300) return false;
+  // A^{-1} = [[dd, -b], [-c, a]] / det ; A^{-T} = [[dd, -c], [-b, a]] / det
+  B[0] = 2.0 * M_PI * dd / det;
+  B[1] = 2.0 * M_PI * -c / det;
+  B[2] = 2.0 * M_PI * -b / det;
+  B[3] = 2.0 * M_PI * a / det;
+  return true;
+}
+
+// All integer vectors m with |B m|^2 <= lim, lexicographic order, and their |B m|^2.
+static void layer_candidates(int d, const double* A, const double* B, double lim, std::vector<int32_t>& out,
+                             std::vector<double>& s2) {
+  // |m_k| = |(B^{-1} G)_k| <= |row_k(B^{-1})| |G|, row_k(B^{-1}) = column k of A / (2 pi)
+  const double r = std::sqrt(lim);
+  int bound[2] = {0, 0};
+  for (int k = 0; k < d; ++k) {
+    double nrm = 0.0;
+    for (int i = 0; i < d; ++i) nrm += A[i + d * k] * A[i + d * k];
+    bound[k] = (int)std::floor(r * std::sqrt(nrm) / (2.0 * M_PI)) + 1;
+  }
+  out.clear();
+  s2.clear();
+  if (d == 1) {
+    for (int m = -bound[0]; m <= bound[0]; ++m) {
+      const double g = B[0] * m;
+      const double s = g * g;
+      if (s <= lim) {
+        out.push_back(m);
+        s2.push_back(s);
+      }
+    }
+  } else {
+    for (int m0 = -bound[0]; m0 <= bound[0]; ++m0)
+      for (int m1 = -bound[1]; m1 <= bound[1]; ++m1) {
+        const double g0 = B[0] * m0 + B[1] * m1, g1 = B[2] * m0 + B[3] * m1;
+        const double s = g0 * g0 + g1 * g1;
+        if (s <= lim) {
+          out.push_back(m0);
+          out.push_back(m1);
+          s2.push_back(s);
+        }
+      }
+  }
+}
+
+static inline uint64_t pack_key(const int32_t* v, int len) {
+  uint64_t k = 0;
+  for (int i = 0; i < len; ++i) k = (k << 16) | (uint64_t)(uint16_t)(int16_t)v[i];
+  return k;
+}
+
+static lsx_status build_stencil(int d, int nv, const int32_t* idx, const double* re, const double* im,
+                                Stencil& st, int layer) {
+  if (nv < 0) return fail(LSX_E_INVALID, "negative potential size");
+  if (nv > 0 && (!idx || !re || !im)) return fail(LSX_E_INVALID, "null potential array");
+  st.nv = nv;
+  st.idx.assign(idx, idx + (size_t)nv * d);
+  st.re.assign(re, re + nv);
+  st.im.assign(im, im + nv);
+  double vmax = 0.0;
+  for (int e = 0; e < nv; ++e) {
+    if (!std::isfinite(re[e]) || !std::isfinite(im[e]))
+      return fail(LSX_E_INVALID, "non-finite potential coefficient");
+    vmax = std::max(vmax, std::hypot(re[e], im[e]));
+    for (int k = 0; k < d; ++k)
+      if (std::abs(idx[e * d + k]) > 16000) return fail(LSX_E_INVALID, "potential index out of range");
+  }
+  std::unordered_map<uint64_t, int> pos;
+  for (int e = 0; e < nv; ++e) {
+    const uint64_t key = pack_key(&idx[e * d], d);
+    if (pos.count(key)) return fail(LSX_E_INVALID, "duplicate potential index in layer " + std::to_string(layer));
+    pos[key] = e;
+  }
+  st.real = true;
+  const double tol = 1e-14 * vmax;
+  for (int e = 0; e < nv; ++e) {
+    int32_t neg[2];
+    for (int k = 0; k < d; ++k) neg[k] = -idx[e * d + k];
+    auto it = pos.find(pack_key(neg, d));
+    if (it == pos.end()) {
+      if (std::hypot(re[e], im[e]) > tol)
+        return fail(LSX_E_NOT_HERMITIAN, "layer " + std::to_string(layer) + ": v_{-m} missing for a nonzero v_m");
+      continue;
+    }
+    const int o = it->second;
+    if (std::fabs(re[o] - re[e]) > tol || std::fabs(im[o] + im[e]) > tol)
+      return fail(LSX_E_NOT_HERMITIAN, "layer " + std::to_string(layer) + ": v_{-m} != conj(v_m)");
+    if (im[e] != 0.0) st.real = false;
+  }
+  return LSX_OK;
+}
+
+extern "C" const char* lsx_last_error(void) { return g_err.c_str(); }
+
+extern "C" lsx_status lsx_system_create(int32_t d, const double* A1, const double* A2, double Ec, int32_t cutoff,
+                                        int32_t nv1, const int32_t* v1_idx, const double* v1_re,
+                                        const double* v1_im, int32_t nv2, const int32_t* v2_idx,
+                                        const double* v2_re, const double* v2_im, lsx_system** out) {
+  if (!out || !A1 || !A2) return fail(LSX_E_INVALID, "null argument");
+  if (d != 1 && d != 2) return fail(LSX_E_INVALID, "d must be 1 or 2");
+  if (!(Ec > 0.0) || !std::isfinite(Ec)) return fail(LSX_E_INVALID, "Ec must be finite and > 0");
+  if (cutoff != LSX_CUTOFF_BALL && cutoff != LSX_CUTOFF_PRODUCT) return fail(LSX_E_INVALID, "bad cutoff");
+  lsx_system* sys = new (std::nothrow) lsx_system();
+  if (!sys) return fail(LSX_E_OOM, "host allocation failed");
+  sys->d = d;
+  sys->Ec = Ec;
+  sys->cutoff = cutoff;
+  for (int k = 0; k < d * d; ++k) {
+    sys->A[0][k] = A1[k];
+    sys->A[1][k] = A2[k];
+  }
+  for (int j = 0; j < 2; ++j)
+    if (!reciprocal(d, sys->A[j], sys->B[j])) {
+      delete sys;
+      return fail(LSX_E_INVALID, "lattice matrix A" + std::to_string(j + 1) + " is singular or non-finite");
+    }
+  lsx_status st = build_stencil(d, nv1, v1_idx, v1_re, v1_im, sys->pot[0], 1);
+  if (st == LSX_OK) st = build_stencil(d, nv2, v2_idx, v2_re, v2_im, sys->pot[1], 2);
+  if (st != LSX_OK) {
+    delete sys;
+    return st;
+  }
+
+  // lifted index set: candidates per layer (lexicographic), then pairs (m outer, n inner)
+  const double lim = 2.0 * Ec * (1.0 + 1e-12);
+  std::vector<int32_t> cm, cn;
+  std::vector<double> sm, sn;
+  layer_candidates(d, sys->A[0], sys->B[0], lim, cm, sm);
+  layer_candidates(d, sys->A[1], sys->B[1], lim, cn, sn);
+  const int64_t nm = (int64_t)sm.size(), nn = (int64_t)sn.size();
+  for (int64_t a = 0; a < nm; ++a)
+    for (int64_t b = 0; b < nn; ++b) {
+      if (cutoff == LSX_CUTOFF_BALL && !(sm[a] + sn[b] <= lim)) continue;
+      for (int k = 0; k < d; ++k) sys->mn.push_back(cm[a * d + k]);
+      for (int k = 0; k < d; ++k) sys->mn.push_back(cn[b * d + k]);
+    }
+  sys->N = (int64_t)sys->mn.size() / (2 * d);
+  if (sys->N >= (int64_t)1 << 31) {
+    delete sys;
+    return fail(LSX_E_INVALID, "lifted index set too large");
+  }
+  const int64_t N = sys->N;
+  sys->K2.resize(N);
+  for (int64_t i = 0; i < N; ++i) {
+    const int32_t* r = &sys->mn[i * 2 * d];
+    double s = 0.0;
+    for (int k = 0; k < d; ++k) {
+      double g = 0.0;
+      for (int c = 0; c < d; ++c) g += sys->B[0][k * d + c] * r[c] + sys->B[1][k * d + c] * r[d + c];
+      s += g * g;
+    }
+    sys->K2[i] = s;
+  }
+
+  // fibres: layer 1 groups rows by n (key = last d entries), layer 2 by m (first d entries)
+  for (int layer = 1; layer <= 2; ++layer) {
+    const int off = (layer == 1) ? d : 0;
+    std::vector<int32_t> order(N);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+      for (int k = 0; k < d; ++k) {
+        const int32_t a = sys->mn[(int64_t)x * 2 * d + off + k], b = sys->mn[(int64_t)y * 2 * d + off + k];
+        if (a != b) return a < b;
+      }
+      return false;
+    });
+    FibreTable& ft = sys->fib[layer - 1];
+    ft.rows = order;
+    ft.ptr.clear();
+    ft.ptr.push_back(0);
+    for (int64_t i = 1; i <= N; ++i) {
+      bool boundary = (i == N);
+      if (!boundary)
+        for (int k = 0; k < d; ++k)
+          if (sys->mn[(int64_t)order[i] * 2 * d + off + k] != sys->mn[(int64_t)order[i - 1] * 2 * d + off + k])
+            boundary = true;
+      if (boundary) ft.ptr.push_back((int32_t)i);
+    }
+    if (N == 0) ft.ptr.assign(1, 0);
+    ft.maxL = 0;
+    for (size_t f = 0; f + 1 < ft.ptr.size(); ++f) ft.maxL = std::max(ft.maxL, ft.ptr[f + 1] - ft.ptr[f]);
+  }
+
+  // neighbour tables for the potential terms of the energy
+  std::unordered_map<uint64_t, int32_t> where;
+  where.reserve((size_t)N * 2);
+  for (int64_t i = 0; i < N; ++i) where[pack_key(&sys->mn[i * 2 * d], 2 * d)] = (int32_t)i;
+  for (int j = 0; j < 2; ++j) {
+    const Stencil& S = sys->pot[j];
+    sys->nbr[j].assign((size_t)N * S.nv, -1);
+    for (int64_t i = 0; i < N; ++i) {
+      int32_t v[4];
+      for (int p = 0; p < S.nv; ++p) {
+        for (int k = 0; k < 2 * d; ++k) v[k] = sys->mn[i * 2 * d + k];
+        const int off = (j == 0) ? 0 : d;
+        for (int k = 0; k < d; ++k) v[off + k] -= S.idx[p * d + k];
+        auto it = where.find(pack_key(v, 2 * d));
+        if (it != where.end()) sys->nbr[j][i * S.nv + p] = it->second;
+      }
+    }
+  }
+  *out = sys;
+  return LSX_OK;
+}
+
+extern "C" lsx_status lsx_system_size(const lsx_system* sys, int64_t* N, int64_t* nf1, int64_t* nf2) {
+  if (!sys) return fail(LSX_E_INVALID, "null system");
+  if (N) *N = sys->N;
+  if (nf1) *nf1 = (int64_t)sys->fib[0].ptr.size() - 1;
+  if (nf2) *nf2 = (int64_t)sys->fib[1].ptr.size() - 1;
+  return LSX_OK;
+}
+
+extern "C" lsx_status lsx_index_get(const lsx_system* sys, int32_t* mn) {
+  if (!sys || !mn) return fail(LSX_E_INVALID, "null argument");
+  if (!sys->mn.empty()) std::memcpy(mn, sys->mn.data(), sys->mn.size() * sizeof(int32_t));
+  return LSX_OK;
+}
+
+extern "C" lsx_status lsx_fibre_get(const lsx_system* sys, int32_t layer, int32_t* ptr, int32_t* rows) {
+  if (!sys) return fail(LSX_E_INVALID, "null system");
+  if (layer != 1 && layer != 2) return fail(LSX_E_INVALID, "layer must be 1 or 2");
+  const FibreTable& ft = sys->fib[layer - 1];
+  if (ptr) std::memcpy(ptr, ft.ptr.data(), ft.ptr.size() * sizeof(int32_t));
+  if (rows && !ft.rows.empty()) std::memcpy(rows, ft.rows.data(), ft.rows.size() * sizeof(int32_t));
+  return LSX_OK;
+}
+
+extern "C" lsx_status lsx_system_destroy(lsx_system* sys) {
+  if (!sys) return LSX_OK;
+  if (sys->nplans > 0) return fail(LSX_E_STATE, "system still has live plans");
+  delete sys;
+  return LSX_OK;
+}
+
+// ================================================================ plan
+struct PropSet {
+  bool present = false;
+  double t = 0.0;
+  DBuf<char> data;
+  std::vector<int64_t> h_off;
+  DBuf<int64_t> off;
+};
+
+struct LayerDev {
+  int nf = 0;
+  int maxL = 0;
+  std::vector<int32_t> h_ptr;
+  DBuf<int32_t> ptr, rows;
+  DBuf<int32_t> nbr;
+  DBuf<double2> v;  // stencil values (for the energy)
+  PropSet prop[2];  // [0] = tau, [1] = tau/2
+};
+
+struct lsx_plan {
+  lsx_system* sys = nullptr;
+  double tau = 0.0, kappa = 0.0;
+  int scheme = LSX_STRANG, precision = LSX_FP64, fmt = PF_F64;
+  DBuf<double> K2;
+  DBuf<double2> diag;  // mixed formats: per fibre-row diagonal, [layer*2+half] blocks of N
+  DBuf<double2> phase[2];  // exp(-i kappa t |K|^2/2) for t = tau, tau/2
+  LayerDev L[2];
+  int nstates = 0;
+};
+
+static lsx_status precompute_layer(lsx_plan* pl, int layer, hipStream_t s) {
+  lsx_system* sys = pl->sys;
+  LayerDev& ld = pl->L[layer - 1];
+  const FibreTable& ft = sys->fib[layer - 1];
+  const Stencil& S = sys->pot[layer - 1];
+  const int nf = ld.nf;
+  if (nf == 0) return LSX_OK;
+  const int embed = S.real ? 0 : 1;
+  std::vector<int32_t> ndim(nf), emb(nf, embed);
+  std::vector<int64_t> moff(nf), loff(nf);
+  int64_t mt = 0, lt = 0;
+  int maxn = 0;
+  for (int f = 0; f < nf; ++f) {
+    const int L = ft.ptr[f + 1] - ft.ptr[f];
+    int n = embed ? 2 * L : L;
+    n += (n & 1);
+    if (n < 2) n = 2;
+    ndim[f] = n;
+    maxn = std::max(maxn, n);
+    moff[f] = mt;
+    loff[f] = lt;
+    mt += (int64_t)n * n;
+    lt += n;
+  }
+  if (maxn > 8192) return fail(LSX_E_INVALID, "fibre too long for the eigensolver (max 8192)");
+  DBuf<int32_t> d_ndim, d_emb, d_info, d_mn, d_vidx;
+  DBuf<int64_t> d_moff, d_loff;
+  DBuf<double> A, VT, lam, d_vre, d_vim;
+  DBuf<double2> cs;
+  LSX_TRY(d_ndim.upload(ndim, s));
+  LSX_TRY(d_emb.upload(emb, s));
+  LSX_TRY(d_moff.upload(moff, s));
+  LSX_TRY(d_loff.upload(loff, s));
+  LSX_TRY(d_mn.upload(sys->mn, s));
+  LSX_TRY(d_vidx.upload(S.idx, s));
+  LSX_TRY(d_vre.upload(S.re, s));
+  LSX_TRY(d_vim.upload(S.im, s));
+  LSX_TRY(A.alloc(mt));
+  LSX_TRY(VT.alloc(mt));
+  LSX_TRY(lam.alloc(lt));
+  LSX_TRY(cs.alloc(lt));
+  LSX_TRY(d_info.alloc(nf));
+  LSX_HIP_TRY(launch_assemble(s, nf, ld.ptr.p, ld.rows.p, d_mn.p, sys->d, layer, pl->K2.p, S.nv, d_vidx.p,
+                              d_vre.p, d_vim.p, pl->kappa, embed, A.p, d_moff.p, d_ndim.p));
+  LSX_HIP_TRY(launch_jacobi(s, nf, maxn, A.p, VT.p, d_moff.p, d_ndim.p, lam.p, d_loff.p, d_info.p, 60));
+  std::vector<int32_t> info(nf);
+  LSX_HIP_TRY(hipMemcpyAsync(info.data(), d_info.p, nf * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  LSX_HIP_TRY(hipStreamSynchronize(s));
+  for (int f = 0; f < nf; ++f)
+    if (info[f] < 0)
+      return fail(LSX_E_EIG, "Jacobi did not converge for layer " + std::to_string(layer) + " fibre " +
+                                 std::to_string(f));
+  // propagators for the sub-step lengths the scheme needs
+  for (int h = 0; h < 2; ++h) {
+    PropSet& ps = ld.prop[h];
+    const bool need = (h == 0) || (layer == 1 && pl->scheme == LSX_STRANG);
+    if (!need) continue;
+    ps.t = (h == 0) ? pl->tau : 0.5 * pl->tau;
+    ps.h_off.resize(nf);
+    int64_t bytes = 0;
+    for (int f = 0; f < nf; ++f) {
+      ps.h_off[f] = bytes;
+      bytes += prop_bytes(pl->fmt, ft.ptr[f + 1] - ft.ptr[f]);
+      bytes = (bytes + 255) & ~(int64_t)255;
+    }
+    LSX_TRY(ps.data.alloc(bytes));
+    LSX_TRY(ps.off.upload(ps.h_off, s));
+    LSX_HIP_TRY(hipMemsetAsync(ps.data.p, 0, bytes, s));
+    LSX_HIP_TRY(launch_eig_phase(s, lt, lam.p, ps.t, cs.p));
+    double2* dg = pl->diag.p ? pl->diag.p + (size_t)((layer - 1) * 2 + h) * sys->N : nullptr;
+    LSX_HIP_TRY(launch_form(s, pl->fmt, nf, ft.maxL, ld.ptr.p, VT.p, d_moff.p, d_ndim.p, d_emb.p, cs.p,
+                            d_loff.p, ps.data.p, ps.off.p, dg));
+    ps.present = true;
+  }
+  LSX_HIP_TRY(hipStreamSynchronize(s));
+  return LSX_OK;
+}
+
+extern "C" lsx_status lsx_plan_create(lsx_system* sys, double tau, int32_t scheme, double kappa,
+                                      int32_t precision, void* stream, lsx_plan** out) {
+  if (!sys || !out) return fail(LSX_E_INVALID, "null argument");
+  if (!std::isfinite(tau) || tau == 0.0) return fail(LSX_E_INVALID, "tau must be finite and nonzero");
+  if (scheme != LSX_LIE && scheme != LSX_STRANG) return fail(LSX_E_INVALID, "bad scheme");
+  if (!(kappa >= 0.0 && kappa <= 1.0)) return fail(LSX_E_INVALID, "kappa must be in [0, 1]");
+  if (precision != LSX_FP64 && precision != LSX_MIX_FP32 && precision != LSX_MIX_BF16X3)
+    return fail(LSX_E_INVALID, "bad precision");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  lsx_plan* pl = new (std::nothrow) lsx_plan();
+  if (!pl) return fail(LSX_E_OOM, "host allocation failed");
+  pl->sys = sys;
+  pl->tau = tau;
+  pl->kappa = kappa;
+  pl->scheme = scheme;
+  pl->precision = precision;
+  pl->fmt = precision == LSX_FP64 ? PF_F64 : (precision == LSX_MIX_FP32 ? PF_F32 : PF_BF16X3);
+  auto cleanup = [&](lsx_status st) {
+    delete pl;
+    return st;
+  };
+  lsx_status st = pl->K2.upload(sys->K2, s);
+  if (st != LSX_OK) return cleanup(st);
+  if (pl->fmt != PF_F64) {
+    st = pl->diag.alloc((size_t)4 * std::max<int64_t>(sys->N, 1));
+    if (st != LSX_OK) return cleanup(st);
+  }
+  for (int j = 0; j < 2; ++j) {
+    LayerDev& ld = pl->L[j];
+    const FibreTable& ft = sys->fib[j];
+    ld.nf = (int)ft.ptr.size() - 1;
+    ld.maxL = ft.maxL;
+    ld.h_ptr = ft.ptr;
+    if ((st = ld.ptr.upload(ft.ptr, s)) != LSX_OK) return cleanup(st);
+    if ((st = ld.rows.upload(ft.rows, s)) != LSX_OK) return cleanup(st);
+    if ((st = ld.nbr.upload(sys->nbr[j], s)) != LSX_OK) return cleanup(st);
+    std::vector<double2> v(sys->pot[j].nv);
+    for (int p = 0; p < sys->pot[j].nv; ++p) v[p] = make_double2(sys->pot[j].re[p], sys->pot[j].im[p]);
+    if ((st = ld.v.upload(v, s)) != LSX_OK) return cleanup(st);
+  }
+  if (kappa != 0.0) {
+    for (int h = 0; h < 2; ++h) {
+      const double t = (h == 0) ? tau : 0.5 * tau;
+      if ((st = pl->phase[h].alloc(std::max<int64_t>(sys->N, 1))) != LSX_OK) return cleanup(st);
+      if (sys->N > 0) {
+        hipError_t e = launch_phase_table(s, sys->N, pl->K2.p, 0.5 * kappa * t, pl->phase[h].p);
+        if (e != hipSuccess) return cleanup(fail(LSX_E_HIP, std::string("phase table: ") + hipGetErrorString(e)));
+      }
+    }
+  }
+  for (int layer = 1; layer <= 2; ++layer)
+    if ((st = precompute_layer(pl, layer, s)) != LSX_OK) return cleanup(st);
+  sys->nplans++;
+  *out = pl;
+  return LSX_OK;
+}
+
+extern "C" lsx_status lsx_plan_propagator(const lsx_plan* pl, int32_t layer, int32_t half, int32_t fibre,
+                                          double* out, void* stream) {
+  if (!pl || !out) return fail(LSX_E_INVALID, "null argument");
+  if (layer != 1 && layer != 2) return fail(LSX_E_INVALID, "layer must be 1 or 2");
+  if (half != 0 && half != 1) return fail(LSX_E_INVALID, "half must be 0 or 1");
+  const LayerDev& ld = pl->L[layer - 1];
+  if (fibre < 0 || fibre >= ld.nf) return fail(LSX_E_INVALID, "fibre out of range");
+  const PropSet& ps = ld.prop[half];
+  if (!ps.present) return fail(LSX_E_INVALID, "plan holds no propagator for this layer/half");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int L = ld.h_ptr[fibre + 1] - ld.h_ptr[fibre];
+  const int64_t bytes = prop_bytes(pl->fmt, L);
+  std::vector<char> raw(bytes);
+  LSX_HIP_TRY(hipMemcpyAsync(raw.data(), ps.data.p + ps.h_off[fibre], bytes, hipMemcpyDeviceToHost, s));
+  std::vector<double2> dg;
+  if (pl->fmt != PF_F64) {
+    dg.resize(L);
+    const double2* src = pl->diag.p + (size_t)((layer - 1) * 2 + half) * pl->sys->N + ld.h_ptr[fibre];
+    LSX_HIP_TRY(hipMemcpyAsync(dg.data(), src, L * sizeof(double2), hipMemcpyDeviceToHost, s));
+  }
+  LSX_HIP_TRY(hipStreamSynchronize(s));
+  auto bf = [](uint16_t h) {
+    uint32_t u = (uint32_t)h << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return (double)f;
+  };
+  for (int a = 0; a < L; ++a)
+    for (int b = 0; b < L; ++b) {
+      double re, im;
+      if (pl->fmt == PF_F64 || pl->fmt == PF_F32) {
+        const int Lp = round_up(L, 16);
+        const int64_t idx = ((int64_t)(a / 16) * (Lp / 4) + b / 4) * 64 + (a % 16) + 16 * (b % 4);
+        if (pl->fmt == PF_F64) {
+          const double* p = reinterpret_cast<const double*>(raw.data()) + 2 * idx;
+          re = p[0];
+          im = p[1];
+        } else {
+          const float* p = reinterpret_cast<const float*>(raw.data()) + 2 * idx;
+          re = p[0];
+          im = p[1];
+        }
+      } else {
+        const int Lp = round_up(L, 32);
+        const int64_t chunk = (int64_t)(a / 16) * (Lp / 32) + b / 32;
+        const int lane = (a % 16) + 16 * ((b % 32) / 8), el = b % 8;
+        const uint16_t* q = reinterpret_cast<const uint16_t*>(raw.data());
+        re = im = 0.0;
+        for (int term = 0; term < 3; ++term) {
+          re += bf(q[((chunk * 6 + 2 * term) * 64 + lane) * 8 + el]);
+          im += bf(q[((chunk * 6 + 2 * term + 1) * 64 + lane) * 8 + el]);
+        }
+      }
+      if (pl->fmt != PF_F64 && a == b) {
+        re = dg[a].x;
+        im = dg[a].y;
+      }
+      out[2 * ((int64_t)a * L + b)] = re;
+      out[2 * ((int64_t)a * L + b) + 1] = im;
+    }
+  return LSX_OK;
+}
+
+extern "C" lsx_status lsx_plan_destroy(lsx_plan* pl) {
+  if (!pl) return LSX_OK;
+  if (pl->nstates > 0) return fail(LSX_E_STATE, "plan still has live states");
+  pl->sys->nplans--;
+  delete pl;
+  return LSX_OK;
+}
+
+// ================================================================ state
+struct lsx_state {
+  lsx_plan* plan = nullptr;
+  int W = 0;
+  double2* buf[2] = {nullptr, nullptr};
+  bool owns0 = false;
+  DBuf<double2> own0, work;
+  DBuf<int4> tiles[2];
+  int ntiles[2] = {0, 0};
+  int nb = 1, ks = 4;
+  DBuf<double> partial, result;
+  int nred = 0;
+};
+
+static void build_tiles(const lsx_plan* pl, int layer, int W, int nb, std::vector<int4>& out) {
+  const LayerDev& ld = pl->L[layer - 1];
+  const int wt = (W == 1) ? 1 : (W + 16 * nb - 1) / (16 * nb);
+  std::vector<int> order(ld.nf);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    return (ld.h_ptr[x + 1] - ld.h_ptr[x]) > (ld.h_ptr[y + 1] - ld.h_ptr[y]);
+  });
+  out.clear();
+  for (int f : order) {
+    const int L = ld.h_ptr[f + 1] - ld.h_ptr[f];
+    const int nrb = (L + 15) / 16;
+    for (int rb = 0; rb < nrb; ++rb)
+      for (int wb = 0; wb < wt; ++wb) out.push_back(make_int4(f, rb, wb, 0));
+  }
+}
+
+static int env_int(const char* name, int dflt) {
+  const char* v = std::getenv(name);
+  return v ? std::atoi(v) : dflt;
+}
+
+extern "C" lsx_status lsx_state_create(lsx_plan* pl, int32_t W, void* dev_ptr, lsx_state** out) {
+  if (!pl || !out) return fail(LSX_E_INVALID, "null argument");
+  if (W < 1 || W > 65536) return fail(LSX_E_INVALID, "W must be in [1, 65536]");
+  if (dev_ptr && (reinterpret_cast<uintptr_t>(dev_ptr) % 16) != 0)
+    return fail(LSX_E_INVALID, "wrapped device pointer must be 16-byte aligned");
+  const int64_t N = pl->sys->N;
+  lsx_state* st = new (std::nothrow) lsx_state();
+  if (!st) return fail(LSX_E_OOM, "host allocation failed");
+  st->plan = pl;
+  st->W = W;
+  auto cleanup = [&](lsx_status e) {
+    delete st;
+    return e;
+  };
+  lsx_status e;
+  const size_t total = (size_t)std::max<int64_t>(N, 1) * W;
+  if (dev_ptr) {
+    st->buf[0] = reinterpret_cast<double2*>(dev_ptr);
+  } else {
+    if ((e = st->own0.alloc(total)) != LSX_OK) return cleanup(e);
+    st->buf[0] = st->own0.p;
+    st->owns0 = true;
+    if (hipMemset(st->buf[0], 0, total * sizeof(double2)) != hipSuccess)
+      return cleanup(fail(LSX_E_HIP, "hipMemset of state failed"));
+  }
+  if ((e = st->work.alloc(total)) != LSX_OK) return cleanup(e);
+  st->buf[1] = st->work.p;
+  st->nb = env_int("LSX_NB", W >= 48 ? 2 : 1);
+  st->ks = env_int("LSX_KS", 4);
+  if (st->nb != 1 && st->nb != 2 && st->nb != 4) st->nb = 1;
+  if (st->ks != 1 && st->ks != 2 && st->ks != 4) st->ks = 4;
+  for (int layer = 1; layer <= 2; ++layer) {
+    std::vector<int4> t;
+    build_tiles(pl, layer, W, st->nb, t);
+    st->ntiles[layer - 1] = (int)t.size();
+    if ((e = st->tiles[layer - 1].upload(t, nullptr)) != LSX_OK) return cleanup(e);
+  }
+  st->nred = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (N + 255) / 256));
+  const int nfmax = std::max(pl->L[0].nf, pl->L[1].nf);
+  if ((e = st->partial.alloc((size_t)st->nred * W)) != LSX_OK) return cleanup(e);
+  if ((e = st->result.alloc((size_t)W * (2 + 2 * (size_t)std::max(nfmax, 1)))) != LSX_OK) return cleanup(e);
+  if (hipDeviceSynchronize() != hipSuccess) return cleanup(fail(LSX_E_HIP, "state setup failed"));
+  pl->nstates++;
+  *out = st;
+  return LSX_OK;
+}
+
+extern "C" lsx_status lsx_state_upload(lsx_state* st, const double* host, void* stream) {
+  if (!st || !host) return fail(LSX_E_INVALID, "null argument");
+  const size_t bytes = (size_t)st->plan->sys->N * st->W * sizeof(double2);
+  if (bytes)
+    LSX_HIP_TRY(hipMemcpyAsync(st->buf[0], host, bytes, hipMemcpyHostToDevice, reinterpret_cast<hipStream_t>(stream)));
+  return LSX_OK;
+}
+
+extern "C" lsx_status lsx_state_download(lsx_state* st, double* host, void* stream) {
+  if (!st || !host) return fail(LSX_E_INVALID, "null argument");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const size_t bytes = (size_t)st->plan->sys->N * st->W * sizeof(double2);
+  if (bytes) LSX_HIP_TRY(hipMemcpyAsync(host, st->buf[0], bytes, hipMemcpyDeviceToHost, s));
+  LSX_HIP_TRY(hipStreamSynchronize(s));
+  return LSX_OK;
+}
+
+extern "C" lsx_status lsx_state_device_ptr(const lsx_state* st, void** dev) {
+  if (!st || !dev) return fail(LSX_E_INVALID, "null argument");
+  *dev = st->buf[0];
+  return LSX_OK;
+}
+
+extern "C" lsx_status lsx_state_destroy(lsx_state* st) {
+  if (!st) return LSX_OK;
+  st->plan->nstates--;
+  delete st;
+  return LSX_OK;
+}
+
+// ================================================================ step composer
+// Between API calls the state lives in buf[0]; a fibre pass reads buf[cur] and writes
+// buf[1-cur]; the composer copies back at the end when an odd number of passes ran.
+namespace {
+struct Runner {
+  lsx_plan* pl;
+  lsx_state* st;
+  hipStream_t s;
+  int cur = 0;
+
+  lsx_status pass(int layer, int half) {
+    const LayerDev& ld = pl->L[layer - 1];
+    const PropSet& ps = ld.prop[half];
+    if (!ps.present) return fail(LSX_E_INVALID, "plan holds no propagator for this layer/half");
+    PassArgs a;
+    a.tiles = st->tiles[layer - 1].p;
+    a.ptr = ld.ptr.p;
+    a.rows = ld.rows.p;
+    a.poff = ps.off.p;
+    a.P = ps.data.p;
+    a.diag = pl->diag.p ? pl->diag.p + (size_t)((layer - 1) * 2 + half) * pl->sys->N : nullptr;
+    a.X = st->buf[cur];
+    a.Y = st->buf[1 - cur];
+    a.W = st->W;
+    LSX_HIP_TRY(launch_pass(s, pl->fmt, st->W, st->ntiles[layer - 1], st->nb, st->ks, a));
+    cur ^= 1;
+    return LSX_OK;
+  }
+  lsx_status phase(int half) {
+    if (pl->kappa == 0.0 || pl->sys->N == 0) return LSX_OK;
+    LSX_HIP_TRY(launch_phase_apply(s, pl->sys->N, st->W, pl->phase[half].p, st->buf[cur]));
+    return LSX_OK;
+  }
+  lsx_status finish() {
+    if (cur != 0) {
+      if (st->owns0) {
+        // both arrays belong to the library: swap roles instead of copying
+        std::swap(st->buf[0], st->buf[1]);
+      } else {
+        LSX_HIP_TRY(hipMemcpyAsync(st->buf[0], st->buf[1], (size_t)pl->sys->N * st->W * sizeof(double2),
+                                   hipMemcpyDeviceToDevice, s));
+      }
+      cur = 0;
+    }
+    return LSX_OK;
+  }
+};
+}  // namespace
+
+static lsx_status check_pair(lsx_plan* pl, lsx_state* st) {
+  if (!pl || !st) return fail(LSX_E_INVALID, "null argument");
+  if (st->plan != pl) return fail(LSX_E_STATE, "state belongs to another plan");
+  return LSX_OK;
+}
+
+extern "C" lsx_status lsx_step(lsx_plan* pl, lsx_state* st, int64_t nsteps, void* stream) {
+  LSX_TRY(check_pair(pl, st));
+  if (nsteps < 0) return fail(LSX_E_INVALID, "nsteps must be >= 0");
+  if (nsteps == 0 || pl->sys->N == 0) return LSX_OK;
+  Runner r{pl, st, reinterpret_cast<hipStream_t>(stream)};
+  if (pl->scheme == LSX_LIE) {
+    for (int64_t k = 0; k < nsteps; ++k) {
+      LSX_TRY(r.pass(1, 0));
+      LSX_TRY(r.phase(0));
+      LSX_TRY(r.pass(2, 0));
+    }
+  } else {
+    LSX_TRY(r.pass(1, 1));
+    for (int64_t k = 0; k < nsteps; ++k) {
+      LSX_TRY(r.phase(1));
+      LSX_TRY(r.pass(2, 0));
+      LSX_TRY(r.phase(1));
+      LSX_TRY(r.pass(1, k + 1 < nsteps ? 0 : 1));
+    }
+  }
+  return r.finish();
+}
+
+extern "C" lsx_status lsx_fibre_pass(lsx_plan* pl, lsx_state* st, int32_t layer, int32_t half, int32_t count,
+                                     void* stream) {
+  LSX_TRY(check_pair(pl, st));
+  if (layer != 1 && layer != 2) return fail(LSX_E_INVALID, "layer must be 1 or 2");
+  if (half != 0 && half != 1) return fail(LSX_E_INVALID, "half must be 0 or 1");
+  if (count < 0) return fail(LSX_E_INVALID, "count must be >= 0");
+  if (pl->sys->N == 0 || count == 0) return LSX_OK;
+  Runner r{pl, st, reinterpret_cast<hipStream_t>(stream)};
+  for (int32_t k = 0; k < count; ++k) LSX_TRY(r.pass(layer, half));
+  return r.finish();
+}
+
+extern "C" lsx_status lsx_phase(lsx_plan* pl, lsx_state* st, int32_t half, void* stream) {
+  LSX_TRY(check_pair(pl, st));
+  if (half != 0 && half != 1) return fail(LSX_E_INVALID, "half must be 0 or 1");
+  Runner r{pl, st, reinterpret_cast<hipStream_t>(stream)};
+  return r.phase(half);
+}
+
+extern "C" lsx_status lsx_observables(lsx_plan* pl, lsx_state* st, uint32_t mask, double* out, void* stream) {
+  LSX_TRY(check_pair(pl, st));
+  if (!out) return fail(LSX_E_INVALID, "null output");
+  if (mask == 0 || (mask & ~15u)) return fail(LSX_E_INVALID, "bad observable mask");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const lsx_system* sys = pl->sys;
+  const int W = st->W;
+  const int64_t N = sys->N;
+  double* dres = st->result.p;
+  size_t count = 0;
+  if (mask & LSX_OBS_MASS) {
+    LSX_HIP_TRY(launch_reduce(s, 0, N, W, st->buf[0], pl->K2.p, 0, nullptr, nullptr, 0, nullptr, nullptr,
+                              st->partial.p, st->nred, dres + count));
+    count += W;
+  }
+  if (mask & LSX_OBS_ENERGY) {
+    LSX_HIP_TRY(launch_reduce(s, 1, N, W, st->buf[0], pl->K2.p, sys->pot[0].nv, pl->L[0].nbr.p, pl->L[0].v.p,
+                              sys->pot[1].nv, pl->L[1].nbr.p, pl->L[1].v.p, st->partial.p, st->nred, dres + count));
+    count += W;
+  }
+  for (int layer = 1; layer <= 2; ++layer)
+    if (mask & (layer == 1 ? LSX_OBS_FIBRE_MASS_1 : LSX_OBS_FIBRE_MASS_2)) {
+      const LayerDev& ld = pl->L[layer - 1];
+      LSX_HIP_TRY(launch_fibre_mass(s, ld.nf, ld.ptr.p, ld.rows.p, W, st->buf[0], dres + count));
+      count += (size_t)ld.nf * W;
+    }
+  LSX_HIP_TRY(hipMemcpyAsync(out, dres, count * sizeof(double), hipMemcpyDeviceToHost, s));
+  LSX_HIP_TRY(hipStreamSynchronize(s));
+  for (size_t i = 0; i < count; ++i)
+    if (!std::isfinite(out[i])) return fail(LSX_E_NONFINITE, "observable is NaN or Inf");
+  return LSX_OK;
+}

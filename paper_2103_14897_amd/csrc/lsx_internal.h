@@ -1,0 +1,89 @@
+// Internal declarations shared by the host library and the HIP kernels of liblsx.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "lsx.h"
+
+namespace lsx {
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string& msg);
+#define LSX_HIP_TRY(expr)                                                                   \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess) {                                                                 \
+      ::lsx::set_error(std::string(#expr) + ": " + hipGetErrorString(e_));                  \
+      return LSX_E_HIP;                                                                     \
+    }                                                                                       \
+  } while (0)
+
+// ---------------------------------------------------------------- storage formats
+// Propagator storage, per fibre f of length L (all formats zero-padded):
+//  PF_F64    : complex128 P, Lp = roundup(L,16); chunk (rb, ks) = rows 16rb.., cols 4ks..
+//              holds 64 double2, lane l = (row%16) + 16*(col%4).  Chunk index rb*(Lp/4)+ks.
+//              This is exactly the A-operand order of v_mfma_f64_16x16x4f64.
+//  PF_F32    : the off-diagonal part E of P as complex64 in the same chunk order
+//              (A-operand order of v_mfma_f32_16x16x4f32), diagonal held in FP64 separately.
+//  PF_BF16X3 : E split into three bf16 terms; Lp = roundup(L,32); chunk (rb, kc) = rows
+//              16rb.., cols 32kc..; per chunk 6 planes (term*2 + {re,im}) of 64 lanes x 8
+//              bf16, lane l = (row%16) + 16*((col%32)/8), element col%8 -- the A-operand
+//              order of v_mfma_f32_16x16x32_bf16.
+enum PropFormat { PF_F64 = 0, PF_F32 = 1, PF_BF16X3 = 2 };
+
+inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
+inline int prop_pad(int fmt) { return fmt == PF_BF16X3 ? 32 : 16; }
+// size in bytes of one fibre's propagator storage
+inline int64_t prop_bytes(int fmt, int L) {
+  int64_t Lp = round_up(L, prop_pad(fmt));
+  switch (fmt) {
+    case PF_F64: return Lp * Lp * 16;
+    case PF_F32: return Lp * Lp * 8;
+    default: return Lp * Lp * 12;  // 3 terms x (re, im) x bf16
+  }
+}
+
+struct Tile {
+  int32_t f, rb, wb, pad;
+};
+
+// arguments of every fibre-pass kernel
+struct PassArgs {
+  const int4* tiles;
+  const int32_t* ptr;    // fibre row pointers (nfibres+1)
+  const int32_t* rows;   // row ids of each fibre, concatenated
+  const int64_t* poff;   // per fibre byte offset into the propagator storage
+  const void* P;         // propagator storage (format per kernel)
+  const double2* diag;   // mixed formats: diagonal of P at fibre-row position ptr[f]+a
+  const double2* X;      // input state  [N][W]
+  double2* Y;            // output state [N][W]
+  int32_t W;
+};
+
+// ---------------------------------------------------------------- kernel launchers (lsx_kernels.hip)
+hipError_t launch_assemble(hipStream_t s, int nf, const int32_t* ptr, const int32_t* rows,
+                           const int32_t* mn, int d, int layer, const double* K2, int nv,
+                           const int32_t* vidx, const double* vre, const double* vim, double kappa,
+                           int embed, double* A, const int64_t* moff, const int32_t* ndim);
+hipError_t launch_jacobi(hipStream_t s, int nf, int maxn, double* A, double* VT, const int64_t* moff,
+                         const int32_t* ndim, double* lam, const int64_t* loff, int32_t* info,
+                         int maxsweeps);
+hipError_t launch_eig_phase(hipStream_t s, int64_t nlam, const double* lam, double t, double2* cs);
+hipError_t launch_form(hipStream_t s, int fmt, int nf, int maxL, const int32_t* ptr, const double* VT,
+                       const int64_t* moff, const int32_t* ndim, const int32_t* embed,
+                       const double2* cs, const int64_t* loff, void* P, const int64_t* poff,
+                       double2* diag);
+hipError_t launch_phase_table(hipStream_t s, int64_t N, const double* K2, double theta_scale, double2* ph);
+hipError_t launch_phase_apply(hipStream_t s, int64_t N, int W, const double2* ph, double2* c);
+hipError_t launch_pass(hipStream_t s, int fmt, int W, int ntiles, int nb, int ksplit, const PassArgs& a);
+hipError_t launch_reduce(hipStream_t s, int kind, int64_t N, int W, const double2* c, const double* K2,
+                         int nv1, const int32_t* nbr1, const double2* v1, int nv2, const int32_t* nbr2,
+                         const double2* v2, double* partial, int nblocks, double* out);
+hipError_t launch_fibre_mass(hipStream_t s, int nf, const int32_t* ptr, const int32_t* rows, int W,
+                             const double2* c, double* out);
+
+}  // namespace lsx

@@ -1,0 +1,845 @@
+// HIP kernels of liblsx for MI355X (gfx950, CDNA4, wave64).
+//
+// Exact-flow layer splitting on the lifted plane-wave coefficients
+// (Wang, Chen, Zhou & Zhou, arXiv 2103.14897, Secs. 3-4, App. A):
+//   * fibre Hamiltonian assembly      H_j(fibre) = (1-kappa)/2 D + V^j     (eqs. 3.5-3.6)
+//   * batched FP64 Jacobi eigensolver (one workgroup per fibre, any length)
+//   * propagator formation            P(t) = U exp(-i t Lambda) U^H
+//   * kinetic phase                   c_i <- exp(-i kappa t |K_i|^2/2) c_i  (Alg. 3 step 1)
+//   * fibre passes                    X_f <- P_f X_f for all fibres of a layer (Alg. 2 steps 1/2)
+//                                     as grouped complex GEMMs on MFMA (FP64, FP32, BF16x3)
+//   * FP64 reductions                 mass (eq. 2.3), energy (eq. 2.4), fibre masses
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "lsx_internal.h"
+
+namespace lsx {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef unsigned short v8u16 __attribute__((ext_vector_type(8)));
+
+// ---------------------------------------------------------------- helpers
+__device__ __forceinline__ unsigned short f2bf(float f) {
+  // round to nearest even (finite inputs only)
+  unsigned int u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float((unsigned int)h << 16); }
+
+// three-term bf16 split of a double: x ~= t0 + t1 + t2
+__device__ __forceinline__ void split3(double x, unsigned short& t0, unsigned short& t1, unsigned short& t2) {
+  t0 = f2bf((float)x);
+  double r = x - (double)bf2f(t0);
+  t1 = f2bf((float)r);
+  r = r - (double)bf2f(t1);
+  t2 = f2bf((float)r);
+}
+// same split from an fp32 value (all residuals exact in fp32)
+__device__ __forceinline__ void split3f(float x, unsigned short& t0, unsigned short& t1, unsigned short& t2) {
+  t0 = f2bf(x);
+  float r = x - bf2f(t0);
+  t1 = f2bf(r);
+  r = r - bf2f(t1);
+  t2 = f2bf(r);
+}
+
+template <int BS>
+__device__ double block_sum(double v, double* sh) {
+  // deterministic tree sum over a block of BS threads
+  sh[threadIdx.x] = v;
+  __syncthreads();
+#pragma unroll
+  for (int s = BS / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// ---------------------------------------------------------------- assembly (eq. 3.6 on one fibre)
+// A (ndim x ndim, row-major) <- H_j restricted to fibre f, or for complex H its real
+// embedding [[Re H, -Im H], [Im H, Re H]]; padding rows/cols are zero.
+__global__ void k_assemble(const int32_t* ptr, const int32_t* rows, const int32_t* mn, int d, int layer,
+                           const double* K2, int nv, const int32_t* vidx, const double* vre,
+                           const double* vim, double kappa, int embed, double* Aall, const int64_t* moff,
+                           const int32_t* ndim) {
+  const int f = blockIdx.x;
+  const int r0 = ptr[f], L = ptr[f + 1] - r0;
+  const int n = ndim[f];
+  double* A = Aall + moff[f];
+  const int own = (layer == 1) ? 0 : d;
+  const int La = embed ? 2 * L : L;
+  const int64_t nn = (int64_t)n * n;
+  for (int64_t e = threadIdx.x; e < nn; e += blockDim.x) {
+    const int a = (int)(e / n), b = (int)(e % n);
+    double val = 0.0;
+    if (a < La && b < La) {
+      const int ar = a % L, br = b % L, qa = a / L, qb = b / L;
+      const int ia = rows[r0 + ar], ib = rows[r0 + br];
+      double hr = 0.0, hi = 0.0;
+      for (int v = 0; v < nv; ++v) {
+        bool match = true;
+        for (int k = 0; k < d; ++k)
+          match = match && (mn[(int64_t)ia * 2 * d + own + k] - mn[(int64_t)ib * 2 * d + own + k] == vidx[v * d + k]);
+        if (match) {
+          hr += vre[v];
+          hi += vim[v];
+        }
+      }
+      if (ar == br) hr += (1.0 - kappa) * 0.25 * K2[ia];
+      if (!embed) val = hr;
+      else val = (qa == qb) ? hr : (qa == 0 ? -hi : hi);
+    }
+    A[e] = val;
+  }
+}
+
+// ---------------------------------------------------------------- batched cyclic Jacobi
+// One workgroup per fibre.  Round-robin (circle) ordering: in round r the pairs are
+// (n-1, r) and ((r+i) mod (n-1), (r-i) mod (n-1)), i = 1..n/2-1, all disjoint, so a round
+// is A <- J^T A J with J a product of n/2 independent plane rotations.  The update is
+// done one 2x2 block at a time (block (i,j) depends only on rotations i and j), which
+// needs no barrier between the row and the column transformation.  VT holds V^T, so
+// H = V diag(lambda) V^T on exit, eigenvalues in the diagonal of A.
+template <int BS>
+__global__ __launch_bounds__(BS) void k_jacobi(double* Aall, double* VTall, const int64_t* moff,
+                                               const int32_t* ndim, double* lam, const int64_t* loff,
+                                               int32_t* info, int maxsweeps) {
+  const int f = blockIdx.x;
+  const int n = ndim[f];
+  double* A = Aall + moff[f];
+  double* VT = VTall + moff[f];
+  extern __shared__ double sh[];
+  const int np = n / 2;
+  double* rc = sh;
+  double* rs = sh + np;
+  int* rp = reinterpret_cast<int*>(sh + 2 * np);
+  int* rq = rp + np;
+  __shared__ double red[BS];
+  __shared__ int rotated;
+  const int tid = threadIdx.x;
+  const int64_t nn = (int64_t)n * n;
+
+  for (int64_t e = tid; e < nn; e += BS) VT[e] = ((e / n) == (e % n)) ? 1.0 : 0.0;
+  double s2 = 0.0;
+  for (int64_t e = tid; e < nn; e += BS) s2 += A[e] * A[e];
+  const double normF = sqrt(block_sum<BS>(s2, red));
+  const double tiny = 1e-18 * normF;
+
+  int sweep = 0;
+  bool done = (n < 2);
+  for (; sweep < maxsweeps && !done; ++sweep) {
+    if (tid == 0) rotated = 0;
+    __syncthreads();
+    const int m = n - 1;
+    for (int r = 0; r < m; ++r) {
+      for (int i = tid; i < np; i += BS) {
+        const int p = (i == 0) ? m : (r + i) % m;
+        const int q = (i == 0) ? r : (r - i + m) % m;
+        const double app = A[(int64_t)p * n + p], aqq = A[(int64_t)q * n + q], apq = A[(int64_t)p * n + q];
+        double c = 1.0, s = 0.0;
+        if (fabs(apq) > 1e-16 * sqrt(fabs(app * aqq)) + tiny) {
+          const double th = (aqq - app) / (2.0 * apq);
+          const double t = (fabs(th) > 1e150) ? 0.5 / th
+                                              : ((th >= 0.0) ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+          c = 1.0 / sqrt(t * t + 1.0);
+          s = t * c;
+          rotated = 1;
+        }
+        rc[i] = c;
+        rs[i] = s;
+        rp[i] = p;
+        rq[i] = q;
+      }
+      __syncthreads();
+      const int nb = np * np;
+      for (int idx = tid; idx < nb; idx += BS) {
+        const int i = idx / np, j = idx - (idx / np) * np;
+        const double ci = rc[i], si = rs[i], cj = rc[j], sj = rs[j];
+        if (si == 0.0 && sj == 0.0) continue;
+        const int64_t p = rp[i], q = rq[i], p2 = rp[j], q2 = rq[j];
+        const double a = A[p * n + p2], b = A[p * n + q2], cc = A[q * n + p2], dd = A[q * n + q2];
+        const double a1 = ci * a - si * cc, b1 = ci * b - si * dd;
+        const double c1 = si * a + ci * cc, d1 = si * b + ci * dd;
+        double a2 = cj * a1 - sj * b1, b2 = sj * a1 + cj * b1;
+        double c2 = cj * c1 - sj * d1, d2 = sj * c1 + cj * d1;
+        if (i == j) {
+          b2 = 0.0;
+          c2 = 0.0;
+        }
+        A[p * n + p2] = a2;
+        A[p * n + q2] = b2;
+        A[q * n + p2] = c2;
+        A[q * n + q2] = d2;
+      }
+      const int nv = np * n;
+      for (int idx = tid; idx < nv; idx += BS) {
+        const int i = idx / n, col = idx - (idx / n) * n;
+        const double s = rs[i];
+        if (s == 0.0) continue;
+        const double c = rc[i];
+        const int64_t p = rp[i], q = rq[i];
+        const double x = VT[p * n + col], y = VT[q * n + col];
+        VT[p * n + col] = c * x - s * y;
+        VT[q * n + col] = s * x + c * y;
+      }
+      __syncthreads();
+    }
+    done = (rotated == 0);
+    __syncthreads();
+  }
+  for (int k = tid; k < n; k += BS) lam[loff[f] + k] = A[(int64_t)k * n + k];
+  if (tid == 0) info[f] = done ? sweep : -1;
+}
+
+__global__ void k_eig_phase(int64_t nlam, const double* lam, double t, double2* cs) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nlam) {
+    double s, c;
+    sincos(t * lam[i], &s, &c);
+    cs[i] = make_double2(c, s);
+  }
+}
+
+// ---------------------------------------------------------------- propagator formation
+// P(t)[a][b] = sum_k V[a][k] exp(-i t lambda_k) V[b][k]; for an embedded complex H the
+// blocks of cos(tM) and sin(tM) give P = (C_A + S_B) + i (C_B - S_A).
+template <int FMT>
+__global__ void k_form(const int32_t* ptr, const double* VTall, const int64_t* moff, const int32_t* ndim,
+                       const int32_t* embed, const double2* csall, const int64_t* loff, void* Pall,
+                       const int64_t* poff, double2* diag) {
+  const int f = blockIdx.x;
+  const int r0 = ptr[f], L = ptr[f + 1] - r0;
+  const int n = ndim[f];
+  const int emb = embed[f];
+  const double* VT = VTall + moff[f];
+  const double2* cs = csall + loff[f];
+  char* P = reinterpret_cast<char*>(Pall) + poff[f];
+  const int LL = L * L;
+  for (int e = blockIdx.y * blockDim.x + threadIdx.x; e < LL; e += gridDim.y * blockDim.x) {
+    const int a = e / L, b = e - (e / L) * L;
+    double CA = 0.0, SA = 0.0, CB = 0.0, SB = 0.0;
+    for (int k = 0; k < n; ++k) {
+      const double2 c = cs[k];
+      const double v = VT[(int64_t)k * n + b];
+      const double uv = VT[(int64_t)k * n + a] * v;
+      CA += uv * c.x;
+      SA += uv * c.y;
+      if (emb) {
+        const double u2v = VT[(int64_t)k * n + L + a] * v;
+        CB += u2v * c.x;
+        SB += u2v * c.y;
+      }
+    }
+    const double pr = CA + SB, pi = CB - SA;
+    if (FMT == PF_F64) {
+      const int Lp = (L + 15) & ~15;
+      const int64_t idx = ((int64_t)(a >> 4) * (Lp >> 2) + (b >> 2)) * 64 + (a & 15) + 16 * (b & 3);
+      reinterpret_cast<double2*>(P)[idx] = make_double2(pr, pi);
+    } else if (a == b) {
+      diag[r0 + a] = make_double2(pr, pi);
+    } else if (FMT == PF_F32) {
+      const int Lp = (L + 15) & ~15;
+      const int64_t idx = ((int64_t)(a >> 4) * (Lp >> 2) + (b >> 2)) * 64 + (a & 15) + 16 * (b & 3);
+      reinterpret_cast<float2*>(P)[idx] = make_float2((float)pr, (float)pi);
+    } else {
+      const int Lp = (L + 31) & ~31;
+      const int64_t chunk = (int64_t)(a >> 4) * (Lp >> 5) + (b >> 5);
+      const int lane = (a & 15) + 16 * ((b & 31) >> 3), el = b & 7;
+      unsigned short* Q = reinterpret_cast<unsigned short*>(P);
+      unsigned short t[6];
+      split3(pr, t[0], t[2], t[4]);
+      split3(pi, t[1], t[3], t[5]);
+#pragma unroll
+      for (int pl = 0; pl < 6; ++pl) Q[((chunk * 6 + pl) * 64 + lane) * 8 + el] = t[pl];
+    }
+  }
+}
+
+// ---------------------------------------------------------------- kinetic phase
+__global__ void k_phase_table(int64_t N, const double* K2, double scale, double2* ph) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N) {
+    double s, c;
+    sincos(scale * K2[i], &s, &c);
+    ph[i] = make_double2(c, -s);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_phase_apply(int64_t N, int W, const double2* __restrict__ ph,
+                                                     double2* __restrict__ c) {
+  const int64_t total = N * (int64_t)W;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+    const double2 p = ph[e / W];
+    const double2 x = c[e];
+    c[e] = make_double2(p.x * x.x - p.y * x.y, p.x * x.y + p.y * x.x);
+  }
+}
+
+// ---------------------------------------------------------------- fibre-pass epilogue
+// acc[nb][0/1][r]: this lane's part of the 16x16 output blocks, column lane%16 and
+// row 4*(lane/16)+r for the FP32-accumulating MFMAs, row 4*r+lane/16 for
+// v_mfma_f64_16x16x4f64 (ROWS_F64).  Summed over the KS waves in fixed order and
+// stored; mixed formats add the FP64 diagonal term d_a x_a.
+template <int NB, int KS, bool MIX, bool ROWS_F64>
+__device__ __forceinline__ void pass_epilogue(const PassArgs& a, double (&acc)[NB][2][4], int f, int rb,
+                                              int wb, double* red) {
+  const int lane = threadIdx.x & 63, kw = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int r0 = a.ptr[f], L = a.ptr[f + 1] - r0;
+  const int W = a.W;
+  if (KS > 1) {
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) red[(((kw * NB + nb) * 2 + c) * 4 + r) * 64 + lane] = acc[nb][c][r];
+    __syncthreads();
+  }
+  for (int r = (KS > 1 ? kw : 0); r < 4; r += KS) {
+    const int arow = 16 * rb + (ROWS_F64 ? 4 * r + lk : 4 * lk + r);
+    if (arow >= L) continue;
+    const int64_t row = a.rows[r0 + arow];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const int w = (wb * NB + nb) * 16 + li;
+      if (w >= W) continue;
+      double yr, yi;
+      if (KS > 1) {
+        yr = 0.0;
+        yi = 0.0;
+        for (int j = 0; j < KS; ++j) {
+          yr += red[(((j * NB + nb) * 2 + 0) * 4 + r) * 64 + lane];
+          yi += red[(((j * NB + nb) * 2 + 1) * 4 + r) * 64 + lane];
+        }
+      } else {
+        yr = acc[nb][0][r];
+        yi = acc[nb][1][r];
+      }
+      if (MIX) {
+        const double2 dg = a.diag[r0 + arow];
+        const double2 x = a.X[row * W + w];
+        yr += dg.x * x.x - dg.y * x.y;
+        yi += dg.x * x.y + dg.y * x.x;
+      }
+      a.Y[row * W + w] = make_double2(yr, yi);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- FP64 fibre pass (MFMA)
+// Tile = (fibre f, 16 output rows rb, 16*NB columns wb); KS waves split the k range.
+template <int NB, int KS>
+__global__ __launch_bounds__(64 * KS) void k_pass_f64(PassArgs a) {
+  extern __shared__ double red[];
+  const int4 t = a.tiles[blockIdx.x];
+  const int f = t.x, rb = t.y, wb = t.z;
+  const int r0 = a.ptr[f], L = a.ptr[f + 1] - r0;
+  const int nks = ((L + 15) & ~15) >> 2;
+  const int lane = threadIdx.x & 63, kw = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int W = a.W;
+  const double2* P = reinterpret_cast<const double2*>(reinterpret_cast<const char*>(a.P) + a.poff[f]) +
+                     (int64_t)rb * nks * 64 + lane;
+  const int32_t* rows = a.rows + r0;
+  int wc[NB];
+  bool wok[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    wc[nb] = (wb * NB + nb) * 16 + li;
+    wok[nb] = wc[nb] < W;
+  }
+  v4d cr[NB], ci[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    cr[nb] = (v4d){0.0, 0.0, 0.0, 0.0};
+    ci[nb] = (v4d){0.0, 0.0, 0.0, 0.0};
+  }
+  for (int ks = kw; ks < nks; ks += KS) {
+    const double2 p = P[(int64_t)ks * 64];
+    const int k = 4 * ks + lk;
+    const bool kok = k < L;
+    const int64_t xb = kok ? (int64_t)rows[k] * W : 0;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      double2 x = make_double2(0.0, 0.0);
+      if (kok && wok[nb]) x = a.X[xb + wc[nb]];
+      cr[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(p.x, x.x, cr[nb], 0, 0, 0);
+      cr[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-p.y, x.y, cr[nb], 0, 0, 0);
+      ci[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(p.x, x.y, ci[nb], 0, 0, 0);
+      ci[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(p.y, x.x, ci[nb], 0, 0, 0);
+    }
+  }
+  double acc[NB][2][4];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      acc[nb][0][r] = cr[nb][r];
+      acc[nb][1][r] = ci[nb][r];
+    }
+  pass_epilogue<NB, KS, false, true>(a, acc, f, rb, wb, red);
+}
+
+// ---------------------------------------------------------------- mixed FP32 fibre pass (MFMA)
+// y = d .* x (FP64) + E x~ with E complex64, x~ = fp32(x), FP32 MFMA accumulation.
+template <int NB, int KS>
+__global__ __launch_bounds__(64 * KS) void k_pass_f32(PassArgs a) {
+  extern __shared__ double red[];
+  const int4 t = a.tiles[blockIdx.x];
+  const int f = t.x, rb = t.y, wb = t.z;
+  const int r0 = a.ptr[f], L = a.ptr[f + 1] - r0;
+  const int nks = ((L + 15) & ~15) >> 2;
+  const int lane = threadIdx.x & 63, kw = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int W = a.W;
+  const float2* P = reinterpret_cast<const float2*>(reinterpret_cast<const char*>(a.P) + a.poff[f]) +
+                    (int64_t)rb * nks * 64 + lane;
+  const int32_t* rows = a.rows + r0;
+  int wc[NB];
+  bool wok[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    wc[nb] = (wb * NB + nb) * 16 + li;
+    wok[nb] = wc[nb] < W;
+  }
+  v4f cr[NB], ci[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    cr[nb] = (v4f){0.f, 0.f, 0.f, 0.f};
+    ci[nb] = (v4f){0.f, 0.f, 0.f, 0.f};
+  }
+  for (int ks = kw; ks < nks; ks += KS) {
+    const float2 p = P[(int64_t)ks * 64];
+    const int k = 4 * ks + lk;
+    const bool kok = k < L;
+    const int64_t xb = kok ? (int64_t)rows[k] * W : 0;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      double2 x = make_double2(0.0, 0.0);
+      if (kok && wok[nb]) x = a.X[xb + wc[nb]];
+      const float xr = (float)x.x, xi = (float)x.y;
+      cr[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(p.x, xr, cr[nb], 0, 0, 0);
+      cr[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(-p.y, xi, cr[nb], 0, 0, 0);
+      ci[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(p.x, xi, ci[nb], 0, 0, 0);
+      ci[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(p.y, xr, ci[nb], 0, 0, 0);
+    }
+  }
+  double acc[NB][2][4];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      acc[nb][0][r] = (double)cr[nb][r];
+      acc[nb][1][r] = (double)ci[nb][r];
+    }
+  pass_epilogue<NB, KS, true, false>(a, acc, f, rb, wb, red);
+}
+
+// ---------------------------------------------------------------- mixed BF16x3 fibre pass (MFMA)
+// E = E0+E1+E2 and x~ = x0+x1+x2 (bf16 terms); the six products E0x0, E0x1, E1x0, E0x2,
+// E1x1, E2x0 on v_mfma_f32_16x16x32_bf16 with FP32 accumulation, plus the FP64 diagonal.
+__device__ __forceinline__ v8bf as_bf(const v8u16& u) { return __builtin_bit_cast(v8bf, u); }
+
+template <int NB, int KS>
+__global__ __launch_bounds__(64 * KS) void k_pass_bf16x3(PassArgs a) {
+  extern __shared__ double red[];
+  const int4 t = a.tiles[blockIdx.x];
+  const int f = t.x, rb = t.y, wb = t.z;
+  const int r0 = a.ptr[f], L = a.ptr[f + 1] - r0;
+  const int nkc = ((L + 31) & ~31) >> 5;
+  const int lane = threadIdx.x & 63, kw = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int W = a.W;
+  const v8u16* P = reinterpret_cast<const v8u16*>(reinterpret_cast<const char*>(a.P) + a.poff[f]) +
+                   (int64_t)rb * nkc * 6 * 64 + lane;
+  const int32_t* rows = a.rows + r0;
+  int wc[NB];
+  bool wok[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    wc[nb] = (wb * NB + nb) * 16 + li;
+    wok[nb] = wc[nb] < W;
+  }
+  v4f cr[NB], ci[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    cr[nb] = (v4f){0.f, 0.f, 0.f, 0.f};
+    ci[nb] = (v4f){0.f, 0.f, 0.f, 0.f};
+  }
+  for (int kc = kw; kc < nkc; kc += KS) {
+    // E planes: term0 re, term0 im, term1 re, term1 im, term2 re, term2 im
+    const v8u16* Pc = P + (int64_t)kc * 6 * 64;
+    const v8bf er0 = as_bf(Pc[0]), ei0 = as_bf(Pc[64]);
+    const v8bf er1 = as_bf(Pc[128]), ei1 = as_bf(Pc[192]);
+    const v8bf er2 = as_bf(Pc[256]), ei2 = as_bf(Pc[320]);
+    const int kbase = 32 * kc + 8 * lk;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      v8u16 xr0, xr1, xr2, xi0, xi1, xi2;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int k = kbase + e;
+        double2 x = make_double2(0.0, 0.0);
+        if (k < L && wok[nb]) x = a.X[(int64_t)rows[k] * W + wc[nb]];
+        unsigned short a0, a1, a2, b0, b1, b2;
+        split3f((float)x.x, a0, a1, a2);
+        split3f((float)x.y, b0, b1, b2);
+        xr0[e] = a0; xr1[e] = a1; xr2[e] = a2;
+        xi0[e] = b0; xi1[e] = b1; xi2[e] = b2;
+      }
+      const v8u16 sgn = (v8u16){0x8000, 0x8000, 0x8000, 0x8000, 0x8000, 0x8000, 0x8000, 0x8000};
+      const v8bf Xr0 = as_bf(xr0), Xr1 = as_bf(xr1), Xr2 = as_bf(xr2);
+      const v8bf Xi0 = as_bf(xi0), Xi1 = as_bf(xi1), Xi2 = as_bf(xi2);
+      const v8bf Xn0 = as_bf(xi0 ^ sgn), Xn1 = as_bf(xi1 ^ sgn), Xn2 = as_bf(xi2 ^ sgn);
+      // real part: Er Xr - Ei Xi, smallest terms first
+      v4f c = cr[nb];
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(er2, Xr0, c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(er1, Xr1, c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(er0, Xr2, c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ei2, Xn0, c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ei1, Xn1, c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ei0, Xn2, c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(er1, Xr0, c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(er0, Xr1, c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ei1, Xn0, c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ei0, Xn1, c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(er0, Xr0, c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ei0, Xn0, c, 0, 0, 0);
+      cr[nb] = c;
+      // imaginary part: Er Xi + Ei Xr
+      v4f d = ci[nb];
+      d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(er2, Xi0, d, 0, 0, 0);
+      d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(er1, Xi1, d, 0, 0, 0);
+      d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(er0, Xi2, d, 0, 0, 0);
+      d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ei2, Xr0, d, 0, 0, 0);
+      d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ei1, Xr1, d, 0, 0, 0);
+      d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ei0, Xr2, d, 0, 0, 0);
+      d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(er1, Xi0, d, 0, 0, 0);
+      d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(er0, Xi1, d, 0, 0, 0);
+      d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ei1, Xr0, d, 0, 0, 0);
+      d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ei0, Xr1, d, 0, 0, 0);
+      d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(er0, Xi0, d, 0, 0, 0);
+      d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ei0, Xr0, d, 0, 0, 0);
+      ci[nb] = d;
+    }
+  }
+  double acc[NB][2][4];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      acc[nb][0][r] = (double)cr[nb][r];
+      acc[nb][1][r] = (double)ci[nb][r];
+    }
+  pass_epilogue<NB, KS, true, false>(a, acc, f, rb, wb, red);
+}
+
+// ---------------------------------------------------------------- single-state fibre pass (W = 1)
+// HBM-bound GEMV: each propagator entry is read once per pass.  Lane (li, lk) of chunk
+// (rb, k) multiplies entry (16rb+li, col) by x[col]; the four k-lanes and the KS waves
+// are summed in fixed order.  Mixed formats: E entries (rounded to their storage
+// precision) times the FP64 state, FP64 accumulation, plus the FP64 diagonal term.
+template <int KS, int FMT>
+__global__ __launch_bounds__(64 * KS) void k_gemv(PassArgs a) {
+  __shared__ double red[2 * KS * 16];
+  const int4 t = a.tiles[blockIdx.x];
+  const int f = t.x, rb = t.y;
+  const int r0 = a.ptr[f], L = a.ptr[f + 1] - r0;
+  const int lane = threadIdx.x & 63, kw = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int32_t* rows = a.rows + r0;
+  const char* Pb = reinterpret_cast<const char*>(a.P) + a.poff[f];
+  double yr = 0.0, yi = 0.0;
+  if (FMT == PF_BF16X3) {
+    const int nkc = ((L + 31) & ~31) >> 5;
+    const v8u16* P = reinterpret_cast<const v8u16*>(Pb) + (int64_t)rb * nkc * 6 * 64 + lane;
+    for (int kc = kw; kc < nkc; kc += KS) {
+      const v8u16* Pc = P + (int64_t)kc * 6 * 64;
+      const v8u16 r0v = Pc[0], i0v = Pc[64], r1v = Pc[128], i1v = Pc[192], r2v = Pc[256], i2v = Pc[320];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int k = 32 * kc + 8 * lk + e;
+        if (k < L) {
+          const double2 x = a.X[rows[k]];
+          const double er = (double)(bf2f(r0v[e]) + bf2f(r1v[e]) + bf2f(r2v[e]));
+          const double ei = (double)(bf2f(i0v[e]) + bf2f(i1v[e]) + bf2f(i2v[e]));
+          yr += er * x.x - ei * x.y;
+          yi += er * x.y + ei * x.x;
+        }
+      }
+    }
+  } else {
+    const int nks = ((L + 15) & ~15) >> 2;
+    for (int ks = kw; ks < nks; ks += KS) {
+      const int k = 4 * ks + lk;
+      double pr, pi;
+      if (FMT == PF_F64) {
+        const double2 p = reinterpret_cast<const double2*>(Pb)[((int64_t)rb * nks + ks) * 64 + lane];
+        pr = p.x;
+        pi = p.y;
+      } else {
+        const float2 p = reinterpret_cast<const float2*>(Pb)[((int64_t)rb * nks + ks) * 64 + lane];
+        pr = p.x;
+        pi = p.y;
+      }
+      if (k < L) {
+        const double2 x = a.X[rows[k]];
+        yr += pr * x.x - pi * x.y;
+        yi += pr * x.y + pi * x.x;
+      }
+    }
+  }
+  // sum the four k-lanes of each row (lanes li, li+16, li+32, li+48)
+  yr += __shfl_xor(yr, 16);
+  yi += __shfl_xor(yi, 16);
+  yr += __shfl_xor(yr, 32);
+  yi += __shfl_xor(yi, 32);
+  if (lk == 0) {
+    red[(kw * 2 + 0) * 16 + li] = yr;
+    red[(kw * 2 + 1) * 16 + li] = yi;
+  }
+  __syncthreads();
+  if (threadIdx.x < 16) {
+    const int arow = 16 * rb + li;
+    if (arow < L) {
+      double sr = 0.0, si = 0.0;
+      for (int j = 0; j < KS; ++j) {
+        sr += red[(j * 2 + 0) * 16 + li];
+        si += red[(j * 2 + 1) * 16 + li];
+      }
+      const int64_t row = rows[arow];
+      if (FMT != PF_F64) {
+        const double2 dg = a.diag[r0 + arow];
+        const double2 x = a.X[row];
+        sr += dg.x * x.x - dg.y * x.y;
+        si += dg.x * x.y + dg.y * x.x;
+      }
+      a.Y[row] = make_double2(sr, si);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- FP64 reductions
+// kind 0: |c|^2;  kind 1: 1/2 K2 |c|^2 + Re conj(c_iw) sum_p v_p c_{nbr(i,p), w} (both layers)
+__global__ __launch_bounds__(256) void k_reduce_partial(int kind, int64_t N, int W, const double2* c,
+                                                        const double* K2, int nv1, const int32_t* nbr1,
+                                                        const double2* v1, int nv2, const int32_t* nbr2,
+                                                        const double2* v2, double* partial, int R) {
+  __shared__ double red[256];
+  const int b = blockIdx.x;
+  const int64_t i0 = (int64_t)b * R;
+  const int64_t i1 = min(N, i0 + R);
+  const int WB = W < 256 ? W : 256;
+  const int S = 256 / WB;
+  const int tid = threadIdx.x;
+  for (int w0 = 0; w0 < W; w0 += WB) {
+    const int w = w0 + tid % WB, s = tid / WB;
+    double acc = 0.0;
+    if (w < W && s < S) {
+      for (int64_t i = i0 + s; i < i1; i += S) {
+        const double2 x = c[i * W + w];
+        const double m2 = x.x * x.x + x.y * x.y;
+        if (kind == 0) {
+          acc += m2;
+        } else {
+          double hr = 0.0, hi = 0.0;
+          for (int p = 0; p < nv1; ++p) {
+            const int j = nbr1[i * nv1 + p];
+            if (j >= 0) {
+              const double2 y = c[(int64_t)j * W + w], v = v1[p];
+              hr += v.x * y.x - v.y * y.y;
+              hi += v.x * y.y + v.y * y.x;
+            }
+          }
+          for (int p = 0; p < nv2; ++p) {
+            const int j = nbr2[i * nv2 + p];
+            if (j >= 0) {
+              const double2 y = c[(int64_t)j * W + w], v = v2[p];
+              hr += v.x * y.x - v.y * y.y;
+              hi += v.x * y.y + v.y * y.x;
+            }
+          }
+          acc += 0.5 * K2[i] * m2 + (x.x * hr + x.y * hi);
+        }
+      }
+    }
+    red[tid] = acc;
+    __syncthreads();
+    if (tid < WB && w0 + tid < W) {
+      double sum = 0.0;
+      for (int j = 0; j < S; ++j) sum += red[j * WB + tid];
+      partial[(int64_t)b * W + w0 + tid] = sum;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_reduce_final(int nblocks, int W, const double* partial, double* out) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w < W) {
+    double s = 0.0;
+    for (int b = 0; b < nblocks; ++b) s += partial[(int64_t)b * W + w];
+    out[w] = s;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_fibre_mass(const int32_t* ptr, const int32_t* rows, int W,
+                                                    const double2* c, double* out) {
+  __shared__ double red[256];
+  const int f = blockIdx.x;
+  const int r0 = ptr[f], L = ptr[f + 1] - r0;
+  const int WB = W < 256 ? W : 256;
+  const int S = 256 / WB;
+  const int tid = threadIdx.x;
+  for (int w0 = 0; w0 < W; w0 += WB) {
+    const int w = w0 + tid % WB, s = tid / WB;
+    double acc = 0.0;
+    if (w < W && s < S)
+      for (int a = s; a < L; a += S) {
+        const double2 x = c[(int64_t)rows[r0 + a] * W + w];
+        acc += x.x * x.x + x.y * x.y;
+      }
+    red[tid] = acc;
+    __syncthreads();
+    if (tid < WB && w0 + tid < W) {
+      double sum = 0.0;
+      for (int j = 0; j < S; ++j) sum += red[j * WB + tid];
+      out[(int64_t)f * W + w0 + tid] = sum;
+    }
+    __syncthreads();
+  }
+}
+
+// ================================================================ launchers
+hipError_t launch_assemble(hipStream_t s, int nf, const int32_t* ptr, const int32_t* rows, const int32_t* mn,
+                           int d, int layer, const double* K2, int nv, const int32_t* vidx, const double* vre,
+                           const double* vim, double kappa, int embed, double* A, const int64_t* moff,
+                           const int32_t* ndim) {
+  hipLaunchKernelGGL(k_assemble, dim3(nf), dim3(256), 0, s, ptr, rows, mn, d, layer, K2, nv, vidx, vre, vim,
+                     kappa, embed, A, moff, ndim);
+  return hipGetLastError();
+}
+
+hipError_t launch_jacobi(hipStream_t s, int nf, int maxn, double* A, double* VT, const int64_t* moff,
+                         const int32_t* ndim, double* lam, const int64_t* loff, int32_t* info, int maxsweeps) {
+  const size_t shm = (size_t)(maxn / 2) * (2 * sizeof(double) + 2 * sizeof(int));
+  if (maxn > 256)
+    hipLaunchKernelGGL(k_jacobi<1024>, dim3(nf), dim3(1024), shm, s, A, VT, moff, ndim, lam, loff, info,
+                       maxsweeps);
+  else
+    hipLaunchKernelGGL(k_jacobi<256>, dim3(nf), dim3(256), shm, s, A, VT, moff, ndim, lam, loff, info,
+                       maxsweeps);
+  return hipGetLastError();
+}
+
+hipError_t launch_eig_phase(hipStream_t s, int64_t nlam, const double* lam, double t, double2* cs) {
+  if (nlam == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_eig_phase, dim3((unsigned)((nlam + 255) / 256)), dim3(256), 0, s, nlam, lam, t, cs);
+  return hipGetLastError();
+}
+
+hipError_t launch_form(hipStream_t s, int fmt, int nf, int maxL, const int32_t* ptr, const double* VT,
+                       const int64_t* moff, const int32_t* ndim, const int32_t* embed, const double2* cs,
+                       const int64_t* loff, void* P, const int64_t* poff, double2* diag) {
+  const int64_t maxLL = (int64_t)maxL * maxL;
+  const unsigned gy = (unsigned)std::max<int64_t>(1, std::min<int64_t>((maxLL + 255) / 256, 4096));
+  const dim3 g(nf, gy);
+  if (fmt == PF_F64)
+    hipLaunchKernelGGL(k_form<PF_F64>, g, dim3(256), 0, s, ptr, VT, moff, ndim, embed, cs, loff, P, poff, diag);
+  else if (fmt == PF_F32)
+    hipLaunchKernelGGL(k_form<PF_F32>, g, dim3(256), 0, s, ptr, VT, moff, ndim, embed, cs, loff, P, poff, diag);
+  else
+    hipLaunchKernelGGL(k_form<PF_BF16X3>, g, dim3(256), 0, s, ptr, VT, moff, ndim, embed, cs, loff, P, poff,
+                       diag);
+  return hipGetLastError();
+}
+
+hipError_t launch_phase_table(hipStream_t s, int64_t N, const double* K2, double scale, double2* ph) {
+  hipLaunchKernelGGL(k_phase_table, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, N, K2, scale, ph);
+  return hipGetLastError();
+}
+
+hipError_t launch_phase_apply(hipStream_t s, int64_t N, int W, const double2* ph, double2* c) {
+  const int64_t total = N * (int64_t)W;
+  const unsigned grid = (unsigned)std::min<int64_t>((total + 255) / 256, 256 * 64);
+  hipLaunchKernelGGL(k_phase_apply, dim3(grid), dim3(256), 0, s, N, W, ph, c);
+  return hipGetLastError();
+}
+
+template <int NB, int KS>
+static hipError_t launch_mfma(hipStream_t s, int fmt, int ntiles, const PassArgs& a) {
+  const size_t shm = KS > 1 ? (size_t)KS * NB * 2 * 4 * 64 * sizeof(double) : 0;
+  if (fmt == PF_F64)
+    hipLaunchKernelGGL((k_pass_f64<NB, KS>), dim3(ntiles), dim3(64 * KS), shm, s, a);
+  else if (fmt == PF_F32)
+    hipLaunchKernelGGL((k_pass_f32<NB, KS>), dim3(ntiles), dim3(64 * KS), shm, s, a);
+  else
+    hipLaunchKernelGGL((k_pass_bf16x3<NB, KS>), dim3(ntiles), dim3(64 * KS), shm, s, a);
+  return hipGetLastError();
+}
+
+template <int KS>
+static hipError_t launch_gemv(hipStream_t s, int fmt, int ntiles, const PassArgs& a) {
+  if (fmt == PF_F64)
+    hipLaunchKernelGGL((k_gemv<KS, PF_F64>), dim3(ntiles), dim3(64 * KS), 0, s, a);
+  else if (fmt == PF_F32)
+    hipLaunchKernelGGL((k_gemv<KS, PF_F32>), dim3(ntiles), dim3(64 * KS), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_gemv<KS, PF_BF16X3>), dim3(ntiles), dim3(64 * KS), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_pass(hipStream_t s, int fmt, int W, int ntiles, int nb, int ksplit, const PassArgs& a) {
+  if (ntiles == 0) return hipSuccess;
+  if (W == 1) {
+    switch (ksplit) {
+      case 1: return launch_gemv<1>(s, fmt, ntiles, a);
+      case 2: return launch_gemv<2>(s, fmt, ntiles, a);
+      default: return launch_gemv<4>(s, fmt, ntiles, a);
+    }
+  }
+#define LSX_MFMA_CASE(NB_, KS_) \
+  if (nb == NB_ && ksplit == KS_) return launch_mfma<NB_, KS_>(s, fmt, ntiles, a);
+  LSX_MFMA_CASE(1, 1)
+  LSX_MFMA_CASE(1, 2)
+  LSX_MFMA_CASE(1, 4)
+  LSX_MFMA_CASE(2, 1)
+  LSX_MFMA_CASE(2, 2)
+  LSX_MFMA_CASE(2, 4)
+  LSX_MFMA_CASE(4, 1)
+  LSX_MFMA_CASE(4, 2)
+  LSX_MFMA_CASE(4, 4)
+#undef LSX_MFMA_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_reduce(hipStream_t s, int kind, int64_t N, int W, const double2* c, const double* K2, int nv1,
+                         const int32_t* nbr1, const double2* v1, int nv2, const int32_t* nbr2, const double2* v2,
+                         double* partial, int nblocks, double* out) {
+  const int R = (int)((N + nblocks - 1) / nblocks);
+  hipLaunchKernelGGL(k_reduce_partial, dim3(nblocks), dim3(256), 0, s, kind, N, W, c, K2, nv1, nbr1, v1, nv2,
+                     nbr2, v2, partial, R);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_reduce_final, dim3((W + 255) / 256), dim3(256), 0, s, nblocks, W, partial, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_fibre_mass(hipStream_t s, int nf, const int32_t* ptr, const int32_t* rows, int W,
+                             const double2* c, double* out) {
+  if (nf == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fibre_mass, dim3(nf), dim3(256), 0, s, ptr, rows, W, c, out);
+  return hipGetLastError();
+}
+
+}  // namespace lsx

@@ -1,0 +1,227 @@
+"""ctypes binding of liblsx.so (argument marshalling only).
+
+Every function of ``include/lsx.h`` is exposed under the same name with the same
+arguments; the classes ``System``, ``Plan`` and ``State`` only hold handles and
+call those functions.  All computation happens in the HIP library; importing
+this module does not load it, the first call does, and it raises if the library
+has not been built (``python -m paper_2103_14897_amd.build``).
+
+Device memory and streams may come from PyTorch: pass ``tensor.data_ptr()`` of a
+contiguous complex128 CUDA tensor of shape [N, W] to ``State(..., dev_ptr=...)``
+and ``torch.cuda.current_stream().cuda_stream`` as a stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liblsx.so")
+
+LSX_OK, LSX_E_INVALID, LSX_E_NOT_HERMITIAN, LSX_E_OOM, LSX_E_HIP, LSX_E_EIG, LSX_E_NONFINITE, LSX_E_STATE = (
+    0, -1, -2, -3, -4, -5, -6, -7)
+CUTOFF = {"ball": 0, "product": 1}
+SCHEME = {"lie": 0, "strang": 1}
+PRECISION = {"fp64": 0, "mix_fp32": 1, "mix_bf16x3": 2}
+OBS_MASS, OBS_ENERGY, OBS_FIBRE_MASS_1, OBS_FIBRE_MASS_2 = 1, 2, 4, 8
+
+_lib = None
+
+_p = C.c_void_p
+_i32p = C.POINTER(C.c_int32)
+_i64p = C.POINTER(C.c_int64)
+_dp = C.POINTER(C.c_double)
+
+_SIGS = {
+    "lsx_last_error": (C.c_char_p, []),
+    "lsx_system_create": (C.c_int, [C.c_int32, _dp, _dp, C.c_double, C.c_int32,
+                                    C.c_int32, _i32p, _dp, _dp, C.c_int32, _i32p, _dp, _dp, C.POINTER(_p)]),
+    "lsx_system_size": (C.c_int, [_p, _i64p, _i64p, _i64p]),
+    "lsx_index_get": (C.c_int, [_p, _i32p]),
+    "lsx_fibre_get": (C.c_int, [_p, C.c_int32, _i32p, _i32p]),
+    "lsx_system_destroy": (C.c_int, [_p]),
+    "lsx_plan_create": (C.c_int, [_p, C.c_double, C.c_int32, C.c_double, C.c_int32, _p, C.POINTER(_p)]),
+    "lsx_plan_propagator": (C.c_int, [_p, C.c_int32, C.c_int32, C.c_int32, _dp, _p]),
+    "lsx_plan_destroy": (C.c_int, [_p]),
+    "lsx_state_create": (C.c_int, [_p, C.c_int32, _p, C.POINTER(_p)]),
+    "lsx_state_upload": (C.c_int, [_p, _dp, _p]),
+    "lsx_state_download": (C.c_int, [_p, _dp, _p]),
+    "lsx_state_device_ptr": (C.c_int, [_p, C.POINTER(_p)]),
+    "lsx_state_destroy": (C.c_int, [_p]),
+    "lsx_step": (C.c_int, [_p, _p, C.c_int64, _p]),
+    "lsx_fibre_pass": (C.c_int, [_p, _p, C.c_int32, C.c_int32, C.c_int32, _p]),
+    "lsx_phase": (C.c_int, [_p, _p, C.c_int32, _p]),
+    "lsx_observables": (C.c_int, [_p, _p, C.c_uint32, _dp, _p]),
+}
+
+
+class LsxError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"lsx error {code}: {msg}")
+        self.code = code
+
+
+def lib():
+    """Load liblsx.so (once) and declare the C signatures."""
+    global _lib
+    if _lib is None:
+        # One HIP runtime per process: when PyTorch is installed its bundled
+        # libamdhip64.so.7 is loaded first, so liblsx.so (same SONAME) binds to it and
+        # torch streams / device pointers are valid in the library.
+        try:
+            import torch  # noqa: F401
+        except ImportError:  # pragma: no cover
+            pass
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2103_14897_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(code):
+    if code != LSX_OK:
+        raise LsxError(code, lib().lsx_last_error().decode())
+
+
+def _stream(s):
+    if s is None:
+        return None
+    if hasattr(s, "cuda_stream"):
+        return _p(s.cuda_stream)
+    return _p(int(s))
+
+
+def _dptr(a):
+    return a.ctypes.data_as(_dp)
+
+
+class System:
+    """lsx_system: lattices, potentials and the lifted cutoff set (host only)."""
+
+    def __init__(self, d, A1, A2, Ec, cutoff="ball", pot1=None, pot2=None):
+        self.d = int(d)
+        A1 = np.asfortranarray(np.asarray(A1, dtype=np.float64).reshape(d, d)).ravel(order="F")
+        A2 = np.asfortranarray(np.asarray(A2, dtype=np.float64).reshape(d, d)).ravel(order="F")
+        self._keep = []
+        args = []
+        for pot in (pot1 or {}, pot2 or {}):
+            keys = sorted(pot.keys())
+            idx = np.ascontiguousarray(np.array(keys, dtype=np.int32).reshape(len(keys), d))
+            vals = np.array([complex(pot[k]) for k in keys], dtype=np.complex128)
+            re, im = np.ascontiguousarray(vals.real), np.ascontiguousarray(vals.imag)
+            self._keep += [idx, re, im]
+            args += [len(keys), idx.ctypes.data_as(_i32p), _dptr(re), _dptr(im)]
+        h = _p()
+        _check(lib().lsx_system_create(self.d, _dptr(A1), _dptr(A2), float(Ec), CUTOFF[cutoff], *args,
+                                       C.byref(h)))
+        self.h = h
+        N, f1, f2 = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(lib().lsx_system_size(self.h, C.byref(N), C.byref(f1), C.byref(f2)))
+        self.N, self.nfibres = N.value, {1: f1.value, 2: f2.value}
+
+    @classmethod
+    def from_spec(cls, spec):
+        return cls(spec.d, spec.A1, spec.A2, spec.Ec, spec.cutoff, spec.pot1, spec.pot2)
+
+    def index(self):
+        mn = np.zeros((self.N, 2 * self.d), dtype=np.int32)
+        _check(lib().lsx_index_get(self.h, mn.ctypes.data_as(_i32p)))
+        return mn
+
+    def fibres(self, layer):
+        ptr = np.zeros(self.nfibres[layer] + 1, dtype=np.int32)
+        rows = np.zeros(self.N, dtype=np.int32)
+        _check(lib().lsx_fibre_get(self.h, layer, ptr.ctypes.data_as(_i32p), rows.ctypes.data_as(_i32p)))
+        return ptr, rows
+
+    def destroy(self):
+        if self.h:
+            _check(lib().lsx_system_destroy(self.h))
+            self.h = None
+
+
+class Plan:
+    """lsx_plan: one-time fibre eigendecomposition and propagators on the GPU."""
+
+    def __init__(self, system, tau, scheme="strang", kappa=0.0, precision="fp64", stream=None):
+        self.system = system
+        self.tau, self.scheme, self.kappa, self.precision = float(tau), scheme, float(kappa), precision
+        h = _p()
+        _check(lib().lsx_plan_create(system.h, self.tau, SCHEME[scheme], self.kappa, PRECISION[precision],
+                                     _stream(stream), C.byref(h)))
+        self.h = h
+
+    def propagator(self, layer, half, fibre, stream=None):
+        ptr, _ = self.system.fibres(layer)
+        L = int(ptr[fibre + 1] - ptr[fibre])
+        out = np.zeros((L, L), dtype=np.complex128)
+        _check(lib().lsx_plan_propagator(self.h, layer, half, fibre, out.ctypes.data_as(_dp), _stream(stream)))
+        return out
+
+    def destroy(self):
+        if self.h:
+            _check(lib().lsx_plan_destroy(self.h))
+            self.h = None
+
+
+class State:
+    """lsx_state: W wavepackets c[N][W] complex128 on the device."""
+
+    def __init__(self, plan, W, dev_ptr=None):
+        self.plan, self.W, self.N = plan, int(W), plan.system.N
+        h = _p()
+        _check(lib().lsx_state_create(plan.h, self.W, _p(dev_ptr) if dev_ptr else None, C.byref(h)))
+        self.h = h
+
+    def upload(self, c, stream=None):
+        c = np.ascontiguousarray(np.asarray(c, dtype=np.complex128).reshape(self.N, self.W))
+        _check(lib().lsx_state_upload(self.h, c.ctypes.data_as(_dp), _stream(stream)))
+        self._pending = c  # kept alive until the next call (stream-ordered copy)
+
+    def download(self, stream=None):
+        out = np.zeros((self.N, self.W), dtype=np.complex128)
+        _check(lib().lsx_state_download(self.h, out.ctypes.data_as(_dp), _stream(stream)))
+        return out
+
+    def device_ptr(self):
+        p = _p()
+        _check(lib().lsx_state_device_ptr(self.h, C.byref(p)))
+        return p.value
+
+    def step(self, nsteps, stream=None):
+        _check(lib().lsx_step(self.plan.h, self.h, int(nsteps), _stream(stream)))
+
+    def fibre_pass(self, layer, half=0, count=1, stream=None):
+        _check(lib().lsx_fibre_pass(self.plan.h, self.h, int(layer), int(half), int(count), _stream(stream)))
+
+    def phase(self, half=0, stream=None):
+        _check(lib().lsx_phase(self.plan.h, self.h, int(half), _stream(stream)))
+
+    def observables(self, mask=OBS_MASS | OBS_ENERGY, stream=None):
+        sys = self.plan.system
+        sizes = [(OBS_MASS, self.W), (OBS_ENERGY, self.W),
+                 (OBS_FIBRE_MASS_1, sys.nfibres[1] * self.W), (OBS_FIBRE_MASS_2, sys.nfibres[2] * self.W)]
+        total = sum(n for bit, n in sizes if mask & bit)
+        out = np.zeros(total, dtype=np.float64)
+        code = lib().lsx_observables(self.plan.h, self.h, int(mask), _dptr(out), _stream(stream))
+        _check(code)
+        res, o = {}, 0
+        names = {OBS_MASS: "mass", OBS_ENERGY: "energy", OBS_FIBRE_MASS_1: "fibre_mass_1",
+                 OBS_FIBRE_MASS_2: "fibre_mass_2"}
+        for bit, n in sizes:
+            if mask & bit:
+                v = out[o:o + n]
+                res[names[bit]] = v.reshape(-1, self.W) if bit >= OBS_FIBRE_MASS_1 else v
+                o += n
+        return res
+
+    def destroy(self):
+        if self.h:
+            _check(lib().lsx_state_destroy(self.h))
+            self.h = None

@@ -1,0 +1,198 @@
+"""GPU parity: the HIP path through the C-ABI against the CPU oracle.
+
+FP64 path bar: relative L2 <= 1e-12 per step (per sub-step for single passes).
+Mixed paths: error vs the oracle reported and bounded (<= 1e-6 after T is the bar
+for the workload runs; single sub-steps are checked at FP32 rounding level).
+"""
+import numpy as np
+import pytest
+
+from oracle import observables, splitting
+from paper_2103_14897_amd import lsx
+from paper_2103_14897_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+ASYM1 = {(1,): 0.6 + 0.45j, (-1,): 0.6 - 0.45j, (2,): 0.2 - 0.1j, (-2,): 0.2 + 0.1j}
+ASYM2 = {(1,): 0.5 - 0.3j, (-1,): 0.5 + 0.3j, (0,): 0.15}
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def colrel(a, b):
+    return (np.linalg.norm(a - b, axis=0) / np.linalg.norm(b, axis=0)).max()
+
+
+def build(spec, tau, scheme="strang", kappa=0.0, precision="fp64"):
+    print(f"[case] {spec.name} cutoff={spec.cutoff} tau={tau} {scheme} kappa={kappa} {precision}", flush=True)
+    S = lsx.System.from_spec(spec)
+    P = lsx.Plan(S, tau, scheme, kappa, precision)
+    O = splitting.Lifted.from_spec(spec)
+    return S, P, O
+
+
+def teardown(*objs):
+    for o in objs:
+        o.destroy()
+
+
+CASES = [
+    (wl.chain_system(200.0), 0.0),
+    (wl.chain_system(200.0), 1.0),
+    (wl.chain_system(971.0, pot1=ASYM1, pot2=ASYM2), 0.0),
+    (wl.chain_system(971.0, pot1=ASYM1, pot2=ASYM2), 0.5),
+    (wl.twisted_system(300.0), 0.0),
+    (wl.chain_system(400.0, cutoff="product"), 1.0),
+]
+IDS = ["tiny-k0", "tiny-k1", "complex-k0", "complex-k05", "twisted300", "product-k1"]
+
+
+@pytest.mark.parametrize("spec,kappa", CASES, ids=IDS)
+def test_propagators_fp64(spec, kappa):
+    S, P, O = build(spec, 0.013, "strang", kappa)
+    plan = splitting.SplitPlan(O, kappa)
+    for layer, half in ((1, 0), (1, 1), (2, 0)):
+        t = 0.013 if half == 0 else 0.0065
+        ref = plan.propagators(layer, t)
+        for f in range(S.nfibres[layer]):
+            got = P.propagator(layer, half, f)
+            assert np.abs(got - ref[f]).max() < 1e-13, (layer, half, f)
+    teardown(P, S)
+
+
+@pytest.mark.parametrize("spec,kappa", CASES, ids=IDS)
+@pytest.mark.parametrize("W", [1, 3, 16, 37, 64])
+def test_single_pass_and_phase_fp64(spec, kappa, W):
+    S, P, O = build(spec, 0.02, "strang", kappa)
+    plan = splitting.SplitPlan(O, kappa)
+    c = wl.random_state(S.N, W, seed=W)
+    st = lsx.State(P, W)
+    for layer, half in ((1, 0), (1, 1), (2, 0)):
+        t = 0.02 if half == 0 else 0.01
+        st.upload(c)
+        st.fibre_pass(layer, half)
+        assert rel(st.download(), plan.apply_fibres(c, layer, t)) < 1e-13, (layer, half)
+    for half in (0, 1):
+        st.upload(c)
+        st.phase(half)
+        t = 0.02 if half == 0 else 0.01
+        assert rel(st.download(), plan.apply_phase(c, t)) < 1e-15
+    teardown(st, P, S)
+
+
+@pytest.mark.parametrize("scheme", ["strang", "lie"])
+@pytest.mark.parametrize("kappa", [0.0, 1.0])
+def test_tiny_chain_trajectory(scheme, kappa):
+    # 1D+1D, Ec = 200, one wavepacket, tau = 0.01 to T = 1 (100 steps)
+    w = wl.tiny_chain()
+    S, P, O = build(w.spec, w.tau, scheme, kappa)
+    plan = splitting.SplitPlan(O, kappa)
+    assert np.array_equal(S.index(), O.mn)
+    c = w.initial_state(O.mn)
+    st = lsx.State(P, 1)
+    st.upload(c)
+    step = plan.strang_step if scheme == "strang" else plan.lie_step
+    ref = c
+    for k in range(1, w.nsteps + 1):
+        prev = st.download()
+        st.step(1)
+        got = st.download()
+        # one step from the same input: <= 1e-12
+        assert rel(got, step(prev, w.tau)) < 1e-12, k
+        ref = step(ref, w.tau)
+    assert rel(st.download(), ref) < 1e-12 * w.nsteps
+    # a single call of all steps (merged half-steps) agrees as well
+    st.upload(c)
+    st.step(w.nsteps)
+    assert rel(st.download(), ref) < 1e-12 * w.nsteps
+    obs = st.observables(lsx.OBS_MASS | lsx.OBS_ENERGY)
+    assert abs(obs["mass"][0] - 1.0) < 1e-12
+    assert abs(obs["energy"][0] - observables.energy(O, ref)[0]) < 1e-10 * abs(obs["energy"][0])
+    teardown(st, P, S)
+
+
+@pytest.mark.parametrize("kappa", [0.0, 1.0])
+def test_chain_64_wavepackets_fp64(kappa):
+    # 1D+1D, Ec = 2e4, 64 wavepackets, tau = 1e-3: 20 steps against the oracle
+    w = wl.chain()
+    S, P, O = build(w.spec, w.tau, "strang", kappa)
+    plan = splitting.SplitPlan(O, kappa)
+    c = w.initial_state(O.mn)
+    st = lsx.State(P, w.W)
+    st.upload(c)
+    st.step(1)
+    assert colrel(st.download(), plan.strang_step(c, w.tau)) < 1e-12
+    st.upload(c)
+    st.step(20)
+    ref = plan.evolve(c, w.tau, 20)
+    assert colrel(st.download(), ref) < 20e-12
+    # reductions against the oracle's observables of the same (downloaded) state
+    got = st.download()
+    obs = st.observables(lsx.OBS_MASS | lsx.OBS_ENERGY | lsx.OBS_FIBRE_MASS_1 | lsx.OBS_FIBRE_MASS_2)
+    assert np.abs(obs["mass"] - observables.mass(got)).max() < 1e-14
+    e_ref = observables.energy(O, got)
+    assert np.abs(obs["energy"] - e_ref).max() < 1e-13 * np.abs(e_ref).max()
+    for layer in (1, 2):
+        fm = observables.fibre_mass(O, got, layer)
+        assert np.abs(obs[f"fibre_mass_{layer}"] - fm).max() < 1e-14
+    # unitarity of the stepped state (Thm 4.4 analogue for exact sub-flows)
+    assert np.abs(obs["mass"] - observables.mass(c)).max() < 1e-13 * 20
+    teardown(st, P, S)
+
+
+@pytest.mark.parametrize("precision,tol_pass", [("mix_fp32", 1e-8), ("mix_bf16x3", 1e-8)])
+@pytest.mark.parametrize("W", [1, 64])
+def test_mixed_single_pass(precision, tol_pass, W):
+    w = wl.chain()
+    S, P, O = build(w.spec, w.tau, "strang", 0.0, precision)
+    plan = splitting.SplitPlan(O, 0.0)
+    c = w.initial_state(O.mn) if W == 64 else wl.random_state(O.N, 1, seed=3)
+    st = lsx.State(P, W)
+    for layer, half in ((1, 0), (1, 1), (2, 0)):
+        t = w.tau if half == 0 else w.tau / 2
+        st.upload(c)
+        st.fibre_pass(layer, half)
+        err = colrel(st.download(), plan.apply_fibres(c, layer, t))
+        print(f"  {precision} W={W} layer {layer} half {half}: rel err {err:.3e}")
+        assert err < tol_pass
+    teardown(st, P, S)
+
+
+@pytest.mark.parametrize("precision", ["mix_fp32", "mix_bf16x3"])
+def test_mixed_chain_full_T(precision):
+    # the metric's bar: mixed path within 1e-6 relative L2 (max over wavepackets) of FP64 after T
+    w = wl.chain()
+    S = lsx.System.from_spec(w.spec)
+    mn = S.index()
+    c = w.initial_state(mn)
+    res = {}
+    for prec in ("fp64", precision):
+        P = lsx.Plan(S, w.tau, "strang", 0.0, prec)
+        st = lsx.State(P, w.W)
+        st.upload(c)
+        st.step(w.nsteps)
+        res[prec] = st.download()
+        teardown(st, P)
+    err = colrel(res[precision], res["fp64"])
+    print(f"  {precision}: rel L2 after T = {err:.3e}")
+    assert err < 1e-6
+    S.destroy()
+
+
+def test_wrapped_torch_tensor_and_stream():
+    import torch
+    w = wl.chain(Ec=971.0, W=8)
+    S, P, O = build(w.spec, w.tau)
+    plan = splitting.SplitPlan(O, 0.0)
+    c = w.initial_state(O.mn)
+    t = torch.from_numpy(c).to("cuda")
+    torch.cuda.synchronize()
+    stream = torch.cuda.Stream()
+    st = lsx.State(P, w.W, dev_ptr=t.data_ptr())
+    with torch.cuda.stream(stream):
+        st.step(5, stream=stream)
+    stream.synchronize()
+    assert colrel(t.cpu().numpy(), plan.evolve(c, w.tau, 5)) < 5e-12
+    teardown(st, P, S)
