@@ -123,8 +123,14 @@ def main():
         k1.record(stream)
         k1.synchronize()
         kus = k0.elapsed_time(k1) * 1e3 / args.kernel_reps
+        k0.record(stream)
+        st.fibre_pass(1, 0, args.kernel_reps, stream)
+        k1.record(stream)
+        k1.synchronize()
+        kus1 = k0.elapsed_time(k1) * 1e3 / args.kernel_reps
         res[path] = {"coeff_steps_per_s": N * W * args.steps / (ms * 1e-3), "ms_per_step": ms / args.steps,
-                     "wall_ms": wall * 1e3, "precompute_s": pre, "layer2_pass_us": kus}
+                     "wall_ms": wall * 1e3, "precompute_s": pre, "layer2_pass_us": kus, "layer1_pass_us": kus1,
+                     "tiles": {"layer1": st.tuning(1)[:2], "layer2": st.tuning(2)[:2]}}
         st.destroy()
         P.destroy()
     ref = finals.get("fp64")

@@ -167,6 +167,15 @@ lsx_status lsx_state_download(lsx_state* st, double* host, void* stream);
  * after a step or pass, so query the address again after such calls. */
 lsx_status lsx_state_device_ptr(const lsx_state* st, void** dev_ptr);
 
+/*
+ * Tile shape chosen for the fibre passes of `layer` (1 or 2) of this state: each
+ * workgroup covers 16 output rows x 16*nb columns with ks waves splitting the fibre
+ * length.  At creation every candidate shape is timed on the state's own size
+ * (LSX_AUTOTUNE=0 disables, LSX_NB / LSX_KS force a shape); pass_us is the measured
+ * time of one pass with the chosen shape (0 if nothing was timed).  Outputs may be NULL.
+ */
+lsx_status lsx_state_tuning(const lsx_state* st, int32_t layer, int32_t* nb, int32_t* ks, double* pass_us);
+
 lsx_status lsx_state_destroy(lsx_state* st);
 
 /*

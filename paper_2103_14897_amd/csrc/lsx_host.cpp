@@ -352,6 +352,7 @@ struct LayerDev {
   int nf = 0;
   int maxL = 0;
   std::vector<int32_t> h_ptr;
+  std::vector<int64_t> h_poff;  // byte offset of each fibre's propagator (same for every t)
   DBuf<int32_t> ptr, rows;
   DBuf<int32_t> nbr;
   DBuf<double2> v;  // stencil values (for the energy)
@@ -365,6 +366,8 @@ struct lsx_plan {
   DBuf<double> K2;
   DBuf<double2> diag;  // mixed formats: per fibre-row diagonal, [layer*2+half] blocks of N
   DBuf<double2> phase[2];  // exp(-i kappa t |K|^2/2) for t = tau, tau/2
+  DBuf<int32_t> pos1;      // position of canonical index i in the layer-1 fibre order
+  DBuf<double2> zero;      // 1 KiB of zeros (out-of-range operand loads of the passes)
   LayerDev L[2];
   int nstates = 0;
 };
@@ -434,6 +437,7 @@ static lsx_status precompute_layer(lsx_plan* pl, int layer, hipStream_t s) {
       bytes += prop_bytes(pl->fmt, ft.ptr[f + 1] - ft.ptr[f]);
       bytes = (bytes + 255) & ~(int64_t)255;
     }
+    ld.h_poff = ps.h_off;
     LSX_TRY(ps.data.alloc(bytes));
     LSX_TRY(ps.off.upload(ps.h_off, s));
     LSX_HIP_TRY(hipMemsetAsync(ps.data.p, 0, bytes, s));
@@ -486,6 +490,17 @@ extern "C" lsx_status lsx_plan_create(lsx_system* sys, double tau, int32_t schem
     std::vector<double2> v(sys->pot[j].nv);
     for (int p = 0; p < sys->pot[j].nv; ++p) v[p] = make_double2(sys->pot[j].re[p], sys->pot[j].im[p]);
     if ((st = ld.v.upload(v, s)) != LSX_OK) return cleanup(st);
+  }
+  {
+    // layer-2 fibres (fixed m) are contiguous runs of the canonical order; the
+    // passes rely on it to read and write that layout without an index table
+    const FibreTable& f2 = sys->fib[1];
+    for (int64_t i = 0; i < sys->N; ++i)
+      if (f2.rows[i] != (int32_t)i) return cleanup(fail(LSX_E_STATE, "internal: layer-2 fibre order"));
+    std::vector<int32_t> pos1(std::max<int64_t>(sys->N, 1), 0);
+    for (int64_t p = 0; p < sys->N; ++p) pos1[sys->fib[0].rows[p]] = (int32_t)p;
+    if ((st = pl->pos1.upload(pos1, s)) != LSX_OK) return cleanup(st);
+    if ((st = pl->zero.upload(std::vector<double2>(64, make_double2(0.0, 0.0)), s)) != LSX_OK) return cleanup(st);
   }
   if (kappa != 0.0) {
     for (int h = 0; h < 2; ++h) {
@@ -582,33 +597,153 @@ struct lsx_state {
   double2* buf[2] = {nullptr, nullptr};
   bool owns0 = false;
   DBuf<double2> own0, work;
-  DBuf<int4> tiles[2];
+  DBuf<TileDesc> tiles[2];
   int ntiles[2] = {0, 0};
-  int nb = 1, ks = 4;
+  int nb[2] = {1, 1}, ks[2] = {4, 4};  // tile shape per layer (16*nb columns, ks waves split k)
+  float tuned_us[2] = {0.f, 0.f};      // measured pass time of the chosen shape (0: not tuned)
   DBuf<double> partial, result;
   int nred = 0;
 };
 
-static void build_tiles(const lsx_plan* pl, int layer, int W, int nb, std::vector<int4>& out) {
+static int env_int(const char* name, int dflt);
+
+// Tile order of one fibre pass.  Workgroup i of a launch runs on XCD i % 8, and each
+// XCD has its own L2, so whole fibres are assigned to XCDs (longest first, to the
+// least-loaded XCD) and the XCD queues are interleaved; every queue lists its largest
+// tiles first.  Shorter queues are padded with empty tiles (f = -1).
+static void build_tiles(const lsx_plan* pl, int layer, int W, int nb, int wb0, int wb1, std::vector<TileDesc>& out) {
   const LayerDev& ld = pl->L[layer - 1];
-  const int wt = (W == 1) ? 1 : (W + 16 * nb - 1) / (16 * nb);
+  const int wt = wb1 - wb0;
+  (void)W;
+  const int NX = std::max(1, env_int("LSX_XCDS", 8));
   std::vector<int> order(ld.nf);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
     return (ld.h_ptr[x + 1] - ld.h_ptr[x]) > (ld.h_ptr[y + 1] - ld.h_ptr[y]);
   });
-  out.clear();
+  // balance the bins by tile count (equal counts need no padding tiles), ties by cost
+  std::vector<double> load(NX, 0.0);
+  std::vector<int64_t> count(NX, 0);
+  std::vector<std::vector<TileDesc>> bins(NX);
   for (int f : order) {
     const int L = ld.h_ptr[f + 1] - ld.h_ptr[f];
     const int nrb = (L + 15) / 16;
+    int x = 0;
+    for (int y = 1; y < NX; ++y)
+      if (count[y] < count[x] || (count[y] == count[x] && load[y] < load[x])) x = y;
+    count[x] += (int64_t)nrb * wt;
+    load[x] += (double)nrb * wt * (L + 8);
     for (int rb = 0; rb < nrb; ++rb)
-      for (int wb = 0; wb < wt; ++wb) out.push_back(make_int4(f, rb, wb, 0));
+      for (int wb = wb0; wb < wb1; ++wb) {
+        TileDesc t;
+        t.r0 = ld.h_ptr[f];
+        t.L = L;
+        t.rb = rb;
+        t.wb = wb;
+        t.poff = ld.h_poff.empty() ? 0 : ld.h_poff[f];
+        t.f = f;
+        t.pad = 0;
+        bins[x].push_back(t);
+      }
   }
+  TileDesc empty{};
+  empty.f = -1;
+  size_t maxlen = 0;
+  for (auto& b : bins) maxlen = std::max(maxlen, b.size());
+  out.clear();
+  for (size_t i = 0; i < maxlen; ++i)
+    for (int x = 0; x < NX; ++x) out.push_back(i < bins[x].size() ? bins[x][i] : empty);
+  while (!out.empty() && out.back().f < 0) out.pop_back();
 }
 
 static int env_int(const char* name, int dflt) {
   const char* v = std::getenv(name);
   return v ? std::atoi(v) : dflt;
+}
+
+// Tile shape per layer.  LSX_NB / LSX_KS force a shape; otherwise, unless
+// LSX_AUTOTUNE=0, every candidate shape is timed on this state's own size (reading the
+// state array, writing only the work array, so the state is not modified) and the
+// fastest one per layer is kept.
+static lsx_status choose_tiles(lsx_plan* pl, lsx_state* st) {
+  const int W = st->W;
+  struct Shape {
+    int nb, ks;
+  };
+  std::vector<Shape> cands;
+  const int fnb = env_int("LSX_NB", 0), fks = env_int("LSX_KS", 0);
+  if (W == 1) {
+    for (int k : {1, 2, 4}) cands.push_back({1, k});
+  } else {
+    for (int nb : {1, 2, 4})
+      for (int k : {1, 2, 4})
+        if (16 * nb <= round_up(W, 16) && !(nb == 4 && k == 4)) cands.push_back({nb, k});
+  }
+  if (fnb > 0 || fks > 0) {
+    const Shape f{(fnb == 1 || fnb == 2 || fnb == 4) ? fnb : 1, (fks == 1 || fks == 2 || fks == 4) ? fks : 2};
+    cands.assign(1, f);
+  } else if (env_int("LSX_AUTOTUNE", 1) == 0 || pl->sys->N == 0) {
+    cands.assign(1, Shape{1, W == 1 ? 4 : 2});
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  const bool timing = cands.size() > 1;
+  if (timing && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) {
+    if (e0) (void)hipEventDestroy(e0);
+    return fail(LSX_E_HIP, "event creation failed");
+  }
+  lsx_status err = LSX_OK;
+  for (int layer = 1; layer <= 2 && err == LSX_OK; ++layer) {
+    float best = -1.f;
+    for (const Shape& c : cands) {
+      std::vector<TileDesc> t;
+      const int wt = (W == 1) ? 1 : (W + 16 * c.nb - 1) / (16 * c.nb);
+      build_tiles(pl, layer, W, c.nb, 0, wt, t);
+      DBuf<TileDesc> d;
+      if ((err = d.upload(t, nullptr)) != LSX_OK) break;
+      float ms = 0.f;
+      if (timing) {
+        // steady-state access pattern of the step: fibre-contiguous read, scattered write
+        const LayerDev& ld = pl->L[layer - 1];
+        PassArgs a;
+        a.tiles = d.p;
+        a.in_pos = nullptr;
+        a.out_pos = (layer == 1) ? ld.rows.p : pl->pos1.p;
+        a.ph_idx = nullptr;
+        a.ph = nullptr;
+        a.P = ld.prop[0].data.p;
+        a.diag = pl->diag.p ? pl->diag.p + (size_t)((layer - 1) * 2) * pl->sys->N : nullptr;
+        a.X = st->buf[0];
+        a.Y = st->buf[1];
+        a.zero = pl->zero.p;
+        a.W = W;
+        const int reps = 5;
+        hipError_t he = launch_pass(nullptr, pl->fmt, W, (int)t.size(), c.nb, c.ks, a);
+        if (he == hipSuccess) he = hipEventRecord(e0, nullptr);
+        for (int r = 0; r < reps && he == hipSuccess; ++r) he = launch_pass(nullptr, pl->fmt, W, (int)t.size(), c.nb, c.ks, a);
+        if (he == hipSuccess) he = hipEventRecord(e1, nullptr);
+        if (he == hipSuccess) he = hipEventSynchronize(e1);
+        if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+        if (he != hipSuccess) {
+          err = fail(LSX_E_HIP, std::string("autotune: ") + hipGetErrorString(he));
+          break;
+        }
+        ms /= reps;
+      }
+      if (best < 0.f || ms < best) {
+        best = ms;
+        st->nb[layer - 1] = c.nb;
+        st->ks[layer - 1] = c.ks;
+        st->tiles[layer - 1].release();
+        std::swap(st->tiles[layer - 1].p, d.p);
+        std::swap(st->tiles[layer - 1].n, d.n);
+        st->ntiles[layer - 1] = (int)t.size();
+      }
+    }
+    st->tuned_us[layer - 1] = timing ? best * 1e3f : 0.f;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  return err;
 }
 
 extern "C" lsx_status lsx_state_create(lsx_plan* pl, int32_t W, void* dev_ptr, lsx_state** out) {
@@ -638,16 +773,7 @@ extern "C" lsx_status lsx_state_create(lsx_plan* pl, int32_t W, void* dev_ptr, l
   }
   if ((e = st->work.alloc(total)) != LSX_OK) return cleanup(e);
   st->buf[1] = st->work.p;
-  st->nb = env_int("LSX_NB", W >= 48 ? 2 : 1);
-  st->ks = env_int("LSX_KS", 4);
-  if (st->nb != 1 && st->nb != 2 && st->nb != 4) st->nb = 1;
-  if (st->ks != 1 && st->ks != 2 && st->ks != 4) st->ks = 4;
-  for (int layer = 1; layer <= 2; ++layer) {
-    std::vector<int4> t;
-    build_tiles(pl, layer, W, st->nb, t);
-    st->ntiles[layer - 1] = (int)t.size();
-    if ((e = st->tiles[layer - 1].upload(t, nullptr)) != LSX_OK) return cleanup(e);
-  }
+  if ((e = choose_tiles(pl, st)) != LSX_OK) return cleanup(e);
   st->nred = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (N + 255) / 256));
   const int nfmax = std::max(pl->L[0].nf, pl->L[1].nf);
   if ((e = st->partial.alloc((size_t)st->nred * W)) != LSX_OK) return cleanup(e);
@@ -681,6 +807,16 @@ extern "C" lsx_status lsx_state_device_ptr(const lsx_state* st, void** dev) {
   return LSX_OK;
 }
 
+extern "C" lsx_status lsx_state_tuning(const lsx_state* st, int32_t layer, int32_t* nb, int32_t* ks,
+                                       double* pass_us) {
+  if (!st) return fail(LSX_E_INVALID, "null state");
+  if (layer != 1 && layer != 2) return fail(LSX_E_INVALID, "layer must be 1 or 2");
+  if (nb) *nb = st->nb[layer - 1];
+  if (ks) *ks = st->ks[layer - 1];
+  if (pass_us) *pass_us = st->tuned_us[layer - 1];
+  return LSX_OK;
+}
+
 extern "C" lsx_status lsx_state_destroy(lsx_state* st) {
   if (!st) return LSX_OK;
   st->plan->nstates--;
@@ -689,31 +825,49 @@ extern "C" lsx_status lsx_state_destroy(lsx_state* st) {
 }
 
 // ================================================================ step composer
-// Between API calls the state lives in buf[0]; a fibre pass reads buf[cur] and writes
-// buf[1-cur]; the composer copies back at the end when an odd number of passes ran.
+// Between API calls the state lives in buf[0] in canonical order.  A fibre pass reads
+// buf[cur] and writes buf[1-cur].  Array layouts: 2 = canonical (layer-2 fibres are
+// contiguous runs), 1 = layer-1 fibre order.  A pass writes the layout the next pass
+// reads fibre-contiguously, so only the first pass of a call gathers through an index
+// table; the last pass writes canonical order.  The kinetic phase that follows a pass
+// is applied in that pass's epilogue.
 namespace {
 struct Runner {
   lsx_plan* pl;
   lsx_state* st;
   hipStream_t s;
   int cur = 0;
+  int lay = 2;
 
-  lsx_status pass(int layer, int half) {
+  // index table of layer `layer`'s fibre positions inside an array of layout `in`
+  const int32_t* table(int layer, int layout) const {
+    if (layout == layer) return nullptr;  // fibre-contiguous
+    return layer == 1 ? pl->L[0].rows.p   // layer-1 fibre position -> canonical index
+                      : pl->pos1.p;       // canonical index -> layer-1 fibre position
+  }
+
+  // F_layer(t) with t = tau (half 0) or tau/2; `next` is the layer of the following
+  // pass (0: none, write canonical order); phase_half >= 0 fuses Phase(kappa t') after it.
+  lsx_status pass(int layer, int half, int next, int phase_half) {
     const LayerDev& ld = pl->L[layer - 1];
     const PropSet& ps = ld.prop[half];
     if (!ps.present) return fail(LSX_E_INVALID, "plan holds no propagator for this layer/half");
+    const int outlay = (next == 0) ? 2 : next;
     PassArgs a;
     a.tiles = st->tiles[layer - 1].p;
-    a.ptr = ld.ptr.p;
-    a.rows = ld.rows.p;
-    a.poff = ps.off.p;
+    a.in_pos = table(layer, lay);
+    a.out_pos = table(layer, outlay);
+    a.ph_idx = (layer == 1) ? pl->L[0].rows.p : nullptr;
+    a.ph = (phase_half >= 0 && pl->kappa != 0.0) ? pl->phase[phase_half].p : nullptr;
     a.P = ps.data.p;
     a.diag = pl->diag.p ? pl->diag.p + (size_t)((layer - 1) * 2 + half) * pl->sys->N : nullptr;
     a.X = st->buf[cur];
     a.Y = st->buf[1 - cur];
+    a.zero = pl->zero.p;
     a.W = st->W;
-    LSX_HIP_TRY(launch_pass(s, pl->fmt, st->W, st->ntiles[layer - 1], st->nb, st->ks, a));
+    LSX_HIP_TRY(launch_pass(s, pl->fmt, st->W, st->ntiles[layer - 1], st->nb[layer - 1], st->ks[layer - 1], a));
     cur ^= 1;
+    lay = outlay;
     return LSX_OK;
   }
   lsx_status phase(int half) {
@@ -743,27 +897,37 @@ static lsx_status check_pair(lsx_plan* pl, lsx_state* st) {
   return LSX_OK;
 }
 
+// Runs `body(Runner&)` on the caller's stream and leaves the canonical result in buf[0].
+template <typename Body>
+static lsx_status run_passes(lsx_plan* pl, lsx_state* st, hipStream_t s, Body body) {
+  Runner r{pl, st, s};
+  LSX_TRY(body(r));
+  return r.finish();
+}
+
 extern "C" lsx_status lsx_step(lsx_plan* pl, lsx_state* st, int64_t nsteps, void* stream) {
   LSX_TRY(check_pair(pl, st));
   if (nsteps < 0) return fail(LSX_E_INVALID, "nsteps must be >= 0");
   if (nsteps == 0 || pl->sys->N == 0) return LSX_OK;
-  Runner r{pl, st, reinterpret_cast<hipStream_t>(stream)};
-  if (pl->scheme == LSX_LIE) {
-    for (int64_t k = 0; k < nsteps; ++k) {
-      LSX_TRY(r.pass(1, 0));
-      LSX_TRY(r.phase(0));
-      LSX_TRY(r.pass(2, 0));
+  const bool lie = (pl->scheme == LSX_LIE);
+  return run_passes(pl, st, reinterpret_cast<hipStream_t>(stream), [&](Runner& r) -> lsx_status {
+    if (lie) {
+      // per step: F1(tau), Phase(kappa tau), F2(tau)
+      for (int64_t k = 0; k < nsteps; ++k) {
+        LSX_TRY(r.pass(1, 0, 2, 0));
+        LSX_TRY(r.pass(2, 0, k + 1 < nsteps ? 1 : 0, -1));
+      }
+    } else {
+      // F1(tau/2) [Phase, F2(tau), Phase, F1(tau)] ... [Phase, F2(tau), Phase, F1(tau/2)]
+      LSX_TRY(r.pass(1, 1, 2, 1));
+      for (int64_t k = 0; k < nsteps; ++k) {
+        const bool last = (k + 1 == nsteps);
+        LSX_TRY(r.pass(2, 0, 1, 1));
+        LSX_TRY(r.pass(1, last ? 1 : 0, last ? 0 : 2, last ? -1 : 1));
+      }
     }
-  } else {
-    LSX_TRY(r.pass(1, 1));
-    for (int64_t k = 0; k < nsteps; ++k) {
-      LSX_TRY(r.phase(1));
-      LSX_TRY(r.pass(2, 0));
-      LSX_TRY(r.phase(1));
-      LSX_TRY(r.pass(1, k + 1 < nsteps ? 0 : 1));
-    }
-  }
-  return r.finish();
+    return LSX_OK;
+  });
 }
 
 extern "C" lsx_status lsx_fibre_pass(lsx_plan* pl, lsx_state* st, int32_t layer, int32_t half, int32_t count,
@@ -773,9 +937,10 @@ extern "C" lsx_status lsx_fibre_pass(lsx_plan* pl, lsx_state* st, int32_t layer,
   if (half != 0 && half != 1) return fail(LSX_E_INVALID, "half must be 0 or 1");
   if (count < 0) return fail(LSX_E_INVALID, "count must be >= 0");
   if (pl->sys->N == 0 || count == 0) return LSX_OK;
-  Runner r{pl, st, reinterpret_cast<hipStream_t>(stream)};
-  for (int32_t k = 0; k < count; ++k) LSX_TRY(r.pass(layer, half));
-  return r.finish();
+  return run_passes(pl, st, reinterpret_cast<hipStream_t>(stream), [&](Runner& r) -> lsx_status {
+    for (int32_t k = 0; k < count; ++k) LSX_TRY(r.pass(layer, half, k + 1 < count ? layer : 0, -1));
+    return LSX_OK;
+  });
 }
 
 extern "C" lsx_status lsx_phase(lsx_plan* pl, lsx_state* st, int32_t half, void* stream) {

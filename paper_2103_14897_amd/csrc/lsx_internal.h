@@ -47,20 +47,29 @@ inline int64_t prop_bytes(int fmt, int L) {
   }
 }
 
-struct Tile {
-  int32_t f, rb, wb, pad;
+// Tile of a fibre pass (32 bytes, read with one scalar load): fibre f starting at
+// fibre position r0 with length L, output rows 16*rb.., columns 16*NB*wb.., and the
+// byte offset of the fibre's propagator.  f < 0 marks a padding tile.
+struct TileDesc {
+  int32_t r0, L, rb, wb;
+  int64_t poff;
+  int32_t f, pad;
 };
 
-// arguments of every fibre-pass kernel
+// Arguments of every fibre-pass kernel.  Element k of fibre f (fibre position
+// p = r0 + k) is row in_pos[p] of X and row out_pos[p] of Y (identity when null),
+// so a pass can read one array layout and write another.
 struct PassArgs {
-  const int4* tiles;
-  const int32_t* ptr;    // fibre row pointers (nfibres+1)
-  const int32_t* rows;   // row ids of each fibre, concatenated
-  const int64_t* poff;   // per fibre byte offset into the propagator storage
-  const void* P;         // propagator storage (format per kernel)
-  const double2* diag;   // mixed formats: diagonal of P at fibre-row position ptr[f]+a
-  const double2* X;      // input state  [N][W]
-  double2* Y;            // output state [N][W]
+  const TileDesc* tiles;
+  const int32_t* in_pos;
+  const int32_t* out_pos;
+  const int32_t* ph_idx;  // canonical index of fibre position p (identity when null)
+  const double2* ph;      // kinetic phase applied to the output rows (none when null)
+  const void* P;          // propagator storage (format per kernel)
+  const double2* diag;    // mixed formats: diagonal of P at fibre position p
+  const double2* X;       // input state  [rows][W]
+  double2* Y;             // output state [rows][W]
+  const void* zero;       // >= 256 zero bytes: target of every out-of-range operand load
   int32_t W;
 };
 

@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 
 #include "lsx_internal.h"
 
@@ -287,14 +288,15 @@ __global__ __launch_bounds__(256) void k_phase_apply(int64_t N, int W, const dou
 // ---------------------------------------------------------------- fibre-pass epilogue
 // acc[nb][0/1][r]: this lane's part of the 16x16 output blocks, column lane%16 and
 // row 4*(lane/16)+r for the FP32-accumulating MFMAs, row 4*r+lane/16 for
-// v_mfma_f64_16x16x4f64 (ROWS_F64).  Summed over the KS waves in fixed order and
-// stored; mixed formats add the FP64 diagonal term d_a x_a.
+// v_mfma_f64_16x16x4f64 (ROWS_F64).  Summed over the KS waves in fixed order; mixed
+// formats add the FP64 diagonal term d_a x_a; an optional kinetic phase multiplies
+// the output row (the phase sub-step that follows this pass, fused).
 template <int NB, int KS, bool MIX, bool ROWS_F64>
-__device__ __forceinline__ void pass_epilogue(const PassArgs& a, double (&acc)[NB][2][4], int f, int rb,
-                                              int wb, double* red) {
-  const int lane = threadIdx.x & 63, kw = threadIdx.x >> 6;
+__device__ __forceinline__ void pass_epilogue(const PassArgs& a, const TileDesc& t, double (&acc)[NB][2][4],
+                                              double* red) {
+  const int lane = threadIdx.x & 63, kw = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int li = lane & 15, lk = lane >> 4;
-  const int r0 = a.ptr[f], L = a.ptr[f + 1] - r0;
+  const int r0 = t.r0, L = t.L, rb = t.rb, wb = t.wb;
   const int W = a.W;
   if (KS > 1) {
 #pragma unroll
@@ -308,7 +310,11 @@ __device__ __forceinline__ void pass_epilogue(const PassArgs& a, double (&acc)[N
   for (int r = (KS > 1 ? kw : 0); r < 4; r += KS) {
     const int arow = 16 * rb + (ROWS_F64 ? 4 * r + lk : 4 * lk + r);
     if (arow >= L) continue;
-    const int64_t row = a.rows[r0 + arow];
+    const int p = r0 + arow;
+    const int64_t orow = a.out_pos ? a.out_pos[p] : p;
+    const int64_t irow = a.in_pos ? a.in_pos[p] : p;
+    double2 ph = make_double2(1.0, 0.0);
+    if (a.ph) ph = a.ph[a.ph_idx ? a.ph_idx[p] : p];
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
       const int w = (wb * NB + nb) * 16 + li;
@@ -326,222 +332,298 @@ __device__ __forceinline__ void pass_epilogue(const PassArgs& a, double (&acc)[N
         yi = acc[nb][1][r];
       }
       if (MIX) {
-        const double2 dg = a.diag[r0 + arow];
-        const double2 x = a.X[row * W + w];
+        const double2 dg = a.diag[p];
+        const double2 x = a.X[irow * W + w];
         yr += dg.x * x.x - dg.y * x.y;
         yi += dg.x * x.y + dg.y * x.x;
       }
-      a.Y[row * W + w] = make_double2(yr, yi);
+      if (a.ph) {
+        const double zr = ph.x * yr - ph.y * yi;
+        yi = ph.x * yi + ph.y * yr;
+        yr = zr;
+      }
+      a.Y[orow * W + w] = make_double2(yr, yi);
     }
   }
 }
 
-// ---------------------------------------------------------------- FP64 fibre pass (MFMA)
-// Tile = (fibre f, 16 output rows rb, 16*NB columns wb); KS waves split the k range.
-template <int NB, int KS>
+// ---------------------------------------------------------------- MFMA fibre passes
+// Tile = (fibre, 16 output rows rb, 16*NB columns wb).  The KS waves of a workgroup
+// take interleaved groups of U k-steps; all loads of a group (propagator chunk and
+// state operands) are issued before its MFMAs, so a group pays the memory latency
+// once.  When the input array is laid out fibre-contiguously (in_pos null) the state
+// operands need no index load at all.
+
+__device__ __forceinline__ int64_t in_row(const PassArgs& a, int p) { return a.in_pos ? a.in_pos[p] : p; }
+
+// Operand loads of one group of U k-steps (4 fibre positions each) for the FP64/FP32
+// kernels: propagator chunk per k-step (A operand) and NB state values (B operand).
+template <typename PT, int NB, int U>
+struct Group4 {
+  PT p[U];
+  double2 x[U][NB];
+};
+
+// All operand loads are unconditional: an out-of-range operand (k-step past the
+// fibre, column past W) is read from a zeroed buffer instead, so the address is
+// selected, not the value, and no loaded value is consumed before the MFMAs that need
+// it -- the loads of the next group stay in flight during the current group.
+// GATHER: element k of the fibre is row in_pos[r0 + k] of X, else row r0 + k.
+template <bool GATHER>
+__device__ __forceinline__ int64_t xrow(const PassArgs& a, int p) {
+  return GATHER ? (int64_t)a.in_pos[p] : (int64_t)p;
+}
+
+template <bool GATHER, typename PT, int NB, int U>
+__device__ __forceinline__ void load_group4(Group4<PT, NB, U>& G, const PassArgs& a, const PT* P, int g, int nks,
+                                            int r0, int L, int lk, const int (&wc)[NB], const bool (&wok)[NB]) {
+  const PT* zp = reinterpret_cast<const PT*>(a.zero);
+  const double2* zx = reinterpret_cast<const double2*>(a.zero);
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int ks = g + u, k = 4 * ks + lk;
+    G.p[u] = *((ks < nks) ? P + (int64_t)ks * 64 : zp);
+    const bool ok = ks < nks && k < L;
+    const int64_t row = xrow<GATHER>(a, r0 + (ok ? k : 0));
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) G.x[u][nb] = *((ok && wok[nb]) ? a.X + row * a.W + wc[nb] : zx);
+  }
+}
+
+template <int NB, int U>
+__device__ __forceinline__ void mma_group_f64(v4d (&rr)[NB], v4d (&ii)[NB], v4d (&ri)[NB], v4d (&ir)[NB],
+                                              const Group4<double2, NB, U>& G) {
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      rr[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(G.p[u].x, G.x[u][nb].x, rr[nb], 0, 0, 0);
+      ii[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(G.p[u].y, G.x[u][nb].y, ii[nb], 0, 0, 0);
+      ri[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(G.p[u].x, G.x[u][nb].y, ri[nb], 0, 0, 0);
+      ir[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(G.p[u].y, G.x[u][nb].x, ir[nb], 0, 0, 0);
+    }
+}
+
+template <int NB, int U>
+__device__ __forceinline__ void mma_group_f32(v4f (&rr)[NB], v4f (&ii)[NB], v4f (&ri)[NB], v4f (&ir)[NB],
+                                              const Group4<float2, NB, U>& G) {
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const float xr = (float)G.x[u][nb].x, xi = (float)G.x[u][nb].y;
+      rr[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(G.p[u].x, xr, rr[nb], 0, 0, 0);
+      ii[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(G.p[u].y, xi, ii[nb], 0, 0, 0);
+      ri[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(G.p[u].x, xi, ri[nb], 0, 0, 0);
+      ir[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(G.p[u].y, xr, ir[nb], 0, 0, 0);
+    }
+}
+
+// FP64: complex128 P, X on v_mfma_f64_16x16x4f64.  Four independent accumulator chains
+// per column block (Pr Xr, Pi Xi, Pr Xi, Pi Xr); groups of U k-steps are double
+// buffered in registers, so the loads of group g+1 are in flight during the MFMAs of g.
+template <int NB, int KS, int U, bool GATHER>
 __global__ __launch_bounds__(64 * KS) void k_pass_f64(PassArgs a) {
   extern __shared__ double red[];
-  const int4 t = a.tiles[blockIdx.x];
-  const int f = t.x, rb = t.y, wb = t.z;
-  const int r0 = a.ptr[f], L = a.ptr[f + 1] - r0;
+  const TileDesc t = a.tiles[blockIdx.x];
+  if (t.f < 0) return;
+  const int r0 = t.r0, L = t.L;
   const int nks = ((L + 15) & ~15) >> 2;
-  const int lane = threadIdx.x & 63, kw = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, kw = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int li = lane & 15, lk = lane >> 4;
-  const int W = a.W;
-  const double2* P = reinterpret_cast<const double2*>(reinterpret_cast<const char*>(a.P) + a.poff[f]) +
-                     (int64_t)rb * nks * 64 + lane;
-  const int32_t* rows = a.rows + r0;
+  const double2* P = reinterpret_cast<const double2*>(reinterpret_cast<const char*>(a.P) + t.poff) +
+                     (int64_t)t.rb * nks * 64 + lane;
   int wc[NB];
   bool wok[NB];
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) {
-    wc[nb] = (wb * NB + nb) * 16 + li;
-    wok[nb] = wc[nb] < W;
+    wc[nb] = (t.wb * NB + nb) * 16 + li;
+    wok[nb] = wc[nb] < a.W;
   }
-  v4d cr[NB], ci[NB];
+  v4d rr[NB], ii[NB], ri[NB], ir[NB];
 #pragma unroll
-  for (int nb = 0; nb < NB; ++nb) {
-    cr[nb] = (v4d){0.0, 0.0, 0.0, 0.0};
-    ci[nb] = (v4d){0.0, 0.0, 0.0, 0.0};
-  }
-  for (int ks = kw; ks < nks; ks += KS) {
-    const double2 p = P[(int64_t)ks * 64];
-    const int k = 4 * ks + lk;
-    const bool kok = k < L;
-    const int64_t xb = kok ? (int64_t)rows[k] * W : 0;
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-      double2 x = make_double2(0.0, 0.0);
-      if (kok && wok[nb]) x = a.X[xb + wc[nb]];
-      cr[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(p.x, x.x, cr[nb], 0, 0, 0);
-      cr[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-p.y, x.y, cr[nb], 0, 0, 0);
-      ci[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(p.x, x.y, ci[nb], 0, 0, 0);
-      ci[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(p.y, x.x, ci[nb], 0, 0, 0);
-    }
+  for (int nb = 0; nb < NB; ++nb) rr[nb] = ii[nb] = ri[nb] = ir[nb] = (v4d){0.0, 0.0, 0.0, 0.0};
+  // two register buffers in ping-pong: B is loaded while A is consumed and vice versa
+  Group4<double2, NB, U> A, B;
+  const int stride = KS * U;
+  int g = kw * U;
+  load_group4<GATHER>(A, a, P, g, nks, r0, L, lk, wc, wok);
+  for (; g < nks; g += 2 * stride) {
+    load_group4<GATHER>(B, a, P, g + stride, nks, r0, L, lk, wc, wok);  // past the end: zeros
+    __builtin_amdgcn_sched_barrier(0);
+    mma_group_f64(rr, ii, ri, ir, A);
+    if (g + stride >= nks) break;
+    load_group4<GATHER>(A, a, P, g + 2 * stride, nks, r0, L, lk, wc, wok);
+    __builtin_amdgcn_sched_barrier(0);
+    mma_group_f64(rr, ii, ri, ir, B);
   }
   double acc[NB][2][4];
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      acc[nb][0][r] = cr[nb][r];
-      acc[nb][1][r] = ci[nb][r];
+      acc[nb][0][r] = rr[nb][r] - ii[nb][r];
+      acc[nb][1][r] = ri[nb][r] + ir[nb][r];
     }
-  pass_epilogue<NB, KS, false, true>(a, acc, f, rb, wb, red);
+  pass_epilogue<NB, KS, false, true>(a, t, acc, red);
 }
 
-// ---------------------------------------------------------------- mixed FP32 fibre pass (MFMA)
-// y = d .* x (FP64) + E x~ with E complex64, x~ = fp32(x), FP32 MFMA accumulation.
-template <int NB, int KS>
+// Mixed FP32: y = d .* x (FP64) + E x~ with E complex64, x~ = fp32(x), FP32 MFMA
+// accumulation (v_mfma_f32_16x16x4f32), same pipelining as the FP64 kernel.
+template <int NB, int KS, int U, bool GATHER>
 __global__ __launch_bounds__(64 * KS) void k_pass_f32(PassArgs a) {
   extern __shared__ double red[];
-  const int4 t = a.tiles[blockIdx.x];
-  const int f = t.x, rb = t.y, wb = t.z;
-  const int r0 = a.ptr[f], L = a.ptr[f + 1] - r0;
+  const TileDesc t = a.tiles[blockIdx.x];
+  if (t.f < 0) return;
+  const int r0 = t.r0, L = t.L;
   const int nks = ((L + 15) & ~15) >> 2;
-  const int lane = threadIdx.x & 63, kw = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, kw = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int li = lane & 15, lk = lane >> 4;
-  const int W = a.W;
-  const float2* P = reinterpret_cast<const float2*>(reinterpret_cast<const char*>(a.P) + a.poff[f]) +
-                    (int64_t)rb * nks * 64 + lane;
-  const int32_t* rows = a.rows + r0;
+  const float2* P = reinterpret_cast<const float2*>(reinterpret_cast<const char*>(a.P) + t.poff) +
+                    (int64_t)t.rb * nks * 64 + lane;
   int wc[NB];
   bool wok[NB];
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) {
-    wc[nb] = (wb * NB + nb) * 16 + li;
-    wok[nb] = wc[nb] < W;
+    wc[nb] = (t.wb * NB + nb) * 16 + li;
+    wok[nb] = wc[nb] < a.W;
   }
-  v4f cr[NB], ci[NB];
+  v4f rr[NB], ii[NB], ri[NB], ir[NB];
 #pragma unroll
-  for (int nb = 0; nb < NB; ++nb) {
-    cr[nb] = (v4f){0.f, 0.f, 0.f, 0.f};
-    ci[nb] = (v4f){0.f, 0.f, 0.f, 0.f};
-  }
-  for (int ks = kw; ks < nks; ks += KS) {
-    const float2 p = P[(int64_t)ks * 64];
-    const int k = 4 * ks + lk;
-    const bool kok = k < L;
-    const int64_t xb = kok ? (int64_t)rows[k] * W : 0;
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-      double2 x = make_double2(0.0, 0.0);
-      if (kok && wok[nb]) x = a.X[xb + wc[nb]];
-      const float xr = (float)x.x, xi = (float)x.y;
-      cr[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(p.x, xr, cr[nb], 0, 0, 0);
-      cr[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(-p.y, xi, cr[nb], 0, 0, 0);
-      ci[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(p.x, xi, ci[nb], 0, 0, 0);
-      ci[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(p.y, xr, ci[nb], 0, 0, 0);
-    }
+  for (int nb = 0; nb < NB; ++nb) rr[nb] = ii[nb] = ri[nb] = ir[nb] = (v4f){0.f, 0.f, 0.f, 0.f};
+  Group4<float2, NB, U> A, B;
+  const int stride = KS * U;
+  int g = kw * U;
+  load_group4<GATHER>(A, a, P, g, nks, r0, L, lk, wc, wok);
+  for (; g < nks; g += 2 * stride) {
+    load_group4<GATHER>(B, a, P, g + stride, nks, r0, L, lk, wc, wok);  // past the end: zeros
+    __builtin_amdgcn_sched_barrier(0);
+    mma_group_f32(rr, ii, ri, ir, A);
+    if (g + stride >= nks) break;
+    load_group4<GATHER>(A, a, P, g + 2 * stride, nks, r0, L, lk, wc, wok);
+    __builtin_amdgcn_sched_barrier(0);
+    mma_group_f32(rr, ii, ri, ir, B);
   }
   double acc[NB][2][4];
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      acc[nb][0][r] = (double)cr[nb][r];
-      acc[nb][1][r] = (double)ci[nb][r];
+      acc[nb][0][r] = (double)rr[nb][r] - (double)ii[nb][r];
+      acc[nb][1][r] = (double)ri[nb][r] + (double)ir[nb][r];
     }
-  pass_epilogue<NB, KS, true, false>(a, acc, f, rb, wb, red);
+  pass_epilogue<NB, KS, true, false>(a, t, acc, red);
 }
 
-// ---------------------------------------------------------------- mixed BF16x3 fibre pass (MFMA)
-// E = E0+E1+E2 and x~ = x0+x1+x2 (bf16 terms); the six products E0x0, E0x1, E1x0, E0x2,
-// E1x1, E2x0 on v_mfma_f32_16x16x32_bf16 with FP32 accumulation, plus the FP64 diagonal.
+// Mixed BF16x3: E = E0+E1+E2 and x~ = x0+x1+x2 (bf16 terms); the six products E0x0,
+// E0x1, E1x0, E0x2, E1x1, E2x0 on v_mfma_f32_16x16x32_bf16 with FP32 accumulation, plus
+// the FP64 diagonal term.  A k-step here is a chunk of 32 fibre positions.  Four
+// accumulator chains (Er Xr, Ei Xi, Er Xi, Ei Xr); chunk loads are double buffered.
 __device__ __forceinline__ v8bf as_bf(const v8u16& u) { return __builtin_bit_cast(v8bf, u); }
 
-template <int NB, int KS>
+template <int NB>
+struct ChunkBF {
+  v8u16 e[6];
+  double2 x[NB][8];
+};
+
+template <bool GATHER, int NB>
+__device__ __forceinline__ void load_chunk_bf(ChunkBF<NB>& C, const PassArgs& a, const v8u16* P, int kc, int nkc,
+                                              int r0, int L, int lk, const int (&wc)[NB], const bool (&wok)[NB]) {
+  const bool kin = kc < nkc;
+  const v8u16* zp = reinterpret_cast<const v8u16*>(a.zero);
+  const double2* zx = reinterpret_cast<const double2*>(a.zero);
+#pragma unroll
+  for (int pl = 0; pl < 6; ++pl) C.e[pl] = *(kin ? P + ((int64_t)kc * 6 + pl) * 64 : zp);
+#pragma unroll
+  for (int el = 0; el < 8; ++el) {
+    const int k = 32 * kc + 8 * lk + el;
+    const bool ok = kin && k < L;
+    const int64_t row = xrow<GATHER>(a, r0 + (ok ? k : 0));
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) C.x[nb][el] = *((ok && wok[nb]) ? a.X + row * a.W + wc[nb] : zx);
+  }
+}
+
+// acc += A (3 bf16 terms) * B (3 bf16 terms), six cross products, smallest first
+__device__ __forceinline__ v4f mma3(v4f c, const v8bf& a0, const v8bf& a1, const v8bf& a2, const v8bf& b0,
+                                    const v8bf& b1, const v8bf& b2) {
+  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, b0, c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b2, c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b0, c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b1, c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, c, 0, 0, 0);
+  return c;
+}
+
+template <int NB>
+__device__ __forceinline__ void mma_chunk_bf(v4f (&rr)[NB], v4f (&ii)[NB], v4f (&ri)[NB], v4f (&ir)[NB],
+                                             const ChunkBF<NB>& C) {
+  const v8bf er0 = as_bf(C.e[0]), ei0 = as_bf(C.e[1]), er1 = as_bf(C.e[2]);
+  const v8bf ei1 = as_bf(C.e[3]), er2 = as_bf(C.e[4]), ei2 = as_bf(C.e[5]);
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    v8u16 xr0, xr1, xr2, xi0, xi1, xi2;
+#pragma unroll
+    for (int el = 0; el < 8; ++el) {
+      unsigned short a0, a1, a2, b0, b1, b2;
+      split3f((float)C.x[nb][el].x, a0, a1, a2);
+      split3f((float)C.x[nb][el].y, b0, b1, b2);
+      xr0[el] = a0; xr1[el] = a1; xr2[el] = a2;
+      xi0[el] = b0; xi1[el] = b1; xi2[el] = b2;
+    }
+    const v8bf Xr0 = as_bf(xr0), Xr1 = as_bf(xr1), Xr2 = as_bf(xr2);
+    const v8bf Xi0 = as_bf(xi0), Xi1 = as_bf(xi1), Xi2 = as_bf(xi2);
+    rr[nb] = mma3(rr[nb], er0, er1, er2, Xr0, Xr1, Xr2);
+    ii[nb] = mma3(ii[nb], ei0, ei1, ei2, Xi0, Xi1, Xi2);
+    ri[nb] = mma3(ri[nb], er0, er1, er2, Xi0, Xi1, Xi2);
+    ir[nb] = mma3(ir[nb], ei0, ei1, ei2, Xr0, Xr1, Xr2);
+  }
+}
+
+template <int NB, int KS, int U, bool GATHER>
 __global__ __launch_bounds__(64 * KS) void k_pass_bf16x3(PassArgs a) {
   extern __shared__ double red[];
-  const int4 t = a.tiles[blockIdx.x];
-  const int f = t.x, rb = t.y, wb = t.z;
-  const int r0 = a.ptr[f], L = a.ptr[f + 1] - r0;
+  const TileDesc t = a.tiles[blockIdx.x];
+  if (t.f < 0) return;
+  const int r0 = t.r0, L = t.L;
   const int nkc = ((L + 31) & ~31) >> 5;
-  const int lane = threadIdx.x & 63, kw = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, kw = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int li = lane & 15, lk = lane >> 4;
-  const int W = a.W;
-  const v8u16* P = reinterpret_cast<const v8u16*>(reinterpret_cast<const char*>(a.P) + a.poff[f]) +
-                   (int64_t)rb * nkc * 6 * 64 + lane;
-  const int32_t* rows = a.rows + r0;
+  const v8u16* P = reinterpret_cast<const v8u16*>(reinterpret_cast<const char*>(a.P) + t.poff) +
+                   (int64_t)t.rb * nkc * 6 * 64 + lane;
   int wc[NB];
   bool wok[NB];
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) {
-    wc[nb] = (wb * NB + nb) * 16 + li;
-    wok[nb] = wc[nb] < W;
+    wc[nb] = (t.wb * NB + nb) * 16 + li;
+    wok[nb] = wc[nb] < a.W;
   }
-  v4f cr[NB], ci[NB];
+  v4f rr[NB], ii[NB], ri[NB], ir[NB];
 #pragma unroll
-  for (int nb = 0; nb < NB; ++nb) {
-    cr[nb] = (v4f){0.f, 0.f, 0.f, 0.f};
-    ci[nb] = (v4f){0.f, 0.f, 0.f, 0.f};
-  }
-  for (int kc = kw; kc < nkc; kc += KS) {
-    // E planes: term0 re, term0 im, term1 re, term1 im, term2 re, term2 im
-    const v8u16* Pc = P + (int64_t)kc * 6 * 64;
-    const v8bf er0 = as_bf(Pc[0]), ei0 = as_bf(Pc[64]);
-    const v8bf er1 = as_bf(Pc[128]), ei1 = as_bf(Pc[192]);
-    const v8bf er2 = as_bf(Pc[256]), ei2 = as_bf(Pc[320]);
-    const int kbase = 32 * kc + 8 * lk;
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-      v8u16 xr0, xr1, xr2, xi0, xi1, xi2;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int k = kbase + e;
-        double2 x = make_double2(0.0, 0.0);
-        if (k < L && wok[nb]) x = a.X[(int64_t)rows[k] * W + wc[nb]];
-        unsigned short a0, a1, a2, b0, b1, b2;
-        split3f((float)x.x, a0, a1, a2);
-        split3f((float)x.y, b0, b1, b2);
-        xr0[e] = a0; xr1[e] = a1; xr2[e] = a2;
-        xi0[e] = b0; xi1[e] = b1; xi2[e] = b2;
-      }
-      const v8u16 sgn = (v8u16){0x8000, 0x8000, 0x8000, 0x8000, 0x8000, 0x8000, 0x8000, 0x8000};
-      const v8bf Xr0 = as_bf(xr0), Xr1 = as_bf(xr1), Xr2 = as_bf(xr2);
-      const v8bf Xi0 = as_bf(xi0), Xi1 = as_bf(xi1), Xi2 = as_bf(xi2);
-      const v8bf Xn0 = as_bf(xi0 ^ sgn), Xn1 = as_bf(xi1 ^ sgn), Xn2 = as_bf(xi2 ^ sgn);
-      // real part: Er Xr - Ei Xi, smallest terms first
-      v4f c = cr[nb];
-      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(er2, Xr0, c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(er1, Xr1, c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(er0, Xr2, c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ei2, Xn0, c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ei1, Xn1, c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ei0, Xn2, c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(er1, Xr0, c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(er0, Xr1, c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ei1, Xn0, c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ei0, Xn1, c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(er0, Xr0, c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ei0, Xn0, c, 0, 0, 0);
-      cr[nb] = c;
-      // imaginary part: Er Xi + Ei Xr
-      v4f d = ci[nb];
-      d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(er2, Xi0, d, 0, 0, 0);
-      d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(er1, Xi1, d, 0, 0, 0);
-      d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(er0, Xi2, d, 0, 0, 0);
-      d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ei2, Xr0, d, 0, 0, 0);
-      d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ei1, Xr1, d, 0, 0, 0);
-      d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ei0, Xr2, d, 0, 0, 0);
-      d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(er1, Xi0, d, 0, 0, 0);
-      d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(er0, Xi1, d, 0, 0, 0);
-      d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ei1, Xr0, d, 0, 0, 0);
-      d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ei0, Xr1, d, 0, 0, 0);
-      d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(er0, Xi0, d, 0, 0, 0);
-      d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ei0, Xr0, d, 0, 0, 0);
-      ci[nb] = d;
-    }
+  for (int nb = 0; nb < NB; ++nb) rr[nb] = ii[nb] = ri[nb] = ir[nb] = (v4f){0.f, 0.f, 0.f, 0.f};
+  ChunkBF<NB> A, B;
+  int kc = kw;
+  load_chunk_bf<GATHER>(A, a, P, kc, nkc, r0, L, lk, wc, wok);
+  for (; kc < nkc; kc += 2 * KS) {
+    load_chunk_bf<GATHER>(B, a, P, kc + KS, nkc, r0, L, lk, wc, wok);  // past the end: zeros
+    __builtin_amdgcn_sched_barrier(0);
+    mma_chunk_bf(rr, ii, ri, ir, A);
+    if (kc + KS >= nkc) break;
+    load_chunk_bf<GATHER>(A, a, P, kc + 2 * KS, nkc, r0, L, lk, wc, wok);
+    __builtin_amdgcn_sched_barrier(0);
+    mma_chunk_bf(rr, ii, ri, ir, B);
   }
   double acc[NB][2][4];
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      acc[nb][0][r] = (double)cr[nb][r];
-      acc[nb][1][r] = (double)ci[nb][r];
+      acc[nb][0][r] = (double)rr[nb][r] - (double)ii[nb][r];
+      acc[nb][1][r] = (double)ri[nb][r] + (double)ir[nb][r];
     }
-  pass_epilogue<NB, KS, true, false>(a, acc, f, rb, wb, red);
+  pass_epilogue<NB, KS, true, false>(a, t, acc, red);
 }
 
 // ---------------------------------------------------------------- single-state fibre pass (W = 1)
@@ -552,13 +634,12 @@ __global__ __launch_bounds__(64 * KS) void k_pass_bf16x3(PassArgs a) {
 template <int KS, int FMT>
 __global__ __launch_bounds__(64 * KS) void k_gemv(PassArgs a) {
   __shared__ double red[2 * KS * 16];
-  const int4 t = a.tiles[blockIdx.x];
-  const int f = t.x, rb = t.y;
-  const int r0 = a.ptr[f], L = a.ptr[f + 1] - r0;
-  const int lane = threadIdx.x & 63, kw = threadIdx.x >> 6;
+  const TileDesc t = a.tiles[blockIdx.x];
+  if (t.f < 0) return;
+  const int r0 = t.r0, L = t.L, rb = t.rb;
+  const int lane = threadIdx.x & 63, kw = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int li = lane & 15, lk = lane >> 4;
-  const int32_t* rows = a.rows + r0;
-  const char* Pb = reinterpret_cast<const char*>(a.P) + a.poff[f];
+  const char* Pb = reinterpret_cast<const char*>(a.P) + t.poff;
   double yr = 0.0, yi = 0.0;
   if (FMT == PF_BF16X3) {
     const int nkc = ((L + 31) & ~31) >> 5;
@@ -570,7 +651,7 @@ __global__ __launch_bounds__(64 * KS) void k_gemv(PassArgs a) {
       for (int e = 0; e < 8; ++e) {
         const int k = 32 * kc + 8 * lk + e;
         if (k < L) {
-          const double2 x = a.X[rows[k]];
+          const double2 x = a.X[in_row(a, r0 + k)];
           const double er = (double)(bf2f(r0v[e]) + bf2f(r1v[e]) + bf2f(r2v[e]));
           const double ei = (double)(bf2f(i0v[e]) + bf2f(i1v[e]) + bf2f(i2v[e]));
           yr += er * x.x - ei * x.y;
@@ -593,7 +674,7 @@ __global__ __launch_bounds__(64 * KS) void k_gemv(PassArgs a) {
         pi = p.y;
       }
       if (k < L) {
-        const double2 x = a.X[rows[k]];
+        const double2 x = a.X[in_row(a, r0 + k)];
         yr += pr * x.x - pi * x.y;
         yi += pr * x.y + pi * x.x;
       }
@@ -617,14 +698,20 @@ __global__ __launch_bounds__(64 * KS) void k_gemv(PassArgs a) {
         sr += red[(j * 2 + 0) * 16 + li];
         si += red[(j * 2 + 1) * 16 + li];
       }
-      const int64_t row = rows[arow];
+      const int p = r0 + arow;
       if (FMT != PF_F64) {
-        const double2 dg = a.diag[r0 + arow];
-        const double2 x = a.X[row];
+        const double2 dg = a.diag[p];
+        const double2 x = a.X[in_row(a, p)];
         sr += dg.x * x.x - dg.y * x.y;
         si += dg.x * x.y + dg.y * x.x;
       }
-      a.Y[row] = make_double2(sr, si);
+      if (a.ph) {
+        const double2 ph = a.ph[a.ph_idx ? a.ph_idx[p] : p];
+        const double zr = ph.x * sr - ph.y * si;
+        si = ph.x * si + ph.y * sr;
+        sr = zr;
+      }
+      a.Y[a.out_pos ? a.out_pos[p] : p] = make_double2(sr, si);
     }
   }
 }
@@ -776,16 +863,41 @@ hipError_t launch_phase_apply(hipStream_t s, int64_t N, int W, const double2* ph
   return hipGetLastError();
 }
 
-template <int NB, int KS>
-static hipError_t launch_mfma(hipStream_t s, int fmt, int ntiles, const PassArgs& a) {
+// Prefetch depth of the FP64/FP32 passes (k-steps per register group); LSX_PREFETCH
+// selects 1, 2 or 4 (default 2).
+static int prefetch_depth() {
+  static int u = [] {
+    const char* v = std::getenv("LSX_PREFETCH");
+    const int x = v ? std::atoi(v) : 2;
+    return (x == 1 || x == 4) ? x : 2;
+  }();
+  return u;
+}
+
+template <int NB, int KS, int U, bool G>
+static hipError_t launch_mfma_u(hipStream_t s, int fmt, int ntiles, const PassArgs& a) {
   const size_t shm = KS > 1 ? (size_t)KS * NB * 2 * 4 * 64 * sizeof(double) : 0;
   if (fmt == PF_F64)
-    hipLaunchKernelGGL((k_pass_f64<NB, KS>), dim3(ntiles), dim3(64 * KS), shm, s, a);
+    hipLaunchKernelGGL((k_pass_f64<NB, KS, U, G>), dim3(ntiles), dim3(64 * KS), shm, s, a);
   else if (fmt == PF_F32)
-    hipLaunchKernelGGL((k_pass_f32<NB, KS>), dim3(ntiles), dim3(64 * KS), shm, s, a);
+    hipLaunchKernelGGL((k_pass_f32<NB, KS, U, G>), dim3(ntiles), dim3(64 * KS), shm, s, a);
   else
-    hipLaunchKernelGGL((k_pass_bf16x3<NB, KS>), dim3(ntiles), dim3(64 * KS), shm, s, a);
+    hipLaunchKernelGGL((k_pass_bf16x3<NB, KS, 1, G>), dim3(ntiles), dim3(64 * KS), shm, s, a);
   return hipGetLastError();
+}
+
+template <int NB, int KS, bool G>
+static hipError_t launch_mfma_g(hipStream_t s, int fmt, int ntiles, const PassArgs& a) {
+  switch (fmt == PF_BF16X3 ? 1 : prefetch_depth()) {
+    case 1: return launch_mfma_u<NB, KS, 1, G>(s, fmt, ntiles, a);
+    case 4: return launch_mfma_u<NB, KS, 4, G>(s, fmt, ntiles, a);
+    default: return launch_mfma_u<NB, KS, 2, G>(s, fmt, ntiles, a);
+  }
+}
+
+template <int NB, int KS>
+static hipError_t launch_mfma(hipStream_t s, int fmt, int ntiles, const PassArgs& a) {
+  return a.in_pos ? launch_mfma_g<NB, KS, true>(s, fmt, ntiles, a) : launch_mfma_g<NB, KS, false>(s, fmt, ntiles, a);
 }
 
 template <int KS>

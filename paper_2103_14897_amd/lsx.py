@@ -48,6 +48,7 @@ _SIGS = {
     "lsx_state_upload": (C.c_int, [_p, _dp, _p]),
     "lsx_state_download": (C.c_int, [_p, _dp, _p]),
     "lsx_state_device_ptr": (C.c_int, [_p, C.POINTER(_p)]),
+    "lsx_state_tuning": (C.c_int, [_p, C.c_int32, _i32p, _i32p, _dp]),
     "lsx_state_destroy": (C.c_int, [_p]),
     "lsx_step": (C.c_int, [_p, _p, C.c_int64, _p]),
     "lsx_fibre_pass": (C.c_int, [_p, _p, C.c_int32, C.c_int32, C.c_int32, _p]),
@@ -220,6 +221,12 @@ class State:
                 res[names[bit]] = v.reshape(-1, self.W) if bit >= OBS_FIBRE_MASS_1 else v
                 o += n
         return res
+
+    def tuning(self, layer):
+        """(nb, ks, pass_us) of the tile shape chosen for `layer`'s fibre passes."""
+        nb, ks, us = C.c_int32(), C.c_int32(), C.c_double()
+        _check(lib().lsx_state_tuning(self.h, int(layer), C.byref(nb), C.byref(ks), C.byref(us)))
+        return nb.value, ks.value, us.value
 
     def destroy(self):
         if self.h:
