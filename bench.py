@@ -95,6 +95,9 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=400)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-mib", type=int, default=64)
+    ap.add_argument("--workload", default="chain", choices=["chain", "twisted", "twisted1", "tiny"],
+                    help="chain: the metric's workload (default); the others are extra measurements")
+    ap.add_argument("--kappa", type=float, default=0.0)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -104,7 +107,8 @@ def main():
         sys.exit(2)
     import torch
 
-    w = wl.chain()
+    w = {"chain": wl.chain, "twisted": wl.twisted, "twisted1": lambda: wl.twisted(W=1),
+         "tiny": wl.tiny_chain}[args.workload]()
     S = lsx.System.from_spec(w.spec)
     mn = S.index()
     c0 = w.initial_state(mn)
@@ -124,7 +128,7 @@ def main():
     finals = {}
     for path in args.paths.split(","):
         t0 = time.perf_counter()
-        P = lsx.Plan(S, w.tau, "strang", 0.0, path, stream)
+        P = lsx.Plan(S, w.tau, "strang", args.kappa, path, stream)
         pre = time.perf_counter() - t0
         st = lsx.State(P, W)
         # accuracy run to T
@@ -156,9 +160,20 @@ def main():
         k1.record(stream)
         k1.synchronize()
         kus1 = k0.elapsed_time(k1) * 1e3 / args.kernel_reps
+        phase_us = None
+        if args.kappa != 0.0:
+            k0.record(stream)
+            for _ in range(args.kernel_reps):
+                st.phase(1, stream)
+            k1.record(stream)
+            k1.synchronize()
+            phase_us = k0.elapsed_time(k1) * 1e3 / args.kernel_reps
         res[path] = {"coeff_steps_per_s": N * W * args.steps / (ms * 1e-3), "ms_per_step": ms / args.steps,
                      "wall_ms": wall * 1e3, "precompute_s": pre, "layer2_pass_us": kus, "layer1_pass_us": kus1,
                      "tiles": {"layer1": st.tuning(1)[:2], "layer2": st.tuning(2)[:2]}}
+        if phase_us is not None:
+            res[path]["phase_us"] = phase_us
+            res[path]["phase_GBps"] = (2.0 * N * W * 16 + 16.0 * N) / (phase_us * 1e-6) / 1e9
         st.destroy()
         P.destroy()
     ref = finals.get("fp64")
@@ -185,7 +200,8 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": nbytes / t / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                 "frac": nbytes / t / HBM_PEAK}
-    roof.update({"traffic": measured_traffic(best), "kernel": f"fibre pass, layer 2 ({best})",
+    roof.update({"traffic": measured_traffic(best) if args.workload == "chain" and args.kappa == 0.0 else None,
+                 "kernel": f"fibre pass, layer 2 ({best})",
                  "algorithmic_flops": flops, "algorithmic_bytes": nbytes,
                  "other_roof_frac": (nbytes / t / HBM_PEAK) if bound == "mfma" else (flops / t / PEAK[best])})
     out = {
@@ -201,8 +217,11 @@ def main():
         "vs_baseline": None,
         "dtype": DTYPE[best],
         "data": "synthetic",
-        "config": {"workload": "chain1d_golden_Ec2e4_W64_strang_tau1e-3", "N": N, "W": W,
-                   "fibres": [S.nfibres[1], S.nfibres[2]], "path": best, "kappa": 0.0},
+        "config": {"workload": {"chain": "chain1d_golden_Ec2e4_W64_strang_tau1e-3",
+                                "twisted": "twisted_tri_pm2.5deg_Ec6500_W128_strang_tau5e-3",
+                                "twisted1": "twisted_tri_pm2.5deg_Ec6500_W1_strang_tau5e-3",
+                                "tiny": "chain1d_golden_Ec200_W1_strang_tau1e-2"}[args.workload],
+                   "N": N, "W": W, "fibres": [S.nfibres[1], S.nfibres[2]], "path": best, "kappa": args.kappa},
         "roofline": roof,
         "paths": res,
     }

@@ -48,7 +48,12 @@ typedef enum {
 } lsx_status;
 
 enum { LSX_CUTOFF_BALL = 0, LSX_CUTOFF_PRODUCT = 1 };
-enum { LSX_LIE = 0, LSX_STRANG = 1 };
+enum {
+  LSX_LIE = 0,       /* exact fibre flows, Lie order F1 F2 (App. A)                       */
+  LSX_STRANG = 1,    /* exact fibre flows, Strang F1(tau/2) F2(tau) F1(tau/2) (App. A)    */
+  LSX_LIE_BE = 2,    /* backward Euler fibre solves, Lie order (Alg. 2, eqs. 4.3-4.4)      */
+  LSX_STRANG_CN = 3  /* Crank-Nicolson fibre solves, Strang order (eq. 4.6)              */
+};
 enum { LSX_FP64 = 0, LSX_MIX_FP32 = 1, LSX_MIX_BF16X3 = 2 };
 enum {
   LSX_OBS_MASS = 1,         /* W doubles */
@@ -120,8 +125,13 @@ lsx_status lsx_system_destroy(lsx_system* sys);
  * For every fibre the FP64 fibre Hamiltonian is assembled and diagonalised on the
  * device (batched Jacobi), and P(t) = U exp(-i t Lambda) U^H is formed for the
  * sub-step lengths the scheme needs:
- *   LSX_LIE    : F1(tau), Phase(kappa tau), F2(tau)                                per step
- *   LSX_STRANG : F1(tau/2), Phase(kappa tau/2), F2(tau), Phase(kappa tau/2), F1(tau/2) per step
+ *   LSX_LIE, LSX_LIE_BE       : F1(tau), Phase(kappa tau), F2(tau)                      per step
+ *   LSX_STRANG, LSX_STRANG_CN : F1(tau/2), Phase(kappa tau/2), F2(tau), Phase(kappa tau/2), F1(tau/2)
+ * with F(t) = f(H_j) per fibre and, per eigenvalue lambda, f = exp(-i t lambda) (exact
+ * flows), 1/(1 + i t lambda) (backward Euler) or (1 - i t lambda/2)/(1 + i t lambda/2)
+ * (Crank-Nicolson; for t = tau/2 this is (4I + i tau H)^{-1}(4I - i tau H) of eq. 4.6).
+ * With kappa = 1 fibres whose index windows coincide up to a translation share one
+ * eigendecomposition and one stored propagator.
  * precision    LSX_FP64: complex128 propagators, FP64 MFMA.
  *              LSX_MIX_FP32: P = diag(d) + E with d complex128 and E complex64, FP32 MFMA
  *                 on E with FP32 accumulation, FP64 diagonal term and FP64 carried state.
@@ -180,8 +190,9 @@ lsx_status lsx_state_destroy(lsx_state* st);
 
 /*
  * lsx_step -- advances the state by exactly nsteps * tau with the plan's scheme
- * (App. A compositions; Strang half-steps of consecutive steps inside one call
- * are merged, F1(tau/2) F1(tau/2) = F1(tau)).  nsteps >= 0.  Stream-ordered.
+ * (App. A compositions; with exact flows the Strang half-steps of consecutive steps inside
+ * one call are merged, F1(tau/2) F1(tau/2) = F1(tau); Crank-Nicolson steps are applied
+ * unmerged).  nsteps >= 0.  Stream-ordered.
  */
 lsx_status lsx_step(lsx_plan* plan, lsx_state* st, int64_t nsteps, void* stream);
 

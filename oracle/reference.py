@@ -81,3 +81,17 @@ class Supercell:
         H2 = (1.0 - kappa) / 2.0 * self.D + self.V2
         E = lambda A, t: scipy.linalg.expm(-1j * t * A)  # noqa: E731
         return E(H2, tau) @ E(kappa * self.D, tau) @ E(H1, tau)
+
+
+def dense_rational_step_matrix(sys, tau: float, scheme: str, kappa: float = 0.0) -> np.ndarray:
+    """One Lie-BE (Alg. 2) or Strang-CN (eq. 4.6) step as a dense N x N matrix, from linear
+    solves with the full split operators (kinetic share by its exact exponential)."""
+    Dk, H1, H2 = full_split_operators(sys, kappa)
+    N = H1.shape[0]
+    I = np.eye(N)
+    E = lambda A, t: scipy.linalg.expm(-1j * t * A)  # noqa: E731
+    if scheme == "lie_be":
+        B = lambda A, t: np.linalg.solve(I + 1j * t * A, I)  # noqa: E731
+        return B(H2, tau) @ E(Dk, tau) @ B(H1, tau)
+    C = lambda A, t: np.linalg.solve(I + 0.5j * t * A, I - 0.5j * t * A)  # noqa: E731
+    return C(H1, tau / 2) @ E(Dk, tau / 2) @ C(H2, tau) @ E(Dk, tau / 2) @ C(H1, tau / 2)

@@ -72,11 +72,19 @@ def propagator_from_hamiltonian(H: np.ndarray, t: float) -> np.ndarray:
 
 
 class SplitPlan:
-    """Per-fibre propagators for one (system, kappa), cached per (layer, t)."""
+    """Per-fibre propagators for one (system, kappa), cached per (layer, t).
 
-    def __init__(self, sys: Lifted, kappa: float = 0.0):
+    ``flow`` selects the fibre sub-step: ``"exact"`` exp(-i t H_j) (eigh), ``"be"`` the
+    backward-Euler solve (I + i t H_j)^{-1} of Alg. 2 / eqs. (4.3)-(4.4), or ``"cn"`` the
+    Crank-Nicolson solve (I + i t H_j / 2)^{-1}(I - i t H_j / 2) of eq. (4.6) (for t = tau/2
+    this is (4I + i tau H)^{-1}(4I - i tau H)).  The rational sub-steps are formed by
+    linear solves with the fibre matrix, not from its eigenvalues.
+    """
+
+    def __init__(self, sys: Lifted, kappa: float = 0.0, flow: str = "exact"):
         self.sys = sys
         self.kappa = float(kappa)
+        self.flow = flow
         self._eig = {}
         self._P = {}
 
@@ -92,8 +100,19 @@ class SplitPlan:
     def propagators(self, layer: int, t: float):
         key = (layer, float(t))
         if key not in self._P:
-            self._P[key] = [(U * np.exp(-1j * t * lam)[None, :]) @ U.conj().T
-                            for lam, U in self.eig(layer)]
+            if self.flow == "exact":
+                self._P[key] = [(U * np.exp(-1j * t * lam)[None, :]) @ U.conj().T
+                                for lam, U in self.eig(layer)]
+            else:
+                out = []
+                for _, rows in self.sys.fib[layer]:
+                    H = self.sys.fibre_hamiltonian(layer, rows, self.kappa)
+                    I = np.eye(len(rows))
+                    if self.flow == "be":
+                        out.append(np.linalg.solve(I + 1j * t * H, I))
+                    else:
+                        out.append(np.linalg.solve(I + 0.5j * t * H, I - 0.5j * t * H))
+                self._P[key] = out
         return self._P[key]
 
     def apply_fibres(self, c: np.ndarray, layer: int, t: float) -> np.ndarray:

@@ -353,6 +353,9 @@ struct LayerDev {
   int maxL = 0;
   std::vector<int32_t> h_ptr;
   std::vector<int64_t> h_poff;  // byte offset of each fibre's propagator (same for every t)
+  std::vector<int32_t> h_d0;    // fibre position of each fibre's diagonal (its representative's)
+  std::vector<int32_t> rep;     // distinct-propagator slot of each fibre
+  int nunique = 0;
   DBuf<int32_t> ptr, rows;
   DBuf<int32_t> nbr;
   DBuf<double2> v;  // stencil values (for the energy)
@@ -372,6 +375,10 @@ struct lsx_plan {
   int nstates = 0;
 };
 
+// Sub-step flow of a scheme: 0 exact exponential, 1 backward Euler, 2 Crank-Nicolson.
+static int scheme_flow(int scheme) { return scheme == LSX_LIE_BE ? 1 : (scheme == LSX_STRANG_CN ? 2 : 0); }
+static bool scheme_strang(int scheme) { return scheme == LSX_STRANG || scheme == LSX_STRANG_CN; }
+
 static lsx_status precompute_layer(lsx_plan* pl, int layer, hipStream_t s) {
   lsx_system* sys = pl->sys;
   LayerDev& ld = pl->L[layer - 1];
@@ -379,28 +386,64 @@ static lsx_status precompute_layer(lsx_plan* pl, int layer, hipStream_t s) {
   const Stencil& S = sys->pot[layer - 1];
   const int nf = ld.nf;
   if (nf == 0) return LSX_OK;
+  const int d = sys->d;
+  const int own = (layer == 1) ? 0 : d;
+  // With kappa = 1 a fibre Hamiltonian is the potential restricted to the fibre's window
+  // of own indices, which is translation invariant: fibres whose windows coincide up to a
+  // shift share one eigendecomposition and one stored propagator.
+  ld.rep.resize(nf);
+  std::vector<int32_t> uniq;
+  if (pl->kappa == 1.0) {
+    std::map<std::vector<int32_t>, int> seen;
+    for (int f = 0; f < nf; ++f) {
+      std::vector<int32_t> key;
+      const int r0 = ft.ptr[f], L = ft.ptr[f + 1] - r0;
+      key.reserve((size_t)L * d);
+      const int32_t* base = &sys->mn[(int64_t)ft.rows[r0] * 2 * d + own];
+      for (int a = 0; a < L; ++a)
+        for (int k = 0; k < d; ++k) key.push_back(sys->mn[(int64_t)ft.rows[r0 + a] * 2 * d + own + k] - base[k]);
+      auto it = seen.find(key);
+      if (it == seen.end()) {
+        seen.emplace(std::move(key), (int)uniq.size());
+        ld.rep[f] = (int)uniq.size();
+        uniq.push_back(f);
+      } else {
+        ld.rep[f] = it->second;
+      }
+    }
+  } else {
+    for (int f = 0; f < nf; ++f) {
+      ld.rep[f] = f;
+      uniq.push_back(f);
+    }
+  }
+  const int nu = (int)uniq.size();
+  ld.nunique = nu;
   const int embed = S.real ? 0 : 1;
-  std::vector<int32_t> ndim(nf), emb(nf, embed);
-  std::vector<int64_t> moff(nf), loff(nf);
+  std::vector<int32_t> ndim(nu), emb(nu, embed);
+  std::vector<int64_t> moff(nu), loff(nu);
   int64_t mt = 0, lt = 0;
-  int maxn = 0;
-  for (int f = 0; f < nf; ++f) {
+  int maxn = 0, maxL = 0;
+  for (int b = 0; b < nu; ++b) {
+    const int f = uniq[b];
     const int L = ft.ptr[f + 1] - ft.ptr[f];
+    maxL = std::max(maxL, L);
     int n = embed ? 2 * L : L;
     n += (n & 1);
     if (n < 2) n = 2;
-    ndim[f] = n;
+    ndim[b] = n;
     maxn = std::max(maxn, n);
-    moff[f] = mt;
-    loff[f] = lt;
+    moff[b] = mt;
+    loff[b] = lt;
     mt += (int64_t)n * n;
     lt += n;
   }
   if (maxn > 8192) return fail(LSX_E_INVALID, "fibre too long for the eigensolver (max 8192)");
-  DBuf<int32_t> d_ndim, d_emb, d_info, d_mn, d_vidx;
+  DBuf<int32_t> d_ndim, d_emb, d_info, d_mn, d_vidx, d_fid;
   DBuf<int64_t> d_moff, d_loff;
   DBuf<double> A, VT, lam, d_vre, d_vim;
-  DBuf<double2> cs;
+  DBuf<double2> gh;
+  LSX_TRY(d_fid.upload(uniq, s));
   LSX_TRY(d_ndim.upload(ndim, s));
   LSX_TRY(d_emb.upload(emb, s));
   LSX_TRY(d_moff.upload(moff, s));
@@ -412,38 +455,45 @@ static lsx_status precompute_layer(lsx_plan* pl, int layer, hipStream_t s) {
   LSX_TRY(A.alloc(mt));
   LSX_TRY(VT.alloc(mt));
   LSX_TRY(lam.alloc(lt));
-  LSX_TRY(cs.alloc(lt));
-  LSX_TRY(d_info.alloc(nf));
-  LSX_HIP_TRY(launch_assemble(s, nf, ld.ptr.p, ld.rows.p, d_mn.p, sys->d, layer, pl->K2.p, S.nv, d_vidx.p,
+  LSX_TRY(gh.alloc(lt));
+  LSX_TRY(d_info.alloc(nu));
+  LSX_HIP_TRY(launch_assemble(s, nu, d_fid.p, ld.ptr.p, ld.rows.p, d_mn.p, d, layer, pl->K2.p, S.nv, d_vidx.p,
                               d_vre.p, d_vim.p, pl->kappa, embed, A.p, d_moff.p, d_ndim.p));
-  LSX_HIP_TRY(launch_jacobi(s, nf, maxn, A.p, VT.p, d_moff.p, d_ndim.p, lam.p, d_loff.p, d_info.p, 60));
-  std::vector<int32_t> info(nf);
-  LSX_HIP_TRY(hipMemcpyAsync(info.data(), d_info.p, nf * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  LSX_HIP_TRY(launch_jacobi(s, nu, maxn, A.p, VT.p, d_moff.p, d_ndim.p, lam.p, d_loff.p, d_info.p, 60));
+  std::vector<int32_t> info(nu);
+  LSX_HIP_TRY(hipMemcpyAsync(info.data(), d_info.p, nu * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   LSX_HIP_TRY(hipStreamSynchronize(s));
-  for (int f = 0; f < nf; ++f)
-    if (info[f] < 0)
+  for (int b = 0; b < nu; ++b)
+    if (info[b] < 0)
       return fail(LSX_E_EIG, "Jacobi did not converge for layer " + std::to_string(layer) + " fibre " +
-                                 std::to_string(f));
-  // propagators for the sub-step lengths the scheme needs
+                                 std::to_string(uniq[b]));
+  // propagator storage: one slot per distinct fibre; fibres map to their representative
+  std::vector<int64_t> uoff(nu);
+  int64_t bytes = 0;
+  for (int b = 0; b < nu; ++b) {
+    uoff[b] = bytes;
+    bytes += prop_bytes(pl->fmt, ft.ptr[uniq[b] + 1] - ft.ptr[uniq[b]]);
+    bytes = (bytes + 255) & ~(int64_t)255;
+  }
+  ld.h_poff.resize(nf);
+  ld.h_d0.resize(nf);
+  for (int f = 0; f < nf; ++f) {
+    ld.h_poff[f] = uoff[ld.rep[f]];
+    ld.h_d0[f] = ft.ptr[uniq[ld.rep[f]]];
+  }
+  const int flow = scheme_flow(pl->scheme);
   for (int h = 0; h < 2; ++h) {
     PropSet& ps = ld.prop[h];
-    const bool need = (h == 0) || (layer == 1 && pl->scheme == LSX_STRANG);
+    const bool need = (h == 0) || (layer == 1 && scheme_strang(pl->scheme));
     if (!need) continue;
     ps.t = (h == 0) ? pl->tau : 0.5 * pl->tau;
-    ps.h_off.resize(nf);
-    int64_t bytes = 0;
-    for (int f = 0; f < nf; ++f) {
-      ps.h_off[f] = bytes;
-      bytes += prop_bytes(pl->fmt, ft.ptr[f + 1] - ft.ptr[f]);
-      bytes = (bytes + 255) & ~(int64_t)255;
-    }
-    ld.h_poff = ps.h_off;
+    ps.h_off = ld.h_poff;
     LSX_TRY(ps.data.alloc(bytes));
-    LSX_TRY(ps.off.upload(ps.h_off, s));
+    LSX_TRY(ps.off.upload(uoff, s));
     LSX_HIP_TRY(hipMemsetAsync(ps.data.p, 0, bytes, s));
-    LSX_HIP_TRY(launch_eig_phase(s, lt, lam.p, ps.t, cs.p));
+    LSX_HIP_TRY(launch_eig_fn(s, lt, lam.p, ps.t, flow, gh.p));
     double2* dg = pl->diag.p ? pl->diag.p + (size_t)((layer - 1) * 2 + h) * sys->N : nullptr;
-    LSX_HIP_TRY(launch_form(s, pl->fmt, nf, ft.maxL, ld.ptr.p, VT.p, d_moff.p, d_ndim.p, d_emb.p, cs.p,
+    LSX_HIP_TRY(launch_form(s, pl->fmt, nu, maxL, d_fid.p, ld.ptr.p, VT.p, d_moff.p, d_ndim.p, d_emb.p, gh.p,
                             d_loff.p, ps.data.p, ps.off.p, dg));
     ps.present = true;
   }
@@ -455,7 +505,8 @@ extern "C" lsx_status lsx_plan_create(lsx_system* sys, double tau, int32_t schem
                                       int32_t precision, void* stream, lsx_plan** out) {
   if (!sys || !out) return fail(LSX_E_INVALID, "null argument");
   if (!std::isfinite(tau) || tau == 0.0) return fail(LSX_E_INVALID, "tau must be finite and nonzero");
-  if (scheme != LSX_LIE && scheme != LSX_STRANG) return fail(LSX_E_INVALID, "bad scheme");
+  if (scheme != LSX_LIE && scheme != LSX_STRANG && scheme != LSX_LIE_BE && scheme != LSX_STRANG_CN)
+    return fail(LSX_E_INVALID, "bad scheme");
   if (!(kappa >= 0.0 && kappa <= 1.0)) return fail(LSX_E_INVALID, "kappa must be in [0, 1]");
   if (precision != LSX_FP64 && precision != LSX_MIX_FP32 && precision != LSX_MIX_BF16X3)
     return fail(LSX_E_INVALID, "bad precision");
@@ -536,7 +587,7 @@ extern "C" lsx_status lsx_plan_propagator(const lsx_plan* pl, int32_t layer, int
   std::vector<double2> dg;
   if (pl->fmt != PF_F64) {
     dg.resize(L);
-    const double2* src = pl->diag.p + (size_t)((layer - 1) * 2 + half) * pl->sys->N + ld.h_ptr[fibre];
+    const double2* src = pl->diag.p + (size_t)((layer - 1) * 2 + half) * pl->sys->N + ld.h_d0[fibre];
     LSX_HIP_TRY(hipMemcpyAsync(dg.data(), src, L * sizeof(double2), hipMemcpyDeviceToHost, s));
   }
   LSX_HIP_TRY(hipStreamSynchronize(s));
@@ -642,7 +693,7 @@ static void build_tiles(const lsx_plan* pl, int layer, int W, int nb, int wb0, i
         t.wb = wb;
         t.poff = ld.h_poff.empty() ? 0 : ld.h_poff[f];
         t.f = f;
-        t.pad = 0;
+        t.d0 = ld.h_d0.empty() ? ld.h_ptr[f] : ld.h_d0[f];
         bins[x].push_back(t);
       }
   }
@@ -909,9 +960,18 @@ extern "C" lsx_status lsx_step(lsx_plan* pl, lsx_state* st, int64_t nsteps, void
   LSX_TRY(check_pair(pl, st));
   if (nsteps < 0) return fail(LSX_E_INVALID, "nsteps must be >= 0");
   if (nsteps == 0 || pl->sys->N == 0) return LSX_OK;
-  const bool lie = (pl->scheme == LSX_LIE);
+  const bool lie = !scheme_strang(pl->scheme);
+  const bool cn = (pl->scheme == LSX_STRANG_CN);
   return run_passes(pl, st, reinterpret_cast<hipStream_t>(stream), [&](Runner& r) -> lsx_status {
-    if (lie) {
+    if (cn) {
+      // Crank-Nicolson factors do not compose (C(t/2)^2 != C(t)): no merging, eq. (4.6)
+      for (int64_t k = 0; k < nsteps; ++k) {
+        const bool last = (k + 1 == nsteps);
+        LSX_TRY(r.pass(1, 1, 2, 1));
+        LSX_TRY(r.pass(2, 0, 1, 1));
+        LSX_TRY(r.pass(1, 1, last ? 0 : 1, -1));
+      }
+    } else if (lie) {
       // per step: F1(tau), Phase(kappa tau), F2(tau)
       for (int64_t k = 0; k < nsteps; ++k) {
         LSX_TRY(r.pass(1, 0, 2, 0));

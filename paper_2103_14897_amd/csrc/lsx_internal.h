@@ -48,12 +48,13 @@ inline int64_t prop_bytes(int fmt, int L) {
 }
 
 // Tile of a fibre pass (32 bytes, read with one scalar load): fibre f starting at
-// fibre position r0 with length L, output rows 16*rb.., columns 16*NB*wb.., and the
-// byte offset of the fibre's propagator.  f < 0 marks a padding tile.
+// fibre position r0 with length L, output rows 16*rb.., columns 16*NB*wb.., the byte
+// offset of the fibre's propagator and of its diagonal.  f < 0 marks a padding tile.
 struct TileDesc {
   int32_t r0, L, rb, wb;
   int64_t poff;
-  int32_t f, pad;
+  int32_t f;
+  int32_t d0;  // mixed formats: position of this propagator's diagonal (fibres may share one)
 };
 
 // Arguments of every fibre-pass kernel.  Element k of fibre f (fibre position
@@ -74,18 +75,17 @@ struct PassArgs {
 };
 
 // ---------------------------------------------------------------- kernel launchers (lsx_kernels.hip)
-hipError_t launch_assemble(hipStream_t s, int nf, const int32_t* ptr, const int32_t* rows,
-                           const int32_t* mn, int d, int layer, const double* K2, int nv,
-                           const int32_t* vidx, const double* vre, const double* vim, double kappa,
-                           int embed, double* A, const int64_t* moff, const int32_t* ndim);
+hipError_t launch_assemble(hipStream_t s, int nb, const int32_t* fid, const int32_t* ptr, const int32_t* rows,
+                           const int32_t* mn, int d, int layer, const double* K2, int nv, const int32_t* vidx,
+                           const double* vre, const double* vim, double kappa, int embed, double* A,
+                           const int64_t* moff, const int32_t* ndim);
 hipError_t launch_jacobi(hipStream_t s, int nf, int maxn, double* A, double* VT, const int64_t* moff,
                          const int32_t* ndim, double* lam, const int64_t* loff, int32_t* info,
                          int maxsweeps);
-hipError_t launch_eig_phase(hipStream_t s, int64_t nlam, const double* lam, double t, double2* cs);
-hipError_t launch_form(hipStream_t s, int fmt, int nf, int maxL, const int32_t* ptr, const double* VT,
-                       const int64_t* moff, const int32_t* ndim, const int32_t* embed,
-                       const double2* cs, const int64_t* loff, void* P, const int64_t* poff,
-                       double2* diag);
+hipError_t launch_eig_fn(hipStream_t s, int64_t nlam, const double* lam, double t, int flow, double2* gh);
+hipError_t launch_form(hipStream_t s, int fmt, int nb, int maxL, const int32_t* fid, const int32_t* ptr,
+                       const double* VT, const int64_t* moff, const int32_t* ndim, const int32_t* embed,
+                       const double2* gh, const int64_t* loff, void* P, const int64_t* poff, double2* diag);
 hipError_t launch_phase_table(hipStream_t s, int64_t N, const double* K2, double theta_scale, double2* ph);
 hipError_t launch_phase_apply(hipStream_t s, int64_t N, int W, const double2* ph, double2* c);
 hipError_t launch_pass(hipStream_t s, int fmt, int W, int ntiles, int nb, int ksplit, const PassArgs& a);

@@ -67,14 +67,16 @@ __device__ double block_sum(double v, double* sh) {
 // ---------------------------------------------------------------- assembly (eq. 3.6 on one fibre)
 // A (ndim x ndim, row-major) <- H_j restricted to fibre f, or for complex H its real
 // embedding [[Re H, -Im H], [Im H, Re H]]; padding rows/cols are zero.
-__global__ void k_assemble(const int32_t* ptr, const int32_t* rows, const int32_t* mn, int d, int layer,
-                           const double* K2, int nv, const int32_t* vidx, const double* vre,
+// Block b assembles fibre fid[b] into its own slot b.
+__global__ void k_assemble(const int32_t* fid, const int32_t* ptr, const int32_t* rows, const int32_t* mn, int d,
+                           int layer, const double* K2, int nv, const int32_t* vidx, const double* vre,
                            const double* vim, double kappa, int embed, double* Aall, const int64_t* moff,
                            const int32_t* ndim) {
-  const int f = blockIdx.x;
+  const int b = blockIdx.x;
+  const int f = fid[b];
   const int r0 = ptr[f], L = ptr[f + 1] - r0;
-  const int n = ndim[f];
-  double* A = Aall + moff[f];
+  const int n = ndim[b];
+  double* A = Aall + moff[b];
   const int own = (layer == 1) ? 0 : d;
   const int La = embed ? 2 * L : L;
   const int64_t nn = (int64_t)n * n;
@@ -132,7 +134,10 @@ __global__ __launch_bounds__(BS) void k_jacobi(double* Aall, double* VTall, cons
   double s2 = 0.0;
   for (int64_t e = tid; e < nn; e += BS) s2 += A[e] * A[e];
   const double normF = sqrt(block_sum<BS>(s2, red));
-  const double tiny = 1e-18 * normF;
+  // rotations are skipped below 1e-16 of the pair's diagonal scale plus 1e-16 ||H||_F:
+  // the absolute term sits at rounding-noise level, so matrices with zero diagonal
+  // (potential-only fibres) converge instead of rotating noise until the sweep limit
+  const double tiny = 1e-16 * normF;
 
   int sweep = 0;
   bool done = (n < 2);
@@ -200,36 +205,57 @@ __global__ __launch_bounds__(BS) void k_jacobi(double* Aall, double* VTall, cons
   if (tid == 0) info[f] = done ? sweep : -1;
 }
 
-__global__ void k_eig_phase(int64_t nlam, const double* lam, double t, double2* cs) {
+// f(lambda) = g + i h of one sub-step of length t for each eigenvalue:
+//   flow 0 (exact flow)        exp(-i t lambda)
+//   flow 1 (backward Euler)    1 / (1 + i t lambda)                     (Alg. 2)
+//   flow 2 (Crank-Nicolson)    (1 - i t lambda / 2) / (1 + i t lambda / 2)  (eq. 4.6)
+__global__ void k_eig_fn(int64_t nlam, const double* lam, double t, int flow, double2* gh) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < nlam) {
-    double s, c;
-    sincos(t * lam[i], &s, &c);
-    cs[i] = make_double2(c, s);
+    const double x = t * lam[i];
+    double g, h;
+    if (flow == 0) {
+      double sn, cn;
+      sincos(x, &sn, &cn);
+      g = cn;
+      h = -sn;
+    } else if (flow == 1) {
+      const double den = 1.0 + x * x;
+      g = 1.0 / den;
+      h = -x / den;
+    } else {
+      const double q = 0.25 * x * x, den = 1.0 + q;
+      g = (1.0 - q) / den;
+      h = -x / den;
+    }
+    gh[i] = make_double2(g, h);
   }
 }
 
 // ---------------------------------------------------------------- propagator formation
-// P(t)[a][b] = sum_k V[a][k] exp(-i t lambda_k) V[b][k]; for an embedded complex H the
-// blocks of cos(tM) and sin(tM) give P = (C_A + S_B) + i (C_B - S_A).
+// P(t) = f(H) = sum_k V[.][k] f(lambda_k) V[.][k]^T with f = g + i h.  For an embedded
+// complex H (real form M = [[Re H, -Im H], [Im H, Re H]]), g(M) and h(M) hold Re/Im of g(H)
+// and h(H) in their left blocks (C_A, C_B and S_A, S_B), so P = (C_A - S_B) + i (C_B + S_A).
+// Block b forms fibre fid[b] (slot b); the mixed formats' diagonal goes to positions ptr[f]+a.
 template <int FMT>
-__global__ void k_form(const int32_t* ptr, const double* VTall, const int64_t* moff, const int32_t* ndim,
-                       const int32_t* embed, const double2* csall, const int64_t* loff, void* Pall,
-                       const int64_t* poff, double2* diag) {
-  const int f = blockIdx.x;
+__global__ void k_form(const int32_t* fid, const int32_t* ptr, const double* VTall, const int64_t* moff,
+                       const int32_t* ndim, const int32_t* embed, const double2* ghall, const int64_t* loff,
+                       void* Pall, const int64_t* poff, double2* diag) {
+  const int b = blockIdx.x;
+  const int f = fid[b];
   const int r0 = ptr[f], L = ptr[f + 1] - r0;
-  const int n = ndim[f];
-  const int emb = embed[f];
-  const double* VT = VTall + moff[f];
-  const double2* cs = csall + loff[f];
-  char* P = reinterpret_cast<char*>(Pall) + poff[f];
+  const int n = ndim[b];
+  const int emb = embed[b];
+  const double* VT = VTall + moff[b];
+  const double2* gh = ghall + loff[b];
+  char* P = reinterpret_cast<char*>(Pall) + poff[b];
   const int LL = L * L;
   for (int e = blockIdx.y * blockDim.x + threadIdx.x; e < LL; e += gridDim.y * blockDim.x) {
-    const int a = e / L, b = e - (e / L) * L;
+    const int a = e / L, bb = e - (e / L) * L;
     double CA = 0.0, SA = 0.0, CB = 0.0, SB = 0.0;
     for (int k = 0; k < n; ++k) {
-      const double2 c = cs[k];
-      const double v = VT[(int64_t)k * n + b];
+      const double2 c = gh[k];
+      const double v = VT[(int64_t)k * n + bb];
       const double uv = VT[(int64_t)k * n + a] * v;
       CA += uv * c.x;
       SA += uv * c.y;
@@ -239,21 +265,21 @@ __global__ void k_form(const int32_t* ptr, const double* VTall, const int64_t* m
         SB += u2v * c.y;
       }
     }
-    const double pr = CA + SB, pi = CB - SA;
+    const double pr = CA - SB, pi = CB + SA;
     if (FMT == PF_F64) {
       const int Lp = (L + 15) & ~15;
-      const int64_t idx = ((int64_t)(a >> 4) * (Lp >> 2) + (b >> 2)) * 64 + (a & 15) + 16 * (b & 3);
+      const int64_t idx = ((int64_t)(a >> 4) * (Lp >> 2) + (bb >> 2)) * 64 + (a & 15) + 16 * (bb & 3);
       reinterpret_cast<double2*>(P)[idx] = make_double2(pr, pi);
-    } else if (a == b) {
+    } else if (a == bb) {
       diag[r0 + a] = make_double2(pr, pi);
     } else if (FMT == PF_F32) {
       const int Lp = (L + 15) & ~15;
-      const int64_t idx = ((int64_t)(a >> 4) * (Lp >> 2) + (b >> 2)) * 64 + (a & 15) + 16 * (b & 3);
+      const int64_t idx = ((int64_t)(a >> 4) * (Lp >> 2) + (bb >> 2)) * 64 + (a & 15) + 16 * (bb & 3);
       reinterpret_cast<float2*>(P)[idx] = make_float2((float)pr, (float)pi);
     } else {
       const int Lp = (L + 31) & ~31;
-      const int64_t chunk = (int64_t)(a >> 4) * (Lp >> 5) + (b >> 5);
-      const int lane = (a & 15) + 16 * ((b & 31) >> 3), el = b & 7;
+      const int64_t chunk = (int64_t)(a >> 4) * (Lp >> 5) + (bb >> 5);
+      const int lane = (a & 15) + 16 * ((bb & 31) >> 3), el = bb & 7;
       unsigned short* Q = reinterpret_cast<unsigned short*>(P);
       unsigned short t[6];
       split3(pr, t[0], t[2], t[4]);
@@ -332,7 +358,7 @@ __device__ __forceinline__ void pass_epilogue(const PassArgs& a, const TileDesc&
         yi = acc[nb][1][r];
       }
       if (MIX) {
-        const double2 dg = a.diag[p];
+        const double2 dg = a.diag[t.d0 + arow];
         const double2 x = a.X[irow * W + w];
         yr += dg.x * x.x - dg.y * x.y;
         yi += dg.x * x.y + dg.y * x.x;
@@ -700,7 +726,7 @@ __global__ __launch_bounds__(64 * KS) void k_gemv(PassArgs a) {
       }
       const int p = r0 + arow;
       if (FMT != PF_F64) {
-        const double2 dg = a.diag[p];
+        const double2 dg = a.diag[t.d0 + arow];
         const double2 x = a.X[in_row(a, p)];
         sr += dg.x * x.x - dg.y * x.y;
         si += dg.x * x.y + dg.y * x.x;
@@ -808,11 +834,11 @@ __global__ __launch_bounds__(256) void k_fibre_mass(const int32_t* ptr, const in
 }
 
 // ================================================================ launchers
-hipError_t launch_assemble(hipStream_t s, int nf, const int32_t* ptr, const int32_t* rows, const int32_t* mn,
-                           int d, int layer, const double* K2, int nv, const int32_t* vidx, const double* vre,
-                           const double* vim, double kappa, int embed, double* A, const int64_t* moff,
-                           const int32_t* ndim) {
-  hipLaunchKernelGGL(k_assemble, dim3(nf), dim3(256), 0, s, ptr, rows, mn, d, layer, K2, nv, vidx, vre, vim,
+hipError_t launch_assemble(hipStream_t s, int nb, const int32_t* fid, const int32_t* ptr, const int32_t* rows,
+                           const int32_t* mn, int d, int layer, const double* K2, int nv, const int32_t* vidx,
+                           const double* vre, const double* vim, double kappa, int embed, double* A,
+                           const int64_t* moff, const int32_t* ndim) {
+  hipLaunchKernelGGL(k_assemble, dim3(nb), dim3(256), 0, s, fid, ptr, rows, mn, d, layer, K2, nv, vidx, vre, vim,
                      kappa, embed, A, moff, ndim);
   return hipGetLastError();
 }
@@ -829,24 +855,24 @@ hipError_t launch_jacobi(hipStream_t s, int nf, int maxn, double* A, double* VT,
   return hipGetLastError();
 }
 
-hipError_t launch_eig_phase(hipStream_t s, int64_t nlam, const double* lam, double t, double2* cs) {
+hipError_t launch_eig_fn(hipStream_t s, int64_t nlam, const double* lam, double t, int flow, double2* gh) {
   if (nlam == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_eig_phase, dim3((unsigned)((nlam + 255) / 256)), dim3(256), 0, s, nlam, lam, t, cs);
+  hipLaunchKernelGGL(k_eig_fn, dim3((unsigned)((nlam + 255) / 256)), dim3(256), 0, s, nlam, lam, t, flow, gh);
   return hipGetLastError();
 }
 
-hipError_t launch_form(hipStream_t s, int fmt, int nf, int maxL, const int32_t* ptr, const double* VT,
-                       const int64_t* moff, const int32_t* ndim, const int32_t* embed, const double2* cs,
-                       const int64_t* loff, void* P, const int64_t* poff, double2* diag) {
+hipError_t launch_form(hipStream_t s, int fmt, int nb, int maxL, const int32_t* fid, const int32_t* ptr,
+                       const double* VT, const int64_t* moff, const int32_t* ndim, const int32_t* embed,
+                       const double2* gh, const int64_t* loff, void* P, const int64_t* poff, double2* diag) {
   const int64_t maxLL = (int64_t)maxL * maxL;
   const unsigned gy = (unsigned)std::max<int64_t>(1, std::min<int64_t>((maxLL + 255) / 256, 4096));
-  const dim3 g(nf, gy);
+  const dim3 g(nb, gy);
   if (fmt == PF_F64)
-    hipLaunchKernelGGL(k_form<PF_F64>, g, dim3(256), 0, s, ptr, VT, moff, ndim, embed, cs, loff, P, poff, diag);
+    hipLaunchKernelGGL(k_form<PF_F64>, g, dim3(256), 0, s, fid, ptr, VT, moff, ndim, embed, gh, loff, P, poff, diag);
   else if (fmt == PF_F32)
-    hipLaunchKernelGGL(k_form<PF_F32>, g, dim3(256), 0, s, ptr, VT, moff, ndim, embed, cs, loff, P, poff, diag);
+    hipLaunchKernelGGL(k_form<PF_F32>, g, dim3(256), 0, s, fid, ptr, VT, moff, ndim, embed, gh, loff, P, poff, diag);
   else
-    hipLaunchKernelGGL(k_form<PF_BF16X3>, g, dim3(256), 0, s, ptr, VT, moff, ndim, embed, cs, loff, P, poff,
+    hipLaunchKernelGGL(k_form<PF_BF16X3>, g, dim3(256), 0, s, fid, ptr, VT, moff, ndim, embed, gh, loff, P, poff,
                        diag);
   return hipGetLastError();
 }

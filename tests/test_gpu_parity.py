@@ -196,3 +196,49 @@ def test_wrapped_torch_tensor_and_stream():
     stream.synchronize()
     assert colrel(t.cpu().numpy(), plan.evolve(c, w.tau, 5)) < 5e-12
     teardown(st, P, S)
+
+
+@pytest.mark.parametrize("scheme,flow", [("lie_be", "be"), ("strang_cn", "cn")])
+@pytest.mark.parametrize("precision", ["fp64", "mix_fp32"])
+def test_rational_schemes(scheme, flow, precision):
+    # Alg. 2 (BE, Lie order) and eq. (4.6) (CN, Strang order) on the GPU vs the oracle's solves
+    spec = wl.chain_system(971.0, pot1=ASYM1, pot2=ASYM2)
+    S, P, O = build(spec, 0.01, scheme, 0.0, precision)
+    plan = splitting.SplitPlan(O, 0.0, flow)
+    step = plan.lie_step if scheme == "lie_be" else plan.strang_step
+    c = wl.random_state(S.N, 8, seed=9)
+    st = lsx.State(P, 8)
+    st.upload(c)
+    st.step(1)
+    tol = 1e-12 if precision == "fp64" else 1e-7
+    assert colrel(st.download(), step(c, 0.01)) < tol
+    st.upload(c)
+    st.step(10)
+    ref = plan.evolve(c, 0.01, 10, "lie" if scheme == "lie_be" else "strang")
+    assert colrel(st.download(), ref) < 10 * tol
+    m = st.observables(lsx.OBS_MASS)["mass"]
+    if flow == "cn":
+        assert np.abs(m - 1.0).max() < 1e-12 if precision == "fp64" else 1e-7
+    else:
+        assert np.all(m < 1.0)
+    teardown(st, P, S)
+
+
+def test_kappa1_shared_windows_twisted():
+    # kappa = 1: fibres with equal index windows share one propagator; every fibre's
+    # propagator still equals the oracle's own per-fibre exponential
+    spec = wl.twisted_system(900.0)
+    S, P, O = build(spec, 0.005, "strang", 1.0)
+    plan = splitting.SplitPlan(O, 1.0)
+    for layer, half in ((1, 0), (1, 1), (2, 0)):
+        t = 0.005 if half == 0 else 0.0025
+        ref = plan.propagators(layer, t)
+        for f in range(S.nfibres[layer]):
+            assert np.abs(P.propagator(layer, half, f) - ref[f]).max() < 1e-13
+    w = wl.Workload(spec, W=16, sigma=3.0, kmax=5.0, tau=0.005, T=0.05)
+    c = w.initial_state(O.mn)
+    st = lsx.State(P, 16)
+    st.upload(c)
+    st.step(10)
+    assert colrel(st.download(), plan.evolve(c, 0.005, 10)) < 1e-11
+    teardown(st, P, S)

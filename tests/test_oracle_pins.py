@@ -250,3 +250,53 @@ def test_energy_conserved_by_exact_flow_and_mass_by_fibres():
     for layer in (1, 2):
         fm = observables.fibre_mass(sys, c, layer)
         assert np.allclose(fm.sum(axis=0), observables.mass(c), rtol=0, atol=1e-14)
+
+
+# ---------------------------------------------------------------- rational fully discrete schemes
+@pytest.mark.parametrize("scheme,flow", [("lie_be", "be"), ("strang_cn", "cn")])
+def test_rational_step_equals_dense_solves(scheme, flow):
+    # Alg. 2 (backward Euler, Lie order) and eq. (4.6) (Crank-Nicolson, Strang order): the
+    # fibre-wise solves equal solves with the full lifted split operators
+    spec = wl.chain_system(200.0, pot1=ASYM1, pot2=ASYM2)
+    sys = lifted_sys(spec)
+    plan = splitting.SplitPlan(sys, 0.0, flow)
+    c = wl.random_state(sys.N, 2, seed=8)
+    step = plan.lie_step if scheme == "lie_be" else plan.strang_step
+    ref = reference.dense_rational_step_matrix(sys, 0.03, scheme) @ c
+    assert rel(step(c, 0.03), ref) < 1e-13
+
+
+def test_cn_factor_reading_matches_eq_4_6():
+    # (4I + i tau H)^{-1}(4I - i tau H) is the Cayley factor of a half step tau/2
+    H = np.array([[1.0, 0.3 - 0.2j], [0.3 + 0.2j, -0.5]])
+    tau = 0.07
+    lhs = np.linalg.solve(4 * np.eye(2) + 1j * tau * H, 4 * np.eye(2) - 1j * tau * H)
+    rhs = np.linalg.solve(np.eye(2) + 0.5j * (tau / 2) * H, np.eye(2) - 0.5j * (tau / 2) * H)
+    assert np.abs(lhs - rhs).max() < 1e-15
+
+
+def test_rational_orders_and_mass():
+    # Thm 4.2: BE-Lie is O(tau); Thm 4.3: CN-Strang is O(tau^2); Thm 4.4: CN conserves mass;
+    # BE is contractive (its factors have norm <= 1), so the mass decays
+    spec = wl.chain_system(200.0)
+    sys = lifted_sys(spec)
+    c0 = wl.gaussian_state(spec, sys.mn, np.zeros((1, 1)), 2.0)
+    exact = reference.exact_flow(sys, c0, 1.0)
+    # BE reaches its O(tau) regime only once tau lambda_max << 1 (lambda_max ~ Ec / 2 here)
+    for flow, scheme, order, Ks in (("be", "lie", 1.0, (400, 800, 1600)), ("cn", "strang", 2.0, (20, 40, 80))):
+        errs = []
+        for K in Ks:
+            cK = splitting.SplitPlan(sys, 0.0, flow).evolve(c0, 1.0 / K, K, scheme)
+            errs.append(np.linalg.norm(cK - exact))
+        slope = math.log2(errs[1] / errs[2])
+        assert abs(slope - order) < 0.2, (flow, errs)
+    c_cn = splitting.SplitPlan(sys, 0.0, "cn").evolve(c0, 0.05, 40, "strang")
+    assert abs(observables.mass(c_cn)[0] - observables.mass(c0)[0]) < 1e-13
+    masses = []
+    c = c0
+    plan = splitting.SplitPlan(sys, 0.0, "be")
+    for _ in range(10):
+        c = plan.lie_step(c, 0.05)
+        masses.append(observables.mass(c)[0])
+    assert all(b <= a + 1e-15 for a, b in zip([observables.mass(c0)[0]] + masses, masses))
+    assert masses[-1] < observables.mass(c0)[0] - 1e-6
