@@ -86,6 +86,73 @@ def cpu_baseline(spec, c0, tau, budget_s=15.0):
                       f"precompute {pre:.2f}s excluded"}
 
 
+def batch_workload(args):
+    """Many uneven systems in one grouped launch per pass, against stepping them one by one.
+
+    Systems (seeded PCG64): `--batch-1d` 1D+1D chains with period ratio drawn from
+    {golden mean, sqrt 2, sqrt 3} and Ec log-uniform in [1e3, 2e4], plus `--batch-2d`
+    twisted triangular bilayers with twist uniform in [1, 6] deg and N log-uniform in
+    [1e5, 4e5] (Ec = 6500 sqrt(N / 398821)); 16 wavepackets each; kappa = 1 (potential-only
+    fibre windows, shared propagators), Strang, tau = 1e-3 (1D) / 5e-3 (2D), `--paths`
+    first entry as precision.
+    """
+    import math
+    import torch
+    rng = np.random.default_rng(0)
+    prec = args.paths.split(",")[0]
+    specs = []
+    for _ in range(args.batch_1d):
+        ratio = [wl.GOLDEN, math.sqrt(2.0), math.sqrt(3.0)][rng.integers(3)]
+        Ec = float(np.exp(rng.uniform(np.log(1e3), np.log(2e4))))
+        specs.append((wl.chain_system(Ec, L2=ratio), 1e-3))
+    for _ in range(args.batch_2d):
+        theta = float(rng.uniform(1.0, 6.0))
+        Ntarget = float(np.exp(rng.uniform(np.log(1e5), np.log(4e5))))
+        specs.append((wl.twisted_system(6500.0 * math.sqrt(Ntarget / 398821.0), theta_deg=theta), 5e-3))
+    stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    items = []
+    for spec, tau in specs:
+        S = lsx.System.from_spec(spec)
+        P = lsx.Plan(S, tau, "strang", 1.0, prec, stream)
+        st = lsx.State(P, 16)
+        st.upload(wl.random_state(S.N, 16, seed=len(items)), stream)
+        items.append((S, P, st))
+    pre = time.perf_counter() - t0
+    B = lsx.Batch([it[2] for it in items])
+    coeffs = sum(it[0].N * 16 for it in items)
+    B.step(args.warmup, stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    B.step(args.steps, stream)
+    e1.record(stream)
+    e1.synchronize()
+    ms_batch = e0.elapsed_time(e1)
+    e0.record(stream)
+    for it in items:
+        it[2].step(args.steps, stream)
+    e1.record(stream)
+    e1.synchronize()
+    ms_seq = e0.elapsed_time(e1)
+    out = {"metric": METRIC + " (batched systems)", "value": coeffs * args.steps / (ms_batch * 1e-3),
+           "unit": "coeff*steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": ms_batch / args.steps, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": DTYPE[prec], "data": "synthetic",
+           "config": {"workload": f"batch_{args.batch_1d}x1d_{args.batch_2d}x2d_W16_kappa1",
+                      "systems": len(items), "total_coefficients": coeffs,
+                      "N_range": [min(it[0].N for it in items), max(it[0].N for it in items)],
+                      "tiles": {"layer1": B.tuning(1)[:2], "layer2": B.tuning(2)[:2]}},
+           "sequential_value": coeffs * args.steps / (ms_seq * 1e-3), "sequential_ms_per_step": ms_seq / args.steps,
+           "precompute_s": pre}
+    print(json.dumps(out))
+    B.destroy()
+    for S, P, st in items:
+        st.destroy()
+        P.destroy()
+        S.destroy()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -95,7 +162,9 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=400)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-mib", type=int, default=64)
-    ap.add_argument("--workload", default="chain", choices=["chain", "twisted", "twisted1", "tiny"],
+    ap.add_argument("--batch-1d", type=int, default=240)
+    ap.add_argument("--batch-2d", type=int, default=16)
+    ap.add_argument("--workload", default="chain", choices=["chain", "twisted", "twisted1", "tiny", "batch"],
                     help="chain: the metric's workload (default); the others are extra measurements")
     ap.add_argument("--kappa", type=float, default=0.0)
     args = ap.parse_args()
@@ -107,6 +176,8 @@ def main():
         sys.exit(2)
     import torch
 
+    if args.workload == "batch":
+        return batch_workload(args)
     w = {"chain": wl.chain, "twisted": wl.twisted, "twisted1": lambda: wl.twisted(W=1),
          "tiny": wl.tiny_chain}[args.workload]()
     S = lsx.System.from_spec(w.spec)

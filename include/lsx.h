@@ -224,6 +224,27 @@ lsx_status lsx_phase(lsx_plan* plan, lsx_state* st, int32_t half, void* stream);
  */
 lsx_status lsx_observables(lsx_plan* plan, lsx_state* st, uint32_t mask, double* out, void* stream);
 
+/*
+ * Batched systems -- several independent (plan, state) pairs advanced together: every
+ * fibre pass of the batch is ONE grouped kernel launch over the tiles of all systems
+ * (fibres of uneven lengths, systems of different cutoffs, lattices, W), and the
+ * repeated part of the step sequence is captured once in a HIP graph and replayed.
+ *
+ * lsx_batch_create: plans[i] and states[i] (i < n) must match (states[i] created on
+ *   plans[i]); all plans must share the scheme and the precision; states must be all
+ *   W = 1 or all W >= 2.  The tile shape is autotuned on the whole batch as for a state.
+ *   Plans and states must outlive the batch (destroying a state that is in a batch returns
+ *   LSX_E_STATE).  While a batch step is in flight no other call may use its states.
+ * lsx_batch_step: advances every state by nsteps * tau_i with its plan's scheme, exactly
+ *   as lsx_step would (bit-for-bit up to the tile shape's summation order).  Stream-ordered.
+ * lsx_batch_tuning: tile shape and measured pass time of `layer` for the whole batch.
+ */
+typedef struct lsx_batch lsx_batch;
+lsx_status lsx_batch_create(lsx_plan* const* plans, lsx_state* const* states, int32_t n, lsx_batch** out);
+lsx_status lsx_batch_step(lsx_batch* batch, int64_t nsteps, void* stream);
+lsx_status lsx_batch_tuning(const lsx_batch* batch, int32_t layer, int32_t* nb, int32_t* ks, double* pass_us);
+lsx_status lsx_batch_destroy(lsx_batch* batch);
+
 #ifdef __cplusplus
 }
 #endif

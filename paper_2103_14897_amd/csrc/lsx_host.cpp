@@ -7,6 +7,8 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <memory>
+#include <tuple>
 #include <numeric>
 #include <string>
 #include <unordered_map>
@@ -654,6 +656,7 @@ struct lsx_state {
   float tuned_us[2] = {0.f, 0.f};      // measured pass time of the chosen shape (0: not tuned)
   DBuf<double> partial, result;
   int nred = 0;
+  int nbatches = 0;                    // batches that reference this state
 };
 
 static int env_int(const char* name, int dflt);
@@ -870,6 +873,7 @@ extern "C" lsx_status lsx_state_tuning(const lsx_state* st, int32_t layer, int32
 
 extern "C" lsx_status lsx_state_destroy(lsx_state* st) {
   if (!st) return LSX_OK;
+  if (st->nbatches > 0) return fail(LSX_E_STATE, "state is still part of a batch");
   st->plan->nstates--;
   delete st;
   return LSX_OK;
@@ -1040,5 +1044,373 @@ extern "C" lsx_status lsx_observables(lsx_plan* pl, lsx_state* st, uint32_t mask
   LSX_HIP_TRY(hipStreamSynchronize(s));
   for (size_t i = 0; i < count; ++i)
     if (!std::isfinite(out[i])) return fail(LSX_E_NONFINITE, "observable is NaN or Inf");
+  return LSX_OK;
+}
+
+// ================================================================ batched systems
+namespace {
+struct PassSpec {
+  int layer, half, next, phase_half;
+};
+struct PatternKey {
+  int layer, half, inlay, outlay, phase_half, cur;
+  bool operator<(const PatternKey& o) const {
+    return std::tie(layer, half, inlay, outlay, phase_half, cur) <
+           std::tie(o.layer, o.half, o.inlay, o.outlay, o.phase_half, o.cur);
+  }
+};
+}  // namespace
+
+struct lsx_batch {
+  std::vector<lsx_plan*> pl;
+  std::vector<lsx_state*> st;
+  int fmt = 0, scheme = 0;
+  bool w1 = false;
+  DBuf<TileDesc> tiles[2];
+  int ntiles[2] = {0, 0};
+  int nb[2] = {1, 1}, ks[2] = {2, 2};
+  float tuned_us[2] = {0.f, 0.f};
+  std::map<PatternKey, std::unique_ptr<DBuf<PassArgs>>> args;
+  std::vector<std::pair<double2*, double2*>> bufs;  // buffers the argument arrays refer to
+  DBuf<int32_t> marker;                              // non-null in_pos marker for gathering passes
+  hipStream_t cap = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  ~lsx_batch() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap) (void)hipStreamDestroy(cap);
+  }
+};
+
+// index table of `layer`'s fibre positions inside an array of layout `layout` (see Runner)
+static const int32_t* layout_table(const lsx_plan* pl, int layer, int layout) {
+  if (layout == layer) return nullptr;
+  return layer == 1 ? pl->L[0].rows.p : pl->pos1.p;
+}
+
+static void batch_drop_graph(lsx_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+}
+
+// per-system argument array of one pass pattern (built once, kept on the device)
+static lsx_status batch_args(lsx_batch* b, const PatternKey& k, const PassArgs** out) {
+  auto it = b->args.find(k);
+  if (it == b->args.end()) {
+    std::vector<PassArgs> v(b->pl.size());
+    for (size_t i = 0; i < b->pl.size(); ++i) {
+      const lsx_plan* pl = b->pl[i];
+      const lsx_state* st = b->st[i];
+      const LayerDev& ld = pl->L[k.layer - 1];
+      const PropSet& ps = ld.prop[k.half];
+      if (!ps.present) return fail(LSX_E_INVALID, "plan holds no propagator for this layer/half");
+      PassArgs& a = v[i];
+      a.tiles = nullptr;
+      a.in_pos = layout_table(pl, k.layer, k.inlay);
+      a.out_pos = layout_table(pl, k.layer, k.outlay);
+      a.ph_idx = (k.layer == 1) ? pl->L[0].rows.p : nullptr;
+      a.ph = (k.phase_half >= 0 && pl->kappa != 0.0) ? pl->phase[k.phase_half].p : nullptr;
+      a.P = ps.data.p;
+      a.diag = pl->diag.p ? pl->diag.p + (size_t)((k.layer - 1) * 2 + k.half) * pl->sys->N : nullptr;
+      a.X = st->buf[k.cur];
+      a.Y = st->buf[1 - k.cur];
+      a.zero = pl->zero.p;
+      a.batch = nullptr;
+      a.W = st->W;
+    }
+    auto d = std::make_unique<DBuf<PassArgs>>();
+    LSX_TRY(d->alloc(v.size()));
+    LSX_HIP_TRY(hipMemcpy(d->p, v.data(), v.size() * sizeof(PassArgs), hipMemcpyHostToDevice));
+    it = b->args.emplace(k, std::move(d)).first;
+  }
+  *out = it->second->p;
+  return LSX_OK;
+}
+
+// Tiles of all systems for one layer, f = system index, XCD-interleaved as build_tiles.
+static void batch_tiles(const lsx_batch* b, int layer, int nb, std::vector<TileDesc>& out) {
+  const int NX = std::max(1, env_int("LSX_XCDS", 8));
+  struct Item {
+    int sys, f, L;
+  };
+  std::vector<Item> items;
+  for (size_t i = 0; i < b->pl.size(); ++i) {
+    const LayerDev& ld = b->pl[i]->L[layer - 1];
+    for (int f = 0; f < ld.nf; ++f) items.push_back({(int)i, f, ld.h_ptr[f + 1] - ld.h_ptr[f]});
+  }
+  std::stable_sort(items.begin(), items.end(), [](const Item& x, const Item& y) { return x.L > y.L; });
+  std::vector<double> load(NX, 0.0);
+  std::vector<int64_t> count(NX, 0);
+  std::vector<std::vector<TileDesc>> bins(NX);
+  for (const Item& it : items) {
+    const lsx_plan* pl = b->pl[it.sys];
+    const LayerDev& ld = pl->L[layer - 1];
+    const int W = b->st[it.sys]->W;
+    const int wt = (W == 1) ? 1 : (W + 16 * nb - 1) / (16 * nb);
+    const int nrb = (it.L + 15) / 16;
+    int x = 0;
+    for (int y = 1; y < NX; ++y)
+      if (count[y] < count[x] || (count[y] == count[x] && load[y] < load[x])) x = y;
+    count[x] += (int64_t)nrb * wt;
+    load[x] += (double)nrb * wt * (it.L + 8);
+    for (int rb = 0; rb < nrb; ++rb)
+      for (int wb = 0; wb < wt; ++wb) {
+        TileDesc t;
+        t.r0 = ld.h_ptr[it.f];
+        t.L = it.L;
+        t.rb = rb;
+        t.wb = wb;
+        t.poff = ld.h_poff[it.f];
+        t.f = it.sys;
+        t.d0 = ld.h_d0[it.f];
+        bins[x].push_back(t);
+      }
+  }
+  TileDesc empty{};
+  empty.f = -1;
+  size_t maxlen = 0;
+  for (auto& bn : bins) maxlen = std::max(maxlen, bn.size());
+  out.clear();
+  for (size_t i = 0; i < maxlen; ++i)
+    for (int x = 0; x < NX; ++x) out.push_back(i < bins[x].size() ? bins[x][i] : empty);
+  while (!out.empty() && out.back().f < 0) out.pop_back();
+}
+
+// Launches one batched pass; (cur, lay) follow the same rules as Runner.
+static lsx_status batch_pass(lsx_batch* b, hipStream_t s, const PassSpec& p, int& cur, int& lay) {
+  const int outlay = (p.next == 0) ? 2 : p.next;
+  const PatternKey k{p.layer, p.half, lay, outlay, p.phase_half, cur};
+  const PassArgs* d = nullptr;
+  LSX_TRY(batch_args(b, k, &d));
+  PassArgs a0{};
+  a0.tiles = b->tiles[p.layer - 1].p;
+  a0.in_pos = (lay == p.layer) ? nullptr : b->marker.p;  // gather flag, uniform over the batch
+  a0.batch = d;
+  LSX_HIP_TRY(launch_pass(s, b->fmt, b->w1 ? 1 : 2, b->ntiles[p.layer - 1], b->nb[p.layer - 1],
+                          b->ks[p.layer - 1], a0, true));
+  cur ^= 1;
+  lay = outlay;
+  return LSX_OK;
+}
+
+extern "C" lsx_status lsx_batch_create(lsx_plan* const* plans, lsx_state* const* states, int32_t n, lsx_batch** out) {
+  if (!plans || !states || !out || n < 1) return fail(LSX_E_INVALID, "bad batch arguments");
+  lsx_batch* b = new (std::nothrow) lsx_batch();
+  if (!b) return fail(LSX_E_OOM, "host allocation failed");
+  auto cleanup = [&](lsx_status e) {
+    delete b;
+    return e;
+  };
+  for (int i = 0; i < n; ++i) {
+    if (!plans[i] || !states[i] || states[i]->plan != plans[i])
+      return cleanup(fail(LSX_E_STATE, "batch entry " + std::to_string(i) + ": state does not belong to plan"));
+    if (plans[i]->scheme != plans[0]->scheme || plans[i]->fmt != plans[0]->fmt)
+      return cleanup(fail(LSX_E_INVALID, "batch plans must share scheme and precision"));
+    if ((states[i]->W == 1) != (states[0]->W == 1))
+      return cleanup(fail(LSX_E_INVALID, "batch states must be all W = 1 or all W >= 2"));
+    for (int j = 0; j < i; ++j)
+      if (states[j] == states[i]) return cleanup(fail(LSX_E_INVALID, "a state appears twice in the batch"));
+    b->pl.push_back(plans[i]);
+    b->st.push_back(states[i]);
+  }
+  b->fmt = plans[0]->fmt;
+  b->scheme = plans[0]->scheme;
+  b->w1 = states[0]->W == 1;
+  lsx_status e;
+  if ((e = b->marker.alloc(1)) != LSX_OK) return cleanup(e);
+  // tile shape: autotune over the combined tiles with the steady-state pass patterns
+  struct Shape {
+    int nb, ks;
+  };
+  std::vector<Shape> cands;
+  int maxW = 1;
+  for (lsx_state* st : b->st) maxW = std::max(maxW, st->W);
+  if (b->w1) {
+    cands.push_back({1, 4});
+  } else {
+    for (int nbv : {1, 2, 4})
+      for (int k : {1, 2, 4})
+        if (16 * nbv <= round_up(maxW, 16) && !(nbv == 4 && k == 4)) cands.push_back({nbv, k});
+    const int fnb = env_int("LSX_NB", 0), fks = env_int("LSX_KS", 0);
+    if (fnb > 0 || fks > 0) cands.assign(1, Shape{fnb > 0 ? fnb : 1, fks > 0 ? fks : 2});
+    else if (env_int("LSX_AUTOTUNE", 1) == 0) cands.assign(1, Shape{1, 2});
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return cleanup(fail(LSX_E_HIP, "event creation failed"));
+  }
+  for (int layer = 1; layer <= 2; ++layer) {
+    float best = -1.f;
+    for (const Shape& c : cands) {
+      std::vector<TileDesc> t;
+      batch_tiles(b, layer, c.nb, t);
+      DBuf<TileDesc> d;
+      if ((e = d.upload(t, nullptr)) != LSX_OK) break;
+      // time a steady-state pass (fibre-contiguous read, scattered write) into the work arrays
+      std::swap(b->tiles[layer - 1].p, d.p);
+      std::swap(b->tiles[layer - 1].n, d.n);
+      const int save_nt = b->ntiles[layer - 1], save_nb = b->nb[layer - 1], save_ks = b->ks[layer - 1];
+      b->ntiles[layer - 1] = (int)t.size();
+      b->nb[layer - 1] = c.nb;
+      b->ks[layer - 1] = c.ks;
+      float ms = 0.f;
+      if (cands.size() > 1) {
+        int cur = 0, lay = layer;
+        const PassSpec p{layer, 0, layer == 1 ? 2 : 1, -1};
+        hipError_t he = hipSuccess;
+        int c2 = 0, l2 = lay;
+        if ((e = batch_pass(b, nullptr, p, c2, l2)) != LSX_OK) break;
+        he = hipEventRecord(e0, nullptr);
+        for (int r = 0; r < 5 && he == hipSuccess; ++r) {
+          cur = 0;
+          lay = layer;
+          if ((e = batch_pass(b, nullptr, p, cur, lay)) != LSX_OK) break;
+        }
+        if (e != LSX_OK) break;
+        if (he == hipSuccess) he = hipEventRecord(e1, nullptr);
+        if (he == hipSuccess) he = hipEventSynchronize(e1);
+        if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+        if (he != hipSuccess) {
+          e = fail(LSX_E_HIP, std::string("batch autotune: ") + hipGetErrorString(he));
+          break;
+        }
+        ms /= 5;
+      }
+      if (best < 0.f || ms < best) {
+        best = ms;  // keep: the new tiles stay installed
+      } else {
+        // restore the previous best
+        std::swap(b->tiles[layer - 1].p, d.p);
+        std::swap(b->tiles[layer - 1].n, d.n);
+        b->ntiles[layer - 1] = save_nt;
+        b->nb[layer - 1] = save_nb;
+        b->ks[layer - 1] = save_ks;
+      }
+    }
+    if (e != LSX_OK) break;
+    b->tuned_us[layer - 1] = cands.size() > 1 ? best * 1e3f : 0.f;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e != LSX_OK) return cleanup(e);
+  if (hipDeviceSynchronize() != hipSuccess) return cleanup(fail(LSX_E_HIP, "batch setup failed"));
+  for (lsx_state* st : b->st) st->nbatches++;
+  for (lsx_state* st : b->st) b->bufs.emplace_back(st->buf[0], st->buf[1]);
+  *out = b;
+  return LSX_OK;
+}
+
+extern "C" lsx_status lsx_batch_step(lsx_batch* b, int64_t nsteps, void* stream) {
+  if (!b) return fail(LSX_E_INVALID, "null batch");
+  if (nsteps < 0) return fail(LSX_E_INVALID, "nsteps must be >= 0");
+  if (nsteps == 0) return LSX_OK;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  // argument arrays refer to the states' arrays: rebuild them if a state swapped its arrays
+  for (size_t i = 0; i < b->st.size(); ++i)
+    if (b->bufs[i].first != b->st[i]->buf[0] || b->bufs[i].second != b->st[i]->buf[1]) {
+      b->args.clear();
+      batch_drop_graph(b);
+      for (size_t j = 0; j < b->st.size(); ++j) b->bufs[j] = {b->st[j]->buf[0], b->st[j]->buf[1]};
+      break;
+    }
+  std::vector<PassSpec> head, body, tail;
+  int64_t reps = 0;
+  if (b->scheme == LSX_STRANG) {
+    head = {{1, 1, 2, 1}};
+    body = {{2, 0, 1, 1}, {1, 0, 2, 1}};
+    tail = {{2, 0, 1, 1}, {1, 1, 0, -1}};
+    reps = nsteps - 1;
+  } else if (b->scheme == LSX_STRANG_CN) {
+    for (int64_t k = 0; k < nsteps; ++k) {
+      const bool last = (k + 1 == nsteps);
+      tail.push_back({1, 1, 2, 1});
+      tail.push_back({2, 0, 1, 1});
+      tail.push_back({1, 1, last ? 0 : 1, -1});
+    }
+  } else {  // Lie with exact or backward-Euler flows
+    if (nsteps == 1) {
+      tail = {{1, 0, 2, 0}, {2, 0, 0, -1}};
+    } else {
+      head = {{1, 0, 2, 0}, {2, 0, 1, -1}};
+      body = {{1, 0, 2, 0}, {2, 0, 1, -1}};
+      tail = {{1, 0, 2, 0}, {2, 0, 0, -1}};
+      reps = nsteps - 2;
+    }
+  }
+  int cur = 0, lay = 2;
+  for (const PassSpec& p : head) LSX_TRY(batch_pass(b, s, p, cur, lay));
+  if (reps > 0) {
+    // the body returns to the same (array, layout) state, so one captured graph serves
+    // every repetition; it is built on first use and kept with the batch
+    const int cur0 = cur, lay0 = lay;
+    if (!b->exec || env_int("LSX_GRAPH", 1) == 0) {
+      if (env_int("LSX_GRAPH", 1) == 0) {
+        for (int64_t r = 0; r < reps; ++r)
+          for (const PassSpec& p : body) LSX_TRY(batch_pass(b, s, p, cur, lay));
+      } else {
+        // build every argument array first: capture must not do synchronous copies
+        int c2 = cur, l2 = lay;
+        for (const PassSpec& p : body) {
+          const int outlay = (p.next == 0) ? 2 : p.next;
+          const PassArgs* d = nullptr;
+          LSX_TRY(batch_args(b, PatternKey{p.layer, p.half, l2, outlay, p.phase_half, c2}, &d));
+          c2 ^= 1;
+          l2 = outlay;
+        }
+        if (!b->cap) LSX_HIP_TRY(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+        LSX_HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+        lsx_status cap_err = LSX_OK;
+        for (const PassSpec& p : body)
+          if ((cap_err = batch_pass(b, b->cap, p, cur, lay)) != LSX_OK) break;
+        hipGraph_t g = nullptr;
+        const hipError_t ee = hipStreamEndCapture(b->cap, &g);
+        if (cap_err != LSX_OK) {
+          if (g) (void)hipGraphDestroy(g);
+          return cap_err;
+        }
+        LSX_HIP_TRY(ee);
+        b->graph = g;
+        LSX_HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+        cur = cur0;
+        lay = lay0;
+      }
+    }
+    if (b->exec && env_int("LSX_GRAPH", 1) != 0) {
+      for (int64_t r = 0; r < reps; ++r) LSX_HIP_TRY(hipGraphLaunch(b->exec, s));
+      // the body has an even number of passes and ends in the layout it started from
+      for (const PassSpec& p : body) {
+        cur ^= 1;
+        lay = (p.next == 0) ? 2 : p.next;
+      }
+      if (body.size() % 2 == 0) cur = cur0;
+      lay = lay0;
+    }
+  }
+  for (const PassSpec& p : tail) LSX_TRY(batch_pass(b, s, p, cur, lay));
+  if (cur != 0) {
+    for (lsx_state* st : b->st)
+      LSX_HIP_TRY(hipMemcpyAsync(st->buf[0], st->buf[1], (size_t)st->plan->sys->N * st->W * sizeof(double2),
+                                 hipMemcpyDeviceToDevice, s));
+  }
+  return LSX_OK;
+}
+
+extern "C" lsx_status lsx_batch_tuning(const lsx_batch* b, int32_t layer, int32_t* nb, int32_t* ks, double* pass_us) {
+  if (!b) return fail(LSX_E_INVALID, "null batch");
+  if (layer != 1 && layer != 2) return fail(LSX_E_INVALID, "layer must be 1 or 2");
+  if (nb) *nb = b->nb[layer - 1];
+  if (ks) *ks = b->ks[layer - 1];
+  if (pass_us) *pass_us = b->tuned_us[layer - 1];
+  return LSX_OK;
+}
+
+extern "C" lsx_status lsx_batch_destroy(lsx_batch* b) {
+  if (!b) return LSX_OK;
+  for (lsx_state* st : b->st) st->nbatches--;
+  delete b;
   return LSX_OK;
 }

@@ -57,6 +57,7 @@ struct TileDesc {
   int32_t d0;  // mixed formats: position of this propagator's diagonal (fibres may share one)
 };
 
+struct PassArgs;
 // Arguments of every fibre-pass kernel.  Element k of fibre f (fibre position
 // p = r0 + k) is row in_pos[p] of X and row out_pos[p] of Y (identity when null),
 // so a pass can read one array layout and write another.
@@ -71,6 +72,7 @@ struct PassArgs {
   const double2* X;       // input state  [rows][W]
   double2* Y;             // output state [rows][W]
   const void* zero;       // >= 256 zero bytes: target of every out-of-range operand load
+  const PassArgs* batch;  // batched launches: per-system arguments, indexed by TileDesc::f
   int32_t W;
 };
 
@@ -88,7 +90,8 @@ hipError_t launch_form(hipStream_t s, int fmt, int nb, int maxL, const int32_t* 
                        const double2* gh, const int64_t* loff, void* P, const int64_t* poff, double2* diag);
 hipError_t launch_phase_table(hipStream_t s, int64_t N, const double* K2, double theta_scale, double2* ph);
 hipError_t launch_phase_apply(hipStream_t s, int64_t N, int W, const double2* ph, double2* c);
-hipError_t launch_pass(hipStream_t s, int fmt, int W, int ntiles, int nb, int ksplit, const PassArgs& a);
+hipError_t launch_pass(hipStream_t s, int fmt, int W, int ntiles, int nb, int ksplit, const PassArgs& a,
+                       bool batched = false);
 hipError_t launch_reduce(hipStream_t s, int kind, int64_t N, int W, const double2* c, const double* K2,
                          int nv1, const int32_t* nbr1, const double2* v1, int nv2, const int32_t* nbr2,
                          const double2* v2, double* partial, int nblocks, double* out);

@@ -448,11 +448,13 @@ __device__ __forceinline__ void mma_group_f32(v4f (&rr)[NB], v4f (&ii)[NB], v4f 
 // FP64: complex128 P, X on v_mfma_f64_16x16x4f64.  Four independent accumulator chains
 // per column block (Pr Xr, Pi Xi, Pr Xi, Pi Xr); groups of U k-steps are double
 // buffered in registers, so the loads of group g+1 are in flight during the MFMAs of g.
-template <int NB, int KS, int U, bool GATHER>
-__global__ __launch_bounds__(64 * KS) void k_pass_f64(PassArgs a) {
+template <int NB, int KS, int U, bool GATHER, bool BATCH>
+__global__ __launch_bounds__(64 * KS) void k_pass_f64(PassArgs a0) {
   extern __shared__ double red[];
-  const TileDesc t = a.tiles[blockIdx.x];
+  const TileDesc t = a0.tiles[blockIdx.x];
   if (t.f < 0) return;
+  // batched launches: this tile's system arguments (uniform scalar loads)
+  const PassArgs a = BATCH ? a0.batch[t.f] : a0;
   const int r0 = t.r0, L = t.L;
   const int nks = ((L + 15) & ~15) >> 2;
   const int lane = threadIdx.x & 63, kw = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -496,11 +498,13 @@ __global__ __launch_bounds__(64 * KS) void k_pass_f64(PassArgs a) {
 
 // Mixed FP32: y = d .* x (FP64) + E x~ with E complex64, x~ = fp32(x), FP32 MFMA
 // accumulation (v_mfma_f32_16x16x4f32), same pipelining as the FP64 kernel.
-template <int NB, int KS, int U, bool GATHER>
-__global__ __launch_bounds__(64 * KS) void k_pass_f32(PassArgs a) {
+template <int NB, int KS, int U, bool GATHER, bool BATCH>
+__global__ __launch_bounds__(64 * KS) void k_pass_f32(PassArgs a0) {
   extern __shared__ double red[];
-  const TileDesc t = a.tiles[blockIdx.x];
+  const TileDesc t = a0.tiles[blockIdx.x];
   if (t.f < 0) return;
+  // batched launches: this tile's system arguments (uniform scalar loads)
+  const PassArgs a = BATCH ? a0.batch[t.f] : a0;
   const int r0 = t.r0, L = t.L;
   const int nks = ((L + 15) & ~15) >> 2;
   const int lane = threadIdx.x & 63, kw = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -608,11 +612,13 @@ __device__ __forceinline__ void mma_chunk_bf(v4f (&rr)[NB], v4f (&ii)[NB], v4f (
   }
 }
 
-template <int NB, int KS, int U, bool GATHER>
-__global__ __launch_bounds__(64 * KS) void k_pass_bf16x3(PassArgs a) {
+template <int NB, int KS, int U, bool GATHER, bool BATCH>
+__global__ __launch_bounds__(64 * KS) void k_pass_bf16x3(PassArgs a0) {
   extern __shared__ double red[];
-  const TileDesc t = a.tiles[blockIdx.x];
+  const TileDesc t = a0.tiles[blockIdx.x];
   if (t.f < 0) return;
+  // batched launches: this tile's system arguments (uniform scalar loads)
+  const PassArgs a = BATCH ? a0.batch[t.f] : a0;
   const int r0 = t.r0, L = t.L;
   const int nkc = ((L + 31) & ~31) >> 5;
   const int lane = threadIdx.x & 63, kw = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -657,11 +663,12 @@ __global__ __launch_bounds__(64 * KS) void k_pass_bf16x3(PassArgs a) {
 // (rb, k) multiplies entry (16rb+li, col) by x[col]; the four k-lanes and the KS waves
 // are summed in fixed order.  Mixed formats: E entries (rounded to their storage
 // precision) times the FP64 state, FP64 accumulation, plus the FP64 diagonal term.
-template <int KS, int FMT>
-__global__ __launch_bounds__(64 * KS) void k_gemv(PassArgs a) {
+template <int KS, int FMT, bool BATCH>
+__global__ __launch_bounds__(64 * KS) void k_gemv(PassArgs a0) {
   __shared__ double red[2 * KS * 16];
-  const TileDesc t = a.tiles[blockIdx.x];
+  const TileDesc t = a0.tiles[blockIdx.x];
   if (t.f < 0) return;
+  const PassArgs a = BATCH ? a0.batch[t.f] : a0;
   const int r0 = t.r0, L = t.L, rb = t.rb;
   const int lane = threadIdx.x & 63, kw = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int li = lane & 15, lk = lane >> 4;
@@ -900,54 +907,61 @@ static int prefetch_depth() {
   return u;
 }
 
-template <int NB, int KS, int U, bool G>
+template <int NB, int KS, int U, bool G, bool B>
 static hipError_t launch_mfma_u(hipStream_t s, int fmt, int ntiles, const PassArgs& a) {
   const size_t shm = KS > 1 ? (size_t)KS * NB * 2 * 4 * 64 * sizeof(double) : 0;
   if (fmt == PF_F64)
-    hipLaunchKernelGGL((k_pass_f64<NB, KS, U, G>), dim3(ntiles), dim3(64 * KS), shm, s, a);
+    hipLaunchKernelGGL((k_pass_f64<NB, KS, U, G, B>), dim3(ntiles), dim3(64 * KS), shm, s, a);
   else if (fmt == PF_F32)
-    hipLaunchKernelGGL((k_pass_f32<NB, KS, U, G>), dim3(ntiles), dim3(64 * KS), shm, s, a);
+    hipLaunchKernelGGL((k_pass_f32<NB, KS, U, G, B>), dim3(ntiles), dim3(64 * KS), shm, s, a);
   else
-    hipLaunchKernelGGL((k_pass_bf16x3<NB, KS, 1, G>), dim3(ntiles), dim3(64 * KS), shm, s, a);
+    hipLaunchKernelGGL((k_pass_bf16x3<NB, KS, 1, G, B>), dim3(ntiles), dim3(64 * KS), shm, s, a);
   return hipGetLastError();
 }
 
 template <int NB, int KS, bool G>
-static hipError_t launch_mfma_g(hipStream_t s, int fmt, int ntiles, const PassArgs& a) {
+static hipError_t launch_mfma_g(hipStream_t s, int fmt, int ntiles, const PassArgs& a, bool batched) {
+  if (batched) return launch_mfma_u<NB, KS, 2, G, true>(s, fmt, ntiles, a);
   switch (fmt == PF_BF16X3 ? 1 : prefetch_depth()) {
-    case 1: return launch_mfma_u<NB, KS, 1, G>(s, fmt, ntiles, a);
-    case 4: return launch_mfma_u<NB, KS, 4, G>(s, fmt, ntiles, a);
-    default: return launch_mfma_u<NB, KS, 2, G>(s, fmt, ntiles, a);
+    case 1: return launch_mfma_u<NB, KS, 1, G, false>(s, fmt, ntiles, a);
+    case 4: return launch_mfma_u<NB, KS, 4, G, false>(s, fmt, ntiles, a);
+    default: return launch_mfma_u<NB, KS, 2, G, false>(s, fmt, ntiles, a);
   }
 }
 
 template <int NB, int KS>
-static hipError_t launch_mfma(hipStream_t s, int fmt, int ntiles, const PassArgs& a) {
-  return a.in_pos ? launch_mfma_g<NB, KS, true>(s, fmt, ntiles, a) : launch_mfma_g<NB, KS, false>(s, fmt, ntiles, a);
+static hipError_t launch_mfma(hipStream_t s, int fmt, int ntiles, const PassArgs& a, bool batched, bool gather) {
+  return gather ? launch_mfma_g<NB, KS, true>(s, fmt, ntiles, a, batched)
+                : launch_mfma_g<NB, KS, false>(s, fmt, ntiles, a, batched);
 }
 
-template <int KS>
+template <int KS, bool B>
 static hipError_t launch_gemv(hipStream_t s, int fmt, int ntiles, const PassArgs& a) {
   if (fmt == PF_F64)
-    hipLaunchKernelGGL((k_gemv<KS, PF_F64>), dim3(ntiles), dim3(64 * KS), 0, s, a);
+    hipLaunchKernelGGL((k_gemv<KS, PF_F64, B>), dim3(ntiles), dim3(64 * KS), 0, s, a);
   else if (fmt == PF_F32)
-    hipLaunchKernelGGL((k_gemv<KS, PF_F32>), dim3(ntiles), dim3(64 * KS), 0, s, a);
+    hipLaunchKernelGGL((k_gemv<KS, PF_F32, B>), dim3(ntiles), dim3(64 * KS), 0, s, a);
   else
-    hipLaunchKernelGGL((k_gemv<KS, PF_BF16X3>), dim3(ntiles), dim3(64 * KS), 0, s, a);
+    hipLaunchKernelGGL((k_gemv<KS, PF_BF16X3, B>), dim3(ntiles), dim3(64 * KS), 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_pass(hipStream_t s, int fmt, int W, int ntiles, int nb, int ksplit, const PassArgs& a) {
+// batched: tile.f is a system index into a.batch and every system has its own W; the
+// caller passes gather = whether the systems' in_pos tables are set (uniform per pass)
+hipError_t launch_pass(hipStream_t s, int fmt, int W, int ntiles, int nb, int ksplit, const PassArgs& a,
+                       bool batched) {
   if (ntiles == 0) return hipSuccess;
+  const bool gather = a.in_pos != nullptr;
   if (W == 1) {
+    if (batched) return launch_gemv<4, true>(s, fmt, ntiles, a);
     switch (ksplit) {
-      case 1: return launch_gemv<1>(s, fmt, ntiles, a);
-      case 2: return launch_gemv<2>(s, fmt, ntiles, a);
-      default: return launch_gemv<4>(s, fmt, ntiles, a);
+      case 1: return launch_gemv<1, false>(s, fmt, ntiles, a);
+      case 2: return launch_gemv<2, false>(s, fmt, ntiles, a);
+      default: return launch_gemv<4, false>(s, fmt, ntiles, a);
     }
   }
 #define LSX_MFMA_CASE(NB_, KS_) \
-  if (nb == NB_ && ksplit == KS_) return launch_mfma<NB_, KS_>(s, fmt, ntiles, a);
+  if (nb == NB_ && ksplit == KS_) return launch_mfma<NB_, KS_>(s, fmt, ntiles, a, batched, gather);
   LSX_MFMA_CASE(1, 1)
   LSX_MFMA_CASE(1, 2)
   LSX_MFMA_CASE(1, 4)

@@ -54,6 +54,10 @@ _SIGS = {
     "lsx_fibre_pass": (C.c_int, [_p, _p, C.c_int32, C.c_int32, C.c_int32, _p]),
     "lsx_phase": (C.c_int, [_p, _p, C.c_int32, _p]),
     "lsx_observables": (C.c_int, [_p, _p, C.c_uint32, _dp, _p]),
+    "lsx_batch_create": (C.c_int, [C.POINTER(_p), C.POINTER(_p), C.c_int32, C.POINTER(_p)]),
+    "lsx_batch_step": (C.c_int, [_p, C.c_int64, _p]),
+    "lsx_batch_tuning": (C.c_int, [_p, C.c_int32, _i32p, _i32p, _dp]),
+    "lsx_batch_destroy": (C.c_int, [_p]),
 }
 
 
@@ -231,4 +235,30 @@ class State:
     def destroy(self):
         if self.h:
             _check(lib().lsx_state_destroy(self.h))
+            self.h = None
+
+
+class Batch:
+    """lsx_batch: several (plan, state) pairs stepped together by grouped launches."""
+
+    def __init__(self, states):
+        n = len(states)
+        plans = (_p * n)(*[st.plan.h.value for st in states])
+        sts = (_p * n)(*[st.h.value for st in states])
+        h = _p()
+        _check(lib().lsx_batch_create(plans, sts, n, C.byref(h)))
+        self.h = h
+        self.states = list(states)
+
+    def step(self, nsteps, stream=None):
+        _check(lib().lsx_batch_step(self.h, int(nsteps), _stream(stream)))
+
+    def tuning(self, layer):
+        nb, ks, us = C.c_int32(), C.c_int32(), C.c_double()
+        _check(lib().lsx_batch_tuning(self.h, int(layer), C.byref(nb), C.byref(ks), C.byref(us)))
+        return nb.value, ks.value, us.value
+
+    def destroy(self):
+        if self.h:
+            _check(lib().lsx_batch_destroy(self.h))
             self.h = None
