@@ -208,3 +208,19 @@ def chain(Ec: float = 2.0e4, W: int = 64) -> Workload:
 def twisted(Ec: float = 6500.0, W: int = 128) -> Workload:
     """Twisted triangular bilayer (+-2.5 deg), Ec = 6500, 128 wavepackets, tau = 5e-3 to T = 1."""
     return Workload(twisted_system(Ec), W=W, sigma=3.0, kmax=5.0, tau=5.0e-3, T=1.0)
+
+
+def uniforms(shape, seed: int = 0) -> np.ndarray:
+    """Uniform [0, 1) draws (PCG64) for the sampling steps; passed to every implementation as data."""
+    return np.random.default_rng(seed).random(shape)
+
+
+def mlp_init(nin: int, width: int = 64, seed: int = 0) -> np.ndarray:
+    """Initial parameters of the proposal network as one float32 vector, in the order
+    W1 [nin, width], b1, W2 [width, width], b2, w3 [width], b3: weights normal with variance
+    1 / fan_in (the output layer scaled by 0.1), biases zero."""
+    rng = np.random.default_rng(seed)
+    parts = [rng.standard_normal(nin * width) / math.sqrt(nin), np.zeros(width),
+             rng.standard_normal(width * width) / math.sqrt(width), np.zeros(width),
+             0.1 * rng.standard_normal(width) / math.sqrt(width), np.zeros(1)]
+    return np.concatenate(parts).astype(np.float32)
