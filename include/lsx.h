@@ -245,6 +245,127 @@ lsx_status lsx_batch_step(lsx_batch* batch, int64_t nsteps, void* stream);
 lsx_status lsx_batch_tuning(const lsx_batch* batch, int32_t layer, int32_t* nb, int32_t* ks, double* pass_us);
 lsx_status lsx_batch_destroy(lsx_batch* batch);
 
+/* ================================================================ semi-implicit, random batch and
+ * stochastic layer splitting
+ *
+ * lsx_si_step -- nsteps steps of the semi-implicit method (Alg. 1, Sec. 4.1):
+ *     c <- (I + i tau D)^{-1} (c - i tau V^1 c - i tau V^2 c),   D = diag(|G1m + G2n|^2 / 2),
+ *   with the plan's tau.  The potentials act through the neighbour stencil of eq. 3.6 in FP64;
+ *   the plan's scheme, kappa and precision do not enter.  Stream-ordered; uses the state's
+ *   work array.
+ */
+lsx_status lsx_si_step(lsx_plan* plan, lsx_state* st, int64_t nsteps, void* stream);
+
+typedef struct lsx_sampler lsx_sampler;
+typedef struct lsx_mlp lsx_mlp;
+
+/*
+ * lsx_sampler_create -- workspace of the stochastic steps of (plan, st).  Every wavepacket
+ *   (column) of the state samples on its own.
+ *   p1, p2  fibres drawn per wavepacket for each layer-1 / layer-2 sub-step, >= 0.  For
+ *           lsx_ss_step, 0 makes that layer's sub-steps the full deterministic pass (the
+ *           fallback); lsx_rb_step needs 1 <= p_j <= nfibres_j.
+ *   eps     in [0, 1]: uniform share of the importance proposal (keeps every q_f > 0).
+ *   Layers with more than 2048 fibres are rejected (LSX_E_INVALID).  The sampler must be
+ *   destroyed before its state and plan (LSX_E_STATE otherwise).
+ */
+lsx_status lsx_sampler_create(lsx_plan* plan, lsx_state* st, int32_t p1, int32_t p2, double eps,
+                              lsx_sampler** out);
+/* Attach the proposal network (NULL: uniform proposal).  Its input count must be d + 3.
+ * The network must outlive the sampler's use of it (lsx_mlp_destroy refuses while attached). */
+lsx_status lsx_sampler_set_mlp(lsx_sampler* sm, lsx_mlp* mlp);
+lsx_status lsx_sampler_destroy(lsx_sampler* sm);
+
+/*
+ * lsx_rb_step -- nsteps steps of the random batch method (Alg. 4): the step of lsx_si_step
+ *   with V^1 applied only on p1 layer-1 fibres and V^2 only on p2 layer-2 fibres, chosen per
+ *   wavepacket uniformly without replacement and scaled by nfibres_j / p_j (the fibre counts
+ *   stand for |I_2| and |I_1| of the paper).
+ *   u  device array [nsteps][2][W][pmax] of uniforms in [0, 1), pmax = max(p1, p2);
+ *      u[k][j-1][w][s] places the s-th pick of layer j for wavepacket w in step k by a partial
+ *      Fisher-Yates shuffle (position s swaps with s + floor(u (nfibres_j - s))).
+ *   Stream-ordered; the caller keeps u alive until the stream has passed the call.
+ */
+lsx_status lsx_rb_step(lsx_sampler* sm, const double* u, int64_t nsteps, void* stream);
+
+/*
+ * lsx_ss_step -- nsteps steps of stochastic layer splitting: the plan's Lie or Strang
+ *   composition (App. A; unmerged) with every fibre sub-step F_j(t) c = c + sum_f (P_f - I) c_f
+ *   replaced by the unbiased estimate
+ *       c + sum_{s=1..p_j} (P_{f_s}(t) - I) c_{f_s} / (p_j q_{f_s}),
+ *   the fibres f_s drawn independently per wavepacket from q = (1 - eps) softmax(z) + eps / nf
+ *   (z: the attached network on lsx_sampler_features of the state entering the sub-step;
+ *   uniform q without a network).  This carries the random batch idea of Alg. 4 over to the
+ *   fibre flows of Alg. 2 / App. A.  Sub-steps: Lie F1(tau), F2(tau); Strang F1(tau/2),
+ *   F2(tau), F1(tau/2); the kinetic phase follows F1 and F2 as in lsx_step when kappa > 0.
+ *   u  device array [nsteps][nsub][W][pmax] (nsub = 2 Lie, 3 Strang): draw s of sub-step k
+ *      in step n is the first fibre whose running sum of q exceeds u[n][k][w][s].
+ *   Stream-ordered; uses the state's work array.
+ */
+lsx_status lsx_ss_step(lsx_sampler* sm, const double* u, int64_t nsteps, void* stream);
+
+/*
+ * lsx_sampler_weights -- one layer's sampling alone.  wt: device [nfibres][W] (FP64).
+ *   mode 0: importance draws (weights 1/(p q_f) summed per fibre) from logits z (device
+ *           [W][nfibres] FP32, NULL = uniform) with the sampler's eps and p_layer >= 1;
+ *   mode 1: Alg. 4 subsets, weight nfibres / p_layer on the chosen fibres (z ignored).
+ *   u: device [W][p_layer].  Stream-ordered.
+ */
+lsx_status lsx_sampler_weights(lsx_sampler* sm, int32_t layer, int32_t mode, const float* z, const double* u,
+                               double* wt, void* stream);
+
+/*
+ * lsx_sampler_features -- inputs of the proposal network for the state's current coefficients:
+ *   X device [W][nfibres][d+3] FP32, per wavepacket and fibre of `layer`: shift / Kmax (d
+ *   entries), |shift / Kmax|^2, log10(max(fibre mass, 1e-30)) / 10, layer sign (-1 layer 1,
+ *   +1 layer 2); shift = G2 n for the layer-1 fibre of n, G1 m for the layer-2 fibre of m
+ *   (the Bloch shift of Sec. 3), Kmax = sqrt(2 Ec).  Stream-ordered.
+ */
+lsx_status lsx_sampler_features(lsx_sampler* sm, int32_t layer, float* X, void* stream);
+
+/*
+ * lsx_sampler_increments -- b device [W][nfibres] FP64: ||(P_f(t) - I) c_f||^2 per wavepacket
+ *   and fibre of `layer`, t = tau (half 0) or tau/2 (half 1), from the plan's propagators.  The
+ *   optimal proposal of a sub-step is q_f ~ sqrt(b_f); these are the network's training
+ *   targets.  The state is not modified (the work array is).  Stream-ordered.
+ */
+lsx_status lsx_sampler_increments(lsx_sampler* sm, int32_t layer, int32_t half, double* b, void* stream);
+
+/* ================================================================ proposal network
+ *
+ * A 3-layer tanh MLP of width 64 in FP32: z = w3 . tanh(W2^T tanh(W1^T x + b1) + b2) + b3 with
+ * nin in [1, 8] inputs.  Flat parameter order: W1 [nin][64] row-major, b1 [64], W2 [64][64]
+ * row-major, b2 [64], w3 [64], b3 (64 nin + 4289 floats).  Device arrays are the caller's.
+ *
+ * lsx_mlp_create     parameters and Adam moments start at zero.
+ * lsx_mlp_set/get    host copies of the flat parameters (set also resets Adam; get synchronises).
+ * lsx_mlp_forward    z[m] for the M rows of X [M][nin] (device).
+ * lsx_mlp_backward   grad (device, nparams) = d(sum_m dz[m] z[m]) / d theta.
+ * lsx_mlp_loss       normalised variance objective of groups g = rows gptr[g]..gptr[g+1]
+ *                    (gptr device, ngroups + 1 entries): q = (1 - eps) softmax(z_g) + eps / n_g,
+ *                    l_g = sum b/q / (sum sqrt b)^2; out (device, 2 doubles) = mean of l_g over
+ *                    groups with sum b > 0 and 1 / their count; dz (device, gptr[ngroups]) =
+ *                    gradient of that mean.
+ * lsx_mlp_adam       one Adam step (Kingma & Ba) with gradient grad (device).
+ * lsx_mlp_train_step forward, objective, backward and Adam on one batch of M rows; out as in
+ *                    lsx_mlp_loss, evaluated before the update.
+ * All stream-ordered except get.
+ */
+lsx_status lsx_mlp_create(int32_t nin, lsx_mlp** out);
+lsx_status lsx_mlp_nparams(const lsx_mlp* mlp, int64_t* n);
+lsx_status lsx_mlp_set(lsx_mlp* mlp, const float* theta, void* stream);
+lsx_status lsx_mlp_get(const lsx_mlp* mlp, float* theta, void* stream);
+lsx_status lsx_mlp_forward(const lsx_mlp* mlp, const float* X, int64_t M, float* z, void* stream);
+lsx_status lsx_mlp_backward(lsx_mlp* mlp, const float* X, int64_t M, const float* dz, float* grad, void* stream);
+lsx_status lsx_mlp_loss(lsx_mlp* mlp, const float* z, const double* b, const int64_t* gptr, int64_t ngroups,
+                        double eps, double* out, float* dz, void* stream);
+lsx_status lsx_mlp_adam(lsx_mlp* mlp, const float* grad, double lr, double beta1, double beta2, double adam_eps,
+                        void* stream);
+lsx_status lsx_mlp_train_step(lsx_mlp* mlp, const float* X, int64_t M, const double* b, const int64_t* gptr,
+                              int64_t ngroups, double eps, double lr, double beta1, double beta2, double adam_eps,
+                              double* out, void* stream);
+lsx_status lsx_mlp_destroy(lsx_mlp* mlp);
+
 #ifdef __cplusplus
 }
 #endif

@@ -18,7 +18,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", os.path.
           "-I", CSRC, "-Wall", "-Wno-unused-function",
           # packed FP32 VALU forms are kept out of every code object
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-SOURCES = ["lsx_host.cpp", "lsx_kernels.hip"]
+SOURCES = ["lsx_host.cpp", "lsx_kernels.hip", "lsx_sample.hip"]
 
 
 def _compile(src):

@@ -657,6 +657,7 @@ struct lsx_state {
   DBuf<double> partial, result;
   int nred = 0;
   int nbatches = 0;                    // batches that reference this state
+  int nsamplers = 0;                   // samplers that reference this state
 };
 
 static int env_int(const char* name, int dflt);
@@ -874,6 +875,7 @@ extern "C" lsx_status lsx_state_tuning(const lsx_state* st, int32_t layer, int32
 extern "C" lsx_status lsx_state_destroy(lsx_state* st) {
   if (!st) return LSX_OK;
   if (st->nbatches > 0) return fail(LSX_E_STATE, "state is still part of a batch");
+  if (st->nsamplers > 0) return fail(LSX_E_STATE, "state still has a sampler");
   st->plan->nstates--;
   delete st;
   return LSX_OK;
@@ -1412,5 +1414,458 @@ extern "C" lsx_status lsx_batch_destroy(lsx_batch* b) {
   if (!b) return LSX_OK;
   for (lsx_state* st : b->st) st->nbatches--;
   delete b;
+  return LSX_OK;
+}
+
+// ================================================================ proposal network
+struct lsx_mlp {
+  int nin = 0, n = 0;
+  DBuf<float> theta, m, v, grad, partial, z, dz;
+  DBuf<double> lg, out;
+  DBuf<int32_t> active;
+  int64_t t = 0;  // Adam steps taken
+  int nsamplers = 0;
+};
+
+template <typename T>
+static lsx_status ensure(DBuf<T>& b, size_t n) {
+  if (b.n >= n && b.p) return LSX_OK;
+  return b.alloc(n);
+}
+
+extern "C" lsx_status lsx_mlp_create(int32_t nin, lsx_mlp** out) {
+  if (!out) return fail(LSX_E_INVALID, "null argument");
+  if (nin < 1 || nin > 8) return fail(LSX_E_INVALID, "nin must be in [1, 8]");
+  std::unique_ptr<lsx_mlp> m(new (std::nothrow) lsx_mlp());
+  if (!m) return fail(LSX_E_OOM, "host allocation failed");
+  m->nin = nin;
+  m->n = mlp_nparams(nin);
+  LSX_TRY(m->theta.alloc(m->n));
+  LSX_TRY(m->m.alloc(m->n));
+  LSX_TRY(m->v.alloc(m->n));
+  LSX_TRY(m->grad.alloc(m->n));
+  LSX_TRY(m->out.alloc(2));
+  LSX_HIP_TRY(hipMemset(m->theta.p, 0, m->n * sizeof(float)));
+  LSX_HIP_TRY(hipMemset(m->m.p, 0, m->n * sizeof(float)));
+  LSX_HIP_TRY(hipMemset(m->v.p, 0, m->n * sizeof(float)));
+  *out = m.release();
+  return LSX_OK;
+}
+
+extern "C" lsx_status lsx_mlp_nparams(const lsx_mlp* m, int64_t* n) {
+  if (!m || !n) return fail(LSX_E_INVALID, "null argument");
+  *n = m->n;
+  return LSX_OK;
+}
+
+extern "C" lsx_status lsx_mlp_set(lsx_mlp* m, const float* theta, void* stream) {
+  if (!m || !theta) return fail(LSX_E_INVALID, "null argument");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  LSX_HIP_TRY(hipMemcpyAsync(m->theta.p, theta, m->n * sizeof(float), hipMemcpyHostToDevice, s));
+  LSX_HIP_TRY(hipMemsetAsync(m->m.p, 0, m->n * sizeof(float), s));
+  LSX_HIP_TRY(hipMemsetAsync(m->v.p, 0, m->n * sizeof(float), s));
+  LSX_HIP_TRY(hipStreamSynchronize(s));
+  m->t = 0;
+  return LSX_OK;
+}
+
+extern "C" lsx_status lsx_mlp_get(const lsx_mlp* m, float* theta, void* stream) {
+  if (!m || !theta) return fail(LSX_E_INVALID, "null argument");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  LSX_HIP_TRY(hipMemcpyAsync(theta, m->theta.p, m->n * sizeof(float), hipMemcpyDeviceToHost, s));
+  LSX_HIP_TRY(hipStreamSynchronize(s));
+  return LSX_OK;
+}
+
+extern "C" lsx_status lsx_mlp_forward(const lsx_mlp* m, const float* X, int64_t M, float* z, void* stream) {
+  if (!m || (M > 0 && (!X || !z))) return fail(LSX_E_INVALID, "null argument");
+  if (M < 0) return fail(LSX_E_INVALID, "M must be >= 0");
+  LSX_HIP_TRY(launch_mlp_fwd(reinterpret_cast<hipStream_t>(stream), m->theta.p, m->nin, X, M, z));
+  return LSX_OK;
+}
+
+static lsx_status mlp_backward(lsx_mlp* m, const float* X, int64_t M, const float* dz, const double* gscale,
+                               float* grad, hipStream_t s) {
+  LSX_TRY(ensure(m->partial, (size_t)mlp_bwd_blocks(M) * m->n));
+  LSX_HIP_TRY(launch_mlp_bwd(s, m->theta.p, m->nin, X, M, dz, gscale, m->partial.p, grad));
+  return LSX_OK;
+}
+
+extern "C" lsx_status lsx_mlp_backward(lsx_mlp* m, const float* X, int64_t M, const float* dz, float* grad,
+                                       void* stream) {
+  if (!m || !grad || (M > 0 && (!X || !dz))) return fail(LSX_E_INVALID, "null argument");
+  if (M < 0) return fail(LSX_E_INVALID, "M must be >= 0");
+  return mlp_backward(m, X, M, dz, nullptr, grad, reinterpret_cast<hipStream_t>(stream));
+}
+
+static lsx_status mlp_loss(lsx_mlp* m, const float* z, const double* b, const int64_t* gptr, int64_t G, double eps,
+                           double* out, float* dz, hipStream_t s) {
+  LSX_TRY(ensure(m->lg, (size_t)std::max<int64_t>(G, 1)));
+  LSX_TRY(ensure(m->active, (size_t)std::max<int64_t>(G, 1)));
+  LSX_HIP_TRY(launch_loss(s, z, b, gptr, G, eps, m->lg.p, m->active.p, dz, out));
+  return LSX_OK;
+}
+
+extern "C" lsx_status lsx_mlp_loss(lsx_mlp* m, const float* z, const double* b, const int64_t* gptr,
+                                   int64_t ngroups, double eps, double* out, float* dz, void* stream) {
+  if (!m || !out || (ngroups > 0 && (!z || !b || !gptr || !dz))) return fail(LSX_E_INVALID, "null argument");
+  if (ngroups < 0) return fail(LSX_E_INVALID, "ngroups must be >= 0");
+  if (!(eps >= 0.0 && eps <= 1.0)) return fail(LSX_E_INVALID, "eps must be in [0, 1]");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (ngroups == 0) {
+    LSX_HIP_TRY(hipMemsetAsync(out, 0, 2 * sizeof(double), s));
+    return LSX_OK;
+  }
+  LSX_TRY(mlp_loss(m, z, b, gptr, ngroups, eps, out, dz, s));
+  // dz of the mean: scale by 1 / (number of active groups), read from out[1]
+  int64_t M = 0;
+  LSX_HIP_TRY(hipMemcpyAsync(&M, gptr + ngroups, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  LSX_HIP_TRY(hipStreamSynchronize(s));
+  LSX_HIP_TRY(launch_scale_f32(s, M, out + 1, dz));
+  return LSX_OK;
+}
+
+static lsx_status mlp_adam(lsx_mlp* m, const float* grad, double lr, double b1, double b2, double eps,
+                           hipStream_t s) {
+  m->t += 1;
+  const double c1 = 1.0 / (1.0 - std::pow(b1, (double)m->t));
+  const double c2 = 1.0 / (1.0 - std::pow(b2, (double)m->t));
+  LSX_HIP_TRY(launch_adam(s, m->n, m->theta.p, m->m.p, m->v.p, grad, lr, b1, b2, eps, c1, c2));
+  return LSX_OK;
+}
+
+static bool adam_args_ok(double lr, double b1, double b2, double eps) {
+  return std::isfinite(lr) && b1 >= 0.0 && b1 < 1.0 && b2 >= 0.0 && b2 < 1.0 && eps > 0.0;
+}
+
+extern "C" lsx_status lsx_mlp_adam(lsx_mlp* m, const float* grad, double lr, double b1, double b2, double eps,
+                                   void* stream) {
+  if (!m || !grad) return fail(LSX_E_INVALID, "null argument");
+  if (!adam_args_ok(lr, b1, b2, eps)) return fail(LSX_E_INVALID, "bad Adam hyper-parameters");
+  return mlp_adam(m, grad, lr, b1, b2, eps, reinterpret_cast<hipStream_t>(stream));
+}
+
+extern "C" lsx_status lsx_mlp_train_step(lsx_mlp* m, const float* X, int64_t M, const double* b,
+                                         const int64_t* gptr, int64_t ngroups, double eps, double lr, double b1,
+                                         double b2, double adam_eps, double* out, void* stream) {
+  if (!m || !X || !b || !gptr || !out) return fail(LSX_E_INVALID, "null argument");
+  if (M < 1 || ngroups < 1) return fail(LSX_E_INVALID, "need M >= 1 rows and ngroups >= 1");
+  if (!(eps >= 0.0 && eps <= 1.0)) return fail(LSX_E_INVALID, "eps must be in [0, 1]");
+  if (!adam_args_ok(lr, b1, b2, adam_eps)) return fail(LSX_E_INVALID, "bad Adam hyper-parameters");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  LSX_TRY(ensure(m->z, (size_t)M));
+  LSX_TRY(ensure(m->dz, (size_t)M));
+  LSX_HIP_TRY(launch_mlp_fwd(s, m->theta.p, m->nin, X, M, m->z.p));
+  LSX_TRY(mlp_loss(m, m->z.p, b, gptr, ngroups, eps, out, m->dz.p, s));
+  LSX_TRY(mlp_backward(m, X, M, m->dz.p, out + 1, m->grad.p, s));
+  return mlp_adam(m, m->grad.p, lr, b1, b2, adam_eps, s);
+}
+
+extern "C" lsx_status lsx_mlp_destroy(lsx_mlp* m) {
+  if (!m) return LSX_OK;
+  if (m->nsamplers > 0) return fail(LSX_E_STATE, "network is attached to a sampler");
+  delete m;
+  return LSX_OK;
+}
+
+// ================================================================ stochastic steps
+// Sampled fibre sub-steps run in the canonical layout: the weighted pass reads the state,
+// writes the rows of the sampled fibres into the work array, and those rows are copied
+// back; every other row is left untouched.  Tiles are listed fibre-major, so the tiles of
+// the sampled fibres are compacted on the device without any host round trip.
+static constexpr int kSamplerMaxFibres = 2048;
+
+struct lsx_sampler {
+  lsx_plan* pl = nullptr;
+  lsx_state* st = nullptr;
+  lsx_mlp* mlp = nullptr;
+  int p[2] = {0, 0};
+  double eps = 0.0;
+  int nf[2] = {0, 0};
+  int ntiles[2] = {0, 0};
+  DBuf<TileDesc> tilesF[2], tilesC[2];
+  DBuf<int32_t> tptr[2], fid[2];
+  DBuf<int32_t> count, flag;
+  DBuf<double> wt[2], mass, sfeat[2];
+  DBuf<float> X, z;
+};
+
+extern "C" lsx_status lsx_sampler_create(lsx_plan* pl, lsx_state* st, int32_t p1, int32_t p2, double eps,
+                                         lsx_sampler** out) {
+  LSX_TRY(check_pair(pl, st));
+  if (!out) return fail(LSX_E_INVALID, "null argument");
+  if (p1 < 0 || p2 < 0) return fail(LSX_E_INVALID, "p1, p2 must be >= 0");
+  if (!(eps >= 0.0 && eps <= 1.0)) return fail(LSX_E_INVALID, "eps must be in [0, 1]");
+  const lsx_system* sys = pl->sys;
+  const int W = st->W, d = sys->d;
+  for (int j = 0; j < 2; ++j)
+    if (pl->L[j].nf > kSamplerMaxFibres)
+      return fail(LSX_E_INVALID, "sampler supports at most 2048 fibres per layer");
+  std::unique_ptr<lsx_sampler> sm(new (std::nothrow) lsx_sampler());
+  if (!sm) return fail(LSX_E_OOM, "host allocation failed");
+  sm->pl = pl;
+  sm->st = st;
+  sm->p[0] = p1;
+  sm->p[1] = p2;
+  sm->eps = eps;
+  const double kmax = std::sqrt(2.0 * sys->Ec);
+  int maxnf = 1;
+  for (int j = 0; j < 2; ++j) {
+    const LayerDev& ld = pl->L[j];
+    const FibreTable& ft = sys->fib[j];
+    const int nf = ld.nf;
+    sm->nf[j] = nf;
+    maxnf = std::max(maxnf, nf);
+    // fibre-major tiles in the state's tile shape
+    const int nb = st->nb[j];
+    const int nwb = (W + 16 * nb - 1) / (16 * nb);
+    std::vector<TileDesc> tiles;
+    std::vector<int32_t> tptr(nf + 1, 0);
+    for (int f = 0; f < nf; ++f) {
+      const int L = ld.h_ptr[f + 1] - ld.h_ptr[f];
+      for (int rb = 0; rb < (L + 15) / 16; ++rb)
+        for (int wb = 0; wb < nwb; ++wb) {
+          TileDesc t;
+          t.r0 = ld.h_ptr[f];
+          t.L = L;
+          t.rb = rb;
+          t.wb = wb;
+          t.poff = ld.h_poff.empty() ? 0 : ld.h_poff[f];
+          t.f = f;
+          t.d0 = ld.h_d0.empty() ? ld.h_ptr[f] : ld.h_d0[f];
+          tiles.push_back(t);
+        }
+      tptr[f + 1] = (int32_t)tiles.size();
+    }
+    sm->ntiles[j] = (int)tiles.size();
+    LSX_TRY(sm->tilesF[j].upload(tiles, nullptr));
+    LSX_TRY(sm->tilesC[j].alloc(tiles.size()));
+    LSX_TRY(sm->tptr[j].upload(tptr, nullptr));
+    // fibre of every canonical row, and the per-fibre shift features
+    std::vector<int32_t> fid((size_t)sys->N, 0);
+    std::vector<double> sf((size_t)nf * (d + 1), 0.0);
+    const double* B = sys->B[j == 0 ? 1 : 0];  // layer-1 fibres are shifted by G2 n, layer-2 by G1 m
+    const int other = (j == 0) ? d : 0;       // offset of the fibre's fixed index inside (m, n)
+    for (int f = 0; f < nf; ++f) {
+      for (int a = ft.ptr[f]; a < ft.ptr[f + 1]; ++a) fid[ft.rows[a]] = f;
+      if (ft.ptr[f + 1] > ft.ptr[f]) {
+        const int32_t* mn = &sys->mn[(size_t)ft.rows[ft.ptr[f]] * 2 * d];
+        double s2 = 0.0;
+        for (int k = 0; k < d; ++k) {
+          double g = 0.0;
+          for (int l = 0; l < d; ++l) g += B[k * d + l] * mn[other + l];
+          const double x = g / kmax;
+          sf[(size_t)f * (d + 1) + k] = x;
+          s2 += x * x;
+        }
+        sf[(size_t)f * (d + 1) + d] = s2;
+      }
+    }
+    LSX_TRY(sm->fid[j].upload(fid, nullptr));
+    LSX_TRY(sm->sfeat[j].upload(sf, nullptr));
+    LSX_TRY(sm->wt[j].alloc((size_t)std::max(nf, 1) * W));
+  }
+  LSX_TRY(sm->count.alloc(2));
+  LSX_TRY(sm->flag.alloc(maxnf));
+  LSX_TRY(sm->mass.alloc((size_t)maxnf * W));
+  LSX_TRY(sm->X.alloc((size_t)maxnf * W * (d + 3)));
+  LSX_TRY(sm->z.alloc((size_t)maxnf * W));
+  LSX_HIP_TRY(hipDeviceSynchronize());
+  st->nsamplers++;
+  *out = sm.release();
+  return LSX_OK;
+}
+
+extern "C" lsx_status lsx_sampler_set_mlp(lsx_sampler* sm, lsx_mlp* mlp) {
+  if (!sm) return fail(LSX_E_INVALID, "null argument");
+  if (mlp && mlp->nin != sm->pl->sys->d + 3) return fail(LSX_E_INVALID, "network must take d + 3 inputs");
+  if (sm->mlp) sm->mlp->nsamplers--;
+  sm->mlp = mlp;
+  if (mlp) mlp->nsamplers++;
+  return LSX_OK;
+}
+
+extern "C" lsx_status lsx_sampler_destroy(lsx_sampler* sm) {
+  if (!sm) return LSX_OK;
+  if (sm->mlp) sm->mlp->nsamplers--;
+  sm->st->nsamplers--;
+  delete sm;
+  return LSX_OK;
+}
+
+namespace {
+// canonical-layout position table of a layer's fibre positions (null: identity)
+const int32_t* canon_pos(const lsx_plan* pl, int layer) { return layer == 1 ? pl->L[0].rows.p : nullptr; }
+
+PassArgs canon_pass_args(const lsx_plan* pl, const lsx_state* st, int layer, int half) {
+  const LayerDev& ld = pl->L[layer - 1];
+  PassArgs a;
+  a.in_pos = canon_pos(pl, layer);
+  a.out_pos = canon_pos(pl, layer);
+  a.P = ld.prop[half].data.p;
+  a.diag = pl->diag.p ? pl->diag.p + (size_t)((layer - 1) * 2 + half) * pl->sys->N : nullptr;
+  a.X = st->buf[0];
+  a.Y = st->buf[1];
+  a.zero = pl->zero.p;
+  a.W = st->W;
+  return a;
+}
+
+// state's current coefficients -> network inputs of `layer` in sm->X
+lsx_status sampler_features(lsx_sampler* sm, int layer, float* X, hipStream_t s) {
+  const lsx_plan* pl = sm->pl;
+  const LayerDev& ld = pl->L[layer - 1];
+  const int W = sm->st->W;
+  LSX_HIP_TRY(launch_fibre_mass(s, ld.nf, ld.ptr.p, ld.rows.p, W, sm->st->buf[0], sm->mass.p));
+  LSX_HIP_TRY(launch_features(s, ld.nf, W, pl->sys->d, sm->sfeat[layer - 1].p, sm->mass.p,
+                              layer == 1 ? -1.f : 1.f, X));
+  return LSX_OK;
+}
+
+// one sampled sub-step of `layer` with propagators `half`, uniforms u [W][ustride]
+lsx_status sampled_substep(lsx_sampler* sm, int layer, int half, const double* u, int ustride, hipStream_t s) {
+  lsx_plan* pl = sm->pl;
+  lsx_state* st = sm->st;
+  const int j = layer - 1;
+  const int W = st->W, nf = sm->nf[j];
+  if (nf == 0) return LSX_OK;
+  if (!pl->L[j].prop[half].present) return fail(LSX_E_INVALID, "plan holds no propagator for this sub-step");
+  if (sm->p[j] == 0) {  // fallback: the deterministic pass
+    Runner r{pl, st, s};
+    LSX_TRY(r.pass(layer, half, 0, -1));
+    return r.finish();
+  }
+  const float* z = nullptr;
+  if (sm->mlp) {
+    LSX_TRY(sampler_features(sm, layer, sm->X.p, s));
+    LSX_HIP_TRY(launch_mlp_fwd(s, sm->mlp->theta.p, sm->mlp->nin, sm->X.p, (int64_t)W * nf, sm->z.p));
+    z = sm->z.p;
+  }
+  LSX_HIP_TRY(launch_sample_weights(s, nf, W, sm->p[j], ustride, u, z, sm->eps, sm->wt[j].p));
+  LSX_HIP_TRY(launch_compact(s, nf, W, sm->wt[j].p, sm->flag.p, sm->tptr[j].p, sm->tilesF[j].p, sm->tilesC[j].p,
+                             sm->count.p + j));
+  PassArgs a = canon_pass_args(pl, st, layer, half);
+  a.tiles = sm->tilesC[j].p;
+  a.tcount = sm->count.p + j;
+  a.wt = sm->wt[j].p;
+  LSX_HIP_TRY(launch_pass(s, pl->fmt, W, sm->ntiles[j], st->nb[j], st->ks[j], a));
+  LSX_HIP_TRY(launch_copy_tiles(s, sm->ntiles[j], sm->tilesC[j].p, sm->count.p + j, 16 * st->nb[j],
+                                canon_pos(pl, layer), W, st->buf[1], st->buf[0]));
+  return LSX_OK;
+}
+
+lsx_status phase_canon(lsx_plan* pl, lsx_state* st, int half, hipStream_t s) {
+  if (pl->kappa == 0.0 || pl->sys->N == 0) return LSX_OK;
+  LSX_HIP_TRY(launch_phase_apply(s, pl->sys->N, st->W, pl->phase[half].p, st->buf[0]));
+  return LSX_OK;
+}
+
+// Alg. 1 / Alg. 4 step from buf[0] into buf[1], then back into buf[0]
+lsx_status si_once(lsx_plan* pl, lsx_state* st, const double* wt1, const int32_t* fid1, const double* wt2,
+                   const int32_t* fid2, hipStream_t s) {
+  const lsx_system* sys = pl->sys;
+  LSX_HIP_TRY(launch_si_step(s, sys->N, st->W, pl->tau, pl->K2.p, sys->pot[0].nv, pl->L[0].nbr.p, pl->L[0].v.p,
+                             wt1, fid1, sys->pot[1].nv, pl->L[1].nbr.p, pl->L[1].v.p, wt2, fid2, st->buf[0],
+                             st->buf[1]));
+  Runner r{pl, st, s};
+  r.cur = 1;
+  return r.finish();
+}
+}  // namespace
+
+extern "C" lsx_status lsx_si_step(lsx_plan* pl, lsx_state* st, int64_t nsteps, void* stream) {
+  LSX_TRY(check_pair(pl, st));
+  if (nsteps < 0) return fail(LSX_E_INVALID, "nsteps must be >= 0");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  for (int64_t k = 0; k < nsteps && pl->sys->N > 0; ++k) LSX_TRY(si_once(pl, st, nullptr, nullptr, nullptr, nullptr, s));
+  return LSX_OK;
+}
+
+extern "C" lsx_status lsx_rb_step(lsx_sampler* sm, const double* u, int64_t nsteps, void* stream) {
+  if (!sm) return fail(LSX_E_INVALID, "null argument");
+  if (nsteps < 0) return fail(LSX_E_INVALID, "nsteps must be >= 0");
+  if (nsteps == 0 || sm->pl->sys->N == 0) return LSX_OK;
+  if (!u) return fail(LSX_E_INVALID, "null uniforms");
+  for (int j = 0; j < 2; ++j)
+    if (sm->p[j] < 1 || sm->p[j] > sm->nf[j]) return fail(LSX_E_INVALID, "random batch needs 1 <= p_j <= nfibres_j");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int W = sm->st->W, pmax = std::max(sm->p[0], sm->p[1]);
+  const int64_t per = (int64_t)W * pmax;
+  for (int64_t k = 0; k < nsteps; ++k) {
+    for (int j = 0; j < 2; ++j)
+      LSX_HIP_TRY(launch_subset_weights(s, sm->nf[j], W, sm->p[j], pmax, u + (2 * k + j) * per, sm->wt[j].p));
+    LSX_TRY(si_once(sm->pl, sm->st, sm->wt[0].p, sm->fid[0].p, sm->wt[1].p, sm->fid[1].p, s));
+  }
+  return LSX_OK;
+}
+
+extern "C" lsx_status lsx_ss_step(lsx_sampler* sm, const double* u, int64_t nsteps, void* stream) {
+  if (!sm) return fail(LSX_E_INVALID, "null argument");
+  if (nsteps < 0) return fail(LSX_E_INVALID, "nsteps must be >= 0");
+  if (nsteps == 0 || sm->pl->sys->N == 0) return LSX_OK;
+  if (!u && (sm->p[0] > 0 || sm->p[1] > 0)) return fail(LSX_E_INVALID, "null uniforms");
+  lsx_plan* pl = sm->pl;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const bool strang = scheme_strang(pl->scheme);
+  // (layer, propagator half, phase half after it or -1)
+  struct Sub {
+    int layer, half, ph;
+  };
+  const Sub lie[2] = {{1, 0, 0}, {2, 0, -1}};
+  const Sub str[3] = {{1, 1, 1}, {2, 0, 1}, {1, 1, -1}};
+  const Sub* subs = strang ? str : lie;
+  const int nsub = strang ? 3 : 2;
+  const int W = sm->st->W, pmax = std::max(1, std::max(sm->p[0], sm->p[1]));
+  const int64_t per = (int64_t)W * pmax;
+  for (int64_t k = 0; k < nsteps; ++k)
+    for (int i = 0; i < nsub; ++i) {
+      const double* uk = u ? u + (k * nsub + i) * per : nullptr;
+      LSX_TRY(sampled_substep(sm, subs[i].layer, subs[i].half, uk, pmax, s));
+      if (subs[i].ph >= 0) LSX_TRY(phase_canon(pl, sm->st, subs[i].ph, s));
+    }
+  return LSX_OK;
+}
+
+extern "C" lsx_status lsx_sampler_weights(lsx_sampler* sm, int32_t layer, int32_t mode, const float* z,
+                                          const double* u, double* wt, void* stream) {
+  if (!sm || !u || !wt) return fail(LSX_E_INVALID, "null argument");
+  if (layer != 1 && layer != 2) return fail(LSX_E_INVALID, "layer must be 1 or 2");
+  const int j = layer - 1, p = sm->p[j], nf = sm->nf[j];
+  if (p < 1) return fail(LSX_E_INVALID, "p of this layer must be >= 1");
+  if (nf == 0) return LSX_OK;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (mode == 0) {
+    LSX_HIP_TRY(launch_sample_weights(s, nf, sm->st->W, p, p, u, z, sm->eps, wt));
+  } else if (mode == 1) {
+    if (p > nf) return fail(LSX_E_INVALID, "subsets need p <= nfibres");
+    LSX_HIP_TRY(launch_subset_weights(s, nf, sm->st->W, p, p, u, wt));
+  } else {
+    return fail(LSX_E_INVALID, "mode must be 0 or 1");
+  }
+  return LSX_OK;
+}
+
+extern "C" lsx_status lsx_sampler_features(lsx_sampler* sm, int32_t layer, float* X, void* stream) {
+  if (!sm || !X) return fail(LSX_E_INVALID, "null argument");
+  if (layer != 1 && layer != 2) return fail(LSX_E_INVALID, "layer must be 1 or 2");
+  if (sm->nf[layer - 1] == 0) return LSX_OK;
+  return sampler_features(sm, layer, X, reinterpret_cast<hipStream_t>(stream));
+}
+
+extern "C" lsx_status lsx_sampler_increments(lsx_sampler* sm, int32_t layer, int32_t half, double* b,
+                                             void* stream) {
+  if (!sm || !b) return fail(LSX_E_INVALID, "null argument");
+  if (layer != 1 && layer != 2) return fail(LSX_E_INVALID, "layer must be 1 or 2");
+  if (half != 0 && half != 1) return fail(LSX_E_INVALID, "half must be 0 or 1");
+  lsx_plan* pl = sm->pl;
+  lsx_state* st = sm->st;
+  const LayerDev& ld = pl->L[layer - 1];
+  if (ld.nf == 0) return LSX_OK;
+  if (!ld.prop[half].present) return fail(LSX_E_INVALID, "plan holds no propagator for this layer/half");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  PassArgs a = canon_pass_args(pl, st, layer, half);
+  a.tiles = st->tiles[layer - 1].p;
+  LSX_HIP_TRY(launch_pass(s, pl->fmt, st->W, st->ntiles[layer - 1], st->nb[layer - 1], st->ks[layer - 1], a));
+  LSX_HIP_TRY(launch_fibre_incr(s, ld.nf, ld.ptr.p, ld.rows.p, st->W, st->buf[0], st->buf[1], b));
   return LSX_OK;
 }

@@ -61,19 +61,23 @@ struct PassArgs;
 // Arguments of every fibre-pass kernel.  Element k of fibre f (fibre position
 // p = r0 + k) is row in_pos[p] of X and row out_pos[p] of Y (identity when null),
 // so a pass can read one array layout and write another.
+// Weighted passes (wt set): the output is x + wt[f][w] (P_f x - x) per fibre f and column
+// w, i.e. a weighted fibre increment; tcount (device) bounds the tiles a launch runs.
 struct PassArgs {
-  const TileDesc* tiles;
-  const int32_t* in_pos;
-  const int32_t* out_pos;
-  const int32_t* ph_idx;  // canonical index of fibre position p (identity when null)
-  const double2* ph;      // kinetic phase applied to the output rows (none when null)
-  const void* P;          // propagator storage (format per kernel)
-  const double2* diag;    // mixed formats: diagonal of P at fibre position p
-  const double2* X;       // input state  [rows][W]
-  double2* Y;             // output state [rows][W]
-  const void* zero;       // >= 256 zero bytes: target of every out-of-range operand load
-  const PassArgs* batch;  // batched launches: per-system arguments, indexed by TileDesc::f
-  int32_t W;
+  const TileDesc* tiles = nullptr;
+  const int32_t* in_pos = nullptr;
+  const int32_t* out_pos = nullptr;
+  const int32_t* ph_idx = nullptr;  // canonical index of fibre position p (identity when null)
+  const double2* ph = nullptr;      // kinetic phase applied to the output rows (none when null)
+  const void* P = nullptr;          // propagator storage (format per kernel)
+  const double2* diag = nullptr;    // mixed formats: diagonal of P at fibre position p
+  const double2* X = nullptr;       // input state  [rows][W]
+  double2* Y = nullptr;             // output state [rows][W]
+  const void* zero = nullptr;       // >= 256 zero bytes: target of every out-of-range operand load
+  const PassArgs* batch = nullptr;  // batched launches: per-system arguments, indexed by TileDesc::f
+  const double* wt = nullptr;       // weighted passes: [fibre][W] increment weights
+  const int32_t* tcount = nullptr;  // device tile count: workgroups at or past it exit
+  int32_t W = 0;
 };
 
 // ---------------------------------------------------------------- kernel launchers (lsx_kernels.hip)
@@ -97,5 +101,33 @@ hipError_t launch_reduce(hipStream_t s, int kind, int64_t N, int W, const double
                          const double2* v2, double* partial, int nblocks, double* out);
 hipError_t launch_fibre_mass(hipStream_t s, int nf, const int32_t* ptr, const int32_t* rows, int W,
                              const double2* c, double* out);
+
+// ---------------------------------------------------------------- stochastic steps (lsx_sample.hip)
+hipError_t launch_si_step(hipStream_t s, int64_t N, int W, double tau, const double* K2, int nv1,
+                          const int32_t* nbr1, const double2* v1, const double* wt1, const int32_t* fid1, int nv2,
+                          const int32_t* nbr2, const double2* v2, const double* wt2, const int32_t* fid2,
+                          const double2* X, double2* Y);
+hipError_t launch_subset_weights(hipStream_t s, int nf, int W, int p, int ustride, const double* u, double* wt);
+hipError_t launch_sample_weights(hipStream_t s, int nf, int W, int p, int ustride, const double* u, const float* z,
+                                 double eps, double* wt);
+hipError_t launch_compact(hipStream_t s, int nf, int W, const double* wt, int32_t* flag, const int32_t* tptr,
+                          const TileDesc* tiles, TileDesc* out, int32_t* count);
+hipError_t launch_copy_tiles(hipStream_t s, int ntiles, const TileDesc* tiles, const int32_t* count, int ncols,
+                             const int32_t* pos, int W, const double2* src, double2* dst);
+hipError_t launch_fibre_incr(hipStream_t s, int nf, const int32_t* ptr, const int32_t* rows, int W,
+                             const double2* X, const double2* Y, double* out);
+hipError_t launch_features(hipStream_t s, int nf, int W, int d, const double* sfeat, const double* mass,
+                           float sign, float* X);
+// proposal network (width 64, FP32)
+int mlp_nparams(int nin);
+int mlp_bwd_blocks(int64_t M);
+hipError_t launch_mlp_fwd(hipStream_t s, const float* theta, int nin, const float* X, int64_t M, float* z);
+hipError_t launch_mlp_bwd(hipStream_t s, const float* theta, int nin, const float* X, int64_t M, const float* dz,
+                          const double* gscale, float* partial, float* grad);
+hipError_t launch_loss(hipStream_t s, const float* z, const double* b, const int64_t* gptr, int64_t G, double eps,
+                       double* lg, int32_t* active, float* dz, double* out);
+hipError_t launch_scale_f32(hipStream_t s, int64_t n, const double* scale, float* x);
+hipError_t launch_adam(hipStream_t s, int n, float* theta, float* m, float* v, const float* grad, double lr,
+                       double b1, double b2, double eps, double c1, double c2);
 
 }  // namespace lsx

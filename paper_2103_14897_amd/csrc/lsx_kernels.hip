@@ -357,11 +357,18 @@ __device__ __forceinline__ void pass_epilogue(const PassArgs& a, const TileDesc&
         yr = acc[nb][0][r];
         yi = acc[nb][1][r];
       }
-      if (MIX) {
-        const double2 dg = a.diag[t.d0 + arow];
+      if (MIX || a.wt) {
         const double2 x = a.X[irow * W + w];
-        yr += dg.x * x.x - dg.y * x.y;
-        yi += dg.x * x.y + dg.y * x.x;
+        if (MIX) {
+          const double2 dg = a.diag[t.d0 + arow];
+          yr += dg.x * x.x - dg.y * x.y;
+          yi += dg.x * x.y + dg.y * x.x;
+        }
+        if (a.wt) {
+          const double g = a.wt[(int64_t)t.f * W + w];
+          yr = x.x + g * (yr - x.x);
+          yi = x.y + g * (yi - x.y);
+        }
       }
       if (a.ph) {
         const double zr = ph.x * yr - ph.y * yi;
@@ -451,6 +458,7 @@ __device__ __forceinline__ void mma_group_f32(v4f (&rr)[NB], v4f (&ii)[NB], v4f 
 template <int NB, int KS, int U, bool GATHER, bool BATCH>
 __global__ __launch_bounds__(64 * KS) void k_pass_f64(PassArgs a0) {
   extern __shared__ double red[];
+  if (a0.tcount && (int)blockIdx.x >= *a0.tcount) return;
   const TileDesc t = a0.tiles[blockIdx.x];
   if (t.f < 0) return;
   // batched launches: this tile's system arguments (uniform scalar loads)
@@ -501,6 +509,7 @@ __global__ __launch_bounds__(64 * KS) void k_pass_f64(PassArgs a0) {
 template <int NB, int KS, int U, bool GATHER, bool BATCH>
 __global__ __launch_bounds__(64 * KS) void k_pass_f32(PassArgs a0) {
   extern __shared__ double red[];
+  if (a0.tcount && (int)blockIdx.x >= *a0.tcount) return;
   const TileDesc t = a0.tiles[blockIdx.x];
   if (t.f < 0) return;
   // batched launches: this tile's system arguments (uniform scalar loads)
@@ -615,6 +624,7 @@ __device__ __forceinline__ void mma_chunk_bf(v4f (&rr)[NB], v4f (&ii)[NB], v4f (
 template <int NB, int KS, int U, bool GATHER, bool BATCH>
 __global__ __launch_bounds__(64 * KS) void k_pass_bf16x3(PassArgs a0) {
   extern __shared__ double red[];
+  if (a0.tcount && (int)blockIdx.x >= *a0.tcount) return;
   const TileDesc t = a0.tiles[blockIdx.x];
   if (t.f < 0) return;
   // batched launches: this tile's system arguments (uniform scalar loads)
@@ -666,6 +676,7 @@ __global__ __launch_bounds__(64 * KS) void k_pass_bf16x3(PassArgs a0) {
 template <int KS, int FMT, bool BATCH>
 __global__ __launch_bounds__(64 * KS) void k_gemv(PassArgs a0) {
   __shared__ double red[2 * KS * 16];
+  if (a0.tcount && (int)blockIdx.x >= *a0.tcount) return;
   const TileDesc t = a0.tiles[blockIdx.x];
   if (t.f < 0) return;
   const PassArgs a = BATCH ? a0.batch[t.f] : a0;
@@ -732,11 +743,18 @@ __global__ __launch_bounds__(64 * KS) void k_gemv(PassArgs a0) {
         si += red[(j * 2 + 1) * 16 + li];
       }
       const int p = r0 + arow;
-      if (FMT != PF_F64) {
-        const double2 dg = a.diag[t.d0 + arow];
+      if (FMT != PF_F64 || a.wt) {
         const double2 x = a.X[in_row(a, p)];
-        sr += dg.x * x.x - dg.y * x.y;
-        si += dg.x * x.y + dg.y * x.x;
+        if (FMT != PF_F64) {
+          const double2 dg = a.diag[t.d0 + arow];
+          sr += dg.x * x.x - dg.y * x.y;
+          si += dg.x * x.y + dg.y * x.x;
+        }
+        if (a.wt) {
+          const double g = a.wt[t.f];
+          sr = x.x + g * (sr - x.x);
+          si = x.y + g * (si - x.y);
+        }
       }
       if (a.ph) {
         const double2 ph = a.ph[a.ph_idx ? a.ph_idx[p] : p];

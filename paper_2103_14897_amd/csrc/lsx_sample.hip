@@ -1,0 +1,686 @@
+// Stochastic steps of liblsx: the semi-implicit step (Alg. 1) and its random batch form
+// (Alg. 4) as one neighbour-stencil kernel, per-column fibre sampling (subsets without
+// replacement, importance draws from a proposal), compaction of the sampled fibres' tiles,
+// the per-fibre features and increment norms the proposal is trained on, and the proposal
+// network itself (a width-64 tanh MLP in FP32: forward, backward, variance objective, Adam).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lsx_internal.h"
+
+namespace lsx {
+
+// ---------------------------------------------------------------- semi-implicit / random batch
+// out[i][w] = (x - i tau (a1 (V^1 x)_i + a2 (V^2 x)_i)) / (1 + i tau |K_i|^2 / 2), where
+// (V^j x)_i = sum_p v_p x[nbr_j(i, p)] (the layer-j potential inside row i's fibre) and
+// a_j = wt_j[fibre_j(i)][w] (1 when wt_j is null: Alg. 1).  One thread per (row, column).
+__global__ __launch_bounds__(256) void k_si_step(int64_t N, int W, double tau, const double* __restrict__ K2,
+                                                 int nv1, const int32_t* __restrict__ nbr1,
+                                                 const double2* __restrict__ v1, const double* __restrict__ wt1,
+                                                 const int32_t* __restrict__ fid1, int nv2,
+                                                 const int32_t* __restrict__ nbr2, const double2* __restrict__ v2,
+                                                 const double* __restrict__ wt2, const int32_t* __restrict__ fid2,
+                                                 const double2* __restrict__ X, double2* __restrict__ Y) {
+  const int64_t total = N * (int64_t)W;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+    const int64_t i = e / W;
+    const int w = (int)(e - i * W);
+    double s1r = 0.0, s1i = 0.0, s2r = 0.0, s2i = 0.0;
+    for (int p = 0; p < nv1; ++p) {
+      const int j = nbr1[i * nv1 + p];
+      if (j >= 0) {
+        const double2 y = X[(int64_t)j * W + w], v = v1[p];
+        s1r += v.x * y.x - v.y * y.y;
+        s1i += v.x * y.y + v.y * y.x;
+      }
+    }
+    for (int p = 0; p < nv2; ++p) {
+      const int j = nbr2[i * nv2 + p];
+      if (j >= 0) {
+        const double2 y = X[(int64_t)j * W + w], v = v2[p];
+        s2r += v.x * y.x - v.y * y.y;
+        s2i += v.x * y.y + v.y * y.x;
+      }
+    }
+    const double a1 = wt1 ? wt1[(int64_t)fid1[i] * W + w] : 1.0;
+    const double a2 = wt2 ? wt2[(int64_t)fid2[i] * W + w] : 1.0;
+    const double2 x = X[e];
+    // z = x - i tau (a1 s1 + a2 s2)
+    const double zr = x.x + tau * (a1 * s1i + a2 * s2i);
+    const double zi = x.y - tau * (a1 * s1r + a2 * s2r);
+    // z / (1 + i b) = z (1 - i b) / (1 + b^2)
+    const double b = 0.5 * tau * K2[i];
+    const double den = 1.0 + b * b;
+    Y[e] = make_double2((zr + b * zi) / den, (zi - b * zr) / den);
+  }
+}
+
+// ---------------------------------------------------------------- per-column sampling
+// Random subset of p of the nf fibres for column w = blockIdx.x (Alg. 4): partial
+// Fisher-Yates with the uniforms u[w][0..p-1] (position s swaps with
+// s + floor(u (nf - s))), weight nf/p on the chosen fibres, 0 elsewhere; wt is [nf][W].
+__global__ __launch_bounds__(256) void k_subset_weights(int nf, int W, int p, int ustride, const double* u,
+                                                        double* wt) {
+  extern __shared__ int32_t perm[];
+  const int w = blockIdx.x;
+  for (int f = threadIdx.x; f < nf; f += blockDim.x) perm[f] = f;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double* uw = u + (int64_t)w * ustride;
+    for (int s = 0; s < p; ++s) {
+      int j = s + (int)floor(uw[s] * (double)(nf - s));
+      j = j < nf - 1 ? j : nf - 1;
+      const int tmp = perm[s];
+      perm[s] = perm[j];
+      perm[j] = tmp;
+    }
+  }
+  __syncthreads();
+  for (int f = threadIdx.x; f < nf; f += blockDim.x) wt[(int64_t)f * W + w] = 0.0;
+  __syncthreads();
+  const double g = (double)nf / (double)p;
+  for (int s = threadIdx.x; s < p; s += blockDim.x) wt[(int64_t)perm[s] * W + w] = g;
+}
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int h = blockDim.x >> 1; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ double block_max(double v, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int h = blockDim.x >> 1; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + h]);
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// Importance draws for column w = blockIdx.x: q = (1 - eps) softmax(z[w]) + eps / nf
+// (uniform when z is null), cdf = running sum of q in fibre order, draw s lands on the
+// first fibre whose cdf exceeds u[w][s] (the last fibre if none), and adds 1 / (p q_f)
+// to that fibre's weight.  All draws of a fibre add the same value, so the sum does not
+// depend on their order.  Dynamic LDS: 3 * nf doubles.  256 threads.
+__global__ __launch_bounds__(256) void k_sample_weights(int nf, int W, int p, int ustride, const double* u,
+                                                        const float* z, double eps, double* wt) {
+  extern __shared__ double sm[];
+  double* q = sm;
+  double* cdf = sm + nf;
+  double* acc = sm + 2 * nf;
+  __shared__ double red[256];
+  const int w = blockIdx.x;
+  if (z) {
+    const float* zw = z + (int64_t)w * nf;
+    double mx = -INFINITY;
+    for (int f = threadIdx.x; f < nf; f += blockDim.x) mx = fmax(mx, (double)zw[f]);
+    mx = block_max(mx, red);
+    double s = 0.0;
+    for (int f = threadIdx.x; f < nf; f += blockDim.x) {
+      const double e = exp((double)zw[f] - mx);
+      q[f] = e;
+      s += e;
+    }
+    s = block_sum(s, red);
+    for (int f = threadIdx.x; f < nf; f += blockDim.x) q[f] = (1.0 - eps) * q[f] / s + eps / nf;
+  } else {
+    for (int f = threadIdx.x; f < nf; f += blockDim.x) q[f] = 1.0 / nf;
+  }
+  for (int f = threadIdx.x; f < nf; f += blockDim.x) acc[f] = 0.0;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double c = 0.0;
+    for (int f = 0; f < nf; ++f) {
+      c += q[f];
+      cdf[f] = c;
+    }
+  }
+  __syncthreads();
+  const double* uw = u + (int64_t)w * ustride;
+  for (int s = threadIdx.x; s < p; s += blockDim.x) {
+    const double us = uw[s];
+    int lo = 0, hi = nf;  // first f with cdf[f] > us
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (cdf[mid] > us)
+        hi = mid;
+      else
+        lo = mid + 1;
+    }
+    const int f = lo < nf ? lo : nf - 1;
+    atomicAdd(&acc[f], 1.0 / ((double)p * q[f]));
+  }
+  __syncthreads();
+  for (int f = threadIdx.x; f < nf; f += blockDim.x) wt[(int64_t)f * W + w] = acc[f];
+}
+
+// flag[f] = 1 if any column gives fibre f a nonzero weight
+__global__ __launch_bounds__(256) void k_union_flags(int nf, int W, const double* wt, int32_t* flag) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nf) return;
+  int any = 0;
+  for (int w = 0; w < W; ++w) any |= (wt[(int64_t)f * W + w] != 0.0);
+  flag[f] = any;
+}
+
+// Compaction of the flagged fibres' tiles (tiles listed fibre-major, fibre f owning
+// tiles tptr[f]..tptr[f+1]) into out, in fibre order; *count = number of tiles kept.
+// One workgroup of 1024 threads; thread t scans fibres [t*chunk, (t+1)*chunk).
+__global__ __launch_bounds__(1024) void k_compact_tiles(int nf, const int32_t* flag, const int32_t* tptr,
+                                                        const TileDesc* tiles, TileDesc* out, int32_t* count) {
+  __shared__ int32_t scan[1024];
+  const int t = threadIdx.x;
+  const int chunk = (nf + 1023) / 1024;
+  const int f0 = min(nf, t * chunk), f1 = min(nf, f0 + chunk);
+  int mine = 0;
+  for (int f = f0; f < f1; ++f)
+    if (flag[f]) mine += tptr[f + 1] - tptr[f];
+  scan[t] = mine;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {  // inclusive Hillis-Steele scan
+    const int v = t >= off ? scan[t - off] : 0;
+    __syncthreads();
+    scan[t] += v;
+    __syncthreads();
+  }
+  int pos = scan[t] - mine;
+  for (int f = f0; f < f1; ++f)
+    if (flag[f])
+      for (int k = tptr[f]; k < tptr[f + 1]; ++k) out[pos++] = tiles[k];
+  if (t == 1023) *count = scan[1023];
+}
+
+// Copies the rows x columns block of every listed tile from src to dst (positions through
+// pos when set); tiles at or past *count are skipped.  256 threads per tile.
+__global__ __launch_bounds__(256) void k_copy_tiles(const TileDesc* tiles, const int32_t* count, int ncols,
+                                                    const int32_t* pos, int W, const double2* src, double2* dst) {
+  if ((int)blockIdx.x >= *count) return;
+  const TileDesc t = tiles[blockIdx.x];
+  const int rows = min(16, t.L - 16 * t.rb);
+  const int c0 = t.wb * ncols;
+  const int cols = min(ncols, W - c0);
+  for (int e = threadIdx.x; e < rows * ncols; e += blockDim.x) {
+    const int r = e / ncols, c = e - r * ncols;
+    if (c >= cols) continue;
+    const int p = t.r0 + 16 * t.rb + r;
+    const int64_t row = pos ? pos[p] : p;
+    dst[row * W + c0 + c] = src[row * W + c0 + c];
+  }
+}
+
+// ---------------------------------------------------------------- training data
+// b[w][f] = sum over the fibre's rows of |Y - X|^2 (one workgroup per fibre)
+__global__ __launch_bounds__(256) void k_fibre_incr(const int32_t* ptr, const int32_t* rows, int nf, int W,
+                                                    const double2* X, const double2* Y, double* out) {
+  __shared__ double red[256];
+  const int f = blockIdx.x;
+  const int r0 = ptr[f], L = ptr[f + 1] - r0;
+  const int WB = W < 256 ? W : 256;
+  const int S = 256 / WB;
+  const int tid = threadIdx.x;
+  for (int w0 = 0; w0 < W; w0 += WB) {
+    const int w = w0 + tid % WB, s = tid / WB;
+    double acc = 0.0;
+    if (w < W && s < S)
+      for (int a = s; a < L; a += S) {
+        const int64_t e = (int64_t)rows[r0 + a] * W + w;
+        const double dr = Y[e].x - X[e].x, di = Y[e].y - X[e].y;
+        acc += dr * dr + di * di;
+      }
+    red[tid] = acc;
+    __syncthreads();
+    if (tid < WB && w0 + tid < W) {
+      double sum = 0.0;
+      for (int j = 0; j < S; ++j) sum += red[j * WB + tid];
+      out[(int64_t)(w0 + tid) * nf + f] = sum;
+    }
+    __syncthreads();
+  }
+}
+
+// X[w][f][:] = (shift / Kmax (d), |shift / Kmax|^2, log10(max(mass, 1e-30)) / 10, layer sign)
+// from sfeat[f] = (shift / Kmax, |shift / Kmax|^2) and mass [nf][W].
+__global__ __launch_bounds__(256) void k_features(int nf, int W, int d, const double* sfeat, const double* mass,
+                                                  float sign, float* X) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)nf * W) return;
+  const int w = (int)(e / nf), f = (int)(e - (int64_t)w * nf);
+  const int nin = d + 3;
+  float* x = X + e * nin;
+  for (int k = 0; k <= d; ++k) x[k] = (float)sfeat[f * (d + 1) + k];
+  x[d + 1] = (float)(log10(fmax(mass[(int64_t)f * W + w], 1e-30)) / 10.0);
+  x[d + 2] = sign;
+}
+
+// ---------------------------------------------------------------- proposal network
+// Flat FP32 parameters: W1 [nin][64], b1 [64], W2 [64][64], b2 [64], w3 [64], b3.
+// z = w3 . tanh(W2^T tanh(W1^T x + b1) + b2) + b3.  Rows are processed in blocks of 32
+// by 256 threads: thread (r = tid / 8, q = tid % 8) owns row r and hidden units
+// 8q..8q+7 of both layers; activations are exchanged through LDS (row stride 65).
+constexpr int MLP_H = 64;
+constexpr int MLP_NIN_MAX = 8;
+constexpr int MLP_LD = 65;
+constexpr int MLP_ROWS = 32;
+constexpr int MLP_UPT = 8;  // hidden units per thread
+
+struct MlpOff {
+  int W1, b1, W2, b2, w3, b3, n;
+  __host__ __device__ explicit MlpOff(int nin) {
+    W1 = 0;
+    b1 = nin * MLP_H;
+    W2 = b1 + MLP_H;
+    b2 = W2 + MLP_H * MLP_H;
+    w3 = b2 + MLP_H;
+    b3 = w3 + MLP_H;
+    n = b3 + 1;
+  }
+};
+
+int mlp_nparams(int nin) { return MlpOff(nin).n; }
+
+__device__ __forceinline__ void mlp_stage(const float* theta, int n, float* sp) {
+  for (int k = threadIdx.x; k < n; k += blockDim.x) sp[k] = theta[k];
+}
+
+// first layer for row r, units 8q..: H1[r][j] = tanh(b1 + x . W1[:, j])
+__device__ __forceinline__ void mlp_layer1(const float* sp, const MlpOff& o, int nin, const float (&x)[MLP_NIN_MAX],
+                                           int r, int q, float* H1) {
+#pragma unroll
+  for (int jj = 0; jj < MLP_UPT; ++jj) {
+    const int j = MLP_UPT * q + jj;
+    float a = sp[o.b1 + j];
+    for (int i = 0; i < nin; ++i) a += x[i] * sp[o.W1 + i * MLP_H + j];
+    H1[r * MLP_LD + j] = tanhf(a);
+  }
+}
+
+// second layer for row r, units 8q..: h2[k] = tanh(b2 + sum_j H1[r][j] W2[j][k])
+__device__ __forceinline__ void mlp_layer2(const float* sp, const MlpOff& o, int r, int q, const float* H1,
+                                           float (&h2)[MLP_UPT]) {
+#pragma unroll
+  for (int kk = 0; kk < MLP_UPT; ++kk) h2[kk] = sp[o.b2 + MLP_UPT * q + kk];
+#pragma unroll 4
+  for (int j = 0; j < MLP_H; ++j) {
+    const float hj = H1[r * MLP_LD + j];
+    const float* w2 = sp + o.W2 + j * MLP_H + MLP_UPT * q;
+#pragma unroll
+    for (int kk = 0; kk < MLP_UPT; ++kk) h2[kk] += hj * w2[kk];
+  }
+#pragma unroll
+  for (int kk = 0; kk < MLP_UPT; ++kk) h2[kk] = tanhf(h2[kk]);
+}
+
+__device__ __forceinline__ void mlp_load_row(const float* X, int64_t M, int nin, int64_t m, float (&x)[MLP_NIN_MAX]) {
+#pragma unroll
+  for (int i = 0; i < MLP_NIN_MAX; ++i) x[i] = (m < M && i < nin) ? X[m * nin + i] : 0.f;
+}
+
+__global__ __launch_bounds__(256) void k_mlp_fwd(const float* theta, int nin, const float* X, int64_t M, float* z) {
+  extern __shared__ float sp[];
+  const MlpOff o(nin);
+  float* H1 = sp + ((o.n + 3) & ~3);
+  mlp_stage(theta, o.n, sp);
+  __syncthreads();
+  const int r = threadIdx.x >> 3, q = threadIdx.x & 7;
+  const int64_t nblk = (M + MLP_ROWS - 1) / MLP_ROWS;
+  for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+    const int64_t m = blk * MLP_ROWS + r;
+    float x[MLP_NIN_MAX];
+    mlp_load_row(X, M, nin, m, x);
+    mlp_layer1(sp, o, nin, x, r, q, H1);
+    __syncthreads();
+    float h2[MLP_UPT];
+    mlp_layer2(sp, o, r, q, H1, h2);
+    float zp = 0.f;
+#pragma unroll
+    for (int kk = 0; kk < MLP_UPT; ++kk) zp += h2[kk] * sp[o.w3 + MLP_UPT * q + kk];
+    zp += __shfl_xor(zp, 1);
+    zp += __shfl_xor(zp, 2);
+    zp += __shfl_xor(zp, 4);
+    if (q == 0 && m < M) z[m] = zp + sp[o.b3];
+    __syncthreads();
+  }
+}
+
+// Backward of sum_m g_m z_m, g_m = dz[m] * (*gscale when set).  Per row block: delta2 =
+// g w3 (1 - h2^2), delta1 = (W2 delta2)(1 - h1^2); thread (j = tid/4, part) accumulates
+// dW2[j][16 part..] = sum_r H1[r][j] D2[r][k], the row-owning threads accumulate the bias
+// and w3 terms, and the workgroup's partial gradient is written to partial[blockIdx.x][:].
+__global__ __launch_bounds__(256) void k_mlp_bwd(const float* theta, int nin, const float* X, int64_t M,
+                                                 const float* dz, const double* gscale, float* partial) {
+  extern __shared__ float sp[];
+  const MlpOff o(nin);
+  float* H1 = sp + ((o.n + 3) & ~3);
+  float* D2 = H1 + MLP_ROWS * MLP_LD;
+  float* D1 = D2 + MLP_ROWS * MLP_LD;
+  float* XS = D1 + MLP_ROWS * MLP_LD;  // [MLP_ROWS][MLP_NIN_MAX]
+  float* G = XS + MLP_ROWS * MLP_NIN_MAX;
+  mlp_stage(theta, o.n, sp);
+  __syncthreads();
+  const int tid = threadIdx.x;
+  const int r = tid >> 3, q = tid & 7;
+  const float gs = gscale ? (float)*gscale : 1.f;
+  float accW2[16], accw3[MLP_UPT], accb2[MLP_UPT], accb1[MLP_UPT], accW1[2], accb3 = 0.f;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) accW2[k] = 0.f;
+#pragma unroll
+  for (int k = 0; k < MLP_UPT; ++k) accw3[k] = accb2[k] = accb1[k] = 0.f;
+  accW1[0] = accW1[1] = 0.f;
+  const int64_t nblk = (M + MLP_ROWS - 1) / MLP_ROWS;
+  for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+    const int64_t m = blk * MLP_ROWS + r;
+    float x[MLP_NIN_MAX];
+    mlp_load_row(X, M, nin, m, x);
+    const float g = (m < M) ? dz[m] * gs : 0.f;
+    if (q == 0) {
+#pragma unroll
+      for (int i = 0; i < MLP_NIN_MAX; ++i) XS[r * MLP_NIN_MAX + i] = x[i];
+      accb3 += g;
+    }
+    mlp_layer1(sp, o, nin, x, r, q, H1);
+    __syncthreads();
+    float h2[MLP_UPT];
+    mlp_layer2(sp, o, r, q, H1, h2);
+#pragma unroll
+    for (int kk = 0; kk < MLP_UPT; ++kk) {
+      const int k = MLP_UPT * q + kk;
+      const float d2 = g * sp[o.w3 + k] * (1.f - h2[kk] * h2[kk]);
+      D2[r * MLP_LD + k] = d2;
+      accw3[kk] += g * h2[kk];
+      accb2[kk] += d2;
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int jj = 0; jj < MLP_UPT; ++jj) {
+      const int j = MLP_UPT * q + jj;
+      float s = 0.f;
+      const float* w2 = sp + o.W2 + j * MLP_H;
+#pragma unroll 4
+      for (int k = 0; k < MLP_H; ++k) s += w2[k] * D2[r * MLP_LD + k];
+      const float h = H1[r * MLP_LD + j];
+      const float d1 = s * (1.f - h * h);
+      D1[r * MLP_LD + j] = d1;
+      accb1[jj] += d1;
+    }
+    __syncthreads();
+    {  // outer products over the rows of the block
+      const int j = tid >> 2, k0 = 16 * (tid & 3);
+#pragma unroll 2
+      for (int rr = 0; rr < MLP_ROWS; ++rr) {
+        const float h = H1[rr * MLP_LD + j];
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) accW2[kk] += h * D2[rr * MLP_LD + k0 + kk];
+      }
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int e = tid + 256 * u;
+        if (e < nin * MLP_H) {
+          const int i = e / MLP_H, jj = e % MLP_H;
+          float s = 0.f;
+#pragma unroll 4
+          for (int rr = 0; rr < MLP_ROWS; ++rr) s += XS[rr * MLP_NIN_MAX + i] * D1[rr * MLP_LD + jj];
+          accW1[u] += s;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  float* out = partial + (int64_t)blockIdx.x * o.n;
+  {
+    const int j = tid >> 2, k0 = 16 * (tid & 3);
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) out[o.W2 + j * MLP_H + k0 + kk] = accW2[kk];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int e = tid + 256 * u;
+      if (e < nin * MLP_H) out[o.W1 + e] = accW1[u];
+    }
+  }
+  // row-owned sums: reduce over the block's rows (fixed order) through LDS
+#pragma unroll
+  for (int kk = 0; kk < MLP_UPT; ++kk) {
+    H1[r * MLP_LD + MLP_UPT * q + kk] = accb1[kk];
+    D2[r * MLP_LD + MLP_UPT * q + kk] = accb2[kk];
+    D1[r * MLP_LD + MLP_UPT * q + kk] = accw3[kk];
+  }
+  if (q == 0) G[r] = accb3;
+  __syncthreads();
+  if (tid < 3 * MLP_H) {
+    const int which = tid / MLP_H, k = tid % MLP_H;
+    const float* buf = which == 0 ? H1 : (which == 1 ? D2 : D1);
+    float s = 0.f;
+    for (int rr = 0; rr < MLP_ROWS; ++rr) s += buf[rr * MLP_LD + k];
+    out[(which == 0 ? o.b1 : (which == 1 ? o.b2 : o.w3)) + k] = s;
+  } else if (tid == 3 * MLP_H) {
+    float s = 0.f;
+    for (int rr = 0; rr < MLP_ROWS; ++rr) s += G[rr];
+    out[o.b3] = s;
+  }
+}
+
+// grad[e] = sum over workgroups of partial[b][e] (FP64, fixed order)
+__global__ __launch_bounds__(256) void k_mlp_reduce(int nparts, int n, const float* partial, float* grad) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  double s = 0.0;
+  for (int b = 0; b < nparts; ++b) s += partial[(int64_t)b * n + e];
+  grad[e] = (float)s;
+}
+
+// Variance objective per group g (rows gptr[g]..gptr[g+1]), one workgroup per group:
+// q = (1 - eps) softmax(z) + eps / n, l_g = sum b/q / (sum sqrt b)^2 and the unscaled
+// gradient (1 - eps)/S sigma_f (sum_h r_h sigma_h - r_f), r = b / q^2; groups with
+// sum b = 0 get l_g = 0, active = 0 and zero gradient.
+__global__ __launch_bounds__(256) void k_loss_groups(const float* z, const double* b, const int64_t* gptr,
+                                                     int64_t G, double eps, double* lg, int32_t* active,
+                                                     float* dz) {
+  __shared__ double red[256];
+  for (int64_t g = blockIdx.x; g < G; g += gridDim.x) {
+    const int64_t r0 = gptr[g], r1 = gptr[g + 1];
+    const double n = (double)(r1 - r0);
+    double mx = -INFINITY, sb = 0.0, ss = 0.0;
+    for (int64_t k = r0 + threadIdx.x; k < r1; k += blockDim.x) {
+      mx = fmax(mx, (double)z[k]);
+      sb += b[k];
+      ss += sqrt(b[k]);
+    }
+    mx = block_max(mx, red);
+    sb = block_sum(sb, red);
+    ss = block_sum(ss, red);
+    if (!(sb > 0.0)) {
+      for (int64_t k = r0 + threadIdx.x; k < r1; k += blockDim.x) dz[k] = 0.f;
+      if (threadIdx.x == 0) {
+        lg[g] = 0.0;
+        active[g] = 0;
+      }
+      continue;
+    }
+    double se = 0.0;
+    for (int64_t k = r0 + threadIdx.x; k < r1; k += blockDim.x) se += exp((double)z[k] - mx);
+    se = block_sum(se, red);
+    double sl = 0.0, srs = 0.0;
+    for (int64_t k = r0 + threadIdx.x; k < r1; k += blockDim.x) {
+      const double sig = exp((double)z[k] - mx) / se;
+      const double qf = (1.0 - eps) * sig + eps / n;
+      sl += b[k] / qf;
+      srs += b[k] / (qf * qf) * sig;
+    }
+    sl = block_sum(sl, red);
+    srs = block_sum(srs, red);
+    const double S = ss * ss;
+    for (int64_t k = r0 + threadIdx.x; k < r1; k += blockDim.x) {
+      const double sig = exp((double)z[k] - mx) / se;
+      const double qf = (1.0 - eps) * sig + eps / n;
+      const double rf = b[k] / (qf * qf);
+      dz[k] = (float)((1.0 - eps) / S * sig * (srs - rf));
+    }
+    if (threadIdx.x == 0) {
+      lg[g] = sl / S;
+      active[g] = 1;
+    }
+  }
+}
+
+// out[0] = mean of l_g over active groups, out[1] = 1 / (number of active groups) (0 if none)
+__global__ __launch_bounds__(256) void k_loss_final(int64_t G, const double* lg, const int32_t* active,
+                                                    double* out) {
+  __shared__ double red[256];
+  double s = 0.0, a = 0.0;
+  for (int64_t g = threadIdx.x; g < G; g += blockDim.x) {
+    s += lg[g];
+    a += active[g];
+  }
+  s = block_sum(s, red);
+  a = block_sum(a, red);
+  if (threadIdx.x == 0) {
+    out[0] = a > 0.0 ? s / a : 0.0;
+    out[1] = a > 0.0 ? 1.0 / a : 0.0;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_scale_f32(int64_t n, const double* scale, float* x) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) x[e] = (float)((double)x[e] * *scale);
+}
+
+// Adam (Kingma & Ba): m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+// theta -= lr (m c1) / (sqrt(v c2) + eps) with c1 = 1/(1-b1^t), c2 = 1/(1-b2^t).
+__global__ __launch_bounds__(256) void k_adam(int n, float* theta, float* m, float* v, const float* grad,
+                                              double lr, double b1, double b2, double eps, double c1, double c2) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const double g = grad[e];
+  const double mm = b1 * m[e] + (1.0 - b1) * g;
+  const double vv = b2 * v[e] + (1.0 - b2) * g * g;
+  m[e] = (float)mm;
+  v[e] = (float)vv;
+  theta[e] = (float)((double)theta[e] - lr * (mm * c1) / (sqrt(vv * c2) + eps));
+}
+
+// ================================================================ launchers
+static unsigned grid_for(int64_t n, int64_t cap) {
+  const int64_t g = (n + 255) / 256;
+  return (unsigned)(g < 1 ? 1 : (g > cap ? cap : g));
+}
+
+hipError_t launch_si_step(hipStream_t s, int64_t N, int W, double tau, const double* K2, int nv1,
+                          const int32_t* nbr1, const double2* v1, const double* wt1, const int32_t* fid1, int nv2,
+                          const int32_t* nbr2, const double2* v2, const double* wt2, const int32_t* fid2,
+                          const double2* X, double2* Y) {
+  if (N == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_si_step, dim3(grid_for(N * (int64_t)W, 256 * 64)), dim3(256), 0, s, N, W, tau, K2, nv1,
+                     nbr1, v1, wt1, fid1, nv2, nbr2, v2, wt2, fid2, X, Y);
+  return hipGetLastError();
+}
+
+hipError_t launch_subset_weights(hipStream_t s, int nf, int W, int p, int ustride, const double* u, double* wt) {
+  hipLaunchKernelGGL(k_subset_weights, dim3(W), dim3(256), (size_t)nf * sizeof(int32_t), s, nf, W, p, ustride, u,
+                     wt);
+  return hipGetLastError();
+}
+
+hipError_t launch_sample_weights(hipStream_t s, int nf, int W, int p, int ustride, const double* u, const float* z,
+                                 double eps, double* wt) {
+  hipLaunchKernelGGL(k_sample_weights, dim3(W), dim3(256), (size_t)3 * nf * sizeof(double), s, nf, W, p, ustride,
+                     u, z, eps, wt);
+  return hipGetLastError();
+}
+
+hipError_t launch_compact(hipStream_t s, int nf, int W, const double* wt, int32_t* flag, const int32_t* tptr,
+                          const TileDesc* tiles, TileDesc* out, int32_t* count) {
+  hipLaunchKernelGGL(k_union_flags, dim3((nf + 255) / 256), dim3(256), 0, s, nf, W, wt, flag);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_compact_tiles, dim3(1), dim3(1024), 0, s, nf, flag, tptr, tiles, out, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_tiles(hipStream_t s, int ntiles, const TileDesc* tiles, const int32_t* count, int ncols,
+                             const int32_t* pos, int W, const double2* src, double2* dst) {
+  if (ntiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_tiles, dim3(ntiles), dim3(256), 0, s, tiles, count, ncols, pos, W, src, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_fibre_incr(hipStream_t s, int nf, const int32_t* ptr, const int32_t* rows, int W,
+                             const double2* X, const double2* Y, double* out) {
+  if (nf == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fibre_incr, dim3(nf), dim3(256), 0, s, ptr, rows, nf, W, X, Y, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_features(hipStream_t s, int nf, int W, int d, const double* sfeat, const double* mass,
+                           float sign, float* X) {
+  const int64_t n = (int64_t)nf * W;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_features, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, nf, W, d, sfeat, mass, sign,
+                     X);
+  return hipGetLastError();
+}
+
+static size_t mlp_lds_fwd(int nin) {
+  return (size_t)(((MlpOff(nin).n + 3) & ~3) + MLP_ROWS * MLP_LD) * sizeof(float);
+}
+static size_t mlp_lds_bwd(int nin) {
+  return (size_t)(((MlpOff(nin).n + 3) & ~3) + 3 * MLP_ROWS * MLP_LD + MLP_ROWS * MLP_NIN_MAX + MLP_ROWS) *
+         sizeof(float);
+}
+
+int mlp_bwd_blocks(int64_t M) {
+  const int64_t nblk = (M + MLP_ROWS - 1) / MLP_ROWS;
+  return (int)(nblk < 1 ? 1 : (nblk > 512 ? 512 : nblk));
+}
+
+hipError_t launch_mlp_fwd(hipStream_t s, const float* theta, int nin, const float* X, int64_t M, float* z) {
+  if (M == 0) return hipSuccess;
+  const int64_t nblk = (M + MLP_ROWS - 1) / MLP_ROWS;
+  const unsigned grid = (unsigned)(nblk > 2048 ? 2048 : nblk);
+  hipLaunchKernelGGL(k_mlp_fwd, dim3(grid), dim3(256), mlp_lds_fwd(nin), s, theta, nin, X, M, z);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_bwd(hipStream_t s, const float* theta, int nin, const float* X, int64_t M, const float* dz,
+                          const double* gscale, float* partial, float* grad) {
+  const int nparts = mlp_bwd_blocks(M);
+  const int n = MlpOff(nin).n;
+  hipLaunchKernelGGL(k_mlp_bwd, dim3(nparts), dim3(256), mlp_lds_bwd(nin), s, theta, nin, X, M, dz, gscale, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_mlp_reduce, dim3((n + 255) / 256), dim3(256), 0, s, nparts, n, partial, grad);
+  return hipGetLastError();
+}
+
+hipError_t launch_loss(hipStream_t s, const float* z, const double* b, const int64_t* gptr, int64_t G, double eps,
+                       double* lg, int32_t* active, float* dz, double* out) {
+  if (G == 0) return hipSuccess;
+  const unsigned grid = (unsigned)(G > 65536 ? 65536 : G);
+  hipLaunchKernelGGL(k_loss_groups, dim3(grid), dim3(256), 0, s, z, b, gptr, G, eps, lg, active, dz);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, s, G, lg, active, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_f32(hipStream_t s, int64_t n, const double* scale, float* x) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scale_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, scale, x);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(hipStream_t s, int n, float* theta, float* m, float* v, const float* grad, double lr,
+                       double b1, double b2, double eps, double c1, double c2) {
+  hipLaunchKernelGGL(k_adam, dim3((n + 255) / 256), dim3(256), 0, s, n, theta, m, v, grad, lr, b1, b2, eps, c1, c2);
+  return hipGetLastError();
+}
+
+}  // namespace lsx

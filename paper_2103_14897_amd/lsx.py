@@ -58,6 +58,26 @@ _SIGS = {
     "lsx_batch_step": (C.c_int, [_p, C.c_int64, _p]),
     "lsx_batch_tuning": (C.c_int, [_p, C.c_int32, _i32p, _i32p, _dp]),
     "lsx_batch_destroy": (C.c_int, [_p]),
+    "lsx_si_step": (C.c_int, [_p, _p, C.c_int64, _p]),
+    "lsx_sampler_create": (C.c_int, [_p, _p, C.c_int32, C.c_int32, C.c_double, C.POINTER(_p)]),
+    "lsx_sampler_set_mlp": (C.c_int, [_p, _p]),
+    "lsx_sampler_destroy": (C.c_int, [_p]),
+    "lsx_rb_step": (C.c_int, [_p, _p, C.c_int64, _p]),
+    "lsx_ss_step": (C.c_int, [_p, _p, C.c_int64, _p]),
+    "lsx_sampler_weights": (C.c_int, [_p, C.c_int32, C.c_int32, _p, _p, _p, _p]),
+    "lsx_sampler_features": (C.c_int, [_p, C.c_int32, _p, _p]),
+    "lsx_sampler_increments": (C.c_int, [_p, C.c_int32, C.c_int32, _p, _p]),
+    "lsx_mlp_create": (C.c_int, [C.c_int32, C.POINTER(_p)]),
+    "lsx_mlp_nparams": (C.c_int, [_p, _i64p]),
+    "lsx_mlp_set": (C.c_int, [_p, C.POINTER(C.c_float), _p]),
+    "lsx_mlp_get": (C.c_int, [_p, C.POINTER(C.c_float), _p]),
+    "lsx_mlp_forward": (C.c_int, [_p, _p, C.c_int64, _p, _p]),
+    "lsx_mlp_backward": (C.c_int, [_p, _p, C.c_int64, _p, _p, _p]),
+    "lsx_mlp_loss": (C.c_int, [_p, _p, _p, _p, C.c_int64, C.c_double, _p, _p, _p]),
+    "lsx_mlp_adam": (C.c_int, [_p, _p, C.c_double, C.c_double, C.c_double, C.c_double, _p]),
+    "lsx_mlp_train_step": (C.c_int, [_p, _p, C.c_int64, _p, _p, C.c_int64, C.c_double, C.c_double, C.c_double,
+                                     C.c_double, C.c_double, _p, _p]),
+    "lsx_mlp_destroy": (C.c_int, [_p]),
 }
 
 
@@ -104,6 +124,15 @@ def _stream(s):
 
 def _dptr(a):
     return a.ctypes.data_as(_dp)
+
+
+def _dev(x):
+    """Device pointer argument: a torch tensor (its data_ptr), an int address, or None."""
+    if x is None:
+        return None
+    if hasattr(x, "data_ptr"):
+        return _p(x.data_ptr())
+    return _p(int(x))
 
 
 class System:
@@ -226,6 +255,10 @@ class State:
                 o += n
         return res
 
+    def si_step(self, nsteps, stream=None):
+        """Semi-implicit steps (Alg. 1) with the plan's tau."""
+        _check(lib().lsx_si_step(self.plan.h, self.h, int(nsteps), _stream(stream)))
+
     def tuning(self, layer):
         """(nb, ks, pass_us) of the tile shape chosen for `layer`'s fibre passes."""
         nb, ks, us = C.c_int32(), C.c_int32(), C.c_double()
@@ -261,4 +294,89 @@ class Batch:
     def destroy(self):
         if self.h:
             _check(lib().lsx_batch_destroy(self.h))
+            self.h = None
+
+
+class Mlp:
+    """lsx_mlp: the width-64 tanh proposal network (FP32 parameters on the device).
+
+    Array arguments are device pointers (torch tensors or int addresses)."""
+
+    def __init__(self, nin):
+        h = _p()
+        _check(lib().lsx_mlp_create(int(nin), C.byref(h)))
+        self.h, self.nin = h, int(nin)
+        n = C.c_int64()
+        _check(lib().lsx_mlp_nparams(self.h, C.byref(n)))
+        self.nparams = n.value
+
+    def set(self, theta, stream=None):
+        t = np.ascontiguousarray(np.asarray(theta, dtype=np.float32).reshape(self.nparams))
+        _check(lib().lsx_mlp_set(self.h, t.ctypes.data_as(C.POINTER(C.c_float)), _stream(stream)))
+
+    def get(self, stream=None):
+        t = np.zeros(self.nparams, dtype=np.float32)
+        _check(lib().lsx_mlp_get(self.h, t.ctypes.data_as(C.POINTER(C.c_float)), _stream(stream)))
+        return t
+
+    def forward(self, X, M, z, stream=None):
+        _check(lib().lsx_mlp_forward(self.h, _dev(X), int(M), _dev(z), _stream(stream)))
+
+    def backward(self, X, M, dz, grad, stream=None):
+        _check(lib().lsx_mlp_backward(self.h, _dev(X), int(M), _dev(dz), _dev(grad), _stream(stream)))
+
+    def loss(self, z, b, gptr, ngroups, eps, out, dz, stream=None):
+        _check(lib().lsx_mlp_loss(self.h, _dev(z), _dev(b), _dev(gptr), int(ngroups), float(eps), _dev(out),
+                                  _dev(dz), _stream(stream)))
+
+    def adam(self, grad, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        _check(lib().lsx_mlp_adam(self.h, _dev(grad), float(lr), float(beta1), float(beta2), float(eps),
+                                  _stream(stream)))
+
+    def train_step(self, X, M, b, gptr, ngroups, eps, lr, out, beta1=0.9, beta2=0.999, adam_eps=1e-8,
+                   stream=None):
+        _check(lib().lsx_mlp_train_step(self.h, _dev(X), int(M), _dev(b), _dev(gptr), int(ngroups), float(eps),
+                                        float(lr), float(beta1), float(beta2), float(adam_eps), _dev(out),
+                                        _stream(stream)))
+
+    def destroy(self):
+        if self.h:
+            _check(lib().lsx_mlp_destroy(self.h))
+            self.h = None
+
+
+class Sampler:
+    """lsx_sampler: semi-implicit / random batch / stochastic splitting steps of one state.
+
+    Array arguments are device pointers (torch tensors or int addresses)."""
+
+    def __init__(self, state, p1, p2, eps=0.05):
+        h = _p()
+        _check(lib().lsx_sampler_create(state.plan.h, state.h, int(p1), int(p2), float(eps), C.byref(h)))
+        self.h, self.state, self.p, self.eps = h, state, (int(p1), int(p2)), float(eps)
+        self.mlp = None
+
+    def set_mlp(self, mlp):
+        _check(lib().lsx_sampler_set_mlp(self.h, mlp.h if mlp is not None else None))
+        self.mlp = mlp
+
+    def rb_step(self, u, nsteps, stream=None):
+        _check(lib().lsx_rb_step(self.h, _dev(u), int(nsteps), _stream(stream)))
+
+    def ss_step(self, u, nsteps, stream=None):
+        _check(lib().lsx_ss_step(self.h, _dev(u), int(nsteps), _stream(stream)))
+
+    def weights(self, layer, mode, z, u, wt, stream=None):
+        _check(lib().lsx_sampler_weights(self.h, int(layer), int(mode), _dev(z), _dev(u), _dev(wt),
+                                         _stream(stream)))
+
+    def features(self, layer, X, stream=None):
+        _check(lib().lsx_sampler_features(self.h, int(layer), _dev(X), _stream(stream)))
+
+    def increments(self, layer, half, b, stream=None):
+        _check(lib().lsx_sampler_increments(self.h, int(layer), int(half), _dev(b), _stream(stream)))
+
+    def destroy(self):
+        if self.h:
+            _check(lib().lsx_sampler_destroy(self.h))
             self.h = None

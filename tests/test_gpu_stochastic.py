@@ -1,0 +1,450 @@
+"""GPU parity of the semi-implicit (Alg. 1), random batch (Alg. 4) and stochastic layer-splitting
+steps, the fibre sampling, the proposal network's forward / backward / objective / Adam kernels,
+and a test of what the trained proposal gains over uniform sampling.
+
+Tolerances: FP64 state paths compare per column in relative L2 (1e-12 per step, summation order
+only); sampling decisions compare exactly (both sides decide in FP64 from the same inputs); the
+FP32 network compares with the FP64 oracle within FP32 rounding of 64-term sums (1e-5 relative
+for logits, 1e-4 for gradients summed over all rows).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import splitting  # noqa: E402
+from oracle import stochastic as sto  # noqa: E402
+from paper_2103_14897_amd import lsx  # noqa: E402
+from paper_2103_14897_amd import workloads as wl  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def colrel(a, b):
+    return (np.linalg.norm(a - b, axis=0) / np.linalg.norm(b, axis=0)).max()
+
+
+def dev(a, dtype=None):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).to(DEV)
+
+
+@pytest.fixture(scope="module")
+def chain_sys():
+    spec = wl.chain_system(2.0e4)
+    S = lsx.System.from_spec(spec)
+    O = splitting.Lifted.from_spec(spec)
+    assert np.array_equal(S.index(), O.mn)
+    yield spec, S, O
+    S.destroy()
+
+
+@pytest.fixture(scope="module")
+def twisted_sys():
+    spec = wl.twisted_system(1500.0)
+    S = lsx.System.from_spec(spec)
+    O = splitting.Lifted.from_spec(spec)
+    assert np.array_equal(S.index(), O.mn)
+    yield spec, S, O
+    S.destroy()
+
+
+def _pair(S, tau, scheme, kappa, precision, W):
+    P = lsx.Plan(S, tau, scheme, kappa, precision)
+    st = lsx.State(P, W)
+    return P, st
+
+
+# ---------------------------------------------------------------- Alg. 1 / Alg. 4
+
+@pytest.mark.parametrize("which", ["chain", "twisted"])
+def test_semi_implicit_matches_oracle(which, chain_sys, twisted_sys):
+    spec, S, O = chain_sys if which == "chain" else twisted_sys
+    print(f"[case] semi-implicit {which} N={S.N}", flush=True)
+    tau = 1e-3 if which == "chain" else 5e-3
+    P, st = _pair(S, tau, "strang", 0.0, "fp64", 5)
+    try:
+        c = wl.random_state(S.N, 5, seed=2)
+        st.upload(c)
+        st.si_step(3)
+        ref = c
+        for _ in range(3):
+            ref = sto.semi_implicit_step(O, ref, tau)
+        assert colrel(st.download(), ref) < 3e-12
+    finally:
+        st.destroy()
+        P.destroy()
+
+
+def test_subset_and_importance_weights_exact(chain_sys):
+    spec, S, O = chain_sys
+    W = 6
+    P, st = _pair(S, 1e-3, "strang", 0.0, "fp64", W)
+    sm = lsx.Sampler(st, 7, 5, eps=0.1)
+    try:
+        for layer, p in ((1, 7), (2, 5)):
+            nf = S.nfibres[layer]
+            u = wl.uniforms((W, p), seed=10 + layer)
+            wt = torch.zeros((nf, W), dtype=torch.float64, device=DEV)
+            sm.weights(layer, 1, None, dev(u), wt)
+            assert np.array_equal(wt.cpu().numpy(), sto.subset_weights(nf, p, u))
+            z = np.random.default_rng(layer).standard_normal((W, nf)).astype(np.float32)
+            for zz in (None, z):
+                sm.weights(layer, 0, None if zz is None else dev(zz), dev(u), wt)
+                ref = sto.draw_weights(sto.proposal(None if zz is None else zz.astype(np.float64), nf, W, 0.1), u)
+                got = wt.cpu().numpy()
+                assert np.array_equal(got != 0, ref != 0)
+                assert np.allclose(got, ref, rtol=1e-13, atol=0)
+    finally:
+        sm.destroy()
+        st.destroy()
+        P.destroy()
+
+
+def test_random_batch_matches_oracle(twisted_sys):
+    spec, S, O = twisted_sys
+    W, p1, p2, tau, K = 4, 9, 17, 5e-3, 3
+    print(f"[case] random batch twisted N={S.N} p=({p1},{p2})", flush=True)
+    P, st = _pair(S, tau, "lie", 0.0, "fp64", W)
+    sm = lsx.Sampler(st, p1, p2)
+    try:
+        pmax = max(p1, p2)
+        u = wl.uniforms((K, 2, W, pmax), seed=3)
+        c = wl.random_state(S.N, W, seed=4)
+        st.upload(c)
+        sm.rb_step(dev(u), K)
+        ref = c
+        for k in range(K):
+            ref = sto.random_batch_step(O, ref, tau, p1, u[k, 0, :, :p1], p2, u[k, 1, :, :p2])
+        assert colrel(st.download(), ref) < 3e-12
+        bad = lsx.Sampler(st, 0, 1)
+        with pytest.raises(lsx.LsxError):
+            bad.rb_step(dev(u), 1)
+        bad.destroy()
+    finally:
+        sm.destroy()
+        st.destroy()
+        P.destroy()
+
+
+# ---------------------------------------------------------------- stochastic layer splitting
+
+@pytest.mark.parametrize("scheme,kappa,precision", [("strang", 0.0, "fp64"), ("lie", 0.5, "fp64"),
+                                                     ("strang", 1.0, "fp64"), ("strang", 0.0, "mix_fp32")])
+def test_stochastic_splitting_uniform_matches_oracle(chain_sys, scheme, kappa, precision):
+    spec, S, O = chain_sys
+    W, p, tau, K = 20, 6, 1e-3, 4
+    print(f"[case] stochastic {scheme} kappa={kappa} {precision} W={W} p={p}", flush=True)
+    P, st = _pair(S, tau, scheme, kappa, precision, W)
+    sm = lsx.Sampler(st, p, p, eps=0.05)
+    try:
+        plan = splitting.SplitPlan(O, kappa)
+        nsub = len(sto.substeps(scheme, tau))
+        u = wl.uniforms((K, nsub, W, p), seed=5)
+        c = wl.random_state(S.N, W, seed=6)
+        st.upload(c)
+        sm.ss_step(dev(u), K)
+        ref = c
+        for k in range(K):
+            ref = sto.stochastic_step(plan, ref, tau, scheme, u[k], None, 0.05)
+        err = colrel(st.download(), ref)
+        print(f"  rel err {err:.2e}")
+        assert err < (3e-12 if precision == "fp64" else 1e-6)
+    finally:
+        sm.destroy()
+        st.destroy()
+        P.destroy()
+
+
+def test_stochastic_splitting_fallback_is_deterministic(twisted_sys):
+    spec, S, O = twisted_sys
+    W = 3
+    P, st = _pair(S, 5e-3, "strang", 0.0, "fp64", W)
+    sm = lsx.Sampler(st, 0, 0)
+    ref_st = lsx.State(P, W)
+    try:
+        c = wl.random_state(S.N, W, seed=8)
+        st.upload(c)
+        ref_st.upload(c)
+        sm.ss_step(None, 3)
+        ref_st.step(3)
+        assert colrel(st.download(), ref_st.download()) < 1e-13
+    finally:
+        sm.destroy()
+        ref_st.destroy()
+        st.destroy()
+        P.destroy()
+
+
+@pytest.mark.parametrize("which", ["chain", "twisted"])
+def test_features_and_increments_match_oracle(which, chain_sys, twisted_sys):
+    spec, S, O = chain_sys if which == "chain" else twisted_sys
+    W = 5
+    P, st = _pair(S, 2e-3, "strang", 0.0, "fp64", W)
+    sm = lsx.Sampler(st, 1, 1)
+    try:
+        plan = splitting.SplitPlan(O, 0.0)
+        c = wl.random_state(S.N, W, seed=9)
+        c[: S.N // 3] *= 1e-20  # far-apart fibre masses exercise the log feature
+        st.upload(c)
+        for layer in (1, 2):
+            nf = S.nfibres[layer]
+            X = torch.zeros((W, nf, O.d + 3), dtype=torch.float32, device=DEV)
+            sm.features(layer, X)
+            ref = sto.features(O, layer, c)
+            assert np.allclose(X.cpu().numpy(), ref, rtol=2e-7, atol=2e-7)
+            for half, t in ((0, 2e-3), (1, 1e-3)) if layer == 1 else ((0, 2e-3),):  # Strang: F2 only at tau
+                b = torch.zeros((W, nf), dtype=torch.float64, device=DEV)
+                sm.increments(layer, half, b)
+                bref = sto.increments(plan, layer, t, c)
+                assert np.allclose(b.cpu().numpy(), bref, rtol=1e-9, atol=1e-300)
+        assert colrel(st.download(), c) == 0.0  # the state is unchanged
+    finally:
+        sm.destroy()
+        st.destroy()
+        P.destroy()
+
+
+# ---------------------------------------------------------------- proposal network
+
+def _mlp_case(nin=5, M=1000, seed=0):
+    theta = wl.mlp_init(nin, 64, seed=seed)
+    theta = theta + 0.1 * np.random.default_rng(seed + 1).standard_normal(theta.size).astype(np.float32)
+    X = np.random.default_rng(seed + 2).standard_normal((M, nin)).astype(np.float32)
+    return theta.astype(np.float32), X
+
+
+@pytest.mark.parametrize("M", [1, 31, 1000, 70001])
+def test_mlp_forward_backward_match_oracle(M):
+    nin = 5
+    theta, X = _mlp_case(nin, M)
+    net = lsx.Mlp(nin)
+    try:
+        net.set(theta)
+        assert np.array_equal(net.get(), theta)
+        Xd = dev(X)
+        z = torch.zeros(M, dtype=torch.float32, device=DEV)
+        net.forward(Xd, M, z)
+        zref = sto.mlp_forward(theta.astype(np.float64), X.astype(np.float64))
+        assert np.abs(z.cpu().numpy() - zref).max() < 1e-5 * max(1.0, np.abs(zref).max())
+        dz = np.random.default_rng(3).standard_normal(M).astype(np.float32)
+        g = torch.zeros(net.nparams, dtype=torch.float32, device=DEV)
+        net.backward(Xd, M, dev(dz), g)
+        gref = sto.mlp_backward(theta.astype(np.float64), X.astype(np.float64), dz.astype(np.float64))
+        assert np.linalg.norm(g.cpu().numpy() - gref) < 1e-4 * np.linalg.norm(gref)
+    finally:
+        net.destroy()
+
+
+def test_proposal_loss_and_adam_match_oracle():
+    rng = np.random.default_rng(7)
+    sizes = [13, 1, 200, 57, 889, 30]
+    gptr = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    M = int(gptr[-1])
+    z = rng.standard_normal(M).astype(np.float32)
+    b = rng.random(M) ** 4
+    b[gptr[3]:gptr[4]] = 0.0  # skipped group
+    net = lsx.Mlp(4)
+    try:
+        out = torch.zeros(2, dtype=torch.float64, device=DEV)
+        dz = torch.zeros(M, dtype=torch.float32, device=DEV)
+        net.loss(dev(z), dev(b), dev(gptr), len(sizes), 0.05, out, dz)
+        L, dzref, _ = sto.proposal_loss(z.astype(np.float64), b, gptr, 0.05)
+        o = out.cpu().numpy()
+        assert abs(o[0] - L) < 1e-12 * L and o[1] == 1.0 / 5
+        assert np.abs(dz.cpu().numpy() - dzref).max() < 1e-6 * np.abs(dzref).max()
+        # Adam: two steps with the same gradient from a set parameter vector
+        theta = wl.mlp_init(4, 64, seed=4)
+        net.set(theta)
+        grad = rng.standard_normal(net.nparams).astype(np.float32)
+        th, m, v = theta.astype(np.float64), np.zeros(net.nparams), np.zeros(net.nparams)
+        for t in (1, 2):
+            net.adam(dev(grad), 1e-2)
+            th, m, v = sto.adam_step(th, m, v, grad.astype(np.float64), t, 1e-2)
+        assert np.abs(net.get() - th).max() < 1e-6
+    finally:
+        net.destroy()
+
+
+def test_train_step_matches_oracle_update():
+    """One fused train step = forward, objective gradient, backward, Adam (oracle in FP64)."""
+    nin = 4
+    rng = np.random.default_rng(11)
+    gptr = np.arange(0, 40 * 25 + 1, 25).astype(np.int64)
+    M = int(gptr[-1])
+    X = rng.standard_normal((M, nin)).astype(np.float32)
+    b = rng.random(M) ** 3
+    theta = wl.mlp_init(nin, 64, seed=2)
+    net = lsx.Mlp(nin)
+    try:
+        net.set(theta)
+        out = torch.zeros(2, dtype=torch.float64, device=DEV)
+        net.train_step(dev(X), M, dev(b), dev(gptr), len(gptr) - 1, 0.05, 3e-3, out)
+        th = theta.astype(np.float64)
+        z = sto.mlp_forward(th, X.astype(np.float64))
+        L, dz, _ = sto.proposal_loss(z, b, gptr, 0.05)
+        g = sto.mlp_backward(th, X.astype(np.float64), dz)
+        th1, _, _ = sto.adam_step(th, np.zeros_like(th), np.zeros_like(th), g, 1, 3e-3)
+        assert abs(out.cpu().numpy()[0] - L) < 1e-5 * L
+        # entries whose gradient is tiny flip direction under rounding; compare the rest
+        sig = np.abs(g) > 1e-3 * np.abs(g).max()
+        assert np.abs(net.get() - th1)[sig].max() < 1e-5
+    finally:
+        net.destroy()
+
+
+def _safe_uniforms(plan, O, c, tau, scheme, theta, K, W, p, eps, seed, margin=1e-4):
+    """Uniforms for K stochastic steps whose draws stay at least `margin` away from every cdf
+    boundary of the oracle's proposal, so FP32 network rounding cannot change a decision."""
+    rng = np.random.default_rng(seed)
+    subs = sto.substeps(scheme, tau)
+    u = np.zeros((K, len(subs), W, p))
+    x = c
+    for k in range(K):
+        for i, (layer, t, tph) in enumerate(subs):
+            nf = len(O.fib[layer])
+            X = sto.features(O, layer, x).astype(np.float32).astype(np.float64)
+            q = sto.proposal(sto.mlp_forward(theta, X.reshape(-1, X.shape[-1])).reshape(W, nf), nf, W, eps)
+            for w in range(W):
+                cdf = np.cumsum(q[w])
+                for s in range(p):
+                    while True:
+                        v = rng.random()
+                        if np.abs(cdf - v).min() > margin:
+                            break
+                    u[k, i, w, s] = v
+            x = sto.sampled_pass(plan, layer, t, x, sto.draw_weights(q, u[k, i]))
+            if tph != 0.0 and plan.kappa != 0.0:
+                x = plan.apply_phase(x, tph)
+    return u, x
+
+
+def test_stochastic_splitting_learned_matches_oracle(chain_sys):
+    spec, S, O = chain_sys
+    W, p, tau, K, eps = 6, 5, 1e-3, 3, 0.05
+    theta = wl.mlp_init(O.d + 3, 64, seed=3)
+    P, st = _pair(S, tau, "strang", 0.0, "fp64", W)
+    sm = lsx.Sampler(st, p, p, eps=eps)
+    net = lsx.Mlp(O.d + 3)
+    try:
+        net.set(theta)
+        sm.set_mlp(net)
+        plan = splitting.SplitPlan(O, 0.0)
+        c = wl.gaussian_state(spec, O.mn, wl.draw_k0(W, 1, seed=4), 2.0)
+        u, ref = _safe_uniforms(plan, O, c, tau, "strang", theta.astype(np.float64), K, W, p, eps, seed=12)
+        st.upload(c)
+        sm.ss_step(dev(u), K)
+        # The FP32 logits carry ~1e-6 relative error into every weight 1/(p q); weighted increments
+        # of low-probability fibres reach tens of times the state norm, hence ~1e-5 here.  A changed
+        # draw would instead move the state by a whole weighted increment (O(1) relative).
+        err = colrel(st.download(), ref)
+        print(f"  learned stochastic Strang rel err {err:.2e}")
+        assert err < 2e-4
+        with pytest.raises(lsx.LsxError):
+            net.destroy()  # attached
+        sm.set_mlp(None)
+    finally:
+        sm.destroy()
+        net.destroy()
+        st.destroy()
+        P.destroy()
+
+
+# ---------------------------------------------------------------- what the learned proposal gains
+
+def test_learned_proposal_beats_uniform(twisted_sys):
+    """Train the proposal on the GPU from plain trajectories, then on held-out wavepackets compare
+    (a) the variance objective and (b) the actual stochastic-splitting error against the
+    deterministic step, both at equal p, learned vs uniform."""
+    spec, S, O = twisted_sys
+    tau, eps = 5e-3, 0.05
+    nin = O.d + 3
+    Wt = 32
+    print(f"[case] learned proposal twisted N={S.N} fibres={S.nfibres}", flush=True)
+    P, st = _pair(S, tau, "strang", 0.0, "fp64", Wt)
+    sm = lsx.Sampler(st, 8, 8, eps=eps)
+    net = lsx.Mlp(nin)
+    try:
+        # training data: features and increment targets along plain trajectories
+        c0 = wl.gaussian_state(spec, O.mn, wl.draw_k0(Wt, 2, seed=1, kmax=5.0), 3.0)
+        st.upload(c0)
+        Xs, bs = [], []
+        for snap in range(6):
+            for layer, half in ((1, 1), (2, 0)):
+                nf = S.nfibres[layer]
+                X = torch.zeros((Wt, nf, nin), dtype=torch.float32, device=DEV)
+                b = torch.zeros((Wt, nf), dtype=torch.float64, device=DEV)
+                sm.features(layer, X)
+                sm.increments(layer, half, b)
+                Xs.append(X.reshape(-1, nin))
+                bs.append(b.reshape(-1))
+            st.step(5)
+        X = torch.cat(Xs)
+        b = torch.cat(bs)
+        gptr = dev(np.concatenate([[0], np.cumsum([S.nfibres[l] for _ in range(6) for l in (1, 2)
+                                                    for _ in range(Wt)])]).astype(np.int64))
+        G = 6 * 2 * Wt
+        M = X.shape[0]
+        net.set(wl.mlp_init(nin, 64, seed=0))
+        out = torch.zeros(2, dtype=torch.float64, device=DEV)
+        losses = []
+        for it in range(400):
+            net.train_step(X, M, b, gptr, G, eps, 3e-3, out)
+            if it % 100 == 0 or it == 399:
+                losses.append(float(out[0].cpu()))
+        print("  training objective", [f"{x:.3g}" for x in losses])
+        assert losses[-1] < 0.5 * losses[0]
+
+        # held-out wavepackets: objective of learned vs uniform proposal
+        Wv = 16
+        P2, st2 = _pair(S, tau, "strang", 0.0, "fp64", Wv)
+        sv = lsx.Sampler(st2, 8, 8, eps=eps)
+        ref_st = lsx.State(P2, Wv)
+        try:
+            cv = wl.gaussian_state(spec, O.mn, wl.draw_k0(Wv, 2, seed=77, kmax=5.0), 3.0)
+            st2.upload(cv)
+            ratios = []
+            for layer, half in ((1, 1), (2, 0)):
+                nf = S.nfibres[layer]
+                Xv = torch.zeros((Wv, nf, nin), dtype=torch.float32, device=DEV)
+                bv = torch.zeros((Wv, nf), dtype=torch.float64, device=DEV)
+                sv.features(layer, Xv)
+                sv.increments(layer, half, bv)
+                zv = torch.zeros(Wv * nf, dtype=torch.float32, device=DEV)
+                net.forward(Xv.reshape(-1, nin), Wv * nf, zv)
+                gp = dev(np.arange(0, Wv * nf + 1, nf).astype(np.int64))
+                dzv = torch.zeros(Wv * nf, dtype=torch.float32, device=DEV)
+                net.loss(zv, bv.reshape(-1), gp, Wv, eps, out, dzv)
+                l_learned = float(out[0].cpu())
+                net.loss(torch.zeros_like(zv), bv.reshape(-1), gp, Wv, eps, out, dzv)
+                l_uniform = float(out[0].cpu())
+                ratios.append(l_uniform / l_learned)
+                print(f"  layer {layer}: objective uniform {l_uniform:.3g} learned {l_learned:.3g}")
+            assert min(ratios) > 3.0
+
+            # actual errors after 20 stochastic steps at equal p (each column its own realisation)
+            K = 20
+            ref_st.upload(cv)
+            ref_st.step(K)
+            det = ref_st.download()
+            errs = {}
+            for name, mlp in (("uniform", None), ("learned", net)):
+                sv.set_mlp(mlp)
+                st2.upload(cv)
+                u = wl.uniforms((K, 3, Wv, 8), seed=99)
+                sv.ss_step(dev(u), K)
+                x = st2.download()
+                errs[name] = float(np.mean(np.linalg.norm(x - det, axis=0)))
+            sv.set_mlp(None)
+            print(f"  mean L2 error after {K} steps: {errs}")
+            assert errs["learned"] < 0.5 * errs["uniform"]
+        finally:
+            sv.destroy()
+            ref_st.destroy()
+            st2.destroy()
+            P2.destroy()
+    finally:
+        sm.destroy()
+        net.destroy()
+        st.destroy()
+        P.destroy()
