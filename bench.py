@@ -153,6 +153,204 @@ def batch_workload(args):
         S.destroy()
 
 
+def learned_workload(args):
+    """Learned importance-sampling proposal on the twisted bilayer (triangular lattices at
+    +-2.5 deg, Ec = 6500: N = 398821, 889 + 889 fibres), stochastic Strang layer splitting with
+    tau = 5e-3 to T = 1 (200 steps), precision = first of `--paths`.  kappa = 1: the kinetic part
+    is the exact phase and the sampled fibre flows are potential-only, so every fibre increment
+    (P_f - I) c_f is O(tau |V|) and importance weights above 1 do not blow the estimate up (with
+    kappa = 0, |P_f - I| reaches 2 on high-energy components and the weighted estimates diverge).
+
+    Training: `--learn-traj` plain trajectories (k0 area-uniform in |k0| <= 5, seed 0, sigma = 3),
+    features and optimal-proposal targets of both sub-steps every 20 steps, `--train-iters`
+    full-batch Adam steps on the GPU.  Evaluation: 8 held-out wavepackets (seed 1) x 16
+    realisations each (W = 128): the learned proposal with `--learn-p` draws per sub-step, the
+    uniform proposal at the same expected propagator work, and the deterministic step as the
+    reference (L2 error after T, variance of energy and mass over realisations).
+    """
+    import math
+    import torch
+    from paper_2103_14897_amd import proposal
+
+    prec = args.paths.split(",")[0]
+    p = args.learn_p
+    eps = 0.05
+    spec = wl.twisted_system(6500.0)
+    tau, K = 5e-3, 200
+    stream = torch.cuda.current_stream()
+    S = lsx.System.from_spec(spec)
+    mn = S.index()
+    nin = spec.d + 3
+    t0 = time.perf_counter()
+    P = lsx.Plan(S, tau, "strang", 1.0, prec, stream)
+    pre = time.perf_counter() - t0
+    Ls = {l: np.diff(S.fibres(l)[0]).astype(np.float64) for l in (1, 2)}
+    # ---- training data from plain trajectories
+    Wt = args.learn_traj
+    st = lsx.State(P, Wt)
+    sm = lsx.Sampler(st, p, p, eps)
+    st.upload(wl.gaussian_state(spec, mn, wl.draw_k0(Wt, 2, seed=0, kmax=5.0), 3.0), stream)
+    t0 = time.perf_counter()
+    X, b, gptr = proposal.collect(sm, st, K, 20, stream)
+    torch.cuda.synchronize()
+    t_collect = time.perf_counter() - t0
+    sm.destroy()
+    st.destroy()
+    M = int(X.shape[0])
+    net = lsx.Mlp(nin)
+    net.set(wl.mlp_init(nin, 64, seed=0))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    log = proposal.train(net, X, b, gptr, args.train_iters, 3e-3, eps, log_every=max(1, args.train_iters // 6),
+                         stream=stream)
+    e1.record(stream)
+    e1.synchronize()
+    ms_train = e0.elapsed_time(e1) / args.train_iters
+    # flops per row of one train step: forward 2 (nin H + H^2 + H); backward recomputes the
+    # forward and adds W2 delta2, the W2 and W1 outer products (2 H^2 each) and 2 nin H
+    H = 64
+    fl_row = 2 * (nin * H + H * H + H) + 2 * (nin * H + H * H) + 2 * H * H + 2 * H * H + 2 * nin * H
+    train_tf = fl_row * M / (ms_train * 1e-3) / 1e12
+    del X, b, gptr
+    # ---- held-out evaluation: 8 wavepackets x 16 realisations
+    nw, nr = 8, 16
+    W = nw * nr
+    k0 = np.repeat(wl.draw_k0(nw, 2, seed=1, kmax=5.0), nr, axis=0)
+    c0 = wl.gaussian_state(spec, mn, k0, 3.0)
+    st = lsx.State(P, W)
+    sm = lsx.Sampler(st, p, p, eps)
+    st.upload(c0, stream)
+    obj, cost_l, cost_u = {}, [], []
+    for layer, half in proposal.substep_layers("strang"):
+        nf = S.nfibres[layer]
+        Xv = torch.empty((W, nf, nin), dtype=torch.float32, device="cuda")
+        bv = torch.empty((W, nf), dtype=torch.float64, device="cuda")
+        sm.features(layer, Xv, stream)
+        sm.increments(layer, half, bv, stream)
+        obj[f"layer{layer}"] = {"uniform": proposal.objective(None, Xv.reshape(-1, nin), bv.reshape(-1), nf, eps),
+                                "learned": proposal.objective(net, Xv.reshape(-1, nin), bv.reshape(-1), nf, eps)}
+        z = torch.empty(W * nf, dtype=torch.float32, device="cuda")
+        net.forward(Xv.reshape(-1, nin), W * nf, z, stream)
+        zz = z.reshape(W, nf).double().cpu().numpy()
+        q = np.exp(zz - zz.max(axis=1, keepdims=True))
+        q = (1 - eps) * q / q.sum(axis=1, keepdims=True) + eps / nf
+        cost_l.append(float((q * Ls[layer][None, :] ** 2).sum(axis=1).mean()))
+        cost_u.append(float((Ls[layer] ** 2).mean()))
+    # expected propagator work per draw (sum of L^2 weighted by q) at the initial states
+    pu = int(math.ceil(p * sum(cost_l) / sum(cost_u)))
+    sm.destroy()
+    runs = {}
+    ref = lsx.State(P, W)
+    ref.upload(c0, stream)
+    e0.record(stream)
+    ref.step(K, stream)
+    e1.record(stream)
+    e1.synchronize()
+    runs["deterministic"] = {"ms_per_step": e0.elapsed_time(e1) / K}
+    det = ref.download(stream)
+    obs_det = ref.observables(lsx.OBS_MASS | lsx.OBS_ENERGY, stream)
+    ref.destroy()
+    for name, pp, mlp in (("learned", p, net), ("uniform_equal_cost", pu, None), ("uniform_equal_p", p, None)):
+        smr = lsx.Sampler(st, pp, pp, eps)
+        smr.set_mlp(mlp)
+        u = torch.as_tensor(wl.uniforms((K, 3, W, pp), seed=7), device="cuda")
+        st.upload(c0, stream)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        smr.ss_step(u, K, stream)
+        e1.record(stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / K
+        x = st.download(stream)
+        obs = st.observables(lsx.OBS_MASS | lsx.OBS_ENERGY, stream)
+        err = np.linalg.norm(x - det, axis=0)
+        runs[name] = {"p": pp, "ms_per_step": ms,
+                      "l2_error_mean": float(err.mean()), "l2_error_median": float(np.median(err)),
+                      "energy_var_mean": float(obs["energy"].reshape(nw, nr).var(axis=1).mean()),
+                      "energy_bias_mean": float(np.abs(obs["energy"].reshape(nw, nr).mean(axis=1)
+                                                       - obs_det["energy"].reshape(nw, nr)[:, 0]).mean()),
+                      "mass_var_mean": float(obs["mass"].reshape(nw, nr).var(axis=1).mean())}
+        smr.set_mlp(None)
+        smr.destroy()
+        del u
+    st.destroy()
+    out = {"metric": "coeff·steps/s of learned stochastic layer splitting; L2 error and observable variance "
+                     "vs uniform sampling at equal cost",
+           "value": S.N * W / (runs["learned"]["ms_per_step"] * 1e-3), "unit": "coeff*steps/s", "n_gpus": 1,
+           "steps": K, "warmup": 0, "ms_per_step": runs["learned"]["ms_per_step"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[prec] + " (network f32)", "data": "synthetic",
+           "config": {"workload": "twisted_tri_pm2.5deg_Ec6500_kappa1_stochastic_strang_tau5e-3_learned_proposal",
+                      "N": S.N, "fibres": [S.nfibres[1], S.nfibres[2]], "p": p, "eps": eps,
+                      "train_trajectories": Wt, "eval_columns": f"{nw} wavepackets x {nr} realisations"},
+           "training": {"rows": M, "iters": args.train_iters, "ms_per_iter": ms_train, "collect_s": t_collect,
+                        "objective_log": log, "plan_precompute_s": pre},
+           "heldout_objective": obj,
+           "expected_work_per_draw": {"learned": sum(cost_l) / 2, "uniform": sum(cost_u) / 2},
+           "runs": runs,
+           "roofline": {"bound": "alu", "achieved": train_tf, "peak": 157.3, "unit": "TFLOP/s",
+                        "frac": train_tf / 157.3, "traffic": None,
+                        "kernel": "proposal network train step (forward + objective + backward + Adam), FP32 VALU"}}
+    print(json.dumps(out))
+    net.destroy()
+    P.destroy()
+    S.destroy()
+
+
+def si_workload(args):
+    """Semi-implicit (Alg. 1) and random batch (Alg. 4, 1/10 of the fibres per layer) steps on the
+    twisted bilayer (Ec = 6500, N = 398821, W = 128, tau = 5e-3): one neighbour-stencil kernel per
+    step, HBM-bound.  The plan is built with kappa = 1 (these steps use only |K|^2 and the stencil)."""
+    import torch
+
+    w = wl.twisted()
+    S = lsx.System.from_spec(w.spec)
+    P = lsx.Plan(S, w.tau, "strang", 1.0, "fp64")
+    W, N = w.W, S.N
+    c0 = w.initial_state(S.index())
+    st = lsx.State(P, W)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    res = {}
+    st.upload(c0, stream)
+    st.si_step(args.warmup, stream)
+    e0.record(stream)
+    st.si_step(args.steps, stream)
+    e1.record(stream)
+    e1.synchronize()
+    res["alg1"] = {"ms_per_step": e0.elapsed_time(e1) / args.steps}
+    st.upload(c0, stream)
+    st.si_step(w.nsteps, stream)
+    res["alg1"]["mass_after_T"] = float(st.observables(lsx.OBS_MASS, stream)["mass"].mean())
+    p1, p2 = max(1, S.nfibres[1] // 10), max(1, S.nfibres[2] // 10)
+    sm = lsx.Sampler(st, p1, p2)
+    u = torch.as_tensor(wl.uniforms((args.steps, 2, W, max(p1, p2)), seed=3), device="cuda")
+    st.upload(c0, stream)
+    e0.record(stream)
+    sm.rb_step(u, args.steps, stream)
+    e1.record(stream)
+    e1.synchronize()
+    res["alg4"] = {"ms_per_step": e0.elapsed_time(e1) / args.steps, "p": [p1, p2]}
+    sm.destroy()
+    nv = len(w.spec.pot1) + len(w.spec.pot2)
+    # algorithmic bytes of one stencil launch: read and write the state, |K|^2 and the stencil
+    # table (neighbour rows are read again from cache, not from HBM)
+    nbytes = 2.0 * N * W * 16 + 8.0 * N + 4.0 * nv * N
+    t = res["alg1"]["ms_per_step"] * 1e-3
+    out = {"metric": "coeff·steps/s of the semi-implicit step (Alg. 1); random batch (Alg. 4) beside it",
+           "value": N * W / t, "unit": "coeff*steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": res["alg1"]["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "twisted_tri_pm2.5deg_Ec6500_W128_semi_implicit_tau5e-3", "N": N, "W": W},
+           "runs": res,
+           "roofline": {"bound": "hbm", "achieved": nbytes / t / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                        "frac": nbytes / t / HBM_PEAK, "traffic": None, "kernel": "k_si_step (Alg. 1)",
+                        "algorithmic_bytes": nbytes}}
+    print(json.dumps(out))
+    st.destroy()
+    P.destroy()
+    S.destroy()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -164,7 +362,11 @@ def main():
     ap.add_argument("--calib-mib", type=int, default=64)
     ap.add_argument("--batch-1d", type=int, default=240)
     ap.add_argument("--batch-2d", type=int, default=16)
-    ap.add_argument("--workload", default="chain", choices=["chain", "twisted", "twisted1", "tiny", "batch"],
+    ap.add_argument("--learn-traj", type=int, default=200)
+    ap.add_argument("--learn-p", type=int, default=16)
+    ap.add_argument("--train-iters", type=int, default=300)
+    ap.add_argument("--workload", default="chain",
+                    choices=["chain", "twisted", "twisted1", "tiny", "batch", "learned", "si"],
                     help="chain: the metric's workload (default); the others are extra measurements")
     ap.add_argument("--kappa", type=float, default=0.0)
     args = ap.parse_args()
@@ -178,6 +380,10 @@ def main():
 
     if args.workload == "batch":
         return batch_workload(args)
+    if args.workload == "learned":
+        return learned_workload(args)
+    if args.workload == "si":
+        return si_workload(args)
     w = {"chain": wl.chain, "twisted": wl.twisted, "twisted1": lambda: wl.twisted(W=1),
          "tiny": wl.tiny_chain}[args.workload]()
     S = lsx.System.from_spec(w.spec)

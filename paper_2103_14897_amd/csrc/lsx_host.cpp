@@ -1766,7 +1766,7 @@ lsx_status si_once(lsx_plan* pl, lsx_state* st, const double* wt1, const int32_t
   const lsx_system* sys = pl->sys;
   LSX_HIP_TRY(launch_si_step(s, sys->N, st->W, pl->tau, pl->K2.p, sys->pot[0].nv, pl->L[0].nbr.p, pl->L[0].v.p,
                              wt1, fid1, sys->pot[1].nv, pl->L[1].nbr.p, pl->L[1].v.p, wt2, fid2, st->buf[0],
-                             st->buf[1]));
+                             st->buf[1], pl->zero.p));
   Runner r{pl, st, s};
   r.cur = 1;
   return r.finish();

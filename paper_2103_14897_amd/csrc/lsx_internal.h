@@ -106,7 +106,7 @@ hipError_t launch_fibre_mass(hipStream_t s, int nf, const int32_t* ptr, const in
 hipError_t launch_si_step(hipStream_t s, int64_t N, int W, double tau, const double* K2, int nv1,
                           const int32_t* nbr1, const double2* v1, const double* wt1, const int32_t* fid1, int nv2,
                           const int32_t* nbr2, const double2* v2, const double* wt2, const int32_t* fid2,
-                          const double2* X, double2* Y);
+                          const double2* X, double2* Y, const double2* zero);
 hipError_t launch_subset_weights(hipStream_t s, int nf, int W, int p, int ustride, const double* u, double* wt);
 hipError_t launch_sample_weights(hipStream_t s, int nf, int W, int p, int ustride, const double* u, const float* z,
                                  double eps, double* wt);

@@ -6,6 +6,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+#include <cstdlib>
+
 #include "lsx_internal.h"
 
 namespace lsx {
@@ -14,45 +17,75 @@ namespace lsx {
 // out[i][w] = (x - i tau (a1 (V^1 x)_i + a2 (V^2 x)_i)) / (1 + i tau |K_i|^2 / 2), where
 // (V^j x)_i = sum_p v_p x[nbr_j(i, p)] (the layer-j potential inside row i's fibre) and
 // a_j = wt_j[fibre_j(i)][w] (1 when wt_j is null: Alg. 1).  One thread per (row, column).
-__global__ __launch_bounds__(256) void k_si_step(int64_t N, int W, double tau, const double* __restrict__ K2,
+//
+// Cache blocking: every neighbour row is read again by nv other rows, the layer-1 ones
+// (m - p, n) from far away in canonical order.  Workgroup b runs on XCD b % 8, so XCD x
+// takes the contiguous slab x of the rows, and sweeps it in blocks of CW columns: the rows
+// between a neighbour's first and last use then fit in that XCD's own L2.
+//
+// Stencil sizes NV1, NV2 are compile-time for the common cases (1D cosine: 2, 2D first shell:
+// 6) so every neighbour index and value is loaded before any is used; a missing neighbour
+// (index -1) reads a zero row instead of branching.  NV1 = 0 selects runtime loops.
+template <int NVC>
+__device__ __forceinline__ void si_stencil(int64_t i, int w, int W, int nv, const int32_t* __restrict__ nbr,
+                                           const double2* __restrict__ v, const double2* __restrict__ X,
+                                           const double2* __restrict__ zero, double& sr, double& si) {
+  if (NVC > 0) {
+    int j[8];
+    double2 y[8];
+#pragma unroll
+    for (int p = 0; p < NVC; ++p) j[p] = nbr[i * NVC + p];
+#pragma unroll
+    for (int p = 0; p < NVC; ++p) y[p] = *(j[p] >= 0 ? X + (int64_t)j[p] * W + w : zero);
+#pragma unroll
+    for (int p = 0; p < NVC; ++p) {
+      const double2 c = v[p];
+      sr += c.x * y[p].x - c.y * y[p].y;
+      si += c.x * y[p].y + c.y * y[p].x;
+    }
+  } else {
+    for (int p = 0; p < nv; ++p) {
+      const int jj = nbr[i * nv + p];
+      const double2 y = *(jj >= 0 ? X + (int64_t)jj * W + w : zero), c = v[p];
+      sr += c.x * y.x - c.y * y.y;
+      si += c.x * y.y + c.y * y.x;
+    }
+  }
+}
+
+template <int NV1, int NV2>
+__global__ __launch_bounds__(256) void k_si_step(int64_t N, int W, int CW, double tau, const double* __restrict__ K2,
                                                  int nv1, const int32_t* __restrict__ nbr1,
                                                  const double2* __restrict__ v1, const double* __restrict__ wt1,
                                                  const int32_t* __restrict__ fid1, int nv2,
                                                  const int32_t* __restrict__ nbr2, const double2* __restrict__ v2,
                                                  const double* __restrict__ wt2, const int32_t* __restrict__ fid2,
-                                                 const double2* __restrict__ X, double2* __restrict__ Y) {
-  const int64_t total = N * (int64_t)W;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
-    const int64_t i = e / W;
-    const int w = (int)(e - i * W);
-    double s1r = 0.0, s1i = 0.0, s2r = 0.0, s2i = 0.0;
-    for (int p = 0; p < nv1; ++p) {
-      const int j = nbr1[i * nv1 + p];
-      if (j >= 0) {
-        const double2 y = X[(int64_t)j * W + w], v = v1[p];
-        s1r += v.x * y.x - v.y * y.y;
-        s1i += v.x * y.y + v.y * y.x;
-      }
+                                                 const double2* __restrict__ X, double2* __restrict__ Y,
+                                                 const double2* __restrict__ zero) {
+  const int xcd = blockIdx.x & 7;
+  const int G = gridDim.x >> 3, lb = blockIdx.x >> 3;
+  const int64_t slab = (N + 7) / 8;
+  const int64_t r0 = xcd * slab, r1 = min(N, r0 + slab);
+  const int rpi = 256 / CW;  // rows per workgroup iteration
+  const int tr = threadIdx.x / CW, tc = threadIdx.x - tr * CW;
+  for (int cb = 0; cb < W; cb += CW) {
+    const int w = cb + tc;
+    if (w >= W) continue;
+    for (int64_t i = r0 + (int64_t)lb * rpi + tr; i < r1; i += (int64_t)G * rpi) {
+      double s1r = 0.0, s1i = 0.0, s2r = 0.0, s2i = 0.0;
+      si_stencil<NV1>(i, w, W, nv1, nbr1, v1, X, zero, s1r, s1i);
+      si_stencil<NV2>(i, w, W, nv2, nbr2, v2, X, zero, s2r, s2i);
+      const double a1 = wt1 ? wt1[(int64_t)fid1[i] * W + w] : 1.0;
+      const double a2 = wt2 ? wt2[(int64_t)fid2[i] * W + w] : 1.0;
+      const double2 x = X[i * W + w];
+      // z = x - i tau (a1 s1 + a2 s2)
+      const double zr = x.x + tau * (a1 * s1i + a2 * s2i);
+      const double zi = x.y - tau * (a1 * s1r + a2 * s2r);
+      // z / (1 + i b) = z (1 - i b) / (1 + b^2)
+      const double b = 0.5 * tau * K2[i];
+      const double den = 1.0 + b * b;
+      Y[i * W + w] = make_double2((zr + b * zi) / den, (zi - b * zr) / den);
     }
-    for (int p = 0; p < nv2; ++p) {
-      const int j = nbr2[i * nv2 + p];
-      if (j >= 0) {
-        const double2 y = X[(int64_t)j * W + w], v = v2[p];
-        s2r += v.x * y.x - v.y * y.y;
-        s2i += v.x * y.y + v.y * y.x;
-      }
-    }
-    const double a1 = wt1 ? wt1[(int64_t)fid1[i] * W + w] : 1.0;
-    const double a2 = wt2 ? wt2[(int64_t)fid2[i] * W + w] : 1.0;
-    const double2 x = X[e];
-    // z = x - i tau (a1 s1 + a2 s2)
-    const double zr = x.x + tau * (a1 * s1i + a2 * s2i);
-    const double zi = x.y - tau * (a1 * s1r + a2 * s2r);
-    // z / (1 + i b) = z (1 - i b) / (1 + b^2)
-    const double b = 0.5 * tau * K2[i];
-    const double den = 1.0 + b * b;
-    Y[e] = make_double2((zr + b * zi) / den, (zi - b * zr) / den);
   }
 }
 
@@ -576,10 +609,28 @@ static unsigned grid_for(int64_t n, int64_t cap) {
 hipError_t launch_si_step(hipStream_t s, int64_t N, int W, double tau, const double* K2, int nv1,
                           const int32_t* nbr1, const double2* v1, const double* wt1, const int32_t* fid1, int nv2,
                           const int32_t* nbr2, const double2* v2, const double* wt2, const int32_t* fid2,
-                          const double2* X, double2* Y) {
+                          const double2* X, double2* Y, const double2* zero) {
   if (N == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_si_step, dim3(grid_for(N * (int64_t)W, 256 * 64)), dim3(256), 0, s, N, W, tau, K2, nv1,
-                     nbr1, v1, wt1, fid1, nv2, nbr2, v2, wt2, fid2, X, Y);
+  // column block: LSX_SI_CW (1..256, a power of two) or 8; 256 workgroups per XCD
+  static const int cw_env = [] {
+    const char* v = std::getenv("LSX_SI_CW");
+    const int x = v ? std::atoi(v) : 8;
+    return (x >= 1 && x <= 256 && (x & (x - 1)) == 0) ? x : 8;
+  }();
+  int CW = cw_env;
+  while (CW > 1 && CW / 2 >= W) CW /= 2;  // narrow states: no idle lanes beyond W
+  const int64_t rows_per_xcd = (N + 7) / 8;
+  const int64_t G = std::min<int64_t>(256, std::max<int64_t>(1, (rows_per_xcd * CW + 255) / 256));
+  const dim3 grid((unsigned)(8 * G));
+  if (nv1 == 2 && nv2 == 2)
+    hipLaunchKernelGGL((k_si_step<2, 2>), grid, dim3(256), 0, s, N, W, CW, tau, K2, nv1, nbr1, v1, wt1, fid1, nv2,
+                       nbr2, v2, wt2, fid2, X, Y, zero);
+  else if (nv1 == 6 && nv2 == 6)
+    hipLaunchKernelGGL((k_si_step<6, 6>), grid, dim3(256), 0, s, N, W, CW, tau, K2, nv1, nbr1, v1, wt1, fid1, nv2,
+                       nbr2, v2, wt2, fid2, X, Y, zero);
+  else
+    hipLaunchKernelGGL((k_si_step<0, 0>), grid, dim3(256), 0, s, N, W, CW, tau, K2, nv1, nbr1, v1, wt1, fid1, nv2,
+                       nbr2, v2, wt2, fid2, X, Y, zero);
   return hipGetLastError();
 }
 

@@ -361,7 +361,8 @@ def test_learned_proposal_beats_uniform(twisted_sys):
     nin = O.d + 3
     Wt = 32
     print(f"[case] learned proposal twisted N={S.N} fibres={S.nfibres}", flush=True)
-    P, st = _pair(S, tau, "strang", 0.0, "fp64", Wt)
+    # kappa = 1: potential-only fibre flows, so weighted increments stay O(tau |V|)
+    P, st = _pair(S, tau, "strang", 1.0, "fp64", Wt)
     sm = lsx.Sampler(st, 8, 8, eps=eps)
     net = lsx.Mlp(nin)
     try:
@@ -397,7 +398,7 @@ def test_learned_proposal_beats_uniform(twisted_sys):
 
         # held-out wavepackets: objective of learned vs uniform proposal
         Wv = 16
-        P2, st2 = _pair(S, tau, "strang", 0.0, "fp64", Wv)
+        P2, st2 = _pair(S, tau, "strang", 1.0, "fp64", Wv)
         sv = lsx.Sampler(st2, 8, 8, eps=eps)
         ref_st = lsx.State(P2, Wv)
         try:
