@@ -423,38 +423,44 @@ __device__ __forceinline__ void load_group4(Group4<PT, NB, U>& G, const PassArgs
   }
 }
 
+// Complex products with three real MFMAs (the 3M / Gauss form): for P = a + ib and
+// x = c + id,  k1 = (a + b) c,  k2 = a (d - c),  k3 = b (c + d);  Re = k1 - k3, Im = k1 + k2.
+// The sums a + b, d - c, c + d are formed on the VALU in the operand precision.
 template <int NB, int U>
-__device__ __forceinline__ void mma_group_f64(v4d (&rr)[NB], v4d (&ii)[NB], v4d (&ri)[NB], v4d (&ir)[NB],
+__device__ __forceinline__ void mma_group_f64(v4d (&k1)[NB], v4d (&k2)[NB], v4d (&k3)[NB],
                                               const Group4<double2, NB, U>& G) {
 #pragma unroll
-  for (int u = 0; u < U; ++u)
+  for (int u = 0; u < U; ++u) {
+    const double ps = G.p[u].x + G.p[u].y;
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
-      rr[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(G.p[u].x, G.x[u][nb].x, rr[nb], 0, 0, 0);
-      ii[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(G.p[u].y, G.x[u][nb].y, ii[nb], 0, 0, 0);
-      ri[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(G.p[u].x, G.x[u][nb].y, ri[nb], 0, 0, 0);
-      ir[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(G.p[u].y, G.x[u][nb].x, ir[nb], 0, 0, 0);
+      const double xr = G.x[u][nb].x, xi = G.x[u][nb].y;
+      k1[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ps, xr, k1[nb], 0, 0, 0);
+      k2[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(G.p[u].x, xi - xr, k2[nb], 0, 0, 0);
+      k3[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(G.p[u].y, xr + xi, k3[nb], 0, 0, 0);
     }
+  }
 }
 
 template <int NB, int U>
-__device__ __forceinline__ void mma_group_f32(v4f (&rr)[NB], v4f (&ii)[NB], v4f (&ri)[NB], v4f (&ir)[NB],
+__device__ __forceinline__ void mma_group_f32(v4f (&k1)[NB], v4f (&k2)[NB], v4f (&k3)[NB],
                                               const Group4<float2, NB, U>& G) {
 #pragma unroll
-  for (int u = 0; u < U; ++u)
+  for (int u = 0; u < U; ++u) {
+    const float ps = G.p[u].x + G.p[u].y;
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
       const float xr = (float)G.x[u][nb].x, xi = (float)G.x[u][nb].y;
-      rr[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(G.p[u].x, xr, rr[nb], 0, 0, 0);
-      ii[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(G.p[u].y, xi, ii[nb], 0, 0, 0);
-      ri[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(G.p[u].x, xi, ri[nb], 0, 0, 0);
-      ir[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(G.p[u].y, xr, ir[nb], 0, 0, 0);
+      k1[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ps, xr, k1[nb], 0, 0, 0);
+      k2[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(G.p[u].x, xi - xr, k2[nb], 0, 0, 0);
+      k3[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(G.p[u].y, xr + xi, k3[nb], 0, 0, 0);
     }
+  }
 }
 
-// FP64: complex128 P, X on v_mfma_f64_16x16x4f64.  Four independent accumulator chains
-// per column block (Pr Xr, Pi Xi, Pr Xi, Pi Xr); groups of U k-steps are double
-// buffered in registers, so the loads of group g+1 are in flight during the MFMAs of g.
+// FP64: complex128 P, X on v_mfma_f64_16x16x4f64.  Three independent accumulator chains
+// per column block (the 3M products above); groups of U k-steps are double buffered in
+// registers, so the loads of group g+1 are in flight during the MFMAs of g.
 template <int NB, int KS, int U, bool GATHER, bool BATCH>
 __global__ __launch_bounds__(64 * KS) void k_pass_f64(PassArgs a0) {
   extern __shared__ double red[];
@@ -476,9 +482,9 @@ __global__ __launch_bounds__(64 * KS) void k_pass_f64(PassArgs a0) {
     wc[nb] = (t.wb * NB + nb) * 16 + li;
     wok[nb] = wc[nb] < a.W;
   }
-  v4d rr[NB], ii[NB], ri[NB], ir[NB];
+  v4d k1[NB], k2[NB], k3[NB];
 #pragma unroll
-  for (int nb = 0; nb < NB; ++nb) rr[nb] = ii[nb] = ri[nb] = ir[nb] = (v4d){0.0, 0.0, 0.0, 0.0};
+  for (int nb = 0; nb < NB; ++nb) k1[nb] = k2[nb] = k3[nb] = (v4d){0.0, 0.0, 0.0, 0.0};
   // two register buffers in ping-pong: B is loaded while A is consumed and vice versa
   Group4<double2, NB, U> A, B;
   const int stride = KS * U;
@@ -487,25 +493,25 @@ __global__ __launch_bounds__(64 * KS) void k_pass_f64(PassArgs a0) {
   for (; g < nks; g += 2 * stride) {
     load_group4<GATHER>(B, a, P, g + stride, nks, r0, L, lk, wc, wok);  // past the end: zeros
     __builtin_amdgcn_sched_barrier(0);
-    mma_group_f64(rr, ii, ri, ir, A);
+    mma_group_f64(k1, k2, k3, A);
     if (g + stride >= nks) break;
     load_group4<GATHER>(A, a, P, g + 2 * stride, nks, r0, L, lk, wc, wok);
     __builtin_amdgcn_sched_barrier(0);
-    mma_group_f64(rr, ii, ri, ir, B);
+    mma_group_f64(k1, k2, k3, B);
   }
   double acc[NB][2][4];
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      acc[nb][0][r] = rr[nb][r] - ii[nb][r];
-      acc[nb][1][r] = ri[nb][r] + ir[nb][r];
+      acc[nb][0][r] = k1[nb][r] - k3[nb][r];
+      acc[nb][1][r] = k1[nb][r] + k2[nb][r];
     }
   pass_epilogue<NB, KS, false, true>(a, t, acc, red);
 }
 
 // Mixed FP32: y = d .* x (FP64) + E x~ with E complex64, x~ = fp32(x), FP32 MFMA
-// accumulation (v_mfma_f32_16x16x4f32), same pipelining as the FP64 kernel.
+// accumulation (v_mfma_f32_16x16x4f32, 3M products), same pipelining as the FP64 kernel.
 template <int NB, int KS, int U, bool GATHER, bool BATCH>
 __global__ __launch_bounds__(64 * KS) void k_pass_f32(PassArgs a0) {
   extern __shared__ double red[];
@@ -527,9 +533,9 @@ __global__ __launch_bounds__(64 * KS) void k_pass_f32(PassArgs a0) {
     wc[nb] = (t.wb * NB + nb) * 16 + li;
     wok[nb] = wc[nb] < a.W;
   }
-  v4f rr[NB], ii[NB], ri[NB], ir[NB];
+  v4f k1[NB], k2[NB], k3[NB];
 #pragma unroll
-  for (int nb = 0; nb < NB; ++nb) rr[nb] = ii[nb] = ri[nb] = ir[nb] = (v4f){0.f, 0.f, 0.f, 0.f};
+  for (int nb = 0; nb < NB; ++nb) k1[nb] = k2[nb] = k3[nb] = (v4f){0.f, 0.f, 0.f, 0.f};
   Group4<float2, NB, U> A, B;
   const int stride = KS * U;
   int g = kw * U;
@@ -537,19 +543,19 @@ __global__ __launch_bounds__(64 * KS) void k_pass_f32(PassArgs a0) {
   for (; g < nks; g += 2 * stride) {
     load_group4<GATHER>(B, a, P, g + stride, nks, r0, L, lk, wc, wok);  // past the end: zeros
     __builtin_amdgcn_sched_barrier(0);
-    mma_group_f32(rr, ii, ri, ir, A);
+    mma_group_f32(k1, k2, k3, A);
     if (g + stride >= nks) break;
     load_group4<GATHER>(A, a, P, g + 2 * stride, nks, r0, L, lk, wc, wok);
     __builtin_amdgcn_sched_barrier(0);
-    mma_group_f32(rr, ii, ri, ir, B);
+    mma_group_f32(k1, k2, k3, B);
   }
   double acc[NB][2][4];
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      acc[nb][0][r] = (double)rr[nb][r] - (double)ii[nb][r];
-      acc[nb][1][r] = (double)ri[nb][r] + (double)ir[nb][r];
+      acc[nb][0][r] = (double)k1[nb][r] - (double)k3[nb][r];
+      acc[nb][1][r] = (double)k1[nb][r] + (double)k2[nb][r];
     }
   pass_epilogue<NB, KS, true, false>(a, t, acc, red);
 }
