@@ -176,7 +176,7 @@ def learned_workload(args):
     p = args.learn_p
     eps = 0.05
     spec = wl.twisted_system(6500.0)
-    tau, K = 5e-3, 200
+    tau, K = 5e-3, args.learn_steps
     stream = torch.cuda.current_stream()
     S = lsx.System.from_spec(spec)
     mn = S.index()
@@ -365,6 +365,7 @@ def main():
     ap.add_argument("--learn-traj", type=int, default=200)
     ap.add_argument("--learn-p", type=int, default=16)
     ap.add_argument("--train-iters", type=int, default=300)
+    ap.add_argument("--learn-steps", type=int, default=200, help="learned mode: evaluation steps (T = steps tau)")
     ap.add_argument("--workload", default="chain",
                     choices=["chain", "twisted", "twisted1", "tiny", "batch", "learned", "si"],
                     help="chain: the metric's workload (default); the others are extra measurements")
