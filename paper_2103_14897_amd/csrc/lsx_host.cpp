@@ -1569,10 +1569,12 @@ extern "C" lsx_status lsx_mlp_destroy(lsx_mlp* m) {
 }
 
 // ================================================================ stochastic steps
-// Sampled fibre sub-steps run in the canonical layout: the weighted pass reads the state,
-// writes the rows of the sampled fibres into the work array, and those rows are copied
-// back; every other row is left untouched.  Tiles are listed fibre-major, so the tiles of
-// the sampled fibres are compacted on the device without any host round trip.
+// Sampled fibre sub-steps run in the canonical layout.  After the draws, every fibre gets
+// the list of columns (wavepackets) that drew it; tiles cover only those (fibre, column)
+// pairs, so the pass does the method's own work rather than a full pass.  The weighted
+// pass reads the state and writes the sampled (rows, columns) into the work array, from
+// which they are copied back; every other entry is left untouched.  The tile lists are
+// built on the device, with no host round trip.
 static constexpr int kSamplerMaxFibres = 2048;
 
 struct lsx_sampler {
@@ -1582,13 +1584,18 @@ struct lsx_sampler {
   int p[2] = {0, 0};
   double eps = 0.0;
   int nf[2] = {0, 0};
-  int ntiles[2] = {0, 0};
-  DBuf<TileDesc> tilesF[2], tilesC[2];
-  DBuf<int32_t> tptr[2], fid[2];
-  DBuf<int32_t> count, flag;
+  int ntiles[2] = {0, 0};  // tiles of a pass over every fibre and column: the launch bound
+  DBuf<TileDesc> tiles[2];  // tiles of the sampled (fibre, column) pairs, built per sub-step
+  DBuf<int32_t> cols[2], ncols[2], off[2], fid[2], d0[2];
+  DBuf<int64_t> poff[2];
+  DBuf<int32_t> count;
   DBuf<double> wt[2], mass, sfeat[2];
   DBuf<float> X, z;
 };
+
+// column block of the sampled passes: one 16-column block per tile (the sampled columns of
+// a fibre are typically few)
+static constexpr int kSampledNB = 1;
 
 extern "C" lsx_status lsx_sampler_create(lsx_plan* pl, lsx_state* st, int32_t p1, int32_t p2, double eps,
                                          lsx_sampler** out) {
@@ -1616,31 +1623,23 @@ extern "C" lsx_status lsx_sampler_create(lsx_plan* pl, lsx_state* st, int32_t p1
     const int nf = ld.nf;
     sm->nf[j] = nf;
     maxnf = std::max(maxnf, nf);
-    // fibre-major tiles in the state's tile shape
-    const int nb = st->nb[j];
-    const int nwb = (W + 16 * nb - 1) / (16 * nb);
-    std::vector<TileDesc> tiles;
-    std::vector<int32_t> tptr(nf + 1, 0);
+    const int nwb = (W + 16 * kSampledNB - 1) / (16 * kSampledNB);
+    int64_t ntiles = 0;
+    for (int f = 0; f < nf; ++f) ntiles += (int64_t)((ld.h_ptr[f + 1] - ld.h_ptr[f] + 15) / 16) * nwb;
+    if (ntiles > INT32_MAX) return fail(LSX_E_INVALID, "too many tiles for one sampled pass");
+    sm->ntiles[j] = (int)ntiles;
+    LSX_TRY(sm->tiles[j].alloc((size_t)std::max<int64_t>(ntiles, 1)));
+    LSX_TRY(sm->cols[j].alloc((size_t)std::max(nf, 1) * W));
+    LSX_TRY(sm->ncols[j].alloc(std::max(nf, 1)));
+    LSX_TRY(sm->off[j].alloc(std::max(nf, 1)));
+    std::vector<int64_t> poff(nf, 0);
+    std::vector<int32_t> d0(nf, 0);
     for (int f = 0; f < nf; ++f) {
-      const int L = ld.h_ptr[f + 1] - ld.h_ptr[f];
-      for (int rb = 0; rb < (L + 15) / 16; ++rb)
-        for (int wb = 0; wb < nwb; ++wb) {
-          TileDesc t;
-          t.r0 = ld.h_ptr[f];
-          t.L = L;
-          t.rb = rb;
-          t.wb = wb;
-          t.poff = ld.h_poff.empty() ? 0 : ld.h_poff[f];
-          t.f = f;
-          t.d0 = ld.h_d0.empty() ? ld.h_ptr[f] : ld.h_d0[f];
-          tiles.push_back(t);
-        }
-      tptr[f + 1] = (int32_t)tiles.size();
+      poff[f] = ld.h_poff.empty() ? 0 : ld.h_poff[f];
+      d0[f] = ld.h_d0.empty() ? ld.h_ptr[f] : ld.h_d0[f];
     }
-    sm->ntiles[j] = (int)tiles.size();
-    LSX_TRY(sm->tilesF[j].upload(tiles, nullptr));
-    LSX_TRY(sm->tilesC[j].alloc(tiles.size()));
-    LSX_TRY(sm->tptr[j].upload(tptr, nullptr));
+    LSX_TRY(sm->poff[j].upload(poff, nullptr));
+    LSX_TRY(sm->d0[j].upload(d0, nullptr));
     // fibre of every canonical row, and the per-fibre shift features
     std::vector<int32_t> fid((size_t)sys->N, 0);
     std::vector<double> sf((size_t)nf * (d + 1), 0.0);
@@ -1666,7 +1665,6 @@ extern "C" lsx_status lsx_sampler_create(lsx_plan* pl, lsx_state* st, int32_t p1
     LSX_TRY(sm->wt[j].alloc((size_t)std::max(nf, 1) * W));
   }
   LSX_TRY(sm->count.alloc(2));
-  LSX_TRY(sm->flag.alloc(maxnf));
   LSX_TRY(sm->mass.alloc((size_t)maxnf * W));
   LSX_TRY(sm->X.alloc((size_t)maxnf * W * (d + 3)));
   LSX_TRY(sm->z.alloc((size_t)maxnf * W));
@@ -1742,15 +1740,18 @@ lsx_status sampled_substep(lsx_sampler* sm, int layer, int half, const double* u
     z = sm->z.p;
   }
   LSX_HIP_TRY(launch_sample_weights(s, nf, W, sm->p[j], ustride, u, z, sm->eps, sm->wt[j].p));
-  LSX_HIP_TRY(launch_compact(s, nf, W, sm->wt[j].p, sm->flag.p, sm->tptr[j].p, sm->tilesF[j].p, sm->tilesC[j].p,
-                             sm->count.p + j));
+  const LayerDev& ld = pl->L[j];
+  LSX_HIP_TRY(launch_sampled_tiles(s, nf, W, kSampledNB, sm->wt[j].p, ld.ptr.p, sm->poff[j].p, sm->d0[j].p,
+                                   sm->cols[j].p, sm->ncols[j].p, sm->off[j].p, sm->tiles[j].p, sm->count.p + j));
   PassArgs a = canon_pass_args(pl, st, layer, half);
-  a.tiles = sm->tilesC[j].p;
+  a.tiles = sm->tiles[j].p;
   a.tcount = sm->count.p + j;
   a.wt = sm->wt[j].p;
-  LSX_HIP_TRY(launch_pass(s, pl->fmt, W, sm->ntiles[j], st->nb[j], st->ks[j], a));
-  LSX_HIP_TRY(launch_copy_tiles(s, sm->ntiles[j], sm->tilesC[j].p, sm->count.p + j, 16 * st->nb[j],
-                                canon_pos(pl, layer), W, st->buf[1], st->buf[0]));
+  a.cols = sm->cols[j].p;
+  a.ncols = sm->ncols[j].p;
+  LSX_HIP_TRY(launch_pass(s, pl->fmt, W, sm->ntiles[j], kSampledNB, st->ks[j], a));
+  LSX_HIP_TRY(launch_copy_cols(s, sm->ntiles[j], sm->tiles[j].p, sm->count.p + j, kSampledNB, canon_pos(pl, layer),
+                               W, sm->cols[j].p, sm->ncols[j].p, st->buf[1], st->buf[0]));
   return LSX_OK;
 }
 

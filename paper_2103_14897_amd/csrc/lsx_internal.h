@@ -77,6 +77,10 @@ struct PassArgs {
   const PassArgs* batch = nullptr;  // batched launches: per-system arguments, indexed by TileDesc::f
   const double* wt = nullptr;       // weighted passes: [fibre][W] increment weights
   const int32_t* tcount = nullptr;  // device tile count: workgroups at or past it exit
+  // column-gathered passes: column slot s of fibre f is state column cols[f][s] for
+  // s < ncols[f] (TileDesc::wb then counts blocks of 16 NB slots, not of columns)
+  const int32_t* cols = nullptr;
+  const int32_t* ncols = nullptr;
   int32_t W = 0;
 };
 
@@ -110,10 +114,13 @@ hipError_t launch_si_step(hipStream_t s, int64_t N, int W, double tau, const dou
 hipError_t launch_subset_weights(hipStream_t s, int nf, int W, int p, int ustride, const double* u, double* wt);
 hipError_t launch_sample_weights(hipStream_t s, int nf, int W, int p, int ustride, const double* u, const float* z,
                                  double eps, double* wt);
-hipError_t launch_compact(hipStream_t s, int nf, int W, const double* wt, int32_t* flag, const int32_t* tptr,
-                          const TileDesc* tiles, TileDesc* out, int32_t* count);
-hipError_t launch_copy_tiles(hipStream_t s, int ntiles, const TileDesc* tiles, const int32_t* count, int ncols,
-                             const int32_t* pos, int W, const double2* src, double2* dst);
+// column lists of the sampled fibres and their tiles (16 NB column slots per tile)
+hipError_t launch_sampled_tiles(hipStream_t s, int nf, int W, int NB, const double* wt, const int32_t* ptr,
+                                const int64_t* poff, const int32_t* d0, int32_t* cols, int32_t* ncols, int32_t* off,
+                                TileDesc* tiles, int32_t* count);
+hipError_t launch_copy_cols(hipStream_t s, int ntiles, const TileDesc* tiles, const int32_t* count, int NB,
+                            const int32_t* pos, int W, const int32_t* cols, const int32_t* ncols, const double2* src,
+                            double2* dst);
 hipError_t launch_fibre_incr(hipStream_t s, int nf, const int32_t* ptr, const int32_t* rows, int W,
                              const double2* X, const double2* Y, double* out);
 hipError_t launch_features(hipStream_t s, int nf, int W, int d, const double* sfeat, const double* mass,

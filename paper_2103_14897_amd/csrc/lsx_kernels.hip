@@ -311,6 +311,22 @@ __global__ __launch_bounds__(256) void k_phase_apply(int64_t N, int W, const dou
   }
 }
 
+// ---------------------------------------------------------------- tile columns
+// State column of this lane's slot in each of the tile's NB column blocks (slot
+// (wb NB + nb) 16 + lane % 16), and whether it exists.  Column-gathered passes look the
+// slot up in the fibre's column list.
+template <int NB>
+__device__ __forceinline__ void tile_cols(const PassArgs& a, const TileDesc& t, int li, int (&wc)[NB],
+                                          bool (&wok)[NB]) {
+  const int nc = a.cols ? a.ncols[t.f] : a.W;
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    const int sl = (t.wb * NB + nb) * 16 + li;
+    wok[nb] = sl < nc;
+    wc[nb] = a.cols ? (wok[nb] ? a.cols[(int64_t)t.f * a.W + sl] : 0) : sl;
+  }
+}
+
 // ---------------------------------------------------------------- fibre-pass epilogue
 // acc[nb][0/1][r]: this lane's part of the 16x16 output blocks, column lane%16 and
 // row 4*(lane/16)+r for the FP32-accumulating MFMAs, row 4*r+lane/16 for
@@ -319,10 +335,10 @@ __global__ __launch_bounds__(256) void k_phase_apply(int64_t N, int W, const dou
 // the output row (the phase sub-step that follows this pass, fused).
 template <int NB, int KS, bool MIX, bool ROWS_F64>
 __device__ __forceinline__ void pass_epilogue(const PassArgs& a, const TileDesc& t, double (&acc)[NB][2][4],
-                                              double* red) {
+                                              double* red, const int (&wc)[NB], const bool (&wok)[NB]) {
   const int lane = threadIdx.x & 63, kw = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int li = lane & 15, lk = lane >> 4;
-  const int r0 = t.r0, L = t.L, rb = t.rb, wb = t.wb;
+  const int lk = lane >> 4;
+  const int r0 = t.r0, L = t.L, rb = t.rb;
   const int W = a.W;
   if (KS > 1) {
 #pragma unroll
@@ -343,8 +359,8 @@ __device__ __forceinline__ void pass_epilogue(const PassArgs& a, const TileDesc&
     if (a.ph) ph = a.ph[a.ph_idx ? a.ph_idx[p] : p];
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
-      const int w = (wb * NB + nb) * 16 + li;
-      if (w >= W) continue;
+      const int w = wc[nb];
+      if (!wok[nb]) continue;
       double yr, yi;
       if (KS > 1) {
         yr = 0.0;
@@ -477,11 +493,7 @@ __global__ __launch_bounds__(64 * KS) void k_pass_f64(PassArgs a0) {
                      (int64_t)t.rb * nks * 64 + lane;
   int wc[NB];
   bool wok[NB];
-#pragma unroll
-  for (int nb = 0; nb < NB; ++nb) {
-    wc[nb] = (t.wb * NB + nb) * 16 + li;
-    wok[nb] = wc[nb] < a.W;
-  }
+  tile_cols<NB>(a, t, li, wc, wok);
   v4d k1[NB], k2[NB], k3[NB];
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) k1[nb] = k2[nb] = k3[nb] = (v4d){0.0, 0.0, 0.0, 0.0};
@@ -507,7 +519,7 @@ __global__ __launch_bounds__(64 * KS) void k_pass_f64(PassArgs a0) {
       acc[nb][0][r] = k1[nb][r] - k3[nb][r];
       acc[nb][1][r] = k1[nb][r] + k2[nb][r];
     }
-  pass_epilogue<NB, KS, false, true>(a, t, acc, red);
+  pass_epilogue<NB, KS, false, true>(a, t, acc, red, wc, wok);
 }
 
 // Mixed FP32: y = d .* x (FP64) + E x~ with E complex64, x~ = fp32(x), FP32 MFMA
@@ -528,11 +540,7 @@ __global__ __launch_bounds__(64 * KS) void k_pass_f32(PassArgs a0) {
                     (int64_t)t.rb * nks * 64 + lane;
   int wc[NB];
   bool wok[NB];
-#pragma unroll
-  for (int nb = 0; nb < NB; ++nb) {
-    wc[nb] = (t.wb * NB + nb) * 16 + li;
-    wok[nb] = wc[nb] < a.W;
-  }
+  tile_cols<NB>(a, t, li, wc, wok);
   v4f k1[NB], k2[NB], k3[NB];
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) k1[nb] = k2[nb] = k3[nb] = (v4f){0.f, 0.f, 0.f, 0.f};
@@ -557,7 +565,7 @@ __global__ __launch_bounds__(64 * KS) void k_pass_f32(PassArgs a0) {
       acc[nb][0][r] = (double)k1[nb][r] - (double)k3[nb][r];
       acc[nb][1][r] = (double)k1[nb][r] + (double)k2[nb][r];
     }
-  pass_epilogue<NB, KS, true, false>(a, t, acc, red);
+  pass_epilogue<NB, KS, true, false>(a, t, acc, red, wc, wok);
 }
 
 // Mixed BF16x3: E = E0+E1+E2 and x~ = x0+x1+x2 (bf16 terms); the six products E0x0,
@@ -643,11 +651,7 @@ __global__ __launch_bounds__(64 * KS) void k_pass_bf16x3(PassArgs a0) {
                    (int64_t)t.rb * nkc * 6 * 64 + lane;
   int wc[NB];
   bool wok[NB];
-#pragma unroll
-  for (int nb = 0; nb < NB; ++nb) {
-    wc[nb] = (t.wb * NB + nb) * 16 + li;
-    wok[nb] = wc[nb] < a.W;
-  }
+  tile_cols<NB>(a, t, li, wc, wok);
   v4f rr[NB], ii[NB], ri[NB], ir[NB];
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) rr[nb] = ii[nb] = ri[nb] = ir[nb] = (v4f){0.f, 0.f, 0.f, 0.f};
@@ -671,7 +675,7 @@ __global__ __launch_bounds__(64 * KS) void k_pass_bf16x3(PassArgs a0) {
       acc[nb][0][r] = (double)rr[nb][r] - (double)ii[nb][r];
       acc[nb][1][r] = (double)ri[nb][r] + (double)ir[nb][r];
     }
-  pass_epilogue<NB, KS, true, false>(a, t, acc, red);
+  pass_epilogue<NB, KS, true, false>(a, t, acc, red, wc, wok);
 }
 
 // ---------------------------------------------------------------- single-state fibre pass (W = 1)

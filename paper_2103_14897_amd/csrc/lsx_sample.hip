@@ -197,57 +197,91 @@ __global__ __launch_bounds__(256) void k_sample_weights(int nf, int W, int p, in
   for (int f = threadIdx.x; f < nf; f += blockDim.x) wt[(int64_t)f * W + w] = acc[f];
 }
 
-// flag[f] = 1 if any column gives fibre f a nonzero weight
-__global__ __launch_bounds__(256) void k_union_flags(int nf, int W, const double* wt, int32_t* flag) {
-  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+// Column list of every fibre: the columns (in increasing order) whose weight on it is
+// nonzero.  One wave per fibre compacts 64 columns at a time with a ballot.
+__global__ __launch_bounds__(256) void k_fibre_cols(int nf, int W, const double* wt, int32_t* cols, int32_t* ncols) {
+  const int f = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (f >= nf) return;
-  int any = 0;
-  for (int w = 0; w < W; ++w) any |= (wt[(int64_t)f * W + w] != 0.0);
-  flag[f] = any;
+  int base = 0;
+  for (int w0 = 0; w0 < W; w0 += 64) {
+    const int w = w0 + lane;
+    const bool on = w < W && wt[(int64_t)f * W + w] != 0.0;
+    const unsigned long long m = __ballot(on);
+    const int pos = __popcll(m & ((1ull << lane) - 1ull));
+    if (on) cols[(int64_t)f * W + base + pos] = w;
+    base += __popcll(m);
+  }
+  if (lane == 0) ncols[f] = base;
 }
 
-// Compaction of the flagged fibres' tiles (tiles listed fibre-major, fibre f owning
-// tiles tptr[f]..tptr[f+1]) into out, in fibre order; *count = number of tiles kept.
-// One workgroup of 1024 threads; thread t scans fibres [t*chunk, (t+1)*chunk).
-__global__ __launch_bounds__(1024) void k_compact_tiles(int nf, const int32_t* flag, const int32_t* tptr,
-                                                        const TileDesc* tiles, TileDesc* out, int32_t* count) {
+// Tile offsets of the sampled fibres: fibre f needs ceil(L_f / 16) row blocks times
+// ceil(ncols_f / (16 NB)) column-slot blocks; off = exclusive scan in fibre order.
+// One workgroup of 1024 threads; thread t scans fibres [t chunk, (t + 1) chunk).
+__global__ __launch_bounds__(1024) void k_scan_tiles(int nf, int NB, const int32_t* ptr, const int32_t* ncols,
+                                                     int32_t* off, int32_t* count) {
   __shared__ int32_t scan[1024];
   const int t = threadIdx.x;
   const int chunk = (nf + 1023) / 1024;
   const int f0 = min(nf, t * chunk), f1 = min(nf, f0 + chunk);
+  const int cw = 16 * NB;
   int mine = 0;
-  for (int f = f0; f < f1; ++f)
-    if (flag[f]) mine += tptr[f + 1] - tptr[f];
+  for (int f = f0; f < f1; ++f) mine += ((ptr[f + 1] - ptr[f] + 15) / 16) * ((ncols[f] + cw - 1) / cw);
   scan[t] = mine;
   __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {  // inclusive Hillis-Steele scan
-    const int v = t >= off ? scan[t - off] : 0;
+  for (int o = 1; o < 1024; o <<= 1) {  // inclusive Hillis-Steele scan
+    const int v = t >= o ? scan[t - o] : 0;
     __syncthreads();
     scan[t] += v;
     __syncthreads();
   }
   int pos = scan[t] - mine;
-  for (int f = f0; f < f1; ++f)
-    if (flag[f])
-      for (int k = tptr[f]; k < tptr[f + 1]; ++k) out[pos++] = tiles[k];
+  for (int f = f0; f < f1; ++f) {
+    off[f] = pos;
+    pos += ((ptr[f + 1] - ptr[f] + 15) / 16) * ((ncols[f] + cw - 1) / cw);
+  }
   if (t == 1023) *count = scan[1023];
 }
 
-// Copies the rows x columns block of every listed tile from src to dst (positions through
-// pos when set); tiles at or past *count are skipped.  256 threads per tile.
-__global__ __launch_bounds__(256) void k_copy_tiles(const TileDesc* tiles, const int32_t* count, int ncols,
-                                                    const int32_t* pos, int W, const double2* src, double2* dst) {
+// Tiles of fibre f = blockIdx.x at off[f]: (row block rb, column-slot block cb), rb major.
+__global__ __launch_bounds__(256) void k_emit_tiles(int NB, const int32_t* ptr, const int64_t* poff,
+                                                    const int32_t* d0, const int32_t* ncols, const int32_t* off,
+                                                    TileDesc* out) {
+  const int f = blockIdx.x;
+  const int r0 = ptr[f], L = ptr[f + 1] - r0;
+  const int cw = 16 * NB;
+  const int nc = (ncols[f] + cw - 1) / cw;
+  const int n = ((L + 15) / 16) * nc;
+  for (int k = threadIdx.x; k < n; k += blockDim.x) {
+    TileDesc t;
+    t.r0 = r0;
+    t.L = L;
+    t.rb = k / nc;
+    t.wb = k - t.rb * nc;
+    t.poff = poff ? poff[f] : 0;
+    t.f = f;
+    t.d0 = d0 ? d0[f] : r0;
+    out[off[f] + k] = t;
+  }
+}
+
+// Copies the (rows x gathered columns) block of every listed tile from src to dst (rows
+// through pos when set); tiles at or past *count are skipped.  256 threads per tile.
+__global__ __launch_bounds__(256) void k_copy_cols(const TileDesc* tiles, const int32_t* count, int NB,
+                                                   const int32_t* pos, int W, const int32_t* cols,
+                                                   const int32_t* ncols, const double2* src, double2* dst) {
   if ((int)blockIdx.x >= *count) return;
   const TileDesc t = tiles[blockIdx.x];
   const int rows = min(16, t.L - 16 * t.rb);
-  const int c0 = t.wb * ncols;
-  const int cols = min(ncols, W - c0);
-  for (int e = threadIdx.x; e < rows * ncols; e += blockDim.x) {
-    const int r = e / ncols, c = e - r * ncols;
-    if (c >= cols) continue;
+  const int cw = 16 * NB;
+  const int s0 = t.wb * cw, ns = min(cw, ncols[t.f] - s0);
+  for (int e = threadIdx.x; e < rows * cw; e += blockDim.x) {
+    const int r = e / cw, c = e - r * cw;
+    if (c >= ns) continue;
+    const int w = cols[(int64_t)t.f * W + s0 + c];
     const int p = t.r0 + 16 * t.rb + r;
     const int64_t row = pos ? pos[p] : p;
-    dst[row * W + c0 + c] = src[row * W + c0 + c];
+    dst[row * W + w] = src[row * W + w];
   }
 }
 
@@ -647,19 +681,25 @@ hipError_t launch_sample_weights(hipStream_t s, int nf, int W, int p, int ustrid
   return hipGetLastError();
 }
 
-hipError_t launch_compact(hipStream_t s, int nf, int W, const double* wt, int32_t* flag, const int32_t* tptr,
-                          const TileDesc* tiles, TileDesc* out, int32_t* count) {
-  hipLaunchKernelGGL(k_union_flags, dim3((nf + 255) / 256), dim3(256), 0, s, nf, W, wt, flag);
+hipError_t launch_sampled_tiles(hipStream_t s, int nf, int W, int NB, const double* wt, const int32_t* ptr,
+                                const int64_t* poff, const int32_t* d0, int32_t* cols, int32_t* ncols, int32_t* off,
+                                TileDesc* tiles, int32_t* count) {
+  if (nf == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fibre_cols, dim3((nf + 3) / 4), dim3(256), 0, s, nf, W, wt, cols, ncols);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_compact_tiles, dim3(1), dim3(1024), 0, s, nf, flag, tptr, tiles, out, count);
+  hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, s, nf, NB, ptr, ncols, off, count);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_emit_tiles, dim3(nf), dim3(256), 0, s, NB, ptr, poff, d0, ncols, off, tiles);
   return hipGetLastError();
 }
 
-hipError_t launch_copy_tiles(hipStream_t s, int ntiles, const TileDesc* tiles, const int32_t* count, int ncols,
-                             const int32_t* pos, int W, const double2* src, double2* dst) {
+hipError_t launch_copy_cols(hipStream_t s, int ntiles, const TileDesc* tiles, const int32_t* count, int NB,
+                            const int32_t* pos, int W, const int32_t* cols, const int32_t* ncols, const double2* src,
+                            double2* dst) {
   if (ntiles == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_copy_tiles, dim3(ntiles), dim3(256), 0, s, tiles, count, ncols, pos, W, src, dst);
+  hipLaunchKernelGGL(k_copy_cols, dim3(ntiles), dim3(256), 0, s, tiles, count, NB, pos, W, cols, ncols, src, dst);
   return hipGetLastError();
 }
 
