@@ -142,9 +142,20 @@ class SplitPlan:
             c = self.apply_phase(c, tau / 2)
         return self.apply_fibres(c, 1, tau / 2)
 
+    def yoshida4_step(self, c: np.ndarray, tau: float) -> np.ndarray:
+        """Fourth-order symmetric composition of three Strang steps (Yoshida's triple jump,
+        the higher-order splitting the paper refers to in App. A): S(g1 tau) S(g0 tau) S(g1 tau)
+        with g1 = 1 / (2 - 2^(1/3)) and g0 = 1 - 2 g1, so that 2 g1 + g0 = 1 and
+        2 g1^3 + g0^3 = 0.  Applied unmerged."""
+        g1 = 1.0 / (2.0 - 2.0 ** (1.0 / 3.0))
+        g0 = 1.0 - 2.0 * g1
+        for g in (g1, g0, g1):
+            c = self.strang_step(c, g * tau)
+        return c
+
     def evolve(self, c: np.ndarray, tau: float, nsteps: int, scheme: str = "strang",
                callback=None) -> np.ndarray:
-        step = self.strang_step if scheme == "strang" else self.lie_step
+        step = {"strang": self.strang_step, "lie": self.lie_step, "yoshida4": self.yoshida4_step}[scheme]
         for k in range(nsteps):
             c = step(c, tau)
             if callback is not None:

@@ -300,3 +300,41 @@ def test_rational_orders_and_mass():
         masses.append(observables.mass(c)[0])
     assert all(b <= a + 1e-15 for a, b in zip([observables.mass(c0)[0]] + masses, masses))
     assert masses[-1] < observables.mass(c0)[0] - 1e-6
+
+
+@pytest.mark.parametrize("kappa", [0.0, 1.0])
+def test_yoshida_fourth_order_vs_brute_force(kappa):
+    """The triple-jump composition of Strang steps (App. A: higher-order splittings) converges
+    at order 4 to exp(-i T H) of the full lifted matrix, and beats Strang at equal tau."""
+    spec = wl.chain_system(200.0)
+    sys = lifted_sys(spec)
+    plan = splitting.SplitPlan(sys, kappa)
+    c0 = wl.gaussian_state(spec, sys.mn, np.zeros((1, 1)), 2.0)
+    T = 1.0
+    exact = reference.exact_flow(sys, c0, T)
+    errs = []
+    for K in (32, 64, 128):  # asymptotic range: errors 2e-4 .. 4e-6
+        errs.append(np.linalg.norm(plan.evolve(c0, T / K, K, "yoshida4") - exact))
+    slopes = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert all(abs(s - 4.0) < 0.35 for s in slopes), (errs, slopes)
+    assert errs[-1] < 0.1 * np.linalg.norm(plan.evolve(c0, T / 128, 128, "strang") - exact)
+
+
+def test_yoshida_unitarity_and_reversibility():
+    """A composition of unitary flows is unitary; the symmetric triple jump is time-reversible."""
+    spec = wl.chain_system(971.0, pot1=ASYM1, pot2=ASYM2)
+    sys = lifted_sys(spec)
+    c0 = wl.random_state(sys.N, 3, seed=8)
+    for kappa in (0.0, 0.6):
+        plan = splitting.SplitPlan(sys, kappa)
+        c = plan.evolve(c0, 0.01, 30, "yoshida4")
+        assert np.abs(observables.mass(c) - observables.mass(c0)).max() < 1e-13 * 90
+        back = splitting.SplitPlan(sys, kappa).evolve(c, -0.01, 30, "yoshida4")
+        assert rel(back, c0) < 1e-12
+
+
+def test_yoshida_coefficients():
+    """2 g1 + g0 = 1 (consistency) and 2 g1^3 + g0^3 = 0 (third-order error term cancels)."""
+    g1 = 1.0 / (2.0 - 2.0 ** (1.0 / 3.0))
+    g0 = 1.0 - 2.0 * g1
+    assert abs(2 * g1 + g0 - 1.0) < 1e-15 and abs(2 * g1 ** 3 + g0 ** 3) < 1e-14
