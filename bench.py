@@ -370,6 +370,8 @@ def main():
                     choices=["chain", "twisted", "twisted1", "tiny", "batch", "learned", "si"],
                     help="chain: the metric's workload (default); the others are extra measurements")
     ap.add_argument("--kappa", type=float, default=0.0)
+    ap.add_argument("--scheme", default="strang", choices=["strang", "lie", "yoshida4", "strang_cn", "lie_be"],
+                    help="composition of the timed steps (the metric is quoted on strang)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -406,7 +408,7 @@ def main():
     finals = {}
     for path in args.paths.split(","):
         t0 = time.perf_counter()
-        P = lsx.Plan(S, w.tau, "strang", args.kappa, path, stream)
+        P = lsx.Plan(S, w.tau, args.scheme, args.kappa, path, stream)
         pre = time.perf_counter() - t0
         st = lsx.State(P, W)
         # accuracy run to T
@@ -499,7 +501,8 @@ def main():
                                 "twisted": "twisted_tri_pm2.5deg_Ec6500_W128_strang_tau5e-3",
                                 "twisted1": "twisted_tri_pm2.5deg_Ec6500_W1_strang_tau5e-3",
                                 "tiny": "chain1d_golden_Ec200_W1_strang_tau1e-2"}[args.workload],
-                   "N": N, "W": W, "fibres": [S.nfibres[1], S.nfibres[2]], "path": best, "kappa": args.kappa},
+                   "N": N, "W": W, "fibres": [S.nfibres[1], S.nfibres[2]], "path": best, "kappa": args.kappa,
+                   "scheme": args.scheme},
         "roofline": roof,
         "paths": res,
     }

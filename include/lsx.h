@@ -52,7 +52,8 @@ enum {
   LSX_LIE = 0,       /* exact fibre flows, Lie order F1 F2 (App. A)                       */
   LSX_STRANG = 1,    /* exact fibre flows, Strang F1(tau/2) F2(tau) F1(tau/2) (App. A)    */
   LSX_LIE_BE = 2,    /* backward Euler fibre solves, Lie order (Alg. 2, eqs. 4.3-4.4)      */
-  LSX_STRANG_CN = 3  /* Crank-Nicolson fibre solves, Strang order (eq. 4.6)              */
+  LSX_STRANG_CN = 3, /* Crank-Nicolson fibre solves, Strang order (eq. 4.6)              */
+  LSX_YOSHIDA4 = 4   /* exact flows, fourth order: Strang steps of g1 tau, g0 tau, g1 tau  */
 };
 enum { LSX_FP64 = 0, LSX_MIX_FP32 = 1, LSX_MIX_BF16X3 = 2 };
 enum {
@@ -127,6 +128,16 @@ lsx_status lsx_system_destroy(lsx_system* sys);
  * sub-step lengths the scheme needs:
  *   LSX_LIE, LSX_LIE_BE       : F1(tau), Phase(kappa tau), F2(tau)                      per step
  *   LSX_STRANG, LSX_STRANG_CN : F1(tau/2), Phase(kappa tau/2), F2(tau), Phase(kappa tau/2), F1(tau/2)
+ *   LSX_YOSHIDA4              : S(g1 tau) S(g0 tau) S(g1 tau) with S the Strang step,
+ *                               g1 = 1/(2 - 2^(1/3)), g0 = 1 - 2 g1 (the symmetric triple jump of
+ *                               Yoshida's higher-order splittings, which the paper points to in
+ *                               App. A); the adjacent F1 halves are merged.
+ * The sub-step lengths a plan holds ("slots", used by lsx_plan_propagator, lsx_fibre_pass,
+ * lsx_phase and lsx_sampler_increments):
+ *   Lie, BE-Lie     : layer 1 {0: tau}, layer 2 {0: tau}, phase {0: tau}
+ *   Strang, CN      : layer 1 {0: tau, 1: tau/2}, layer 2 {0: tau}, phase {0: tau, 1: tau/2}
+ *   Yoshida         : layer 1 {0: g1 tau, 1: g1 tau/2, 2: (g1+g0) tau/2},
+ *                     layer 2 {0: g1 tau, 2: g0 tau}, phase {0: g1 tau/2, 1: g0 tau/2}
  * with F(t) = f(H_j) per fibre and, per eigenvalue lambda, f = exp(-i t lambda) (exact
  * flows), 1/(1 + i t lambda) (backward Euler) or (1 - i t lambda/2)/(1 + i t lambda/2)
  * (Crank-Nicolson; for t = tau/2 this is (4I + i tau H)^{-1}(4I - i tau H) of eq. 4.6).
@@ -146,9 +157,10 @@ lsx_status lsx_plan_create(lsx_system* sys, double tau, int32_t scheme, double k
 
 /*
  * Copies one fibre propagator P(t) back to the host as a dense L*L complex matrix
- * (row-major, interleaved; L = fibre length), with t = tau (half = 0) or tau/2
- * (half = 1).  For mixed plans this is d + E as stored (E rounded to the plan's
- * precision).  LSX_E_INVALID if the plan holds no such propagator.  Synchronous.
+ * (row-major, interleaved; L = fibre length), with t the sub-step length of slot `half`
+ * (0: tau, 1: tau/2 for Lie/Strang; see lsx_plan_create).  For mixed plans this is d + E as
+ * stored (E rounded to the plan's precision).  LSX_E_INVALID if the plan holds no such
+ * propagator.  Synchronous.
  */
 lsx_status lsx_plan_propagator(const lsx_plan* plan, int32_t layer, int32_t half, int32_t fibre,
                                double* out, void* stream);
@@ -191,24 +203,27 @@ lsx_status lsx_state_destroy(lsx_state* st);
 /*
  * lsx_step -- advances the state by exactly nsteps * tau with the plan's scheme
  * (App. A compositions; with exact flows the Strang half-steps of consecutive steps inside
- * one call are merged, F1(tau/2) F1(tau/2) = F1(tau); Crank-Nicolson steps are applied
- * unmerged).  nsteps >= 0.  Stream-ordered.
+ * one call are merged, F1(tau/2) F1(tau/2) = F1(tau), and so are the adjacent F1 sub-steps
+ * of the Yoshida scheme; Crank-Nicolson steps are applied unmerged).  nsteps >= 0.
+ * Stream-ordered.
  */
 lsx_status lsx_step(lsx_plan* plan, lsx_state* st, int64_t nsteps, void* stream);
 
 /*
  * lsx_fibre_pass -- one layer sub-step on its own: c[rows_f] <- P_f(t) c[rows_f]
  * for every fibre f of `layer` (Alg. 2 steps 1/2 with exact fibre flows), with
- * t = tau (half = 0) or tau/2 (half = 1), applied `count` >= 0 times back to back
- * (one kernel launch each; count > 1 is used to time the pass).  Stream-ordered.
+ * t the length of slot `half` (0: tau, 1: tau/2 for Lie/Strang; see lsx_plan_create),
+ * applied `count` >= 0 times back to back (one kernel launch each; count > 1 is used to
+ * time the pass).  Stream-ordered.
  */
 lsx_status lsx_fibre_pass(lsx_plan* plan, lsx_state* st, int32_t layer, int32_t half, int32_t count,
                           void* stream);
 
 /*
  * lsx_phase -- kinetic sub-step c_i <- exp(-i kappa t |G1m+G2n|^2 / 2) c_i, with
- * t = tau (half = 0) or tau/2 (half = 1) and the plan's kappa (Alg. 3 step 1 with
- * kinetic share kappa).  A no-op when kappa = 0.  Stream-ordered.
+ * t the plan's phase slot `half` (0: tau, 1: tau/2 for Lie/Strang; see lsx_plan_create)
+ * and the plan's kappa (Alg. 3 step 1 with kinetic share kappa).  A no-op when kappa = 0.
+ * Stream-ordered.
  */
 lsx_status lsx_phase(lsx_plan* plan, lsx_state* st, int32_t half, void* stream);
 
@@ -325,7 +340,7 @@ lsx_status lsx_sampler_features(lsx_sampler* sm, int32_t layer, float* X, void* 
 
 /*
  * lsx_sampler_increments -- b device [W][nfibres] FP64: ||(P_f(t) - I) c_f||^2 per wavepacket
- *   and fibre of `layer`, t = tau (half 0) or tau/2 (half 1), from the plan's propagators.  The
+ *   and fibre of `layer`, t = the length of slot `half` (0: tau, 1: tau/2), from the plan's propagators.  The
  *   optimal proposal of a sub-step is q_f ~ sqrt(b_f); these are the network's training
  *   targets.  The state is not modified (the work array is).  Stream-ordered.
  */

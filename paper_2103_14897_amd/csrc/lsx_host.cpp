@@ -361,7 +361,7 @@ struct LayerDev {
   DBuf<int32_t> ptr, rows;
   DBuf<int32_t> nbr;
   DBuf<double2> v;  // stencil values (for the energy)
-  PropSet prop[2];  // [0] = tau, [1] = tau/2
+  PropSet prop[3];  // sub-step slots, times per scheme in scheme_times()
 };
 
 struct lsx_plan {
@@ -369,8 +369,8 @@ struct lsx_plan {
   double tau = 0.0, kappa = 0.0;
   int scheme = LSX_STRANG, precision = LSX_FP64, fmt = PF_F64;
   DBuf<double> K2;
-  DBuf<double2> diag;  // mixed formats: per fibre-row diagonal, [layer*2+half] blocks of N
-  DBuf<double2> phase[2];  // exp(-i kappa t |K|^2/2) for t = tau, tau/2
+  DBuf<double2> diag;  // mixed formats: per fibre-row diagonal, [layer*3+slot] blocks of N
+  DBuf<double2> phase[3];  // exp(-i kappa t |K|^2/2) for the scheme's phase times
   DBuf<int32_t> pos1;      // position of canonical index i in the layer-1 fibre order
   DBuf<double2> zero;      // 1 KiB of zeros (out-of-range operand loads of the passes)
   LayerDev L[2];
@@ -380,6 +380,32 @@ struct lsx_plan {
 // Sub-step flow of a scheme: 0 exact exponential, 1 backward Euler, 2 Crank-Nicolson.
 static int scheme_flow(int scheme) { return scheme == LSX_LIE_BE ? 1 : (scheme == LSX_STRANG_CN ? 2 : 0); }
 static bool scheme_strang(int scheme) { return scheme == LSX_STRANG || scheme == LSX_STRANG_CN; }
+
+// Yoshida's symmetric triple jump S4(tau) = S2(g1 tau) S2(g0 tau) S2(g1 tau) of Strang steps
+// S2, with 2 g1 + g0 = 1 and 2 g1^3 + g0^3 = 0 (fourth order).
+static const double kYoshidaG1 = 1.0 / (2.0 - std::cbrt(2.0));
+static const double kYoshidaG0 = 1.0 - 2.0 * kYoshidaG1;
+
+// Times of a scheme's propagator slots per layer and of its kinetic-phase tables (NaN: the
+// slot is not used).
+//  Lie, BE-Lie        : layer 1 {tau}, layer 2 {tau}, phase {tau}
+//  Strang, CN-Strang  : layer 1 {tau, tau/2}, layer 2 {tau}, phase {tau, tau/2}
+//  Yoshida (4th order): layer 1 {g1 tau, g1 tau/2, (g1+g0) tau/2}, layer 2 {g1 tau, -, g0 tau},
+//                       phase {g1 tau/2, g0 tau/2}
+struct SchemeTimes {
+  double t[2][3];
+  double ph[3];
+};
+static SchemeTimes scheme_times(int scheme, double tau) {
+  const double X = std::nan("");
+  if (scheme == LSX_YOSHIDA4) {
+    const double g1 = kYoshidaG1, g0 = kYoshidaG0;
+    return {{{g1 * tau, 0.5 * g1 * tau, 0.5 * (g1 + g0) * tau}, {g1 * tau, X, g0 * tau}},
+            {0.5 * g1 * tau, 0.5 * g0 * tau, X}};
+  }
+  if (scheme_strang(scheme)) return {{{tau, 0.5 * tau, X}, {tau, X, X}}, {tau, 0.5 * tau, X}};
+  return {{{tau, X, X}, {tau, X, X}}, {tau, X, X}};
+}
 
 static lsx_status precompute_layer(lsx_plan* pl, int layer, hipStream_t s) {
   lsx_system* sys = pl->sys;
@@ -484,17 +510,17 @@ static lsx_status precompute_layer(lsx_plan* pl, int layer, hipStream_t s) {
     ld.h_d0[f] = ft.ptr[uniq[ld.rep[f]]];
   }
   const int flow = scheme_flow(pl->scheme);
-  for (int h = 0; h < 2; ++h) {
+  const SchemeTimes times = scheme_times(pl->scheme, pl->tau);
+  for (int h = 0; h < 3; ++h) {
     PropSet& ps = ld.prop[h];
-    const bool need = (h == 0) || (layer == 1 && scheme_strang(pl->scheme));
-    if (!need) continue;
-    ps.t = (h == 0) ? pl->tau : 0.5 * pl->tau;
+    if (std::isnan(times.t[layer - 1][h])) continue;
+    ps.t = times.t[layer - 1][h];
     ps.h_off = ld.h_poff;
     LSX_TRY(ps.data.alloc(bytes));
     LSX_TRY(ps.off.upload(uoff, s));
     LSX_HIP_TRY(hipMemsetAsync(ps.data.p, 0, bytes, s));
     LSX_HIP_TRY(launch_eig_fn(s, lt, lam.p, ps.t, flow, gh.p));
-    double2* dg = pl->diag.p ? pl->diag.p + (size_t)((layer - 1) * 2 + h) * sys->N : nullptr;
+    double2* dg = pl->diag.p ? pl->diag.p + (size_t)((layer - 1) * 3 + h) * sys->N : nullptr;
     LSX_HIP_TRY(launch_form(s, pl->fmt, nu, maxL, d_fid.p, ld.ptr.p, VT.p, d_moff.p, d_ndim.p, d_emb.p, gh.p,
                             d_loff.p, ps.data.p, ps.off.p, dg));
     ps.present = true;
@@ -507,7 +533,8 @@ extern "C" lsx_status lsx_plan_create(lsx_system* sys, double tau, int32_t schem
                                       int32_t precision, void* stream, lsx_plan** out) {
   if (!sys || !out) return fail(LSX_E_INVALID, "null argument");
   if (!std::isfinite(tau) || tau == 0.0) return fail(LSX_E_INVALID, "tau must be finite and nonzero");
-  if (scheme != LSX_LIE && scheme != LSX_STRANG && scheme != LSX_LIE_BE && scheme != LSX_STRANG_CN)
+  if (scheme != LSX_LIE && scheme != LSX_STRANG && scheme != LSX_LIE_BE && scheme != LSX_STRANG_CN &&
+      scheme != LSX_YOSHIDA4)
     return fail(LSX_E_INVALID, "bad scheme");
   if (!(kappa >= 0.0 && kappa <= 1.0)) return fail(LSX_E_INVALID, "kappa must be in [0, 1]");
   if (precision != LSX_FP64 && precision != LSX_MIX_FP32 && precision != LSX_MIX_BF16X3)
@@ -528,7 +555,7 @@ extern "C" lsx_status lsx_plan_create(lsx_system* sys, double tau, int32_t schem
   lsx_status st = pl->K2.upload(sys->K2, s);
   if (st != LSX_OK) return cleanup(st);
   if (pl->fmt != PF_F64) {
-    st = pl->diag.alloc((size_t)4 * std::max<int64_t>(sys->N, 1));
+    st = pl->diag.alloc((size_t)6 * std::max<int64_t>(sys->N, 1));
     if (st != LSX_OK) return cleanup(st);
   }
   for (int j = 0; j < 2; ++j) {
@@ -556,8 +583,10 @@ extern "C" lsx_status lsx_plan_create(lsx_system* sys, double tau, int32_t schem
     if ((st = pl->zero.upload(std::vector<double2>(64, make_double2(0.0, 0.0)), s)) != LSX_OK) return cleanup(st);
   }
   if (kappa != 0.0) {
-    for (int h = 0; h < 2; ++h) {
-      const double t = (h == 0) ? tau : 0.5 * tau;
+    const SchemeTimes times = scheme_times(scheme, tau);
+    for (int h = 0; h < 3; ++h) {
+      const double t = times.ph[h];
+      if (std::isnan(t)) continue;
       if ((st = pl->phase[h].alloc(std::max<int64_t>(sys->N, 1))) != LSX_OK) return cleanup(st);
       if (sys->N > 0) {
         hipError_t e = launch_phase_table(s, sys->N, pl->K2.p, 0.5 * kappa * t, pl->phase[h].p);
@@ -576,7 +605,7 @@ extern "C" lsx_status lsx_plan_propagator(const lsx_plan* pl, int32_t layer, int
                                           double* out, void* stream) {
   if (!pl || !out) return fail(LSX_E_INVALID, "null argument");
   if (layer != 1 && layer != 2) return fail(LSX_E_INVALID, "layer must be 1 or 2");
-  if (half != 0 && half != 1) return fail(LSX_E_INVALID, "half must be 0 or 1");
+  if (half < 0 || half > 2) return fail(LSX_E_INVALID, "slot must be 0, 1 or 2");
   const LayerDev& ld = pl->L[layer - 1];
   if (fibre < 0 || fibre >= ld.nf) return fail(LSX_E_INVALID, "fibre out of range");
   const PropSet& ps = ld.prop[half];
@@ -589,7 +618,7 @@ extern "C" lsx_status lsx_plan_propagator(const lsx_plan* pl, int32_t layer, int
   std::vector<double2> dg;
   if (pl->fmt != PF_F64) {
     dg.resize(L);
-    const double2* src = pl->diag.p + (size_t)((layer - 1) * 2 + half) * pl->sys->N + ld.h_d0[fibre];
+    const double2* src = pl->diag.p + (size_t)((layer - 1) * 3 + half) * pl->sys->N + ld.h_d0[fibre];
     LSX_HIP_TRY(hipMemcpyAsync(dg.data(), src, L * sizeof(double2), hipMemcpyDeviceToHost, s));
   }
   LSX_HIP_TRY(hipStreamSynchronize(s));
@@ -766,7 +795,7 @@ static lsx_status choose_tiles(lsx_plan* pl, lsx_state* st) {
         a.ph_idx = nullptr;
         a.ph = nullptr;
         a.P = ld.prop[0].data.p;
-        a.diag = pl->diag.p ? pl->diag.p + (size_t)((layer - 1) * 2) * pl->sys->N : nullptr;
+        a.diag = pl->diag.p ? pl->diag.p + (size_t)((layer - 1) * 3) * pl->sys->N : nullptr;
         a.X = st->buf[0];
         a.Y = st->buf[1];
         a.zero = pl->zero.p;
@@ -908,7 +937,9 @@ struct Runner {
   lsx_status pass(int layer, int half, int next, int phase_half) {
     const LayerDev& ld = pl->L[layer - 1];
     const PropSet& ps = ld.prop[half];
-    if (!ps.present) return fail(LSX_E_INVALID, "plan holds no propagator for this layer/half");
+    if (!ps.present) return fail(LSX_E_INVALID, "plan holds no propagator for this layer/slot");
+    if (phase_half >= 0 && pl->kappa != 0.0 && !pl->phase[phase_half].p)
+      return fail(LSX_E_INVALID, "plan holds no phase table for this slot");
     const int outlay = (next == 0) ? 2 : next;
     PassArgs a;
     a.tiles = st->tiles[layer - 1].p;
@@ -917,7 +948,7 @@ struct Runner {
     a.ph_idx = (layer == 1) ? pl->L[0].rows.p : nullptr;
     a.ph = (phase_half >= 0 && pl->kappa != 0.0) ? pl->phase[phase_half].p : nullptr;
     a.P = ps.data.p;
-    a.diag = pl->diag.p ? pl->diag.p + (size_t)((layer - 1) * 2 + half) * pl->sys->N : nullptr;
+    a.diag = pl->diag.p ? pl->diag.p + (size_t)((layer - 1) * 3 + half) * pl->sys->N : nullptr;
     a.X = st->buf[cur];
     a.Y = st->buf[1 - cur];
     a.zero = pl->zero.p;
@@ -929,6 +960,7 @@ struct Runner {
   }
   lsx_status phase(int half) {
     if (pl->kappa == 0.0 || pl->sys->N == 0) return LSX_OK;
+    if (!pl->phase[half].p) return fail(LSX_E_INVALID, "plan holds no phase table for this slot");
     LSX_HIP_TRY(launch_phase_apply(s, pl->sys->N, st->W, pl->phase[half].p, st->buf[cur]));
     return LSX_OK;
   }
@@ -962,36 +994,70 @@ static lsx_status run_passes(lsx_plan* pl, lsx_state* st, hipStream_t s, Body bo
   return r.finish();
 }
 
+namespace {
+// One fibre pass of a step sequence: layer, propagator slot, layer of the following pass
+// (0: none, write canonical order) and the phase slot fused after it (-1: none).
+struct PassSpec {
+  int layer, half, next, phase_half;
+};
+
+// The passes of nsteps steps of a scheme as head, body (repeated reps times) and tail, with
+// the sub-steps of consecutive steps merged where the flows compose (App. A):
+//  Strang  : F1(t/2) [Ph F2(t) Ph F1(t)]^(n-1) Ph F2(t) Ph F1(t/2)           (Ph = phase(t/2))
+//  Lie     : [F1(t) Ph F2(t)]^n                                               (Ph = phase(t))
+//  CN      : [F1(t/2) Ph F2(t) Ph F1(t/2)]^n, unmerged (C(t/2)^2 != C(t), eq. 4.6)
+//  Yoshida : S2(g1 t) S2(g0 t) S2(g1 t) per step; inside a step the adjacent F1 halves merge into
+//            F1((g1+g0) t/2), between steps into F1(g1 t).  Slots as in scheme_times().
+// Every body has an even number of passes and returns to the layout it started from.
+void step_sequence(int scheme, int64_t nsteps, std::vector<PassSpec>& head, std::vector<PassSpec>& body,
+                   std::vector<PassSpec>& tail, int64_t& reps) {
+  head.clear();
+  body.clear();
+  tail.clear();
+  reps = 0;
+  if (scheme == LSX_STRANG) {
+    head = {{1, 1, 2, 1}};
+    body = {{2, 0, 1, 1}, {1, 0, 2, 1}};
+    tail = {{2, 0, 1, 1}, {1, 1, 0, -1}};
+    reps = nsteps - 1;
+  } else if (scheme == LSX_YOSHIDA4) {
+    const std::vector<PassSpec> inner = {{2, 0, 1, 0}, {1, 2, 2, 1}, {2, 2, 1, 1}, {1, 2, 2, 0}, {2, 0, 1, 0}};
+    head = {{1, 1, 2, 0}};
+    body = inner;
+    body.push_back({1, 0, 2, 0});
+    tail = inner;
+    tail.push_back({1, 1, 0, -1});
+    reps = nsteps - 1;
+  } else if (scheme == LSX_STRANG_CN) {
+    for (int64_t k = 0; k < nsteps; ++k) {
+      const bool last = (k + 1 == nsteps);
+      tail.push_back({1, 1, 2, 1});
+      tail.push_back({2, 0, 1, 1});
+      tail.push_back({1, 1, last ? 0 : 1, -1});
+    }
+  } else if (nsteps == 1) {  // Lie with exact or backward-Euler flows
+    tail = {{1, 0, 2, 0}, {2, 0, 0, -1}};
+  } else {
+    head = {{1, 0, 2, 0}, {2, 0, 1, -1}};
+    body = {{1, 0, 2, 0}, {2, 0, 1, -1}};
+    tail = {{1, 0, 2, 0}, {2, 0, 0, -1}};
+    reps = nsteps - 2;
+  }
+}
+}  // namespace
+
 extern "C" lsx_status lsx_step(lsx_plan* pl, lsx_state* st, int64_t nsteps, void* stream) {
   LSX_TRY(check_pair(pl, st));
   if (nsteps < 0) return fail(LSX_E_INVALID, "nsteps must be >= 0");
   if (nsteps == 0 || pl->sys->N == 0) return LSX_OK;
-  const bool lie = !scheme_strang(pl->scheme);
-  const bool cn = (pl->scheme == LSX_STRANG_CN);
+  std::vector<PassSpec> head, body, tail;
+  int64_t reps = 0;
+  step_sequence(pl->scheme, nsteps, head, body, tail, reps);
   return run_passes(pl, st, reinterpret_cast<hipStream_t>(stream), [&](Runner& r) -> lsx_status {
-    if (cn) {
-      // Crank-Nicolson factors do not compose (C(t/2)^2 != C(t)): no merging, eq. (4.6)
-      for (int64_t k = 0; k < nsteps; ++k) {
-        const bool last = (k + 1 == nsteps);
-        LSX_TRY(r.pass(1, 1, 2, 1));
-        LSX_TRY(r.pass(2, 0, 1, 1));
-        LSX_TRY(r.pass(1, 1, last ? 0 : 1, -1));
-      }
-    } else if (lie) {
-      // per step: F1(tau), Phase(kappa tau), F2(tau)
-      for (int64_t k = 0; k < nsteps; ++k) {
-        LSX_TRY(r.pass(1, 0, 2, 0));
-        LSX_TRY(r.pass(2, 0, k + 1 < nsteps ? 1 : 0, -1));
-      }
-    } else {
-      // F1(tau/2) [Phase, F2(tau), Phase, F1(tau)] ... [Phase, F2(tau), Phase, F1(tau/2)]
-      LSX_TRY(r.pass(1, 1, 2, 1));
-      for (int64_t k = 0; k < nsteps; ++k) {
-        const bool last = (k + 1 == nsteps);
-        LSX_TRY(r.pass(2, 0, 1, 1));
-        LSX_TRY(r.pass(1, last ? 1 : 0, last ? 0 : 2, last ? -1 : 1));
-      }
-    }
+    for (const PassSpec& p : head) LSX_TRY(r.pass(p.layer, p.half, p.next, p.phase_half));
+    for (int64_t k = 0; k < reps; ++k)
+      for (const PassSpec& p : body) LSX_TRY(r.pass(p.layer, p.half, p.next, p.phase_half));
+    for (const PassSpec& p : tail) LSX_TRY(r.pass(p.layer, p.half, p.next, p.phase_half));
     return LSX_OK;
   });
 }
@@ -1000,7 +1066,7 @@ extern "C" lsx_status lsx_fibre_pass(lsx_plan* pl, lsx_state* st, int32_t layer,
                                      void* stream) {
   LSX_TRY(check_pair(pl, st));
   if (layer != 1 && layer != 2) return fail(LSX_E_INVALID, "layer must be 1 or 2");
-  if (half != 0 && half != 1) return fail(LSX_E_INVALID, "half must be 0 or 1");
+  if (half < 0 || half > 2) return fail(LSX_E_INVALID, "slot must be 0, 1 or 2");
   if (count < 0) return fail(LSX_E_INVALID, "count must be >= 0");
   if (pl->sys->N == 0 || count == 0) return LSX_OK;
   return run_passes(pl, st, reinterpret_cast<hipStream_t>(stream), [&](Runner& r) -> lsx_status {
@@ -1011,7 +1077,7 @@ extern "C" lsx_status lsx_fibre_pass(lsx_plan* pl, lsx_state* st, int32_t layer,
 
 extern "C" lsx_status lsx_phase(lsx_plan* pl, lsx_state* st, int32_t half, void* stream) {
   LSX_TRY(check_pair(pl, st));
-  if (half != 0 && half != 1) return fail(LSX_E_INVALID, "half must be 0 or 1");
+  if (half < 0 || half > 2) return fail(LSX_E_INVALID, "slot must be 0, 1 or 2");
   Runner r{pl, st, reinterpret_cast<hipStream_t>(stream)};
   return r.phase(half);
 }
@@ -1051,9 +1117,6 @@ extern "C" lsx_status lsx_observables(lsx_plan* pl, lsx_state* st, uint32_t mask
 
 // ================================================================ batched systems
 namespace {
-struct PassSpec {
-  int layer, half, next, phase_half;
-};
 struct PatternKey {
   int layer, half, inlay, outlay, phase_half, cur;
   bool operator<(const PatternKey& o) const {
@@ -1116,7 +1179,7 @@ static lsx_status batch_args(lsx_batch* b, const PatternKey& k, const PassArgs**
       a.ph_idx = (k.layer == 1) ? pl->L[0].rows.p : nullptr;
       a.ph = (k.phase_half >= 0 && pl->kappa != 0.0) ? pl->phase[k.phase_half].p : nullptr;
       a.P = ps.data.p;
-      a.diag = pl->diag.p ? pl->diag.p + (size_t)((k.layer - 1) * 2 + k.half) * pl->sys->N : nullptr;
+      a.diag = pl->diag.p ? pl->diag.p + (size_t)((k.layer - 1) * 3 + k.half) * pl->sys->N : nullptr;
       a.X = st->buf[k.cur];
       a.Y = st->buf[1 - k.cur];
       a.zero = pl->zero.p;
@@ -1321,28 +1384,7 @@ extern "C" lsx_status lsx_batch_step(lsx_batch* b, int64_t nsteps, void* stream)
     }
   std::vector<PassSpec> head, body, tail;
   int64_t reps = 0;
-  if (b->scheme == LSX_STRANG) {
-    head = {{1, 1, 2, 1}};
-    body = {{2, 0, 1, 1}, {1, 0, 2, 1}};
-    tail = {{2, 0, 1, 1}, {1, 1, 0, -1}};
-    reps = nsteps - 1;
-  } else if (b->scheme == LSX_STRANG_CN) {
-    for (int64_t k = 0; k < nsteps; ++k) {
-      const bool last = (k + 1 == nsteps);
-      tail.push_back({1, 1, 2, 1});
-      tail.push_back({2, 0, 1, 1});
-      tail.push_back({1, 1, last ? 0 : 1, -1});
-    }
-  } else {  // Lie with exact or backward-Euler flows
-    if (nsteps == 1) {
-      tail = {{1, 0, 2, 0}, {2, 0, 0, -1}};
-    } else {
-      head = {{1, 0, 2, 0}, {2, 0, 1, -1}};
-      body = {{1, 0, 2, 0}, {2, 0, 1, -1}};
-      tail = {{1, 0, 2, 0}, {2, 0, 0, -1}};
-      reps = nsteps - 2;
-    }
-  }
+  step_sequence(b->scheme, nsteps, head, body, tail, reps);
   int cur = 0, lay = 2;
   for (const PassSpec& p : head) LSX_TRY(batch_pass(b, s, p, cur, lay));
   if (reps > 0) {
@@ -1701,7 +1743,7 @@ PassArgs canon_pass_args(const lsx_plan* pl, const lsx_state* st, int layer, int
   a.in_pos = canon_pos(pl, layer);
   a.out_pos = canon_pos(pl, layer);
   a.P = ld.prop[half].data.p;
-  a.diag = pl->diag.p ? pl->diag.p + (size_t)((layer - 1) * 2 + half) * pl->sys->N : nullptr;
+  a.diag = pl->diag.p ? pl->diag.p + (size_t)((layer - 1) * 3 + half) * pl->sys->N : nullptr;
   a.X = st->buf[0];
   a.Y = st->buf[1];
   a.zero = pl->zero.p;
@@ -1757,6 +1799,7 @@ lsx_status sampled_substep(lsx_sampler* sm, int layer, int half, const double* u
 
 lsx_status phase_canon(lsx_plan* pl, lsx_state* st, int half, hipStream_t s) {
   if (pl->kappa == 0.0 || pl->sys->N == 0) return LSX_OK;
+  if (!pl->phase[half].p) return fail(LSX_E_INVALID, "plan holds no phase table for this slot");
   LSX_HIP_TRY(launch_phase_apply(s, pl->sys->N, st->W, pl->phase[half].p, st->buf[0]));
   return LSX_OK;
 }
@@ -1806,6 +1849,7 @@ extern "C" lsx_status lsx_ss_step(lsx_sampler* sm, const double* u, int64_t nste
   if (nsteps == 0 || sm->pl->sys->N == 0) return LSX_OK;
   if (!u && (sm->p[0] > 0 || sm->p[1] > 0)) return fail(LSX_E_INVALID, "null uniforms");
   lsx_plan* pl = sm->pl;
+  if (pl->scheme == LSX_YOSHIDA4) return fail(LSX_E_INVALID, "stochastic steps take Lie or Strang schemes");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const bool strang = scheme_strang(pl->scheme);
   // (layer, propagator half, phase half after it or -1)
@@ -1857,7 +1901,7 @@ extern "C" lsx_status lsx_sampler_increments(lsx_sampler* sm, int32_t layer, int
                                              void* stream) {
   if (!sm || !b) return fail(LSX_E_INVALID, "null argument");
   if (layer != 1 && layer != 2) return fail(LSX_E_INVALID, "layer must be 1 or 2");
-  if (half != 0 && half != 1) return fail(LSX_E_INVALID, "half must be 0 or 1");
+  if (half < 0 || half > 2) return fail(LSX_E_INVALID, "slot must be 0, 1 or 2");
   lsx_plan* pl = sm->pl;
   lsx_state* st = sm->st;
   const LayerDev& ld = pl->L[layer - 1];

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liblsx.so")
 LSX_OK, LSX_E_INVALID, LSX_E_NOT_HERMITIAN, LSX_E_OOM, LSX_E_HIP, LSX_E_EIG, LSX_E_NONFINITE, LSX_E_STATE = (
     0, -1, -2, -3, -4, -5, -6, -7)
 CUTOFF = {"ball": 0, "product": 1}
-SCHEME = {"lie": 0, "strang": 1, "lie_be": 2, "strang_cn": 3}
+SCHEME = {"lie": 0, "strang": 1, "lie_be": 2, "strang_cn": 3, "yoshida4": 4}
 PRECISION = {"fp64": 0, "mix_fp32": 1, "mix_bf16x3": 2}
 OBS_MASS, OBS_ENERGY, OBS_FIBRE_MASS_1, OBS_FIBRE_MASS_2 = 1, 2, 4, 8
 
