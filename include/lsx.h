@@ -191,8 +191,9 @@ lsx_status lsx_state_device_ptr(const lsx_state* st, void** dev_ptr);
 
 /*
  * Tile shape chosen for the fibre passes of `layer` (1 or 2) of this state: each
- * workgroup covers 16 output rows x 16*nb columns with ks waves splitting the fibre
- * length.  At creation every candidate shape is timed on the state's own size
+ * workgroup covers 16*nb columns and either 16 output rows with ks > 0 waves splitting the
+ * fibre length, or (ks < 0, mixed FP32) -ks consecutive 16-row blocks, one per wave, that
+ * share the state operand staged once per workgroup in LDS.  At creation every candidate shape is timed on the state's own size
  * (LSX_AUTOTUNE=0 disables, LSX_NB / LSX_KS force a shape); pass_us is the measured
  * time of one pass with the chosen shape (0 if nothing was timed).  Outputs may be NULL.
  */

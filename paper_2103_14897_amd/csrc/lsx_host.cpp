@@ -695,7 +695,9 @@ static int env_int(const char* name, int dflt);
 // XCD has its own L2, so whole fibres are assigned to XCDs (longest first, to the
 // least-loaded XCD) and the XCD queues are interleaved; every queue lists its largest
 // tiles first.  Shorter queues are padded with empty tiles (f = -1).
-static void build_tiles(const lsx_plan* pl, int layer, int W, int nb, int wb0, int wb1, std::vector<TileDesc>& out) {
+// ms > 1: tiles of the row-split kernels, rb counts groups of ms 16-row blocks.
+static void build_tiles(const lsx_plan* pl, int layer, int W, int nb, int wb0, int wb1, std::vector<TileDesc>& out,
+                        int ms = 1) {
   const LayerDev& ld = pl->L[layer - 1];
   const int wt = wb1 - wb0;
   (void)W;
@@ -711,7 +713,7 @@ static void build_tiles(const lsx_plan* pl, int layer, int W, int nb, int wb0, i
   std::vector<std::vector<TileDesc>> bins(NX);
   for (int f : order) {
     const int L = ld.h_ptr[f + 1] - ld.h_ptr[f];
-    const int nrb = (L + 15) / 16;
+    const int nrb = ((L + 15) / 16 + ms - 1) / ms;
     int x = 0;
     for (int y = 1; y < NX; ++y)
       if (count[y] < count[x] || (count[y] == count[x] && load[y] < load[x])) x = y;
@@ -751,6 +753,8 @@ static int env_int(const char* name, int dflt) {
 // fastest one per layer is kept.
 static lsx_status choose_tiles(lsx_plan* pl, lsx_state* st) {
   const int W = st->W;
+  // ks > 0: ks waves split the fibre length; ks < 0: -ks waves take consecutive row blocks
+  // and share the LDS-staged state operand (mixed FP32 and BF16x3 paths, BF16x3 with nb <= 2)
   struct Shape {
     int nb, ks;
   };
@@ -762,9 +766,16 @@ static lsx_status choose_tiles(lsx_plan* pl, lsx_state* st) {
     for (int nb : {1, 2, 4})
       for (int k : {1, 2, 4})
         if (16 * nb <= round_up(W, 16) && !(nb == 4 && k == 4)) cands.push_back({nb, k});
+    if (pl->fmt == PF_F32 || pl->fmt == PF_BF16X3)
+      for (int nb : {1, 2, 4})
+        for (int m : {2, 4})
+          if (16 * nb <= round_up(W, 16) && !(pl->fmt == PF_BF16X3 && nb == 4)) cands.push_back({nb, -m});
   }
-  if (fnb > 0 || fks > 0) {
-    const Shape f{(fnb == 1 || fnb == 2 || fnb == 4) ? fnb : 1, (fks == 1 || fks == 2 || fks == 4) ? fks : 2};
+  if (fnb > 0 || fks != 0) {
+    const bool rowsplit = fks < 0 && W > 1 && pl->fmt != PF_F64 && (fks == -2 || fks == -4) &&
+                          !(pl->fmt == PF_BF16X3 && fnb == 4);
+    const Shape f{(fnb == 1 || fnb == 2 || fnb == 4) ? fnb : 1,
+                  rowsplit ? fks : ((fks == 1 || fks == 2 || fks == 4) ? fks : 2)};
     cands.assign(1, f);
   } else if (env_int("LSX_AUTOTUNE", 1) == 0 || pl->sys->N == 0) {
     cands.assign(1, Shape{1, W == 1 ? 4 : 2});
@@ -781,7 +792,7 @@ static lsx_status choose_tiles(lsx_plan* pl, lsx_state* st) {
     for (const Shape& c : cands) {
       std::vector<TileDesc> t;
       const int wt = (W == 1) ? 1 : (W + 16 * c.nb - 1) / (16 * c.nb);
-      build_tiles(pl, layer, W, c.nb, 0, wt, t);
+      build_tiles(pl, layer, W, c.nb, 0, wt, t, c.ks < 0 ? -c.ks : 1);
       DBuf<TileDesc> d;
       if ((err = d.upload(t, nullptr)) != LSX_OK) break;
       float ms = 0.f;
@@ -1791,7 +1802,8 @@ lsx_status sampled_substep(lsx_sampler* sm, int layer, int half, const double* u
   a.wt = sm->wt[j].p;
   a.cols = sm->cols[j].p;
   a.ncols = sm->ncols[j].p;
-  LSX_HIP_TRY(launch_pass(s, pl->fmt, W, sm->ntiles[j], kSampledNB, st->ks[j], a));
+  // sampled tiles are per row block: a fibre-length split, never the row-split kernel
+  LSX_HIP_TRY(launch_pass(s, pl->fmt, W, sm->ntiles[j], kSampledNB, st->ks[j] > 0 ? st->ks[j] : 2, a));
   LSX_HIP_TRY(launch_copy_cols(s, sm->ntiles[j], sm->tiles[j].p, sm->count.p + j, kSampledNB, canon_pos(pl, layer),
                                W, sm->cols[j].p, sm->ncols[j].p, st->buf[1], st->buf[0]));
   return LSX_OK;

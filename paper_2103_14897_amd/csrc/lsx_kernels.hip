@@ -568,6 +568,124 @@ __global__ __launch_bounds__(64 * KS) void k_pass_f32(PassArgs a0) {
   pass_epilogue<NB, KS, true, false>(a, t, acc, red, wc, wok);
 }
 
+// ---------------------------------------------------------------- row-split passes, LDS-staged state
+// Workgroup = MS waves on MS consecutive 16-row blocks of one fibre (tile rb counts groups
+// of MS blocks) and the same 16 NB columns.  The state operand of every 16-row chunk of
+// the fibre is read from memory once per workgroup, converted once (FP32 and the 3M sums
+// x_r, x_i - x_r, x_r + x_i) into double-buffered LDS and read there by all MS waves, so
+// each state row is fetched once per row-block group instead of once per row block.  Each
+// wave streams its own propagator rows, one chunk ahead in registers.  No cross-wave
+// reduction: every wave owns its output rows.  Needs MS <= 4 NB.
+template <int NB, int MS>
+struct StageMap {
+  static constexpr int CW = 16 * NB;           // columns of a chunk
+  static constexpr int PER = 16 * CW / (64 * MS);  // elements per thread per chunk
+  static constexpr int RSTEP = 64 * MS / CW;   // chunk rows between a thread's elements
+};
+
+template <int PER, int RSTEP, bool GATHER>
+__device__ __forceinline__ void stage_load_f32(double2 (&v)[PER], const PassArgs& a, int ch, int r0, int L, int w,
+                                               bool wok, int rr0) {
+  const double2* zx = reinterpret_cast<const double2*>(a.zero);
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int k = 16 * ch + rr0 + j * RSTEP;
+    const bool ok = wok && k < L;
+    const int64_t row = xrow<GATHER>(a, r0 + (ok ? k : 0));
+    v[j] = *(ok ? a.X + row * a.W + w : zx);
+  }
+}
+
+template <int NB, int MS, bool GATHER>
+__global__ __launch_bounds__(64 * MS) void k_pass_f32m(PassArgs a) {
+  using SM = StageMap<NB, MS>;
+  __shared__ float4 xs[2][16][SM::CW];
+  if (a.tcount && (int)blockIdx.x >= *a.tcount) return;
+  const TileDesc t0 = a.tiles[blockIdx.x];
+  if (t0.f < 0) return;
+  const int r0 = t0.r0, L = t0.L;
+  const int nks = ((L + 15) & ~15) >> 2;
+  const int nch = nks >> 2;
+  const int lane = threadIdx.x & 63, kw = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int li = lane & 15, lk = lane >> 4;
+  TileDesc t = t0;
+  t.rb = t0.rb * MS + kw;
+  const bool act = t.rb < ((L + 15) >> 4);
+  const float2* zp = reinterpret_cast<const float2*>(a.zero);
+  const float2* P = reinterpret_cast<const float2*>(reinterpret_cast<const char*>(a.P) + t.poff) +
+                    (int64_t)(act ? t.rb : 0) * nks * 64 + lane;
+  int wc[NB];
+  bool wok[NB];
+  tile_cols<NB>(a, t, li, wc, wok);
+  // this thread's staging slot: column c (fixed), rows rr0 + j RSTEP of each chunk
+  const int c = threadIdx.x % SM::CW, rr0 = threadIdx.x / SM::CW;
+  int sw;
+  bool sok;
+  {
+    const int nc = a.cols ? a.ncols[t.f] : a.W;
+    const int sl = t.wb * SM::CW + c;
+    sok = sl < nc;
+    sw = a.cols ? (sok ? a.cols[(int64_t)t.f * a.W + sl] : 0) : sl;
+  }
+  v4f k1[NB], k2[NB], k3[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) k1[nb] = k2[nb] = k3[nb] = (v4f){0.f, 0.f, 0.f, 0.f};
+  double2 sv[SM::PER];
+  float2 Ac[4], An[4];
+  stage_load_f32<SM::PER, SM::RSTEP, GATHER>(sv, a, 0, r0, L, sw, sok, rr0);
+#pragma unroll
+  for (int u = 0; u < 4; ++u) Ac[u] = act ? P[u * 64] : *zp;
+#pragma unroll
+  for (int j = 0; j < SM::PER; ++j) {
+    const float xr = (float)sv[j].x, xi = (float)sv[j].y;
+    xs[0][rr0 + j * SM::RSTEP][c] = make_float4(xr, xi - xr, xr + xi, 0.f);
+  }
+  __syncthreads();
+  for (int ch = 0; ch < nch; ++ch) {
+    const int buf = ch & 1;
+    const bool more = ch + 1 < nch;
+    if (more) {
+      stage_load_f32<SM::PER, SM::RSTEP, GATHER>(sv, a, ch + 1, r0, L, sw, sok, rr0);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) An[u] = act ? P[(int64_t)(4 * (ch + 1) + u) * 64] : *zp;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    if (act) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const float ps = Ac[u].x + Ac[u].y;
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          const float4 b = xs[buf][4 * u + lk][nb * 16 + li];
+          k1[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ps, b.x, k1[nb], 0, 0, 0);
+          k2[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(Ac[u].x, b.y, k2[nb], 0, 0, 0);
+          k3[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(Ac[u].y, b.z, k3[nb], 0, 0, 0);
+        }
+      }
+    }
+    if (more) {
+#pragma unroll
+      for (int j = 0; j < SM::PER; ++j) {
+        const float xr = (float)sv[j].x, xi = (float)sv[j].y;
+        xs[buf ^ 1][rr0 + j * SM::RSTEP][c] = make_float4(xr, xi - xr, xr + xi, 0.f);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) Ac[u] = An[u];
+    }
+    __syncthreads();
+  }
+  if (!act) return;
+  double acc[NB][2][4];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      acc[nb][0][r] = (double)k1[nb][r] - (double)k3[nb][r];
+      acc[nb][1][r] = (double)k1[nb][r] + (double)k2[nb][r];
+    }
+  pass_epilogue<NB, 1, true, false>(a, t, acc, nullptr, wc, wok);
+}
+
 // Mixed BF16x3: E = E0+E1+E2 and x~ = x0+x1+x2 (bf16 terms); the six products E0x0,
 // E0x1, E1x0, E0x2, E1x1, E2x0 on v_mfma_f32_16x16x32_bf16 with FP32 accumulation, plus
 // the FP64 diagonal term.  A k-step here is a chunk of 32 fibre positions.  Four
@@ -676,6 +794,128 @@ __global__ __launch_bounds__(64 * KS) void k_pass_bf16x3(PassArgs a0) {
       acc[nb][1][r] = (double)ri[nb][r] + (double)ir[nb][r];
     }
   pass_epilogue<NB, KS, true, false>(a, t, acc, red, wc, wok);
+}
+
+// Row-split BF16x3 pass: as k_pass_f32m, with 32-row chunks.  The staging threads split each
+// state value once (x~ = fp32(x) into three bf16 terms, real and imaginary parts) into six
+// LDS planes stored column-major (a lane's 8 consecutive k values are one 16-byte read);
+// every wave multiplies its own propagator rows (six bf16 planes, one chunk ahead in
+// registers) with the shared planes.  Needs MS <= 8 NB.
+template <int NB>
+struct StageBF {
+  static constexpr int CW = 16 * NB;
+  static constexpr int KP = 40;  // padded k stride of a column (32 used)
+};
+
+template <int NB, int MS, bool GATHER>
+__global__ __launch_bounds__(64 * MS) void k_pass_bf16m(PassArgs a) {
+  constexpr int CW = StageBF<NB>::CW, KP = StageBF<NB>::KP;
+  constexpr int PER = 32 * CW / (64 * MS), RSTEP = 64 * MS / CW;
+  __shared__ __attribute__((aligned(16))) unsigned short xb[2][6][CW][KP];
+  if (a.tcount && (int)blockIdx.x >= *a.tcount) return;
+  const TileDesc t0 = a.tiles[blockIdx.x];
+  if (t0.f < 0) return;
+  const int r0 = t0.r0, L = t0.L;
+  const int nkc = ((L + 31) & ~31) >> 5;
+  const int lane = threadIdx.x & 63, kw = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int li = lane & 15, lk = lane >> 4;
+  TileDesc t = t0;
+  t.rb = t0.rb * MS + kw;
+  const bool act = t.rb < ((L + 15) >> 4);
+  const v8u16* zp = reinterpret_cast<const v8u16*>(a.zero);
+  const v8u16* P = reinterpret_cast<const v8u16*>(reinterpret_cast<const char*>(a.P) + t.poff) +
+                   (int64_t)(act ? t.rb : 0) * nkc * 6 * 64 + lane;
+  int wc[NB];
+  bool wok[NB];
+  tile_cols<NB>(a, t, li, wc, wok);
+  const int c = threadIdx.x % CW, rr0 = threadIdx.x / CW;
+  int sw;
+  bool sok;
+  {
+    const int nc = a.cols ? a.ncols[t.f] : a.W;
+    const int sl = t.wb * CW + c;
+    sok = sl < nc;
+    sw = a.cols ? (sok ? a.cols[(int64_t)t.f * a.W + sl] : 0) : sl;
+  }
+  const double2* zx = reinterpret_cast<const double2*>(a.zero);
+  v4f rr[NB], ii[NB], ri[NB], ir[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) rr[nb] = ii[nb] = ri[nb] = ir[nb] = (v4f){0.f, 0.f, 0.f, 0.f};
+  double2 sv[PER];
+  v8u16 Ac[6], An[6];
+  auto load_state = [&](int kc) {
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int k = 32 * kc + rr0 + j * RSTEP;
+      const bool ok = sok && k < L;
+      const int64_t row = xrow<GATHER>(a, r0 + (ok ? k : 0));
+      sv[j] = *(ok ? a.X + row * a.W + sw : zx);
+    }
+  };
+  auto store_state = [&](int buf) {
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      unsigned short q0, q1, q2, q3, q4, q5;
+      split3f((float)sv[j].x, q0, q1, q2);
+      split3f((float)sv[j].y, q3, q4, q5);
+      const int k = rr0 + j * RSTEP;
+      xb[buf][0][c][k] = q0;
+      xb[buf][1][c][k] = q1;
+      xb[buf][2][c][k] = q2;
+      xb[buf][3][c][k] = q3;
+      xb[buf][4][c][k] = q4;
+      xb[buf][5][c][k] = q5;
+    }
+  };
+  load_state(0);
+#pragma unroll
+  for (int pl = 0; pl < 6; ++pl) Ac[pl] = act ? P[pl * 64] : *zp;
+  store_state(0);
+  __syncthreads();
+  for (int kc = 0; kc < nkc; ++kc) {
+    const int buf = kc & 1;
+    const bool more = kc + 1 < nkc;
+    if (more) {
+      load_state(kc + 1);
+#pragma unroll
+      for (int pl = 0; pl < 6; ++pl) An[pl] = act ? P[((int64_t)(kc + 1) * 6 + pl) * 64] : *zp;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    if (act) {
+      const v8bf er0 = as_bf(Ac[0]), ei0 = as_bf(Ac[1]), er1 = as_bf(Ac[2]);
+      const v8bf ei1 = as_bf(Ac[3]), er2 = as_bf(Ac[4]), ei2 = as_bf(Ac[5]);
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const int col = nb * 16 + li;
+        const v8bf Xr0 = as_bf(*reinterpret_cast<const v8u16*>(&xb[buf][0][col][8 * lk]));
+        const v8bf Xr1 = as_bf(*reinterpret_cast<const v8u16*>(&xb[buf][1][col][8 * lk]));
+        const v8bf Xr2 = as_bf(*reinterpret_cast<const v8u16*>(&xb[buf][2][col][8 * lk]));
+        const v8bf Xi0 = as_bf(*reinterpret_cast<const v8u16*>(&xb[buf][3][col][8 * lk]));
+        const v8bf Xi1 = as_bf(*reinterpret_cast<const v8u16*>(&xb[buf][4][col][8 * lk]));
+        const v8bf Xi2 = as_bf(*reinterpret_cast<const v8u16*>(&xb[buf][5][col][8 * lk]));
+        rr[nb] = mma3(rr[nb], er0, er1, er2, Xr0, Xr1, Xr2);
+        ii[nb] = mma3(ii[nb], ei0, ei1, ei2, Xi0, Xi1, Xi2);
+        ri[nb] = mma3(ri[nb], er0, er1, er2, Xi0, Xi1, Xi2);
+        ir[nb] = mma3(ir[nb], ei0, ei1, ei2, Xr0, Xr1, Xr2);
+      }
+    }
+    if (more) {
+      store_state(buf ^ 1);
+#pragma unroll
+      for (int pl = 0; pl < 6; ++pl) Ac[pl] = An[pl];
+    }
+    __syncthreads();
+  }
+  if (!act) return;
+  double acc[NB][2][4];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      acc[nb][0][r] = (double)rr[nb][r] - (double)ii[nb][r];
+      acc[nb][1][r] = (double)ri[nb][r] + (double)ir[nb][r];
+    }
+  pass_epilogue<NB, 1, true, false>(a, t, acc, nullptr, wc, wok);
 }
 
 // ---------------------------------------------------------------- single-state fibre pass (W = 1)
@@ -987,6 +1227,41 @@ hipError_t launch_pass(hipStream_t s, int fmt, int W, int ntiles, int nb, int ks
       case 2: return launch_gemv<2, false>(s, fmt, ntiles, a);
       default: return launch_gemv<4, false>(s, fmt, ntiles, a);
     }
+  }
+  if (ksplit < 0) {
+    if (batched || fmt == PF_F64) return hipErrorInvalidValue;
+    if (fmt == PF_BF16X3) {
+#define LSX_ROWSPLIT_BF(NB_, MS_)                                                                       \
+  if (nb == NB_ && -ksplit == MS_) {                                                                    \
+    if (gather)                                                                                         \
+      hipLaunchKernelGGL((k_pass_bf16m<NB_, MS_, true>), dim3(ntiles), dim3(64 * MS_), 0, s, a);        \
+    else                                                                                                \
+      hipLaunchKernelGGL((k_pass_bf16m<NB_, MS_, false>), dim3(ntiles), dim3(64 * MS_), 0, s, a);       \
+    return hipGetLastError();                                                                           \
+  }
+      LSX_ROWSPLIT_BF(1, 2)
+      LSX_ROWSPLIT_BF(1, 4)
+      LSX_ROWSPLIT_BF(2, 2)
+      LSX_ROWSPLIT_BF(2, 4)
+#undef LSX_ROWSPLIT_BF
+      return hipErrorInvalidValue;
+    }
+#define LSX_ROWSPLIT_CASE(NB_, MS_)                                                                      \
+  if (nb == NB_ && -ksplit == MS_) {                                                                    \
+    if (gather)                                                                                         \
+      hipLaunchKernelGGL((k_pass_f32m<NB_, MS_, true>), dim3(ntiles), dim3(64 * MS_), 0, s, a);         \
+    else                                                                                                \
+      hipLaunchKernelGGL((k_pass_f32m<NB_, MS_, false>), dim3(ntiles), dim3(64 * MS_), 0, s, a);        \
+    return hipGetLastError();                                                                           \
+  }
+    LSX_ROWSPLIT_CASE(1, 2)
+    LSX_ROWSPLIT_CASE(1, 4)
+    LSX_ROWSPLIT_CASE(2, 2)
+    LSX_ROWSPLIT_CASE(2, 4)
+    LSX_ROWSPLIT_CASE(4, 2)
+    LSX_ROWSPLIT_CASE(4, 4)
+#undef LSX_ROWSPLIT_CASE
+    return hipErrorInvalidValue;
   }
 #define LSX_MFMA_CASE(NB_, KS_) \
   if (nb == NB_ && ksplit == KS_) return launch_mfma<NB_, KS_>(s, fmt, ntiles, a, batched, gather);
