@@ -300,14 +300,19 @@ __global__ void k_phase_table(int64_t N, const double* K2, double scale, double2
   }
 }
 
-__global__ __launch_bounds__(256) void k_phase_apply(int64_t N, int W, const double2* __restrict__ ph,
+// Thread (r, w) of a workgroup takes column w (and w + TW, ...) of rows r, r + RPB, ... of a
+// grid-stride sweep, TW = W rounded up to a power of two (at most 256), RPB = 256 / TW: no
+// per-element index division, and every row's phase is loaded once per thread.
+__global__ __launch_bounds__(256) void k_phase_apply(int64_t N, int W, int TW, const double2* __restrict__ ph,
                                                      double2* __restrict__ c) {
-  const int64_t total = N * (int64_t)W;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
-    const double2 p = ph[e / W];
-    const double2 x = c[e];
-    c[e] = make_double2(p.x * x.x - p.y * x.y, p.x * x.y + p.y * x.x);
+  const int rpb = 256 / TW;
+  const int r = threadIdx.x / TW, w0 = threadIdx.x - r * TW;
+  for (int64_t i = (int64_t)blockIdx.x * rpb + r; i < N; i += (int64_t)gridDim.x * rpb) {
+    const double2 p = ph[i];
+    for (int w = w0; w < W; w += TW) {
+      const double2 x = c[i * W + w];
+      c[i * W + w] = make_double2(p.x * x.x - p.y * x.y, p.x * x.y + p.y * x.x);
+    }
   }
 }
 
@@ -955,6 +960,7 @@ __global__ __launch_bounds__(64 * KS) void k_gemv(PassArgs a0) {
     }
   } else {
     const int nks = ((L + 15) & ~15) >> 2;
+#pragma unroll 4
     for (int ks = kw; ks < nks; ks += KS) {
       const int k = 4 * ks + lk;
       double pr, pi;
@@ -1091,13 +1097,26 @@ __global__ __launch_bounds__(256) void k_fibre_mass(const int32_t* ptr, const in
   const int tid = threadIdx.x;
   for (int w0 = 0; w0 < W; w0 += WB) {
     const int w = w0 + tid % WB, s = tid / WB;
-    double acc = 0.0;
-    if (w < W && s < S)
-      for (int a = s; a < L; a += S) {
-        const double2 x = c[(int64_t)rows[r0 + a] * W + w];
-        acc += x.x * x.x + x.y * x.y;
+    // four independent partial sums keep four rows in flight per thread
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+    if (w < W && s < S) {
+      int a = s;
+      for (; a + 3 * S < L; a += 4 * S) {
+        const double2 x0 = c[(int64_t)rows[r0 + a] * W + w];
+        const double2 x1 = c[(int64_t)rows[r0 + a + S] * W + w];
+        const double2 x2 = c[(int64_t)rows[r0 + a + 2 * S] * W + w];
+        const double2 x3 = c[(int64_t)rows[r0 + a + 3 * S] * W + w];
+        acc0 += x0.x * x0.x + x0.y * x0.y;
+        acc1 += x1.x * x1.x + x1.y * x1.y;
+        acc2 += x2.x * x2.x + x2.y * x2.y;
+        acc3 += x3.x * x3.x + x3.y * x3.y;
       }
-    red[tid] = acc;
+      for (; a < L; a += S) {
+        const double2 x = c[(int64_t)rows[r0 + a] * W + w];
+        acc0 += x.x * x.x + x.y * x.y;
+      }
+    }
+    red[tid] = (acc0 + acc1) + (acc2 + acc3);
     __syncthreads();
     if (tid < WB && w0 + tid < W) {
       double sum = 0.0;
@@ -1158,9 +1177,12 @@ hipError_t launch_phase_table(hipStream_t s, int64_t N, const double* K2, double
 }
 
 hipError_t launch_phase_apply(hipStream_t s, int64_t N, int W, const double2* ph, double2* c) {
-  const int64_t total = N * (int64_t)W;
-  const unsigned grid = (unsigned)std::min<int64_t>((total + 255) / 256, 256 * 64);
-  hipLaunchKernelGGL(k_phase_apply, dim3(grid), dim3(256), 0, s, N, W, ph, c);
+  int TW = 1;
+  while (TW < W && TW < 256) TW <<= 1;
+  const int64_t rows_per_block = 256 / TW;
+  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((N + rows_per_block - 1) / rows_per_block,
+                                                                        256 * 64));
+  hipLaunchKernelGGL(k_phase_apply, dim3(grid), dim3(256), 0, s, N, W, TW, ph, c);
   return hipGetLastError();
 }
 
