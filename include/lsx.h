@@ -60,7 +60,8 @@ enum {
   LSX_OBS_MASS = 1,         /* W doubles */
   LSX_OBS_ENERGY = 2,       /* W doubles */
   LSX_OBS_FIBRE_MASS_1 = 4, /* nfibres_1 * W doubles, [fibre][w] */
-  LSX_OBS_FIBRE_MASS_2 = 8  /* nfibres_2 * W doubles, [fibre][w] */
+  LSX_OBS_FIBRE_MASS_2 = 8, /* nfibres_2 * W doubles, [fibre][w] */
+  LSX_OBS_FIBRE_MASS_3 = 16 /* nfibres_3 * W doubles, [fibre][w] (three-layer systems) */
 };
 
 typedef struct lsx_system lsx_system;
@@ -98,10 +99,39 @@ lsx_status lsx_system_create(int32_t d, const double* A1, const double* A2, doub
                              int32_t nv2, const int32_t* v2_idx, const double* v2_re, const double* v2_im,
                              lsx_system** out);
 
-/* Sizes: N = |I|, and the number of fibres of each layer.  Any output pointer may be NULL. */
+/*
+ * lsx_system_create_layers -- a system of nlayers = 2 or 3 periodic layers (Sec. 2; the
+ * lifting of Sec. 3 with one index block per layer).
+ *
+ *  A            nlayers pointers to d*d lattice matrices (column-major, as above).
+ *  nv, v_idx, v_re, v_im
+ *               nlayers entries each: the Fourier coefficients of layer j's potential in
+ *               the format of lsx_system_create (nv[j] may be 0; the arrays must not be NULL).
+ *  cutoff       LSX_CUTOFF_BALL:    sum_j |G_j m_j|^2 <= 2 Ec
+ *               LSX_CUTOFF_PRODUCT: |G_j m_j|^2 <= 2 Ec for every j (same tolerance as above).
+ *
+ * The lifted index of a row is (m_1, ..., m_nlayers), each m_j in Z^d; canonical order is
+ * lexicographic in that tuple, and V^j couples only m_j.  A layer-j fibre fixes every block
+ * but m_j; fibres are ordered by their fixed blocks (lexicographic, layer order), rows
+ * ascending, so the last layer's fibres are contiguous runs of the canonical order.  With
+ * nlayers = 2 this is lsx_system_create.  Three-layer systems take the Lie and Strang schemes
+ * and the deterministic entry points (plans, states, lsx_step, lsx_fibre_pass, lsx_phase,
+ * lsx_observables); batches, samplers and the semi-implicit step reject them with
+ * LSX_E_INVALID.  Index entries beyond +-511 (three layers, d = 2) are rejected.
+ */
+lsx_status lsx_system_create_layers(int32_t d, int32_t nlayers, const double* const* A, double Ec, int32_t cutoff,
+                                    const int32_t* nv, const int32_t* const* v_idx, const double* const* v_re,
+                                    const double* const* v_im, lsx_system** out);
+
+/* Number of layers and, if nfibres is not NULL, the fibre count of every layer (nlayers
+ * int64 entries). */
+lsx_status lsx_system_layers(const lsx_system* sys, int32_t* nlayers, int64_t* nfibres);
+
+/* Sizes: N = |I|, and the number of fibres of layers 1 and 2.  Any output pointer may be NULL. */
 lsx_status lsx_system_size(const lsx_system* sys, int64_t* N, int64_t* nfibres1, int64_t* nfibres2);
 
-/* The lifted index set: mn is N*2d int32 (host), row i = (m_1..m_d, n_1..n_d) of index i. */
+/* The lifted index set: mn is N*nlayers*d int32 (host), row i = (m_1, ..., m_nlayers) of
+ * index i (for two layers (m_1..m_d, n_1..n_d)). */
 lsx_status lsx_index_get(const lsx_system* sys, int32_t* mn);
 
 /*
@@ -138,6 +168,12 @@ lsx_status lsx_system_destroy(lsx_system* sys);
  *   Strang, CN      : layer 1 {0: tau, 1: tau/2}, layer 2 {0: tau}, phase {0: tau, 1: tau/2}
  *   Yoshida         : layer 1 {0: g1 tau, 1: g1 tau/2, 2: (g1+g0) tau/2},
  *                     layer 2 {0: g1 tau, 2: g0 tau}, phase {0: g1 tau/2, 1: g0 tau/2}
+ * Three-layer systems (Lie and Strang only), with H_j = (1 - kappa)/3 D + V^j:
+ *   Lie             : F1(tau), F2(tau), Phase(kappa tau), F3(tau); every layer {0: tau},
+ *                     phase {0: tau}
+ *   Strang          : F1(tau/2), F2(tau/2), Phase(kappa tau/2), F3(tau), Phase(kappa tau/2),
+ *                     F2(tau/2), F1(tau/2); layer 1 {0: tau, 1: tau/2}, layer 2 {1: tau/2},
+ *                     layer 3 {0: tau}, phase {0: tau, 1: tau/2}
  * with F(t) = f(H_j) per fibre and, per eigenvalue lambda, f = exp(-i t lambda) (exact
  * flows), 1/(1 + i t lambda) (backward Euler) or (1 - i t lambda/2)/(1 + i t lambda/2)
  * (Crank-Nicolson; for t = tau/2 this is (4I + i tau H)^{-1}(4I - i tau H) of eq. 4.6).
@@ -190,7 +226,7 @@ lsx_status lsx_state_download(lsx_state* st, double* host, void* stream);
 lsx_status lsx_state_device_ptr(const lsx_state* st, void** dev_ptr);
 
 /*
- * Tile shape chosen for the fibre passes of `layer` (1 or 2) of this state: each
+ * Tile shape chosen for the fibre passes of `layer` (1 .. nlayers) of this state: each
  * workgroup covers 16*nb columns and either 16 output rows with ks > 0 waves splitting the
  * fibre length, or (ks < 0, mixed FP32) -ks consecutive 16-row blocks, one per wave, that
  * share the state operand staged once per workgroup in LDS.  At creation every candidate shape is timed on the state's own size
@@ -232,9 +268,10 @@ lsx_status lsx_phase(lsx_plan* plan, lsx_state* st, int32_t half, void* stream);
  * lsx_observables -- FP64 reductions on the device, result copied to `out` (host).
  * mask selects, in this order of output blocks:
  *   LSX_OBS_MASS          N_w = sum_i |c_iw|^2  (eq. 2.3 via the orthonormality 3.1)
- *   LSX_OBS_ENERGY        E_w = sum_i 1/2 |K_i|^2 |c_iw|^2 + Re c_w^H (V^1 + V^2) c_w (eq. 2.4)
+ *   LSX_OBS_ENERGY        E_w = sum_i 1/2 |K_i|^2 |c_iw|^2 + Re c_w^H (V^1 + V^2 [+ V^3]) c_w (eq. 2.4)
  *   LSX_OBS_FIBRE_MASS_1  [f][w] partial masses over layer-1 fibres
  *   LSX_OBS_FIBRE_MASS_2  [f][w] partial masses over layer-2 fibres
+ *   LSX_OBS_FIBRE_MASS_3  [f][w] partial masses over layer-3 fibres (three-layer systems)
  * Deterministic (fixed reduction order).  Synchronises the stream.
  * LSX_E_NONFINITE if any requested value is NaN/Inf (out is still written).
  */

@@ -82,18 +82,22 @@ struct FibreTable {
   int maxL = 0;
 };
 
+// Up to kMaxLayers layers; the lifted index of row i is (m_1, ..., m_nl), each m_j in Z^d.
+static constexpr int kMaxLayers = 3;
+
 struct lsx_system {
   int d = 1;
-  double A[2][4] = {};
-  double B[2][4] = {};  // reciprocal 2 pi A^{-T}, row-major d x d
+  int nl = 2;  // number of layers
+  double A[kMaxLayers][4] = {};
+  double B[kMaxLayers][4] = {};  // reciprocal 2 pi A^{-T}, row-major d x d
   double Ec = 0.0;
   int cutoff = 0;
   int64_t N = 0;
-  std::vector<int32_t> mn;  // N * 2d
-  std::vector<double> K2;   // |G1m + G2n|^2
-  Stencil pot[2];
-  FibreTable fib[2];
-  std::vector<int32_t> nbr[2];  // N * nv_j: index of (m - p, n) / (m, n - q), or -1
+  std::vector<int32_t> mn;  // N * nl d
+  std::vector<double> K2;   // |G_1 m_1 + ... + G_nl m_nl|^2
+  Stencil pot[kMaxLayers];
+  FibreTable fib[kMaxLayers];
+  std::vector<int32_t> nbr[kMaxLayers];  // N * nv_j: row with m_j shifted by -p, or -1
   int nplans = 0;
 };
 
@@ -151,9 +155,13 @@ static void layer_candidates(int d, const double* A, const double* B, double lim
   }
 }
 
+// 64-bit key of an integer vector: 16 bits per entry up to 4 entries, 10 bits up to 6
+// (callers check the entries fit: |v| < 2^15 or < 2^9).
 static inline uint64_t pack_key(const int32_t* v, int len) {
   uint64_t k = 0;
-  for (int i = 0; i < len; ++i) k = (k << 16) | (uint64_t)(uint16_t)(int16_t)v[i];
+  const int bits = len <= 4 ? 16 : 10;
+  const uint64_t mask = (1ull << bits) - 1ull;
+  for (int i = 0; i < len; ++i) k = (k << bits) | ((uint64_t)(int64_t)v[i] & mask);
   return k;
 }
 
@@ -200,114 +208,158 @@ static lsx_status build_stencil(int d, int nv, const int32_t* idx, const double*
 
 extern "C" const char* lsx_last_error(void) { return g_err.c_str(); }
 
-extern "C" lsx_status lsx_system_create(int32_t d, const double* A1, const double* A2, double Ec, int32_t cutoff,
-                                        int32_t nv1, const int32_t* v1_idx, const double* v1_re,
-                                        const double* v1_im, int32_t nv2, const int32_t* v2_idx,
-                                        const double* v2_re, const double* v2_im, lsx_system** out) {
-  if (!out || !A1 || !A2) return fail(LSX_E_INVALID, "null argument");
+// The lifted cutoff set of nl layers (Sec. 3; more than two layers as in Sec. 2): the
+// candidate indices of every layer (lexicographic), combined with m_1 outermost, kept when
+// sum_j |G_j m_j|^2 <= 2 Ec (ball, relative tolerance 1e-12) or each term is (product);
+// then |K|^2, the fibres of every layer and the potentials' neighbour tables.
+static lsx_status create_system(int32_t d, int32_t nl, const double* const* A, double Ec, int32_t cutoff,
+                                const int32_t* nv, const int32_t* const* v_idx, const double* const* v_re,
+                                const double* const* v_im, lsx_system** out) {
+  if (!out || !A) return fail(LSX_E_INVALID, "null argument");
   if (d != 1 && d != 2) return fail(LSX_E_INVALID, "d must be 1 or 2");
+  if (nl < 2 || nl > kMaxLayers) return fail(LSX_E_INVALID, "number of layers must be 2 or 3");
+  for (int j = 0; j < nl; ++j)
+    if (!A[j]) return fail(LSX_E_INVALID, "null lattice matrix");
   if (!(Ec > 0.0) || !std::isfinite(Ec)) return fail(LSX_E_INVALID, "Ec must be finite and > 0");
   if (cutoff != LSX_CUTOFF_BALL && cutoff != LSX_CUTOFF_PRODUCT) return fail(LSX_E_INVALID, "bad cutoff");
-  lsx_system* sys = new (std::nothrow) lsx_system();
+  std::unique_ptr<lsx_system> sys(new (std::nothrow) lsx_system());
   if (!sys) return fail(LSX_E_OOM, "host allocation failed");
   sys->d = d;
+  sys->nl = nl;
   sys->Ec = Ec;
   sys->cutoff = cutoff;
-  for (int k = 0; k < d * d; ++k) {
-    sys->A[0][k] = A1[k];
-    sys->A[1][k] = A2[k];
-  }
-  for (int j = 0; j < 2; ++j)
-    if (!reciprocal(d, sys->A[j], sys->B[j])) {
-      delete sys;
+  for (int j = 0; j < nl; ++j) {
+    for (int k = 0; k < d * d; ++k) sys->A[j][k] = A[j][k];
+    if (!reciprocal(d, sys->A[j], sys->B[j]))
       return fail(LSX_E_INVALID, "lattice matrix A" + std::to_string(j + 1) + " is singular or non-finite");
-    }
-  lsx_status st = build_stencil(d, nv1, v1_idx, v1_re, v1_im, sys->pot[0], 1);
-  if (st == LSX_OK) st = build_stencil(d, nv2, v2_idx, v2_re, v2_im, sys->pot[1], 2);
-  if (st != LSX_OK) {
-    delete sys;
-    return st;
   }
+  for (int j = 0; j < nl; ++j)
+    LSX_TRY(build_stencil(d, nv ? nv[j] : 0, v_idx ? v_idx[j] : nullptr, v_re ? v_re[j] : nullptr,
+                          v_im ? v_im[j] : nullptr, sys->pot[j], j + 1));
 
-  // lifted index set: candidates per layer (lexicographic), then pairs (m outer, n inner)
+  // lifted index set
   const double lim = 2.0 * Ec * (1.0 + 1e-12);
-  std::vector<int32_t> cm, cn;
-  std::vector<double> sm, sn;
-  layer_candidates(d, sys->A[0], sys->B[0], lim, cm, sm);
-  layer_candidates(d, sys->A[1], sys->B[1], lim, cn, sn);
-  const int64_t nm = (int64_t)sm.size(), nn = (int64_t)sn.size();
-  for (int64_t a = 0; a < nm; ++a)
-    for (int64_t b = 0; b < nn; ++b) {
-      if (cutoff == LSX_CUTOFF_BALL && !(sm[a] + sn[b] <= lim)) continue;
-      for (int k = 0; k < d; ++k) sys->mn.push_back(cm[a * d + k]);
-      for (int k = 0; k < d; ++k) sys->mn.push_back(cn[b * d + k]);
+  const int S = nl * d;
+  std::vector<int32_t> cand[kMaxLayers];
+  std::vector<double> s2[kMaxLayers];
+  for (int j = 0; j < nl; ++j) layer_candidates(d, sys->A[j], sys->B[j], lim, cand[j], s2[j]);
+  int64_t idx[kMaxLayers] = {0, 0, 0};
+  std::vector<int32_t> row(S);
+  // odometer over the candidate lists, last layer fastest
+  bool any = true;
+  for (int j = 0; j < nl; ++j) any = any && !s2[j].empty();
+  while (any) {
+    double sum = 0.0;
+    bool keep = true;
+    for (int j = 0; j < nl; ++j) {
+      sum += s2[j][idx[j]];
+      if (cutoff == LSX_CUTOFF_PRODUCT && !(s2[j][idx[j]] <= lim)) keep = false;
     }
-  sys->N = (int64_t)sys->mn.size() / (2 * d);
-  if (sys->N >= (int64_t)1 << 31) {
-    delete sys;
-    return fail(LSX_E_INVALID, "lifted index set too large");
+    if (cutoff == LSX_CUTOFF_BALL && !(sum <= lim)) keep = false;
+    if (keep)
+      for (int j = 0; j < nl; ++j)
+        for (int k = 0; k < d; ++k) sys->mn.push_back(cand[j][idx[j] * d + k]);
+    int j = nl - 1;
+    while (j >= 0 && ++idx[j] == (int64_t)s2[j].size()) idx[j--] = 0;
+    if (j < 0) break;
   }
+  sys->N = (int64_t)sys->mn.size() / S;
+  if (sys->N >= (int64_t)1 << 31) return fail(LSX_E_INVALID, "lifted index set too large");
   const int64_t N = sys->N;
+  const int keymax = S <= 4 ? 32767 : 511;
+  for (int32_t v : sys->mn)
+    if (std::abs(v) > keymax) return fail(LSX_E_INVALID, "lifted index out of the supported range");
   sys->K2.resize(N);
   for (int64_t i = 0; i < N; ++i) {
-    const int32_t* r = &sys->mn[i * 2 * d];
+    const int32_t* r = &sys->mn[i * S];
     double s = 0.0;
     for (int k = 0; k < d; ++k) {
       double g = 0.0;
-      for (int c = 0; c < d; ++c) g += sys->B[0][k * d + c] * r[c] + sys->B[1][k * d + c] * r[d + c];
+      for (int j = 0; j < nl; ++j)
+        for (int c = 0; c < d; ++c) g += sys->B[j][k * d + c] * r[j * d + c];
       s += g * g;
     }
     sys->K2[i] = s;
   }
 
-  // fibres: layer 1 groups rows by n (key = last d entries), layer 2 by m (first d entries)
-  for (int layer = 1; layer <= 2; ++layer) {
-    const int off = (layer == 1) ? d : 0;
-    std::vector<int32_t> order(N);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
-      for (int k = 0; k < d; ++k) {
-        const int32_t a = sys->mn[(int64_t)x * 2 * d + off + k], b = sys->mn[(int64_t)y * 2 * d + off + k];
+  // fibres of layer j: rows with equal indices outside block j, keys lexicographic (layer
+  // order), rows ascending; the last layer's fibres are contiguous runs of the canonical order
+  for (int layer = 1; layer <= nl; ++layer) {
+    const int own = (layer - 1) * d;
+    auto key_less = [&](int32_t x, int32_t y) {
+      for (int k = 0; k < S; ++k) {
+        if (k >= own && k < own + d) continue;
+        const int32_t a = sys->mn[(int64_t)x * S + k], b = sys->mn[(int64_t)y * S + k];
         if (a != b) return a < b;
       }
       return false;
-    });
+    };
+    std::vector<int32_t> order(N);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), key_less);
     FibreTable& ft = sys->fib[layer - 1];
     ft.rows = order;
     ft.ptr.clear();
     ft.ptr.push_back(0);
-    for (int64_t i = 1; i <= N; ++i) {
-      bool boundary = (i == N);
-      if (!boundary)
-        for (int k = 0; k < d; ++k)
-          if (sys->mn[(int64_t)order[i] * 2 * d + off + k] != sys->mn[(int64_t)order[i - 1] * 2 * d + off + k])
-            boundary = true;
-      if (boundary) ft.ptr.push_back((int32_t)i);
-    }
+    for (int64_t i = 1; i <= N; ++i)
+      if (i == N || key_less(order[i - 1], order[i]) || key_less(order[i], order[i - 1]))
+        ft.ptr.push_back((int32_t)i);
     if (N == 0) ft.ptr.assign(1, 0);
     ft.maxL = 0;
     for (size_t f = 0; f + 1 < ft.ptr.size(); ++f) ft.maxL = std::max(ft.maxL, ft.ptr[f + 1] - ft.ptr[f]);
   }
 
-  // neighbour tables for the potential terms of the energy
+  // neighbour tables of the potential terms: row with m_j - p, other blocks fixed
   std::unordered_map<uint64_t, int32_t> where;
   where.reserve((size_t)N * 2);
-  for (int64_t i = 0; i < N; ++i) where[pack_key(&sys->mn[i * 2 * d], 2 * d)] = (int32_t)i;
-  for (int j = 0; j < 2; ++j) {
-    const Stencil& S = sys->pot[j];
-    sys->nbr[j].assign((size_t)N * S.nv, -1);
-    for (int64_t i = 0; i < N; ++i) {
-      int32_t v[4];
-      for (int p = 0; p < S.nv; ++p) {
-        for (int k = 0; k < 2 * d; ++k) v[k] = sys->mn[i * 2 * d + k];
-        const int off = (j == 0) ? 0 : d;
-        for (int k = 0; k < d; ++k) v[off + k] -= S.idx[p * d + k];
-        auto it = where.find(pack_key(v, 2 * d));
-        if (it != where.end()) sys->nbr[j][i * S.nv + p] = it->second;
+  for (int64_t i = 0; i < N; ++i) where[pack_key(&sys->mn[i * S], S)] = (int32_t)i;
+  for (int j = 0; j < nl; ++j) {
+    const Stencil& St = sys->pot[j];
+    sys->nbr[j].assign((size_t)N * St.nv, -1);
+    std::vector<int32_t> v(S);
+    for (int64_t i = 0; i < N; ++i)
+      for (int p = 0; p < St.nv; ++p) {
+        for (int k = 0; k < S; ++k) v[k] = sys->mn[i * S + k];
+        bool fits = true;
+        for (int k = 0; k < d; ++k) {
+          v[j * d + k] -= St.idx[p * d + k];
+          fits = fits && std::abs(v[j * d + k]) <= keymax;
+        }
+        if (!fits) continue;
+        auto it = where.find(pack_key(v.data(), S));
+        if (it != where.end()) sys->nbr[j][i * St.nv + p] = it->second;
       }
-    }
   }
-  *out = sys;
+  *out = sys.release();
+  return LSX_OK;
+}
+
+extern "C" lsx_status lsx_system_create(int32_t d, const double* A1, const double* A2, double Ec, int32_t cutoff,
+                                        int32_t nv1, const int32_t* v1_idx, const double* v1_re,
+                                        const double* v1_im, int32_t nv2, const int32_t* v2_idx,
+                                        const double* v2_re, const double* v2_im, lsx_system** out) {
+  if (!A1 || !A2) return fail(LSX_E_INVALID, "null argument");
+  const double* A[2] = {A1, A2};
+  const int32_t nv[2] = {nv1, nv2};
+  const int32_t* idx[2] = {v1_idx, v2_idx};
+  const double* re[2] = {v1_re, v2_re};
+  const double* im[2] = {v1_im, v2_im};
+  return create_system(d, 2, A, Ec, cutoff, nv, idx, re, im, out);
+}
+
+extern "C" lsx_status lsx_system_create_layers(int32_t d, int32_t nlayers, const double* const* A, double Ec,
+                                               int32_t cutoff, const int32_t* nv, const int32_t* const* v_idx,
+                                               const double* const* v_re, const double* const* v_im,
+                                               lsx_system** out) {
+  if (!nv || !v_idx || !v_re || !v_im) return fail(LSX_E_INVALID, "null potential arrays");
+  return create_system(d, nlayers, A, Ec, cutoff, nv, v_idx, v_re, v_im, out);
+}
+
+extern "C" lsx_status lsx_system_layers(const lsx_system* sys, int32_t* nlayers, int64_t* nfibres) {
+  if (!sys) return fail(LSX_E_INVALID, "null system");
+  if (nlayers) *nlayers = sys->nl;
+  if (nfibres)
+    for (int j = 0; j < sys->nl; ++j) nfibres[j] = (int64_t)sys->fib[j].ptr.size() - 1;
   return LSX_OK;
 }
 
@@ -327,7 +379,7 @@ extern "C" lsx_status lsx_index_get(const lsx_system* sys, int32_t* mn) {
 
 extern "C" lsx_status lsx_fibre_get(const lsx_system* sys, int32_t layer, int32_t* ptr, int32_t* rows) {
   if (!sys) return fail(LSX_E_INVALID, "null system");
-  if (layer != 1 && layer != 2) return fail(LSX_E_INVALID, "layer must be 1 or 2");
+  if (layer < 1 || layer > sys->nl) return fail(LSX_E_INVALID, "layer out of range");
   const FibreTable& ft = sys->fib[layer - 1];
   if (ptr) std::memcpy(ptr, ft.ptr.data(), ft.ptr.size() * sizeof(int32_t));
   if (rows && !ft.rows.empty()) std::memcpy(rows, ft.rows.data(), ft.rows.size() * sizeof(int32_t));
@@ -371,11 +423,26 @@ struct lsx_plan {
   DBuf<double> K2;
   DBuf<double2> diag;  // mixed formats: per fibre-row diagonal, [layer*3+slot] blocks of N
   DBuf<double2> phase[3];  // exp(-i kappa t |K|^2/2) for the scheme's phase times
-  DBuf<int32_t> pos1;      // position of canonical index i in the layer-1 fibre order
-  DBuf<double2> zero;      // 1 KiB of zeros (out-of-range operand loads of the passes)
-  LayerDev L[2];
+  // pos[j]: position of canonical index i in the layer-(j+1) fibre order (j < nl - 1; the
+  // last layer's order is canonical); xmap[j][k]: layer-(j+1) fibre position -> layer-(k+1)
+  // fibre position, for j != k both below nl - 1 (three layers)
+  DBuf<int32_t> pos[kMaxLayers - 1];
+  DBuf<int32_t> xmap[kMaxLayers - 1][kMaxLayers - 1];
+  DBuf<double2> zero;  // 1 KiB of zeros (out-of-range operand loads of the passes)
+  LayerDev L[kMaxLayers];
   int nstates = 0;
 };
+
+// Index table of layer `layer`'s fibre positions inside an array of layout `layout` (layout j:
+// layer-j fibre order; layout nl: canonical order, in which the last layer's fibres are
+// contiguous runs); nullptr when the two coincide.
+static const int32_t* layout_map(const lsx_plan* pl, int layer, int layout) {
+  const int nl = pl->sys->nl;
+  if (layout == layer) return nullptr;
+  if (layout == nl) return pl->L[layer - 1].rows.p;  // fibre position -> canonical index
+  if (layer == nl) return pl->pos[layout - 1].p;     // canonical index -> fibre position
+  return pl->xmap[layer - 1][layout - 1].p;
+}
 
 // Sub-step flow of a scheme: 0 exact exponential, 1 backward Euler, 2 Crank-Nicolson.
 static int scheme_flow(int scheme) { return scheme == LSX_LIE_BE ? 1 : (scheme == LSX_STRANG_CN ? 2 : 0); }
@@ -392,19 +459,26 @@ static const double kYoshidaG0 = 1.0 - 2.0 * kYoshidaG1;
 //  Strang, CN-Strang  : layer 1 {tau, tau/2}, layer 2 {tau}, phase {tau, tau/2}
 //  Yoshida (4th order): layer 1 {g1 tau, g1 tau/2, (g1+g0) tau/2}, layer 2 {g1 tau, -, g0 tau},
 //                       phase {g1 tau/2, g0 tau/2}
+// Three layers (Lie and Strang):
+//  Lie                : every layer {tau}, phase {tau}
+//  Strang             : layer 1 {tau, tau/2}, layer 2 {-, tau/2}, layer 3 {tau}, phase {tau, tau/2}
 struct SchemeTimes {
-  double t[2][3];
+  double t[kMaxLayers][3];
   double ph[3];
 };
-static SchemeTimes scheme_times(int scheme, double tau) {
+static SchemeTimes scheme_times(int scheme, double tau, int nl) {
   const double X = std::nan("");
+  if (nl == 3) {
+    if (scheme_strang(scheme)) return {{{tau, 0.5 * tau, X}, {X, 0.5 * tau, X}, {tau, X, X}}, {tau, 0.5 * tau, X}};
+    return {{{tau, X, X}, {tau, X, X}, {tau, X, X}}, {tau, X, X}};
+  }
   if (scheme == LSX_YOSHIDA4) {
     const double g1 = kYoshidaG1, g0 = kYoshidaG0;
-    return {{{g1 * tau, 0.5 * g1 * tau, 0.5 * (g1 + g0) * tau}, {g1 * tau, X, g0 * tau}},
+    return {{{g1 * tau, 0.5 * g1 * tau, 0.5 * (g1 + g0) * tau}, {g1 * tau, X, g0 * tau}, {X, X, X}},
             {0.5 * g1 * tau, 0.5 * g0 * tau, X}};
   }
-  if (scheme_strang(scheme)) return {{{tau, 0.5 * tau, X}, {tau, X, X}}, {tau, 0.5 * tau, X}};
-  return {{{tau, X, X}, {tau, X, X}}, {tau, X, X}};
+  if (scheme_strang(scheme)) return {{{tau, 0.5 * tau, X}, {tau, X, X}, {X, X, X}}, {tau, 0.5 * tau, X}};
+  return {{{tau, X, X}, {tau, X, X}, {X, X, X}}, {tau, X, X}};
 }
 
 static lsx_status precompute_layer(lsx_plan* pl, int layer, hipStream_t s) {
@@ -415,7 +489,8 @@ static lsx_status precompute_layer(lsx_plan* pl, int layer, hipStream_t s) {
   const int nf = ld.nf;
   if (nf == 0) return LSX_OK;
   const int d = sys->d;
-  const int own = (layer == 1) ? 0 : d;
+  const int stride = sys->nl * d;
+  const int own = (layer - 1) * d;
   // With kappa = 1 a fibre Hamiltonian is the potential restricted to the fibre's window
   // of own indices, which is translation invariant: fibres whose windows coincide up to a
   // shift share one eigendecomposition and one stored propagator.
@@ -427,9 +502,9 @@ static lsx_status precompute_layer(lsx_plan* pl, int layer, hipStream_t s) {
       std::vector<int32_t> key;
       const int r0 = ft.ptr[f], L = ft.ptr[f + 1] - r0;
       key.reserve((size_t)L * d);
-      const int32_t* base = &sys->mn[(int64_t)ft.rows[r0] * 2 * d + own];
+      const int32_t* base = &sys->mn[(int64_t)ft.rows[r0] * stride + own];
       for (int a = 0; a < L; ++a)
-        for (int k = 0; k < d; ++k) key.push_back(sys->mn[(int64_t)ft.rows[r0 + a] * 2 * d + own + k] - base[k]);
+        for (int k = 0; k < d; ++k) key.push_back(sys->mn[(int64_t)ft.rows[r0 + a] * stride + own + k] - base[k]);
       auto it = seen.find(key);
       if (it == seen.end()) {
         seen.emplace(std::move(key), (int)uniq.size());
@@ -485,8 +560,10 @@ static lsx_status precompute_layer(lsx_plan* pl, int layer, hipStream_t s) {
   LSX_TRY(lam.alloc(lt));
   LSX_TRY(gh.alloc(lt));
   LSX_TRY(d_info.alloc(nu));
-  LSX_HIP_TRY(launch_assemble(s, nu, d_fid.p, ld.ptr.p, ld.rows.p, d_mn.p, d, layer, pl->K2.p, S.nv, d_vidx.p,
-                              d_vre.p, d_vim.p, pl->kappa, embed, A.p, d_moff.p, d_ndim.p));
+  // kinetic share of H_j: (1 - kappa)/nl * |K|^2/2
+  const double kfac = (1.0 - pl->kappa) / sys->nl * 0.5;
+  LSX_HIP_TRY(launch_assemble(s, nu, d_fid.p, ld.ptr.p, ld.rows.p, d_mn.p, d, stride, own, kfac, pl->K2.p, S.nv,
+                              d_vidx.p, d_vre.p, d_vim.p, embed, A.p, d_moff.p, d_ndim.p));
   LSX_HIP_TRY(launch_jacobi(s, nu, maxn, A.p, VT.p, d_moff.p, d_ndim.p, lam.p, d_loff.p, d_info.p, 60));
   std::vector<int32_t> info(nu);
   LSX_HIP_TRY(hipMemcpyAsync(info.data(), d_info.p, nu * sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -510,7 +587,7 @@ static lsx_status precompute_layer(lsx_plan* pl, int layer, hipStream_t s) {
     ld.h_d0[f] = ft.ptr[uniq[ld.rep[f]]];
   }
   const int flow = scheme_flow(pl->scheme);
-  const SchemeTimes times = scheme_times(pl->scheme, pl->tau);
+  const SchemeTimes times = scheme_times(pl->scheme, pl->tau, sys->nl);
   for (int h = 0; h < 3; ++h) {
     PropSet& ps = ld.prop[h];
     if (std::isnan(times.t[layer - 1][h])) continue;
@@ -539,6 +616,8 @@ extern "C" lsx_status lsx_plan_create(lsx_system* sys, double tau, int32_t schem
   if (!(kappa >= 0.0 && kappa <= 1.0)) return fail(LSX_E_INVALID, "kappa must be in [0, 1]");
   if (precision != LSX_FP64 && precision != LSX_MIX_FP32 && precision != LSX_MIX_BF16X3)
     return fail(LSX_E_INVALID, "bad precision");
+  if (sys->nl > 2 && scheme != LSX_LIE && scheme != LSX_STRANG)
+    return fail(LSX_E_INVALID, "three-layer systems support the Lie and Strang schemes");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   lsx_plan* pl = new (std::nothrow) lsx_plan();
   if (!pl) return fail(LSX_E_OOM, "host allocation failed");
@@ -555,10 +634,11 @@ extern "C" lsx_status lsx_plan_create(lsx_system* sys, double tau, int32_t schem
   lsx_status st = pl->K2.upload(sys->K2, s);
   if (st != LSX_OK) return cleanup(st);
   if (pl->fmt != PF_F64) {
-    st = pl->diag.alloc((size_t)6 * std::max<int64_t>(sys->N, 1));
+    st = pl->diag.alloc((size_t)3 * sys->nl * std::max<int64_t>(sys->N, 1));
     if (st != LSX_OK) return cleanup(st);
   }
-  for (int j = 0; j < 2; ++j) {
+  const int nl = sys->nl;
+  for (int j = 0; j < nl; ++j) {
     LayerDev& ld = pl->L[j];
     const FibreTable& ft = sys->fib[j];
     ld.nf = (int)ft.ptr.size() - 1;
@@ -572,18 +652,28 @@ extern "C" lsx_status lsx_plan_create(lsx_system* sys, double tau, int32_t schem
     if ((st = ld.v.upload(v, s)) != LSX_OK) return cleanup(st);
   }
   {
-    // layer-2 fibres (fixed m) are contiguous runs of the canonical order; the
-    // passes rely on it to read and write that layout without an index table
-    const FibreTable& f2 = sys->fib[1];
+    // the last layer's fibres are contiguous runs of the canonical order; the passes rely
+    // on it to read and write that layout without an index table
+    const FibreTable& fl = sys->fib[nl - 1];
     for (int64_t i = 0; i < sys->N; ++i)
-      if (f2.rows[i] != (int32_t)i) return cleanup(fail(LSX_E_STATE, "internal: layer-2 fibre order"));
-    std::vector<int32_t> pos1(std::max<int64_t>(sys->N, 1), 0);
-    for (int64_t p = 0; p < sys->N; ++p) pos1[sys->fib[0].rows[p]] = (int32_t)p;
-    if ((st = pl->pos1.upload(pos1, s)) != LSX_OK) return cleanup(st);
+      if (fl.rows[i] != (int32_t)i) return cleanup(fail(LSX_E_STATE, "internal: last-layer fibre order"));
+    const size_t n1 = (size_t)std::max<int64_t>(sys->N, 1);
+    std::vector<std::vector<int32_t>> pos(nl - 1, std::vector<int32_t>(n1, 0));
+    for (int j = 0; j + 1 < nl; ++j) {
+      for (int64_t p = 0; p < sys->N; ++p) pos[j][sys->fib[j].rows[p]] = (int32_t)p;
+      if ((st = pl->pos[j].upload(pos[j], s)) != LSX_OK) return cleanup(st);
+    }
+    for (int j = 0; j + 1 < nl; ++j)
+      for (int k = 0; k + 1 < nl; ++k) {
+        if (j == k) continue;
+        std::vector<int32_t> x(n1, 0);
+        for (int64_t p = 0; p < sys->N; ++p) x[p] = pos[k][sys->fib[j].rows[p]];
+        if ((st = pl->xmap[j][k].upload(x, s)) != LSX_OK) return cleanup(st);
+      }
     if ((st = pl->zero.upload(std::vector<double2>(64, make_double2(0.0, 0.0)), s)) != LSX_OK) return cleanup(st);
   }
   if (kappa != 0.0) {
-    const SchemeTimes times = scheme_times(scheme, tau);
+    const SchemeTimes times = scheme_times(scheme, tau, nl);
     for (int h = 0; h < 3; ++h) {
       const double t = times.ph[h];
       if (std::isnan(t)) continue;
@@ -594,7 +684,7 @@ extern "C" lsx_status lsx_plan_create(lsx_system* sys, double tau, int32_t schem
       }
     }
   }
-  for (int layer = 1; layer <= 2; ++layer)
+  for (int layer = 1; layer <= nl; ++layer)
     if ((st = precompute_layer(pl, layer, s)) != LSX_OK) return cleanup(st);
   sys->nplans++;
   *out = pl;
@@ -604,7 +694,7 @@ extern "C" lsx_status lsx_plan_create(lsx_system* sys, double tau, int32_t schem
 extern "C" lsx_status lsx_plan_propagator(const lsx_plan* pl, int32_t layer, int32_t half, int32_t fibre,
                                           double* out, void* stream) {
   if (!pl || !out) return fail(LSX_E_INVALID, "null argument");
-  if (layer != 1 && layer != 2) return fail(LSX_E_INVALID, "layer must be 1 or 2");
+  if (layer < 1 || layer > pl->sys->nl) return fail(LSX_E_INVALID, "layer out of range");
   if (half < 0 || half > 2) return fail(LSX_E_INVALID, "slot must be 0, 1 or 2");
   const LayerDev& ld = pl->L[layer - 1];
   if (fibre < 0 || fibre >= ld.nf) return fail(LSX_E_INVALID, "fibre out of range");
@@ -679,10 +769,10 @@ struct lsx_state {
   double2* buf[2] = {nullptr, nullptr};
   bool owns0 = false;
   DBuf<double2> own0, work;
-  DBuf<TileDesc> tiles[2];
-  int ntiles[2] = {0, 0};
-  int nb[2] = {1, 1}, ks[2] = {4, 4};  // tile shape per layer (16*nb columns, ks waves split k)
-  float tuned_us[2] = {0.f, 0.f};      // measured pass time of the chosen shape (0: not tuned)
+  DBuf<TileDesc> tiles[kMaxLayers];
+  int ntiles[kMaxLayers] = {0, 0, 0};
+  int nb[kMaxLayers] = {1, 1, 1}, ks[kMaxLayers] = {4, 4, 4};  // tile shape per layer (16*nb columns, ks waves split k)
+  float tuned_us[kMaxLayers] = {0.f, 0.f, 0.f};                // measured pass time of the chosen shape (0: not tuned)
   DBuf<double> partial, result;
   int nred = 0;
   int nbatches = 0;                    // batches that reference this state
@@ -787,7 +877,8 @@ static lsx_status choose_tiles(lsx_plan* pl, lsx_state* st) {
     return fail(LSX_E_HIP, "event creation failed");
   }
   lsx_status err = LSX_OK;
-  for (int layer = 1; layer <= 2 && err == LSX_OK; ++layer) {
+  const int nl = pl->sys->nl;
+  for (int layer = 1; layer <= nl && err == LSX_OK; ++layer) {
     float best = -1.f;
     for (const Shape& c : cands) {
       std::vector<TileDesc> t;
@@ -798,15 +889,22 @@ static lsx_status choose_tiles(lsx_plan* pl, lsx_state* st) {
       float ms = 0.f;
       if (timing) {
         // steady-state access pattern of the step: fibre-contiguous read, scattered write
+        // into the next layer's order, with the first propagator slot the plan holds
         const LayerDev& ld = pl->L[layer - 1];
+        int slot = 0;
+        while (slot < 2 && !ld.prop[slot].present) ++slot;
+        if (!ld.prop[slot].present) {
+          err = fail(LSX_E_STATE, "internal: layer without propagators");
+          break;
+        }
         PassArgs a;
         a.tiles = d.p;
         a.in_pos = nullptr;
-        a.out_pos = (layer == 1) ? ld.rows.p : pl->pos1.p;
+        a.out_pos = layout_map(pl, layer, layer % nl + 1);
         a.ph_idx = nullptr;
         a.ph = nullptr;
-        a.P = ld.prop[0].data.p;
-        a.diag = pl->diag.p ? pl->diag.p + (size_t)((layer - 1) * 3) * pl->sys->N : nullptr;
+        a.P = ld.prop[slot].data.p;
+        a.diag = pl->diag.p ? pl->diag.p + (size_t)((layer - 1) * 3 + slot) * pl->sys->N : nullptr;
         a.X = st->buf[0];
         a.Y = st->buf[1];
         a.zero = pl->zero.p;
@@ -870,9 +968,11 @@ extern "C" lsx_status lsx_state_create(lsx_plan* pl, int32_t W, void* dev_ptr, l
   st->buf[1] = st->work.p;
   if ((e = choose_tiles(pl, st)) != LSX_OK) return cleanup(e);
   st->nred = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (N + 255) / 256));
-  const int nfmax = std::max(pl->L[0].nf, pl->L[1].nf);
+  // observables: mass, energy and the fibre masses of every layer in one result block
+  size_t nfsum = 0;
+  for (int j = 0; j < pl->sys->nl; ++j) nfsum += (size_t)pl->L[j].nf;
   if ((e = st->partial.alloc((size_t)st->nred * W)) != LSX_OK) return cleanup(e);
-  if ((e = st->result.alloc((size_t)W * (2 + 2 * (size_t)std::max(nfmax, 1)))) != LSX_OK) return cleanup(e);
+  if ((e = st->result.alloc((size_t)W * (2 + std::max<size_t>(nfsum, 1)))) != LSX_OK) return cleanup(e);
   if (hipDeviceSynchronize() != hipSuccess) return cleanup(fail(LSX_E_HIP, "state setup failed"));
   pl->nstates++;
   *out = st;
@@ -905,7 +1005,7 @@ extern "C" lsx_status lsx_state_device_ptr(const lsx_state* st, void** dev) {
 extern "C" lsx_status lsx_state_tuning(const lsx_state* st, int32_t layer, int32_t* nb, int32_t* ks,
                                        double* pass_us) {
   if (!st) return fail(LSX_E_INVALID, "null state");
-  if (layer != 1 && layer != 2) return fail(LSX_E_INVALID, "layer must be 1 or 2");
+  if (layer < 1 || layer > st->plan->sys->nl) return fail(LSX_E_INVALID, "layer out of range");
   if (nb) *nb = st->nb[layer - 1];
   if (ks) *ks = st->ks[layer - 1];
   if (pass_us) *pass_us = st->tuned_us[layer - 1];
@@ -923,25 +1023,20 @@ extern "C" lsx_status lsx_state_destroy(lsx_state* st) {
 
 // ================================================================ step composer
 // Between API calls the state lives in buf[0] in canonical order.  A fibre pass reads
-// buf[cur] and writes buf[1-cur].  Array layouts: 2 = canonical (layer-2 fibres are
-// contiguous runs), 1 = layer-1 fibre order.  A pass writes the layout the next pass
-// reads fibre-contiguously, so only the first pass of a call gathers through an index
-// table; the last pass writes canonical order.  The kinetic phase that follows a pass
-// is applied in that pass's epilogue.
+// buf[cur] and writes buf[1-cur].  Array layouts: layout j = layer-j fibre order, layout nl =
+// canonical (the last layer's fibres are contiguous runs).  A pass writes the layout the next
+// pass reads fibre-contiguously, so only the first pass of a call gathers through an index
+// table; the last pass writes canonical order.  The kinetic phase that follows a pass is
+// applied in that pass's epilogue.
 namespace {
 struct Runner {
   lsx_plan* pl;
   lsx_state* st;
   hipStream_t s;
   int cur = 0;
-  int lay = 2;
+  int lay = 0;  // layout of buf[cur]; 0 = canonical
 
-  // index table of layer `layer`'s fibre positions inside an array of layout `in`
-  const int32_t* table(int layer, int layout) const {
-    if (layout == layer) return nullptr;  // fibre-contiguous
-    return layer == 1 ? pl->L[0].rows.p   // layer-1 fibre position -> canonical index
-                      : pl->pos1.p;       // canonical index -> layer-1 fibre position
-  }
+  const int32_t* table(int layer, int layout) const { return layout_map(pl, layer, layout); }
 
   // F_layer(t) with t = tau (half 0) or tau/2; `next` is the layer of the following
   // pass (0: none, write canonical order); phase_half >= 0 fuses Phase(kappa t') after it.
@@ -951,12 +1046,13 @@ struct Runner {
     if (!ps.present) return fail(LSX_E_INVALID, "plan holds no propagator for this layer/slot");
     if (phase_half >= 0 && pl->kappa != 0.0 && !pl->phase[phase_half].p)
       return fail(LSX_E_INVALID, "plan holds no phase table for this slot");
-    const int outlay = (next == 0) ? 2 : next;
+    const int nl = pl->sys->nl;
+    const int outlay = (next == 0) ? nl : next;
     PassArgs a;
     a.tiles = st->tiles[layer - 1].p;
-    a.in_pos = table(layer, lay);
+    a.in_pos = table(layer, lay == 0 ? nl : lay);
     a.out_pos = table(layer, outlay);
-    a.ph_idx = (layer == 1) ? pl->L[0].rows.p : nullptr;
+    a.ph_idx = table(layer, nl);
     a.ph = (phase_half >= 0 && pl->kappa != 0.0) ? pl->phase[phase_half].p : nullptr;
     a.P = ps.data.p;
     a.diag = pl->diag.p ? pl->diag.p + (size_t)((layer - 1) * 3 + half) * pl->sys->N : nullptr;
@@ -1013,19 +1109,34 @@ struct PassSpec {
 };
 
 // The passes of nsteps steps of a scheme as head, body (repeated reps times) and tail, with
-// the sub-steps of consecutive steps merged where the flows compose (App. A):
+// the sub-steps of consecutive steps merged where the flows compose (App. A).  Two layers:
 //  Strang  : F1(t/2) [Ph F2(t) Ph F1(t)]^(n-1) Ph F2(t) Ph F1(t/2)           (Ph = phase(t/2))
 //  Lie     : [F1(t) Ph F2(t)]^n                                               (Ph = phase(t))
 //  CN      : [F1(t/2) Ph F2(t) Ph F1(t/2)]^n, unmerged (C(t/2)^2 != C(t), eq. 4.6)
 //  Yoshida : S2(g1 t) S2(g0 t) S2(g1 t) per step; inside a step the adjacent F1 halves merge into
 //            F1((g1+g0) t/2), between steps into F1(g1 t).  Slots as in scheme_times().
-// Every body has an even number of passes and returns to the layout it started from.
-void step_sequence(int scheme, int64_t nsteps, std::vector<PassSpec>& head, std::vector<PassSpec>& body,
+// Every two-layer body has an even number of passes and returns to the layout it started from.
+// Three layers (Ph as above):
+//  Strang  : F1(t/2) F2(t/2) [Ph F3(t) Ph F2(t/2) F1(t) F2(t/2)]^(n-1) Ph F3(t) Ph F2(t/2) F1(t/2)
+//  Lie     : [F1(t) F2(t) Ph F3(t)]^n
+void step_sequence(int scheme, int nl, int64_t nsteps, std::vector<PassSpec>& head, std::vector<PassSpec>& body,
                    std::vector<PassSpec>& tail, int64_t& reps) {
   head.clear();
   body.clear();
   tail.clear();
   reps = 0;
+  if (nl == 3) {
+    if (scheme == LSX_STRANG) {
+      head = {{1, 1, 2, -1}, {2, 1, 3, 1}};
+      body = {{3, 0, 2, 1}, {2, 1, 1, -1}, {1, 0, 2, -1}, {2, 1, 3, 1}};
+      tail = {{3, 0, 2, 1}, {2, 1, 1, -1}, {1, 1, 0, -1}};
+    } else {
+      body = {{1, 0, 2, -1}, {2, 0, 3, 0}, {3, 0, 1, -1}};
+      tail = {{1, 0, 2, -1}, {2, 0, 3, 0}, {3, 0, 0, -1}};
+    }
+    reps = nsteps - 1;
+    return;
+  }
   if (scheme == LSX_STRANG) {
     head = {{1, 1, 2, 1}};
     body = {{2, 0, 1, 1}, {1, 0, 2, 1}};
@@ -1063,7 +1174,7 @@ extern "C" lsx_status lsx_step(lsx_plan* pl, lsx_state* st, int64_t nsteps, void
   if (nsteps == 0 || pl->sys->N == 0) return LSX_OK;
   std::vector<PassSpec> head, body, tail;
   int64_t reps = 0;
-  step_sequence(pl->scheme, nsteps, head, body, tail, reps);
+  step_sequence(pl->scheme, pl->sys->nl, nsteps, head, body, tail, reps);
   return run_passes(pl, st, reinterpret_cast<hipStream_t>(stream), [&](Runner& r) -> lsx_status {
     for (const PassSpec& p : head) LSX_TRY(r.pass(p.layer, p.half, p.next, p.phase_half));
     for (int64_t k = 0; k < reps; ++k)
@@ -1076,7 +1187,7 @@ extern "C" lsx_status lsx_step(lsx_plan* pl, lsx_state* st, int64_t nsteps, void
 extern "C" lsx_status lsx_fibre_pass(lsx_plan* pl, lsx_state* st, int32_t layer, int32_t half, int32_t count,
                                      void* stream) {
   LSX_TRY(check_pair(pl, st));
-  if (layer != 1 && layer != 2) return fail(LSX_E_INVALID, "layer must be 1 or 2");
+  if (layer < 1 || layer > pl->sys->nl) return fail(LSX_E_INVALID, "layer out of range");
   if (half < 0 || half > 2) return fail(LSX_E_INVALID, "slot must be 0, 1 or 2");
   if (count < 0) return fail(LSX_E_INVALID, "count must be >= 0");
   if (pl->sys->N == 0 || count == 0) return LSX_OK;
@@ -1096,7 +1207,8 @@ extern "C" lsx_status lsx_phase(lsx_plan* pl, lsx_state* st, int32_t half, void*
 extern "C" lsx_status lsx_observables(lsx_plan* pl, lsx_state* st, uint32_t mask, double* out, void* stream) {
   LSX_TRY(check_pair(pl, st));
   if (!out) return fail(LSX_E_INVALID, "null output");
-  if (mask == 0 || (mask & ~15u)) return fail(LSX_E_INVALID, "bad observable mask");
+  if (mask == 0 || (mask & ~31u)) return fail(LSX_E_INVALID, "bad observable mask");
+  if ((mask & LSX_OBS_FIBRE_MASS_3) && pl->sys->nl < 3) return fail(LSX_E_INVALID, "system has no layer 3");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const lsx_system* sys = pl->sys;
   const int W = st->W;
@@ -1104,17 +1216,20 @@ extern "C" lsx_status lsx_observables(lsx_plan* pl, lsx_state* st, uint32_t mask
   double* dres = st->result.p;
   size_t count = 0;
   if (mask & LSX_OBS_MASS) {
-    LSX_HIP_TRY(launch_reduce(s, 0, N, W, st->buf[0], pl->K2.p, 0, nullptr, nullptr, 0, nullptr, nullptr,
-                              st->partial.p, st->nred, dres + count));
+    LSX_HIP_TRY(launch_reduce(s, 0, N, W, st->buf[0], pl->K2.p, 0, nullptr, nullptr, 0, nullptr, nullptr, 0,
+                              nullptr, nullptr, st->partial.p, st->nred, dres + count));
     count += W;
   }
   if (mask & LSX_OBS_ENERGY) {
+    const int nv3 = sys->nl > 2 ? sys->pot[2].nv : 0;
     LSX_HIP_TRY(launch_reduce(s, 1, N, W, st->buf[0], pl->K2.p, sys->pot[0].nv, pl->L[0].nbr.p, pl->L[0].v.p,
-                              sys->pot[1].nv, pl->L[1].nbr.p, pl->L[1].v.p, st->partial.p, st->nred, dres + count));
+                              sys->pot[1].nv, pl->L[1].nbr.p, pl->L[1].v.p, nv3, pl->L[2].nbr.p, pl->L[2].v.p,
+                              st->partial.p, st->nred, dres + count));
     count += W;
   }
-  for (int layer = 1; layer <= 2; ++layer)
-    if (mask & (layer == 1 ? LSX_OBS_FIBRE_MASS_1 : LSX_OBS_FIBRE_MASS_2)) {
+  const uint32_t fm_bit[kMaxLayers] = {LSX_OBS_FIBRE_MASS_1, LSX_OBS_FIBRE_MASS_2, LSX_OBS_FIBRE_MASS_3};
+  for (int layer = 1; layer <= sys->nl; ++layer)
+    if (mask & fm_bit[layer - 1]) {
       const LayerDev& ld = pl->L[layer - 1];
       LSX_HIP_TRY(launch_fibre_mass(s, ld.nf, ld.ptr.p, ld.rows.p, W, st->buf[0], dres + count));
       count += (size_t)ld.nf * W;
@@ -1159,10 +1274,9 @@ struct lsx_batch {
   }
 };
 
-// index table of `layer`'s fibre positions inside an array of layout `layout` (see Runner)
+// index table of `layer`'s fibre positions inside an array of layout `layout` (two layers)
 static const int32_t* layout_table(const lsx_plan* pl, int layer, int layout) {
-  if (layout == layer) return nullptr;
-  return layer == 1 ? pl->L[0].rows.p : pl->pos1.p;
+  return layout_map(pl, layer, layout);
 }
 
 static void batch_drop_graph(lsx_batch* b) {
@@ -1285,6 +1399,7 @@ extern "C" lsx_status lsx_batch_create(lsx_plan* const* plans, lsx_state* const*
       return cleanup(fail(LSX_E_STATE, "batch entry " + std::to_string(i) + ": state does not belong to plan"));
     if (plans[i]->scheme != plans[0]->scheme || plans[i]->fmt != plans[0]->fmt)
       return cleanup(fail(LSX_E_INVALID, "batch plans must share scheme and precision"));
+    if (plans[i]->sys->nl != 2) return cleanup(fail(LSX_E_INVALID, "batches hold two-layer systems"));
     if ((states[i]->W == 1) != (states[0]->W == 1))
       return cleanup(fail(LSX_E_INVALID, "batch states must be all W = 1 or all W >= 2"));
     for (int j = 0; j < i; ++j)
@@ -1395,7 +1510,7 @@ extern "C" lsx_status lsx_batch_step(lsx_batch* b, int64_t nsteps, void* stream)
     }
   std::vector<PassSpec> head, body, tail;
   int64_t reps = 0;
-  step_sequence(b->scheme, nsteps, head, body, tail, reps);
+  step_sequence(b->scheme, 2, nsteps, head, body, tail, reps);
   int cur = 0, lay = 2;
   for (const PassSpec& p : head) LSX_TRY(batch_pass(b, s, p, cur, lay));
   if (reps > 0) {
@@ -1657,6 +1772,7 @@ extern "C" lsx_status lsx_sampler_create(lsx_plan* pl, lsx_state* st, int32_t p1
   if (p1 < 0 || p2 < 0) return fail(LSX_E_INVALID, "p1, p2 must be >= 0");
   if (!(eps >= 0.0 && eps <= 1.0)) return fail(LSX_E_INVALID, "eps must be in [0, 1]");
   const lsx_system* sys = pl->sys;
+  if (sys->nl != 2) return fail(LSX_E_INVALID, "samplers hold two-layer systems");
   const int W = st->W, d = sys->d;
   for (int j = 0; j < 2; ++j)
     if (pl->L[j].nf > kSamplerMaxFibres)
@@ -1832,6 +1948,7 @@ lsx_status si_once(lsx_plan* pl, lsx_state* st, const double* wt1, const int32_t
 extern "C" lsx_status lsx_si_step(lsx_plan* pl, lsx_state* st, int64_t nsteps, void* stream) {
   LSX_TRY(check_pair(pl, st));
   if (nsteps < 0) return fail(LSX_E_INVALID, "nsteps must be >= 0");
+  if (pl->sys->nl != 2) return fail(LSX_E_INVALID, "the semi-implicit step takes two-layer systems");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   for (int64_t k = 0; k < nsteps && pl->sys->N > 0; ++k) LSX_TRY(si_once(pl, st, nullptr, nullptr, nullptr, nullptr, s));
   return LSX_OK;

@@ -86,8 +86,8 @@ struct PassArgs {
 
 // ---------------------------------------------------------------- kernel launchers (lsx_kernels.hip)
 hipError_t launch_assemble(hipStream_t s, int nb, const int32_t* fid, const int32_t* ptr, const int32_t* rows,
-                           const int32_t* mn, int d, int layer, const double* K2, int nv, const int32_t* vidx,
-                           const double* vre, const double* vim, double kappa, int embed, double* A,
+                           const int32_t* mn, int d, int stride, int own, double kfac, const double* K2, int nv,
+                           const int32_t* vidx, const double* vre, const double* vim, int embed, double* A,
                            const int64_t* moff, const int32_t* ndim);
 hipError_t launch_jacobi(hipStream_t s, int nf, int maxn, double* A, double* VT, const int64_t* moff,
                          const int32_t* ndim, double* lam, const int64_t* loff, int32_t* info,
@@ -100,9 +100,10 @@ hipError_t launch_phase_table(hipStream_t s, int64_t N, const double* K2, double
 hipError_t launch_phase_apply(hipStream_t s, int64_t N, int W, const double2* ph, double2* c);
 hipError_t launch_pass(hipStream_t s, int fmt, int W, int ntiles, int nb, int ksplit, const PassArgs& a,
                        bool batched = false);
-hipError_t launch_reduce(hipStream_t s, int kind, int64_t N, int W, const double2* c, const double* K2,
-                         int nv1, const int32_t* nbr1, const double2* v1, int nv2, const int32_t* nbr2,
-                         const double2* v2, double* partial, int nblocks, double* out);
+hipError_t launch_reduce(hipStream_t s, int kind, int64_t N, int W, const double2* c, const double* K2, int nv1,
+                         const int32_t* nbr1, const double2* v1, int nv2, const int32_t* nbr2, const double2* v2,
+                         int nv3, const int32_t* nbr3, const double2* v3, double* partial, int nblocks,
+                         double* out);
 hipError_t launch_fibre_mass(hipStream_t s, int nf, const int32_t* ptr, const int32_t* rows, int W,
                              const double2* c, double* out);
 

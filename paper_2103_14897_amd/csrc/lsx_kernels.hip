@@ -66,18 +66,19 @@ __device__ double block_sum(double v, double* sh) {
 
 // ---------------------------------------------------------------- assembly (eq. 3.6 on one fibre)
 // A (ndim x ndim, row-major) <- H_j restricted to fibre f, or for complex H its real
-// embedding [[Re H, -Im H], [Im H, Re H]]; padding rows/cols are zero.
+// embedding [[Re H, -Im H], [Im H, Re H]]; padding rows/cols are zero.  Row i's lifted
+// index is mn[i*stride ...]; layer j's own block starts at entry `own`; the kinetic share
+// on the diagonal is kfac |K|^2 with kfac = (1 - kappa) / (2 nl) for nl layers.
 // Block b assembles fibre fid[b] into its own slot b.
 __global__ void k_assemble(const int32_t* fid, const int32_t* ptr, const int32_t* rows, const int32_t* mn, int d,
-                           int layer, const double* K2, int nv, const int32_t* vidx, const double* vre,
-                           const double* vim, double kappa, int embed, double* Aall, const int64_t* moff,
+                           int stride, int own, double kfac, const double* K2, int nv, const int32_t* vidx,
+                           const double* vre, const double* vim, int embed, double* Aall, const int64_t* moff,
                            const int32_t* ndim) {
   const int b = blockIdx.x;
   const int f = fid[b];
   const int r0 = ptr[f], L = ptr[f + 1] - r0;
   const int n = ndim[b];
   double* A = Aall + moff[b];
-  const int own = (layer == 1) ? 0 : d;
   const int La = embed ? 2 * L : L;
   const int64_t nn = (int64_t)n * n;
   for (int64_t e = threadIdx.x; e < nn; e += blockDim.x) {
@@ -90,13 +91,13 @@ __global__ void k_assemble(const int32_t* fid, const int32_t* ptr, const int32_t
       for (int v = 0; v < nv; ++v) {
         bool match = true;
         for (int k = 0; k < d; ++k)
-          match = match && (mn[(int64_t)ia * 2 * d + own + k] - mn[(int64_t)ib * 2 * d + own + k] == vidx[v * d + k]);
+          match = match && (mn[(int64_t)ia * stride + own + k] - mn[(int64_t)ib * stride + own + k] == vidx[v * d + k]);
         if (match) {
           hr += vre[v];
           hi += vim[v];
         }
       }
-      if (ar == br) hr += (1.0 - kappa) * 0.25 * K2[ia];
+      if (ar == br) hr += kfac * K2[ia];
       if (!embed) val = hr;
       else val = (qa == qb) ? hr : (qa == 0 ? -hi : hi);
     }
@@ -1028,7 +1029,8 @@ __global__ __launch_bounds__(64 * KS) void k_gemv(PassArgs a0) {
 __global__ __launch_bounds__(256) void k_reduce_partial(int kind, int64_t N, int W, const double2* c,
                                                         const double* K2, int nv1, const int32_t* nbr1,
                                                         const double2* v1, int nv2, const int32_t* nbr2,
-                                                        const double2* v2, double* partial, int R) {
+                                                        const double2* v2, int nv3, const int32_t* nbr3,
+                                                        const double2* v3, double* partial, int R) {
   __shared__ double red[256];
   const int b = blockIdx.x;
   const int64_t i0 = (int64_t)b * R;
@@ -1059,6 +1061,14 @@ __global__ __launch_bounds__(256) void k_reduce_partial(int kind, int64_t N, int
             const int j = nbr2[i * nv2 + p];
             if (j >= 0) {
               const double2 y = c[(int64_t)j * W + w], v = v2[p];
+              hr += v.x * y.x - v.y * y.y;
+              hi += v.x * y.y + v.y * y.x;
+            }
+          }
+          for (int p = 0; p < nv3; ++p) {
+            const int j = nbr3[i * nv3 + p];
+            if (j >= 0) {
+              const double2 y = c[(int64_t)j * W + w], v = v3[p];
               hr += v.x * y.x - v.y * y.y;
               hi += v.x * y.y + v.y * y.x;
             }
@@ -1129,11 +1139,11 @@ __global__ __launch_bounds__(256) void k_fibre_mass(const int32_t* ptr, const in
 
 // ================================================================ launchers
 hipError_t launch_assemble(hipStream_t s, int nb, const int32_t* fid, const int32_t* ptr, const int32_t* rows,
-                           const int32_t* mn, int d, int layer, const double* K2, int nv, const int32_t* vidx,
-                           const double* vre, const double* vim, double kappa, int embed, double* A,
+                           const int32_t* mn, int d, int stride, int own, double kfac, const double* K2, int nv,
+                           const int32_t* vidx, const double* vre, const double* vim, int embed, double* A,
                            const int64_t* moff, const int32_t* ndim) {
-  hipLaunchKernelGGL(k_assemble, dim3(nb), dim3(256), 0, s, fid, ptr, rows, mn, d, layer, K2, nv, vidx, vre, vim,
-                     kappa, embed, A, moff, ndim);
+  hipLaunchKernelGGL(k_assemble, dim3(nb), dim3(256), 0, s, fid, ptr, rows, mn, d, stride, own, kfac, K2, nv, vidx,
+                     vre, vim, embed, A, moff, ndim);
   return hipGetLastError();
 }
 
@@ -1302,10 +1312,11 @@ hipError_t launch_pass(hipStream_t s, int fmt, int W, int ntiles, int nb, int ks
 
 hipError_t launch_reduce(hipStream_t s, int kind, int64_t N, int W, const double2* c, const double* K2, int nv1,
                          const int32_t* nbr1, const double2* v1, int nv2, const int32_t* nbr2, const double2* v2,
-                         double* partial, int nblocks, double* out) {
+                         int nv3, const int32_t* nbr3, const double2* v3, double* partial, int nblocks,
+                         double* out) {
   const int R = (int)((N + nblocks - 1) / nblocks);
   hipLaunchKernelGGL(k_reduce_partial, dim3(nblocks), dim3(256), 0, s, kind, N, W, c, K2, nv1, nbr1, v1, nv2,
-                     nbr2, v2, partial, R);
+                     nbr2, v2, nv3, nbr3, v3, partial, R);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_reduce_final, dim3((W + 255) / 256), dim3(256), 0, s, nblocks, W, partial, out);

@@ -24,7 +24,7 @@ LSX_OK, LSX_E_INVALID, LSX_E_NOT_HERMITIAN, LSX_E_OOM, LSX_E_HIP, LSX_E_EIG, LSX
 CUTOFF = {"ball": 0, "product": 1}
 SCHEME = {"lie": 0, "strang": 1, "lie_be": 2, "strang_cn": 3, "yoshida4": 4}
 PRECISION = {"fp64": 0, "mix_fp32": 1, "mix_bf16x3": 2}
-OBS_MASS, OBS_ENERGY, OBS_FIBRE_MASS_1, OBS_FIBRE_MASS_2 = 1, 2, 4, 8
+OBS_MASS, OBS_ENERGY, OBS_FIBRE_MASS_1, OBS_FIBRE_MASS_2, OBS_FIBRE_MASS_3 = 1, 2, 4, 8, 16
 
 _lib = None
 
@@ -37,6 +37,10 @@ _SIGS = {
     "lsx_last_error": (C.c_char_p, []),
     "lsx_system_create": (C.c_int, [C.c_int32, _dp, _dp, C.c_double, C.c_int32,
                                     C.c_int32, _i32p, _dp, _dp, C.c_int32, _i32p, _dp, _dp, C.POINTER(_p)]),
+    "lsx_system_create_layers": (C.c_int, [C.c_int32, C.c_int32, C.POINTER(_dp), C.c_double, C.c_int32,
+                                           _i32p, C.POINTER(_i32p), C.POINTER(_dp), C.POINTER(_dp),
+                                           C.POINTER(_p)]),
+    "lsx_system_layers": (C.c_int, [_p, C.POINTER(C.c_int32), _i64p]),
     "lsx_system_size": (C.c_int, [_p, _i64p, _i64p, _i64p]),
     "lsx_index_get": (C.c_int, [_p, _i32p]),
     "lsx_fibre_get": (C.c_int, [_p, C.c_int32, _i32p, _i32p]),
@@ -135,36 +139,71 @@ def _dev(x):
     return _p(int(x))
 
 
+def _lattice(A, d):
+    return np.asfortranarray(np.asarray(A, dtype=np.float64).reshape(d, d)).ravel(order="F")
+
+
+def _potential(pot, d):
+    keys = sorted((pot or {}).keys())
+    idx = np.ascontiguousarray(np.array(keys, dtype=np.int32).reshape(len(keys), d))
+    vals = np.array([complex(pot[k]) for k in keys], dtype=np.complex128)
+    return len(keys), idx, np.ascontiguousarray(vals.real), np.ascontiguousarray(vals.imag)
+
+
 class System:
     """lsx_system: lattices, potentials and the lifted cutoff set (host only)."""
 
     def __init__(self, d, A1, A2, Ec, cutoff="ball", pot1=None, pot2=None):
         self.d = int(d)
-        A1 = np.asfortranarray(np.asarray(A1, dtype=np.float64).reshape(d, d)).ravel(order="F")
-        A2 = np.asfortranarray(np.asarray(A2, dtype=np.float64).reshape(d, d)).ravel(order="F")
+        A1, A2 = _lattice(A1, d), _lattice(A2, d)
         self._keep = []
         args = []
-        for pot in (pot1 or {}, pot2 or {}):
-            keys = sorted(pot.keys())
-            idx = np.ascontiguousarray(np.array(keys, dtype=np.int32).reshape(len(keys), d))
-            vals = np.array([complex(pot[k]) for k in keys], dtype=np.complex128)
-            re, im = np.ascontiguousarray(vals.real), np.ascontiguousarray(vals.imag)
+        for pot in (pot1, pot2):
+            n, idx, re, im = _potential(pot, d)
             self._keep += [idx, re, im]
-            args += [len(keys), idx.ctypes.data_as(_i32p), _dptr(re), _dptr(im)]
+            args += [n, idx.ctypes.data_as(_i32p), _dptr(re), _dptr(im)]
         h = _p()
         _check(lib().lsx_system_create(self.d, _dptr(A1), _dptr(A2), float(Ec), CUTOFF[cutoff], *args,
                                        C.byref(h)))
+        self._finish(h)
+
+    @classmethod
+    def layers(cls, d, As, Ec, cutoff="ball", pots=None):
+        """A system of len(As) = 2 or 3 layers (lsx_system_create_layers); pots[j] maps index
+        tuples of length d to the Fourier coefficients of layer j's potential."""
+        self = cls.__new__(cls)
+        self.d = d = int(d)
+        nl = len(As)
+        pots = list(pots) if pots is not None else [{}] * nl
+        if len(pots) != nl:
+            raise ValueError("one potential per layer")
+        mats = [_lattice(A, d) for A in As]
+        parts = [_potential(p, d) for p in pots]
+        self._keep = mats + [x for part in parts for x in part[1:]]
+        h = _p()
+        _check(lib().lsx_system_create_layers(
+            d, nl, (_dp * nl)(*[_dptr(A) for A in mats]), float(Ec), CUTOFF[cutoff],
+            (C.c_int32 * nl)(*[p[0] for p in parts]), (_i32p * nl)(*[p[1].ctypes.data_as(_i32p) for p in parts]),
+            (_dp * nl)(*[_dptr(p[2]) for p in parts]), (_dp * nl)(*[_dptr(p[3]) for p in parts]), C.byref(h)))
+        self._finish(h)
+        return self
+
+    def _finish(self, h):
         self.h = h
-        N, f1, f2 = C.c_int64(), C.c_int64(), C.c_int64()
-        _check(lib().lsx_system_size(self.h, C.byref(N), C.byref(f1), C.byref(f2)))
-        self.N, self.nfibres = N.value, {1: f1.value, 2: f2.value}
+        nl = C.c_int32()
+        nf = (C.c_int64 * 3)()
+        _check(lib().lsx_system_layers(self.h, C.byref(nl), nf))
+        N = C.c_int64()
+        _check(lib().lsx_system_size(self.h, C.byref(N), None, None))
+        self.N, self.nlayers = N.value, nl.value
+        self.nfibres = {j + 1: nf[j] for j in range(self.nlayers)}
 
     @classmethod
     def from_spec(cls, spec):
         return cls(spec.d, spec.A1, spec.A2, spec.Ec, spec.cutoff, spec.pot1, spec.pot2)
 
     def index(self):
-        mn = np.zeros((self.N, 2 * self.d), dtype=np.int32)
+        mn = np.zeros((self.N, self.nlayers * self.d), dtype=np.int32)
         _check(lib().lsx_index_get(self.h, mn.ctypes.data_as(_i32p)))
         return mn
 
@@ -239,15 +278,15 @@ class State:
 
     def observables(self, mask=OBS_MASS | OBS_ENERGY, stream=None):
         sys = self.plan.system
-        sizes = [(OBS_MASS, self.W), (OBS_ENERGY, self.W),
-                 (OBS_FIBRE_MASS_1, sys.nfibres[1] * self.W), (OBS_FIBRE_MASS_2, sys.nfibres[2] * self.W)]
+        sizes = [(OBS_MASS, self.W), (OBS_ENERGY, self.W)]
+        sizes += [(OBS_FIBRE_MASS_1 << j, sys.nfibres.get(j + 1, 0) * self.W) for j in range(3)]
         total = sum(n for bit, n in sizes if mask & bit)
         out = np.zeros(total, dtype=np.float64)
         code = lib().lsx_observables(self.plan.h, self.h, int(mask), _dptr(out), _stream(stream))
         _check(code)
         res, o = {}, 0
         names = {OBS_MASS: "mass", OBS_ENERGY: "energy", OBS_FIBRE_MASS_1: "fibre_mass_1",
-                 OBS_FIBRE_MASS_2: "fibre_mass_2"}
+                 OBS_FIBRE_MASS_2: "fibre_mass_2", OBS_FIBRE_MASS_3: "fibre_mass_3"}
         for bit, n in sizes:
             if mask & bit:
                 v = out[o:o + n]

@@ -113,6 +113,40 @@ def twisted_system(Ec: float, theta_deg: float = 5.0, v1: float = 1.0, v2: float
     )
 
 
+@dataclass
+class MultiSpec:
+    """A system of L >= 2 periodic layers (Sec. 2 with one lattice and potential per layer):
+    ``As[j]`` is layer j's d x d lattice matrix (columns primitive vectors), ``pots[j]`` its
+    Fourier coefficients, ``cutoff`` ball (sum_j |G_j m_j|^2 <= 2 Ec) or product."""
+
+    d: int
+    As: list
+    Ec: float
+    cutoff: str = "ball"
+    pots: list = field(default_factory=list)
+    name: str = ""
+
+    @property
+    def L(self) -> int:
+        return len(self.As)
+
+
+def chain_layers(Ec: float, periods=(1.0, GOLDEN, math.sqrt(2.0)), v=(1.0, 0.7, 0.5),
+                 cutoff: str = "ball") -> MultiSpec:
+    """1D chains of the given periods, layer j with potential 2 v_j cos(2 pi x / L_j) (the first
+    len(periods) strengths are used)."""
+    return MultiSpec(d=1, As=[np.array([[float(p)]]) for p in periods], Ec=float(Ec), cutoff=cutoff,
+                     pots=[_cos_pot_1d(x) for _, x in zip(periods, v)], name=f"chain{len(periods)}_Ec{Ec:g}")
+
+
+def twisted_layers(Ec: float, thetas_deg=(-2.5, 0.0, 2.5), v=(1.0, 0.5, 0.7), cutoff: str = "ball") -> MultiSpec:
+    """Triangular layers rotated by the given angles (a twisted trilayer for three angles),
+    first-shell potentials of strengths v_j."""
+    return MultiSpec(d=2, As=[_rot(math.radians(t)) @ TRIANGULAR for t in thetas_deg], Ec=float(Ec), cutoff=cutoff,
+                     pots=[{k: complex(x) for k in FIRST_SHELL} for _, x in zip(thetas_deg, v)],
+                     name=f"twisted{len(thetas_deg)}_Ec{Ec:g}")
+
+
 def draw_k0(W: int, d: int, seed: int = 0, kmax: float = 10.0) -> np.ndarray:
     """Seeded wavepacket centres k0 [W, d] (PCG64).
 

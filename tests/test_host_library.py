@@ -76,3 +76,51 @@ def test_errors():
     s = lsx.System(1, [[1.0]], [[1.6]], 100.0, pot1={(1,): 0.5 + 0.1j, (-1,): 0.5 - 0.1j})
     s.destroy()
     assert lsx.lib().lsx_system_destroy(None) == 0
+
+
+@pytest.mark.parametrize("spec", [wl.chain_layers(150.0), wl.chain_layers(120.0, cutoff="product"),
+                                  wl.twisted_layers(40.0), wl.twisted_layers(30.0, cutoff="product"),
+                                  wl.chain_layers(300.0, periods=(1.0, wl.GOLDEN))],
+                         ids=["chain3", "product3", "twisted3", "twisted3_product", "chain2_layers"])
+def test_layered_index_set_and_fibres_equal_oracle(spec):
+    """lsx_system_create_layers: lifted index set and every layer's fibre table equal the
+    L-layer oracle's exactly."""
+    from oracle import multilayer as ml
+    sys = lsx.System.layers(spec.d, spec.As, spec.Ec, spec.cutoff, spec.pots)
+    mn = ml.index_set(spec.As, spec.Ec, spec.cutoff)
+    assert sys.nlayers == spec.L and sys.N == len(mn)
+    assert np.array_equal(sys.index(), mn.astype(np.int32))
+    for layer in range(1, spec.L + 1):
+        fib = ml.fibres(mn, layer, spec.L, spec.d)
+        ptr, rows = sys.fibres(layer)
+        assert sys.nfibres[layer] == len(fib)
+        assert np.array_equal(ptr, np.cumsum([0] + [len(r) for _, r in fib]))
+        assert np.array_equal(rows, np.concatenate([r for _, r in fib]))
+    # the last layer's fibres are contiguous runs of the canonical order
+    assert np.array_equal(sys.fibres(spec.L)[1], np.arange(sys.N))
+    sys.destroy()
+
+
+def test_two_layers_through_create_layers_equal_create():
+    spec = wl.twisted_system(300.0)
+    a = lsx.System.from_spec(spec)
+    b = lsx.System.layers(spec.d, [spec.A1, spec.A2], spec.Ec, spec.cutoff, [spec.pot1, spec.pot2])
+    assert b.nlayers == 2 and a.nfibres == b.nfibres
+    assert np.array_equal(a.index(), b.index())
+    for layer in (1, 2):
+        assert all(np.array_equal(x, y) for x, y in zip(a.fibres(layer), b.fibres(layer)))
+    a.destroy()
+    b.destroy()
+
+
+def test_layered_errors():
+    one = [[1.0]]
+    for As in ([one], [one, one, one, one]):
+        with pytest.raises(lsx.LsxError) as e:
+            lsx.System.layers(1, As, 100.0)
+        assert e.value.code == lsx.LSX_E_INVALID
+    with pytest.raises(lsx.LsxError) as e:
+        lsx.System.layers(1, [one, [[1.6]], [[1.3]]], 100.0, pots=[{}, {}, {(2,): 0.3}])
+    assert e.value.code == lsx.LSX_E_NOT_HERMITIAN
+    with pytest.raises(ValueError):
+        lsx.System.layers(1, [one, [[1.6]], [[1.3]]], 100.0, pots=[{}, {}])
