@@ -12,6 +12,8 @@ Compositions (App. A, generalised to L parts):
     Lie    : F_1(tau), ..., F_{L-1}(tau), Phase(kappa tau), F_L(tau)
     Strang : F_1(tau/2), ..., F_{L-1}(tau/2), Phase(kappa tau/2), F_L(tau), Phase(kappa tau/2),
              F_{L-1}(tau/2), ..., F_1(tau/2)
+    Yoshida: S(g1 tau) S(g0 tau) S(g1 tau) with S the Strang step, g1 = 1 / (2 - 2^(1/3)),
+             g0 = 1 - 2 g1 (fourth order; App. A points to such higher-order compositions)
 For L = 2 these are the two-layer schemes of `splitting`.  Canonical order of the index set is
 lexicographic in (m_1, ..., m_L); fibres of layer j are ordered lexicographically by their fixed
 indices (in layer order) and list their rows in canonical order.
@@ -167,8 +169,17 @@ class MultiSplitPlan:
             c = self.apply_fibres(c, j, tau / 2)
         return c
 
+    def yoshida4_step(self, c, tau: float):
+        """Symmetric triple jump of Strang steps, applied unmerged: 2 g1 + g0 = 1 and
+        2 g1^3 + g0^3 = 0 cancel the third-order error of the composition."""
+        g1 = 1.0 / (2.0 - 2.0 ** (1.0 / 3.0))
+        g0 = 1.0 - 2.0 * g1
+        for g in (g1, g0, g1):
+            c = self.strang_step(c, g * tau)
+        return c
+
     def evolve(self, c, tau: float, nsteps: int, scheme: str = "strang"):
-        step = self.strang_step if scheme == "strang" else self.lie_step
+        step = {"strang": self.strang_step, "lie": self.lie_step, "yoshida4": self.yoshida4_step}[scheme]
         for _ in range(nsteps):
             c = step(c, tau)
         return c

@@ -37,6 +37,7 @@ def test_two_layers_reduce_to_the_two_layer_oracle(spec):
         p2, pL = splitting.SplitPlan(O2, kappa), ml.MultiSplitPlan(OL, kappa)
         assert rel(pL.strang_step(c, 0.03), p2.strang_step(c, 0.03)) < 1e-13
         assert rel(pL.lie_step(c, 0.03), p2.lie_step(c, 0.03)) < 1e-13
+        assert rel(pL.yoshida4_step(c, 0.03), p2.yoshida4_step(c, 0.03)) < 1e-13
 
 
 @pytest.mark.parametrize("kappa", [0.0, 1.0])
@@ -56,8 +57,9 @@ def test_three_layers_step_equals_dense_products(kappa):
     assert rel(plan.strang_step(c, tau), strang @ c) < 1e-13
 
 
-@pytest.mark.parametrize("scheme,order", [("lie", 1.0), ("strang", 2.0)])
-def test_three_layer_orders(scheme, order):
+@pytest.mark.parametrize("scheme,order,Ks", [("lie", 1.0, (40, 80, 160)), ("strang", 2.0, (40, 80, 160)),
+                                             ("yoshida4", 4.0, (80, 160, 320))])
+def test_three_layer_orders(scheme, order, Ks):
     O = three_chain(100.0)
     Dk, Hs = O.dense(0.0)
     H = Dk + sum(Hs)
@@ -65,7 +67,7 @@ def test_three_layer_orders(scheme, order):
     T = 0.5
     exact = scipy.linalg.expm(-1j * T * H) @ c0
     plan = ml.MultiSplitPlan(O, 0.0)
-    errs = [np.linalg.norm(plan.evolve(c0, T / K, K, scheme) - exact) for K in (40, 80, 160)]
+    errs = [np.linalg.norm(plan.evolve(c0, T / K, K, scheme) - exact) for K in Ks]
     slopes = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
     assert all(abs(s - order) < 0.15 for s in slopes), (errs, slopes)
 
