@@ -351,6 +351,82 @@ def si_workload(args):
     S.destroy()
 
 
+def trilayer_workload(args):
+    """Three layers: the twisted triangular trilayer (layers at -2.5, 0, +2.5 deg, first-shell
+    potentials 1.0, 0.5, 0.7), ball cutoff Ec = 1000 (N = 415135, 9061 fibres per layer of length
+    up to 139), 128 random unit wavepackets (seed 0), tau = 5e-3, kappa = 0.  Each path runs
+    50 steps from the same state for the error against FP64, then the timed steps; every
+    layer's pass is timed on its own (slot tau for layers 1 and 3, tau/2 for layer 2 of the
+    Strang plan)."""
+    import torch
+
+    spec = wl.twisted_layers(1000.0)
+    S = lsx.System.layers(spec.d, spec.As, spec.Ec, spec.cutoff, spec.pots)
+    N, W, tau = S.N, 128, 5e-3
+    c0 = wl.random_state(N, W, seed=0)
+    sumL2 = {j: int(np.sum(np.diff(S.fibres(j)[0]).astype(np.int64) ** 2)) for j in (1, 2, 3)}
+    slot = {"strang": {1: 0, 2: 1, 3: 0}, "lie": {1: 0, 2: 0, 3: 0}, "yoshida4": {1: 0, 2: 0, 3: 0}}[args.scheme]
+    stream = torch.cuda.current_stream()
+    res, finals = {}, {}
+    for path in args.paths.split(","):
+        P = lsx.Plan(S, tau, args.scheme, args.kappa, path, stream)
+        st = lsx.State(P, W)
+        st.upload(c0, stream)
+        st.step(50, stream)
+        finals[path] = st.download(stream)
+        st.upload(c0, stream)
+        st.step(args.warmup, stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        st.step(args.steps, stream)
+        e1.record(stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        passes = {}
+        for j in (1, 2, 3):
+            e0.record(stream)
+            st.fibre_pass(j, slot[j], args.kernel_reps, stream)
+            e1.record(stream)
+            e1.synchronize()
+            passes[j] = e0.elapsed_time(e1) * 1e3 / args.kernel_reps
+        res[path] = {"coeff_steps_per_s": N * W * args.steps / (ms * 1e-3), "ms_per_step": ms / args.steps,
+                     "pass_us": passes, "tiles": {j: st.tuning(j)[:2] for j in (1, 2, 3)}}
+        st.destroy()
+        P.destroy()
+    ref = finals.get("fp64")
+    for path in res:
+        res[path]["rel_l2_vs_fp64_50_steps"] = None if ref is None else float(
+            (np.linalg.norm(finals[path] - ref, axis=0) / np.linalg.norm(ref, axis=0)).max())
+    ok = [p for p in res if p == "fp64" or ref is None or res[p]["rel_l2_vs_fp64_50_steps"] <= 1e-6]
+    best = max(ok, key=lambda p: res[p]["coeff_steps_per_s"])
+    r = res[best]
+    j = max(r["pass_us"], key=lambda k: r["pass_us"][k])  # dominant pass
+    flops = 8.0 * W * sumL2[j]
+    nbytes = 2.0 * N * W * 16 + PROP_BYTES[best] * sumL2[j] + (16.0 * N if best != "fp64" else 0.0)
+    t = r["pass_us"][j] * 1e-6
+    bound = "mfma" if flops / PEAK[best] >= nbytes / HBM_PEAK else "hbm"
+    if bound == "mfma":
+        roof = {"bound": "mfma", "achieved": flops / t / 1e12, "peak": PEAK[best] / 1e12, "unit": "TFLOP/s",
+                "frac": flops / t / PEAK[best]}
+    else:
+        roof = {"bound": "hbm", "achieved": nbytes / t / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                "frac": nbytes / t / HBM_PEAK}
+    roof.update({"traffic": None, "kernel": f"fibre pass, layer {j} ({best})", "algorithmic_flops": flops,
+                 "algorithmic_bytes": nbytes,
+                 "other_roof_frac": (nbytes / t / HBM_PEAK) if bound == "mfma" else (flops / t / PEAK[best])})
+    out = {"metric": "coeff·steps/s of three-layer splitting; % HBM/MFMA peak of the dominant pass",
+           "value": r["coeff_steps_per_s"], "unit": "coeff*steps/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": DTYPE[best], "data": "synthetic",
+           "config": {"workload": f"twisted_trilayer_m2.5_0_p2.5deg_Ec1000_W128_{args.scheme}_tau5e-3", "N": N,
+                      "W": W, "fibres": [S.nfibres[1], S.nfibres[2], S.nfibres[3]], "path": best,
+                      "kappa": args.kappa, "scheme": args.scheme},
+           "roofline": roof, "paths": res}
+    print(json.dumps(out))
+    S.destroy()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -367,7 +443,7 @@ def main():
     ap.add_argument("--train-iters", type=int, default=300)
     ap.add_argument("--learn-steps", type=int, default=200, help="learned mode: evaluation steps (T = steps tau)")
     ap.add_argument("--workload", default="chain",
-                    choices=["chain", "twisted", "twisted1", "tiny", "batch", "learned", "si"],
+                    choices=["chain", "twisted", "twisted1", "tiny", "batch", "learned", "si", "trilayer"],
                     help="chain: the metric's workload (default); the others are extra measurements")
     ap.add_argument("--kappa", type=float, default=0.0)
     ap.add_argument("--scheme", default="strang", choices=["strang", "lie", "yoshida4", "strang_cn", "lie_be"],
@@ -387,6 +463,8 @@ def main():
         return learned_workload(args)
     if args.workload == "si":
         return si_workload(args)
+    if args.workload == "trilayer":
+        return trilayer_workload(args)
     w = {"chain": wl.chain, "twisted": wl.twisted, "twisted1": lambda: wl.twisted(W=1),
          "tiny": wl.tiny_chain}[args.workload]()
     S = lsx.System.from_spec(w.spec)

@@ -114,7 +114,7 @@ lsx_status lsx_system_create(int32_t d, const double* A1, const double* A2, doub
  * lexicographic in that tuple, and V^j couples only m_j.  A layer-j fibre fixes every block
  * but m_j; fibres are ordered by their fixed blocks (lexicographic, layer order), rows
  * ascending, so the last layer's fibres are contiguous runs of the canonical order.  With
- * nlayers = 2 this is lsx_system_create.  Three-layer systems take the Lie and Strang schemes
+ * nlayers = 2 this is lsx_system_create.  Three-layer systems take the Lie, Strang and Yoshida schemes
  * and the deterministic entry points (plans, states, lsx_step, lsx_fibre_pass, lsx_phase,
  * lsx_observables); batches, samplers and the semi-implicit step reject them with
  * LSX_E_INVALID.  Index entries beyond +-511 (three layers, d = 2) are rejected.
@@ -168,12 +168,15 @@ lsx_status lsx_system_destroy(lsx_system* sys);
  *   Strang, CN      : layer 1 {0: tau, 1: tau/2}, layer 2 {0: tau}, phase {0: tau, 1: tau/2}
  *   Yoshida         : layer 1 {0: g1 tau, 1: g1 tau/2, 2: (g1+g0) tau/2},
  *                     layer 2 {0: g1 tau, 2: g0 tau}, phase {0: g1 tau/2, 1: g0 tau/2}
- * Three-layer systems (Lie and Strang only), with H_j = (1 - kappa)/3 D + V^j:
+ * Three-layer systems (Lie, Strang and Yoshida), with H_j = (1 - kappa)/3 D + V^j:
  *   Lie             : F1(tau), F2(tau), Phase(kappa tau), F3(tau); every layer {0: tau},
  *                     phase {0: tau}
  *   Strang          : F1(tau/2), F2(tau/2), Phase(kappa tau/2), F3(tau), Phase(kappa tau/2),
  *                     F2(tau/2), F1(tau/2); layer 1 {0: tau, 1: tau/2}, layer 2 {1: tau/2},
  *                     layer 3 {0: tau}, phase {0: tau, 1: tau/2}
+ *   Yoshida         : the three-layer Strang steps of g1 tau, g0 tau, g1 tau; layer 1 as for two
+ *                     layers, layer 2 {0: g1 tau/2, 1: g0 tau/2}, layer 3 {0: g1 tau, 2: g0 tau},
+ *                     phase {0: g1 tau/2, 1: g0 tau/2}
  * with F(t) = f(H_j) per fibre and, per eigenvalue lambda, f = exp(-i t lambda) (exact
  * flows), 1/(1 + i t lambda) (backward Euler) or (1 - i t lambda/2)/(1 + i t lambda/2)
  * (Crank-Nicolson; for t = tau/2 this is (4I + i tau H)^{-1}(4I - i tau H) of eq. 4.6).

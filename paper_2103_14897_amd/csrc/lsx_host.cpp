@@ -459,9 +459,11 @@ static const double kYoshidaG0 = 1.0 - 2.0 * kYoshidaG1;
 //  Strang, CN-Strang  : layer 1 {tau, tau/2}, layer 2 {tau}, phase {tau, tau/2}
 //  Yoshida (4th order): layer 1 {g1 tau, g1 tau/2, (g1+g0) tau/2}, layer 2 {g1 tau, -, g0 tau},
 //                       phase {g1 tau/2, g0 tau/2}
-// Three layers (Lie and Strang):
+// Three layers (Lie, Strang, Yoshida):
 //  Lie                : every layer {tau}, phase {tau}
 //  Strang             : layer 1 {tau, tau/2}, layer 2 {-, tau/2}, layer 3 {tau}, phase {tau, tau/2}
+//  Yoshida            : layer 1 {g1 tau, g1 tau/2, (g1+g0) tau/2}, layer 2 {g1 tau/2, g0 tau/2},
+//                       layer 3 {g1 tau, -, g0 tau}, phase {g1 tau/2, g0 tau/2}
 struct SchemeTimes {
   double t[kMaxLayers][3];
   double ph[3];
@@ -469,6 +471,13 @@ struct SchemeTimes {
 static SchemeTimes scheme_times(int scheme, double tau, int nl) {
   const double X = std::nan("");
   if (nl == 3) {
+    if (scheme == LSX_YOSHIDA4) {
+      const double g1 = kYoshidaG1, g0 = kYoshidaG0;
+      return {{{g1 * tau, 0.5 * g1 * tau, 0.5 * (g1 + g0) * tau},
+               {0.5 * g1 * tau, 0.5 * g0 * tau, X},
+               {g1 * tau, X, g0 * tau}},
+              {0.5 * g1 * tau, 0.5 * g0 * tau, X}};
+    }
     if (scheme_strang(scheme)) return {{{tau, 0.5 * tau, X}, {X, 0.5 * tau, X}, {tau, X, X}}, {tau, 0.5 * tau, X}};
     return {{{tau, X, X}, {tau, X, X}, {tau, X, X}}, {tau, X, X}};
   }
@@ -616,8 +625,8 @@ extern "C" lsx_status lsx_plan_create(lsx_system* sys, double tau, int32_t schem
   if (!(kappa >= 0.0 && kappa <= 1.0)) return fail(LSX_E_INVALID, "kappa must be in [0, 1]");
   if (precision != LSX_FP64 && precision != LSX_MIX_FP32 && precision != LSX_MIX_BF16X3)
     return fail(LSX_E_INVALID, "bad precision");
-  if (sys->nl > 2 && scheme != LSX_LIE && scheme != LSX_STRANG)
-    return fail(LSX_E_INVALID, "three-layer systems support the Lie and Strang schemes");
+  if (sys->nl > 2 && scheme != LSX_LIE && scheme != LSX_STRANG && scheme != LSX_YOSHIDA4)
+    return fail(LSX_E_INVALID, "three-layer systems support the Lie, Strang and Yoshida schemes");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   lsx_plan* pl = new (std::nothrow) lsx_plan();
   if (!pl) return fail(LSX_E_OOM, "host allocation failed");
@@ -1119,6 +1128,8 @@ struct PassSpec {
 // Three layers (Ph as above):
 //  Strang  : F1(t/2) F2(t/2) [Ph F3(t) Ph F2(t/2) F1(t) F2(t/2)]^(n-1) Ph F3(t) Ph F2(t/2) F1(t/2)
 //  Lie     : [F1(t) F2(t) Ph F3(t)]^n
+//  Yoshida : the three-layer Strang steps of g1 t, g0 t, g1 t with the F1 halves merged as for
+//            two layers (13 passes per step)
 void step_sequence(int scheme, int nl, int64_t nsteps, std::vector<PassSpec>& head, std::vector<PassSpec>& body,
                    std::vector<PassSpec>& tail, int64_t& reps) {
   head.clear();
@@ -1126,7 +1137,16 @@ void step_sequence(int scheme, int nl, int64_t nsteps, std::vector<PassSpec>& he
   tail.clear();
   reps = 0;
   if (nl == 3) {
-    if (scheme == LSX_STRANG) {
+    if (scheme == LSX_YOSHIDA4) {
+      const std::vector<PassSpec> inner = {{2, 0, 3, 0}, {3, 0, 2, 0}, {2, 0, 1, -1}, {1, 2, 2, -1},
+                                           {2, 1, 3, 1}, {3, 2, 2, 1}, {2, 1, 1, -1}, {1, 2, 2, -1},
+                                           {2, 0, 3, 0}, {3, 0, 2, 0}, {2, 0, 1, -1}};
+      head = {{1, 1, 2, -1}};
+      body = inner;
+      body.push_back({1, 0, 2, -1});
+      tail = inner;
+      tail.push_back({1, 1, 0, -1});
+    } else if (scheme == LSX_STRANG) {
       head = {{1, 1, 2, -1}, {2, 1, 3, 1}};
       body = {{3, 0, 2, 1}, {2, 1, 1, -1}, {1, 0, 2, -1}, {2, 1, 3, 1}};
       tail = {{3, 0, 2, 1}, {2, 1, 1, -1}, {1, 1, 0, -1}};
