@@ -142,7 +142,8 @@ def batch_workload(args):
            "config": {"workload": f"batch_{args.batch_1d}x1d_{args.batch_2d}x2d_W16_kappa1",
                       "systems": len(items), "total_coefficients": coeffs,
                       "N_range": [min(it[0].N for it in items), max(it[0].N for it in items)],
-                      "tiles": {"layer1": B.tuning(1)[:2], "layer2": B.tuning(2)[:2]}},
+                      "tiles": {"layer1": B.tuning(1)[:2], "layer2": B.tuning(2)[:2]},
+                      "launch_mode": {"layer1": B.tuning(1)[3], "layer2": B.tuning(2)[3]}},
            "sequential_value": coeffs * args.steps / (ms_seq * 1e-3), "sequential_ms_per_step": ms_seq / args.steps,
            "precompute_s": pre}
     print(json.dumps(out))

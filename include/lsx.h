@@ -288,17 +288,25 @@ lsx_status lsx_observables(lsx_plan* plan, lsx_state* st, uint32_t mask, double*
  *
  * lsx_batch_create: plans[i] and states[i] (i < n) must match (states[i] created on
  *   plans[i]); all plans must share the scheme and the precision; states must be all
- *   W = 1 or all W >= 2.  The tile shape is autotuned on the whole batch as for a state.
+ *   W = 1 or all W >= 2.  The tile shape and the launch mode of every layer's pass are
+ *   autotuned on the whole batch: one workgroup per tile (the hardware dispatcher balances
+ *   the uneven tiles), or a persistent grid of the resident capacity that walks the
+ *   XCD-interleaved tile list with a static stride, or one that claims tiles from per-XCD
+ *   queues on device counters (cleared by the last workgroup of each launch, so replayed
+ *   graphs need no memset).  All three give bit-identical results for one tile shape.
  *   Plans and states must outlive the batch (destroying a state that is in a batch returns
  *   LSX_E_STATE).  While a batch step is in flight no other call may use its states.
  * lsx_batch_step: advances every state by nsteps * tau_i with its plan's scheme, exactly
  *   as lsx_step would (bit-for-bit up to the tile shape's summation order).  Stream-ordered.
- * lsx_batch_tuning: tile shape and measured pass time of `layer` for the whole batch.
+ * lsx_batch_tuning: tile shape, measured pass time and launch mode (0 one workgroup per tile,
+ *   1 persistent with tile queues, 2 persistent with a static stride) of `layer` for the whole
+ *   batch.  Any output pointer may be NULL.
  */
 typedef struct lsx_batch lsx_batch;
 lsx_status lsx_batch_create(lsx_plan* const* plans, lsx_state* const* states, int32_t n, lsx_batch** out);
 lsx_status lsx_batch_step(lsx_batch* batch, int64_t nsteps, void* stream);
-lsx_status lsx_batch_tuning(const lsx_batch* batch, int32_t layer, int32_t* nb, int32_t* ks, double* pass_us);
+lsx_status lsx_batch_tuning(const lsx_batch* batch, int32_t layer, int32_t* nb, int32_t* ks, double* pass_us,
+                            int32_t* launch_mode);
 lsx_status lsx_batch_destroy(lsx_batch* batch);
 
 /* ================================================================ semi-implicit, random batch and

@@ -1284,6 +1284,9 @@ struct lsx_batch {
   std::map<PatternKey, std::unique_ptr<DBuf<PassArgs>>> args;
   std::vector<std::pair<double2*, double2*>> bufs;  // buffers the argument arrays refer to
   DBuf<int32_t> marker;                              // non-null in_pos marker for gathering passes
+  DBuf<int32_t> queue;                               // persistent launches: 9 counters, zero between launches
+  int persist[2] = {0, 0};                           // launch mode per layer: 0 one workgroup per tile,
+                                                     // 1 persistent with tile queues, 2 persistent static stride
   hipStream_t cap = nullptr;
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
@@ -1399,6 +1402,8 @@ static lsx_status batch_pass(lsx_batch* b, hipStream_t s, const PassSpec& p, int
   a0.tiles = b->tiles[p.layer - 1].p;
   a0.in_pos = (lay == p.layer) ? nullptr : b->marker.p;  // gather flag, uniform over the batch
   a0.batch = d;
+  a0.persist = b->persist[p.layer - 1];
+  a0.queue = b->queue.p;
   LSX_HIP_TRY(launch_pass(s, b->fmt, b->w1 ? 1 : 2, b->ntiles[p.layer - 1], b->nb[p.layer - 1],
                           b->ks[p.layer - 1], a0, true));
   cur ^= 1;
@@ -1432,23 +1437,39 @@ extern "C" lsx_status lsx_batch_create(lsx_plan* const* plans, lsx_state* const*
   b->w1 = states[0]->W == 1;
   lsx_status e;
   if ((e = b->marker.alloc(1)) != LSX_OK) return cleanup(e);
-  // tile shape: autotune over the combined tiles with the steady-state pass patterns
+  if ((e = b->queue.alloc(9)) != LSX_OK) return cleanup(e);
+  if (hipMemset(b->queue.p, 0, 9 * sizeof(int32_t)) != hipSuccess)
+    return cleanup(fail(LSX_E_HIP, "hipMemset of the tile queue failed"));
+  // tile shape and launch mode: autotune over the combined tiles with the steady-state pass
+  // patterns.  Modes: 0 one workgroup per tile (the hardware dispatcher balances), 2
+  // persistent grid with a static stride, 1 persistent grid with per-XCD tile queues;
+  // LSX_PERSIST forces one mode, LSX_NB / LSX_KS one shape.
   struct Shape {
-    int nb, ks;
+    int nb, ks, pm;
   };
-  std::vector<Shape> cands;
+  std::vector<Shape> shapes;
   int maxW = 1;
   for (lsx_state* st : b->st) maxW = std::max(maxW, st->W);
   if (b->w1) {
-    cands.push_back({1, 4});
+    shapes.push_back({1, 4, 0});
   } else {
     for (int nbv : {1, 2, 4})
       for (int k : {1, 2, 4})
-        if (16 * nbv <= round_up(maxW, 16) && !(nbv == 4 && k == 4)) cands.push_back({nbv, k});
+        if (16 * nbv <= round_up(maxW, 16) && !(nbv == 4 && k == 4)) shapes.push_back({nbv, k, 0});
     const int fnb = env_int("LSX_NB", 0), fks = env_int("LSX_KS", 0);
-    if (fnb > 0 || fks > 0) cands.assign(1, Shape{fnb > 0 ? fnb : 1, fks > 0 ? fks : 2});
-    else if (env_int("LSX_AUTOTUNE", 1) == 0) cands.assign(1, Shape{1, 2});
+    if (fnb > 0 || fks > 0) shapes.assign(1, Shape{fnb > 0 ? fnb : 1, fks > 0 ? fks : 2, 0});
+    else if (env_int("LSX_AUTOTUNE", 1) == 0) shapes.assign(1, Shape{1, 2, 0});
   }
+  const int fpm = env_int("LSX_PERSIST", -1);
+  std::vector<int> modes = {0, 2, 1};
+  if (fpm >= 0 && fpm <= 2) modes.assign(1, fpm);
+  else if (env_int("LSX_AUTOTUNE", 1) == 0) modes.assign(1, 0);
+  std::vector<Shape> cands;
+  for (int m : modes)
+    for (Shape c : shapes) {
+      c.pm = m;
+      cands.push_back(c);
+    }
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     if (e0) (void)hipEventDestroy(e0);
@@ -1465,9 +1486,11 @@ extern "C" lsx_status lsx_batch_create(lsx_plan* const* plans, lsx_state* const*
       std::swap(b->tiles[layer - 1].p, d.p);
       std::swap(b->tiles[layer - 1].n, d.n);
       const int save_nt = b->ntiles[layer - 1], save_nb = b->nb[layer - 1], save_ks = b->ks[layer - 1];
+      const int save_pm = b->persist[layer - 1];
       b->ntiles[layer - 1] = (int)t.size();
       b->nb[layer - 1] = c.nb;
       b->ks[layer - 1] = c.ks;
+      b->persist[layer - 1] = c.pm;
       float ms = 0.f;
       if (cands.size() > 1) {
         int cur = 0, lay = layer;
@@ -1500,6 +1523,7 @@ extern "C" lsx_status lsx_batch_create(lsx_plan* const* plans, lsx_state* const*
         b->ntiles[layer - 1] = save_nt;
         b->nb[layer - 1] = save_nb;
         b->ks[layer - 1] = save_ks;
+        b->persist[layer - 1] = save_pm;
       }
     }
     if (e != LSX_OK) break;
@@ -1508,6 +1532,16 @@ extern "C" lsx_status lsx_batch_create(lsx_plan* const* plans, lsx_state* const*
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (e != LSX_OK) return cleanup(e);
+  for (int layer = 1; layer <= 2; ++layer)
+    if (b->persist[layer - 1])
+      for (const int32_t* gather : {static_cast<const int32_t*>(nullptr), static_cast<const int32_t*>(b->marker.p)}) {
+        PassArgs a0{};
+        a0.in_pos = gather;
+        a0.persist = b->persist[layer - 1];
+        a0.queue = b->queue.p;
+        if (prepare_persistent(b->fmt, b->w1 ? 1 : 2, b->nb[layer - 1], b->ks[layer - 1], a0) != hipSuccess)
+          return cleanup(fail(LSX_E_HIP, "persistent launch setup failed"));
+      }
   if (hipDeviceSynchronize() != hipSuccess) return cleanup(fail(LSX_E_HIP, "batch setup failed"));
   for (lsx_state* st : b->st) st->nbatches++;
   for (lsx_state* st : b->st) b->bufs.emplace_back(st->buf[0], st->buf[1]);
@@ -1589,9 +1623,11 @@ extern "C" lsx_status lsx_batch_step(lsx_batch* b, int64_t nsteps, void* stream)
   return LSX_OK;
 }
 
-extern "C" lsx_status lsx_batch_tuning(const lsx_batch* b, int32_t layer, int32_t* nb, int32_t* ks, double* pass_us) {
+extern "C" lsx_status lsx_batch_tuning(const lsx_batch* b, int32_t layer, int32_t* nb, int32_t* ks, double* pass_us,
+                                       int32_t* launch_mode) {
   if (!b) return fail(LSX_E_INVALID, "null batch");
   if (layer != 1 && layer != 2) return fail(LSX_E_INVALID, "layer must be 1 or 2");
+  if (launch_mode) *launch_mode = b->persist[layer - 1];
   if (nb) *nb = b->nb[layer - 1];
   if (ks) *ks = b->ks[layer - 1];
   if (pass_us) *pass_us = b->tuned_us[layer - 1];

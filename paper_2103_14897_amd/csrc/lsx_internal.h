@@ -81,6 +81,12 @@ struct PassArgs {
   // s < ncols[f] (TileDesc::wb then counts blocks of 16 NB slots, not of columns)
   const int32_t* cols = nullptr;
   const int32_t* ncols = nullptr;
+  // persistent batched launches: mode (0 none, 1 per-XCD tile queues on device counters,
+  // 2 static stride), 9 device counters that are zero between launches (mode 1) and the
+  // number of tiles in `tiles`
+  int32_t persist = 0;
+  int32_t* queue = nullptr;
+  int32_t ntiles = 0;
   int32_t W = 0;
 };
 
@@ -100,6 +106,9 @@ hipError_t launch_phase_table(hipStream_t s, int64_t N, const double* K2, double
 hipError_t launch_phase_apply(hipStream_t s, int64_t N, int W, const double2* ph, double2* c);
 hipError_t launch_pass(hipStream_t s, int fmt, int W, int ntiles, int nb, int ksplit, const PassArgs& a,
                        bool batched = false);
+// Batched launches with a.persist set: computes (once per kernel) the persistent grid of the pass
+// kernel launch_pass would use, launching nothing, so no occupancy query runs under capture.
+hipError_t prepare_persistent(int fmt, int W, int nb, int ksplit, const PassArgs& a);
 hipError_t launch_reduce(hipStream_t s, int kind, int64_t N, int W, const double2* c, const double* K2, int nv1,
                          const int32_t* nbr1, const double2* v1, int nv2, const int32_t* nbr2, const double2* v2,
                          int nv3, const int32_t* nbr3, const double2* v3, double* partial, int nblocks,

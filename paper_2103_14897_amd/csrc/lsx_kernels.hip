@@ -13,6 +13,8 @@
 
 #include <algorithm>
 #include <cstdlib>
+#include <map>
+#include <mutex>
 
 #include "lsx_internal.h"
 
@@ -480,14 +482,50 @@ __device__ __forceinline__ void mma_group_f32(v4f (&k1)[NB], v4f (&k2)[NB], v4f 
   }
 }
 
+// ---------------------------------------------------------------- persistent batched launches
+// The grid holds what the chip keeps resident (a multiple of 8 workgroups).  The tile list is
+// XCD interleaved (tile i belongs to XCD i mod 8) and workgroup b runs on XCD b mod 8.
+//  persist = 1: workgroup b takes the tiles i = 8 k + (b mod 8), k = 0, 1, ..., of its XCD's
+//    queue through a device atomic counter, so uneven tiles balance dynamically within each
+//    XCD; the claim of the next tile is issued before the current tile runs, so its latency
+//    overlaps the tile's loads.  queue[0..7] are the per-XCD counters and queue[8] counts
+//    finished workgroups; the last workgroup to finish clears all nine, so every launch starts
+//    from zeros without a memset node (graph replays).
+//  persist = 2: workgroup b takes the tiles b, b + G, b + 2G, ... (G = grid size), no atomics.
+// No workgroup waits on another.
+template <typename Tile>
+__device__ __forceinline__ void persistent_tiles(const PassArgs& a0, Tile&& tile) {
+  if (a0.persist == 2) {
+    for (int ti = blockIdx.x; ti < a0.ntiles; ti += gridDim.x) {
+      tile(ti);
+      __syncthreads();  // the tile's LDS is free again
+    }
+    return;
+  }
+  __shared__ int next;
+  const int x = blockIdx.x & 7;
+  if (threadIdx.x == 0) next = 8 * atomicAdd(a0.queue + x, 1) + x;
+  __syncthreads();
+  int ti = next;
+  while (ti < a0.ntiles) {
+    int ahead = 0;
+    if (threadIdx.x == 0) ahead = 8 * atomicAdd(a0.queue + x, 1) + x;
+    tile(ti);
+    __syncthreads();  // the tile's LDS and `next` are free again
+    if (threadIdx.x == 0) next = ahead;
+    __syncthreads();
+    ti = next;
+  }
+  if (threadIdx.x == 0 && atomicAdd(a0.queue + 8, 1) == (int)gridDim.x - 1)
+    for (int i = 0; i < 9; ++i) atomicExch(a0.queue + i, 0);
+}
+
 // FP64: complex128 P, X on v_mfma_f64_16x16x4f64.  Three independent accumulator chains
 // per column block (the 3M products above); groups of U k-steps are double buffered in
 // registers, so the loads of group g+1 are in flight during the MFMAs of g.
 template <int NB, int KS, int U, bool GATHER, bool BATCH>
-__global__ __launch_bounds__(64 * KS) void k_pass_f64(PassArgs a0) {
-  extern __shared__ double red[];
-  if (a0.tcount && (int)blockIdx.x >= *a0.tcount) return;
-  const TileDesc t = a0.tiles[blockIdx.x];
+__device__ __forceinline__ void k_pass_f64_tile(const PassArgs& a0, int ti, double* red) {
+  const TileDesc t = a0.tiles[ti];
   if (t.f < 0) return;
   // batched launches: this tile's system arguments (uniform scalar loads)
   const PassArgs a = BATCH ? a0.batch[t.f] : a0;
@@ -528,13 +566,24 @@ __global__ __launch_bounds__(64 * KS) void k_pass_f64(PassArgs a0) {
   pass_epilogue<NB, KS, false, true>(a, t, acc, red, wc, wok);
 }
 
+template <int NB, int KS, int U, bool GATHER, bool BATCH>
+__global__ __launch_bounds__(64 * KS) void k_pass_f64(PassArgs a0) {
+  extern __shared__ double red[];
+  if (a0.tcount && (int)blockIdx.x >= *a0.tcount) return;
+  k_pass_f64_tile<NB, KS, U, GATHER, BATCH>(a0, blockIdx.x, red);
+}
+
+template <int NB, int KS, int U, bool GATHER>
+__global__ __launch_bounds__(64 * KS) void k_pass_f64_persist(PassArgs a0) {
+  extern __shared__ double red[];
+  persistent_tiles(a0, [&](int ti) { k_pass_f64_tile<NB, KS, U, GATHER, true>(a0, ti, red); });
+}
+
 // Mixed FP32: y = d .* x (FP64) + E x~ with E complex64, x~ = fp32(x), FP32 MFMA
 // accumulation (v_mfma_f32_16x16x4f32, 3M products), same pipelining as the FP64 kernel.
 template <int NB, int KS, int U, bool GATHER, bool BATCH>
-__global__ __launch_bounds__(64 * KS) void k_pass_f32(PassArgs a0) {
-  extern __shared__ double red[];
-  if (a0.tcount && (int)blockIdx.x >= *a0.tcount) return;
-  const TileDesc t = a0.tiles[blockIdx.x];
+__device__ __forceinline__ void k_pass_f32_tile(const PassArgs& a0, int ti, double* red) {
+  const TileDesc t = a0.tiles[ti];
   if (t.f < 0) return;
   // batched launches: this tile's system arguments (uniform scalar loads)
   const PassArgs a = BATCH ? a0.batch[t.f] : a0;
@@ -572,6 +621,19 @@ __global__ __launch_bounds__(64 * KS) void k_pass_f32(PassArgs a0) {
       acc[nb][1][r] = (double)k1[nb][r] + (double)k2[nb][r];
     }
   pass_epilogue<NB, KS, true, false>(a, t, acc, red, wc, wok);
+}
+
+template <int NB, int KS, int U, bool GATHER, bool BATCH>
+__global__ __launch_bounds__(64 * KS) void k_pass_f32(PassArgs a0) {
+  extern __shared__ double red[];
+  if (a0.tcount && (int)blockIdx.x >= *a0.tcount) return;
+  k_pass_f32_tile<NB, KS, U, GATHER, BATCH>(a0, blockIdx.x, red);
+}
+
+template <int NB, int KS, int U, bool GATHER>
+__global__ __launch_bounds__(64 * KS) void k_pass_f32_persist(PassArgs a0) {
+  extern __shared__ double red[];
+  persistent_tiles(a0, [&](int ti) { k_pass_f32_tile<NB, KS, U, GATHER, true>(a0, ti, red); });
 }
 
 // ---------------------------------------------------------------- row-split passes, LDS-staged state
@@ -760,10 +822,8 @@ __device__ __forceinline__ void mma_chunk_bf(v4f (&rr)[NB], v4f (&ii)[NB], v4f (
 }
 
 template <int NB, int KS, int U, bool GATHER, bool BATCH>
-__global__ __launch_bounds__(64 * KS) void k_pass_bf16x3(PassArgs a0) {
-  extern __shared__ double red[];
-  if (a0.tcount && (int)blockIdx.x >= *a0.tcount) return;
-  const TileDesc t = a0.tiles[blockIdx.x];
+__device__ __forceinline__ void k_pass_bf16x3_tile(const PassArgs& a0, int ti, double* red) {
+  const TileDesc t = a0.tiles[ti];
   if (t.f < 0) return;
   // batched launches: this tile's system arguments (uniform scalar loads)
   const PassArgs a = BATCH ? a0.batch[t.f] : a0;
@@ -800,6 +860,19 @@ __global__ __launch_bounds__(64 * KS) void k_pass_bf16x3(PassArgs a0) {
       acc[nb][1][r] = (double)ri[nb][r] + (double)ir[nb][r];
     }
   pass_epilogue<NB, KS, true, false>(a, t, acc, red, wc, wok);
+}
+
+template <int NB, int KS, int U, bool GATHER, bool BATCH>
+__global__ __launch_bounds__(64 * KS) void k_pass_bf16x3(PassArgs a0) {
+  extern __shared__ double red[];
+  if (a0.tcount && (int)blockIdx.x >= *a0.tcount) return;
+  k_pass_bf16x3_tile<NB, KS, U, GATHER, BATCH>(a0, blockIdx.x, red);
+}
+
+template <int NB, int KS, int U, bool GATHER>
+__global__ __launch_bounds__(64 * KS) void k_pass_bf16x3_persist(PassArgs a0) {
+  extern __shared__ double red[];
+  persistent_tiles(a0, [&](int ti) { k_pass_bf16x3_tile<NB, KS, U, GATHER, true>(a0, ti, red); });
 }
 
 // Row-split BF16x3 pass: as k_pass_f32m, with 32-row chunks.  The staging threads split each
@@ -930,10 +1003,8 @@ __global__ __launch_bounds__(64 * MS) void k_pass_bf16m(PassArgs a) {
 // are summed in fixed order.  Mixed formats: E entries (rounded to their storage
 // precision) times the FP64 state, FP64 accumulation, plus the FP64 diagonal term.
 template <int KS, int FMT, bool BATCH>
-__global__ __launch_bounds__(64 * KS) void k_gemv(PassArgs a0) {
-  __shared__ double red[2 * KS * 16];
-  if (a0.tcount && (int)blockIdx.x >= *a0.tcount) return;
-  const TileDesc t = a0.tiles[blockIdx.x];
+__device__ __forceinline__ void k_gemv_tile(const PassArgs& a0, int ti, double* red) {
+  const TileDesc t = a0.tiles[ti];
   if (t.f < 0) return;
   const PassArgs a = BATCH ? a0.batch[t.f] : a0;
   const int r0 = t.r0, L = t.L, rb = t.rb;
@@ -1022,6 +1093,19 @@ __global__ __launch_bounds__(64 * KS) void k_gemv(PassArgs a0) {
       a.Y[a.out_pos ? a.out_pos[p] : p] = make_double2(sr, si);
     }
   }
+}
+
+template <int KS, int FMT, bool BATCH>
+__global__ __launch_bounds__(64 * KS) void k_gemv(PassArgs a0) {
+  __shared__ double red[2 * KS * 16];
+  if (a0.tcount && (int)blockIdx.x >= *a0.tcount) return;
+  k_gemv_tile<KS, FMT, BATCH>(a0, blockIdx.x, red);
+}
+
+template <int KS, int FMT>
+__global__ __launch_bounds__(64 * KS) void k_gemv_persist(PassArgs a0) {
+  __shared__ double red[2 * KS * 16];
+  persistent_tiles(a0, [&](int ti) { k_gemv_tile<KS, FMT, true>(a0, ti, red); });
 }
 
 // ---------------------------------------------------------------- FP64 reductions
@@ -1207,9 +1291,55 @@ static int prefetch_depth() {
   return u;
 }
 
+// Set while prepare_persistent() runs: persistent launchers compute their grid (and so query
+// the kernel's occupancy) and return without launching.
+static thread_local bool g_prepare_only = false;
+
+// Grid of a persistent launch: the kernel's resident workgroups per CU times the CU count,
+// rounded down to a multiple of 8 (whole XCD rounds), at most the tile count rounded up to 8.
+// The occupancy of each kernel is queried once.
+static unsigned persistent_grid(const void* fn, int threads, size_t shm, int ntiles) {
+  static std::map<const void*, int> cap;
+  static std::mutex mu;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = cap.find(fn);
+  if (it == cap.end()) {
+    int dev = 0, ncu = 256, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      ncu = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, threads, shm) != hipSuccess || per < 1) per = 1;
+    it = cap.emplace(fn, std::max(8, (per * ncu) / 8 * 8)).first;
+  }
+  const int want = (ntiles + 7) / 8 * 8;
+  return (unsigned)std::max(8, std::min(want, it->second));
+}
+
+template <int NB, int KS, int U, bool G>
+static hipError_t launch_mfma_persist(hipStream_t s, int fmt, int ntiles, const PassArgs& a0) {
+  PassArgs a = a0;
+  a.ntiles = ntiles;
+  const size_t shm = KS > 1 ? (size_t)KS * NB * 2 * 4 * 64 * sizeof(double) : 0;
+  const void* fn = fmt == PF_F64   ? reinterpret_cast<const void*>(&k_pass_f64_persist<NB, KS, U, G>)
+                   : fmt == PF_F32 ? reinterpret_cast<const void*>(&k_pass_f32_persist<NB, KS, U, G>)
+                                   : reinterpret_cast<const void*>(&k_pass_bf16x3_persist<NB, KS, 1, G>);
+  const dim3 grid(persistent_grid(fn, 64 * KS, shm, ntiles));
+  if (g_prepare_only) return hipSuccess;
+  if (fmt == PF_F64)
+    hipLaunchKernelGGL((k_pass_f64_persist<NB, KS, U, G>), grid, dim3(64 * KS), shm, s, a);
+  else if (fmt == PF_F32)
+    hipLaunchKernelGGL((k_pass_f32_persist<NB, KS, U, G>), grid, dim3(64 * KS), shm, s, a);
+  else
+    hipLaunchKernelGGL((k_pass_bf16x3_persist<NB, KS, 1, G>), grid, dim3(64 * KS), shm, s, a);
+  return hipGetLastError();
+}
+
 template <int NB, int KS, int U, bool G, bool B>
 static hipError_t launch_mfma_u(hipStream_t s, int fmt, int ntiles, const PassArgs& a) {
   const size_t shm = KS > 1 ? (size_t)KS * NB * 2 * 4 * 64 * sizeof(double) : 0;
+  if constexpr (B) {
+    if (a.persist) return launch_mfma_persist<NB, KS, U, G>(s, fmt, ntiles, a);
+  }
   if (fmt == PF_F64)
     hipLaunchKernelGGL((k_pass_f64<NB, KS, U, G, B>), dim3(ntiles), dim3(64 * KS), shm, s, a);
   else if (fmt == PF_F32)
@@ -1236,7 +1366,25 @@ static hipError_t launch_mfma(hipStream_t s, int fmt, int ntiles, const PassArgs
 }
 
 template <int KS, bool B>
-static hipError_t launch_gemv(hipStream_t s, int fmt, int ntiles, const PassArgs& a) {
+static hipError_t launch_gemv(hipStream_t s, int fmt, int ntiles, const PassArgs& a0) {
+  PassArgs a = a0;
+  if constexpr (B) {
+    if (a.persist) {
+      a.ntiles = ntiles;
+      const void* fn = fmt == PF_F64   ? reinterpret_cast<const void*>(&k_gemv_persist<KS, PF_F64>)
+                       : fmt == PF_F32 ? reinterpret_cast<const void*>(&k_gemv_persist<KS, PF_F32>)
+                                       : reinterpret_cast<const void*>(&k_gemv_persist<KS, PF_BF16X3>);
+      const dim3 grid(persistent_grid(fn, 64 * KS, 0, ntiles));
+      if (g_prepare_only) return hipSuccess;
+      if (fmt == PF_F64)
+        hipLaunchKernelGGL((k_gemv_persist<KS, PF_F64>), grid, dim3(64 * KS), 0, s, a);
+      else if (fmt == PF_F32)
+        hipLaunchKernelGGL((k_gemv_persist<KS, PF_F32>), grid, dim3(64 * KS), 0, s, a);
+      else
+        hipLaunchKernelGGL((k_gemv_persist<KS, PF_BF16X3>), grid, dim3(64 * KS), 0, s, a);
+      return hipGetLastError();
+    }
+  }
   if (fmt == PF_F64)
     hipLaunchKernelGGL((k_gemv<KS, PF_F64, B>), dim3(ntiles), dim3(64 * KS), 0, s, a);
   else if (fmt == PF_F32)
@@ -1308,6 +1456,14 @@ hipError_t launch_pass(hipStream_t s, int fmt, int W, int ntiles, int nb, int ks
   LSX_MFMA_CASE(4, 4)
 #undef LSX_MFMA_CASE
   return hipErrorInvalidValue;
+}
+
+hipError_t prepare_persistent(int fmt, int W, int nb, int ksplit, const PassArgs& a) {
+  if (!a.persist) return hipSuccess;
+  g_prepare_only = true;
+  const hipError_t e = launch_pass(nullptr, fmt, W, 1, nb, ksplit, a, true);
+  g_prepare_only = false;
+  return e;
 }
 
 hipError_t launch_reduce(hipStream_t s, int kind, int64_t N, int W, const double2* c, const double* K2, int nv1,

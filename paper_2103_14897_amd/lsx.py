@@ -60,7 +60,7 @@ _SIGS = {
     "lsx_observables": (C.c_int, [_p, _p, C.c_uint32, _dp, _p]),
     "lsx_batch_create": (C.c_int, [C.POINTER(_p), C.POINTER(_p), C.c_int32, C.POINTER(_p)]),
     "lsx_batch_step": (C.c_int, [_p, C.c_int64, _p]),
-    "lsx_batch_tuning": (C.c_int, [_p, C.c_int32, _i32p, _i32p, _dp]),
+    "lsx_batch_tuning": (C.c_int, [_p, C.c_int32, _i32p, _i32p, _dp, _i32p]),
     "lsx_batch_destroy": (C.c_int, [_p]),
     "lsx_si_step": (C.c_int, [_p, _p, C.c_int64, _p]),
     "lsx_sampler_create": (C.c_int, [_p, _p, C.c_int32, C.c_int32, C.c_double, C.POINTER(_p)]),
@@ -326,9 +326,11 @@ class Batch:
         _check(lib().lsx_batch_step(self.h, int(nsteps), _stream(stream)))
 
     def tuning(self, layer):
-        nb, ks, us = C.c_int32(), C.c_int32(), C.c_double()
-        _check(lib().lsx_batch_tuning(self.h, int(layer), C.byref(nb), C.byref(ks), C.byref(us)))
-        return nb.value, ks.value, us.value
+        """(nb, ks, pass_us, launch_mode) chosen for `layer`'s grouped passes (launch_mode: 0 one
+        workgroup per tile, 1 persistent with tile queues, 2 persistent with a static stride)."""
+        nb, ks, us, mode = C.c_int32(), C.c_int32(), C.c_double(), C.c_int32()
+        _check(lib().lsx_batch_tuning(self.h, int(layer), C.byref(nb), C.byref(ks), C.byref(us), C.byref(mode)))
+        return nb.value, ks.value, us.value, mode.value
 
     def destroy(self):
         if self.h:
