@@ -577,10 +577,10 @@ def main():
         "vs_baseline": None,
         "dtype": DTYPE[best],
         "data": "synthetic",
-        "config": {"workload": {"chain": "chain1d_golden_Ec2e4_W64_strang_tau1e-3",
-                                "twisted": "twisted_tri_pm2.5deg_Ec6500_W128_strang_tau5e-3",
-                                "twisted1": "twisted_tri_pm2.5deg_Ec6500_W1_strang_tau5e-3",
-                                "tiny": "chain1d_golden_Ec200_W1_strang_tau1e-2"}[args.workload],
+        "config": {"workload": {"chain": f"chain1d_golden_Ec2e4_W64_{args.scheme}_tau1e-3",
+                                "twisted": f"twisted_tri_pm2.5deg_Ec6500_W128_{args.scheme}_tau5e-3",
+                                "twisted1": f"twisted_tri_pm2.5deg_Ec6500_W1_{args.scheme}_tau5e-3",
+                                "tiny": f"chain1d_golden_Ec200_W1_{args.scheme}_tau1e-2"}[args.workload],
                    "N": N, "W": W, "fibres": [S.nfibres[1], S.nfibres[2]], "path": best, "kappa": args.kappa,
                    "scheme": args.scheme},
         "roofline": roof,
