@@ -243,6 +243,11 @@ static lsx_status create_system(int32_t d, int32_t nl, const double* const* A, d
   std::vector<int32_t> cand[kMaxLayers];
   std::vector<double> s2[kMaxLayers];
   for (int j = 0; j < nl; ++j) layer_candidates(d, sys->A[j], sys->B[j], lim, cand[j], s2[j]);
+  // the combinations walked below bound the set from above; refuse sizes that could not be
+  // indexed anyway before walking them
+  double combos = 1.0;
+  for (int j = 0; j < nl; ++j) combos *= (double)s2[j].size();
+  if (combos > 64.0 * 2147483648.0) return fail(LSX_E_INVALID, "lifted index set too large");
   int64_t idx[kMaxLayers] = {0, 0, 0};
   std::vector<int32_t> row(S);
   // odometer over the candidate lists, last layer fastest

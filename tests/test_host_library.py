@@ -124,3 +124,7 @@ def test_layered_errors():
     assert e.value.code == lsx.LSX_E_NOT_HERMITIAN
     with pytest.raises(ValueError):
         lsx.System.layers(1, [one, [[1.6]], [[1.3]]], 100.0, pots=[{}, {}])
+    # a cutoff whose candidate combinations exceed what could be indexed fails at once
+    with pytest.raises(lsx.LsxError) as e:
+        lsx.System.layers(2, [wl.TRIANGULAR] * 3, 3.0e5)
+    assert e.value.code == lsx.LSX_E_INVALID
