@@ -338,3 +338,28 @@ def test_yoshida_coefficients():
     g1 = 1.0 / (2.0 - 2.0 ** (1.0 / 3.0))
     g0 = 1.0 - 2.0 * g1
     assert abs(2 * g1 + g0 - 1.0) < 1e-15 and abs(2 * g1 ** 3 + g0 ** 3) < 1e-14
+
+
+def test_cutoff_convergence_is_monotone_and_super_algebraic():
+    """The paper states only that a larger energy cutoff is more accurate (Sec. 3).  For data
+    that decays in the lifted index (the plane-wave coefficients of a smooth state), the exact
+    lifted flow exp(-i T H) truncated at Ec approaches the flow at a much larger cutoff
+    monotonically, and faster than any fixed power of Ec (analytic potentials): the apparent
+    order per doubling of Ec keeps growing."""
+    T, k0, sigma, alpha = 1.0, np.array([[3.0]]), 2.0, 0.02
+    ref_spec = wl.chain_system(1600.0)
+    Oref = lifted_sys(ref_spec)
+    cref = reference.exact_flow(Oref, wl.decaying_state(ref_spec, Oref.mn, k0, sigma, alpha), T)
+    where = {tuple(int(x) for x in r): i for i, r in enumerate(Oref.mn)}
+    errs = []
+    for Ec in (50.0, 100.0, 200.0, 400.0, 800.0):
+        spec = wl.chain_system(Ec)
+        O = lifted_sys(spec)
+        c = reference.exact_flow(O, wl.decaying_state(spec, O.mn, k0, sigma, alpha), T)
+        full = np.zeros_like(cref)
+        full[[where[tuple(int(x) for x in r)] for r in O.mn]] = c  # every smaller set nests in the larger
+        errs.append(np.linalg.norm(full - cref) / np.linalg.norm(cref))
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
+    assert all(errs[i + 1] < errs[i] for i in range(len(errs) - 1)), errs
+    assert orders[-1] > orders[-2] > orders[-3] > 3.0, orders
+    assert errs[-1] < 1e-5, errs
