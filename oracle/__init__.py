@@ -17,18 +17,21 @@ splitting    fibre Hamiltonians, exact fibre propagators via eigh, the kinetic
 observables  mass (eq. 2.3 via orthonormality 3.1), energy (eq. 2.4), fibre masses
 reference    brute-force exponentials of the full lifted Hamiltonian and a
              direct commensurate-supercell computation used to pin the rest
-multilayer   index set, fibres, fibre Hamiltonians and Lie / Strang layer splitting
-             for L >= 2 layers (the generalisation of Secs. 2-4)
+multilayer   index set, fibres, fibre Hamiltonians and Lie / Strang / Yoshida layer
+             splitting for L >= 2 layers (the generalisation of Secs. 2-4)
+blocks       lifted systems whose layers share index blocks (Example 3 of Sec. 6:
+             a direction periodic for every layer), split like `multilayer`
 stochastic   semi-implicit (Alg. 1) and random batch (Alg. 4) steps, stochastic
              layer splitting with an importance-sampling proposal, the proposal
              network (MLP forward/backward), its variance objective and Adam
 
 Parity status
 -------------
-Every function here is pinned by tests in ``tests/test_oracle_pins.py`` and
-``tests/test_stochastic_pins.py``, ``tests/test_multilayer_pins.py`` against
+Every function here is pinned by tests in ``tests/test_oracle_pins.py``,
+``tests/test_stochastic_pins.py``, ``tests/test_multilayer_pins.py`` and
+``tests/test_blocks_pins.py`` against
 closed forms, brute force, invariants or an independent supercell computation,
 except where a function's docstring says "parity unpinned".
 """
 
-from . import lifted, splitting, observables, reference, stochastic, multilayer  # noqa: F401
+from . import lifted, splitting, observables, reference, stochastic, multilayer, blocks  # noqa: F401
