@@ -123,6 +123,36 @@ lsx_status lsx_system_create_layers(int32_t d, int32_t nlayers, const double* co
                                     const int32_t* nv, const int32_t* const* v_idx, const double* const* v_re,
                                     const double* const* v_im, lsx_system** out);
 
+/*
+ * lsx_system_create_blocks -- a lifted system whose layers may share index blocks (Example 3
+ * of Sec. 6: a direction that is periodic for every layer is lifted once and coupled by every
+ * layer's potential).
+ *
+ *  D            physical dimension, 1 or 2.
+ *  nblocks      1 to 4 index blocks; block b is an integer vector m_b of block_dim[b] (1 or 2)
+ *               entries with embedding R[b] (D x block_dim[b], column-major: column c is the
+ *               wavevector of entry c), so a lifted index (m_0, ..., m_{B-1}) is the plane
+ *               wave with K = sum_b R_b m_b.  At most 6 index entries in total.
+ *  group        cutoff group of every block (numbered 0, 1, ... without gaps): a lifted index
+ *               is kept when sum_{b in g} |R_b m_b|^2 <= 2 Ec (1 + 1e-12) for every group g.
+ *  nlayers      2 or 3 layers; layer j couples the blocks layer_first[j] .. layer_first[j] +
+ *               layer_count[j] - 1, and the last layer must couple the last block.
+ *  nv, v_idx, v_re, v_im
+ *               layer j's Fourier coefficients as in lsx_system_create, each index having
+ *               as many entries as the layer's blocks together: V^j maps (m) to (m') when
+ *               the coupled entries differ by the coefficient's index and all others agree.
+ *
+ * H = kappa D + sum_j ((1 - kappa)/nlayers D + V^j).  Canonical order is lexicographic in
+ * (m_0, ..., m_{B-1}); a layer-j fibre fixes every entry outside the layer's blocks.  Plans,
+ * states, lsx_step, lsx_fibre_pass, lsx_phase and lsx_observables accept these systems as
+ * any other (the schemes allowed for their number of layers); batches, samplers and the
+ * semi-implicit step reject them.  Host-only; touches no GPU.
+ */
+lsx_status lsx_system_create_blocks(int32_t D, int32_t nblocks, const int32_t* block_dim, const double* const* R,
+                                    const int32_t* group, double Ec, int32_t nlayers, const int32_t* layer_first,
+                                    const int32_t* layer_count, const int32_t* nv, const int32_t* const* v_idx,
+                                    const double* const* v_re, const double* const* v_im, lsx_system** out);
+
 /* Number of layers and, if nfibres is not NULL, the fibre count of every layer (nlayers
  * int64 entries). */
 lsx_status lsx_system_layers(const lsx_system* sys, int32_t* nlayers, int64_t* nfibres);
@@ -130,8 +160,9 @@ lsx_status lsx_system_layers(const lsx_system* sys, int32_t* nlayers, int64_t* n
 /* Sizes: N = |I|, and the number of fibres of layers 1 and 2.  Any output pointer may be NULL. */
 lsx_status lsx_system_size(const lsx_system* sys, int64_t* N, int64_t* nfibres1, int64_t* nfibres2);
 
-/* The lifted index set: mn is N*nlayers*d int32 (host), row i = (m_1, ..., m_nlayers) of
- * index i (for two layers (m_1..m_d, n_1..n_d)). */
+/* The lifted index set: mn is N*S int32 (host), row i the lifted index of coefficient i: S =
+ * nlayers*d entries (m_1, ..., m_nlayers) for systems built from lattices (for two layers
+ * (m_1..m_d, n_1..n_d)), the concatenated blocks for lsx_system_create_blocks. */
 lsx_status lsx_index_get(const lsx_system* sys, int32_t* mn);
 
 /*

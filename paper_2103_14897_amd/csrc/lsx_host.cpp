@@ -82,23 +82,37 @@ struct FibreTable {
   int maxL = 0;
 };
 
-// Up to kMaxLayers layers; the lifted index of row i is (m_1, ..., m_nl), each m_j in Z^d.
+// The lifted index of row i is a sequence of integer blocks (m_0, ..., m_{B-1}), block b of
+// dimension dim_b with physical embedding R_b (K = sum_b R_b m_b).  Layer j's potential
+// couples the contiguous index columns [lown[j], lown[j] + ldim[j]).  Systems built from
+// lattices have one block per layer (the lifted index (m_1, ..., m_nl), each m_j in Z^d).
 static constexpr int kMaxLayers = 3;
+static constexpr int kMaxBlocks = 4;
+static constexpr int kMaxIndex = 6;  // entries of a lifted index
 
 struct lsx_system {
-  int d = 1;
-  int nl = 2;  // number of layers
+  int d = 1;          // layer dimension (systems built from lattices); physical dimension otherwise
+  int nl = 2;         // number of layers
+  bool standard = true;  // built from lattices, one block per layer
   double A[kMaxLayers][4] = {};
   double B[kMaxLayers][4] = {};  // reciprocal 2 pi A^{-T}, row-major d x d
+  int S = 0;                     // entries of a lifted index
+  int lown[kMaxLayers] = {}, ldim[kMaxLayers] = {};
   double Ec = 0.0;
   int cutoff = 0;
   int64_t N = 0;
-  std::vector<int32_t> mn;  // N * nl d
-  std::vector<double> K2;   // |G_1 m_1 + ... + G_nl m_nl|^2
+  std::vector<int32_t> mn;  // N * S
+  std::vector<double> K2;   // |K|^2
   Stencil pot[kMaxLayers];
   FibreTable fib[kMaxLayers];
-  std::vector<int32_t> nbr[kMaxLayers];  // N * nv_j: row with m_j shifted by -p, or -1
+  std::vector<int32_t> nbr[kMaxLayers];  // N * nv_j: row with layer j's columns shifted by -p, or -1
   int nplans = 0;
+};
+
+// One index block: dimension and physical embedding R (row-major D x dim).
+struct BlockSpec {
+  int dim = 1;
+  double R[4] = {};
 };
 
 // A given column-major (A[k + d*c] = row k, column c); returns B = 2 pi A^{-T} row-major.
@@ -119,33 +133,56 @@ static bool reciprocal(int d, const double* A, double* B) {
   return true;
 }
 
-// All integer vectors m with |B m|^2 <= lim, lexicographic order, and their |B m|^2.
-static void layer_candidates(int d, const double* A, const double* B, double lim, std::vector<int32_t>& out,
+// All integer vectors m of a block with |R m|^2 <= lim (R row-major D x dim, full column
+// rank), lexicographic order, and their |R m|^2.  |m_k| <= |row_k(R^+)| |R m| with
+// |row_k(R^+)|^2 = ((R^T R)^{-1})_kk bounds the search.  False if R^T R is singular.
+static bool block_candidates(int D, const BlockSpec& b, double lim, std::vector<int32_t>& out,
                              std::vector<double>& s2) {
-  // |m_k| = |(B^{-1} G)_k| <= |row_k(B^{-1})| |G|, row_k(B^{-1}) = column k of A / (2 pi)
-  const double r = std::sqrt(lim);
+  const int dim = b.dim;
+  double G[4] = {};
+  for (int p = 0; p < dim; ++p)
+    for (int q = 0; q < dim; ++q)
+      for (int k = 0; k < D; ++k) G[p * dim + q] += b.R[k * dim + p] * b.R[k * dim + q];
+  double Ginv_diag[2];
+  if (dim == 1) {
+    if (!(G[0] > 0.0) || !std::isfinite(G[0])) return false;
+    Ginv_diag[0] = 1.0 / G[0];
+  } else {
+    const double det = G[0] * G[3] - G[1] * G[2];
+    if (!(det > 1e-300 * std::max(1.0, G[0] * G[3])) || !std::isfinite(det)) return false;
+    Ginv_diag[0] = G[3] / det;
+    Ginv_diag[1] = G[0] / det;
+  }
   int bound[2] = {0, 0};
-  for (int k = 0; k < d; ++k) {
-    double nrm = 0.0;
-    for (int i = 0; i < d; ++i) nrm += A[i + d * k] * A[i + d * k];
-    bound[k] = (int)std::floor(r * std::sqrt(nrm) / (2.0 * M_PI)) + 1;
+  for (int k = 0; k < dim; ++k) {
+    const double x = std::floor(std::sqrt(lim * Ginv_diag[k])) + 1.0;
+    if (!(x < 1e6)) return false;
+    bound[k] = (int)x;
   }
   out.clear();
   s2.clear();
-  if (d == 1) {
-    for (int m = -bound[0]; m <= bound[0]; ++m) {
-      const double g = B[0] * m;
-      const double s = g * g;
+  auto norm2 = [&](const int32_t* m) {
+    double s = 0.0;
+    for (int k = 0; k < D; ++k) {
+      double g = 0.0;
+      for (int c = 0; c < dim; ++c) g += b.R[k * dim + c] * m[c];
+      s += g * g;
+    }
+    return s;
+  };
+  if (dim == 1) {
+    for (int32_t m = -bound[0]; m <= bound[0]; ++m) {
+      const double s = norm2(&m);
       if (s <= lim) {
         out.push_back(m);
         s2.push_back(s);
       }
     }
   } else {
-    for (int m0 = -bound[0]; m0 <= bound[0]; ++m0)
-      for (int m1 = -bound[1]; m1 <= bound[1]; ++m1) {
-        const double g0 = B[0] * m0 + B[1] * m1, g1 = B[2] * m0 + B[3] * m1;
-        const double s = g0 * g0 + g1 * g1;
+    for (int32_t m0 = -bound[0]; m0 <= bound[0]; ++m0)
+      for (int32_t m1 = -bound[1]; m1 <= bound[1]; ++m1) {
+        const int32_t m[2] = {m0, m1};
+        const double s = norm2(m);
         if (s <= lim) {
           out.push_back(m0);
           out.push_back(m1);
@@ -153,6 +190,7 @@ static void layer_candidates(int d, const double* A, const double* B, double lim
         }
       }
   }
+  return true;
 }
 
 // 64-bit key of an integer vector: 16 bits per entry up to 4 entries, 10 bits up to 6
@@ -190,7 +228,7 @@ static lsx_status build_stencil(int d, int nv, const int32_t* idx, const double*
   st.real = true;
   const double tol = 1e-14 * vmax;
   for (int e = 0; e < nv; ++e) {
-    int32_t neg[2];
+    int32_t neg[kMaxIndex];
     for (int k = 0; k < d; ++k) neg[k] = -idx[e * d + k];
     auto it = pos.find(pack_key(neg, d));
     if (it == pos.end()) {
@@ -208,65 +246,45 @@ static lsx_status build_stencil(int d, int nv, const int32_t* idx, const double*
 
 extern "C" const char* lsx_last_error(void) { return g_err.c_str(); }
 
-// The lifted cutoff set of nl layers (Sec. 3; more than two layers as in Sec. 2): the
-// candidate indices of every layer (lexicographic), combined with m_1 outermost, kept when
-// sum_j |G_j m_j|^2 <= 2 Ec (ball, relative tolerance 1e-12) or each term is (product);
-// then |K|^2, the fibres of every layer and the potentials' neighbour tables.
-static lsx_status create_system(int32_t d, int32_t nl, const double* const* A, double Ec, int32_t cutoff,
-                                const int32_t* nv, const int32_t* const* v_idx, const double* const* v_re,
-                                const double* const* v_im, lsx_system** out) {
-  if (!out || !A) return fail(LSX_E_INVALID, "null argument");
-  if (d != 1 && d != 2) return fail(LSX_E_INVALID, "d must be 1 or 2");
-  if (nl < 2 || nl > kMaxLayers) return fail(LSX_E_INVALID, "number of layers must be 2 or 3");
-  for (int j = 0; j < nl; ++j)
-    if (!A[j]) return fail(LSX_E_INVALID, "null lattice matrix");
-  if (!(Ec > 0.0) || !std::isfinite(Ec)) return fail(LSX_E_INVALID, "Ec must be finite and > 0");
-  if (cutoff != LSX_CUTOFF_BALL && cutoff != LSX_CUTOFF_PRODUCT) return fail(LSX_E_INVALID, "bad cutoff");
-  std::unique_ptr<lsx_system> sys(new (std::nothrow) lsx_system());
-  if (!sys) return fail(LSX_E_OOM, "host allocation failed");
-  sys->d = d;
-  sys->nl = nl;
-  sys->Ec = Ec;
-  sys->cutoff = cutoff;
-  for (int j = 0; j < nl; ++j) {
-    for (int k = 0; k < d * d; ++k) sys->A[j][k] = A[j][k];
-    if (!reciprocal(d, sys->A[j], sys->B[j]))
-      return fail(LSX_E_INVALID, "lattice matrix A" + std::to_string(j + 1) + " is singular or non-finite");
-  }
-  for (int j = 0; j < nl; ++j)
-    LSX_TRY(build_stencil(d, nv ? nv[j] : 0, v_idx ? v_idx[j] : nullptr, v_re ? v_re[j] : nullptr,
-                          v_im ? v_im[j] : nullptr, sys->pot[j], j + 1));
-
-  // lifted index set
+// The lifted cutoff set (Sec. 3; more than two layers as in Sec. 2; shared blocks as in
+// Example 3 of Sec. 6): the candidate vectors of every block (lexicographic), combined with
+// block 0 outermost, kept when every cutoff group g has sum_{b in g} |R_b m_b|^2 <= 2 Ec
+// (relative tolerance 1e-12); then |K|^2, the fibres of every layer (fixing the columns the
+// layer's potential does not couple) and the potentials' neighbour tables.  The stencils,
+// sys->nl, sys->lown and sys->ldim are set by the caller.
+static lsx_status build_lifted(lsx_system* sys, int D, int nb, const BlockSpec* blk, const int* group, double Ec) {
   const double lim = 2.0 * Ec * (1.0 + 1e-12);
-  const int S = nl * d;
-  std::vector<int32_t> cand[kMaxLayers];
-  std::vector<double> s2[kMaxLayers];
-  for (int j = 0; j < nl; ++j) layer_candidates(d, sys->A[j], sys->B[j], lim, cand[j], s2[j]);
+  int S = 0;
+  for (int b = 0; b < nb; ++b) S += blk[b].dim;
+  sys->S = S;
+  const int nl = sys->nl;
+  std::vector<int32_t> cand[kMaxBlocks];
+  std::vector<double> s2[kMaxBlocks];
+  for (int b = 0; b < nb; ++b)
+    if (!block_candidates(D, blk[b], lim, cand[b], s2[b]))
+      return fail(LSX_E_INVALID, "block " + std::to_string(b) + " has a singular or non-finite embedding");
   // the combinations walked below bound the set from above; refuse sizes that could not be
   // indexed anyway before walking them
   double combos = 1.0;
-  for (int j = 0; j < nl; ++j) combos *= (double)s2[j].size();
+  for (int b = 0; b < nb; ++b) combos *= (double)s2[b].size();
   if (combos > 64.0 * 2147483648.0) return fail(LSX_E_INVALID, "lifted index set too large");
-  int64_t idx[kMaxLayers] = {0, 0, 0};
-  std::vector<int32_t> row(S);
-  // odometer over the candidate lists, last layer fastest
+  int ngroups = 0;
+  for (int b = 0; b < nb; ++b) ngroups = std::max(ngroups, group[b] + 1);
+  int64_t idx[kMaxBlocks] = {0, 0, 0, 0};
+  // odometer over the candidate lists, last block fastest
   bool any = true;
-  for (int j = 0; j < nl; ++j) any = any && !s2[j].empty();
+  for (int b = 0; b < nb; ++b) any = any && !s2[b].empty();
   while (any) {
-    double sum = 0.0;
+    double sum[kMaxBlocks] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = 0; b < nb; ++b) sum[group[b]] += s2[b][idx[b]];
     bool keep = true;
-    for (int j = 0; j < nl; ++j) {
-      sum += s2[j][idx[j]];
-      if (cutoff == LSX_CUTOFF_PRODUCT && !(s2[j][idx[j]] <= lim)) keep = false;
-    }
-    if (cutoff == LSX_CUTOFF_BALL && !(sum <= lim)) keep = false;
+    for (int g = 0; g < ngroups; ++g) keep = keep && (sum[g] <= lim);
     if (keep)
-      for (int j = 0; j < nl; ++j)
-        for (int k = 0; k < d; ++k) sys->mn.push_back(cand[j][idx[j] * d + k]);
-    int j = nl - 1;
-    while (j >= 0 && ++idx[j] == (int64_t)s2[j].size()) idx[j--] = 0;
-    if (j < 0) break;
+      for (int b = 0; b < nb; ++b)
+        for (int k = 0; k < blk[b].dim; ++k) sys->mn.push_back(cand[b][idx[b] * blk[b].dim + k]);
+    int b = nb - 1;
+    while (b >= 0 && ++idx[b] == (int64_t)s2[b].size()) idx[b--] = 0;
+    if (b < 0) break;
   }
   sys->N = (int64_t)sys->mn.size() / S;
   if (sys->N >= (int64_t)1 << 31) return fail(LSX_E_INVALID, "lifted index set too large");
@@ -278,22 +296,22 @@ static lsx_status create_system(int32_t d, int32_t nl, const double* const* A, d
   for (int64_t i = 0; i < N; ++i) {
     const int32_t* r = &sys->mn[i * S];
     double s = 0.0;
-    for (int k = 0; k < d; ++k) {
+    for (int k = 0; k < D; ++k) {
       double g = 0.0;
-      for (int j = 0; j < nl; ++j)
-        for (int c = 0; c < d; ++c) g += sys->B[j][k * d + c] * r[j * d + c];
+      for (int b = 0, o = 0; b < nb; o += blk[b].dim, ++b)
+        for (int c = 0; c < blk[b].dim; ++c) g += blk[b].R[k * blk[b].dim + c] * r[o + c];
       s += g * g;
     }
     sys->K2[i] = s;
   }
 
-  // fibres of layer j: rows with equal indices outside block j, keys lexicographic (layer
-  // order), rows ascending; the last layer's fibres are contiguous runs of the canonical order
+  // fibres of layer j: rows with equal indices outside the layer's columns, keys
+  // lexicographic (column order), rows ascending
   for (int layer = 1; layer <= nl; ++layer) {
-    const int own = (layer - 1) * d;
+    const int own = sys->lown[layer - 1], dj = sys->ldim[layer - 1];
     auto key_less = [&](int32_t x, int32_t y) {
       for (int k = 0; k < S; ++k) {
-        if (k >= own && k < own + d) continue;
+        if (k >= own && k < own + dj) continue;
         const int32_t a = sys->mn[(int64_t)x * S + k], b = sys->mn[(int64_t)y * S + k];
         if (a != b) return a < b;
       }
@@ -314,27 +332,127 @@ static lsx_status create_system(int32_t d, int32_t nl, const double* const* A, d
     for (size_t f = 0; f + 1 < ft.ptr.size(); ++f) ft.maxL = std::max(ft.maxL, ft.ptr[f + 1] - ft.ptr[f]);
   }
 
-  // neighbour tables of the potential terms: row with m_j - p, other blocks fixed
+  // neighbour tables of the potential terms: row with the layer's columns shifted by -p,
+  // the other columns fixed
   std::unordered_map<uint64_t, int32_t> where;
   where.reserve((size_t)N * 2);
   for (int64_t i = 0; i < N; ++i) where[pack_key(&sys->mn[i * S], S)] = (int32_t)i;
   for (int j = 0; j < nl; ++j) {
     const Stencil& St = sys->pot[j];
+    const int own = sys->lown[j], dj = sys->ldim[j];
     sys->nbr[j].assign((size_t)N * St.nv, -1);
     std::vector<int32_t> v(S);
     for (int64_t i = 0; i < N; ++i)
       for (int p = 0; p < St.nv; ++p) {
         for (int k = 0; k < S; ++k) v[k] = sys->mn[i * S + k];
         bool fits = true;
-        for (int k = 0; k < d; ++k) {
-          v[j * d + k] -= St.idx[p * d + k];
-          fits = fits && std::abs(v[j * d + k]) <= keymax;
+        for (int k = 0; k < dj; ++k) {
+          v[own + k] -= St.idx[p * dj + k];
+          fits = fits && std::abs(v[own + k]) <= keymax;
         }
         if (!fits) continue;
         auto it = where.find(pack_key(v.data(), S));
         if (it != where.end()) sys->nbr[j][i * St.nv + p] = it->second;
       }
   }
+  return LSX_OK;
+}
+
+// Layers from lattices (Sec. 2): one block per layer with embedding G_j = 2 pi A_j^{-T};
+// the ball cutoff is one group over all blocks, the product cutoff one group per block.
+static lsx_status create_system(int32_t d, int32_t nl, const double* const* A, double Ec, int32_t cutoff,
+                                const int32_t* nv, const int32_t* const* v_idx, const double* const* v_re,
+                                const double* const* v_im, lsx_system** out) {
+  if (!out || !A) return fail(LSX_E_INVALID, "null argument");
+  if (d != 1 && d != 2) return fail(LSX_E_INVALID, "d must be 1 or 2");
+  if (nl < 2 || nl > kMaxLayers) return fail(LSX_E_INVALID, "number of layers must be 2 or 3");
+  for (int j = 0; j < nl; ++j)
+    if (!A[j]) return fail(LSX_E_INVALID, "null lattice matrix");
+  if (!(Ec > 0.0) || !std::isfinite(Ec)) return fail(LSX_E_INVALID, "Ec must be finite and > 0");
+  if (cutoff != LSX_CUTOFF_BALL && cutoff != LSX_CUTOFF_PRODUCT) return fail(LSX_E_INVALID, "bad cutoff");
+  std::unique_ptr<lsx_system> sys(new (std::nothrow) lsx_system());
+  if (!sys) return fail(LSX_E_OOM, "host allocation failed");
+  sys->d = d;
+  sys->nl = nl;
+  sys->standard = true;
+  sys->Ec = Ec;
+  sys->cutoff = cutoff;
+  BlockSpec blk[kMaxLayers];
+  int group[kMaxLayers];
+  for (int j = 0; j < nl; ++j) {
+    for (int k = 0; k < d * d; ++k) sys->A[j][k] = A[j][k];
+    if (!reciprocal(d, sys->A[j], sys->B[j]))
+      return fail(LSX_E_INVALID, "lattice matrix A" + std::to_string(j + 1) + " is singular or non-finite");
+    blk[j].dim = d;
+    for (int k = 0; k < d * d; ++k) blk[j].R[k] = sys->B[j][k];
+    group[j] = cutoff == LSX_CUTOFF_BALL ? 0 : j;
+    sys->lown[j] = j * d;
+    sys->ldim[j] = d;
+  }
+  for (int j = 0; j < nl; ++j)
+    LSX_TRY(build_stencil(d, nv ? nv[j] : 0, v_idx ? v_idx[j] : nullptr, v_re ? v_re[j] : nullptr,
+                          v_im ? v_im[j] : nullptr, sys->pot[j], j + 1));
+  LSX_TRY(build_lifted(sys.get(), d, nl, blk, group, Ec));
+  *out = sys.release();
+  return LSX_OK;
+}
+
+extern "C" lsx_status lsx_system_create_blocks(int32_t D, int32_t nblocks, const int32_t* block_dim,
+                                               const double* const* R, const int32_t* group, double Ec,
+                                               int32_t nlayers, const int32_t* layer_first,
+                                               const int32_t* layer_count, const int32_t* nv,
+                                               const int32_t* const* v_idx, const double* const* v_re,
+                                               const double* const* v_im, lsx_system** out) {
+  if (!out || !block_dim || !R || !group || !layer_first || !layer_count || !nv || !v_idx || !v_re || !v_im)
+    return fail(LSX_E_INVALID, "null argument");
+  if (D != 1 && D != 2) return fail(LSX_E_INVALID, "physical dimension must be 1 or 2");
+  if (nblocks < 1 || nblocks > kMaxBlocks) return fail(LSX_E_INVALID, "number of blocks must be 1 to 4");
+  if (nlayers < 2 || nlayers > kMaxLayers) return fail(LSX_E_INVALID, "number of layers must be 2 or 3");
+  if (!(Ec > 0.0) || !std::isfinite(Ec)) return fail(LSX_E_INVALID, "Ec must be finite and > 0");
+  BlockSpec blk[kMaxBlocks];
+  int grp[kMaxBlocks];
+  int off[kMaxBlocks + 1] = {0};
+  bool used[kMaxBlocks] = {false, false, false, false};
+  for (int b = 0; b < nblocks; ++b) {
+    if (block_dim[b] != 1 && block_dim[b] != 2) return fail(LSX_E_INVALID, "block dimension must be 1 or 2");
+    if (!R[b]) return fail(LSX_E_INVALID, "null block embedding");
+    if (group[b] < 0 || group[b] >= nblocks) return fail(LSX_E_INVALID, "cutoff group out of range");
+    blk[b].dim = block_dim[b];
+    // R[b] column-major D x dim (column c = the wavevector of index component c)
+    for (int k = 0; k < D; ++k)
+      for (int c = 0; c < block_dim[b]; ++c) {
+        const double x = R[b][k + D * c];
+        if (!std::isfinite(x)) return fail(LSX_E_INVALID, "non-finite block embedding");
+        blk[b].R[k * block_dim[b] + c] = x;
+      }
+    grp[b] = group[b];
+    used[group[b]] = true;
+    off[b + 1] = off[b] + block_dim[b];
+  }
+  for (int g = 0; g < nblocks; ++g)
+    if (!used[g] && g < *std::max_element(grp, grp + nblocks))
+      return fail(LSX_E_INVALID, "cutoff groups must be numbered 0, 1, ... without gaps");
+  if (off[nblocks] > kMaxIndex) return fail(LSX_E_INVALID, "lifted index longer than 6 entries");
+  std::unique_ptr<lsx_system> sys(new (std::nothrow) lsx_system());
+  if (!sys) return fail(LSX_E_OOM, "host allocation failed");
+  sys->d = D;
+  sys->nl = nlayers;
+  sys->standard = false;
+  sys->Ec = Ec;
+  sys->cutoff = -1;
+  for (int j = 0; j < nlayers; ++j) {
+    const int f = layer_first[j], c = layer_count[j];
+    if (f < 0 || c < 1 || f + c > nblocks) return fail(LSX_E_INVALID, "layer block range out of range");
+    sys->lown[j] = off[f];
+    sys->ldim[j] = off[f + c] - off[f];
+  }
+  // the last layer's fibres (fixed leading columns) must be contiguous runs of the canonical
+  // order: its block range has to end with the last block
+  if (layer_first[nlayers - 1] + layer_count[nlayers - 1] != nblocks)
+    return fail(LSX_E_INVALID, "the last layer must couple the last block");
+  for (int j = 0; j < nlayers; ++j)
+    LSX_TRY(build_stencil(sys->ldim[j], nv[j], v_idx[j], v_re[j], v_im[j], sys->pot[j], j + 1));
+  LSX_TRY(build_lifted(sys.get(), D, nblocks, blk, grp, Ec));
   *out = sys.release();
   return LSX_OK;
 }
@@ -502,9 +620,9 @@ static lsx_status precompute_layer(lsx_plan* pl, int layer, hipStream_t s) {
   const Stencil& S = sys->pot[layer - 1];
   const int nf = ld.nf;
   if (nf == 0) return LSX_OK;
-  const int d = sys->d;
-  const int stride = sys->nl * d;
-  const int own = (layer - 1) * d;
+  const int d = sys->ldim[layer - 1];  // entries of the index the layer's potential couples
+  const int stride = sys->S;
+  const int own = sys->lown[layer - 1];
   // With kappa = 1 a fibre Hamiltonian is the potential restricted to the fibre's window
   // of own indices, which is translation invariant: fibres whose windows coincide up to a
   // shift share one eigendecomposition and one stored propagator.
@@ -1429,7 +1547,8 @@ extern "C" lsx_status lsx_batch_create(lsx_plan* const* plans, lsx_state* const*
       return cleanup(fail(LSX_E_STATE, "batch entry " + std::to_string(i) + ": state does not belong to plan"));
     if (plans[i]->scheme != plans[0]->scheme || plans[i]->fmt != plans[0]->fmt)
       return cleanup(fail(LSX_E_INVALID, "batch plans must share scheme and precision"));
-    if (plans[i]->sys->nl != 2) return cleanup(fail(LSX_E_INVALID, "batches hold two-layer systems"));
+    if (plans[i]->sys->nl != 2 || !plans[i]->sys->standard)
+      return cleanup(fail(LSX_E_INVALID, "batches hold two-layer systems built from lattices"));
     if ((states[i]->W == 1) != (states[0]->W == 1))
       return cleanup(fail(LSX_E_INVALID, "batch states must be all W = 1 or all W >= 2"));
     for (int j = 0; j < i; ++j)
@@ -1833,7 +1952,7 @@ extern "C" lsx_status lsx_sampler_create(lsx_plan* pl, lsx_state* st, int32_t p1
   if (p1 < 0 || p2 < 0) return fail(LSX_E_INVALID, "p1, p2 must be >= 0");
   if (!(eps >= 0.0 && eps <= 1.0)) return fail(LSX_E_INVALID, "eps must be in [0, 1]");
   const lsx_system* sys = pl->sys;
-  if (sys->nl != 2) return fail(LSX_E_INVALID, "samplers hold two-layer systems");
+  if (sys->nl != 2 || !sys->standard) return fail(LSX_E_INVALID, "samplers hold two-layer systems built from lattices");
   const int W = st->W, d = sys->d;
   for (int j = 0; j < 2; ++j)
     if (pl->L[j].nf > kSamplerMaxFibres)
@@ -2009,7 +2128,8 @@ lsx_status si_once(lsx_plan* pl, lsx_state* st, const double* wt1, const int32_t
 extern "C" lsx_status lsx_si_step(lsx_plan* pl, lsx_state* st, int64_t nsteps, void* stream) {
   LSX_TRY(check_pair(pl, st));
   if (nsteps < 0) return fail(LSX_E_INVALID, "nsteps must be >= 0");
-  if (pl->sys->nl != 2) return fail(LSX_E_INVALID, "the semi-implicit step takes two-layer systems");
+  if (pl->sys->nl != 2 || !pl->sys->standard)
+    return fail(LSX_E_INVALID, "the semi-implicit step takes two-layer systems built from lattices");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   for (int64_t k = 0; k < nsteps && pl->sys->N > 0; ++k) LSX_TRY(si_once(pl, st, nullptr, nullptr, nullptr, nullptr, s));
   return LSX_OK;

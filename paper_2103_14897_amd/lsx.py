@@ -40,6 +40,9 @@ _SIGS = {
     "lsx_system_create_layers": (C.c_int, [C.c_int32, C.c_int32, C.POINTER(_dp), C.c_double, C.c_int32,
                                            _i32p, C.POINTER(_i32p), C.POINTER(_dp), C.POINTER(_dp),
                                            C.POINTER(_p)]),
+    "lsx_system_create_blocks": (C.c_int, [C.c_int32, C.c_int32, _i32p, C.POINTER(_dp), _i32p, C.c_double,
+                                           C.c_int32, _i32p, _i32p, _i32p, C.POINTER(_i32p), C.POINTER(_dp),
+                                           C.POINTER(_dp), C.POINTER(_p)]),
     "lsx_system_layers": (C.c_int, [_p, C.POINTER(C.c_int32), _i64p]),
     "lsx_system_size": (C.c_int, [_p, _i64p, _i64p, _i64p]),
     "lsx_index_get": (C.c_int, [_p, _i32p]),
@@ -188,7 +191,37 @@ class System:
         self._finish(h)
         return self
 
-    def _finish(self, h):
+    @classmethod
+    def blocks(cls, Rs, groups, Ec, layers, pots):
+        """A system whose layers may share index blocks (lsx_system_create_blocks).  Rs[b] is
+        block b's D x dim_b embedding, groups a list of block lists (one per cutoff group),
+        layers a list of (first block, end block) ranges, pots[j] maps index tuples over layer
+        j's blocks to Fourier coefficients."""
+        self = cls.__new__(cls)
+        Rs = [np.asarray(R, dtype=np.float64) for R in Rs]
+        D = Rs[0].shape[0]
+        nb = len(Rs)
+        dims = (C.c_int32 * nb)(*[R.shape[1] for R in Rs])
+        mats = [np.asfortranarray(R).ravel(order="F") for R in Rs]
+        grp = [0] * nb
+        for g, bl in enumerate(groups):
+            for b in bl:
+                grp[b] = g
+        nl = len(layers)
+        off = np.concatenate([[0], np.cumsum([R.shape[1] for R in Rs])])
+        parts = [_potential(p, int(off[e] - off[s0])) for p, (s0, e) in zip(pots, layers)]
+        self._keep = mats + [x for part in parts for x in part[1:]]
+        self.d = D
+        h = _p()
+        _check(lib().lsx_system_create_blocks(
+            D, nb, dims, (_dp * nb)(*[_dptr(A) for A in mats]), (C.c_int32 * nb)(*grp), float(Ec), nl,
+            (C.c_int32 * nl)(*[int(s0) for s0, _ in layers]), (C.c_int32 * nl)(*[int(e - s0) for s0, e in layers]),
+            (C.c_int32 * nl)(*[p[0] for p in parts]), (_i32p * nl)(*[p[1].ctypes.data_as(_i32p) for p in parts]),
+            (_dp * nl)(*[_dptr(p[2]) for p in parts]), (_dp * nl)(*[_dptr(p[3]) for p in parts]), C.byref(h)))
+        self._finish(h, int(off[-1]))
+        return self
+
+    def _finish(self, h, S=None):
         self.h = h
         nl = C.c_int32()
         nf = (C.c_int64 * 3)()
@@ -197,13 +230,14 @@ class System:
         _check(lib().lsx_system_size(self.h, C.byref(N), None, None))
         self.N, self.nlayers = N.value, nl.value
         self.nfibres = {j + 1: nf[j] for j in range(self.nlayers)}
+        self.S = S if S is not None else self.nlayers * self.d
 
     @classmethod
     def from_spec(cls, spec):
         return cls(spec.d, spec.A1, spec.A2, spec.Ec, spec.cutoff, spec.pot1, spec.pot2)
 
     def index(self):
-        mn = np.zeros((self.N, self.nlayers * self.d), dtype=np.int32)
+        mn = np.zeros((self.N, self.S), dtype=np.int32)
         _check(lib().lsx_index_get(self.h, mn.ctypes.data_as(_i32p)))
         return mn
 

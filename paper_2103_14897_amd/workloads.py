@@ -147,6 +147,36 @@ def twisted_layers(Ec: float, thetas_deg=(-2.5, 0.0, 2.5), v=(1.0, 0.5, 0.7), cu
                      name=f"twisted{len(thetas_deg)}_Ec{Ec:g}")
 
 
+@dataclass
+class BlockSpec:
+    """A lifted system whose layers share index blocks: block b has embedding ``Rs[b]`` (D x dim_b,
+    columns the wavevectors of its entries), ``groups`` lists the blocks of each cutoff group
+    (sum over the group of |R_b m_b|^2 <= 2 Ec), ``layers[j]`` = (first block, end block) of the
+    blocks layer j's potential couples, ``pots[j]`` its Fourier coefficients over those blocks."""
+
+    Rs: list
+    groups: list
+    Ec: float
+    layers: list
+    pots: list
+    name: str = ""
+
+
+def example3_system(Ec: float, s1: float = 1.0, s2: float = 2.0,
+                    beta: float = (math.sqrt(5.0) - 1.0) / 2.0) -> BlockSpec:
+    """The quasi-one-dimensional system of Example 3 (Sec. 6):
+    V = s1 cos^2(beta x) cos^2(pi y / 2) + s2 cos^2(x) cos^2(pi y / 2), incommensurate in x and
+    periodic in y.  Blocks (m, p, n): m and n index the x-wavevectors 2 beta m and 2 n of the two
+    factors, p the y-wavevector pi p; cutoff groups (m, n) and p; layer 1 couples (m, p), layer
+    2 couples (p, n).  cos^2(a z) has coefficients 1/2 at 0 and 1/4 at +-2a."""
+    a = {0: 0.5, 1: 0.25, -1: 0.25}
+    p1 = {(k, q): s1 * a[k] * a[q] for k in a for q in a}
+    p2 = {(q, k): s2 * a[k] * a[q] for k in a for q in a}
+    Rs = [np.array([[2.0 * beta], [0.0]]), np.array([[0.0], [math.pi]]), np.array([[2.0], [0.0]])]
+    return BlockSpec(Rs=Rs, groups=[[0, 2], [1]], Ec=float(Ec), layers=[(0, 2), (1, 3)], pots=[p1, p2],
+                     name=f"example3_Ec{Ec:g}")
+
+
 def draw_k0(W: int, d: int, seed: int = 0, kmax: float = 10.0) -> np.ndarray:
     """Seeded wavepacket centres k0 [W, d] (PCG64).
 

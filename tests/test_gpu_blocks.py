@@ -1,0 +1,140 @@
+"""GPU parity for systems whose layers share index blocks (Example 3: x incommensurate, y
+periodic for both layers, lifted by (m, p, n)) against the block oracle: propagators of both
+layers, Lie / Strang / Yoshida trajectories (FP64 <= 2e-12 relative L2 per step, Yoshida
+6e-12), kappa in {0, 0.5, 1}, single passes in every precision at ragged W, mixed precision
+after many steps, mass, energy and fibre masses, and the entry points that reject these
+systems."""
+import numpy as np
+import pytest
+
+from oracle import blocks
+from oracle import multilayer as ml
+from paper_2103_14897_amd import lsx
+from paper_2103_14897_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def colrel(a, b):
+    return (np.linalg.norm(a - b, axis=0) / np.linalg.norm(b, axis=0)).max()
+
+
+def build(Ec):
+    spec = wl.example3_system(Ec)
+    S = lsx.System.blocks(spec.Rs, spec.groups, spec.Ec, spec.layers, spec.pots)
+    O = blocks.example3(Ec)
+    assert S.N == O.N and np.array_equal(S.index(), O.mn.astype(np.int32))
+    return S, O
+
+
+@pytest.mark.parametrize("kappa", [0.0, 1.0])
+def test_example3_propagators(kappa):
+    print(f"[case] example3 propagators kappa={kappa}", flush=True)
+    S, O = build(300.0)
+    plan = ml.MultiSplitPlan(O, kappa)
+    tau = 0.01
+    P = lsx.Plan(S, tau, "strang", kappa, "fp64")
+    try:
+        for layer, slot, t in ((1, 0, tau), (1, 1, tau / 2), (2, 0, tau)):
+            ref = plan.propagators(layer, t)
+            nf = S.nfibres[layer]
+            for f in (0, nf // 2, nf - 1):
+                assert np.abs(P.propagator(layer, slot, f) - ref[f]).max() < 1e-13, (layer, slot, f)
+    finally:
+        P.destroy()
+        S.destroy()
+
+
+@pytest.mark.parametrize("scheme,kappa", [("strang", 0.0), ("strang", 0.5), ("strang", 1.0), ("lie", 0.0),
+                                          ("lie", 0.5), ("yoshida4", 0.0)])
+def test_example3_trajectories(scheme, kappa):
+    print(f"[case] example3 trajectory {scheme} kappa={kappa}", flush=True)
+    S, O = build(100.0)
+    plan = ml.MultiSplitPlan(O, kappa)
+    W, tau = 5, 0.01
+    per_step = 6e-12 if scheme == "yoshida4" else 2e-12
+    P = lsx.Plan(S, tau, scheme, kappa, "fp64")
+    st = lsx.State(P, W)
+    try:
+        c = wl.random_state(S.N, W, seed=9)
+        for nsteps in (1, 5):
+            st.upload(c)
+            st.step(nsteps)
+            assert colrel(st.download(), plan.evolve(c, tau, nsteps, scheme)) < per_step * nsteps, nsteps
+    finally:
+        st.destroy()
+        P.destroy()
+        S.destroy()
+
+
+@pytest.mark.parametrize("W", [1, 17, 64])
+@pytest.mark.parametrize("precision", ["fp64", "mix_fp32", "mix_bf16x3"])
+def test_example3_single_passes(W, precision):
+    S, O = build(300.0)
+    plan = ml.MultiSplitPlan(O, 0.0)
+    tau = 0.01
+    P = lsx.Plan(S, tau, "strang", 0.0, precision)
+    st = lsx.State(P, W)
+    try:
+        c = wl.random_state(S.N, W, seed=W)
+        tol = 1e-12 if precision == "fp64" else 1e-7
+        for layer, slot, t in ((1, 1, tau / 2), (2, 0, tau)):
+            st.upload(c)
+            st.fibre_pass(layer, slot)
+            assert colrel(st.download(), plan.apply_fibres(c, layer, t)) < tol, (layer, st.tuning(layer))
+    finally:
+        st.destroy()
+        P.destroy()
+        S.destroy()
+
+
+def test_example3_mixed_precision_and_observables():
+    S, O = build(100.0)
+    W, tau = 8, 0.01
+    c = wl.random_state(S.N, W, seed=3)
+    out = {}
+    try:
+        for prec in ("fp64", "mix_fp32", "mix_bf16x3"):
+            P = lsx.Plan(S, tau, "strang", 0.0, prec)
+            st = lsx.State(P, W)
+            st.upload(c)
+            st.step(100)
+            out[prec] = st.download()
+            if prec == "fp64":
+                mask = lsx.OBS_MASS | lsx.OBS_ENERGY | lsx.OBS_FIBRE_MASS_1 | lsx.OBS_FIBRE_MASS_2
+                r = st.observables(mask)
+                x = out[prec]
+                D, Vs = O.dense(1.0)  # kappa = 1: H_j = V^j
+                E = np.real(np.einsum("iw,ij,jw->w", x.conj(), D + sum(Vs), x))
+                assert np.abs(r["mass"] - (np.abs(c) ** 2).sum(axis=0)).max() < 1e-12
+                assert np.abs(r["energy"] - E).max() < 1e-11 * np.abs(E).max()
+                for layer in (1, 2):
+                    ref = np.array([(np.abs(x[rows]) ** 2).sum(axis=0) for _, rows in O.fib[layer]])
+                    assert np.abs(r[f"fibre_mass_{layer}"] - ref).max() < 1e-13
+            st.destroy()
+            P.destroy()
+        for prec in ("mix_fp32", "mix_bf16x3"):
+            err = colrel(out[prec], out["fp64"])
+            print(f"  {prec}: 100 steps rel err vs FP64 {err:.2e}")
+            assert err < 1e-6
+    finally:
+        S.destroy()
+
+
+def test_example3_rejections():
+    S, _ = build(40.0)
+    try:
+        P = lsx.Plan(S, 0.01, "strang", 0.0, "fp64")
+        st = lsx.State(P, 2)
+        try:
+            with pytest.raises(lsx.LsxError):
+                st.si_step(1)
+            with pytest.raises(lsx.LsxError):
+                lsx.Sampler(st, 2, 2)
+            with pytest.raises(lsx.LsxError):
+                lsx.Batch([st])
+        finally:
+            st.destroy()
+            P.destroy()
+    finally:
+        S.destroy()

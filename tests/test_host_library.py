@@ -128,3 +128,52 @@ def test_layered_errors():
     with pytest.raises(lsx.LsxError) as e:
         lsx.System.layers(2, [wl.TRIANGULAR] * 3, 3.0e5)
     assert e.value.code == lsx.LSX_E_INVALID
+
+
+def _example3_args(Ec):
+    spec = wl.example3_system(Ec)
+    return spec.Rs, spec.groups, spec.Ec, spec.layers, spec.pots
+
+
+@pytest.mark.parametrize("Ec", [40.0, 300.0])
+def test_block_system_tables_equal_oracle(Ec):
+    """lsx_system_create_blocks on Example 3 (blocks (m, p, n), cutoff groups (m, n) and p,
+    layer 1 on (m, p), layer 2 on (p, n)): index set and fibre tables equal the block oracle."""
+    from oracle import blocks
+    Rs, groups, Ec, layers, pots = _example3_args(Ec)
+    S = lsx.System.blocks(Rs, groups, Ec, layers, pots)
+    O = blocks.example3(Ec)
+    assert S.N == O.N and S.nlayers == 2 and S.S == 3
+    assert np.array_equal(S.index(), O.mn.astype(np.int32))
+    for layer in (1, 2):
+        ptr, rows = S.fibres(layer)
+        assert S.nfibres[layer] == len(O.fib[layer])
+        assert np.array_equal(ptr, np.cumsum([0] + [len(r) for _, r in O.fib[layer]]))
+        assert np.array_equal(rows, np.concatenate([r for _, r in O.fib[layer]]))
+    S.destroy()
+
+
+def test_block_system_reduces_to_the_layer_constructor():
+    spec = wl.twisted_layers(30.0)
+    a = lsx.System.layers(spec.d, spec.As, spec.Ec, spec.cutoff, spec.pots)
+    from oracle import multilayer as ml
+    b = lsx.System.blocks([ml.reciprocal(A) for A in spec.As], [[0, 1, 2]], spec.Ec, [(0, 1), (1, 2), (2, 3)],
+                          spec.pots)
+    assert a.nfibres == b.nfibres and np.array_equal(a.index(), b.index())
+    for layer in (1, 2, 3):
+        assert all(np.array_equal(x, y) for x, y in zip(a.fibres(layer), b.fibres(layer)))
+    a.destroy()
+    b.destroy()
+
+
+def test_block_system_errors():
+    Rs, groups, Ec, layers, pots = _example3_args(40.0)
+    with pytest.raises(lsx.LsxError) as e:  # the last layer must couple the last block
+        lsx.System.blocks(Rs, groups, Ec, [(1, 3), (0, 2)], pots[::-1])
+    assert e.value.code == lsx.LSX_E_INVALID
+    with pytest.raises(lsx.LsxError) as e:  # singular embedding
+        lsx.System.blocks([np.zeros((2, 1))] + Rs[1:], groups, Ec, layers, pots)
+    assert e.value.code == lsx.LSX_E_INVALID
+    with pytest.raises(lsx.LsxError) as e:  # not Hermitian
+        lsx.System.blocks(Rs, groups, Ec, layers, [pots[0], {(1, 0): 0.3}])
+    assert e.value.code == lsx.LSX_E_NOT_HERMITIAN
