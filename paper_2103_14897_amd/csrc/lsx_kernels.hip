@@ -204,7 +204,24 @@ __global__ __launch_bounds__(BS) void k_jacobi(double* Aall, double* VTall, cons
     done = (rotated == 0);
     __syncthreads();
   }
-  for (int k = tid; k < n; k += BS) lam[loff[f] + k] = A[(int64_t)k * n + k];
+  // Each rotation is orthogonal only up to the rounding of (c, s): near-degenerate pairs
+  // (potential-only fibres) take 45-degree rotations with c = s = fl(1/sqrt 2), and
+  // 2 fl(1/sqrt 2)^2 = 1 + 2^-52, so both rows grow by the same factor and thousands of such
+  // rotations per row leave V scaled-orthogonal, V = Q diag(nu), and A = diag(nu) Q^T H Q
+  // diag(nu).  Normalising each eigenvector (row of V^T) and dividing its diagonal entry by
+  // nu^2 recovers Q and the eigenvalues.
+  const int lane = tid & 63, wv = tid >> 6;
+  for (int k = wv; k < n; k += BS / 64) {
+    double s = 0.0;
+    for (int c = lane; c < n; c += 64) {
+      const double x = VT[(int64_t)k * n + c];
+      s += x * x;
+    }
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    const double r = 1.0 / sqrt(s);
+    for (int c = lane; c < n; c += 64) VT[(int64_t)k * n + c] *= r;
+    if (lane == 0) lam[loff[f] + k] = A[(int64_t)k * n + k] / s;
+  }
   if (tid == 0) info[f] = done ? sweep : -1;
 }
 
