@@ -145,8 +145,8 @@ lsx_status lsx_system_create_layers(int32_t d, int32_t nlayers, const double* co
  * H = kappa D + sum_j ((1 - kappa)/nlayers D + V^j).  Canonical order is lexicographic in
  * (m_0, ..., m_{B-1}); a layer-j fibre fixes every entry outside the layer's blocks.  Plans,
  * states, lsx_step, lsx_fibre_pass, lsx_phase and lsx_observables accept these systems as
- * any other (the schemes allowed for their number of layers); batches, samplers and the
- * semi-implicit step reject them.  Host-only; touches no GPU.
+ * any other with the Lie, Strang and Yoshida schemes; the rational schemes, batches, samplers
+ * and the semi-implicit step reject them.  Host-only; touches no GPU.
  */
 lsx_status lsx_system_create_blocks(int32_t D, int32_t nblocks, const int32_t* block_dim, const double* const* R,
                                     const int32_t* group, double Ec, int32_t nlayers, const int32_t* layer_first,

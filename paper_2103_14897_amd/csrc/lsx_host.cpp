@@ -748,8 +748,8 @@ extern "C" lsx_status lsx_plan_create(lsx_system* sys, double tau, int32_t schem
   if (!(kappa >= 0.0 && kappa <= 1.0)) return fail(LSX_E_INVALID, "kappa must be in [0, 1]");
   if (precision != LSX_FP64 && precision != LSX_MIX_FP32 && precision != LSX_MIX_BF16X3)
     return fail(LSX_E_INVALID, "bad precision");
-  if (sys->nl > 2 && scheme != LSX_LIE && scheme != LSX_STRANG && scheme != LSX_YOSHIDA4)
-    return fail(LSX_E_INVALID, "three-layer systems support the Lie, Strang and Yoshida schemes");
+  if ((sys->nl > 2 || !sys->standard) && scheme != LSX_LIE && scheme != LSX_STRANG && scheme != LSX_YOSHIDA4)
+    return fail(LSX_E_INVALID, "three-layer and shared-block systems support the Lie, Strang and Yoshida schemes");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   lsx_plan* pl = new (std::nothrow) lsx_plan();
   if (!pl) return fail(LSX_E_OOM, "host allocation failed");

@@ -124,6 +124,10 @@ def test_example3_mixed_precision_and_observables():
 def test_example3_rejections():
     S, _ = build(40.0)
     try:
+        for scheme in ("lie_be", "strang_cn"):
+            with pytest.raises(lsx.LsxError) as e:
+                lsx.Plan(S, 0.01, scheme, 0.0, "fp64")
+            assert e.value.code == lsx.LSX_E_INVALID
         P = lsx.Plan(S, 0.01, "strang", 0.0, "fp64")
         st = lsx.State(P, 2)
         try:
