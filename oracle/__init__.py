@@ -18,7 +18,8 @@ observables  mass (eq. 2.3 via orthonormality 3.1), energy (eq. 2.4), fibre mass
 reference    brute-force exponentials of the full lifted Hamiltonian and a
              direct commensurate-supercell computation used to pin the rest
 multilayer   index set, fibres, fibre Hamiltonians and Lie / Strang / Yoshida layer
-             splitting for L >= 2 layers (the generalisation of Secs. 2-4)
+             splitting for L >= 2 layers (the generalisation of Secs. 2-4), with exact,
+             backward-Euler or Crank-Nicolson fibre sub-steps
 blocks       lifted systems whose layers share index blocks (Example 3 of Sec. 6:
              a direction periodic for every layer), split like `multilayer`
 stochastic   semi-implicit (Alg. 1) and random batch (Alg. 4) steps, stochastic

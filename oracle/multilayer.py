@@ -120,21 +120,40 @@ class MultiLifted:
 
 
 class MultiSplitPlan:
-    """Exact fibre flows of every layer, cached per (layer, t); unmerged compositions."""
+    """Fibre sub-steps of every layer, cached per (layer, t); unmerged compositions.
 
-    def __init__(self, sys: MultiLifted, kappa: float = 0.0):
+    ``flow`` selects the sub-step: ``"exact"`` exp(-i t H_j) (eigh), ``"be"`` the backward-Euler
+    solve (I + i t H_j)^{-1} (Alg. 2, eqs. 4.3-4.4), or ``"cn"`` the Crank-Nicolson solve
+    (I + i t H_j / 2)^{-1}(I - i t H_j / 2) (eq. 4.6), formed by linear solves with the fibre
+    matrix.  The rational flows are used with the Lie (BE) and Strang (CN) compositions, as
+    for two layers."""
+
+    def __init__(self, sys: MultiLifted, kappa: float = 0.0, flow: str = "exact"):
         self.sys = sys
         self.kappa = float(kappa)
+        self.flow = flow
         self._eig = {}
         self._P = {}
 
     def propagators(self, layer: int, t: float):
-        if layer not in self._eig:
-            self._eig[layer] = [np.linalg.eigh(self.sys.fibre_hamiltonian(layer, rows, self.kappa))
-                                for _, rows in self.sys.fib[layer]]
         key = (layer, float(t))
-        if key not in self._P:
+        if key in self._P:
+            return self._P[key]
+        if self.flow == "exact":
+            if layer not in self._eig:
+                self._eig[layer] = [np.linalg.eigh(self.sys.fibre_hamiltonian(layer, rows, self.kappa))
+                                    for _, rows in self.sys.fib[layer]]
             self._P[key] = [(U * np.exp(-1j * t * lam)[None, :]) @ U.conj().T for lam, U in self._eig[layer]]
+        else:
+            out = []
+            for _, rows in self.sys.fib[layer]:
+                H = self.sys.fibre_hamiltonian(layer, rows, self.kappa)
+                I = np.eye(len(rows))
+                if self.flow == "be":
+                    out.append(np.linalg.solve(I + 1j * t * H, I))
+                else:
+                    out.append(np.linalg.solve(I + 0.5j * t * H, I - 0.5j * t * H))
+            self._P[key] = out
         return self._P[key]
 
     def apply_fibres(self, c, layer: int, t: float):
