@@ -114,7 +114,7 @@ lsx_status lsx_system_create(int32_t d, const double* A1, const double* A2, doub
  * lexicographic in that tuple, and V^j couples only m_j.  A layer-j fibre fixes every block
  * but m_j; fibres are ordered by their fixed blocks (lexicographic, layer order), rows
  * ascending, so the last layer's fibres are contiguous runs of the canonical order.  With
- * nlayers = 2 this is lsx_system_create.  Three-layer systems take the Lie, Strang and Yoshida schemes
+ * nlayers = 2 this is lsx_system_create.  Three-layer systems take every scheme
  * and the deterministic entry points (plans, states, lsx_step, lsx_fibre_pass, lsx_phase,
  * lsx_observables); batches, samplers and the semi-implicit step reject them with
  * LSX_E_INVALID.  Index entries beyond +-511 (three layers, d = 2) are rejected.
@@ -145,8 +145,8 @@ lsx_status lsx_system_create_layers(int32_t d, int32_t nlayers, const double* co
  * H = kappa D + sum_j ((1 - kappa)/nlayers D + V^j).  Canonical order is lexicographic in
  * (m_0, ..., m_{B-1}); a layer-j fibre fixes every entry outside the layer's blocks.  Plans,
  * states, lsx_step, lsx_fibre_pass, lsx_phase and lsx_observables accept these systems as
- * any other with the Lie, Strang and Yoshida schemes; the rational schemes, batches, samplers
- * and the semi-implicit step reject them.  Host-only; touches no GPU.
+ * any other, with every scheme; batches, samplers and the semi-implicit step reject them.
+ * Host-only; touches no GPU.
  */
 lsx_status lsx_system_create_blocks(int32_t D, int32_t nblocks, const int32_t* block_dim, const double* const* R,
                                     const int32_t* group, double Ec, int32_t nlayers, const int32_t* layer_first,
@@ -199,12 +199,12 @@ lsx_status lsx_system_destroy(lsx_system* sys);
  *   Strang, CN      : layer 1 {0: tau, 1: tau/2}, layer 2 {0: tau}, phase {0: tau, 1: tau/2}
  *   Yoshida         : layer 1 {0: g1 tau, 1: g1 tau/2, 2: (g1+g0) tau/2},
  *                     layer 2 {0: g1 tau, 2: g0 tau}, phase {0: g1 tau/2, 1: g0 tau/2}
- * Three-layer systems (Lie, Strang and Yoshida), with H_j = (1 - kappa)/3 D + V^j:
- *   Lie             : F1(tau), F2(tau), Phase(kappa tau), F3(tau); every layer {0: tau},
+ * Three-layer systems, with H_j = (1 - kappa)/3 D + V^j:
+ *   Lie, BE-Lie     : F1(tau), F2(tau), Phase(kappa tau), F3(tau); every layer {0: tau},
  *                     phase {0: tau}
- *   Strang          : F1(tau/2), F2(tau/2), Phase(kappa tau/2), F3(tau), Phase(kappa tau/2),
+ *   Strang, CN      : F1(tau/2), F2(tau/2), Phase(kappa tau/2), F3(tau), Phase(kappa tau/2),
  *                     F2(tau/2), F1(tau/2); layer 1 {0: tau, 1: tau/2}, layer 2 {1: tau/2},
- *                     layer 3 {0: tau}, phase {0: tau, 1: tau/2}
+ *                     layer 3 {0: tau}, phase {0: tau, 1: tau/2} (CN steps are not merged)
  *   Yoshida         : the three-layer Strang steps of g1 tau, g0 tau, g1 tau; layer 1 as for two
  *                     layers, layer 2 {0: g1 tau/2, 1: g0 tau/2}, layer 3 {0: g1 tau, 2: g0 tau},
  *                     phase {0: g1 tau/2, 1: g0 tau/2}

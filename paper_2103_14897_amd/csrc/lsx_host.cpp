@@ -582,9 +582,9 @@ static const double kYoshidaG0 = 1.0 - 2.0 * kYoshidaG1;
 //  Strang, CN-Strang  : layer 1 {tau, tau/2}, layer 2 {tau}, phase {tau, tau/2}
 //  Yoshida (4th order): layer 1 {g1 tau, g1 tau/2, (g1+g0) tau/2}, layer 2 {g1 tau, -, g0 tau},
 //                       phase {g1 tau/2, g0 tau/2}
-// Three layers (Lie, Strang, Yoshida):
-//  Lie                : every layer {tau}, phase {tau}
-//  Strang             : layer 1 {tau, tau/2}, layer 2 {-, tau/2}, layer 3 {tau}, phase {tau, tau/2}
+// Three layers:
+//  Lie, BE-Lie        : every layer {tau}, phase {tau}
+//  Strang, CN-Strang  : layer 1 {tau, tau/2}, layer 2 {-, tau/2}, layer 3 {tau}, phase {tau, tau/2}
 //  Yoshida            : layer 1 {g1 tau, g1 tau/2, (g1+g0) tau/2}, layer 2 {g1 tau/2, g0 tau/2},
 //                       layer 3 {g1 tau, -, g0 tau}, phase {g1 tau/2, g0 tau/2}
 struct SchemeTimes {
@@ -748,8 +748,6 @@ extern "C" lsx_status lsx_plan_create(lsx_system* sys, double tau, int32_t schem
   if (!(kappa >= 0.0 && kappa <= 1.0)) return fail(LSX_E_INVALID, "kappa must be in [0, 1]");
   if (precision != LSX_FP64 && precision != LSX_MIX_FP32 && precision != LSX_MIX_BF16X3)
     return fail(LSX_E_INVALID, "bad precision");
-  if ((sys->nl > 2 || !sys->standard) && scheme != LSX_LIE && scheme != LSX_STRANG && scheme != LSX_YOSHIDA4)
-    return fail(LSX_E_INVALID, "three-layer and shared-block systems support the Lie, Strang and Yoshida schemes");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   lsx_plan* pl = new (std::nothrow) lsx_plan();
   if (!pl) return fail(LSX_E_OOM, "host allocation failed");
@@ -1250,7 +1248,8 @@ struct PassSpec {
 // Every two-layer body has an even number of passes and returns to the layout it started from.
 // Three layers (Ph as above):
 //  Strang  : F1(t/2) F2(t/2) [Ph F3(t) Ph F2(t/2) F1(t) F2(t/2)]^(n-1) Ph F3(t) Ph F2(t/2) F1(t/2)
-//  Lie     : [F1(t) F2(t) Ph F3(t)]^n
+//  Lie, BE  : [F1(t) F2(t) Ph F3(t)]^n
+//  CN      : [F1(t/2) F2(t/2) Ph F3(t) Ph F2(t/2) F1(t/2)]^n, unmerged
 //  Yoshida : the three-layer Strang steps of g1 t, g0 t, g1 t with the F1 halves merged as for
 //            two layers (13 passes per step)
 void step_sequence(int scheme, int nl, int64_t nsteps, std::vector<PassSpec>& head, std::vector<PassSpec>& body,
@@ -1269,6 +1268,16 @@ void step_sequence(int scheme, int nl, int64_t nsteps, std::vector<PassSpec>& he
       body.push_back({1, 0, 2, -1});
       tail = inner;
       tail.push_back({1, 1, 0, -1});
+    } else if (scheme == LSX_STRANG_CN) {
+      for (int64_t k = 0; k < nsteps; ++k) {
+        const bool last = (k + 1 == nsteps);
+        tail.push_back({1, 1, 2, -1});
+        tail.push_back({2, 1, 3, 1});
+        tail.push_back({3, 0, 2, 1});
+        tail.push_back({2, 1, 1, -1});
+        tail.push_back({1, 1, last ? 0 : 1, -1});
+      }
+      return;
     } else if (scheme == LSX_STRANG) {
       head = {{1, 1, 2, -1}, {2, 1, 3, 1}};
       body = {{3, 0, 2, 1}, {2, 1, 1, -1}, {1, 0, 2, -1}, {2, 1, 3, 1}};
