@@ -51,10 +51,15 @@ struct DBuf {
     n = count;
     return LSX_OK;
   }
+  // Set-up copy from a host vector, complete on return: callers pass locals and temporaries,
+  // so the copy must not outlive `v`, whatever HIP does with pageable memory.
   lsx_status upload(const std::vector<T>& v, hipStream_t s) {
     lsx_status st = alloc(v.size());
     if (st != LSX_OK) return st;
-    if (!v.empty()) LSX_HIP_TRY(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    if (!v.empty()) {
+      LSX_HIP_TRY(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+      LSX_HIP_TRY(hipStreamSynchronize(s));
+    }
     return LSX_OK;
   }
 };

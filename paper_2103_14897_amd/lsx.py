@@ -289,6 +289,7 @@ class State:
     def upload(self, c, stream=None):
         c = np.ascontiguousarray(np.asarray(c, dtype=np.complex128).reshape(self.N, self.W))
         _check(lib().lsx_state_upload(self.h, c.ctypes.data_as(_dp), _stream(stream)))
+        self._pending = c  # the copy is stream-ordered: the source lives until the next upload
         self._pending = c  # kept alive until the next call (stream-ordered copy)
 
     def download(self, stream=None):
@@ -388,6 +389,7 @@ class Mlp:
     def set(self, theta, stream=None):
         t = np.ascontiguousarray(np.asarray(theta, dtype=np.float32).reshape(self.nparams))
         _check(lib().lsx_mlp_set(self.h, t.ctypes.data_as(C.POINTER(C.c_float)), _stream(stream)))
+        self._pending = t  # stream-ordered copy: the source lives until the next set
 
     def get(self, stream=None):
         t = np.zeros(self.nparams, dtype=np.float32)
