@@ -114,9 +114,9 @@ lsx_status lsx_system_create(int32_t d, const double* A1, const double* A2, doub
  * lexicographic in that tuple, and V^j couples only m_j.  A layer-j fibre fixes every block
  * but m_j; fibres are ordered by their fixed blocks (lexicographic, layer order), rows
  * ascending, so the last layer's fibres are contiguous runs of the canonical order.  With
- * nlayers = 2 this is lsx_system_create.  Three-layer systems take every scheme
- * and the deterministic entry points (plans, states, lsx_step, lsx_fibre_pass, lsx_phase,
- * lsx_observables); batches, samplers and the semi-implicit step reject them with
+ * nlayers = 2 this is lsx_system_create.  Three-layer systems take every scheme, the
+ * deterministic entry points (plans, states, lsx_step, lsx_fibre_pass, lsx_phase,
+ * lsx_observables) and batches; samplers and the semi-implicit step reject them with
  * LSX_E_INVALID.  Index entries beyond +-511 (three layers, d = 2) are rejected.
  */
 lsx_status lsx_system_create_layers(int32_t d, int32_t nlayers, const double* const* A, double Ec, int32_t cutoff,
@@ -145,7 +145,7 @@ lsx_status lsx_system_create_layers(int32_t d, int32_t nlayers, const double* co
  * H = kappa D + sum_j ((1 - kappa)/nlayers D + V^j).  Canonical order is lexicographic in
  * (m_0, ..., m_{B-1}); a layer-j fibre fixes every entry outside the layer's blocks.  Plans,
  * states, lsx_step, lsx_fibre_pass, lsx_phase and lsx_observables accept these systems as
- * any other, with every scheme; batches, samplers and the semi-implicit step reject them.
+ * any other, with every scheme, and in batches; samplers and the semi-implicit step reject them.
  * Host-only; touches no GPU.
  */
 lsx_status lsx_system_create_blocks(int32_t D, int32_t nblocks, const int32_t* block_dim, const double* const* R,
@@ -318,8 +318,8 @@ lsx_status lsx_observables(lsx_plan* plan, lsx_state* st, uint32_t mask, double*
  * repeated part of the step sequence is captured once in a HIP graph and replayed.
  *
  * lsx_batch_create: plans[i] and states[i] (i < n) must match (states[i] created on
- *   plans[i]); all plans must share the scheme and the precision; states must be all
- *   W = 1 or all W >= 2.  The tile shape and the launch mode of every layer's pass are
+ *   plans[i]); all plans must share the scheme, the precision and the number of layers;
+ *   states must be all W = 1 or all W >= 2.  The tile shape and the launch mode of every layer's pass are
  *   autotuned on the whole batch: one workgroup per tile (the hardware dispatcher balances
  *   the uneven tiles), or a persistent grid of the resident capacity that walks the
  *   XCD-interleaved tile list with a static stride, or one that claims tiles from per-XCD

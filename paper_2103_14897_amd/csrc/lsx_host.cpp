@@ -1288,8 +1288,14 @@ void step_sequence(int scheme, int nl, int64_t nsteps, std::vector<PassSpec>& he
       body = {{3, 0, 2, 1}, {2, 1, 1, -1}, {1, 0, 2, -1}, {2, 1, 3, 1}};
       tail = {{3, 0, 2, 1}, {2, 1, 1, -1}, {1, 1, 0, -1}};
     } else {
-      body = {{1, 0, 2, -1}, {2, 0, 3, 0}, {3, 0, 1, -1}};
+      // the first step reads canonical order, later ones layer-1 order: as head, so that the
+      // repeated body starts and ends in the same layout
       tail = {{1, 0, 2, -1}, {2, 0, 3, 0}, {3, 0, 0, -1}};
+      if (nsteps == 1) return;
+      head = {{1, 0, 2, -1}, {2, 0, 3, 0}, {3, 0, 1, -1}};
+      body = head;
+      reps = nsteps - 2;
+      return;
     }
     reps = nsteps - 1;
     return;
@@ -1414,15 +1420,16 @@ struct lsx_batch {
   std::vector<lsx_state*> st;
   int fmt = 0, scheme = 0;
   bool w1 = false;
-  DBuf<TileDesc> tiles[2];
-  int ntiles[2] = {0, 0};
-  int nb[2] = {1, 1}, ks[2] = {2, 2};
-  float tuned_us[2] = {0.f, 0.f};
+  int nl = 2;  // layers of every system in the batch
+  DBuf<TileDesc> tiles[kMaxLayers];
+  int ntiles[kMaxLayers] = {0, 0, 0};
+  int nb[kMaxLayers] = {1, 1, 1}, ks[kMaxLayers] = {2, 2, 2};
+  float tuned_us[kMaxLayers] = {0.f, 0.f, 0.f};
   std::map<PatternKey, std::unique_ptr<DBuf<PassArgs>>> args;
   std::vector<std::pair<double2*, double2*>> bufs;  // buffers the argument arrays refer to
   DBuf<int32_t> marker;                              // non-null in_pos marker for gathering passes
   DBuf<int32_t> queue;                               // persistent launches: 9 counters, zero between launches
-  int persist[2] = {0, 0};                           // launch mode per layer: 0 one workgroup per tile,
+  int persist[kMaxLayers] = {0, 0, 0};               // launch mode per layer: 0 one workgroup per tile,
                                                      // 1 persistent with tile queues, 2 persistent static stride
   hipStream_t cap = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -1461,7 +1468,7 @@ static lsx_status batch_args(lsx_batch* b, const PatternKey& k, const PassArgs**
       a.tiles = nullptr;
       a.in_pos = layout_table(pl, k.layer, k.inlay);
       a.out_pos = layout_table(pl, k.layer, k.outlay);
-      a.ph_idx = (k.layer == 1) ? pl->L[0].rows.p : nullptr;
+      a.ph_idx = layout_map(pl, k.layer, pl->sys->nl);
       a.ph = (k.phase_half >= 0 && pl->kappa != 0.0) ? pl->phase[k.phase_half].p : nullptr;
       a.P = ps.data.p;
       a.diag = pl->diag.p ? pl->diag.p + (size_t)((k.layer - 1) * 3 + k.half) * pl->sys->N : nullptr;
@@ -1531,7 +1538,7 @@ static void batch_tiles(const lsx_batch* b, int layer, int nb, std::vector<TileD
 
 // Launches one batched pass; (cur, lay) follow the same rules as Runner.
 static lsx_status batch_pass(lsx_batch* b, hipStream_t s, const PassSpec& p, int& cur, int& lay) {
-  const int outlay = (p.next == 0) ? 2 : p.next;
+  const int outlay = (p.next == 0) ? b->nl : p.next;
   const PatternKey k{p.layer, p.half, lay, outlay, p.phase_half, cur};
   const PassArgs* d = nullptr;
   LSX_TRY(batch_args(b, k, &d));
@@ -1561,8 +1568,8 @@ extern "C" lsx_status lsx_batch_create(lsx_plan* const* plans, lsx_state* const*
       return cleanup(fail(LSX_E_STATE, "batch entry " + std::to_string(i) + ": state does not belong to plan"));
     if (plans[i]->scheme != plans[0]->scheme || plans[i]->fmt != plans[0]->fmt)
       return cleanup(fail(LSX_E_INVALID, "batch plans must share scheme and precision"));
-    if (plans[i]->sys->nl != 2 || !plans[i]->sys->standard)
-      return cleanup(fail(LSX_E_INVALID, "batches hold two-layer systems built from lattices"));
+    if (plans[i]->sys->nl != plans[0]->sys->nl)
+      return cleanup(fail(LSX_E_INVALID, "batch systems must have the same number of layers"));
     if ((states[i]->W == 1) != (states[0]->W == 1))
       return cleanup(fail(LSX_E_INVALID, "batch states must be all W = 1 or all W >= 2"));
     for (int j = 0; j < i; ++j)
@@ -1572,6 +1579,7 @@ extern "C" lsx_status lsx_batch_create(lsx_plan* const* plans, lsx_state* const*
   }
   b->fmt = plans[0]->fmt;
   b->scheme = plans[0]->scheme;
+  b->nl = plans[0]->sys->nl;
   b->w1 = states[0]->W == 1;
   lsx_status e;
   if ((e = b->marker.alloc(1)) != LSX_OK) return cleanup(e);
@@ -1613,7 +1621,10 @@ extern "C" lsx_status lsx_batch_create(lsx_plan* const* plans, lsx_state* const*
     if (e0) (void)hipEventDestroy(e0);
     return cleanup(fail(LSX_E_HIP, "event creation failed"));
   }
-  for (int layer = 1; layer <= 2; ++layer) {
+  for (int layer = 1; layer <= b->nl; ++layer) {
+    // time the first propagator slot the plans hold for this layer
+    int slot = 0;
+    while (slot < 2 && !b->pl[0]->L[layer - 1].prop[slot].present) ++slot;
     float best = -1.f;
     for (const Shape& c : cands) {
       std::vector<TileDesc> t;
@@ -1632,7 +1643,7 @@ extern "C" lsx_status lsx_batch_create(lsx_plan* const* plans, lsx_state* const*
       float ms = 0.f;
       if (cands.size() > 1) {
         int cur = 0, lay = layer;
-        const PassSpec p{layer, 0, layer == 1 ? 2 : 1, -1};
+        const PassSpec p{layer, slot, layer % b->nl + 1, -1};
         hipError_t he = hipSuccess;
         int c2 = 0, l2 = lay;
         if ((e = batch_pass(b, nullptr, p, c2, l2)) != LSX_OK) break;
@@ -1670,7 +1681,7 @@ extern "C" lsx_status lsx_batch_create(lsx_plan* const* plans, lsx_state* const*
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (e != LSX_OK) return cleanup(e);
-  for (int layer = 1; layer <= 2; ++layer)
+  for (int layer = 1; layer <= b->nl; ++layer)
     if (b->persist[layer - 1])
       for (const int32_t* gather : {static_cast<const int32_t*>(nullptr), static_cast<const int32_t*>(b->marker.p)}) {
         PassArgs a0{};
@@ -1702,22 +1713,33 @@ extern "C" lsx_status lsx_batch_step(lsx_batch* b, int64_t nsteps, void* stream)
     }
   std::vector<PassSpec> head, body, tail;
   int64_t reps = 0;
-  step_sequence(b->scheme, 2, nsteps, head, body, tail, reps);
-  int cur = 0, lay = 2;
+  step_sequence(b->scheme, b->nl, nsteps, head, body, tail, reps);
+  const int nl = b->nl;
+  int cur = 0, lay = nl;
   for (const PassSpec& p : head) LSX_TRY(batch_pass(b, s, p, cur, lay));
-  if (reps > 0) {
+  // The captured body must return to the (array, layout) state it starts from, so a body with
+  // an odd number of passes (three-layer Lie) is captured twice over; an odd repetition left
+  // over runs eagerly after the replays.
+  std::vector<PassSpec> gbody = body;
+  int64_t greps = reps, extra = 0;
+  if (body.size() % 2 == 1) {
+    gbody.insert(gbody.end(), body.begin(), body.end());
+    greps = reps / 2;
+    extra = reps % 2;
+  }
+  if (greps > 0) {
     // the body returns to the same (array, layout) state, so one captured graph serves
     // every repetition; it is built on first use and kept with the batch
     const int cur0 = cur, lay0 = lay;
     if (!b->exec || env_int("LSX_GRAPH", 1) == 0) {
       if (env_int("LSX_GRAPH", 1) == 0) {
-        for (int64_t r = 0; r < reps; ++r)
-          for (const PassSpec& p : body) LSX_TRY(batch_pass(b, s, p, cur, lay));
+        for (int64_t r = 0; r < greps; ++r)
+          for (const PassSpec& p : gbody) LSX_TRY(batch_pass(b, s, p, cur, lay));
       } else {
         // build every argument array first: capture must not do synchronous copies
         int c2 = cur, l2 = lay;
-        for (const PassSpec& p : body) {
-          const int outlay = (p.next == 0) ? 2 : p.next;
+        for (const PassSpec& p : gbody) {
+          const int outlay = (p.next == 0) ? nl : p.next;
           const PassArgs* d = nullptr;
           LSX_TRY(batch_args(b, PatternKey{p.layer, p.half, l2, outlay, p.phase_half, c2}, &d));
           c2 ^= 1;
@@ -1726,7 +1748,7 @@ extern "C" lsx_status lsx_batch_step(lsx_batch* b, int64_t nsteps, void* stream)
         if (!b->cap) LSX_HIP_TRY(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
         LSX_HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
         lsx_status cap_err = LSX_OK;
-        for (const PassSpec& p : body)
+        for (const PassSpec& p : gbody)
           if ((cap_err = batch_pass(b, b->cap, p, cur, lay)) != LSX_OK) break;
         hipGraph_t g = nullptr;
         const hipError_t ee = hipStreamEndCapture(b->cap, &g);
@@ -1742,16 +1764,14 @@ extern "C" lsx_status lsx_batch_step(lsx_batch* b, int64_t nsteps, void* stream)
       }
     }
     if (b->exec && env_int("LSX_GRAPH", 1) != 0) {
-      for (int64_t r = 0; r < reps; ++r) LSX_HIP_TRY(hipGraphLaunch(b->exec, s));
-      // the body has an even number of passes and ends in the layout it started from
-      for (const PassSpec& p : body) {
-        cur ^= 1;
-        lay = (p.next == 0) ? 2 : p.next;
-      }
-      if (body.size() % 2 == 0) cur = cur0;
+      for (int64_t r = 0; r < greps; ++r) LSX_HIP_TRY(hipGraphLaunch(b->exec, s));
+      // the captured body has an even number of passes and ends in the layout it started from
+      cur = cur0;
       lay = lay0;
     }
   }
+  for (int64_t r = 0; r < extra; ++r)
+    for (const PassSpec& p : body) LSX_TRY(batch_pass(b, s, p, cur, lay));
   for (const PassSpec& p : tail) LSX_TRY(batch_pass(b, s, p, cur, lay));
   if (cur != 0) {
     for (lsx_state* st : b->st)
@@ -1764,7 +1784,7 @@ extern "C" lsx_status lsx_batch_step(lsx_batch* b, int64_t nsteps, void* stream)
 extern "C" lsx_status lsx_batch_tuning(const lsx_batch* b, int32_t layer, int32_t* nb, int32_t* ks, double* pass_us,
                                        int32_t* launch_mode) {
   if (!b) return fail(LSX_E_INVALID, "null batch");
-  if (layer != 1 && layer != 2) return fail(LSX_E_INVALID, "layer must be 1 or 2");
+  if (layer < 1 || layer > b->nl) return fail(LSX_E_INVALID, "layer out of range");
   if (launch_mode) *launch_mode = b->persist[layer - 1];
   if (nb) *nb = b->nb[layer - 1];
   if (ks) *ks = b->ks[layer - 1];

@@ -126,3 +126,78 @@ def test_persistent_launch_equals_one_workgroup_per_tile(monkeypatch, precision,
     for mode in ("1", "2"):
         for a, b in zip(out[mode], out["0"]):
             assert np.array_equal(a, b), mode
+
+
+@pytest.mark.parametrize("scheme", ["strang", "lie", "lie_be", "strang_cn", "yoshida4"])
+def test_three_layer_batch_equals_individual(scheme):
+    """Three-layer systems of different sizes in one batch: every system equals the same system
+    stepped on its own.  Three-layer Lie has an odd number of passes per step, so its graph
+    holds two repetitions and an odd leftover runs eagerly (7 steps: head, 2 replays, 1 extra,
+    tail)."""
+    print(f"[case] three-layer batch {scheme}", flush=True)
+    specs = [(wl.chain_layers(800.0), 8), (wl.chain_layers(1500.0, periods=(1.0, math.sqrt(2.0), math.sqrt(3.0))), 5),
+             (wl.twisted_layers(120.0), 4)]
+    made = []
+    try:
+        for spec, W in specs:
+            S = lsx.System.layers(spec.d, spec.As, spec.Ec, spec.cutoff, spec.pots)
+            P = lsx.Plan(S, 0.004, scheme, 0.3, "fp64")
+            c0 = wl.random_state(S.N, W, seed=W)
+            ref = lsx.State(P, W)
+            ref.upload(c0)
+            ref.step(7)
+            st = lsx.State(P, W)
+            st.upload(c0)
+            made.append((S, P, st, ref, c0))
+        B = lsx.Batch([m[2] for m in made])
+        for _ in range(2):  # the second call replays the captured graph
+            for S, P, st, ref, c0 in made:
+                st.upload(c0)
+            B.step(7)
+            for S, P, st, ref, c0 in made:
+                assert colrel(st.download(), ref.download()) < 1e-13
+        B.destroy()
+    finally:
+        for S, P, st, ref, c0 in made:
+            st.destroy()
+            ref.destroy()
+            P.destroy()
+            S.destroy()
+
+
+def test_example3_batch_and_mixed_layer_counts():
+    made = []
+    try:
+        for k, Ec in enumerate((60.0, 100.0)):
+            spec = wl.example3_system(Ec)
+            S = lsx.System.blocks(spec.Rs, spec.groups, spec.Ec, spec.layers, spec.pots)
+            P = lsx.Plan(S, 0.01, "strang", 0.0, "mix_fp32")
+            c0 = wl.random_state(S.N, 16, seed=k)
+            ref = lsx.State(P, 16)
+            ref.upload(c0)
+            ref.step(6)
+            st = lsx.State(P, 16)
+            st.upload(c0)
+            made.append((S, P, st, ref))
+        B = lsx.Batch([m[2] for m in made])
+        B.step(6)
+        for S, P, st, ref in made:
+            assert colrel(st.download(), ref.download()) < 1e-8
+        B.destroy()
+        spec = wl.chain_layers(400.0)
+        S3 = lsx.System.layers(spec.d, spec.As, spec.Ec, spec.cutoff, spec.pots)
+        P3 = lsx.Plan(S3, 0.01, "strang", 0.0, "mix_fp32")
+        s3 = lsx.State(P3, 16)
+        try:
+            with pytest.raises(lsx.LsxError):
+                lsx.Batch([made[0][2], s3])  # two-layer and three-layer systems do not mix
+        finally:
+            s3.destroy()
+            P3.destroy()
+            S3.destroy()
+    finally:
+        for S, P, st, ref in made:
+            st.destroy()
+            ref.destroy()
+            P.destroy()
+            S.destroy()

@@ -133,8 +133,6 @@ def test_example3_rejections():
                 st.si_step(1)
             with pytest.raises(lsx.LsxError):
                 lsx.Sampler(st, 2, 2)
-            with pytest.raises(lsx.LsxError):
-                lsx.Batch([st])
         finally:
             st.destroy()
             P.destroy()

@@ -3,7 +3,8 @@ every layer and slot, Lie, Strang and Yoshida trajectories (FP64 <= 2e-12 relati
 step; Yoshida 6e-12 per step for its three Strang steps), the
 fused kinetic phase for kappa in {0, 0.4, 1}, single passes at ragged W in every precision,
 mixed precision after many steps, mass, energy and per-layer fibre masses, two layers through
-the layered constructor, and the entry points that take two-layer systems only."""
+the layered constructor, and the entry points that take two-layer systems only (samplers and
+the semi-implicit step)."""
 import numpy as np
 import pytest
 
@@ -244,8 +245,6 @@ def test_three_layer_rejections():
                 st.si_step(1)
             with pytest.raises(lsx.LsxError):
                 lsx.Sampler(st, 2, 2)
-            with pytest.raises(lsx.LsxError):
-                lsx.Batch([st])
             with pytest.raises(lsx.LsxError):
                 st.fibre_pass(4, 0)
         finally:
