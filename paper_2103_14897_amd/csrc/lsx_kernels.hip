@@ -358,6 +358,9 @@ __device__ __forceinline__ void tile_cols(const PassArgs& a, const TileDesc& t, 
 // v_mfma_f64_16x16x4f64 (ROWS_F64).  Summed over the KS waves in fixed order; mixed
 // formats add the FP64 diagonal term d_a x_a; an optional kinetic phase multiplies
 // the output row (the phase sub-step that follows this pass, fused).
+// The output is stored non-temporally: the next pass reads it in the other layer's fibre
+// order, mostly on other XCDs, so keeping it in this XCD's L2 only adds write-back work at
+// the end of the launch (measured: 10% per step on the short-fibre chain).
 template <int NB, int KS, bool MIX, bool ROWS_F64>
 __device__ __forceinline__ void pass_epilogue(const PassArgs& a, const TileDesc& t, double (&acc)[NB][2][4],
                                               double* red, const int (&wc)[NB], const bool (&wok)[NB]) {
@@ -416,7 +419,9 @@ __device__ __forceinline__ void pass_epilogue(const PassArgs& a, const TileDesc&
         yi = ph.x * yi + ph.y * yr;
         yr = zr;
       }
-      a.Y[orow * W + w] = make_double2(yr, yi);
+      double2* y = a.Y + orow * W + w;
+      __builtin_nontemporal_store(yr, &y->x);
+      __builtin_nontemporal_store(yi, &y->y);
     }
   }
 }
@@ -660,21 +665,25 @@ __global__ __launch_bounds__(64 * KS) void k_pass_f32_persist(PassArgs a0) {
 // x_r, x_i - x_r, x_r + x_i) into double-buffered LDS and read there by all MS waves, so
 // each state row is fetched once per row-block group instead of once per row block.  Each
 // wave streams its own propagator rows, one chunk ahead in registers.  No cross-wave
-// reduction: every wave owns its output rows.  Needs MS <= 4 NB.
+// reduction: every wave owns its output rows.  Needs MS <= 4 NB.  Chunks are KC k-steps
+// (4 KC fibre positions); four-wave groups take 32-row chunks, which halves the barriers and
+// doubles the work that hides each chunk's loads without costing occupancy.
 template <int NB, int MS>
 struct StageMap {
+  static constexpr int KC = MS == 4 ? 8 : 4;   // k-steps per chunk
+  static constexpr int CR = 4 * KC;            // rows of a chunk
   static constexpr int CW = 16 * NB;           // columns of a chunk
-  static constexpr int PER = 16 * CW / (64 * MS);  // elements per thread per chunk
+  static constexpr int PER = CR * CW / (64 * MS);  // elements per thread per chunk
   static constexpr int RSTEP = 64 * MS / CW;   // chunk rows between a thread's elements
 };
 
-template <int PER, int RSTEP, bool GATHER>
+template <int PER, int RSTEP, int CR, bool GATHER>
 __device__ __forceinline__ void stage_load_f32(double2 (&v)[PER], const PassArgs& a, int ch, int r0, int L, int w,
                                                bool wok, int rr0) {
   const double2* zx = reinterpret_cast<const double2*>(a.zero);
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
-    const int k = 16 * ch + rr0 + j * RSTEP;
+    const int k = CR * ch + rr0 + j * RSTEP;
     const bool ok = wok && k < L;
     const int64_t row = xrow<GATHER>(a, r0 + (ok ? k : 0));
     v[j] = *(ok ? a.X + row * a.W + w : zx);
@@ -684,13 +693,14 @@ __device__ __forceinline__ void stage_load_f32(double2 (&v)[PER], const PassArgs
 template <int NB, int MS, bool GATHER>
 __global__ __launch_bounds__(64 * MS) void k_pass_f32m(PassArgs a) {
   using SM = StageMap<NB, MS>;
-  __shared__ float4 xs[2][16][SM::CW];
+  constexpr int KC = SM::KC;
+  __shared__ float4 xs[2][SM::CR][SM::CW];
   if (a.tcount && (int)blockIdx.x >= *a.tcount) return;
   const TileDesc t0 = a.tiles[blockIdx.x];
   if (t0.f < 0) return;
   const int r0 = t0.r0, L = t0.L;
   const int nks = ((L + 15) & ~15) >> 2;
-  const int nch = nks >> 2;
+  const int nch = (nks + KC - 1) / KC;  // k-steps past nks read zeros
   const int lane = threadIdx.x & 63, kw = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int li = lane & 15, lk = lane >> 4;
   TileDesc t = t0;
@@ -716,10 +726,10 @@ __global__ __launch_bounds__(64 * MS) void k_pass_f32m(PassArgs a) {
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) k1[nb] = k2[nb] = k3[nb] = (v4f){0.f, 0.f, 0.f, 0.f};
   double2 sv[SM::PER];
-  float2 Ac[4], An[4];
-  stage_load_f32<SM::PER, SM::RSTEP, GATHER>(sv, a, 0, r0, L, sw, sok, rr0);
+  float2 Ac[KC], An[KC];
+  stage_load_f32<SM::PER, SM::RSTEP, SM::CR, GATHER>(sv, a, 0, r0, L, sw, sok, rr0);
 #pragma unroll
-  for (int u = 0; u < 4; ++u) Ac[u] = act ? P[u * 64] : *zp;
+  for (int u = 0; u < KC; ++u) Ac[u] = (act && u < nks) ? P[u * 64] : *zp;
 #pragma unroll
   for (int j = 0; j < SM::PER; ++j) {
     const float xr = (float)sv[j].x, xi = (float)sv[j].y;
@@ -730,14 +740,17 @@ __global__ __launch_bounds__(64 * MS) void k_pass_f32m(PassArgs a) {
     const int buf = ch & 1;
     const bool more = ch + 1 < nch;
     if (more) {
-      stage_load_f32<SM::PER, SM::RSTEP, GATHER>(sv, a, ch + 1, r0, L, sw, sok, rr0);
+      stage_load_f32<SM::PER, SM::RSTEP, SM::CR, GATHER>(sv, a, ch + 1, r0, L, sw, sok, rr0);
 #pragma unroll
-      for (int u = 0; u < 4; ++u) An[u] = act ? P[(int64_t)(4 * (ch + 1) + u) * 64] : *zp;
+      for (int u = 0; u < KC; ++u) {
+        const int ks = KC * (ch + 1) + u;
+        An[u] = (act && ks < nks) ? P[(int64_t)ks * 64] : *zp;
+      }
     }
     __builtin_amdgcn_sched_barrier(0);
     if (act) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < KC; ++u) {
         const float ps = Ac[u].x + Ac[u].y;
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
@@ -755,7 +768,7 @@ __global__ __launch_bounds__(64 * MS) void k_pass_f32m(PassArgs a) {
         xs[buf ^ 1][rr0 + j * SM::RSTEP][c] = make_float4(xr, xi - xr, xr + xi, 0.f);
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) Ac[u] = An[u];
+      for (int u = 0; u < KC; ++u) Ac[u] = An[u];
     }
     __syncthreads();
   }
