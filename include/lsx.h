@@ -269,6 +269,20 @@ lsx_status lsx_state_device_ptr(const lsx_state* st, void** dev_ptr);
  */
 lsx_status lsx_state_tuning(const lsx_state* st, int32_t layer, int32_t* nb, int32_t* ks, double* pass_us);
 
+/*
+ * Store mode chosen for the outputs of this state's fibre passes: *nontemporal = 1 when they
+ * are streamed out of the writing XCD's L2 (non-temporal stores), 0 for ordinary stores.  A
+ * step's next pass reads the output in its own layer's fibre order, mostly on other XCDs, so
+ * the faster mode depends on the state's size relative to the caches.  At creation, after the
+ * tile shapes, a cycle of passes over the layers in step order is timed with both modes
+ * between the work array and a temporary array of the state's size (the state is not read or
+ * written; without memory for the temporary array the mode stays 0).  cycle_us[0], [1] are
+ * the measured cycle times (0 if not timed).  LSX_NT=0 / 1 forces a mode; LSX_AUTOTUNE=0 and
+ * W = 1 (matrix-vector passes) keep 0.  The mode changes no result: both give bit-identical
+ * states.  Outputs may be NULL.
+ */
+lsx_status lsx_state_store_mode(const lsx_state* st, int32_t* nontemporal, double* cycle_us);
+
 lsx_status lsx_state_destroy(lsx_state* st);
 
 /*

@@ -908,6 +908,8 @@ struct lsx_state {
   int ntiles[kMaxLayers] = {0, 0, 0};
   int nb[kMaxLayers] = {1, 1, 1}, ks[kMaxLayers] = {4, 4, 4};  // tile shape per layer (16*nb columns, ks waves split k)
   float tuned_us[kMaxLayers] = {0.f, 0.f, 0.f};                // measured pass time of the chosen shape (0: not tuned)
+  int nt = 0;                          // pass output stores: 0 ordinary, 1 non-temporal
+  float store_us[2] = {0.f, 0.f};      // measured time of a step-like pass cycle per store mode
   DBuf<double> partial, result;
   int nred = 0;
   int nbatches = 0;                    // batches that reference this state
@@ -970,6 +972,74 @@ static void build_tiles(const lsx_plan* pl, int layer, int W, int nb, int wb0, i
 static int env_int(const char* name, int dflt) {
   const char* v = std::getenv(name);
   return v ? std::atoi(v) : dflt;
+}
+
+// Store mode of the pass outputs.  A step's passes each read the previous pass's output in
+// their own layer's fibre order, written mostly by other XCDs; whether ordinary or
+// non-temporal stores make that hand-over faster depends on the state's size relative to the
+// caches.  So a cycle of passes over the layers in step order (layer j reads its fibre order
+// and writes layer j+1's, with the chosen tile shapes) is timed with both, between the work
+// array and a scratch array of the same size, so the state is not modified.  Without room
+// for the scratch array the stores stay ordinary.
+static lsx_status choose_store_mode(lsx_plan* pl, lsx_state* st) {
+  const int nl = pl->sys->nl, W = st->W;
+  const int64_t N = pl->sys->N;
+  DBuf<double2> tmp;
+  if (tmp.alloc((size_t)N * W) != LSX_OK) {
+    st->nt = 0;
+    return LSX_OK;
+  }
+  PassArgs a[kMaxLayers];
+  double cycle_us = 0.0;
+  for (int layer = 1; layer <= nl; ++layer) {
+    const LayerDev& ld = pl->L[layer - 1];
+    int slot = 0;
+    while (slot < 2 && !ld.prop[slot].present) ++slot;
+    if (!ld.prop[slot].present) return fail(LSX_E_STATE, "internal: layer without propagators");
+    PassArgs& x = a[layer - 1];
+    x.tiles = st->tiles[layer - 1].p;
+    x.out_pos = layout_map(pl, layer, layer % nl + 1);
+    x.P = ld.prop[slot].data.p;
+    x.diag = pl->diag.p ? pl->diag.p + (size_t)((layer - 1) * 3 + slot) * N : nullptr;
+    x.zero = pl->zero.p;
+    x.W = W;
+    cycle_us += st->tuned_us[layer - 1] > 0.f ? st->tuned_us[layer - 1] : 10.0;
+  }
+  // about 2 ms of timed passes per mode, at least 3 cycles
+  const int reps = (int)std::max(3.0, std::min(200.0, 2000.0 / cycle_us));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return fail(LSX_E_HIP, "event creation failed");
+  }
+  hipError_t he = hipSuccess;
+  auto cycle = [&](int nt) {
+    double2* src = st->buf[1];
+    double2* dst = tmp.p;
+    for (int layer = 1; layer <= nl && he == hipSuccess; ++layer) {
+      PassArgs x = a[layer - 1];
+      x.X = src;
+      x.Y = dst;
+      x.nt = nt;
+      he = launch_pass(nullptr, pl->fmt, W, st->ntiles[layer - 1], st->nb[layer - 1], st->ks[layer - 1], x);
+      std::swap(src, dst);
+    }
+  };
+  for (int nt = 0; nt < 2 && he == hipSuccess; ++nt) {
+    cycle(nt);  // warm-up
+    if (he == hipSuccess) he = hipEventRecord(e0, nullptr);
+    for (int r = 0; r < reps && he == hipSuccess; ++r) cycle(nt);
+    if (he == hipSuccess) he = hipEventRecord(e1, nullptr);
+    if (he == hipSuccess) he = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+    st->store_us[nt] = ms * 1e3f / reps;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (he != hipSuccess) return fail(LSX_E_HIP, std::string("store-mode tuning: ") + hipGetErrorString(he));
+  st->nt = st->store_us[1] < st->store_us[0] ? 1 : 0;
+  return LSX_OK;
 }
 
 // Tile shape per layer.  LSX_NB / LSX_KS force a shape; otherwise, unless
@@ -1071,7 +1141,14 @@ static lsx_status choose_tiles(lsx_plan* pl, lsx_state* st) {
   }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
-  return err;
+  if (err != LSX_OK) return err;
+  const int fnt = env_int("LSX_NT", -1);
+  if (fnt == 0 || fnt == 1) {
+    st->nt = fnt;
+    return LSX_OK;
+  }
+  if (W == 1 || pl->sys->N == 0 || env_int("LSX_AUTOTUNE", 1) == 0) return LSX_OK;
+  return choose_store_mode(pl, st);
 }
 
 extern "C" lsx_status lsx_state_create(lsx_plan* pl, int32_t W, void* dev_ptr, lsx_state** out) {
@@ -1147,6 +1224,16 @@ extern "C" lsx_status lsx_state_tuning(const lsx_state* st, int32_t layer, int32
   return LSX_OK;
 }
 
+extern "C" lsx_status lsx_state_store_mode(const lsx_state* st, int32_t* nontemporal, double* cycle_us) {
+  if (!st) return fail(LSX_E_INVALID, "null state");
+  if (nontemporal) *nontemporal = st->nt;
+  if (cycle_us) {
+    cycle_us[0] = st->store_us[0];
+    cycle_us[1] = st->store_us[1];
+  }
+  return LSX_OK;
+}
+
 extern "C" lsx_status lsx_state_destroy(lsx_state* st) {
   if (!st) return LSX_OK;
   if (st->nbatches > 0) return fail(LSX_E_STATE, "state is still part of a batch");
@@ -1195,6 +1282,7 @@ struct Runner {
     a.Y = st->buf[1 - cur];
     a.zero = pl->zero.p;
     a.W = st->W;
+    a.nt = st->nt;
     LSX_HIP_TRY(launch_pass(s, pl->fmt, st->W, st->ntiles[layer - 1], st->nb[layer - 1], st->ks[layer - 1], a));
     cur ^= 1;
     lay = outlay;
@@ -1477,6 +1565,7 @@ static lsx_status batch_args(lsx_batch* b, const PatternKey& k, const PassArgs**
       a.zero = pl->zero.p;
       a.batch = nullptr;
       a.W = st->W;
+      a.nt = st->nt;
     }
     auto d = std::make_unique<DBuf<PassArgs>>();
     LSX_TRY(d->alloc(v.size()));

@@ -88,6 +88,9 @@ struct PassArgs {
   int32_t* queue = nullptr;
   int32_t ntiles = 0;
   int32_t W = 0;
+  // output stores: 0 ordinary (lines kept in the writer's L2), 1 non-temporal (streamed out);
+  // the faster one depends on the state's size and is measured per state
+  int32_t nt = 0;
 };
 
 // ---------------------------------------------------------------- kernel launchers (lsx_kernels.hip)

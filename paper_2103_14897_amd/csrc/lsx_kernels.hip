@@ -358,9 +358,10 @@ __device__ __forceinline__ void tile_cols(const PassArgs& a, const TileDesc& t, 
 // v_mfma_f64_16x16x4f64 (ROWS_F64).  Summed over the KS waves in fixed order; mixed
 // formats add the FP64 diagonal term d_a x_a; an optional kinetic phase multiplies
 // the output row (the phase sub-step that follows this pass, fused).
-// The output is stored non-temporally: the next pass reads it in the other layer's fibre
-// order, mostly on other XCDs, so keeping it in this XCD's L2 only adds write-back work at
-// the end of the launch (measured: 10% per step on the short-fibre chain).
+// With a.nt set the output is stored non-temporally.  The next pass reads it in the other
+// layer's fibre order, mostly on other XCDs, so keeping it in this XCD's L2 can only add
+// write-back work at the end of the launch; but for states that fit the last-level cache,
+// ordinary stores leave it there for the next pass.  The host measures which is faster.
 template <int NB, int KS, bool MIX, bool ROWS_F64>
 __device__ __forceinline__ void pass_epilogue(const PassArgs& a, const TileDesc& t, double (&acc)[NB][2][4],
                                               double* red, const int (&wc)[NB], const bool (&wok)[NB]) {
@@ -420,8 +421,16 @@ __device__ __forceinline__ void pass_epilogue(const PassArgs& a, const TileDesc&
         yr = zr;
       }
       double2* y = a.Y + orow * W + w;
-      __builtin_nontemporal_store(yr, &y->x);
-      __builtin_nontemporal_store(yi, &y->y);
+      if (a.nt) {
+        // empty compiler barriers (no instruction) around the stores keep them from being
+        // hoisted or sunk together with the other branch's, which would drop the hint
+        asm volatile("" ::: "memory");
+        __builtin_nontemporal_store(yr, &y->x);
+        __builtin_nontemporal_store(yi, &y->y);
+        asm volatile("" ::: "memory");
+      } else {
+        *y = make_double2(yr, yi);
+      }
     }
   }
 }

@@ -56,6 +56,7 @@ _SIGS = {
     "lsx_state_download": (C.c_int, [_p, _dp, _p]),
     "lsx_state_device_ptr": (C.c_int, [_p, C.POINTER(_p)]),
     "lsx_state_tuning": (C.c_int, [_p, C.c_int32, _i32p, _i32p, _dp]),
+    "lsx_state_store_mode": (C.c_int, [_p, _i32p, _dp]),
     "lsx_state_destroy": (C.c_int, [_p]),
     "lsx_step": (C.c_int, [_p, _p, C.c_int64, _p]),
     "lsx_fibre_pass": (C.c_int, [_p, _p, C.c_int32, C.c_int32, C.c_int32, _p]),
@@ -338,6 +339,12 @@ class State:
         nb, ks, us = C.c_int32(), C.c_int32(), C.c_double()
         _check(lib().lsx_state_tuning(self.h, int(layer), C.byref(nb), C.byref(ks), C.byref(us)))
         return nb.value, ks.value, us.value
+
+    def store_mode(self):
+        """(nontemporal, (cycle_us ordinary, cycle_us non-temporal)) chosen for the pass outputs."""
+        nt, us = C.c_int32(), (C.c_double * 2)()
+        _check(lib().lsx_state_store_mode(self.h, C.byref(nt), us))
+        return nt.value, (us[0], us[1])
 
     def destroy(self):
         if self.h:

@@ -1,0 +1,70 @@
+"""Pass output store modes: ordinary and non-temporal stores give bit-identical trajectories
+(the mode only changes where the written lines live, never a value), on two-layer, three-layer
+and shared-block systems in every precision, and the tuner reports a mode with both cycle
+times measured."""
+import numpy as np
+import pytest
+
+from paper_2103_14897_amd import lsx
+from paper_2103_14897_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def systems():
+    yield "chain", lsx.System.from_spec(wl.chain_system(2000.0))
+    yield "twisted", lsx.System.from_spec(wl.twisted_system(300.0))
+    spec = wl.twisted_layers(60.0)
+    yield "trilayer", lsx.System.layers(spec.d, spec.As, spec.Ec, spec.cutoff, spec.pots)
+    spec = wl.example3_system(200.0)
+    yield "example3", lsx.System.blocks(spec.Rs, spec.groups, spec.Ec, spec.layers, spec.pots)
+
+
+@pytest.mark.parametrize("precision,nb,ks", [("fp64", 1, 2), ("fp64", 2, 1), ("mix_fp32", 1, 4),
+                                             ("mix_fp32", 2, -4), ("mix_bf16x3", 1, 2), ("mix_bf16x3", 2, -2)])
+def test_store_modes_bit_identical(monkeypatch, precision, nb, ks):
+    # one forced tile shape, so that both states sum in the same order
+    monkeypatch.setenv("LSX_NB", str(nb))
+    monkeypatch.setenv("LSX_KS", str(ks))
+    W = 24
+    for name, S in systems():
+        print(f"[case] store modes {name} N={S.N} {precision} nb={nb} ks={ks}", flush=True)
+        P = None
+        try:
+            P = lsx.Plan(S, 5e-3, "strang", 0.0, precision)
+            c = wl.random_state(S.N, W, seed=5)
+            out = []
+            for nt in (0, 1):
+                monkeypatch.setenv("LSX_NT", str(nt))
+                st = lsx.State(P, W)
+                try:
+                    assert st.store_mode()[0] == nt
+                    assert st.tuning(1)[:2] == (nb, ks)
+                    st.upload(c)
+                    st.step(7)
+                    out.append(st.download())
+                finally:
+                    st.destroy()
+            assert np.array_equal(out[0], out[1]), name
+        finally:
+            if P is not None:
+                P.destroy()
+            S.destroy()
+
+
+def test_store_mode_is_tuned():
+    S = lsx.System.from_spec(wl.chain_system(2.0e4))
+    P = lsx.Plan(S, 1e-3, "strang", 0.0, "mix_fp32")
+    try:
+        st = lsx.State(P, 64)
+        nt, us = st.store_mode()
+        print(f"  chain Ec=2e4 W=64: mode {nt}, cycle us {us}")
+        assert nt in (0, 1) and us[0] > 0.0 and us[1] > 0.0
+        assert nt == (1 if us[1] < us[0] else 0)
+        st.destroy()
+        st1 = lsx.State(P, 1)  # matrix-vector passes keep ordinary stores, untimed
+        assert st1.store_mode() == (0, (0.0, 0.0))
+        st1.destroy()
+    finally:
+        P.destroy()
+        S.destroy()
