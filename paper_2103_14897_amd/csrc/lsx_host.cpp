@@ -990,7 +990,6 @@ static lsx_status choose_store_mode(lsx_plan* pl, lsx_state* st) {
     return LSX_OK;
   }
   PassArgs a[kMaxLayers];
-  double cycle_us = 0.0;
   for (int layer = 1; layer <= nl; ++layer) {
     const LayerDev& ld = pl->L[layer - 1];
     int slot = 0;
@@ -1003,10 +1002,7 @@ static lsx_status choose_store_mode(lsx_plan* pl, lsx_state* st) {
     x.diag = pl->diag.p ? pl->diag.p + (size_t)((layer - 1) * 3 + slot) * N : nullptr;
     x.zero = pl->zero.p;
     x.W = W;
-    cycle_us += st->tuned_us[layer - 1] > 0.f ? st->tuned_us[layer - 1] : 10.0;
   }
-  // about 2 ms of timed passes per mode, at least 3 cycles
-  const int reps = (int)std::max(3.0, std::min(200.0, 2000.0 / cycle_us));
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     if (e0) (void)hipEventDestroy(e0);
@@ -1025,15 +1021,21 @@ static lsx_status choose_store_mode(lsx_plan* pl, lsx_state* st) {
       std::swap(src, dst);
     }
   };
-  for (int nt = 0; nt < 2 && he == hipSuccess; ++nt) {
-    cycle(nt);  // warm-up
+  // one timed warm-up cycle per mode sizes the measurement: about 2 ms of passes, at least 3
+  // and at most 200 cycles
+  auto timed = [&](int nt, int reps) {
+    float ms = 0.f;
     if (he == hipSuccess) he = hipEventRecord(e0, nullptr);
     for (int r = 0; r < reps && he == hipSuccess; ++r) cycle(nt);
     if (he == hipSuccess) he = hipEventRecord(e1, nullptr);
     if (he == hipSuccess) he = hipEventSynchronize(e1);
-    float ms = 0.f;
     if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
-    st->store_us[nt] = ms * 1e3f / reps;
+    return ms * 1e3f / reps;
+  };
+  for (int nt = 0; nt < 2 && he == hipSuccess; ++nt) {
+    const float warm_us = timed(nt, 1);
+    const int reps = (int)std::max(3.0, std::min(200.0, 2000.0 / std::max(1.0f, warm_us)));
+    st->store_us[nt] = timed(nt, reps);
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
