@@ -265,7 +265,10 @@ lsx_status lsx_state_device_ptr(const lsx_state* st, void** dev_ptr);
  * fibre length, or (ks < 0, mixed FP32) -ks consecutive 16-row blocks, one per wave, that
  * share the state operand staged once per workgroup in LDS.  At creation every candidate shape is timed on the state's own size
  * (LSX_AUTOTUNE=0 disables, LSX_NB / LSX_KS force a shape); pass_us is the measured
- * time of one pass with the chosen shape (0 if nothing was timed).  Outputs may be NULL.
+ * time of one pass with the chosen shape (0 if nothing was timed).  For the ks > 0 shapes of
+ * the FP64 and mixed FP32 paths the candidates also differ in how many groups of k-steps each
+ * wave keeps in flight (one or two; LSX_PREFETCH=1 / 2 / 4 forces it, a forced shape uses 2),
+ * which changes the summation order, so the rounding, of the pass.  Outputs may be NULL.
  */
 lsx_status lsx_state_tuning(const lsx_state* st, int32_t layer, int32_t* nb, int32_t* ks, double* pass_us);
 

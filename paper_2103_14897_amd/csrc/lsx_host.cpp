@@ -907,6 +907,7 @@ struct lsx_state {
   DBuf<TileDesc> tiles[kMaxLayers];
   int ntiles[kMaxLayers] = {0, 0, 0};
   int nb[kMaxLayers] = {1, 1, 1}, ks[kMaxLayers] = {4, 4, 4};  // tile shape per layer (16*nb columns, ks waves split k)
+  int u[kMaxLayers] = {0, 0, 0};       // K-split FP64/FP32: k-step groups in flight per wave (0: default)
   float tuned_us[kMaxLayers] = {0.f, 0.f, 0.f};                // measured pass time of the chosen shape (0: not tuned)
   int nt = 0;                          // pass output stores: 0 ordinary, 1 non-temporal
   float store_us[2] = {0.f, 0.f};      // measured time of a step-like pass cycle per store mode
@@ -1002,6 +1003,7 @@ static lsx_status choose_store_mode(lsx_plan* pl, lsx_state* st) {
     x.diag = pl->diag.p ? pl->diag.p + (size_t)((layer - 1) * 3 + slot) * N : nullptr;
     x.zero = pl->zero.p;
     x.W = W;
+    x.u = st->u[layer - 1];
   }
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
@@ -1052,30 +1054,36 @@ static lsx_status choose_tiles(lsx_plan* pl, lsx_state* st) {
   const int W = st->W;
   // ks > 0: ks waves split the fibre length; ks < 0: -ks waves take consecutive row blocks
   // and share the LDS-staged state operand (mixed FP32 and BF16x3 paths, BF16x3 with nb <= 2)
+  // u: groups of k-steps each wave of a K-split FP64 / FP32 tile keeps in flight (0: the
+  // library default, LSX_PREFETCH); shorter fibres favour 1 (fewer registers, more waves)
   struct Shape {
-    int nb, ks;
+    int nb, ks, u;
   };
   std::vector<Shape> cands;
   const int fnb = env_int("LSX_NB", 0), fks = env_int("LSX_KS", 0);
+  const bool tune_u = (pl->fmt == PF_F64 || pl->fmt == PF_F32) && std::getenv("LSX_PREFETCH") == nullptr;
   if (W == 1) {
-    for (int k : {1, 2, 4}) cands.push_back({1, k});
+    for (int k : {1, 2, 4}) cands.push_back({1, k, 0});
   } else {
     for (int nb : {1, 2, 4})
       for (int k : {1, 2, 4})
-        if (16 * nb <= round_up(W, 16) && !(nb == 4 && k == 4)) cands.push_back({nb, k});
+        if (16 * nb <= round_up(W, 16) && !(nb == 4 && k == 4)) {
+          cands.push_back({nb, k, tune_u ? 2 : 0});
+          if (tune_u) cands.push_back({nb, k, 1});
+        }
     if (pl->fmt == PF_F32 || pl->fmt == PF_BF16X3)
       for (int nb : {1, 2, 4})
         for (int m : {2, 4})
-          if (16 * nb <= round_up(W, 16) && !(pl->fmt == PF_BF16X3 && nb == 4)) cands.push_back({nb, -m});
+          if (16 * nb <= round_up(W, 16) && !(pl->fmt == PF_BF16X3 && nb == 4)) cands.push_back({nb, -m, 0});
   }
   if (fnb > 0 || fks != 0) {
     const bool rowsplit = fks < 0 && W > 1 && pl->fmt != PF_F64 && (fks == -2 || fks == -4) &&
                           !(pl->fmt == PF_BF16X3 && fnb == 4);
     const Shape f{(fnb == 1 || fnb == 2 || fnb == 4) ? fnb : 1,
-                  rowsplit ? fks : ((fks == 1 || fks == 2 || fks == 4) ? fks : 2)};
+                  rowsplit ? fks : ((fks == 1 || fks == 2 || fks == 4) ? fks : 2), 0};
     cands.assign(1, f);
   } else if (env_int("LSX_AUTOTUNE", 1) == 0 || pl->sys->N == 0) {
-    cands.assign(1, Shape{1, W == 1 ? 4 : 2});
+    cands.assign(1, Shape{1, W == 1 ? 4 : 2, 0});
   }
   hipEvent_t e0 = nullptr, e1 = nullptr;
   const bool timing = cands.size() > 1;
@@ -1116,6 +1124,7 @@ static lsx_status choose_tiles(lsx_plan* pl, lsx_state* st) {
         a.Y = st->buf[1];
         a.zero = pl->zero.p;
         a.W = W;
+        a.u = c.u;
         const int reps = 5;
         hipError_t he = launch_pass(nullptr, pl->fmt, W, (int)t.size(), c.nb, c.ks, a);
         if (he == hipSuccess) he = hipEventRecord(e0, nullptr);
@@ -1133,6 +1142,7 @@ static lsx_status choose_tiles(lsx_plan* pl, lsx_state* st) {
         best = ms;
         st->nb[layer - 1] = c.nb;
         st->ks[layer - 1] = c.ks;
+        st->u[layer - 1] = c.u;
         st->tiles[layer - 1].release();
         std::swap(st->tiles[layer - 1].p, d.p);
         std::swap(st->tiles[layer - 1].n, d.n);
@@ -1285,6 +1295,7 @@ struct Runner {
     a.zero = pl->zero.p;
     a.W = st->W;
     a.nt = st->nt;
+    a.u = st->u[layer - 1];
     LSX_HIP_TRY(launch_pass(s, pl->fmt, st->W, st->ntiles[layer - 1], st->nb[layer - 1], st->ks[layer - 1], a));
     cur ^= 1;
     lay = outlay;

@@ -91,6 +91,9 @@ struct PassArgs {
   // output stores: 0 ordinary (lines kept in the writer's L2), 1 non-temporal (streamed out);
   // the faster one depends on the state's size and is measured per state
   int32_t nt = 0;
+  // K-split FP64 / FP32 passes: groups of k-steps each wave keeps in flight (1, 2 or 4; 0: the
+  // library default), chosen per state by the tile tuner
+  int32_t u = 0;
 };
 
 // ---------------------------------------------------------------- kernel launchers (lsx_kernels.hip)
