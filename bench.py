@@ -424,7 +424,7 @@ def layered_bench(args, S, W, tau, slot, what, workload):
             e1.synchronize()
             passes[j] = e0.elapsed_time(e1) * 1e3 / args.kernel_reps
         res[path] = {"coeff_steps_per_s": N * W * args.steps / (ms * 1e-3), "ms_per_step": ms / args.steps,
-                     "pass_us": passes, "tiles": {j: st.tuning(j)[:2] for j in layers},
+                     "pass_us": passes, "tiles": {j: st.tuning(j)[:2] + (st.prefetch(j),) for j in layers},
                      "nontemporal_stores": st.store_mode()[0]}
         st.destroy()
         P.destroy()
@@ -567,7 +567,8 @@ def main():
             phase_us = k0.elapsed_time(k1) * 1e3 / args.kernel_reps
         res[path] = {"coeff_steps_per_s": N * W * args.steps / (ms * 1e-3), "ms_per_step": ms / args.steps,
                      "wall_ms": wall * 1e3, "precompute_s": pre, "layer2_pass_us": kus, "layer1_pass_us": kus1,
-                     "tiles": {"layer1": st.tuning(1)[:2], "layer2": st.tuning(2)[:2]},
+                     "tiles": {"layer1": st.tuning(1)[:2] + (st.prefetch(1),),
+                               "layer2": st.tuning(2)[:2] + (st.prefetch(2),)},
                      "nontemporal_stores": st.store_mode()[0]}
         if phase_us is not None:
             res[path]["phase_us"] = phase_us

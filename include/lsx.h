@@ -272,6 +272,11 @@ lsx_status lsx_state_device_ptr(const lsx_state* st, void** dev_ptr);
  */
 lsx_status lsx_state_tuning(const lsx_state* st, int32_t layer, int32_t* nb, int32_t* ks, double* pass_us);
 
+/* Groups of k-steps each wave keeps in flight in the fibre passes of `layer` (1 .. nlayers),
+ * as chosen by the tile tuner for the ks > 0 shapes of the FP64 and mixed FP32 paths: 1 or 2,
+ * or 0 where the library default applies (2, or LSX_PREFETCH; also every other shape). */
+lsx_status lsx_state_prefetch(const lsx_state* st, int32_t layer, int32_t* groups);
+
 /*
  * Store mode chosen for the outputs of this state's fibre passes: *nontemporal = 1 when they
  * are streamed out of the writing XCD's L2 (non-temporal stores), 0 for ordinary stores.  A

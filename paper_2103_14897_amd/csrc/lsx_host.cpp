@@ -1236,6 +1236,13 @@ extern "C" lsx_status lsx_state_tuning(const lsx_state* st, int32_t layer, int32
   return LSX_OK;
 }
 
+extern "C" lsx_status lsx_state_prefetch(const lsx_state* st, int32_t layer, int32_t* groups) {
+  if (!st) return fail(LSX_E_INVALID, "null state");
+  if (layer < 1 || layer > st->plan->sys->nl) return fail(LSX_E_INVALID, "layer out of range");
+  if (groups) *groups = st->u[layer - 1];
+  return LSX_OK;
+}
+
 extern "C" lsx_status lsx_state_store_mode(const lsx_state* st, int32_t* nontemporal, double* cycle_us) {
   if (!st) return fail(LSX_E_INVALID, "null state");
   if (nontemporal) *nontemporal = st->nt;

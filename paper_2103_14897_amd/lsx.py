@@ -57,6 +57,7 @@ _SIGS = {
     "lsx_state_device_ptr": (C.c_int, [_p, C.POINTER(_p)]),
     "lsx_state_tuning": (C.c_int, [_p, C.c_int32, _i32p, _i32p, _dp]),
     "lsx_state_store_mode": (C.c_int, [_p, _i32p, _dp]),
+    "lsx_state_prefetch": (C.c_int, [_p, C.c_int32, _i32p]),
     "lsx_state_destroy": (C.c_int, [_p]),
     "lsx_step": (C.c_int, [_p, _p, C.c_int64, _p]),
     "lsx_fibre_pass": (C.c_int, [_p, _p, C.c_int32, C.c_int32, C.c_int32, _p]),
@@ -339,6 +340,12 @@ class State:
         nb, ks, us = C.c_int32(), C.c_int32(), C.c_double()
         _check(lib().lsx_state_tuning(self.h, int(layer), C.byref(nb), C.byref(ks), C.byref(us)))
         return nb.value, ks.value, us.value
+
+    def prefetch(self, layer):
+        """Groups of k-steps in flight per wave chosen for `layer` (0: library default)."""
+        u = C.c_int32()
+        _check(lib().lsx_state_prefetch(self.h, int(layer), C.byref(u)))
+        return u.value
 
     def store_mode(self):
         """(nontemporal, (cycle_us ordinary, cycle_us non-temporal)) chosen for the pass outputs."""
