@@ -1,7 +1,7 @@
-"""Pass output store modes: ordinary and non-temporal stores give bit-identical trajectories
-(the mode only changes where the written lines live, never a value), on two-layer, three-layer
-and shared-block systems in every precision, and the tuner reports a mode with both cycle
-times measured."""
+"""Pass output store modes and the reported prefetch depth.  Ordinary and non-temporal stores
+give bit-identical trajectories (the mode only changes where the written lines live, never a
+value) on two-layer, three-layer and shared-block systems in every precision; the tuner
+reports a store mode with both cycle times measured, and the prefetch depth it chose."""
 import numpy as np
 import pytest
 
@@ -67,4 +67,33 @@ def test_store_mode_is_tuned():
         st1.destroy()
     finally:
         P.destroy()
+        S.destroy()
+
+
+def test_prefetch_depth_reported(monkeypatch):
+    """The tile tuner's prefetch depth: 1 or 2 on the K-split shapes of the FP64 and mixed FP32
+    paths, 0 (library default) for row-split shapes, BF16x3, forced shapes and LSX_PREFETCH."""
+    S = lsx.System.from_spec(wl.chain_system(2.0e4))
+    try:
+        for precision in ("fp64", "mix_fp32", "mix_bf16x3"):
+            P = lsx.Plan(S, 1e-3, "strang", 0.0, precision)
+            try:
+                st = lsx.State(P, 64)
+                for layer in (1, 2):
+                    u, ks = st.prefetch(layer), st.tuning(layer)[1]
+                    print(f"  {precision} layer {layer}: ks {ks} prefetch {u}")
+                    if precision != "mix_bf16x3" and ks > 0:
+                        assert u in (1, 2)
+                    else:
+                        assert u == 0
+                st.destroy()
+                for env in (("LSX_NB", "1"), ("LSX_PREFETCH", "1")):
+                    monkeypatch.setenv(*env)
+                    st = lsx.State(P, 64)
+                    assert st.prefetch(1) == 0 and st.prefetch(2) == 0, env
+                    st.destroy()
+                    monkeypatch.delenv(env[0])
+            finally:
+                P.destroy()
+    finally:
         S.destroy()
