@@ -15,6 +15,7 @@
 #include <cstdlib>
 #include <map>
 #include <mutex>
+#include <type_traits>
 
 #include "lsx_internal.h"
 
@@ -1070,25 +1071,41 @@ __device__ __forceinline__ void k_gemv_tile(const PassArgs& a0, int ti, double* 
       }
     }
   } else {
+    // Groups of G k-steps: all loads of a group are issued before its products, with the
+    // state operand of positions past the fibre read from the zero buffer (their propagator
+    // entries are zero padding), so the loads stay branch-free; the products are summed in
+    // k-step order as one at a time.
+    using PT = typename std::conditional<FMT == PF_F64, double2, float2>::type;
+    constexpr int G = 8;
     const int nks = ((L + 15) & ~15) >> 2;
-#pragma unroll 4
-    for (int ks = kw; ks < nks; ks += KS) {
+    const PT* P = reinterpret_cast<const PT*>(Pb) + (int64_t)rb * nks * 64 + lane;
+    const double2* zx = reinterpret_cast<const double2*>(a.zero);
+    int ks = kw;
+    for (; ks + (G - 1) * KS < nks; ks += G * KS) {
+      PT p[G];
+      double2 x[G];
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const int kk = ks + g * KS, k = 4 * kk + lk;
+        const bool ok = k < L;
+        p[g] = P[(int64_t)kk * 64];
+        x[g] = *(ok ? a.X + in_row(a, r0 + (ok ? k : 0)) : zx);
+      }
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const double pr = p[g].x, pi = p[g].y;
+        yr += pr * x[g].x - pi * x[g].y;
+        yi += pr * x[g].y + pi * x[g].x;
+      }
+    }
+    for (; ks < nks; ks += KS) {
       const int k = 4 * ks + lk;
-      double pr, pi;
-      if (FMT == PF_F64) {
-        const double2 p = reinterpret_cast<const double2*>(Pb)[((int64_t)rb * nks + ks) * 64 + lane];
-        pr = p.x;
-        pi = p.y;
-      } else {
-        const float2 p = reinterpret_cast<const float2*>(Pb)[((int64_t)rb * nks + ks) * 64 + lane];
-        pr = p.x;
-        pi = p.y;
-      }
-      if (k < L) {
-        const double2 x = a.X[in_row(a, r0 + k)];
-        yr += pr * x.x - pi * x.y;
-        yi += pr * x.y + pi * x.x;
-      }
+      const bool ok = k < L;
+      const PT pe = P[(int64_t)ks * 64];
+      const double2 x = *(ok ? a.X + in_row(a, r0 + (ok ? k : 0)) : zx);
+      const double pr = pe.x, pi = pe.y;
+      yr += pr * x.x - pi * x.y;
+      yi += pr * x.y + pi * x.x;
     }
   }
   // sum the four k-lanes of each row (lanes li, li+16, li+32, li+48)
