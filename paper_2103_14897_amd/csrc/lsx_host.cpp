@@ -1125,18 +1125,26 @@ static lsx_status choose_tiles(lsx_plan* pl, lsx_state* st) {
         a.zero = pl->zero.p;
         a.W = W;
         a.u = c.u;
-        const int reps = 5;
+        // five timed passes, then, for passes under 200 us, about 1 ms of them: launch jitter
+        // is comparable to a few-microsecond pass
+        auto time_reps = [&](int reps, float& per) {
+          hipError_t e = hipEventRecord(e0, nullptr);
+          for (int r = 0; r < reps && e == hipSuccess; ++r)
+            e = launch_pass(nullptr, pl->fmt, W, (int)t.size(), c.nb, c.ks, a);
+          if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
+          if (e == hipSuccess) e = hipEventSynchronize(e1);
+          float total = 0.f;
+          if (e == hipSuccess) e = hipEventElapsedTime(&total, e0, e1);
+          per = total / reps;
+          return e;
+        };
         hipError_t he = launch_pass(nullptr, pl->fmt, W, (int)t.size(), c.nb, c.ks, a);
-        if (he == hipSuccess) he = hipEventRecord(e0, nullptr);
-        for (int r = 0; r < reps && he == hipSuccess; ++r) he = launch_pass(nullptr, pl->fmt, W, (int)t.size(), c.nb, c.ks, a);
-        if (he == hipSuccess) he = hipEventRecord(e1, nullptr);
-        if (he == hipSuccess) he = hipEventSynchronize(e1);
-        if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+        if (he == hipSuccess) he = time_reps(5, ms);
+        if (he == hipSuccess && ms < 0.2f) he = time_reps(std::min(100, std::max(5, (int)(1.0f / std::max(ms, 1e-3f)))), ms);
         if (he != hipSuccess) {
           err = fail(LSX_E_HIP, std::string("autotune: ") + hipGetErrorString(he));
           break;
         }
-        ms /= reps;
       }
       if (best < 0.f || ms < best) {
         best = ms;
