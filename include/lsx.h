@@ -273,8 +273,10 @@ lsx_status lsx_state_device_ptr(const lsx_state* st, void** dev_ptr);
 lsx_status lsx_state_tuning(const lsx_state* st, int32_t layer, int32_t* nb, int32_t* ks, double* pass_us);
 
 /* Groups of k-steps each wave keeps in flight in the fibre passes of `layer` (1 .. nlayers),
- * as chosen by the tile tuner for the ks > 0 shapes of the FP64 and mixed FP32 paths: 1 or 2,
- * or 0 where the library default applies (2, or LSX_PREFETCH; also every other shape). */
+ * for the ks > 0 shapes of the FP64 and mixed FP32 paths: 1 or 2, chosen at creation by the
+ * tile tuner's single passes and then kept or flipped by the step-like cycle timed for the
+ * store mode (lsx_state_store_mode); 0 where the library default applies (2, or LSX_PREFETCH;
+ * also every other shape and a forced shape). */
 lsx_status lsx_state_prefetch(const lsx_state* st, int32_t layer, int32_t* groups);
 
 /*
@@ -282,12 +284,13 @@ lsx_status lsx_state_prefetch(const lsx_state* st, int32_t layer, int32_t* group
  * are streamed out of the writing XCD's L2 (non-temporal stores), 0 for ordinary stores.  A
  * step's next pass reads the output in its own layer's fibre order, mostly on other XCDs, so
  * the faster mode depends on the state's size relative to the caches.  At creation, after the
- * tile shapes, a cycle of passes over the layers in step order is timed with both modes
+ * tile shapes, a cycle of passes over the layers in step order is timed with both modes, and
+ * with both prefetch depths on every layer where the tile tuner chose one (lsx_state_prefetch),
  * between the work array and a temporary array of the state's size (the state is not read or
  * written; without memory for the temporary array the mode stays 0).  cycle_us[0], [1] are
- * the measured cycle times (0 if not timed).  LSX_NT=0 / 1 forces a mode; LSX_AUTOTUNE=0 and
- * W = 1 (matrix-vector passes) keep 0.  The mode changes no result: both give bit-identical
- * states.  Outputs may be NULL.
+ * the best cycle times measured with each mode (0 if not timed).  LSX_NT=0 / 1 forces a mode;
+ * LSX_AUTOTUNE=0 and W = 1 (matrix-vector passes) keep 0.  The mode changes no result: both
+ * give bit-identical states.  Outputs may be NULL.
  */
 lsx_status lsx_state_store_mode(const lsx_state* st, int32_t* nontemporal, double* cycle_us);
 

@@ -975,22 +975,24 @@ static int env_int(const char* name, int dflt) {
   return v ? std::atoi(v) : dflt;
 }
 
-// Store mode of the pass outputs.  A step's passes each read the previous pass's output in
-// their own layer's fibre order, written mostly by other XCDs; whether ordinary or
-// non-temporal stores make that hand-over faster depends on the state's size relative to the
-// caches.  So a cycle of passes over the layers in step order (layer j reads its fibre order
-// and writes layer j+1's, with the chosen tile shapes) is timed with both, between the work
-// array and a scratch array of the same size, so the state is not modified.  Without room
-// for the scratch array the stores stay ordinary.
-static lsx_status choose_store_mode(lsx_plan* pl, lsx_state* st) {
+// Store mode of the pass outputs, and the prefetch depth of K-split FP64 / FP32 passes, in the
+// setting of a step.  A step's passes each read the previous pass's output in their own layer's
+// fibre order, written mostly by other XCDs; whether ordinary or non-temporal stores make that
+// hand-over faster depends on the state's size relative to the caches, and how many k-step
+// groups a wave should keep in flight depends on where its operands come from (single-pass
+// timings read them from the same XCD's L2).  So a cycle of passes over the layers in step
+// order (layer j reads its fibre order and writes layer j+1's, with the chosen tile shapes) is
+// timed for both store modes and, on every layer whose depth was tuned, both depths; between
+// the work array and a scratch array of the same size, so the state is not modified.  Without
+// room for the scratch array the stores stay ordinary and the depths as tuned.  With
+// tune_store false only the depths are compared (ordinary stores or the forced mode).
+static lsx_status choose_cycle(lsx_plan* pl, lsx_state* st, bool tune_store) {
   const int nl = pl->sys->nl, W = st->W;
   const int64_t N = pl->sys->N;
   DBuf<double2> tmp;
-  if (tmp.alloc((size_t)N * W) != LSX_OK) {
-    st->nt = 0;
-    return LSX_OK;
-  }
+  if (tmp.alloc((size_t)N * W) != LSX_OK) return LSX_OK;
   PassArgs a[kMaxLayers];
+  int tun[kMaxLayers], ntun = 0;
   for (int layer = 1; layer <= nl; ++layer) {
     const LayerDev& ld = pl->L[layer - 1];
     int slot = 0;
@@ -1003,7 +1005,7 @@ static lsx_status choose_store_mode(lsx_plan* pl, lsx_state* st) {
     x.diag = pl->diag.p ? pl->diag.p + (size_t)((layer - 1) * 3 + slot) * N : nullptr;
     x.zero = pl->zero.p;
     x.W = W;
-    x.u = st->u[layer - 1];
+    if (st->u[layer - 1] == 1 || st->u[layer - 1] == 2) tun[ntun++] = layer - 1;
   }
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
@@ -1011,6 +1013,7 @@ static lsx_status choose_store_mode(lsx_plan* pl, lsx_state* st) {
     return fail(LSX_E_HIP, "event creation failed");
   }
   hipError_t he = hipSuccess;
+  int u[kMaxLayers];
   auto cycle = [&](int nt) {
     double2* src = st->buf[1];
     double2* dst = tmp.p;
@@ -1019,12 +1022,11 @@ static lsx_status choose_store_mode(lsx_plan* pl, lsx_state* st) {
       x.X = src;
       x.Y = dst;
       x.nt = nt;
+      x.u = u[layer - 1];
       he = launch_pass(nullptr, pl->fmt, W, st->ntiles[layer - 1], st->nb[layer - 1], st->ks[layer - 1], x);
       std::swap(src, dst);
     }
   };
-  // one timed warm-up cycle per mode sizes the measurement: about 2 ms of passes, at least 3
-  // and at most 200 cycles
   auto timed = [&](int nt, int reps) {
     float ms = 0.f;
     if (he == hipSuccess) he = hipEventRecord(e0, nullptr);
@@ -1034,15 +1036,34 @@ static lsx_status choose_store_mode(lsx_plan* pl, lsx_state* st) {
     if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
     return ms * 1e3f / reps;
   };
-  for (int nt = 0; nt < 2 && he == hipSuccess; ++nt) {
-    const float warm_us = timed(nt, 1);
-    const int reps = (int)std::max(3.0, std::min(200.0, 2000.0 / std::max(1.0f, warm_us)));
-    st->store_us[nt] = timed(nt, reps);
+  float best = -1.f;
+  int best_nt = st->nt, best_u[kMaxLayers];
+  if (tune_store) st->store_us[0] = st->store_us[1] = 0.f;
+  for (int l = 0; l < nl; ++l) best_u[l] = st->u[l];
+  const int nts = tune_store ? 2 : 1;
+  for (int mask = 0; mask < (1 << ntun) && he == hipSuccess; ++mask) {
+    for (int l = 0; l < nl; ++l) u[l] = st->u[l];
+    for (int j = 0; j < ntun; ++j)
+      if (mask >> j & 1) u[tun[j]] = 3 - u[tun[j]];  // the other depth of {1, 2}
+    for (int m = 0; m < nts && he == hipSuccess; ++m) {
+      const int nt = tune_store ? m : st->nt;
+      // one timed warm-up cycle sizes the measurement: about 2 ms of passes, 3 to 200 cycles
+      const float warm_us = timed(nt, 1);
+      const int reps = (int)std::max(3.0, std::min(200.0, 2000.0 / std::max(1.0f, warm_us)));
+      const float us = timed(nt, reps);
+      if (tune_store && (st->store_us[nt] == 0.f || us < st->store_us[nt])) st->store_us[nt] = us;
+      if (he == hipSuccess && (best < 0.f || us < best)) {
+        best = us;
+        best_nt = nt;
+        for (int l = 0; l < nl; ++l) best_u[l] = u[l];
+      }
+    }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  if (he != hipSuccess) return fail(LSX_E_HIP, std::string("store-mode tuning: ") + hipGetErrorString(he));
-  st->nt = st->store_us[1] < st->store_us[0] ? 1 : 0;
+  if (he != hipSuccess) return fail(LSX_E_HIP, std::string("step-cycle tuning: ") + hipGetErrorString(he));
+  st->nt = best_nt;
+  for (int l = 0; l < nl; ++l) st->u[l] = best_u[l];
   return LSX_OK;
 }
 
@@ -1163,12 +1184,9 @@ static lsx_status choose_tiles(lsx_plan* pl, lsx_state* st) {
   if (e1) (void)hipEventDestroy(e1);
   if (err != LSX_OK) return err;
   const int fnt = env_int("LSX_NT", -1);
-  if (fnt == 0 || fnt == 1) {
-    st->nt = fnt;
-    return LSX_OK;
-  }
+  if (fnt == 0 || fnt == 1) st->nt = fnt;
   if (W == 1 || pl->sys->N == 0 || env_int("LSX_AUTOTUNE", 1) == 0) return LSX_OK;
-  return choose_store_mode(pl, st);
+  return choose_cycle(pl, st, !(fnt == 0 || fnt == 1));
 }
 
 extern "C" lsx_status lsx_state_create(lsx_plan* pl, int32_t W, void* dev_ptr, lsx_state** out) {
