@@ -97,3 +97,33 @@ def test_prefetch_depth_reported(monkeypatch):
                 P.destroy()
     finally:
         S.destroy()
+
+
+def test_autotune_off_keeps_defaults(monkeypatch):
+    """LSX_AUTOTUNE=0: nothing is timed at creation; default shape, library-default depth and
+    ordinary stores, and the step still matches a tuned state to rounding."""
+    S = lsx.System.from_spec(wl.chain_system(2000.0))
+    P = lsx.Plan(S, 1e-3, "strang", 0.0, "mix_fp32")
+    try:
+        c = wl.random_state(S.N, 16, seed=2)
+        st = lsx.State(P, 16)
+        st.upload(c)
+        st.step(20)
+        ref = st.download()
+        st.destroy()
+        monkeypatch.setenv("LSX_AUTOTUNE", "0")
+        st = lsx.State(P, 16)
+        try:
+            assert st.store_mode() == (0, (0.0, 0.0))
+            for layer in (1, 2):
+                assert st.tuning(layer) == (1, 2, 0.0) and st.prefetch(layer) == 0
+            st.upload(c)
+            st.step(20)
+            out = st.download()
+            err = (np.linalg.norm(out - ref, axis=0) / np.linalg.norm(ref, axis=0)).max()
+            assert err < 1e-12, err
+        finally:
+            st.destroy()
+    finally:
+        P.destroy()
+        S.destroy()
