@@ -1,6 +1,12 @@
 """Build liblsx.so (HIP/C++ for gfx950) in-tree with hipcc.
 
     python -m paper_2103_14897_amd.build
+    python -m paper_2103_14897_amd.build --host-asan   # also _build/liblsx_host_asan.so
+
+--host-asan builds a second library whose host code (lsx_host.cpp) is instrumented with
+AddressSanitizer; the device code is the same as the product's and is not instrumented.  It
+is for the CPU tests of the host code (see README.md), loaded through LSX_LIB with the
+sanitizer runtime preloaded; it is never the product library.
 """
 import os
 import subprocess
@@ -47,6 +53,31 @@ def build(verbose=False):
     return LIB
 
 
+def build_host_asan(verbose=False):
+    """_build/liblsx_host_asan.so: the product's device objects with an AddressSanitizer build
+    of the host code (sanitizer flags on the host side only)."""
+    build(verbose)
+    obj = os.path.join(BUILD, "lsx_host_asan.o")
+    flags = [f for f in COMMON if f != "-O3"] + ["-O1", "-g", "-Xarch_host", "-fsanitize=address",
+                                                   "-Xarch_host", "-fno-omit-frame-pointer"]
+    r = subprocess.run(["hipcc", *flags, "-c", os.path.join(CSRC, "lsx_host.cpp"), "-o", obj],
+                       capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for lsx_host.cpp (sanitized):\n{r.stderr}")
+    out = os.path.join(BUILD, "liblsx_host_asan.so")
+    objs = [obj] + [os.path.join(BUILD, s + ".o") for s in SOURCES if s != "lsx_host.cpp"]
+    r = subprocess.run(["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-Xarch_host", "-fsanitize=address",
+                        *objs, "-o", out], capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{r.stderr}")
+    if verbose:
+        print("built", out)
+    return out
+
+
 if __name__ == "__main__":
-    build(verbose=True)
+    if "--host-asan" in sys.argv[1:]:
+        build_host_asan(verbose=True)
+    else:
+        build(verbose=True)
     sys.exit(0)

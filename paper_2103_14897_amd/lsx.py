@@ -17,7 +17,8 @@ import os
 
 import numpy as np
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liblsx.so")
+# the in-tree library; LSX_LIB names another build of it (the host-sanitized one for CPU tests)
+LIB_PATH = os.environ.get("LSX_LIB") or os.path.join(os.path.dirname(os.path.abspath(__file__)), "liblsx.so")
 
 LSX_OK, LSX_E_INVALID, LSX_E_NOT_HERMITIAN, LSX_E_OOM, LSX_E_HIP, LSX_E_EIG, LSX_E_NONFINITE, LSX_E_STATE = (
     0, -1, -2, -3, -4, -5, -6, -7)
