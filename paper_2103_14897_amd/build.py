@@ -58,16 +58,17 @@ def build_host_asan(verbose=False):
     of the host code (sanitizer flags on the host side only)."""
     build(verbose)
     obj = os.path.join(BUILD, "lsx_host_asan.o")
-    flags = [f for f in COMMON if f != "-O3"] + ["-O1", "-g", "-Xarch_host", "-fsanitize=address",
-                                                   "-Xarch_host", "-fno-omit-frame-pointer"]
+    # host-side only: each sanitizer flag follows -Xarch_host
+    san = ["-Xarch_host", "-fsanitize=address"]
+    flags = [f for f in COMMON if f != "-O3"] + ["-O1", "-g", *san, "-Xarch_host", "-fno-omit-frame-pointer"]
     r = subprocess.run(["hipcc", *flags, "-c", os.path.join(CSRC, "lsx_host.cpp"), "-o", obj],
                        capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for lsx_host.cpp (sanitized):\n{r.stderr}")
     out = os.path.join(BUILD, "liblsx_host_asan.so")
     objs = [obj] + [os.path.join(BUILD, s + ".o") for s in SOURCES if s != "lsx_host.cpp"]
-    r = subprocess.run(["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-Xarch_host", "-fsanitize=address",
-                        *objs, "-o", out], capture_output=True, text=True)
+    r = subprocess.run(["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", *san, *objs, "-o", out],
+                       capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
     if verbose:
