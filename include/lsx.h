@@ -349,7 +349,10 @@ lsx_status lsx_observables(lsx_plan* plan, lsx_state* st, uint32_t mask, double*
  *   the uneven tiles), or a persistent grid of the resident capacity that walks the
  *   XCD-interleaved tile list with a static stride, or one that claims tiles from per-XCD
  *   queues on device counters (cleared by the last workgroup of each launch, so replayed
- *   graphs need no memset).  All three give bit-identical results for one tile shape.
+ *   graphs need no memset).  All three give bit-identical results for one tile shape.  For
+ *   the FP64 and mixed FP32 paths the candidates also differ in the groups of k-steps each
+ *   wave keeps in flight (one or two, as for states; LSX_PREFETCH is not applied here, and a
+ *   forced shape keeps two).
  *   Plans and states must outlive the batch (destroying a state that is in a batch returns
  *   LSX_E_STATE).  While a batch step is in flight no other call may use its states.
  * lsx_batch_step: advances every state by nsteps * tau_i with its plan's scheme, exactly

@@ -1563,6 +1563,7 @@ struct lsx_batch {
   std::vector<std::pair<double2*, double2*>> bufs;  // buffers the argument arrays refer to
   DBuf<int32_t> marker;                              // non-null in_pos marker for gathering passes
   DBuf<int32_t> queue;                               // persistent launches: 9 counters, zero between launches
+  int u[kMaxLayers] = {0, 0, 0};                     // K-split FP64/FP32: k-step groups in flight (0: 2)
   int persist[kMaxLayers] = {0, 0, 0};               // launch mode per layer: 0 one workgroup per tile,
                                                      // 1 persistent with tile queues, 2 persistent static stride
   hipStream_t cap = nullptr;
@@ -1683,6 +1684,7 @@ static lsx_status batch_pass(lsx_batch* b, hipStream_t s, const PassSpec& p, int
   a0.batch = d;
   a0.persist = b->persist[p.layer - 1];
   a0.queue = b->queue.p;
+  a0.u = b->u[p.layer - 1];
   LSX_HIP_TRY(launch_pass(s, b->fmt, b->w1 ? 1 : 2, b->ntiles[p.layer - 1], b->nb[p.layer - 1],
                           b->ks[p.layer - 1], a0, true));
   cur ^= 1;
@@ -1725,21 +1727,26 @@ extern "C" lsx_status lsx_batch_create(lsx_plan* const* plans, lsx_state* const*
   // patterns.  Modes: 0 one workgroup per tile (the hardware dispatcher balances), 2
   // persistent grid with a static stride, 1 persistent grid with per-XCD tile queues;
   // LSX_PERSIST forces one mode, LSX_NB / LSX_KS one shape.
+  // u: groups of k-steps in flight per wave of the FP64 / FP32 tiles (0: two), as for states
   struct Shape {
-    int nb, ks, pm;
+    int nb, ks, pm, u;
   };
   std::vector<Shape> shapes;
   int maxW = 1;
   for (lsx_state* st : b->st) maxW = std::max(maxW, st->W);
+  const bool tune_u = (b->fmt == PF_F64 || b->fmt == PF_F32) && std::getenv("LSX_PREFETCH") == nullptr;
   if (b->w1) {
-    shapes.push_back({1, 4, 0});
+    shapes.push_back({1, 4, 0, 0});
   } else {
     for (int nbv : {1, 2, 4})
       for (int k : {1, 2, 4})
-        if (16 * nbv <= round_up(maxW, 16) && !(nbv == 4 && k == 4)) shapes.push_back({nbv, k, 0});
+        if (16 * nbv <= round_up(maxW, 16) && !(nbv == 4 && k == 4)) {
+          shapes.push_back({nbv, k, 0, 0});
+          if (tune_u) shapes.push_back({nbv, k, 0, 1});
+        }
     const int fnb = env_int("LSX_NB", 0), fks = env_int("LSX_KS", 0);
-    if (fnb > 0 || fks > 0) shapes.assign(1, Shape{fnb > 0 ? fnb : 1, fks > 0 ? fks : 2, 0});
-    else if (env_int("LSX_AUTOTUNE", 1) == 0) shapes.assign(1, Shape{1, 2, 0});
+    if (fnb > 0 || fks > 0) shapes.assign(1, Shape{fnb > 0 ? fnb : 1, fks > 0 ? fks : 2, 0, 0});
+    else if (env_int("LSX_AUTOTUNE", 1) == 0) shapes.assign(1, Shape{1, 2, 0, 0});
   }
   const int fpm = env_int("LSX_PERSIST", -1);
   std::vector<int> modes = {0, 2, 1};
@@ -1770,11 +1777,12 @@ extern "C" lsx_status lsx_batch_create(lsx_plan* const* plans, lsx_state* const*
       std::swap(b->tiles[layer - 1].p, d.p);
       std::swap(b->tiles[layer - 1].n, d.n);
       const int save_nt = b->ntiles[layer - 1], save_nb = b->nb[layer - 1], save_ks = b->ks[layer - 1];
-      const int save_pm = b->persist[layer - 1];
+      const int save_pm = b->persist[layer - 1], save_u = b->u[layer - 1];
       b->ntiles[layer - 1] = (int)t.size();
       b->nb[layer - 1] = c.nb;
       b->ks[layer - 1] = c.ks;
       b->persist[layer - 1] = c.pm;
+      b->u[layer - 1] = c.u;
       float ms = 0.f;
       if (cands.size() > 1) {
         int cur = 0, lay = layer;
@@ -1808,6 +1816,7 @@ extern "C" lsx_status lsx_batch_create(lsx_plan* const* plans, lsx_state* const*
         b->nb[layer - 1] = save_nb;
         b->ks[layer - 1] = save_ks;
         b->persist[layer - 1] = save_pm;
+        b->u[layer - 1] = save_u;
       }
     }
     if (e != LSX_OK) break;
@@ -1823,6 +1832,7 @@ extern "C" lsx_status lsx_batch_create(lsx_plan* const* plans, lsx_state* const*
         a0.in_pos = gather;
         a0.persist = b->persist[layer - 1];
         a0.queue = b->queue.p;
+        a0.u = b->u[layer - 1];
         if (prepare_persistent(b->fmt, b->w1 ? 1 : 2, b->nb[layer - 1], b->ks[layer - 1], a0) != hipSuccess)
           return cleanup(fail(LSX_E_HIP, "persistent launch setup failed"));
       }

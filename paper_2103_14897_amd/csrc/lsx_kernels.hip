@@ -1407,7 +1407,9 @@ static hipError_t launch_mfma_u(hipStream_t s, int fmt, int ntiles, const PassAr
 
 template <int NB, int KS, bool G>
 static hipError_t launch_mfma_g(hipStream_t s, int fmt, int ntiles, const PassArgs& a, bool batched) {
-  if (batched) return launch_mfma_u<NB, KS, 2, G, true>(s, fmt, ntiles, a);
+  if (batched)
+    return (fmt != PF_BF16X3 && a.u == 1) ? launch_mfma_u<NB, KS, 1, G, true>(s, fmt, ntiles, a)
+                                          : launch_mfma_u<NB, KS, 2, G, true>(s, fmt, ntiles, a);
   switch (fmt == PF_BF16X3 ? 1 : (a.u == 1 || a.u == 2 || a.u == 4) ? a.u : prefetch_depth()) {
     case 1: return launch_mfma_u<NB, KS, 1, G, false>(s, fmt, ntiles, a);
     case 4: return launch_mfma_u<NB, KS, 4, G, false>(s, fmt, ntiles, a);
