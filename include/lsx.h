@@ -265,7 +265,9 @@ lsx_status lsx_state_device_ptr(const lsx_state* st, void** dev_ptr);
  * fibre length, or (ks < 0, mixed FP32) -ks consecutive 16-row blocks, one per wave, that
  * share the state operand staged once per workgroup in LDS.  At creation every candidate shape is timed on the state's own size
  * (LSX_AUTOTUNE=0 disables, LSX_NB / LSX_KS force a shape); pass_us is the measured
- * time of one pass with the chosen shape (0 if nothing was timed).  For the ks > 0 shapes of
+ * time of one pass with the chosen shape (0 if nothing was timed).  The single-pass winner and
+ * runner-up of each layer are then compared on the step-like cycle described at
+ * lsx_state_store_mode, which keeps whichever makes the cycle faster.  For the ks > 0 shapes of
  * the FP64 and mixed FP32 paths the candidates also differ in how many groups of k-steps each
  * wave keeps in flight (one or two; LSX_PREFETCH=1 / 2 / 4 forces it, a forced shape uses 2),
  * which changes the summation order, so the rounding, of the pass.  Outputs may be NULL.
@@ -284,11 +286,13 @@ lsx_status lsx_state_prefetch(const lsx_state* st, int32_t layer, int32_t* group
  * are streamed out of the writing XCD's L2 (non-temporal stores), 0 for ordinary stores.  A
  * step's next pass reads the output in its own layer's fibre order, mostly on other XCDs, so
  * the faster mode depends on the state's size relative to the caches.  At creation, after the
- * tile shapes, a cycle of passes over the layers in step order is timed with both modes, and
- * with both prefetch depths on every layer where the tile tuner chose one (lsx_state_prefetch),
- * between the work array and a temporary array of the state's size (the state is not read or
- * written; without memory for the temporary array the mode stays 0).  cycle_us[0], [1] are
- * the best cycle times measured with each mode (0 if not timed).  LSX_NT=0 / 1 forces a mode;
+ * tile shapes, a cycle of passes over the layers in step order is timed with both modes, for
+ * the tile tuner's choice and, one layer at a time, for that layer's alternatives (the other
+ * prefetch depth where one was tuned, see lsx_state_prefetch, and the single-pass runner-up
+ * shape); the fastest combination is kept.  The cycle runs between the work array and a
+ * temporary array of the state's size (the state is not read or written; without memory for
+ * the temporary array the mode stays 0).  cycle_us[0], [1] are the best cycle times measured
+ * with each mode (0 if not timed).  LSX_NT=0 / 1 forces a mode;
  * LSX_AUTOTUNE=0 and W = 1 (matrix-vector passes) keep 0.  The mode changes no result: both
  * give bit-identical states.  Outputs may be NULL.
  */

@@ -909,6 +909,12 @@ struct lsx_state {
   int nb[kMaxLayers] = {1, 1, 1}, ks[kMaxLayers] = {4, 4, 4};  // tile shape per layer (16*nb columns, ks waves split k)
   int u[kMaxLayers] = {0, 0, 0};       // K-split FP64/FP32: k-step groups in flight per wave (0: default)
   float tuned_us[kMaxLayers] = {0.f, 0.f, 0.f};                // measured pass time of the chosen shape (0: not tuned)
+  // runner-up tile shape per layer from the single-pass timings (alt_nb = 0: none); the
+  // step-like cycle may prefer it
+  int alt_nb[kMaxLayers] = {0, 0, 0}, alt_ks[kMaxLayers] = {0, 0, 0}, alt_u[kMaxLayers] = {0, 0, 0};
+  int alt_ntiles[kMaxLayers] = {0, 0, 0};
+  float alt_us[kMaxLayers] = {0.f, 0.f, 0.f};
+  DBuf<TileDesc> alt_tiles[kMaxLayers];
   int nt = 0;                          // pass output stores: 0 ordinary, 1 non-temporal
   float store_us[2] = {0.f, 0.f};      // measured time of a step-like pass cycle per store mode
   DBuf<double> partial, result;
@@ -975,37 +981,47 @@ static int env_int(const char* name, int dflt) {
   return v ? std::atoi(v) : dflt;
 }
 
-// Store mode of the pass outputs, and the prefetch depth of K-split FP64 / FP32 passes, in the
-// setting of a step.  A step's passes each read the previous pass's output in their own layer's
-// fibre order, written mostly by other XCDs; whether ordinary or non-temporal stores make that
-// hand-over faster depends on the state's size relative to the caches, and how many k-step
-// groups a wave should keep in flight depends on where its operands come from (single-pass
-// timings read them from the same XCD's L2).  So a cycle of passes over the layers in step
-// order (layer j reads its fibre order and writes layer j+1's, with the chosen tile shapes) is
-// timed for both store modes and, on every layer whose depth was tuned, both depths; between
-// the work array and a scratch array of the same size, so the state is not modified.  Without
-// room for the scratch array the stores stay ordinary and the depths as tuned.  With
-// tune_store false only the depths are compared (ordinary stores or the forced mode).
+// Store mode of the pass outputs, prefetch depth and tile shape, in the setting of a step.  A
+// step's passes each read the previous pass's output in their own layer's fibre order, written
+// mostly by other XCDs; whether ordinary or non-temporal stores make that hand-over faster
+// depends on the state's size relative to the caches, and which tile shape and how many k-step
+// groups in flight suit a layer depend on where its operands come from (single-pass timings
+// read them from the same XCD's L2).  So a cycle of passes over the layers in step order
+// (layer j reads its fibre order and writes layer j+1's) is timed with both store modes, for
+// the single-pass winner of every layer and, one layer at a time, for its alternatives: the
+// winner with the other depth (where a depth was tuned) and the single-pass runner-up.  The
+// cycle runs between the work array and a scratch array of the same size, so the state is not
+// modified.  Without room for the scratch array everything stays as the single passes chose.
+// With tune_store false the store mode stays as set (ordinary or forced).
 static lsx_status choose_cycle(lsx_plan* pl, lsx_state* st, bool tune_store) {
   const int nl = pl->sys->nl, W = st->W;
   const int64_t N = pl->sys->N;
   DBuf<double2> tmp;
   if (tmp.alloc((size_t)N * W) != LSX_OK) return LSX_OK;
   PassArgs a[kMaxLayers];
-  int tun[kMaxLayers], ntun = 0;
   for (int layer = 1; layer <= nl; ++layer) {
     const LayerDev& ld = pl->L[layer - 1];
     int slot = 0;
     while (slot < 2 && !ld.prop[slot].present) ++slot;
     if (!ld.prop[slot].present) return fail(LSX_E_STATE, "internal: layer without propagators");
     PassArgs& x = a[layer - 1];
-    x.tiles = st->tiles[layer - 1].p;
     x.out_pos = layout_map(pl, layer, layer % nl + 1);
     x.P = ld.prop[slot].data.p;
     x.diag = pl->diag.p ? pl->diag.p + (size_t)((layer - 1) * 3 + slot) * N : nullptr;
     x.zero = pl->zero.p;
     x.W = W;
-    if (st->u[layer - 1] == 1 || st->u[layer - 1] == 2) tun[ntun++] = layer - 1;
+  }
+  // per layer: option 0 the single-pass winner, 1 the winner at the other depth, 2 the runner-up
+  struct Opt {
+    bool ok;
+    int nb, ks, u, ntiles;
+    const TileDesc* tiles;
+  };
+  Opt opt[kMaxLayers][3];
+  for (int l = 0; l < nl; ++l) {
+    opt[l][0] = {true, st->nb[l], st->ks[l], st->u[l], st->ntiles[l], st->tiles[l].p};
+    opt[l][1] = {st->u[l] == 1 || st->u[l] == 2, st->nb[l], st->ks[l], 3 - st->u[l], st->ntiles[l], st->tiles[l].p};
+    opt[l][2] = {st->alt_nb[l] > 0, st->alt_nb[l], st->alt_ks[l], st->alt_u[l], st->alt_ntiles[l], st->alt_tiles[l].p};
   }
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
@@ -1013,17 +1029,19 @@ static lsx_status choose_cycle(lsx_plan* pl, lsx_state* st, bool tune_store) {
     return fail(LSX_E_HIP, "event creation failed");
   }
   hipError_t he = hipSuccess;
-  int u[kMaxLayers];
+  int pick[kMaxLayers] = {0, 0, 0};
   auto cycle = [&](int nt) {
     double2* src = st->buf[1];
     double2* dst = tmp.p;
-    for (int layer = 1; layer <= nl && he == hipSuccess; ++layer) {
-      PassArgs x = a[layer - 1];
+    for (int l = 0; l < nl && he == hipSuccess; ++l) {
+      const Opt& o = opt[l][pick[l]];
+      PassArgs x = a[l];
+      x.tiles = o.tiles;
       x.X = src;
       x.Y = dst;
       x.nt = nt;
-      x.u = u[layer - 1];
-      he = launch_pass(nullptr, pl->fmt, W, st->ntiles[layer - 1], st->nb[layer - 1], st->ks[layer - 1], x);
+      x.u = o.u;
+      he = launch_pass(nullptr, pl->fmt, W, o.ntiles, o.nb, o.ks, x);
       std::swap(src, dst);
     }
   };
@@ -1036,34 +1054,57 @@ static lsx_status choose_cycle(lsx_plan* pl, lsx_state* st, bool tune_store) {
     if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
     return ms * 1e3f / reps;
   };
-  float best = -1.f;
-  int best_nt = st->nt, best_u[kMaxLayers];
   if (tune_store) st->store_us[0] = st->store_us[1] = 0.f;
-  for (int l = 0; l < nl; ++l) best_u[l] = st->u[l];
-  const int nts = tune_store ? 2 : 1;
-  for (int mask = 0; mask < (1 << ntun) && he == hipSuccess; ++mask) {
-    for (int l = 0; l < nl; ++l) u[l] = st->u[l];
-    for (int j = 0; j < ntun; ++j)
-      if (mask >> j & 1) u[tun[j]] = 3 - u[tun[j]];  // the other depth of {1, 2}
-    for (int m = 0; m < nts && he == hipSuccess; ++m) {
+  // the cycle with the current picks, each store mode: about 2 ms of passes, 3 to 200 cycles
+  // sized by a timed warm-up cycle; returns the best time and its mode
+  auto evaluate = [&](int& nt_best) {
+    float best = -1.f;
+    for (int m = 0; m < (tune_store ? 2 : 1) && he == hipSuccess; ++m) {
       const int nt = tune_store ? m : st->nt;
-      // one timed warm-up cycle sizes the measurement: about 2 ms of passes, 3 to 200 cycles
       const float warm_us = timed(nt, 1);
       const int reps = (int)std::max(3.0, std::min(200.0, 2000.0 / std::max(1.0f, warm_us)));
       const float us = timed(nt, reps);
       if (tune_store && (st->store_us[nt] == 0.f || us < st->store_us[nt])) st->store_us[nt] = us;
-      if (he == hipSuccess && (best < 0.f || us < best)) {
+      if (best < 0.f || us < best) {
         best = us;
-        best_nt = nt;
-        for (int l = 0; l < nl; ++l) best_u[l] = u[l];
+        nt_best = nt;
       }
     }
-  }
+    return best;
+  };
+  int best_nt = st->nt;
+  float best = evaluate(best_nt);
+  int best_pick[kMaxLayers] = {0, 0, 0};
+  for (int l = 0; l < nl && he == hipSuccess; ++l)
+    for (int k = 1; k < 3 && he == hipSuccess; ++k) {
+      if (!opt[l][k].ok) continue;
+      for (int j = 0; j < nl; ++j) pick[j] = best_pick[j];
+      pick[l] = k;
+      int nt = best_nt;
+      const float us = evaluate(nt);
+      if (he == hipSuccess && us < best) {
+        best = us;
+        best_nt = nt;
+        for (int j = 0; j < nl; ++j) best_pick[j] = pick[j];
+      }
+    }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (he != hipSuccess) return fail(LSX_E_HIP, std::string("step-cycle tuning: ") + hipGetErrorString(he));
   st->nt = best_nt;
-  for (int l = 0; l < nl; ++l) st->u[l] = best_u[l];
+  for (int l = 0; l < nl; ++l) {
+    if (best_pick[l] == 1) {
+      st->u[l] = opt[l][1].u;
+    } else if (best_pick[l] == 2) {  // install the runner-up; the former winner becomes it
+      std::swap(st->nb[l], st->alt_nb[l]);
+      std::swap(st->ks[l], st->alt_ks[l]);
+      std::swap(st->u[l], st->alt_u[l]);
+      std::swap(st->ntiles[l], st->alt_ntiles[l]);
+      std::swap(st->tuned_us[l], st->alt_us[l]);
+      std::swap(st->tiles[l].p, st->alt_tiles[l].p);
+      std::swap(st->tiles[l].n, st->alt_tiles[l].n);
+    }
+  }
   return LSX_OK;
 }
 
@@ -1115,7 +1156,8 @@ static lsx_status choose_tiles(lsx_plan* pl, lsx_state* st) {
   lsx_status err = LSX_OK;
   const int nl = pl->sys->nl;
   for (int layer = 1; layer <= nl && err == LSX_OK; ++layer) {
-    float best = -1.f;
+    float best = -1.f, second = -1.f;
+    st->alt_nb[layer - 1] = 0;
     for (const Shape& c : cands) {
       std::vector<TileDesc> t;
       const int wt = (W == 1) ? 1 : (W + 16 * c.nb - 1) / (16 * c.nb);
@@ -1167,15 +1209,37 @@ static lsx_status choose_tiles(lsx_plan* pl, lsx_state* st) {
           break;
         }
       }
+      const int l = layer - 1;
       if (best < 0.f || ms < best) {
+        if (best >= 0.f) {  // the previous best becomes the runner-up
+          second = best;
+          st->alt_nb[l] = st->nb[l];
+          st->alt_ks[l] = st->ks[l];
+          st->alt_u[l] = st->u[l];
+          st->alt_ntiles[l] = st->ntiles[l];
+          st->alt_us[l] = best * 1e3f;
+          st->alt_tiles[l].release();
+          std::swap(st->alt_tiles[l].p, st->tiles[l].p);
+          std::swap(st->alt_tiles[l].n, st->tiles[l].n);
+        }
         best = ms;
-        st->nb[layer - 1] = c.nb;
-        st->ks[layer - 1] = c.ks;
-        st->u[layer - 1] = c.u;
-        st->tiles[layer - 1].release();
-        std::swap(st->tiles[layer - 1].p, d.p);
-        std::swap(st->tiles[layer - 1].n, d.n);
-        st->ntiles[layer - 1] = (int)t.size();
+        st->nb[l] = c.nb;
+        st->ks[l] = c.ks;
+        st->u[l] = c.u;
+        st->tiles[l].release();
+        std::swap(st->tiles[l].p, d.p);
+        std::swap(st->tiles[l].n, d.n);
+        st->ntiles[l] = (int)t.size();
+      } else if (second < 0.f || ms < second) {
+        second = ms;
+        st->alt_nb[l] = c.nb;
+        st->alt_ks[l] = c.ks;
+        st->alt_u[l] = c.u;
+        st->alt_ntiles[l] = (int)t.size();
+        st->alt_us[l] = ms * 1e3f;
+        st->alt_tiles[l].release();
+        std::swap(st->alt_tiles[l].p, d.p);
+        std::swap(st->alt_tiles[l].n, d.n);
       }
     }
     st->tuned_us[layer - 1] = timing ? best * 1e3f : 0.f;
