@@ -1854,21 +1854,28 @@ extern "C" lsx_status lsx_batch_create(lsx_plan* const* plans, lsx_state* const*
         hipError_t he = hipSuccess;
         int c2 = 0, l2 = lay;
         if ((e = batch_pass(b, nullptr, p, c2, l2)) != LSX_OK) break;
-        he = hipEventRecord(e0, nullptr);
-        for (int r = 0; r < 5 && he == hipSuccess; ++r) {
-          cur = 0;
-          lay = layer;
-          if ((e = batch_pass(b, nullptr, p, cur, lay)) != LSX_OK) break;
-        }
+        // five timed passes, then, for passes under 200 us, about 1 ms of them
+        auto time_reps = [&](int reps, float& per) {
+          float total = 0.f;
+          he = hipEventRecord(e0, nullptr);
+          for (int r = 0; r < reps && he == hipSuccess; ++r) {
+            cur = 0;
+            lay = layer;
+            if ((e = batch_pass(b, nullptr, p, cur, lay)) != LSX_OK) return;
+          }
+          if (he == hipSuccess) he = hipEventRecord(e1, nullptr);
+          if (he == hipSuccess) he = hipEventSynchronize(e1);
+          if (he == hipSuccess) he = hipEventElapsedTime(&total, e0, e1);
+          per = total / reps;
+        };
+        time_reps(5, ms);
+        if (e == LSX_OK && he == hipSuccess && ms < 0.2f)
+          time_reps(std::min(100, std::max(5, (int)(1.0f / std::max(ms, 1e-3f)))), ms);
         if (e != LSX_OK) break;
-        if (he == hipSuccess) he = hipEventRecord(e1, nullptr);
-        if (he == hipSuccess) he = hipEventSynchronize(e1);
-        if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
         if (he != hipSuccess) {
           e = fail(LSX_E_HIP, std::string("batch autotune: ") + hipGetErrorString(he));
           break;
         }
-        ms /= 5;
       }
       if (best < 0.f || ms < best) {
         best = ms;  // keep: the new tiles stay installed
