@@ -263,7 +263,9 @@ lsx_status lsx_state_device_ptr(const lsx_state* st, void** dev_ptr);
  * Tile shape chosen for the fibre passes of `layer` (1 .. nlayers) of this state: each
  * workgroup covers 16*nb columns and either 16 output rows with ks > 0 waves splitting the
  * fibre length, or (ks < 0, mixed FP32) -ks consecutive 16-row blocks, one per wave, that
- * share the state operand staged once per workgroup in LDS.  At creation every candidate shape is timed on the state's own size
+ * share the state operand staged once per workgroup in LDS.  For W = 1 (matrix-vector
+ * passes) ks < 0 means 32 output rows (two row blocks) with -ks waves splitting the fibre
+ * length (FP64 and mixed FP32).  At creation every candidate shape is timed on the state's own size
  * (LSX_AUTOTUNE=0 disables, LSX_NB / LSX_KS force a shape); pass_us is the measured
  * time of one pass with the chosen shape (0 if nothing was timed).  The single-pass winner and
  * runner-up of each layer are then compared on the step-like cycle described at

@@ -1125,7 +1125,11 @@ static lsx_status choose_tiles(lsx_plan* pl, lsx_state* st) {
   const int fnb = env_int("LSX_NB", 0), fks = env_int("LSX_KS", 0);
   const bool tune_u = (pl->fmt == PF_F64 || pl->fmt == PF_F32) && std::getenv("LSX_PREFETCH") == nullptr;
   if (W == 1) {
-    for (int k : {1, 2, 4}) cands.push_back({1, k, 0});
+    // ks < 0: FP64 / FP32 tiles of two row blocks with -ks waves
+    for (int k : {1, 2, 4}) {
+      cands.push_back({1, k, 0});
+      if (pl->fmt != PF_BF16X3) cands.push_back({1, -k, 0});
+    }
   } else {
     for (int nb : {1, 2, 4})
       for (int k : {1, 2, 4})
@@ -1139,8 +1143,9 @@ static lsx_status choose_tiles(lsx_plan* pl, lsx_state* st) {
           if (16 * nb <= round_up(W, 16) && !(pl->fmt == PF_BF16X3 && nb == 4)) cands.push_back({nb, -m, 0});
   }
   if (fnb > 0 || fks != 0) {
-    const bool rowsplit = fks < 0 && W > 1 && pl->fmt != PF_F64 && (fks == -2 || fks == -4) &&
-                          !(pl->fmt == PF_BF16X3 && fnb == 4);
+    const bool rowsplit = fks < 0 && ((W > 1 && pl->fmt != PF_F64 && (fks == -2 || fks == -4) &&
+                                       !(pl->fmt == PF_BF16X3 && fnb == 4)) ||
+                                      (W == 1 && pl->fmt != PF_BF16X3 && (fks == -1 || fks == -2 || fks == -4)));
     const Shape f{(fnb == 1 || fnb == 2 || fnb == 4) ? fnb : 1,
                   rowsplit ? fks : ((fks == 1 || fks == 2 || fks == 4) ? fks : 2), 0};
     cands.assign(1, f);
@@ -1161,7 +1166,8 @@ static lsx_status choose_tiles(lsx_plan* pl, lsx_state* st) {
     for (const Shape& c : cands) {
       std::vector<TileDesc> t;
       const int wt = (W == 1) ? 1 : (W + 16 * c.nb - 1) / (16 * c.nb);
-      build_tiles(pl, layer, W, c.nb, 0, wt, t, c.ks < 0 ? -c.ks : 1);
+      // row blocks per tile: W = 1 pairs for ks < 0, else -ks for the row-split shapes
+      build_tiles(pl, layer, W, c.nb, 0, wt, t, c.ks < 0 ? (W == 1 ? 2 : -c.ks) : 1);
       DBuf<TileDesc> d;
       if ((err = d.upload(t, nullptr)) != LSX_OK) break;
       float ms = 0.f;

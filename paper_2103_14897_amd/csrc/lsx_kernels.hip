@@ -1042,17 +1042,23 @@ __global__ __launch_bounds__(64 * MS) void k_pass_bf16m(PassArgs a) {
 // (rb, k) multiplies entry (16rb+li, col) by x[col]; the four k-lanes and the KS waves
 // are summed in fixed order.  Mixed formats: E entries (rounded to their storage
 // precision) times the FP64 state, FP64 accumulation, plus the FP64 diagonal term.
-template <int KS, int FMT, bool BATCH>
+// FP64 / FP32 tiles may cover RB = 2 consecutive row blocks (tile rb counts pairs): each
+// state load then serves two propagator loads, which halves the state loads per entry.
+template <int KS, int FMT, bool BATCH, int RB = 1>
 __device__ __forceinline__ void k_gemv_tile(const PassArgs& a0, int ti, double* red) {
+  static_assert(RB == 1 || FMT != PF_BF16X3, "BF16x3 single-state tiles cover one row block");
   const TileDesc t = a0.tiles[ti];
   if (t.f < 0) return;
   const PassArgs a = BATCH ? a0.batch[t.f] : a0;
-  const int r0 = t.r0, L = t.L, rb = t.rb;
+  const int r0 = t.r0, L = t.L;
   const int lane = threadIdx.x & 63, kw = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int li = lane & 15, lk = lane >> 4;
   const char* Pb = reinterpret_cast<const char*>(a.P) + t.poff;
-  double yr = 0.0, yi = 0.0;
-  if (FMT == PF_BF16X3) {
+  double yr[RB], yi[RB];
+#pragma unroll
+  for (int j = 0; j < RB; ++j) yr[j] = yi[j] = 0.0;
+  if constexpr (FMT == PF_BF16X3) {
+    const int rb = t.rb;
     const int nkc = ((L + 31) & ~31) >> 5;
     const v8u16* P = reinterpret_cast<const v8u16*>(Pb) + (int64_t)rb * nkc * 6 * 64 + lane;
     for (int kc = kw; kc < nkc; kc += KS) {
@@ -1065,66 +1071,85 @@ __device__ __forceinline__ void k_gemv_tile(const PassArgs& a0, int ti, double* 
           const double2 x = a.X[in_row(a, r0 + k)];
           const double er = (double)(bf2f(r0v[e]) + bf2f(r1v[e]) + bf2f(r2v[e]));
           const double ei = (double)(bf2f(i0v[e]) + bf2f(i1v[e]) + bf2f(i2v[e]));
-          yr += er * x.x - ei * x.y;
-          yi += er * x.y + ei * x.x;
+          yr[0] += er * x.x - ei * x.y;
+          yi[0] += er * x.y + ei * x.x;
         }
       }
     }
   } else {
     // Groups of G k-steps: all loads of a group are issued before its products, with the
     // state operand of positions past the fibre read from the zero buffer (their propagator
-    // entries are zero padding), so the loads stay branch-free; the products are summed in
-    // k-step order as one at a time.
+    // entries are zero padding) and a missing second row block's entries from the zero buffer
+    // too, so the loads stay branch-free; the products are summed in k-step order as one at a
+    // time.
     using PT = typename std::conditional<FMT == PF_F64, double2, float2>::type;
     constexpr int G = 8;
     const int nks = ((L + 15) & ~15) >> 2;
-    const PT* P = reinterpret_cast<const PT*>(Pb) + (int64_t)rb * nks * 64 + lane;
+    const int nrb = (L + 15) >> 4;
+    const PT* zp = reinterpret_cast<const PT*>(a.zero);
     const double2* zx = reinterpret_cast<const double2*>(a.zero);
+    // a tile's first row block always exists; the second (RB = 2) may lie past the fibre
+    const PT* Pj[RB];
+#pragma unroll
+    for (int j = 0; j < RB; ++j) {
+      const int rbj = t.rb * RB + j;
+      Pj[j] = (j == 0 || rbj < nrb) ? reinterpret_cast<const PT*>(Pb) + (int64_t)rbj * nks * 64 + lane : nullptr;
+    }
     int ks = kw;
     for (; ks + (G - 1) * KS < nks; ks += G * KS) {
-      PT p[G];
+      PT p[RB][G];
       double2 x[G];
 #pragma unroll
       for (int g = 0; g < G; ++g) {
         const int kk = ks + g * KS, k = 4 * kk + lk;
         const bool ok = k < L;
-        p[g] = P[(int64_t)kk * 64];
+#pragma unroll
+        for (int j = 0; j < RB; ++j) p[j][g] = *((j == 0 || Pj[j]) ? Pj[j] + (int64_t)kk * 64 : zp);
         x[g] = *(ok ? a.X + in_row(a, r0 + (ok ? k : 0)) : zx);
       }
 #pragma unroll
-      for (int g = 0; g < G; ++g) {
-        const double pr = p[g].x, pi = p[g].y;
-        yr += pr * x[g].x - pi * x[g].y;
-        yi += pr * x[g].y + pi * x[g].x;
-      }
+      for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int j = 0; j < RB; ++j) {
+          const double pr = p[j][g].x, pi = p[j][g].y;
+          yr[j] += pr * x[g].x - pi * x[g].y;
+          yi[j] += pr * x[g].y + pi * x[g].x;
+        }
     }
     for (; ks < nks; ks += KS) {
       const int k = 4 * ks + lk;
       const bool ok = k < L;
-      const PT pe = P[(int64_t)ks * 64];
       const double2 x = *(ok ? a.X + in_row(a, r0 + (ok ? k : 0)) : zx);
-      const double pr = pe.x, pi = pe.y;
-      yr += pr * x.x - pi * x.y;
-      yi += pr * x.y + pi * x.x;
+#pragma unroll
+      for (int j = 0; j < RB; ++j) {
+        const PT pe = *((j == 0 || Pj[j]) ? Pj[j] + (int64_t)ks * 64 : zp);
+        const double pr = pe.x, pi = pe.y;
+        yr[j] += pr * x.x - pi * x.y;
+        yi[j] += pr * x.y + pi * x.x;
+      }
     }
   }
   // sum the four k-lanes of each row (lanes li, li+16, li+32, li+48)
-  yr += __shfl_xor(yr, 16);
-  yi += __shfl_xor(yi, 16);
-  yr += __shfl_xor(yr, 32);
-  yi += __shfl_xor(yi, 32);
-  if (lk == 0) {
-    red[(kw * 2 + 0) * 16 + li] = yr;
-    red[(kw * 2 + 1) * 16 + li] = yi;
+#pragma unroll
+  for (int j = 0; j < RB; ++j) {
+    yr[j] += __shfl_xor(yr[j], 16);
+    yi[j] += __shfl_xor(yi[j], 16);
+    yr[j] += __shfl_xor(yr[j], 32);
+    yi[j] += __shfl_xor(yi[j], 32);
+    if (lk == 0) {
+      red[((kw * RB + j) * 2 + 0) * 16 + li] = yr[j];
+      red[((kw * RB + j) * 2 + 1) * 16 + li] = yi[j];
+    }
   }
   __syncthreads();
-  if (threadIdx.x < 16) {
-    const int arow = 16 * rb + li;
+  if (threadIdx.x < 16 * RB) {
+    const int j = threadIdx.x >> 4, lr = threadIdx.x & 15;
+    const int arow = 16 * (t.rb * RB + j) + lr;
     if (arow < L) {
       double sr = 0.0, si = 0.0;
-      for (int j = 0; j < KS; ++j) {
-        sr += red[(j * 2 + 0) * 16 + li];
-        si += red[(j * 2 + 1) * 16 + li];
+      for (int w = 0; w < KS; ++w) {
+        sr += red[((w * RB + j) * 2 + 0) * 16 + lr];
+        si += red[((w * RB + j) * 2 + 1) * 16 + lr];
       }
       const int p = r0 + arow;
       if (FMT != PF_F64 || a.wt) {
@@ -1151,11 +1176,11 @@ __device__ __forceinline__ void k_gemv_tile(const PassArgs& a0, int ti, double* 
   }
 }
 
-template <int KS, int FMT, bool BATCH>
+template <int KS, int FMT, bool BATCH, int RB = 1>
 __global__ __launch_bounds__(64 * KS) void k_gemv(PassArgs a0) {
-  __shared__ double red[2 * KS * 16];
+  __shared__ double red[2 * KS * 16 * RB];
   if (a0.tcount && (int)blockIdx.x >= *a0.tcount) return;
-  k_gemv_tile<KS, FMT, BATCH>(a0, blockIdx.x, red);
+  k_gemv_tile<KS, FMT, BATCH, RB>(a0, blockIdx.x, red);
 }
 
 template <int KS, int FMT>
@@ -1452,6 +1477,18 @@ static hipError_t launch_gemv(hipStream_t s, int fmt, int ntiles, const PassArgs
   return hipGetLastError();
 }
 
+// single-state FP64 / FP32 tiles of two row blocks (tile rb counts pairs)
+template <int KS>
+static hipError_t launch_gemv_rb2(hipStream_t s, int fmt, int ntiles, const PassArgs& a) {
+  if (fmt == PF_F64)
+    hipLaunchKernelGGL((k_gemv<KS, PF_F64, false, 2>), dim3(ntiles), dim3(64 * KS), 0, s, a);
+  else if (fmt == PF_F32)
+    hipLaunchKernelGGL((k_gemv<KS, PF_F32, false, 2>), dim3(ntiles), dim3(64 * KS), 0, s, a);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
 // batched: tile.f is a system index into a.batch and every system has its own W; the
 // caller passes gather = whether the systems' in_pos tables are set (uniform per pass)
 hipError_t launch_pass(hipStream_t s, int fmt, int W, int ntiles, int nb, int ksplit, const PassArgs& a,
@@ -1460,6 +1497,14 @@ hipError_t launch_pass(hipStream_t s, int fmt, int W, int ntiles, int nb, int ks
   const bool gather = a.in_pos != nullptr;
   if (W == 1) {
     if (batched) return launch_gemv<4, true>(s, fmt, ntiles, a);
+    if (ksplit < 0) {  // tiles of two row blocks, -ksplit waves
+      if (fmt == PF_BF16X3) return hipErrorInvalidValue;
+      switch (-ksplit) {
+        case 1: return launch_gemv_rb2<1>(s, fmt, ntiles, a);
+        case 2: return launch_gemv_rb2<2>(s, fmt, ntiles, a);
+        default: return launch_gemv_rb2<4>(s, fmt, ntiles, a);
+      }
+    }
     switch (ksplit) {
       case 1: return launch_gemv<1, false>(s, fmt, ntiles, a);
       case 2: return launch_gemv<2, false>(s, fmt, ntiles, a);

@@ -57,3 +57,43 @@ def test_rowsplit_shapes(prec, nb, ms, which, monkeypatch):
         P.destroy()
         P64.destroy()
         S.destroy()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mix_fp32"])
+@pytest.mark.parametrize("ks", [-1, -2, -4])
+@pytest.mark.parametrize("which", ["chain", "twisted"])
+def test_single_state_pair_tiles(prec, ks, which, monkeypatch):
+    """W = 1 tiles of two row blocks (ks < 0): single passes of both layers against the oracle
+    and a Strang trajectory against the one-row-block tiles of the same precision."""
+    spec = wl.chain_system(2.0e4) if which == "chain" else wl.twisted_system(1500.0)
+    S = lsx.System.from_spec(spec)
+    O = splitting.Lifted.from_spec(spec)
+    plan = splitting.SplitPlan(O, 0.0)
+    tau = 1e-3
+    print(f"[case] single-state pair tiles {which} {prec} ks={ks}", flush=True)
+    P = lsx.Plan(S, tau, "strang", 0.0, prec)
+    monkeypatch.setenv("LSX_NB", "1")
+    monkeypatch.setenv("LSX_KS", str(ks))
+    st = lsx.State(P, 1)
+    monkeypatch.setenv("LSX_KS", str(-ks))
+    ref = lsx.State(P, 1)
+    monkeypatch.delenv("LSX_NB")
+    monkeypatch.delenv("LSX_KS")
+    try:
+        assert st.tuning(1)[:2] == (1, ks) and ref.tuning(1)[:2] == (1, -ks)
+        c = wl.random_state(S.N, 1, seed=-ks)
+        tol = 1e-12 if prec == "fp64" else 1e-7
+        for layer, half, t in ((1, 0, tau), (1, 1, tau / 2), (2, 0, tau)):
+            st.upload(c)
+            st.fibre_pass(layer, half)
+            assert colrel(st.download(), plan.apply_fibres(c, layer, t)) < tol, (layer, half)
+        st.upload(c)
+        ref.upload(c)
+        st.step(20)
+        ref.step(20)
+        assert colrel(st.download(), ref.download()) < 1e-13
+    finally:
+        st.destroy()
+        ref.destroy()
+        P.destroy()
+        S.destroy()
