@@ -1055,14 +1055,15 @@ static lsx_status choose_cycle(lsx_plan* pl, lsx_state* st, bool tune_store) {
     return ms * 1e3f / reps;
   };
   if (tune_store) st->store_us[0] = st->store_us[1] = 0.f;
-  // the cycle with the current picks, each store mode: about 2 ms of passes, 3 to 200 cycles
-  // sized by a timed warm-up cycle; returns the best time and its mode
+  // the cycle with the current picks, each store mode: about 5 ms of passes, 3 to 500 cycles
+  // sized by a timed warm-up cycle (a few-microsecond cycle needs many for a stable ranking);
+  // returns the best time and its mode
   auto evaluate = [&](int& nt_best) {
     float best = -1.f;
     for (int m = 0; m < (tune_store ? 2 : 1) && he == hipSuccess; ++m) {
       const int nt = tune_store ? m : st->nt;
       const float warm_us = timed(nt, 1);
-      const int reps = (int)std::max(3.0, std::min(200.0, 2000.0 / std::max(1.0f, warm_us)));
+      const int reps = (int)std::max(3.0, std::min(500.0, 5000.0 / std::max(1.0f, warm_us)));
       const float us = timed(nt, reps);
       if (tune_store && (st->store_us[nt] == 0.f || us < st->store_us[nt])) st->store_us[nt] = us;
       if (best < 0.f || us < best) {
