@@ -64,7 +64,8 @@ def test_rowsplit_shapes(prec, nb, ms, which, monkeypatch):
 @pytest.mark.parametrize("which", ["chain", "twisted"])
 def test_single_state_pair_tiles(prec, ks, which, monkeypatch):
     """W = 1 tiles of two row blocks (ks < 0): single passes of both layers against the oracle
-    and a Strang trajectory against the one-row-block tiles of the same precision."""
+    and Strang trajectories (kappa 0 and 0.5, the latter with the phase fused into the pass)
+    against the one-row-block tiles of the same precision."""
     spec = wl.chain_system(2.0e4) if which == "chain" else wl.twisted_system(1500.0)
     S = lsx.System.from_spec(spec)
     O = splitting.Lifted.from_spec(spec)
@@ -87,6 +88,26 @@ def test_single_state_pair_tiles(prec, ks, which, monkeypatch):
             st.upload(c)
             st.fibre_pass(layer, half)
             assert colrel(st.download(), plan.apply_fibres(c, layer, t)) < tol, (layer, half)
+        st.upload(c)
+        ref.upload(c)
+        st.step(20)
+        ref.step(20)
+        assert colrel(st.download(), ref.download()) < 1e-13
+    finally:
+        st.destroy()
+        ref.destroy()
+        P.destroy()
+    # a kinetic share: the phase fused into the pair tiles' epilogue
+    P = lsx.Plan(S, tau, "strang", 0.5, prec)
+    monkeypatch.setenv("LSX_NB", "1")
+    monkeypatch.setenv("LSX_KS", str(ks))
+    st = lsx.State(P, 1)
+    monkeypatch.setenv("LSX_KS", str(-ks))
+    ref = lsx.State(P, 1)
+    monkeypatch.delenv("LSX_NB")
+    monkeypatch.delenv("LSX_KS")
+    try:
+        c = wl.random_state(S.N, 1, seed=7)
         st.upload(c)
         ref.upload(c)
         st.step(20)
