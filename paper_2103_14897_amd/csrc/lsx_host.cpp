@@ -1195,8 +1195,9 @@ static lsx_status choose_tiles(lsx_plan* pl, lsx_state* st) {
         a.zero = pl->zero.p;
         a.W = W;
         a.u = c.u;
-        // five timed passes, then, for passes under 200 us, about 1 ms of them: launch jitter
-        // is comparable to a few-microsecond pass
+        // two timed passes (enough for passes of a millisecond or more), then, for shorter
+        // passes, at least five and about 1 ms of them: launch jitter is comparable to a
+        // few-microsecond pass
         auto time_reps = [&](int reps, float& per) {
           hipError_t e = hipEventRecord(e0, nullptr);
           for (int r = 0; r < reps && e == hipSuccess; ++r)
@@ -1209,8 +1210,8 @@ static lsx_status choose_tiles(lsx_plan* pl, lsx_state* st) {
           return e;
         };
         hipError_t he = launch_pass(nullptr, pl->fmt, W, (int)t.size(), c.nb, c.ks, a);
-        if (he == hipSuccess) he = time_reps(5, ms);
-        if (he == hipSuccess && ms < 0.2f) he = time_reps(std::min(100, std::max(5, (int)(1.0f / std::max(ms, 1e-3f)))), ms);
+        if (he == hipSuccess) he = time_reps(2, ms);
+        if (he == hipSuccess && ms < 1.0f) he = time_reps(std::min(100, std::max(5, (int)(1.0f / std::max(ms, 1e-3f)))), ms);
         if (he != hipSuccess) {
           err = fail(LSX_E_HIP, std::string("autotune: ") + hipGetErrorString(he));
           break;
