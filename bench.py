@@ -380,7 +380,7 @@ def trilayer_workload(args):
 
 
 def example3_workload(args):
-    """Example 3 of Sec. 6 (x incommensurate, y periodic for both layers): V = cos^2(beta x)
+    """Example 3 of Sec. 5 (x incommensurate, y periodic for both layers): V = cos^2(beta x)
     cos^2(pi y/2) + 2 cos^2(x) cos^2(pi y/2), beta = golden ratio - 1, lifted by (m, p, n) with
     layer 1 on (m, p) and layer 2 on (p, n); cutoff Ec = 1000 (N = 74037; 45 + 73 fibres of
     length up to 2117 and 1305), 128 random unit wavepackets (seed 0), tau = 5e-3, kappa = 0.

@@ -72,6 +72,17 @@ typedef struct lsx_state lsx_state;
 const char* lsx_last_error(void);
 
 /*
+ * Diagnostics: device buffers the library holds right now (every system, plan, state, batch,
+ * sampler and network together) and their bytes.  After a failed call the counts are those
+ * before it: set-up failures unwind what they allocated.  Either output may be NULL.
+ * For tests of that unwinding, two environment variables inject failures: LSX_TEST_FAIL_ALLOC=k
+ * makes the k-th device allocation counted from when the variable was set (or last changed)
+ * fail with LSX_E_OOM, and LSX_TEST_FAIL_EIG=1 makes plan creation report that the fibre
+ * eigensolver did not converge (LSX_E_EIG).
+ */
+lsx_status lsx_live_buffers(int64_t* count, int64_t* bytes);
+
+/*
  * lsx_system_create -- the problem statement (Sec. 2) and its lifted cutoff set (Sec. 3).
  *
  *  d            layer dimension, 1 or 2.
@@ -125,7 +136,7 @@ lsx_status lsx_system_create_layers(int32_t d, int32_t nlayers, const double* co
 
 /*
  * lsx_system_create_blocks -- a lifted system whose layers may share index blocks (Example 3
- * of Sec. 6: a direction that is periodic for every layer is lifted once and coupled by every
+ * of Sec. 5: a direction that is periodic for every layer is lifted once and coupled by every
  * layer's potential).
  *
  *  D            physical dimension, 1 or 2.
@@ -300,6 +311,25 @@ lsx_status lsx_state_prefetch(const lsx_state* st, int32_t layer, int32_t* group
  */
 lsx_status lsx_state_store_mode(const lsx_state* st, int32_t* nontemporal, double* cycle_us);
 
+/*
+ * Pinning the tuned shape, for bitwise-repeatable runs.  The tuners above choose from timings,
+ * which vary from run to run, and a different shape or prefetch depth changes the summation
+ * order of a pass.  Reading a state's choice (lsx_state_tuning, lsx_state_prefetch,
+ * lsx_state_store_mode) and setting it on another state, in this or a later process, makes the
+ * two step bit for bit alike.
+ * lsx_state_set_tuning: tile shape (nb, ks) and k-step groups in flight (`groups`, 0 for the
+ *   library default) of `layer`'s passes; the tile list is rebuilt on the host and uploaded
+ *   (synchronous).  Available shapes: W = 1: nb = 1 and ks in {1, 2, 4}, or {-1, -2, -4} except
+ *   for LSX_MIX_BF16X3, groups = 0.  W > 1: nb in {1, 2, 4} with 16 nb <= W rounded up to 16;
+ *   ks in {1, 2, 4} with groups 0, or 1 or 2 for LSX_FP64 / LSX_MIX_FP32; or ks in {-2, -4} for
+ *   the mixed paths (nb <= 2 for LSX_MIX_BF16X3), groups 0.  Anything else is LSX_E_INVALID
+ *   and leaves the state unchanged.  lsx_state_tuning then reports pass_us = 0.
+ * lsx_state_set_store_mode: 0 ordinary, 1 non-temporal output stores (LSX_E_INVALID otherwise).
+ * Neither call touches the state's values.  Not while a step on the state is in flight.
+ */
+lsx_status lsx_state_set_tuning(lsx_state* st, int32_t layer, int32_t nb, int32_t ks, int32_t groups);
+lsx_status lsx_state_set_store_mode(lsx_state* st, int32_t nontemporal);
+
 lsx_status lsx_state_destroy(lsx_state* st);
 
 /*
@@ -341,6 +371,51 @@ lsx_status lsx_phase(lsx_plan* plan, lsx_state* st, int32_t half, void* stream);
  * LSX_E_NONFINITE if any requested value is NaN/Inf (out is still written).
  */
 lsx_status lsx_observables(lsx_plan* plan, lsx_state* st, uint32_t mask, double* out, void* stream);
+
+/*
+ * Descriptor form of the boundary.  The same problem statement (Sec. 2: lattices R_j = A_j Z^d
+ * and the Fourier coefficients of the layer potentials, eq. 2.2; Sec. 3: the cutoff Ec and its
+ * lifted set) and the same plan parameters (tau, scheme of App. A / Alg. 2 / eq. 4.6, kinetic
+ * share, precision) gathered in two structs, with calls named for what they return.  Each is a
+ * thin wrapper of the flat-argument call named beside it, with that call's argument meaning,
+ * layout, ownership and errors.
+ *   lsx_system_desc: d (1 or 2); A1, A2 column-major d x d (entries past d*d ignored); Ec;
+ *     cutoff (LSX_CUTOFF_BALL / LSX_CUTOFF_PRODUCT); per layer j = 0, 1: nv[j] coefficients,
+ *     v_idx[j] (nv[j]*d int32), v_re[j], v_im[j].
+ *   lsx_plan_desc: tau, scheme, kappa, precision as for lsx_plan_create; max_wavepackets > 0
+ *     makes lsx_state_create / lsx_state_wrap refuse W above it (LSX_E_INVALID); 0: no limit.
+ * lsx_system_create_desc = lsx_system_create (host only).
+ * lsx_index_size: *N = |I| (as lsx_system_size's N).
+ * lsx_fibre_info: number of fibres of `layer` (1 .. nlayers) and, if `lengths` is not NULL,
+ *   their lengths (nfibres int32, fibres in the order of lsx_fibre_get).
+ * lsx_plan_create_desc = lsx_plan_create (one-time precompute, synchronises the stream).
+ * lsx_state_wrap = lsx_state_create with a caller-owned device array (dev_ptr must not be
+ *   NULL): c[N][W] complex128, 16-byte aligned, kept alive by the caller until
+ *   lsx_state_destroy.  The host layout of lsx_state_upload / download is [N][W] as on the
+ *   device (W innermost), so that upload and download are plain copies.
+ */
+typedef struct {
+  int32_t d;
+  double A1[4], A2[4];
+  double Ec;
+  int32_t cutoff;
+  int32_t nv[2];
+  const int32_t* v_idx[2];
+  const double* v_re[2];
+  const double* v_im[2];
+} lsx_system_desc;
+typedef struct {
+  double tau;
+  int32_t scheme;
+  double kappa;
+  int32_t precision;
+  int32_t max_wavepackets;
+} lsx_plan_desc;
+lsx_status lsx_system_create_desc(const lsx_system_desc* desc, lsx_system** out);
+lsx_status lsx_index_size(const lsx_system* sys, int64_t* N);
+lsx_status lsx_fibre_info(const lsx_system* sys, int32_t layer, int64_t* nfibres, int32_t* lengths);
+lsx_status lsx_plan_create_desc(lsx_system* sys, const lsx_plan_desc* desc, void* stream, lsx_plan** out);
+lsx_status lsx_state_wrap(lsx_plan* plan, int32_t W, void* dev_ptr, lsx_state** out);
 
 /*
  * Batched systems -- several independent (plan, state) pairs advanced together: every

@@ -20,7 +20,7 @@ reference    brute-force exponentials of the full lifted Hamiltonian and a
 multilayer   index set, fibres, fibre Hamiltonians and Lie / Strang / Yoshida layer
              splitting for L >= 2 layers (the generalisation of Secs. 2-4), with exact,
              backward-Euler or Crank-Nicolson fibre sub-steps
-blocks       lifted systems whose layers share index blocks (Example 3 of Sec. 6:
+blocks       lifted systems whose layers share index blocks (Example 3 of Sec. 5:
              a direction periodic for every layer), split like `multilayer`
 stochastic   semi-implicit (Alg. 1) and random batch (Alg. 4) steps, stochastic
              layer splitting with an importance-sampling proposal, the proposal

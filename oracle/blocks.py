@@ -1,6 +1,6 @@
 """Lifted systems whose layers share index blocks (oracle; test infrastructure only).
 
-Example 3 of Sec. 6 is a two-dimensional system that is periodic in y and incommensurate in
+Example 3 of Sec. 5 is a two-dimensional system that is periodic in y and incommensurate in
 x.  It is lifted with three indices: m and n for the two incommensurate periods in x, and p
 for the shared period in y, so a plane wave is exp(i (G_1 m + G_2 n) x + i G_3 p y).  Each
 potential term is a product of an x-factor of one layer and a y-factor, so V^1 couples the

@@ -3,11 +3,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <tuple>
 #include <numeric>
 #include <string>
@@ -26,6 +28,32 @@ static lsx_status fail(lsx_status st, const std::string& msg) {
   return st;
 }
 
+// ---------------------------------------------------------------- failure injection (tests)
+// LSX_TEST_FAIL_ALLOC=k makes the k-th device allocation counted from when the variable was
+// set (or last changed) report LSX_E_OOM; LSX_TEST_FAIL_EIG=1 makes the fibre eigensolver
+// report non-convergence.  Both exist so that the unwinding of a failed set-up can be tested
+// from the host; unset, they cost one getenv per allocation or plan.
+static bool test_fail_alloc() {
+  static std::mutex mu;
+  static std::string last;
+  static long count = 0;
+  const char* v = std::getenv("LSX_TEST_FAIL_ALLOC");
+  std::lock_guard<std::mutex> lock(mu);
+  if (!v) {
+    last.clear();
+    count = 0;
+    return false;
+  }
+  if (last != v) {
+    last = v;
+    count = 0;
+  }
+  return ++count == std::atol(v);
+}
+
+// Live device buffers of the library and their bytes (diagnostics: lsx_live_buffers).
+static std::atomic<int64_t> g_live_buffers{0}, g_live_bytes{0};
+
 // ---------------------------------------------------------------- device buffer helper
 template <typename T>
 struct DBuf {
@@ -36,19 +64,26 @@ struct DBuf {
   DBuf& operator=(const DBuf&) = delete;
   ~DBuf() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) {
+      (void)hipFree(p);
+      g_live_buffers--;
+      g_live_bytes -= (int64_t)(n * sizeof(T));
+    }
     p = nullptr;
     n = 0;
   }
   lsx_status alloc(size_t count) {
     release();
     if (count == 0) count = 1;
+    if (test_fail_alloc()) return fail(LSX_E_OOM, "injected allocation failure (LSX_TEST_FAIL_ALLOC)");
     if (hipMalloc(reinterpret_cast<void**>(&p), count * sizeof(T)) != hipSuccess) {
       (void)hipGetLastError();
       p = nullptr;
       return fail(LSX_E_OOM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
     }
     n = count;
+    g_live_buffers++;
+    g_live_bytes += (int64_t)(n * sizeof(T));
     return LSX_OK;
   }
   // Set-up copy from a host vector, complete on return: callers pass locals and temporaries,
@@ -251,8 +286,14 @@ static lsx_status build_stencil(int d, int nv, const int32_t* idx, const double*
 
 extern "C" const char* lsx_last_error(void) { return g_err.c_str(); }
 
+extern "C" lsx_status lsx_live_buffers(int64_t* count, int64_t* bytes) {
+  if (count) *count = g_live_buffers.load();
+  if (bytes) *bytes = g_live_bytes.load();
+  return LSX_OK;
+}
+
 // The lifted cutoff set (Sec. 3; more than two layers as in Sec. 2; shared blocks as in
-// Example 3 of Sec. 6): the candidate vectors of every block (lexicographic), combined with
+// Example 3 of Sec. 5): the candidate vectors of every block (lexicographic), combined with
 // block 0 outermost, kept when every cutoff group g has sum_{b in g} |R_b m_b|^2 <= 2 Ec
 // (relative tolerance 1e-12); then |K|^2, the fibres of every layer (fixing the columns the
 // layer's potential does not couple) and the potentials' neighbour tables.  The stencils,
@@ -514,6 +555,30 @@ extern "C" lsx_status lsx_fibre_get(const lsx_system* sys, int32_t layer, int32_
   return LSX_OK;
 }
 
+extern "C" lsx_status lsx_system_create_desc(const lsx_system_desc* desc, lsx_system** out) {
+  if (!desc) return fail(LSX_E_INVALID, "null descriptor");
+  return lsx_system_create(desc->d, desc->A1, desc->A2, desc->Ec, desc->cutoff, desc->nv[0], desc->v_idx[0],
+                           desc->v_re[0], desc->v_im[0], desc->nv[1], desc->v_idx[1], desc->v_re[1],
+                           desc->v_im[1], out);
+}
+
+extern "C" lsx_status lsx_index_size(const lsx_system* sys, int64_t* N) {
+  if (!sys || !N) return fail(LSX_E_INVALID, "null argument");
+  *N = sys->N;
+  return LSX_OK;
+}
+
+extern "C" lsx_status lsx_fibre_info(const lsx_system* sys, int32_t layer, int64_t* nfibres, int32_t* lengths) {
+  if (!sys) return fail(LSX_E_INVALID, "null system");
+  if (layer < 1 || layer > sys->nl) return fail(LSX_E_INVALID, "layer out of range");
+  const FibreTable& ft = sys->fib[layer - 1];
+  const int64_t nf = (int64_t)ft.ptr.size() - 1;
+  if (nfibres) *nfibres = nf;
+  if (lengths)
+    for (int64_t f = 0; f < nf; ++f) lengths[f] = ft.ptr[f + 1] - ft.ptr[f];
+  return LSX_OK;
+}
+
 extern "C" lsx_status lsx_system_destroy(lsx_system* sys) {
   if (!sys) return LSX_OK;
   if (sys->nplans > 0) return fail(LSX_E_STATE, "system still has live plans");
@@ -559,6 +624,7 @@ struct lsx_plan {
   DBuf<double2> zero;  // 1 KiB of zeros (out-of-range operand loads of the passes)
   LayerDev L[kMaxLayers];
   int nstates = 0;
+  int max_w = 0;  // states with more wavepackets are refused (0: no limit)
 };
 
 // Index table of layer `layer`'s fibre positions inside an array of layout `layout` (layout j:
@@ -705,6 +771,8 @@ static lsx_status precompute_layer(lsx_plan* pl, int layer, hipStream_t s) {
   std::vector<int32_t> info(nu);
   LSX_HIP_TRY(hipMemcpyAsync(info.data(), d_info.p, nu * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   LSX_HIP_TRY(hipStreamSynchronize(s));
+  if (const char* fe = std::getenv("LSX_TEST_FAIL_EIG"))
+    if (std::atoi(fe) == 1) info[0] = -1;
   for (int b = 0; b < nu; ++b)
     if (info[b] < 0)
       return fail(LSX_E_EIG, "Jacobi did not converge for layer " + std::to_string(layer) + " fibre " +
@@ -822,6 +890,17 @@ extern "C" lsx_status lsx_plan_create(lsx_system* sys, double tau, int32_t schem
   for (int layer = 1; layer <= nl; ++layer)
     if ((st = precompute_layer(pl, layer, s)) != LSX_OK) return cleanup(st);
   sys->nplans++;
+  *out = pl;
+  return LSX_OK;
+}
+
+extern "C" lsx_status lsx_plan_create_desc(lsx_system* sys, const lsx_plan_desc* desc, void* stream,
+                                           lsx_plan** out) {
+  if (!desc) return fail(LSX_E_INVALID, "null descriptor");
+  if (desc->max_wavepackets < 0) return fail(LSX_E_INVALID, "max_wavepackets must be >= 0");
+  lsx_plan* pl = nullptr;
+  LSX_TRY(lsx_plan_create(sys, desc->tau, desc->scheme, desc->kappa, desc->precision, stream, &pl));
+  pl->max_w = desc->max_wavepackets;
   *out = pl;
   return LSX_OK;
 }
@@ -1264,6 +1343,7 @@ static lsx_status choose_tiles(lsx_plan* pl, lsx_state* st) {
 extern "C" lsx_status lsx_state_create(lsx_plan* pl, int32_t W, void* dev_ptr, lsx_state** out) {
   if (!pl || !out) return fail(LSX_E_INVALID, "null argument");
   if (W < 1 || W > 65536) return fail(LSX_E_INVALID, "W must be in [1, 65536]");
+  if (pl->max_w > 0 && W > pl->max_w) return fail(LSX_E_INVALID, "W exceeds the plan's max_wavepackets");
   if (dev_ptr && (reinterpret_cast<uintptr_t>(dev_ptr) % 16) != 0)
     return fail(LSX_E_INVALID, "wrapped device pointer must be 16-byte aligned");
   const int64_t N = pl->sys->N;
@@ -1299,6 +1379,11 @@ extern "C" lsx_status lsx_state_create(lsx_plan* pl, int32_t W, void* dev_ptr, l
   pl->nstates++;
   *out = st;
   return LSX_OK;
+}
+
+extern "C" lsx_status lsx_state_wrap(lsx_plan* pl, int32_t W, void* dev_ptr, lsx_state** out) {
+  if (!dev_ptr) return fail(LSX_E_INVALID, "null device pointer");
+  return lsx_state_create(pl, W, dev_ptr, out);
 }
 
 extern "C" lsx_status lsx_state_upload(lsx_state* st, const double* host, void* stream) {
@@ -1348,6 +1433,51 @@ extern "C" lsx_status lsx_state_store_mode(const lsx_state* st, int32_t* nontemp
     cycle_us[0] = st->store_us[0];
     cycle_us[1] = st->store_us[1];
   }
+  return LSX_OK;
+}
+
+// Tile shapes the pass kernels are built for (see choose_tiles and launch_pass).
+static bool shape_valid(int fmt, int W, int nb, int ks, int u) {
+  if (W == 1) {
+    if (nb != 1 || u != 0) return false;
+    if (ks == 1 || ks == 2 || ks == 4) return true;
+    return fmt != PF_BF16X3 && (ks == -1 || ks == -2 || ks == -4);
+  }
+  if (!(nb == 1 || nb == 2 || nb == 4) || 16 * nb > round_up(W, 16)) return false;
+  if (ks == 1 || ks == 2 || ks == 4)
+    return u == 0 || ((fmt == PF_F64 || fmt == PF_F32) && (u == 1 || u == 2));
+  if (ks == -2 || ks == -4) return u == 0 && fmt != PF_F64 && !(fmt == PF_BF16X3 && nb == 4);
+  return false;
+}
+
+extern "C" lsx_status lsx_state_set_tuning(lsx_state* st, int32_t layer, int32_t nb, int32_t ks, int32_t groups) {
+  if (!st) return fail(LSX_E_INVALID, "null state");
+  lsx_plan* pl = st->plan;
+  if (layer < 1 || layer > pl->sys->nl) return fail(LSX_E_INVALID, "layer out of range");
+  if (!shape_valid(pl->fmt, st->W, nb, ks, groups))
+    return fail(LSX_E_INVALID, "tile shape not available for this precision and W");
+  const int W = st->W;
+  const int wt = (W == 1) ? 1 : (W + 16 * nb - 1) / (16 * nb);
+  std::vector<TileDesc> t;
+  build_tiles(pl, layer, W, nb, 0, wt, t, ks < 0 ? (W == 1 ? 2 : -ks) : 1);
+  DBuf<TileDesc> d;
+  LSX_TRY(d.upload(t, nullptr));
+  const int l = layer - 1;
+  st->tiles[l].release();
+  std::swap(st->tiles[l].p, d.p);
+  std::swap(st->tiles[l].n, d.n);
+  st->ntiles[l] = (int)t.size();
+  st->nb[l] = nb;
+  st->ks[l] = ks;
+  st->u[l] = groups;
+  st->tuned_us[l] = 0.f;
+  return LSX_OK;
+}
+
+extern "C" lsx_status lsx_state_set_store_mode(lsx_state* st, int32_t nontemporal) {
+  if (!st) return fail(LSX_E_INVALID, "null state");
+  if (nontemporal != 0 && nontemporal != 1) return fail(LSX_E_INVALID, "store mode must be 0 or 1");
+  st->nt = nontemporal;
   return LSX_OK;
 }
 

@@ -88,7 +88,35 @@ _SIGS = {
     "lsx_mlp_train_step": (C.c_int, [_p, _p, C.c_int64, _p, _p, C.c_int64, C.c_double, C.c_double, C.c_double,
                                      C.c_double, C.c_double, _p, _p]),
     "lsx_mlp_destroy": (C.c_int, [_p]),
+    "lsx_live_buffers": (C.c_int, [_i64p, _i64p]),
+    "lsx_state_set_tuning": (C.c_int, [_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
+    "lsx_state_set_store_mode": (C.c_int, [_p, C.c_int32]),
+    "lsx_system_create_desc": (C.c_int, [_p, C.POINTER(_p)]),
+    "lsx_index_size": (C.c_int, [_p, _i64p]),
+    "lsx_fibre_info": (C.c_int, [_p, C.c_int32, _i64p, _i32p]),
+    "lsx_plan_create_desc": (C.c_int, [_p, _p, _p, C.POINTER(_p)]),
+    "lsx_state_wrap": (C.c_int, [_p, C.c_int32, _p, C.POINTER(_p)]),
 }
+
+
+class SystemDesc(C.Structure):
+    """lsx_system_desc of include/lsx.h."""
+    _fields_ = [("d", C.c_int32), ("A1", C.c_double * 4), ("A2", C.c_double * 4), ("Ec", C.c_double),
+                ("cutoff", C.c_int32), ("nv", C.c_int32 * 2), ("v_idx", _i32p * 2), ("v_re", _dp * 2),
+                ("v_im", _dp * 2)]
+
+
+class PlanDesc(C.Structure):
+    """lsx_plan_desc of include/lsx.h."""
+    _fields_ = [("tau", C.c_double), ("scheme", C.c_int32), ("kappa", C.c_double), ("precision", C.c_int32),
+                ("max_wavepackets", C.c_int32)]
+
+
+def live_buffers():
+    """(count, bytes) of the device buffers the library holds (lsx_live_buffers)."""
+    n, b = C.c_int64(), C.c_int64()
+    _check(lib().lsx_live_buffers(C.byref(n), C.byref(b)))
+    return n.value, b.value
 
 
 class LsxError(RuntimeError):
@@ -239,6 +267,45 @@ class System:
     def from_spec(cls, spec):
         return cls(spec.d, spec.A1, spec.A2, spec.Ec, spec.cutoff, spec.pot1, spec.pot2)
 
+    @classmethod
+    def from_desc(cls, d, A1, A2, Ec, cutoff="ball", pot1=None, pot2=None):
+        """The same system through the descriptor form (lsx_system_create_desc)."""
+        self = cls.__new__(cls)
+        self.d = d = int(d)
+        desc = SystemDesc()
+        desc.d = d
+        for k, A in enumerate((A1, A2)):
+            a = _lattice(A, d)
+            getattr(desc, "A%d" % (k + 1))[:len(a)] = list(a)
+        desc.Ec = float(Ec)
+        desc.cutoff = CUTOFF[cutoff]
+        self._keep = []
+        for j, pot in enumerate((pot1, pot2)):
+            n, idx, re, im = _potential(pot, d)
+            self._keep += [idx, re, im]
+            desc.nv[j] = n
+            desc.v_idx[j] = idx.ctypes.data_as(_i32p)
+            desc.v_re[j] = _dptr(re)
+            desc.v_im[j] = _dptr(im)
+        h = _p()
+        _check(lib().lsx_system_create_desc(C.byref(desc), C.byref(h)))
+        self._finish(h)
+        return self
+
+    def index_size(self):
+        """|I| through lsx_index_size."""
+        n = C.c_int64()
+        _check(lib().lsx_index_size(self.h, C.byref(n)))
+        return n.value
+
+    def fibre_info(self, layer):
+        """(number of fibres, int32 lengths) of `layer` through lsx_fibre_info."""
+        nf = C.c_int64()
+        _check(lib().lsx_fibre_info(self.h, int(layer), C.byref(nf), None))
+        lengths = np.zeros(nf.value, dtype=np.int32)
+        _check(lib().lsx_fibre_info(self.h, int(layer), C.byref(nf), lengths.ctypes.data_as(_i32p)))
+        return nf.value, lengths
+
     def index(self):
         mn = np.zeros((self.N, self.S), dtype=np.int32)
         _check(lib().lsx_index_get(self.h, mn.ctypes.data_as(_i32p)))
@@ -259,12 +326,17 @@ class System:
 class Plan:
     """lsx_plan: one-time fibre eigendecomposition and propagators on the GPU."""
 
-    def __init__(self, system, tau, scheme="strang", kappa=0.0, precision="fp64", stream=None):
+    def __init__(self, system, tau, scheme="strang", kappa=0.0, precision="fp64", stream=None,
+                 max_wavepackets=None):
         self.system = system
         self.tau, self.scheme, self.kappa, self.precision = float(tau), scheme, float(kappa), precision
         h = _p()
-        _check(lib().lsx_plan_create(system.h, self.tau, SCHEME[scheme], self.kappa, PRECISION[precision],
-                                     _stream(stream), C.byref(h)))
+        if max_wavepackets is None:
+            _check(lib().lsx_plan_create(system.h, self.tau, SCHEME[scheme], self.kappa, PRECISION[precision],
+                                         _stream(stream), C.byref(h)))
+        else:
+            desc = PlanDesc(self.tau, SCHEME[scheme], self.kappa, PRECISION[precision], int(max_wavepackets))
+            _check(lib().lsx_plan_create_desc(system.h, C.byref(desc), _stream(stream), C.byref(h)))
         self.h = h
 
     def propagator(self, layer, half, fibre, stream=None):
@@ -286,14 +358,24 @@ class State:
     def __init__(self, plan, W, dev_ptr=None):
         self.plan, self.W, self.N = plan, int(W), plan.system.N
         h = _p()
-        _check(lib().lsx_state_create(plan.h, self.W, _p(dev_ptr) if dev_ptr else None, C.byref(h)))
+        if dev_ptr:
+            _check(lib().lsx_state_wrap(plan.h, self.W, _p(dev_ptr), C.byref(h)))
+        else:
+            _check(lib().lsx_state_create(plan.h, self.W, None, C.byref(h)))
         self.h = h
+
+    def set_tuning(self, layer, nb, ks, groups=0):
+        """Pin `layer`'s tile shape and prefetch depth (lsx_state_set_tuning)."""
+        _check(lib().lsx_state_set_tuning(self.h, int(layer), int(nb), int(ks), int(groups)))
+
+    def set_store_mode(self, nontemporal):
+        """Pin the pass output store mode (lsx_state_set_store_mode)."""
+        _check(lib().lsx_state_set_store_mode(self.h, int(nontemporal)))
 
     def upload(self, c, stream=None):
         c = np.ascontiguousarray(np.asarray(c, dtype=np.complex128).reshape(self.N, self.W))
         _check(lib().lsx_state_upload(self.h, c.ctypes.data_as(_dp), _stream(stream)))
         self._pending = c  # the copy is stream-ordered: the source lives until the next upload
-        self._pending = c  # kept alive until the next call (stream-ordered copy)
 
     def download(self, stream=None):
         out = np.zeros((self.N, self.W), dtype=np.complex128)

@@ -164,7 +164,7 @@ class BlockSpec:
 
 def example3_system(Ec: float, s1: float = 1.0, s2: float = 2.0,
                     beta: float = (math.sqrt(5.0) - 1.0) / 2.0) -> BlockSpec:
-    """The quasi-one-dimensional system of Example 3 (Sec. 6):
+    """The quasi-one-dimensional system of Example 3 (Sec. 5):
     V = s1 cos^2(beta x) cos^2(pi y / 2) + s2 cos^2(x) cos^2(pi y / 2), incommensurate in x and
     periodic in y.  Blocks (m, p, n): m and n index the x-wavevectors 2 beta m and 2 n of the two
     factors, p the y-wavevector pi p; cutoff groups (m, n) and p; layer 1 couples (m, p), layer

@@ -1,15 +1,21 @@
 """Batched uneven systems: one grouped launch per pass over several systems.
 
-Each system stepped inside a batch must equal the same system stepped on its own (up to
-the summation order of a different tile shape), for every scheme and precision, with
-systems of different lattices, cutoffs, dimensions and wavepacket counts; the replayed
-HIP graph of the step body must give the same result on every call.
+Each system stepped inside a batch must equal the oracle's unmerged evolution of that
+system (FP64: <= 1e-12 per step; mixed: the rounding bound derived in mixed_bounds.py) and
+the same system stepped on its own (up to the summation order of a different tile shape),
+for every scheme and precision, with systems of different lattices, cutoffs, dimensions and
+wavepacket counts; the replayed HIP graph of the step body must give the same result on
+every call.
 """
 import math
 
 import numpy as np
 import pytest
 
+import mixed_bounds
+from oracle import blocks
+from oracle import multilayer as ml
+from oracle import splitting
 from paper_2103_14897_amd import lsx
 from paper_2103_14897_amd import workloads as wl
 
@@ -34,35 +40,51 @@ def systems():
 @pytest.mark.parametrize("precision,kappa", [("fp64", 0.0), ("mix_fp32", 1.0), ("mix_bf16x3", 0.0)])
 def test_batch_equals_individual(scheme, precision, kappa):
     print(f"[case] batch {scheme} {precision} kappa={kappa}", flush=True)
+    tau, nsteps = 0.004, 7
+    flow = "cn" if scheme == "strang_cn" else "exact"
     made = []
     for spec, W in systems():
         S = lsx.System.from_spec(spec)
-        P = lsx.Plan(S, 0.004, scheme, kappa, precision)
+        P = lsx.Plan(S, tau, scheme, kappa, precision)
         c0 = wl.random_state(S.N, W, seed=W)
         ref_st = lsx.State(P, W)
         ref_st.upload(c0)
-        ref_st.step(7)
+        ref_st.step(nsteps)
         ref = ref_st.download()
         ref_st.destroy()
+        # the oracle's unmerged evolution of the same system from the same data
+        O = splitting.Lifted.from_spec(spec)
+        assert np.array_equal(S.index(), O.mn)
+        plan = splitting.SplitPlan(O, kappa, flow)
+        oref = plan.evolve(c0, tau, nsteps, "lie" if scheme == "lie" else "strang")
+        if precision == "fp64":
+            bound = 0.0
+        elif scheme == "lie":
+            bound = mixed_bounds.sequence_bound(plan, mixed_bounds.lie_passes(tau, nsteps), precision)
+        else:
+            seq = mixed_bounds.strang_passes(tau, nsteps, merged=(flow == "exact"))
+            bound = mixed_bounds.sequence_bound(plan, seq, precision)
         st = lsx.State(P, W)
         st.upload(c0)
-        made.append((S, P, st, c0, ref))
+        made.append((S, P, st, c0, ref, oref, bound))
     B = lsx.Batch([m[2] for m in made])
-    B.step(7)
-    # two runs of a mixed path that differ only in the FP32 summation order of their tiles:
-    # each run's own rounding is <= ~1.3e-10 relative per pass against FP64, so after
-    # 7 steps (14 passes) the two differ by well under 1e-8
-    tol = 1e-13 if precision == "fp64" else 1e-8
-    for S, P, st, c0, ref in made:
-        assert colrel(st.download(), ref) < tol
-    # a second call replays the captured body graph from a fresh upload
-    for S, P, st, c0, ref in made:
-        st.upload(c0)
-    B.step(7)
-    for S, P, st, c0, ref in made:
-        assert colrel(st.download(), ref) < tol
+    fp64_tol = 1e-12 * nsteps
+    for call in range(2):
+        if call:
+            # a second call replays the captured body graph from a fresh upload
+            for m in made:
+                m[2].upload(m[3])
+        B.step(nsteps)
+        for S, P, st, c0, ref, oref, bound in made:
+            got = st.download()
+            e_or, e_ind = colrel(got, oref), colrel(got, ref)
+            print(f"  N={S.N} vs oracle {e_or:.2e} (bound {bound + fp64_tol:.2e}), vs individual {e_ind:.2e}")
+            assert e_or <= bound + fp64_tol
+            # batch and individual runs differ only in their tiles' summation order: each is
+            # within `bound` of FP64 arithmetic (exactly equal orders in FP64: ~rounding)
+            assert e_ind <= (2 * bound if precision != "fp64" else 1e-13)
     B.destroy()
-    for S, P, st, c0, ref in made:
+    for S, P, st, c0, ref, oref, bound in made:
         st.destroy()
         P.destroy()
         S.destroy()
@@ -131,13 +153,16 @@ def test_persistent_launch_equals_one_workgroup_per_tile(monkeypatch, precision,
 @pytest.mark.parametrize("scheme", ["strang", "lie", "lie_be", "strang_cn", "yoshida4"])
 def test_three_layer_batch_equals_individual(scheme):
     """Three-layer systems of different sizes in one batch: every system equals the same system
-    stepped on its own.  Three-layer Lie has an odd number of passes per step, so its graph
+    stepped on its own and the L-layer oracle's unmerged evolution (FP64, 2e-12 per step,
+    6e-12 for Yoshida's three Strang steps).  Three-layer Lie has an odd number of passes per step, so its graph
     holds two repetitions and an odd leftover runs eagerly (7 steps: head, 2 replays, 1 extra,
     tail)."""
     print(f"[case] three-layer batch {scheme}", flush=True)
     specs = [(wl.chain_layers(800.0), 8), (wl.chain_layers(1500.0, periods=(1.0, math.sqrt(2.0), math.sqrt(3.0))), 5),
              (wl.twisted_layers(120.0), 4)]
     made = []
+    flow = {"lie_be": "be", "strang_cn": "cn"}.get(scheme, "exact")
+    per_step = 6e-12 if scheme == "yoshida4" else 2e-12
     try:
         for spec, W in specs:
             S = lsx.System.layers(spec.d, spec.As, spec.Ec, spec.cutoff, spec.pots)
@@ -148,17 +173,23 @@ def test_three_layer_batch_equals_individual(scheme):
             ref.step(7)
             st = lsx.State(P, W)
             st.upload(c0)
-            made.append((S, P, st, ref, c0))
+            O = ml.MultiLifted(spec.d, spec.As, spec.Ec, spec.cutoff, spec.pots)
+            assert np.array_equal(S.index(), O.mn.astype(np.int32))
+            oplan = ml.MultiSplitPlan(O, 0.3, flow)
+            oref = oplan.evolve(c0, 0.004, 7, {"lie_be": "lie", "strang_cn": "strang"}.get(scheme, scheme))
+            made.append((S, P, st, ref, c0, oref))
         B = lsx.Batch([m[2] for m in made])
         for _ in range(2):  # the second call replays the captured graph
-            for S, P, st, ref, c0 in made:
+            for S, P, st, ref, c0, oref in made:
                 st.upload(c0)
             B.step(7)
-            for S, P, st, ref, c0 in made:
-                assert colrel(st.download(), ref.download()) < 1e-13
+            for S, P, st, ref, c0, oref in made:
+                got = st.download()
+                assert colrel(got, ref.download()) < 1e-13
+                assert colrel(got, oref) < 7 * per_step
         B.destroy()
     finally:
-        for S, P, st, ref, c0 in made:
+        for S, P, st, ref, c0, oref in made:
             st.destroy()
             ref.destroy()
             P.destroy()
@@ -168,6 +199,7 @@ def test_three_layer_batch_equals_individual(scheme):
 def test_example3_batch_and_mixed_layer_counts():
     made = []
     try:
+        checks = []
         for k, Ec in enumerate((60.0, 100.0)):
             spec = wl.example3_system(Ec)
             S = lsx.System.blocks(spec.Rs, spec.groups, spec.Ec, spec.layers, spec.pots)
@@ -179,10 +211,17 @@ def test_example3_batch_and_mixed_layer_counts():
             st = lsx.State(P, 16)
             st.upload(c0)
             made.append((S, P, st, ref))
+            O = blocks.example3(Ec)
+            assert np.array_equal(S.index(), O.mn.astype(np.int32))
+            oplan = ml.MultiSplitPlan(O, 0.0)
+            bound = mixed_bounds.sequence_bound(oplan, mixed_bounds.strang_passes(0.01, 6), "mix_fp32")
+            checks.append((oplan.evolve(c0, 0.01, 6, "strang"), bound))
         B = lsx.Batch([m[2] for m in made])
         B.step(6)
-        for S, P, st, ref in made:
-            assert colrel(st.download(), ref.download()) < 1e-8
+        for (S, P, st, ref), (oref, bound) in zip(made, checks):
+            got = st.download()
+            assert colrel(got, oref) <= bound + 6 * 2e-12
+            assert colrel(got, ref.download()) <= 2 * bound
         B.destroy()
         spec = wl.chain_layers(400.0)
         S3 = lsx.System.layers(spec.d, spec.As, spec.Ec, spec.cutoff, spec.pots)

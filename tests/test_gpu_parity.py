@@ -218,7 +218,7 @@ def test_rational_schemes(scheme, flow, precision):
     assert colrel(st.download(), ref) < 10 * tol
     m = st.observables(lsx.OBS_MASS)["mass"]
     if flow == "cn":
-        assert np.abs(m - 1.0).max() < 1e-12 if precision == "fp64" else 1e-7
+        assert np.abs(m - 1.0).max() < (1e-12 if precision == "fp64" else 1e-7)
     else:
         assert np.all(m < 1.0)
     teardown(st, P, S)

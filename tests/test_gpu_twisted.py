@@ -67,10 +67,17 @@ def full_twisted():
     w = wl.twisted()
     print("[case] twisted full size Ec=6500 W=128", flush=True)
     S = lsx.System.from_spec(w.spec)
-    O = splitting.Lifted(w.spec.d, w.spec.A1, w.spec.A2, w.spec.Ec, w.spec.cutoff, w.spec.pot1, w.spec.pot2,
-                         mn=S.index().astype(np.int64))
+    # the oracle enumerates its own index set and fibres; every row list used below is the
+    # oracle's, so a wrong row in the library's tables cannot pass unseen
+    O = splitting.Lifted.from_spec(w.spec)
+    assert np.array_equal(S.index(), O.mn)
     yield w, S, O
     S.destroy()
+
+
+def _oracle_fibres(O, layer):
+    ptr = np.cumsum([0] + [len(r) for _, r in O.fib[layer]])
+    return ptr, [r for _, r in O.fib[layer]]
 
 
 def test_twisted_full_size_sampled_fp64(full_twisted):
@@ -81,13 +88,13 @@ def test_twisted_full_size_sampled_fp64(full_twisted):
     c = wl.random_state(S.N, w.W, seed=11)
     for layer, half in ((1, 0), (1, 1), (2, 0)):
         t = w.tau if half == 0 else w.tau / 2
-        ptr, rows = S.fibres(layer)
+        ptr, rows = _oracle_fibres(O, layer)
         st.upload(c)
         st.fibre_pass(layer, half)
         got = st.download()
         for f in _sample_fibres(ptr, seed=layer + 3 * half):
-            r = rows[ptr[f]:ptr[f + 1]]
-            H = O.fibre_hamiltonian(layer, r.astype(np.int64), 0.0)
+            r = rows[f]
+            H = O.fibre_hamiltonian(layer, r, 0.0)
             Pf = splitting.propagator_from_hamiltonian(H, t)
             assert np.abs(P.propagator(layer, half, f) - Pf).max() < 5e-13, (layer, half, f, len(r))
             assert colrel(got[r], Pf @ c[r]) < 1e-12, (layer, half, f, len(r))
@@ -113,13 +120,13 @@ def test_twisted_full_size_sampled_mixed(full_twisted, precision):
     st = lsx.State(P, w.W)
     try:
         c = wl.random_state(S.N, w.W, seed=5)
-        ptr, rows = S.fibres(2)
+        ptr, rows = _oracle_fibres(O, 2)
         st.upload(c)
         st.fibre_pass(2, 0)
         got = st.download()
         for f in _sample_fibres(ptr, seed=7):
-            r = rows[ptr[f]:ptr[f + 1]]
-            Pf = splitting.propagator_from_hamiltonian(O.fibre_hamiltonian(2, r.astype(np.int64), 0.0), w.tau)
+            r = rows[f]
+            Pf = splitting.propagator_from_hamiltonian(O.fibre_hamiltonian(2, r, 0.0), w.tau)
             err = colrel(got[r], Pf @ c[r])
             assert err < 1e-7, (precision, f, len(r), err)
         st.upload(w.initial_state(O.mn))
@@ -129,3 +136,34 @@ def test_twisted_full_size_sampled_mixed(full_twisted, precision):
     finally:
         st.destroy()
         P.destroy()
+
+
+def test_twisted_full_size_to_T_mixed_within_1e6_of_fp64(full_twisted):
+    """The accuracy bar of the mixed paths on the full twisted bilayer (Ec = 6500, W = 128,
+    Strang tau = 5e-3 to T = 1, 200 steps): after T every wavepacket of the FP32 and BF16x3
+    paths is within 1e-6 relative L2 of the FP64 path (max over wavepackets), and the FP64
+    path keeps every mass to 1e-13 per step (unitary sub-flows, Thm 4.4's exact analogue)."""
+    w, S, O = full_twisted
+    nsteps = int(round(w.T / w.tau))
+    assert nsteps == 200
+    c0 = w.initial_state(O.mn)
+    out = {}
+    for prec in ("fp64", "mix_fp32", "mix_bf16x3"):
+        print(f"[case] twisted full size to T, {prec}", flush=True)
+        P = lsx.Plan(S, w.tau, "strang", 0.0, prec)
+        st = lsx.State(P, w.W)
+        try:
+            st.upload(c0)
+            st.step(nsteps)
+            out[prec] = st.download()
+            m = st.observables(lsx.OBS_MASS)["mass"]
+            drift = float(np.abs(m - 1.0).max())
+            print(f"  {prec}: max |mass - 1| after T {drift:.2e}", flush=True)
+            assert drift < (1e-13 * nsteps if prec == "fp64" else 1e-6), (prec, drift)
+        finally:
+            st.destroy()
+            P.destroy()
+    for prec in ("mix_fp32", "mix_bf16x3"):
+        err = colrel(out[prec], out["fp64"])
+        print(f"  {prec}: max rel L2 vs FP64 after T {err:.2e}", flush=True)
+        assert err <= 1e-6, (prec, err)

@@ -4,6 +4,7 @@ These run without a GPU: lsx_system_* is host-only code.  Index sets and fibre
 tables are integer work and must equal the oracle's exactly.
 """
 import ctypes
+import json
 import os
 import re
 
@@ -50,10 +51,28 @@ def test_index_set_and_fibres_equal_oracle(spec):
     sys.destroy()
 
 
-def test_twisted_full_size_count():
-    sys = lsx.System.from_spec(wl.twisted_system(6500.0))
-    assert sys.N == 398821 and sys.nfibres[1] == 889 and sys.nfibres[2] == 889
-    sys.destroy()
+def test_twisted_full_size_index_set_and_fibres_equal_oracle():
+    """Full-size twisted bilayer (Ec = 6500, N = 398821): the library's lifted index set and
+    both fibre tables (Sec. 3, Fig. 3.1) equal the oracle's bit for bit, and the fibre-length
+    statistics equal the stored ones (written by tests/golden/make_golden.py from the oracle)."""
+    spec = wl.twisted_system(6500.0)
+    sys = lsx.System.from_spec(spec)
+    try:
+        mn = lifted.index_set(spec.A1, spec.A2, spec.Ec, spec.cutoff)
+        assert sys.N == len(mn) == 398821
+        assert np.array_equal(sys.index(), mn.astype(np.int32))
+        gold = json.load(open(os.path.join(ROOT, "tests", "golden", "index_sets.json")))["twisted"]
+        for layer in (1, 2):
+            fib = lifted.fibres(mn, layer)
+            ptr, rows = sys.fibres(layer)
+            assert sys.nfibres[layer] == len(fib) == gold[f"nfibres_{layer}"] == 889
+            assert np.array_equal(ptr, np.cumsum([0] + [len(r) for _, r in fib]))
+            assert np.array_equal(rows, np.concatenate([r for _, r in fib]))
+            L = np.diff(ptr)
+            assert int((L.astype(np.int64) ** 2).sum()) == gold[f"sum_L2_{layer}"]
+            assert [int(L.min()), int(L.max())] == gold[f"minmax_L_{layer}"]
+    finally:
+        sys.destroy()
 
 
 def test_errors():
@@ -177,3 +196,34 @@ def test_block_system_errors():
     with pytest.raises(lsx.LsxError) as e:  # not Hermitian
         lsx.System.blocks(Rs, groups, Ec, layers, [pots[0], {(1, 0): 0.3}])
     assert e.value.code == lsx.LSX_E_NOT_HERMITIAN
+
+
+@pytest.mark.parametrize("spec", [wl.chain_system(2.0e4), wl.twisted_system(300.0, cutoff="product")],
+                         ids=["chain", "product2d"])
+def test_descriptor_form_equals_flat_arguments(spec):
+    """lsx_system_create_desc, lsx_index_size and lsx_fibre_info give the system, size and fibre
+    lengths of the flat-argument calls (host-only work)."""
+    a = lsx.System.from_spec(spec)
+    b = lsx.System.from_desc(spec.d, spec.A1, spec.A2, spec.Ec, spec.cutoff, spec.pot1, spec.pot2)
+    try:
+        assert b.index_size() == a.N == b.N
+        assert np.array_equal(a.index(), b.index())
+        for layer in (1, 2):
+            nf, lengths = b.fibre_info(layer)
+            ptr, rows = a.fibres(layer)
+            assert nf == a.nfibres[layer]
+            assert np.array_equal(lengths, np.diff(ptr))
+            assert np.array_equal(b.fibres(layer)[1], rows)
+        with pytest.raises(lsx.LsxError) as e:
+            b.fibre_info(3)
+        assert e.value.code == lsx.LSX_E_INVALID
+    finally:
+        a.destroy()
+        b.destroy()
+    L = lsx.lib()
+    assert L.lsx_system_create_desc(None, lsx.C.byref(lsx._p())) == lsx.LSX_E_INVALID
+    assert L.lsx_index_size(None, None) == lsx.LSX_E_INVALID
+    assert L.lsx_plan_create_desc(None, None, None, None) == lsx.LSX_E_INVALID
+    assert L.lsx_state_wrap(None, 4, None, None) == lsx.LSX_E_INVALID
+    assert L.lsx_state_set_tuning(None, 1, 1, 2, 0) == lsx.LSX_E_INVALID
+    assert L.lsx_state_set_store_mode(None, 0) == lsx.LSX_E_INVALID
