@@ -461,6 +461,104 @@ def layered_bench(args, S, W, tau, slot, what, workload):
     S.destroy()
 
 
+def time_paths(S, w, c0, paths, scheme, kappa, steps, warmup, reps, stream):
+    """Per precision path: plan precompute, an accuracy run to T, `warmup` untimed then `steps`
+    timed steps (HIP events on `stream`, the stream every kernel is launched on), and `reps`
+    back-to-back launches of each layer's pass (and of the phase when kappa > 0).  Returns the
+    per-path results (with the max relative L2 against the FP64 path after T) and the states
+    after T."""
+    import torch
+
+    N, W = S.N, w.W
+    res = {}
+    finals = {}
+    for path in paths:
+        t0 = time.perf_counter()
+        P = lsx.Plan(S, w.tau, scheme, kappa, path, stream)
+        pre = time.perf_counter() - t0
+        st = lsx.State(P, W)
+        # accuracy run to T
+        st.upload(c0, stream)
+        st.step(w.nsteps, stream)
+        finals[path] = st.download(stream)
+        # timed run
+        st.upload(c0, stream)
+        st.step(warmup, stream)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        st.step(steps, stream)
+        e1.record(stream)
+        e1.synchronize()
+        wall = time.perf_counter() - t0
+        ms = e0.elapsed_time(e1)
+        # each layer's pass, back-to-back launches on the same stream
+        torch.cuda.synchronize()
+        k0, k1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        k0.record(stream)
+        st.fibre_pass(2, 0, reps, stream)
+        k1.record(stream)
+        k1.synchronize()
+        kus = k0.elapsed_time(k1) * 1e3 / reps
+        k0.record(stream)
+        st.fibre_pass(1, 0, reps, stream)
+        k1.record(stream)
+        k1.synchronize()
+        kus1 = k0.elapsed_time(k1) * 1e3 / reps
+        phase_us = None
+        if kappa != 0.0:
+            k0.record(stream)
+            for _ in range(reps):
+                st.phase(1, stream)
+            k1.record(stream)
+            k1.synchronize()
+            phase_us = k0.elapsed_time(k1) * 1e3 / reps
+        res[path] = {"coeff_steps_per_s": N * W * steps / (ms * 1e-3), "ms_per_step": ms / steps,
+                     "wall_ms": wall * 1e3, "precompute_s": pre, "layer2_pass_us": kus, "layer1_pass_us": kus1,
+                     "tiles": {"layer1": st.tuning(1)[:2] + (st.prefetch(1),),
+                               "layer2": st.tuning(2)[:2] + (st.prefetch(2),)},
+                     "nontemporal_stores": st.store_mode()[0]}
+        if phase_us is not None:
+            res[path]["phase_us"] = phase_us
+            res[path]["phase_GBps"] = (2.0 * N * W * 16 + 16.0 * N) / (phase_us * 1e-6) / 1e9
+        print(f"[bench] N={N} W={W} {path}: precompute {pre:.2f} s, {ms / steps * 1e3:.1f} us/step", file=sys.stderr,
+              flush=True)
+        st.destroy()
+        P.destroy()
+    ref = finals.get("fp64")
+    for path in res:
+        res[path]["rel_l2_vs_fp64_after_T"] = (
+            float((np.linalg.norm(finals[path] - ref, axis=0) / np.linalg.norm(ref, axis=0)).max())
+            if ref is not None else None)
+    return res, finals
+
+
+def config3_summary(args, stream):
+    """The MFMA-bound twisted bilayer (triangular lattices at +-2.5 deg, Ec = 6500, N = 398821,
+    W = 128, Strang tau = 5e-3 to T = 1) on every path: ms/step, coeff*steps/s, max relative L2
+    against the FP64 path after T (200 steps), and each layer pass against its path's MFMA peak
+    (8 W sum L^2 flops per pass)."""
+    w = wl.twisted()
+    S = lsx.System.from_spec(w.spec)
+    c0 = w.initial_state(S.index())
+    sumL2 = {j: int(np.sum(np.diff(S.fibres(j)[0]).astype(np.int64) ** 2)) for j in (1, 2)}
+    res, finals = time_paths(S, w, c0, args.paths.split(","), "strang", 0.0, args.config3_steps, 2, 4, stream)
+    del finals
+    out = {"workload": "twisted_tri_pm2.5deg_Ec6500_W128_strang_tau5e-3", "N": S.N, "W": w.W,
+           "steps_to_T": w.nsteps, "timed_steps": args.config3_steps, "paths": {}}
+    for path, r in res.items():
+        q = {k: r[k] for k in ("ms_per_step", "coeff_steps_per_s", "rel_l2_vs_fp64_after_T", "precompute_s",
+                               "layer1_pass_us", "layer2_pass_us", "tiles", "nontemporal_stores")}
+        for j in (1, 2):
+            tf = 8.0 * w.W * sumL2[j] / (r[f"layer{j}_pass_us"] * 1e-6)
+            q[f"layer{j}_pass_TFLOPs"] = tf / 1e12
+            q[f"layer{j}_pass_mfma_frac"] = tf / PEAK[path]
+        out["paths"][path] = q
+    S.destroy()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -469,6 +567,9 @@ def main():
     ap.add_argument("--paths", default="fp64,mix_fp32,mix_bf16x3")
     ap.add_argument("--kernel-reps", type=int, default=400)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-config3", action="store_true",
+                    help="chain workload: leave out the twisted-bilayer summary added to the line")
+    ap.add_argument("--config3-steps", type=int, default=20)
     ap.add_argument("--calib-mib", type=int, default=64)
     ap.add_argument("--batch-1d", type=int, default=240)
     ap.add_argument("--batch-2d", type=int, default=16)
@@ -521,67 +622,9 @@ def main():
     calib_b.copy_(calib_a)
     torch.cuda.synchronize()
     del calib_a, calib_b
-    res = {}
-    finals = {}
-    for path in args.paths.split(","):
-        t0 = time.perf_counter()
-        P = lsx.Plan(S, w.tau, args.scheme, args.kappa, path, stream)
-        pre = time.perf_counter() - t0
-        st = lsx.State(P, W)
-        # accuracy run to T
-        st.upload(c0, stream)
-        st.step(w.nsteps, stream)
-        finals[path] = st.download(stream)
-        # timed run
-        st.upload(c0, stream)
-        st.step(args.warmup, stream)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        t0 = time.perf_counter()
-        e0.record(stream)
-        st.step(args.steps, stream)
-        e1.record(stream)
-        e1.synchronize()
-        wall = time.perf_counter() - t0
-        ms = e0.elapsed_time(e1)
-        # dominant kernel: the layer-2 fibre pass, back-to-back launches on the same stream
-        torch.cuda.synchronize()
-        k0, k1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        k0.record(stream)
-        st.fibre_pass(2, 0, args.kernel_reps, stream)
-        k1.record(stream)
-        k1.synchronize()
-        kus = k0.elapsed_time(k1) * 1e3 / args.kernel_reps
-        k0.record(stream)
-        st.fibre_pass(1, 0, args.kernel_reps, stream)
-        k1.record(stream)
-        k1.synchronize()
-        kus1 = k0.elapsed_time(k1) * 1e3 / args.kernel_reps
-        phase_us = None
-        if args.kappa != 0.0:
-            k0.record(stream)
-            for _ in range(args.kernel_reps):
-                st.phase(1, stream)
-            k1.record(stream)
-            k1.synchronize()
-            phase_us = k0.elapsed_time(k1) * 1e3 / args.kernel_reps
-        res[path] = {"coeff_steps_per_s": N * W * args.steps / (ms * 1e-3), "ms_per_step": ms / args.steps,
-                     "wall_ms": wall * 1e3, "precompute_s": pre, "layer2_pass_us": kus, "layer1_pass_us": kus1,
-                     "tiles": {"layer1": st.tuning(1)[:2] + (st.prefetch(1),),
-                               "layer2": st.tuning(2)[:2] + (st.prefetch(2),)},
-                     "nontemporal_stores": st.store_mode()[0]}
-        if phase_us is not None:
-            res[path]["phase_us"] = phase_us
-            res[path]["phase_GBps"] = (2.0 * N * W * 16 + 16.0 * N) / (phase_us * 1e-6) / 1e9
-        st.destroy()
-        P.destroy()
+    res, finals = time_paths(S, w, c0, args.paths.split(","), args.scheme, args.kappa, args.steps, args.warmup,
+                             args.kernel_reps, stream)
     ref = finals.get("fp64")
-    for path in res:
-        if ref is not None:
-            err = float((np.linalg.norm(finals[path] - ref, axis=0) / np.linalg.norm(ref, axis=0)).max())
-        else:
-            err = None
-        res[path]["rel_l2_vs_fp64_after_T"] = err
     # without the FP64 path there is no reference: every path is eligible (its error is null)
     ok = [p for p in res if p == "fp64" or ref is None or (res[p]["rel_l2_vs_fp64_after_T"] is not None
                                                            and res[p]["rel_l2_vs_fp64_after_T"] <= 1e-6)]
@@ -628,6 +671,8 @@ def main():
         "roofline": roof,
         "paths": res,
     }
+    if counted and not args.no_config3:
+        out["config3"] = config3_summary(args, stream)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w.spec, c0, w.tau)
     print(json.dumps(out))
