@@ -373,6 +373,28 @@ lsx_status lsx_phase(lsx_plan* plan, lsx_state* st, int32_t half, void* stream);
 lsx_status lsx_observables(lsx_plan* plan, lsx_state* st, uint32_t mask, double* out, void* stream);
 
 /*
+ * lsx_observables_noalloc -- lsx_observables for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).  It
+ * calls no hipMalloc, hipFree or allocating library routine.
+ *  dev_c    caller-owned device array c[N][W] complex128 (N of the plan's system), read only.
+ *  W        1 .. 65536 wavepackets (and at most the plan's max_wavepackets, if set).
+ *  mask     as for lsx_observables; the output blocks follow in the same order.
+ *  dev_out  caller-owned DEVICE array that receives the requested blocks (W doubles for mass
+ *           and energy, nfibres_j * W for fibre masses), stream-ordered; nothing is copied to
+ *           the host and the stream is not synchronised.  Non-finite values are not checked
+ *           (the results never reach the host here).
+ * The mass and energy reductions keep their partial sums in a static scratch array of 2^20
+ * doubles (8 MiB) per GPU, held until the process ends; a call needs
+ * W * min(1024, ceil(N / 256)) of them and is refused beyond that with LSX_E_INVALID (fibre
+ * masses alone need none).  Every partial is written before it is read within a call, so no
+ * part of the array has to start at zero.  All calls on one GPU share the array: calls that
+ * overlap on one GPU (different streams or threads) race.  Same kernels, block count and
+ * fixed reduction order as lsx_observables, so the values are identical.
+ */
+lsx_status lsx_observables_noalloc(lsx_plan* plan, const void* dev_c, int32_t W, uint32_t mask, double* dev_out,
+                                   void* stream);
+
+/*
  * Descriptor form of the boundary.  The same problem statement (Sec. 2: lattices R_j = A_j Z^d
  * and the Fourier coefficients of the layer potentials, eq. 2.2; Sec. 3: the cutoff Ec and its
  * lifted set) and the same plan parameters (tau, scheme of App. A / Alg. 2 / eq. 4.6, kinetic

@@ -1740,6 +1740,54 @@ extern "C" lsx_status lsx_observables(lsx_plan* pl, lsx_state* st, uint32_t mask
   return LSX_OK;
 }
 
+// Allocation-free variant of lsx_observables: the state is a caller-owned device array, the
+// results stay on the device, and the reduction partials go to the static scratch array of
+// lsx_kernels.hip (one per GPU, shared by every call on that GPU).  The partials are written
+// before they are read within a call, so nothing needs clearing; calls that overlap on one GPU
+// race on the array.  Same kernels, block count and fixed reduction order as lsx_observables,
+// so the two give identical values.
+extern "C" lsx_status lsx_observables_noalloc(lsx_plan* pl, const void* dev_c, int32_t W, uint32_t mask,
+                                              double* dev_out, void* stream) {
+  if (!pl || !dev_c || !dev_out) return fail(LSX_E_INVALID, "null argument");
+  if (W < 1 || W > 65536) return fail(LSX_E_INVALID, "W must be in [1, 65536]");
+  if (pl->max_w > 0 && W > pl->max_w) return fail(LSX_E_INVALID, "W exceeds the plan's max_wavepackets");
+  if (mask == 0 || (mask & ~31u)) return fail(LSX_E_INVALID, "bad observable mask");
+  if ((mask & LSX_OBS_FIBRE_MASS_3) && pl->sys->nl < 3) return fail(LSX_E_INVALID, "system has no layer 3");
+  const lsx_system* sys = pl->sys;
+  const int64_t N = sys->N;
+  const int nred = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (N + 255) / 256));
+  const bool reduce = (mask & (LSX_OBS_MASS | LSX_OBS_ENERGY)) != 0;
+  if (reduce && (int64_t)nred * W > kStaticScratchDoubles)
+    return fail(LSX_E_INVALID, "W * min(1024, ceil(N / 256)) = " + std::to_string((int64_t)nred * W) +
+                                   " reduction partials exceed the static scratch of " +
+                                   std::to_string(kStaticScratchDoubles) + " doubles");
+  double* part = nullptr;
+  if (reduce) LSX_HIP_TRY(static_scratch(&part));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const double2* c = static_cast<const double2*>(dev_c);
+  size_t count = 0;
+  if (mask & LSX_OBS_MASS) {
+    LSX_HIP_TRY(launch_reduce(s, 0, N, W, c, pl->K2.p, 0, nullptr, nullptr, 0, nullptr, nullptr, 0, nullptr,
+                              nullptr, part, nred, dev_out + count));
+    count += W;
+  }
+  if (mask & LSX_OBS_ENERGY) {
+    const int nv3 = sys->nl > 2 ? sys->pot[2].nv : 0;
+    LSX_HIP_TRY(launch_reduce(s, 1, N, W, c, pl->K2.p, sys->pot[0].nv, pl->L[0].nbr.p, pl->L[0].v.p,
+                              sys->pot[1].nv, pl->L[1].nbr.p, pl->L[1].v.p, nv3, pl->L[2].nbr.p, pl->L[2].v.p, part,
+                              nred, dev_out + count));
+    count += W;
+  }
+  const uint32_t fm_bit[kMaxLayers] = {LSX_OBS_FIBRE_MASS_1, LSX_OBS_FIBRE_MASS_2, LSX_OBS_FIBRE_MASS_3};
+  for (int layer = 1; layer <= sys->nl; ++layer)
+    if (mask & fm_bit[layer - 1]) {
+      const LayerDev& ld = pl->L[layer - 1];
+      LSX_HIP_TRY(launch_fibre_mass(s, ld.nf, ld.ptr.p, ld.rows.p, W, c, dev_out + count));
+      count += (size_t)ld.nf * W;
+    }
+  return LSX_OK;
+}
+
 // ================================================================ batched systems
 namespace {
 struct PatternKey {

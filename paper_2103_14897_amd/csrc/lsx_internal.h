@@ -121,6 +121,11 @@ hipError_t launch_reduce(hipStream_t s, int kind, int64_t N, int W, const double
                          double* out);
 hipError_t launch_fibre_mass(hipStream_t s, int nf, const int32_t* ptr, const int32_t* rows, int W,
                              const double2* c, double* out);
+// Device address of this GPU's static scratch array (kStaticScratchDoubles doubles), looked up
+// once per device on first use; never allocates.
+constexpr int64_t kStaticScratchDoubles = int64_t(1) << 20;  // 8 MiB per GPU
+constexpr int kMaxDevices = 64;
+hipError_t static_scratch(double** ptr);
 
 // ---------------------------------------------------------------- stochastic steps (lsx_sample.hip)
 hipError_t launch_si_step(hipStream_t s, int64_t N, int W, double tau, const double* K2, int nv1,

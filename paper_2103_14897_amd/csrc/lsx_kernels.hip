@@ -1589,4 +1589,29 @@ hipError_t launch_fibre_mass(hipStream_t s, int nf, const int32_t* ptr, const in
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- allocation-free scratch
+// Reduction partials of the allocation-free observables entry point live in this array, one
+// copy per GPU for the life of the process.  Host code never passes the array's name to a
+// kernel (on the host it is a stand-in, not a device address): the address is looked up once
+// per device with that device current and kept.
+static __device__ __align__(256) double scratch[kStaticScratchDoubles];
+
+hipError_t static_scratch(double** ptr) {
+  static std::mutex mu;
+  static double* per_device[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!per_device[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    per_device[dev] = static_cast<double*>(p);
+  }
+  *ptr = per_device[dev];
+  return hipSuccess;
+}
+
 }  // namespace lsx

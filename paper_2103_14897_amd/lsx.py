@@ -89,6 +89,7 @@ _SIGS = {
                                      C.c_double, C.c_double, _p, _p]),
     "lsx_mlp_destroy": (C.c_int, [_p]),
     "lsx_live_buffers": (C.c_int, [_i64p, _i64p]),
+    "lsx_observables_noalloc": (C.c_int, [_p, _p, C.c_int32, C.c_uint32, _p, _p]),
     "lsx_state_set_tuning": (C.c_int, [_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
     "lsx_state_set_store_mode": (C.c_int, [_p, C.c_int32]),
     "lsx_system_create_desc": (C.c_int, [_p, C.POINTER(_p)]),
