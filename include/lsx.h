@@ -189,6 +189,17 @@ lsx_status lsx_fibre_get(const lsx_system* sys, int32_t layer, int32_t* ptr, int
 lsx_status lsx_system_destroy(lsx_system* sys);
 
 /*
+ * Point symmetries of a lattice-built system (host only): rotations R of the plane (multiples
+ * of 30 degrees; in 1D, x -> -x) with R B_j = B_j M_j for an integer matrix M_j on every layer j
+ * (B_j = 2 pi A_j^{-T}, Sec. 2), every potential coefficient at M_j m equal to the one at m
+ * (eq. 2.2) and the lifted index set mapped onto itself (Sec. 3).  *nsym receives their number
+ * (the identity not counted); M, if not NULL, receives nsym * nlayers row-major d x d int32
+ * matrices M_j, symmetry-major.  Plans share fibre propagators over them (lsx_plan_sharing).
+ * Systems built from shared blocks report none.
+ */
+lsx_status lsx_system_symmetries(const lsx_system* sys, int32_t* nsym, int32_t* M);
+
+/*
  * lsx_plan_create -- one-time precompute of the fibre propagators on the GPU.
  *
  * Splitting (Sec. 4.2, App. A) of H = D + V^1 + V^2 (eq. 3.5) with a kinetic
@@ -245,6 +256,20 @@ lsx_status lsx_plan_create(lsx_system* sys, double tau, int32_t scheme, double k
  */
 lsx_status lsx_plan_propagator(const lsx_plan* plan, int32_t layer, int32_t half, int32_t fibre,
                                double* out, void* stream);
+
+/*
+ * Propagator sharing of a plan: *ndistinct = number of distinct fibre propagators the plan
+ * stores per slot for `layer` (1 .. nlayers), *nsym = number of point symmetries other than the
+ * identity they are shared over.  With kappa = 1, fibres whose index windows coincide up to a
+ * translation share one propagator.  With kappa < 1 (every scheme), rotations of the plane (or
+ * x -> -x in 1D) that map every layer's reciprocal lattice, potential and the lifted index set
+ * onto themselves (for the twisted triangular bilayer the six rotations by multiples of 60
+ * degrees) map fibre Hamiltonians onto row permutations of one another (eq. 3.6), so one
+ * propagator serves each orbit (Sec. 3 block structure; LSX_SYMMETRY=0 turns this off).
+ * Results are the same up to rounding either way; lsx_plan_propagator returns every fibre's
+ * propagator in the row order of lsx_fibre_get.  Outputs may be NULL.
+ */
+lsx_status lsx_plan_sharing(const lsx_plan* plan, int32_t layer, int32_t* ndistinct, int32_t* nsym);
 
 /* Frees the plan.  LSX_E_STATE if states built on it are still alive. */
 lsx_status lsx_plan_destroy(lsx_plan* plan);

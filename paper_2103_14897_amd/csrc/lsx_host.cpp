@@ -28,6 +28,11 @@ static lsx_status fail(lsx_status st, const std::string& msg) {
   return st;
 }
 
+static int env_int(const char* name, int dflt) {
+  const char* v = std::getenv(name);
+  return v ? std::atoi(v) : dflt;
+}
+
 // ---------------------------------------------------------------- failure injection (tests)
 // LSX_TEST_FAIL_ALLOC=k makes the k-th device allocation counted from when the variable was
 // set (or last changed) report LSX_E_OOM; LSX_TEST_FAIL_EIG=1 makes the fibre eigensolver
@@ -603,6 +608,12 @@ struct LayerDev {
   std::vector<int32_t> h_d0;    // fibre position of each fibre's diagonal (its representative's)
   std::vector<int32_t> rep;     // distinct-propagator slot of each fibre
   int nunique = 0;
+  // The plan's order of the layer's rows (fibre position -> canonical index): the system's
+  // fibres with their rows ascending, except that a fibre sharing its representative's
+  // propagator through a point symmetry lists the images of the representative's rows.
+  std::vector<int32_t> h_rows;
+  std::vector<int32_t> sym_rep;  // representative fibre under the point symmetries (empty: none)
+  bool ident = false;            // h_rows is the identity (the canonical order)
   DBuf<int32_t> ptr, rows;
   DBuf<int32_t> nbr;
   DBuf<double2> v;  // stencil values (for the energy)
@@ -616,25 +627,30 @@ struct lsx_plan {
   DBuf<double> K2;
   DBuf<double2> diag;  // mixed formats: per fibre-row diagonal, [layer*3+slot] blocks of N
   DBuf<double2> phase[3];  // exp(-i kappa t |K|^2/2) for the scheme's phase times
-  // pos[j]: position of canonical index i in the layer-(j+1) fibre order (j < nl - 1; the
-  // last layer's order is canonical); xmap[j][k]: layer-(j+1) fibre position -> layer-(k+1)
-  // fibre position, for j != k both below nl - 1 (three layers)
-  DBuf<int32_t> pos[kMaxLayers - 1];
-  DBuf<int32_t> xmap[kMaxLayers - 1][kMaxLayers - 1];
+  // pos[j]: position of canonical index i in the layer-(j+1) fibre order; xmap[j][k]:
+  // layer-(j+1) fibre position -> layer-(k+1) fibre position.  Held for the layers whose order
+  // is not the canonical one (every layer but the last, and the last too when point symmetries
+  // reorder its fibres).
+  DBuf<int32_t> pos[kMaxLayers];
+  DBuf<int32_t> xmap[kMaxLayers][kMaxLayers];
+  DBuf<int32_t> iota;  // identity table (batched gathers over systems whose table is the identity)
+  int nsym = 0;        // point symmetries the propagators are shared over (identity excluded)
   DBuf<double2> zero;  // 1 KiB of zeros (out-of-range operand loads of the passes)
   LayerDev L[kMaxLayers];
   int nstates = 0;
   int max_w = 0;  // states with more wavepackets are refused (0: no limit)
 };
 
-// Index table of layer `layer`'s fibre positions inside an array of layout `layout` (layout j:
-// layer-j fibre order; layout nl: canonical order, in which the last layer's fibres are
-// contiguous runs); nullptr when the two coincide.
+// Index table of layer `layer`'s fibre positions inside an array of layout `layout` (layout 0:
+// canonical order; layout j: layer-j fibre order); nullptr when the two coincide.  Without
+// point-symmetry sharing the last layer's fibres are contiguous runs of the canonical order,
+// so layouts 0 and nl coincide.
 static const int32_t* layout_map(const lsx_plan* pl, int layer, int layout) {
-  const int nl = pl->sys->nl;
   if (layout == layer) return nullptr;
-  if (layout == nl) return pl->L[layer - 1].rows.p;  // fibre position -> canonical index
-  if (layer == nl) return pl->pos[layout - 1].p;     // canonical index -> fibre position
+  const LayerDev& ld = pl->L[layer - 1];
+  if (layout == 0) return ld.ident ? nullptr : ld.rows.p;  // fibre position -> canonical index
+  if (pl->L[layout - 1].ident) return ld.rows.p;             // that layout is the canonical order
+  if (ld.ident) return pl->pos[layout - 1].p;                // canonical index -> fibre position
   return pl->xmap[layer - 1][layout - 1].p;
 }
 
@@ -684,6 +700,175 @@ static SchemeTimes scheme_times(int scheme, double tau, int nl) {
   return {{{tau, X, X}, {tau, X, X}, {X, X, X}}, {tau, X, X}};
 }
 
+// ---------------------------------------------------------------- point symmetries
+// A rotation R of the plane (in 1D, x -> -x) is a symmetry of a lattice-built system when, for
+// every layer j, it maps the reciprocal lattice onto itself, R B_j = B_j M_j with M_j an integer
+// matrix, keeps the layer's potential (its coefficient at M_j m equals the one at m) and maps
+// the lifted index set onto itself (the cutoff depends on |G_j m_j| only).  The lifted
+// wavevector K = sum_j B_j m_j then goes to R K, |K|^2 is unchanged, and the fibre Hamiltonian
+// H_j (eq. 3.6, with its kinetic share) at the fibre whose fixed indices are (M_k m_k)_{k != j}
+// is the one at (m_k)_{k != j} with every row (m_j, ...) relabelled (M_j m_j, ...).  So the
+// fibres of an orbit have permuted copies of one Hamiltonian, and every function of it (exact
+// flow, backward Euler or Crank-Nicolson factor) is the same permuted copy.  Ordering each
+// fibre's rows as the images of its representative's rows makes the stored propagators equal.
+struct PointSym {
+  int32_t M[kMaxLayers][4];  // d x d integer matrix per layer, row-major
+};
+
+static std::vector<PointSym> find_point_symmetries(const lsx_system* sys) {
+  std::vector<PointSym> out;
+  if (!sys->standard || sys->N == 0) return out;
+  const int d = sys->d, nl = sys->nl;
+  std::vector<std::vector<double>> Rs;
+  if (d == 1) {
+    Rs.push_back({-1.0});
+  } else {
+    for (int k = 1; k < 12; ++k) {
+      const double th = 2.0 * M_PI * k / 12.0;
+      Rs.push_back({std::cos(th), -std::sin(th), std::sin(th), std::cos(th)});
+    }
+  }
+  std::unordered_map<uint64_t, int32_t> where;
+  const int S = sys->S;
+  for (const auto& R : Rs) {
+    PointSym g{};
+    bool ok = true;
+    for (int j = 0; j < nl && ok; ++j) {
+      // M = B^{-1} R B with B row-major (columns: reciprocal primitive vectors)
+      const double* B = sys->B[j];
+      double Bi[4];
+      if (d == 1) {
+        Bi[0] = 1.0 / B[0];
+      } else {
+        const double det = B[0] * B[3] - B[1] * B[2];
+        Bi[0] = B[3] / det;
+        Bi[1] = -B[1] / det;
+        Bi[2] = -B[2] / det;
+        Bi[3] = B[0] / det;
+      }
+      for (int r = 0; r < d && ok; ++r)
+        for (int c = 0; c < d && ok; ++c) {
+          double x = 0.0;
+          for (int a = 0; a < d; ++a)
+            for (int b = 0; b < d; ++b) x += Bi[r * d + a] * R[a * d + b] * B[b * d + c];
+          const double xr = std::nearbyint(x);
+          if (std::fabs(x - xr) > 1e-9) ok = false;
+          g.M[j][r * d + c] = (int32_t)xr;
+        }
+      // the potential's coefficients are permuted among themselves with equal values
+      const Stencil& st = sys->pot[j];
+      double vmax = 0.0;
+      for (int e = 0; e < st.nv; ++e) vmax = std::max(vmax, std::hypot(st.re[e], st.im[e]));
+      for (int e = 0; e < st.nv && ok; ++e) {
+        int32_t im[2];
+        for (int r = 0; r < d; ++r) {
+          int64_t acc = 0;
+          for (int c = 0; c < d; ++c) acc += (int64_t)g.M[j][r * d + c] * st.idx[(size_t)e * d + c];
+          im[r] = (int32_t)acc;
+        }
+        int f = -1;
+        for (int e2 = 0; e2 < st.nv && f < 0; ++e2) {
+          bool same = true;
+          for (int r = 0; r < d; ++r) same = same && st.idx[(size_t)e2 * d + r] == im[r];
+          if (same) f = e2;
+        }
+        if (f < 0 || std::fabs(st.re[f] - st.re[e]) > 1e-14 * vmax || std::fabs(st.im[f] - st.im[e]) > 1e-14 * vmax)
+          ok = false;
+      }
+    }
+    if (!ok) continue;
+    // the lifted index set maps onto itself
+    if (where.empty())
+      for (int64_t i = 0; i < sys->N; ++i) where[pack_key(&sys->mn[i * S], S)] = (int32_t)i;
+    int32_t img[kMaxIndex];
+    for (int64_t i = 0; i < sys->N && ok; ++i) {
+      const int32_t* m = &sys->mn[i * S];
+      for (int j = 0; j < nl; ++j)
+        for (int r = 0; r < d; ++r) {
+          int64_t acc = 0;
+          for (int c = 0; c < d; ++c) acc += (int64_t)g.M[j][r * d + c] * m[j * d + c];
+          if (std::llabs(acc) > (S <= 4 ? 32767 : 511)) ok = false;
+          img[j * d + r] = (int32_t)acc;
+        }
+      ok = ok && where.count(pack_key(img, S)) > 0;
+    }
+    if (ok) out.push_back(g);
+  }
+  return out;
+}
+
+extern "C" lsx_status lsx_system_symmetries(const lsx_system* sys, int32_t* nsym, int32_t* M) {
+  if (!sys || !nsym) return fail(LSX_E_INVALID, "null argument");
+  const std::vector<PointSym> g = find_point_symmetries(sys);
+  *nsym = (int32_t)g.size();
+  if (M) {
+    const int d = sys->d, nl = sys->nl;
+    for (size_t e = 0; e < g.size(); ++e)
+      for (int j = 0; j < nl; ++j)
+        for (int k = 0; k < d * d; ++k) M[(e * nl + j) * d * d + k] = g[e].M[j][k];
+  }
+  return LSX_OK;
+}
+
+// The plan's row order of every layer and, with point symmetries, each fibre's representative.
+static void plan_orders(lsx_plan* pl, bool use_sym) {
+  const lsx_system* sys = pl->sys;
+  const int nl = sys->nl, d = sys->d, S = sys->S;
+  std::vector<PointSym> syms;
+  if (use_sym) syms = find_point_symmetries(sys);
+  pl->nsym = (int)syms.size();
+  std::unordered_map<uint64_t, int32_t> where;
+  if (!syms.empty())
+    for (int64_t i = 0; i < sys->N; ++i) where[pack_key(&sys->mn[i * S], S)] = (int32_t)i;
+  for (int j = 0; j < nl; ++j) {
+    LayerDev& ld = pl->L[j];
+    const FibreTable& ft = sys->fib[j];
+    const int nf = (int)ft.ptr.size() - 1;
+    ld.h_rows = ft.rows;
+    ld.sym_rep.clear();
+    if (!syms.empty()) {
+      // fibre of every canonical row
+      std::vector<int32_t> fib((size_t)sys->N);
+      for (int f = 0; f < nf; ++f)
+        for (int a = ft.ptr[f]; a < ft.ptr[f + 1]; ++a) fib[ft.rows[a]] = f;
+      ld.sym_rep.assign(nf, -1);
+      int32_t img[kMaxIndex];
+      for (int f = 0; f < nf; ++f) {
+        if (ld.sym_rep[f] >= 0) continue;
+        ld.sym_rep[f] = f;
+        const int r0 = ft.ptr[f], L = ft.ptr[f + 1] - r0;
+        for (const PointSym& g : syms) {
+          // image of the fibre's first row decides the image fibre
+          auto image = [&](int32_t row) {
+            const int32_t* m = &sys->mn[(size_t)row * S];
+            for (int k = 0; k < nl; ++k)
+              for (int r = 0; r < d; ++r) {
+                int64_t acc = 0;
+                for (int c = 0; c < d; ++c) acc += (int64_t)g.M[k][r * d + c] * m[k * d + c];
+                img[k * d + r] = (int32_t)acc;
+              }
+            return where.at(pack_key(img, S));
+          };
+          const int f2 = fib[image(ft.rows[r0])];
+          if (ld.sym_rep[f2] >= 0) continue;
+          if (ft.ptr[f2 + 1] - ft.ptr[f2] != L) continue;  // cannot happen for a symmetry
+          bool same_fibre = true;
+          std::vector<int32_t> rows(L);
+          for (int a = 0; a < L; ++a) {
+            rows[a] = image(ft.rows[r0 + a]);
+            same_fibre = same_fibre && fib[rows[a]] == f2;
+          }
+          if (!same_fibre) continue;
+          ld.sym_rep[f2] = f;
+          std::copy(rows.begin(), rows.end(), ld.h_rows.begin() + ft.ptr[f2]);
+        }
+      }
+    }
+    ld.ident = true;
+    for (int64_t p = 0; p < sys->N && ld.ident; ++p) ld.ident = ld.h_rows[p] == (int32_t)p;
+  }
+}
+
 static lsx_status precompute_layer(lsx_plan* pl, int layer, hipStream_t s) {
   lsx_system* sys = pl->sys;
   LayerDev& ld = pl->L[layer - 1];
@@ -716,6 +901,17 @@ static lsx_status precompute_layer(lsx_plan* pl, int layer, hipStream_t s) {
       } else {
         ld.rep[f] = it->second;
       }
+    }
+  } else if (!ld.sym_rep.empty()) {
+    // fibres of one point-symmetry orbit share their representative's propagator
+    std::vector<int32_t> slot(nf, -1);
+    for (int f = 0; f < nf; ++f) {
+      const int r = ld.sym_rep[f];
+      if (slot[r] < 0) {
+        slot[r] = (int)uniq.size();
+        uniq.push_back(r);
+      }
+      ld.rep[f] = slot[r];
     }
   } else {
     for (int f = 0; f < nf; ++f) {
@@ -841,6 +1037,9 @@ extern "C" lsx_status lsx_plan_create(lsx_system* sys, double tau, int32_t schem
     if (st != LSX_OK) return cleanup(st);
   }
   const int nl = sys->nl;
+  // window sharing (kappa = 1) and point-symmetry sharing are alternatives: at kappa = 1 the
+  // translation-invariant windows already share more; LSX_SYMMETRY=0 turns the latter off
+  plan_orders(pl, kappa != 1.0 && env_int("LSX_SYMMETRY", 1) != 0);
   for (int j = 0; j < nl; ++j) {
     LayerDev& ld = pl->L[j];
     const FibreTable& ft = sys->fib[j];
@@ -848,29 +1047,28 @@ extern "C" lsx_status lsx_plan_create(lsx_system* sys, double tau, int32_t schem
     ld.maxL = ft.maxL;
     ld.h_ptr = ft.ptr;
     if ((st = ld.ptr.upload(ft.ptr, s)) != LSX_OK) return cleanup(st);
-    if ((st = ld.rows.upload(ft.rows, s)) != LSX_OK) return cleanup(st);
+    if ((st = ld.rows.upload(ld.h_rows, s)) != LSX_OK) return cleanup(st);
     if ((st = ld.nbr.upload(sys->nbr[j], s)) != LSX_OK) return cleanup(st);
     std::vector<double2> v(sys->pot[j].nv);
     for (int p = 0; p < sys->pot[j].nv; ++p) v[p] = make_double2(sys->pot[j].re[p], sys->pot[j].im[p]);
     if ((st = ld.v.upload(v, s)) != LSX_OK) return cleanup(st);
   }
   {
-    // the last layer's fibres are contiguous runs of the canonical order; the passes rely
-    // on it to read and write that layout without an index table
-    const FibreTable& fl = sys->fib[nl - 1];
-    for (int64_t i = 0; i < sys->N; ++i)
-      if (fl.rows[i] != (int32_t)i) return cleanup(fail(LSX_E_STATE, "internal: last-layer fibre order"));
+    // position tables between the layers' orders and the canonical order; a layer whose order
+    // is the canonical one (the last layer, unless point symmetries reorder it) needs none
     const size_t n1 = (size_t)std::max<int64_t>(sys->N, 1);
-    std::vector<std::vector<int32_t>> pos(nl - 1, std::vector<int32_t>(n1, 0));
-    for (int j = 0; j + 1 < nl; ++j) {
-      for (int64_t p = 0; p < sys->N; ++p) pos[j][sys->fib[j].rows[p]] = (int32_t)p;
+    std::vector<std::vector<int32_t>> pos(nl);
+    for (int j = 0; j < nl; ++j) {
+      if (pl->L[j].ident) continue;
+      pos[j].assign(n1, 0);
+      for (int64_t p = 0; p < sys->N; ++p) pos[j][pl->L[j].h_rows[p]] = (int32_t)p;
       if ((st = pl->pos[j].upload(pos[j], s)) != LSX_OK) return cleanup(st);
     }
-    for (int j = 0; j + 1 < nl; ++j)
-      for (int k = 0; k + 1 < nl; ++k) {
-        if (j == k) continue;
+    for (int j = 0; j < nl; ++j)
+      for (int k = 0; k < nl; ++k) {
+        if (j == k || pl->L[j].ident || pl->L[k].ident) continue;
         std::vector<int32_t> x(n1, 0);
-        for (int64_t p = 0; p < sys->N; ++p) x[p] = pos[k][sys->fib[j].rows[p]];
+        for (int64_t p = 0; p < sys->N; ++p) x[p] = pos[k][pl->L[j].h_rows[p]];
         if ((st = pl->xmap[j][k].upload(x, s)) != LSX_OK) return cleanup(st);
       }
     if ((st = pl->zero.upload(std::vector<double2>(64, make_double2(0.0, 0.0)), s)) != LSX_OK) return cleanup(st);
@@ -926,6 +1124,15 @@ extern "C" lsx_status lsx_plan_propagator(const lsx_plan* pl, int32_t layer, int
     LSX_HIP_TRY(hipMemcpyAsync(dg.data(), src, L * sizeof(double2), hipMemcpyDeviceToHost, s));
   }
   LSX_HIP_TRY(hipStreamSynchronize(s));
+  // row a of the stored propagator (the plan's order) is row sg[a] of the fibre in the system's
+  // order (rows ascending)
+  std::vector<int> sg(L);
+  {
+    const int r0 = ld.h_ptr[fibre];
+    const std::vector<int32_t>& sr = pl->sys->fib[layer - 1].rows;
+    for (int a = 0; a < L; ++a)
+      sg[a] = (int)(std::lower_bound(sr.begin() + r0, sr.begin() + r0 + L, ld.h_rows[r0 + a]) - (sr.begin() + r0));
+  }
   auto bf = [](uint16_t h) {
     uint32_t u = (uint32_t)h << 16;
     float f;
@@ -962,9 +1169,17 @@ extern "C" lsx_status lsx_plan_propagator(const lsx_plan* pl, int32_t layer, int
         re = dg[a].x;
         im = dg[a].y;
       }
-      out[2 * ((int64_t)a * L + b)] = re;
-      out[2 * ((int64_t)a * L + b) + 1] = im;
+      out[2 * ((int64_t)sg[a] * L + sg[b])] = re;
+      out[2 * ((int64_t)sg[a] * L + sg[b]) + 1] = im;
     }
+  return LSX_OK;
+}
+
+extern "C" lsx_status lsx_plan_sharing(const lsx_plan* pl, int32_t layer, int32_t* ndistinct, int32_t* nsym) {
+  if (!pl) return fail(LSX_E_INVALID, "null plan");
+  if (layer < 1 || layer > pl->sys->nl) return fail(LSX_E_INVALID, "layer out of range");
+  if (ndistinct) *ndistinct = pl->L[layer - 1].nunique;
+  if (nsym) *nsym = pl->nsym;
   return LSX_OK;
 }
 
@@ -1002,7 +1217,6 @@ struct lsx_state {
   int nsamplers = 0;                   // samplers that reference this state
 };
 
-static int env_int(const char* name, int dflt);
 
 // Tile order of one fibre pass.  Workgroup i of a launch runs on XCD i % 8, and each
 // XCD has its own L2, so whole fibres are assigned to XCDs (longest first, to the
@@ -1055,10 +1269,6 @@ static void build_tiles(const lsx_plan* pl, int layer, int W, int nb, int wb0, i
   while (!out.empty() && out.back().f < 0) out.pop_back();
 }
 
-static int env_int(const char* name, int dflt) {
-  const char* v = std::getenv(name);
-  return v ? std::atoi(v) : dflt;
-}
 
 // Store mode of the pass outputs, prefetch depth and tile shape, in the setting of a step.  A
 // step's passes each read the previous pass's output in their own layer's fibre order, written
@@ -1515,13 +1725,12 @@ struct Runner {
     if (!ps.present) return fail(LSX_E_INVALID, "plan holds no propagator for this layer/slot");
     if (phase_half >= 0 && pl->kappa != 0.0 && !pl->phase[phase_half].p)
       return fail(LSX_E_INVALID, "plan holds no phase table for this slot");
-    const int nl = pl->sys->nl;
-    const int outlay = (next == 0) ? nl : next;
+    const int outlay = next;  // 0: canonical order
     PassArgs a;
     a.tiles = st->tiles[layer - 1].p;
-    a.in_pos = table(layer, lay == 0 ? nl : lay);
+    a.in_pos = table(layer, lay);
     a.out_pos = table(layer, outlay);
-    a.ph_idx = table(layer, nl);
+    a.ph_idx = table(layer, 0);
     a.ph = (phase_half >= 0 && pl->kappa != 0.0) ? pl->phase[phase_half].p : nullptr;
     a.P = ps.data.p;
     a.diag = pl->diag.p ? pl->diag.p + (size_t)((layer - 1) * 3 + half) * pl->sys->N : nullptr;
@@ -1809,7 +2018,9 @@ struct lsx_batch {
   int ntiles[kMaxLayers] = {0, 0, 0};
   int nb[kMaxLayers] = {1, 1, 1}, ks[kMaxLayers] = {2, 2, 2};
   float tuned_us[kMaxLayers] = {0.f, 0.f, 0.f};
-  std::map<PatternKey, std::unique_ptr<DBuf<PassArgs>>> args;
+  // per pass pattern: the systems' argument array, and whether any system gathers its input
+  // through an index table (then the launch uses the gathering kernel for every system)
+  std::map<PatternKey, std::pair<std::unique_ptr<DBuf<PassArgs>>, bool>> args;
   std::vector<std::pair<double2*, double2*>> bufs;  // buffers the argument arrays refer to
   DBuf<int32_t> marker;                              // non-null in_pos marker for gathering passes
   DBuf<int32_t> queue;                               // persistent launches: 9 counters, zero between launches
@@ -1839,12 +2050,14 @@ static void batch_drop_graph(lsx_batch* b) {
 }
 
 // per-system argument array of one pass pattern (built once, kept on the device)
-static lsx_status batch_args(lsx_batch* b, const PatternKey& k, const PassArgs** out) {
+static lsx_status batch_args(lsx_batch* b, const PatternKey& k, const PassArgs** out, bool* gather = nullptr) {
   auto it = b->args.find(k);
   if (it == b->args.end()) {
     std::vector<PassArgs> v(b->pl.size());
+    bool any = false;
+    for (size_t i = 0; i < b->pl.size(); ++i) any = any || layout_table(b->pl[i], k.layer, k.inlay) != nullptr;
     for (size_t i = 0; i < b->pl.size(); ++i) {
-      const lsx_plan* pl = b->pl[i];
+      lsx_plan* pl = b->pl[i];
       const lsx_state* st = b->st[i];
       const LayerDev& ld = pl->L[k.layer - 1];
       const PropSet& ps = ld.prop[k.half];
@@ -1852,8 +2065,17 @@ static lsx_status batch_args(lsx_batch* b, const PatternKey& k, const PassArgs**
       PassArgs& a = v[i];
       a.tiles = nullptr;
       a.in_pos = layout_table(pl, k.layer, k.inlay);
+      if (any && !a.in_pos) {
+        // the gathering kernel runs for the whole batch: this system gathers through the identity
+        if (!pl->iota.p) {
+          std::vector<int32_t> id((size_t)std::max<int64_t>(pl->sys->N, 1));
+          std::iota(id.begin(), id.end(), 0);
+          LSX_TRY(pl->iota.upload(id, nullptr));
+        }
+        a.in_pos = pl->iota.p;
+      }
       a.out_pos = layout_table(pl, k.layer, k.outlay);
-      a.ph_idx = layout_map(pl, k.layer, pl->sys->nl);
+      a.ph_idx = layout_map(pl, k.layer, 0);
       a.ph = (k.phase_half >= 0 && pl->kappa != 0.0) ? pl->phase[k.phase_half].p : nullptr;
       a.P = ps.data.p;
       a.diag = pl->diag.p ? pl->diag.p + (size_t)((k.layer - 1) * 3 + k.half) * pl->sys->N : nullptr;
@@ -1867,9 +2089,10 @@ static lsx_status batch_args(lsx_batch* b, const PatternKey& k, const PassArgs**
     auto d = std::make_unique<DBuf<PassArgs>>();
     LSX_TRY(d->alloc(v.size()));
     LSX_HIP_TRY(hipMemcpy(d->p, v.data(), v.size() * sizeof(PassArgs), hipMemcpyHostToDevice));
-    it = b->args.emplace(k, std::move(d)).first;
+    it = b->args.emplace(k, std::make_pair(std::move(d), any)).first;
   }
-  *out = it->second->p;
+  *out = it->second.first->p;
+  if (gather) *gather = it->second.second;
   return LSX_OK;
 }
 
@@ -1924,13 +2147,14 @@ static void batch_tiles(const lsx_batch* b, int layer, int nb, std::vector<TileD
 
 // Launches one batched pass; (cur, lay) follow the same rules as Runner.
 static lsx_status batch_pass(lsx_batch* b, hipStream_t s, const PassSpec& p, int& cur, int& lay) {
-  const int outlay = (p.next == 0) ? b->nl : p.next;
+  const int outlay = p.next;  // 0: canonical order
   const PatternKey k{p.layer, p.half, lay, outlay, p.phase_half, cur};
   const PassArgs* d = nullptr;
-  LSX_TRY(batch_args(b, k, &d));
+  bool gather = false;
+  LSX_TRY(batch_args(b, k, &d, &gather));
   PassArgs a0{};
   a0.tiles = b->tiles[p.layer - 1].p;
-  a0.in_pos = (lay == p.layer) ? nullptr : b->marker.p;  // gather flag, uniform over the batch
+  a0.in_pos = gather ? b->marker.p : nullptr;  // gather flag, uniform over the batch
   a0.batch = d;
   a0.persist = b->persist[p.layer - 1];
   a0.queue = b->queue.p;
@@ -2116,8 +2340,7 @@ extern "C" lsx_status lsx_batch_step(lsx_batch* b, int64_t nsteps, void* stream)
   std::vector<PassSpec> head, body, tail;
   int64_t reps = 0;
   step_sequence(b->scheme, b->nl, nsteps, head, body, tail, reps);
-  const int nl = b->nl;
-  int cur = 0, lay = nl;
+  int cur = 0, lay = 0;  // canonical order
   for (const PassSpec& p : head) LSX_TRY(batch_pass(b, s, p, cur, lay));
   // The captured body must return to the (array, layout) state it starts from, so a body with
   // an odd number of passes (three-layer Lie) is captured twice over; an odd repetition left
@@ -2141,7 +2364,7 @@ extern "C" lsx_status lsx_batch_step(lsx_batch* b, int64_t nsteps, void* stream)
         // build every argument array first: capture must not do synchronous copies
         int c2 = cur, l2 = lay;
         for (const PassSpec& p : gbody) {
-          const int outlay = (p.next == 0) ? nl : p.next;
+          const int outlay = p.next;
           const PassArgs* d = nullptr;
           LSX_TRY(batch_args(b, PatternKey{p.layer, p.half, l2, outlay, p.phase_half, c2}, &d));
           c2 ^= 1;
@@ -2478,7 +2701,7 @@ extern "C" lsx_status lsx_sampler_destroy(lsx_sampler* sm) {
 
 namespace {
 // canonical-layout position table of a layer's fibre positions (null: identity)
-const int32_t* canon_pos(const lsx_plan* pl, int layer) { return layer == 1 ? pl->L[0].rows.p : nullptr; }
+const int32_t* canon_pos(const lsx_plan* pl, int layer) { return layout_map(pl, layer, 0); }
 
 PassArgs canon_pass_args(const lsx_plan* pl, const lsx_state* st, int layer, int half) {
   const LayerDev& ld = pl->L[layer - 1];

@@ -89,6 +89,8 @@ _SIGS = {
                                      C.c_double, C.c_double, _p, _p]),
     "lsx_mlp_destroy": (C.c_int, [_p]),
     "lsx_live_buffers": (C.c_int, [_i64p, _i64p]),
+    "lsx_plan_sharing": (C.c_int, [_p, C.c_int32, _i32p, _i32p]),
+    "lsx_system_symmetries": (C.c_int, [_p, _i32p, _i32p]),
     "lsx_observables_noalloc": (C.c_int, [_p, _p, C.c_int32, C.c_uint32, _p, _p]),
     "lsx_state_set_tuning": (C.c_int, [_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
     "lsx_state_set_store_mode": (C.c_int, [_p, C.c_int32]),
@@ -293,6 +295,14 @@ class System:
         self._finish(h)
         return self
 
+    def symmetries(self):
+        """Integer matrices M [nsym, nlayers, d, d] of the system's point symmetries."""
+        n = C.c_int32()
+        _check(lib().lsx_system_symmetries(self.h, C.byref(n), None))
+        M = np.zeros((n.value, self.nlayers, self.d, self.d), dtype=np.int32)
+        _check(lib().lsx_system_symmetries(self.h, C.byref(n), M.ctypes.data_as(_i32p)))
+        return M
+
     def index_size(self):
         """|I| through lsx_index_size."""
         n = C.c_int64()
@@ -339,6 +349,12 @@ class Plan:
             desc = PlanDesc(self.tau, SCHEME[scheme], self.kappa, PRECISION[precision], int(max_wavepackets))
             _check(lib().lsx_plan_create_desc(system.h, C.byref(desc), _stream(stream), C.byref(h)))
         self.h = h
+
+    def sharing(self, layer):
+        """(distinct propagators stored for `layer`, point symmetries shared over)."""
+        nd, ns = C.c_int32(), C.c_int32()
+        _check(lib().lsx_plan_sharing(self.h, int(layer), C.byref(nd), C.byref(ns)))
+        return nd.value, ns.value
 
     def propagator(self, layer, half, fibre, stream=None):
         ptr, _ = self.system.fibres(layer)

@@ -227,3 +227,82 @@ def test_descriptor_form_equals_flat_arguments(spec):
     assert L.lsx_state_wrap(None, 4, None, None) == lsx.LSX_E_INVALID
     assert L.lsx_state_set_tuning(None, 1, 1, 2, 0) == lsx.LSX_E_INVALID
     assert L.lsx_state_set_store_mode(None, 0) == lsx.LSX_E_INVALID
+
+
+ASYM1 = {(1,): 0.6 + 0.45j, (-1,): 0.6 - 0.45j}
+
+
+@pytest.mark.parametrize("spec,expect", [(wl.chain_system(2.0e4), 1), (wl.chain_system(500.0, L2=1.5), 1),
+                                         (wl.twisted_system(300.0), 5), (wl.twisted_system(300.0, cutoff="product"), 5),
+                                         (wl.twisted_system(600.0, theta_deg=3.0), 5),
+                                         (wl.chain_system(971.0, pot1=ASYM1), 0)],
+                         ids=["chain", "commensurate", "twisted", "product2d", "twist3", "complex-odd"])
+def test_point_symmetries_map_the_oracle_system_onto_itself(spec, expect):
+    """Every point symmetry the library reports (integer M_j per layer) maps the oracle's lifted
+    index set onto itself, keeps every potential coefficient and |K|^2 (Secs. 2-3), and
+    together with the identity the symmetries form a group.  Triangular lattices give the five
+    non-trivial rotations by multiples of 60 degrees, 1D chains x -> -x, and a potential that
+    is not even (complex coefficients) none."""
+    S = lsx.System.from_spec(spec)
+    try:
+        M = S.symmetries()
+    finally:
+        S.destroy()
+    assert M.shape[0] == expect
+    d = spec.d
+    mn = lifted.index_set(spec.A1, spec.A2, spec.Ec, spec.cutoff)
+    K = lifted.lifted_wavevectors(spec.A1, spec.A2, mn)
+    K2 = (K * K).sum(axis=1)
+    keys = {tuple(r): i for i, r in enumerate(mn.tolist())}
+    mats = [np.eye(d, dtype=np.int64)[None].repeat(2, 0)] + [M[e].astype(np.int64) for e in range(M.shape[0])]
+    for Mg in mats[1:]:
+        img = np.concatenate([mn[:, :d] @ Mg[0].T, mn[:, d:] @ Mg[1].T], axis=1)
+        idx = np.array([keys.get(tuple(r), -1) for r in img.tolist()])
+        assert np.all(idx >= 0) and len(set(idx.tolist())) == len(mn)
+        assert np.allclose(K2[idx], K2, rtol=1e-12, atol=1e-9)
+        for pot, Mj in ((spec.pot1, Mg[0]), (spec.pot2, Mg[1])):
+            for m, v in pot.items():
+                im = tuple(int(x) for x in Mj @ np.array(m))
+                assert im in pot and abs(pot[im] - v) <= 1e-14 * max(abs(x) for x in pot.values())
+    # closure: the product of two symmetries is the identity or another reported symmetry
+    as_key = [tuple(Mg.ravel().tolist()) for Mg in mats]
+    for A in mats:
+        for B in mats:
+            assert tuple(np.einsum("jab,jbc->jac", A, B).ravel().tolist()) in as_key
+
+
+def test_point_symmetry_permutes_oracle_fibre_propagators():
+    """The reading behind propagator sharing, checked on the oracle alone: for a symmetry
+    (M_1, M_2), the layer-j fibre with fixed index M_k m_k has the fibre Hamiltonian of the
+    fibre with fixed m_k with rows relabelled m_j -> M_j m_j (eq. 3.6), so its exact propagator
+    is the same matrix permuted, for every kinetic share."""
+    from oracle import splitting
+    spec = wl.twisted_system(300.0)
+    S = lsx.System.from_spec(spec)
+    try:
+        M = S.symmetries().astype(np.int64)
+    finally:
+        S.destroy()
+    O = splitting.Lifted.from_spec(spec)
+    d = spec.d
+    keys = {tuple(r): i for i, r in enumerate(O.mn.tolist())}
+    for kappa in (0.0, 0.5):
+        plan = splitting.SplitPlan(O, kappa)
+        for layer in (1, 2):
+            props = plan.propagators(layer, 0.013)
+            fib_of = {}
+            for f, (_, rows) in enumerate(O.fib[layer]):
+                for r in rows:
+                    fib_of[int(r)] = f
+            for f in (0, len(O.fib[layer]) // 3, len(O.fib[layer]) // 2):
+                rows = O.fib[layer][f][1]
+                for Mg in M:
+                    img = np.concatenate([O.mn[rows, :d] @ Mg[0].T, O.mn[rows, d:] @ Mg[1].T], axis=1)
+                    irows = np.array([keys[tuple(r)] for r in img.tolist()])
+                    f2 = fib_of[int(irows[0])]
+                    r2 = O.fib[layer][f2][1]
+                    assert sorted(irows.tolist()) == r2.tolist()
+                    pos = {int(r): a for a, r in enumerate(r2)}
+                    perm = np.array([pos[int(r)] for r in irows])
+                    P2 = props[f2][np.ix_(perm, perm)]
+                    assert np.abs(P2 - props[f]).max() < 1e-13
