@@ -481,6 +481,7 @@ def time_paths(S, w, c0, paths, scheme, kappa, steps, warmup, reps, stream):
         st.upload(c0, stream)
         st.step(w.nsteps, stream)
         finals[path] = st.download(stream)
+        moved = float((np.linalg.norm(finals[path] - c0, axis=0) / np.linalg.norm(c0, axis=0)).max())
         # timed run
         st.upload(c0, stream)
         st.step(warmup, stream)
@@ -518,12 +519,12 @@ def time_paths(S, w, c0, paths, scheme, kappa, steps, warmup, reps, stream):
                      "wall_ms": wall * 1e3, "precompute_s": pre, "layer2_pass_us": kus, "layer1_pass_us": kus1,
                      "tiles": {"layer1": st.tuning(1)[:2] + (st.prefetch(1),),
                                "layer2": st.tuning(2)[:2] + (st.prefetch(2),)},
-                     "nontemporal_stores": st.store_mode()[0]}
+                     "nontemporal_stores": st.store_mode()[0], "rel_change_after_T": moved}
         if phase_us is not None:
             res[path]["phase_us"] = phase_us
             res[path]["phase_GBps"] = (2.0 * N * W * 16 + 16.0 * N) / (phase_us * 1e-6) / 1e9
-        print(f"[bench] N={N} W={W} {path}: precompute {pre:.2f} s, {ms / steps * 1e3:.1f} us/step", file=sys.stderr,
-              flush=True)
+        print(f"[bench] N={N} W={W} {path}: precompute {pre:.2f} s, {ms / steps * 1e3:.1f} us/step, "
+              f"relative change after T {moved:.3f}", file=sys.stderr, flush=True)
         st.destroy()
         P.destroy()
     ref = finals.get("fp64")
@@ -548,7 +549,8 @@ def config3_summary(args, stream):
     out = {"workload": "twisted_tri_pm2.5deg_Ec6500_W128_strang_tau5e-3", "N": S.N, "W": w.W,
            "steps_to_T": w.nsteps, "timed_steps": args.config3_steps, "paths": {}}
     for path, r in res.items():
-        q = {k: r[k] for k in ("ms_per_step", "coeff_steps_per_s", "rel_l2_vs_fp64_after_T", "precompute_s",
+        q = {k: r[k] for k in ("ms_per_step", "coeff_steps_per_s", "rel_l2_vs_fp64_after_T", "rel_change_after_T",
+                               "precompute_s",
                                "layer1_pass_us", "layer2_pass_us", "tiles", "nontemporal_stores")}
         for j in (1, 2):
             tf = 8.0 * w.W * sumL2[j] / (r[f"layer{j}_pass_us"] * 1e-6)
