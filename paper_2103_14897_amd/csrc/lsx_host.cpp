@@ -869,6 +869,77 @@ static void plan_orders(lsx_plan* pl, bool use_sym) {
   }
 }
 
+// Fibres longer than this many rows (after the complex embedding) take the blocked solver.
+static constexpr int kBlockedMin = 96;
+
+// Blocked two-sided Jacobi (see lsx_kernels.hip) of the matrices `sel` of a precompute batch:
+// sweeps of round-robin block rounds until a sweep rotates nothing, at most maxsweeps; the
+// matrices that converge drop out after each sweep.  info[m] receives the sweeps of matrix m,
+// or -1 without convergence.
+static lsx_status block_jacobi(hipStream_t s, const std::vector<int32_t>& sel, const std::vector<int32_t>& ndim,
+                               double* A, double* VT, const int64_t* d_moff, const int32_t* d_ndim, double* lam,
+                               const int64_t* d_loff, int maxsweeps, std::vector<int32_t>& info) {
+  const int nm = (int)ndim.size();
+  std::vector<int32_t> act(sel);
+  std::stable_sort(act.begin(), act.end(), [&](int x, int y) { return ndim[x] > ndim[y]; });
+  int64_t qsize = 0;
+  for (int m : act) qsize += (int64_t)(ndim[m] / 32) * 1024;
+  DBuf<int32_t> d_sel, d_mat, d_pp, d_pt, d_flag;
+  DBuf<double> d_tiny, d_Q;
+  LSX_TRY(d_sel.upload(sel, s));
+  LSX_TRY(d_tiny.alloc(nm));
+  LSX_TRY(d_flag.alloc(nm));
+  LSX_TRY(d_Q.alloc(qsize));
+  BJArgs g;
+  g.A = A;
+  g.VT = VT;
+  g.moff = d_moff;
+  g.ndim = d_ndim;
+  g.tiny = d_tiny.p;
+  g.Q = d_Q.p;
+  g.flag = d_flag.p;
+  LSX_HIP_TRY(launch_bj_init(s, (int)sel.size(), d_sel.p, g));
+  std::vector<int32_t> flag(nm, 0);
+  int sweep = 0;
+  for (; sweep < maxsweeps && !act.empty(); ++sweep) {
+    const int na = (int)act.size();
+    std::vector<int32_t> pp(na + 1, 0), pt(na + 1, 0);
+    for (int a = 0; a < na; ++a) {
+      const int np = ndim[act[a]] / 32;
+      pp[a + 1] = pp[a] + np;
+      pt[a + 1] = pt[a] + 2 * np * np;
+    }
+    LSX_TRY(d_mat.upload(act, s));
+    LSX_TRY(d_pp.upload(pp, s));
+    LSX_TRY(d_pt.upload(pt, s));
+    LSX_HIP_TRY(hipMemsetAsync(d_flag.p, 0, nm * sizeof(int32_t), s));
+    g.mat = d_mat.p;
+    g.pfx_pairs = d_pp.p;
+    g.pfx_tiles = d_pt.p;
+    const int rounds = ndim[act[0]] / 16 - 1;
+    int count = na;
+    for (int r = 0; r < rounds; ++r) {
+      // matrices with more than r + 1 blocks take part (a prefix: act is sorted by size)
+      while (count > 0 && ndim[act[count - 1]] / 16 - 1 <= r) --count;
+      g.count = count;
+      g.round = r;
+      LSX_HIP_TRY(launch_bj_round(s, pp[count], pt[count], g));
+    }
+    LSX_HIP_TRY(hipMemcpyAsync(flag.data(), d_flag.p, nm * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    LSX_HIP_TRY(hipStreamSynchronize(s));
+    std::vector<int32_t> keep;
+    for (int m : act) {
+      if (flag[m]) keep.push_back(m);
+      else info[m] = sweep + 1;
+    }
+    act.swap(keep);
+  }
+  for (int m : act) info[m] = -1;
+  LSX_HIP_TRY(launch_bj_finish(s, (int)sel.size(), d_sel.p, g, lam, d_loff));
+  LSX_HIP_TRY(hipStreamSynchronize(s));
+  return LSX_OK;
+}
+
 static lsx_status precompute_layer(lsx_plan* pl, int layer, hipStream_t s) {
   lsx_system* sys = pl->sys;
   LayerDev& ld = pl->L[layer - 1];
@@ -926,13 +997,25 @@ static lsx_status precompute_layer(lsx_plan* pl, int layer, hipStream_t s) {
   std::vector<int64_t> moff(nu), loff(nu);
   int64_t mt = 0, lt = 0;
   int maxn = 0, maxL = 0;
+  // Matrices of more than kBlockedMin rows take the blocked solver (padded to a multiple of 32),
+  // the others the scalar one (padded to even); LSX_BLOCKED_JACOBI=0 keeps every fibre scalar.
+  const int blocked_min = env_int("LSX_BLOCKED_JACOBI", 1) != 0 ? kBlockedMin : 1 << 30;
+  std::vector<int32_t> sel_s, sel_b;
+  int maxn_s = 0;
   for (int b = 0; b < nu; ++b) {
     const int f = uniq[b];
     const int L = ft.ptr[f + 1] - ft.ptr[f];
     maxL = std::max(maxL, L);
     int n = embed ? 2 * L : L;
-    n += (n & 1);
-    if (n < 2) n = 2;
+    if (n > blocked_min) {
+      n = round_up(n, 32);
+      sel_b.push_back(b);
+    } else {
+      n += (n & 1);
+      if (n < 2) n = 2;
+      sel_s.push_back(b);
+      maxn_s = std::max(maxn_s, n);
+    }
     ndim[b] = n;
     maxn = std::max(maxn, n);
     moff[b] = mt;
@@ -963,10 +1046,17 @@ static lsx_status precompute_layer(lsx_plan* pl, int layer, hipStream_t s) {
   const double kfac = (1.0 - pl->kappa) / sys->nl * 0.5;
   LSX_HIP_TRY(launch_assemble(s, nu, d_fid.p, ld.ptr.p, ld.rows.p, d_mn.p, d, stride, own, kfac, pl->K2.p, S.nv,
                               d_vidx.p, d_vre.p, d_vim.p, embed, A.p, d_moff.p, d_ndim.p));
-  LSX_HIP_TRY(launch_jacobi(s, nu, maxn, A.p, VT.p, d_moff.p, d_ndim.p, lam.p, d_loff.p, d_info.p, 60));
-  std::vector<int32_t> info(nu);
-  LSX_HIP_TRY(hipMemcpyAsync(info.data(), d_info.p, nu * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  LSX_HIP_TRY(hipStreamSynchronize(s));
+  std::vector<int32_t> info(nu, 0);
+  if (!sel_s.empty()) {
+    DBuf<int32_t> d_sel;
+    LSX_TRY(d_sel.upload(sel_s, s));
+    LSX_HIP_TRY(launch_jacobi(s, (int)sel_s.size(), maxn_s, A.p, VT.p, d_moff.p, d_ndim.p, lam.p, d_loff.p,
+                              d_info.p, 60, d_sel.p));
+    LSX_HIP_TRY(hipMemcpyAsync(info.data(), d_info.p, nu * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    LSX_HIP_TRY(hipStreamSynchronize(s));
+  }
+  if (!sel_b.empty())
+    LSX_TRY(block_jacobi(s, sel_b, ndim, A.p, VT.p, d_moff.p, d_ndim.p, lam.p, d_loff.p, 60, info));
   if (const char* fe = std::getenv("LSX_TEST_FAIL_EIG"))
     if (std::atoi(fe) == 1) info[0] = -1;
   for (int b = 0; b < nu; ++b)

@@ -101,9 +101,35 @@ hipError_t launch_assemble(hipStream_t s, int nb, const int32_t* fid, const int3
                            const int32_t* mn, int d, int stride, int own, double kfac, const double* K2, int nv,
                            const int32_t* vidx, const double* vre, const double* vim, int embed, double* A,
                            const int64_t* moff, const int32_t* ndim);
+// Blocked two-sided Jacobi (long fibres): arguments of one round.  Matrices are indexed by their
+// slot m (moff, ndim: padded size, a multiple of 32).  mat lists this sweep's unconverged
+// matrices by size, largest first; a round runs on the first `count` of them (those with more
+// than `round` + 1 blocks of 16).  pfx_pairs / pfx_tiles are prefix sums over mat of nb/2 pairs
+// and 2 (nb/2)^2 tiles (nb = n/16); Q holds every pair's 32x32 rotation (row-major) at its
+// pfx_pairs index; flag[m] is set to 1 when matrix m was rotated; tiny[m] is its skip threshold.
+struct BJArgs {
+  double* A = nullptr;
+  double* VT = nullptr;
+  const int64_t* moff = nullptr;
+  const int32_t* ndim = nullptr;
+  double* tiny = nullptr;
+  const int32_t* mat = nullptr;
+  const int32_t* pfx_pairs = nullptr;
+  const int32_t* pfx_tiles = nullptr;
+  int count = 0;
+  int round = 0;
+  double* Q = nullptr;
+  int32_t* flag = nullptr;
+};
+hipError_t launch_bj_init(hipStream_t s, int nsel, const int32_t* sel, const BJArgs& g);
+hipError_t launch_bj_round(hipStream_t s, int npairs, int ntiles, const BJArgs& g);
+hipError_t launch_bj_finish(hipStream_t s, int nsel, const int32_t* sel, const BJArgs& g, double* lam,
+                            const int64_t* loff);
+
+// Scalar cyclic Jacobi, one workgroup per matrix; sel (nullable) lists the matrices to solve.
 hipError_t launch_jacobi(hipStream_t s, int nf, int maxn, double* A, double* VT, const int64_t* moff,
                          const int32_t* ndim, double* lam, const int64_t* loff, int32_t* info,
-                         int maxsweeps);
+                         int maxsweeps, const int32_t* sel = nullptr);
 hipError_t launch_eig_fn(hipStream_t s, int64_t nlam, const double* lam, double t, int flow, double2* gh);
 hipError_t launch_form(hipStream_t s, int fmt, int nb, int maxL, const int32_t* fid, const int32_t* ptr,
                        const double* VT, const int64_t* moff, const int32_t* ndim, const int32_t* embed,

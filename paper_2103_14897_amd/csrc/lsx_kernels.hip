@@ -115,11 +115,35 @@ __global__ void k_assemble(const int32_t* fid, const int32_t* ptr, const int32_t
 // done one 2x2 block at a time (block (i,j) depends only on rotations i and j), which
 // needs no barrier between the row and the column transformation.  VT holds V^T, so
 // H = V diag(lambda) V^T on exit, eigenvalues in the diagonal of A.
+// Last step of both Jacobi solvers.  Each rotation is orthogonal only up to the rounding of
+// (c, s): near-degenerate pairs (potential-only fibres) take 45-degree rotations with
+// c = s = fl(1/sqrt 2), and 2 fl(1/sqrt 2)^2 = 1 + 2^-52, so both rows grow by the same factor and
+// thousands of such rotations per row leave V scaled-orthogonal, V = Q diag(nu), and
+// A = diag(nu) Q^T H Q diag(nu).  Normalising each eigenvector (row of V^T) and dividing its
+// diagonal entry by nu^2 recovers Q and the eigenvalues.  One workgroup of BS threads.
+template <int BS>
+__device__ void jacobi_finish(const double* A, double* VT, int n, double* lamf) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  for (int k = wv; k < n; k += BS / 64) {
+    double s = 0.0;
+    for (int c = lane; c < n; c += 64) {
+      const double x = VT[(int64_t)k * n + c];
+      s += x * x;
+    }
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    const double r = 1.0 / sqrt(s);
+    for (int c = lane; c < n; c += 64) VT[(int64_t)k * n + c] *= r;
+    if (lane == 0) lamf[k] = A[(int64_t)k * n + k] / s;
+  }
+}
+
+// sel (nullable): workgroup i solves matrix sel[i] (else matrix i).
 template <int BS>
 __global__ __launch_bounds__(BS) void k_jacobi(double* Aall, double* VTall, const int64_t* moff,
                                                const int32_t* ndim, double* lam, const int64_t* loff,
-                                               int32_t* info, int maxsweeps) {
-  const int f = blockIdx.x;
+                                               int32_t* info, int maxsweeps, const int32_t* sel) {
+  const int f = sel ? sel[blockIdx.x] : blockIdx.x;
   const int n = ndim[f];
   double* A = Aall + moff[f];
   double* VT = VTall + moff[f];
@@ -205,25 +229,254 @@ __global__ __launch_bounds__(BS) void k_jacobi(double* Aall, double* VTall, cons
     done = (rotated == 0);
     __syncthreads();
   }
-  // Each rotation is orthogonal only up to the rounding of (c, s): near-degenerate pairs
-  // (potential-only fibres) take 45-degree rotations with c = s = fl(1/sqrt 2), and
-  // 2 fl(1/sqrt 2)^2 = 1 + 2^-52, so both rows grow by the same factor and thousands of such
-  // rotations per row leave V scaled-orthogonal, V = Q diag(nu), and A = diag(nu) Q^T H Q
-  // diag(nu).  Normalising each eigenvector (row of V^T) and dividing its diagonal entry by
-  // nu^2 recovers Q and the eigenvalues.
-  const int lane = tid & 63, wv = tid >> 6;
-  for (int k = wv; k < n; k += BS / 64) {
-    double s = 0.0;
-    for (int c = lane; c < n; c += 64) {
-      const double x = VT[(int64_t)k * n + c];
-      s += x * x;
-    }
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-    const double r = 1.0 / sqrt(s);
-    for (int c = lane; c < n; c += 64) VT[(int64_t)k * n + c] *= r;
-    if (lane == 0) lam[loff[f] + k] = A[(int64_t)k * n + k] / s;
-  }
+  jacobi_finish<BS>(A, VT, n, lam + loff[f]);
   if (tid == 0) info[f] = done ? sweep : -1;
+}
+
+// ---------------------------------------------------------------- blocked two-sided Jacobi
+// For long fibres.  A matrix of padded size n (a multiple of 32; padding rows and columns are
+// zero and are never rotated) is cut into nb = n/16 blocks of 16 rows.  A round pairs the
+// blocks with the same circle method the scalar solver uses for rows, into nb/2 disjoint pairs
+// P = (I, J).  For every pair the 32x32 diagonal subproblem A[P, P] takes one cyclic Jacobi
+// sweep in LDS, whose rotations accumulate into Q_P; then every 32x32 tile of A and of V^T is
+// replaced, A[P, P'] <- Q_P^T A[P, P'] Q_P' and V^T[P, R] <- Q_P^T V^T[P, R] (R: 32 columns).
+// Each output tile depends only on its own input tile and two rotations, so a round is two
+// launches with no other synchronisation, and the tile products run on the FP64 matrix cores.
+// A sweep with no rotation in any subproblem leaves every off-diagonal entry below the same
+// threshold as the scalar solver's; the same rotation formula and final normalisation apply.
+
+// slot a of a prefix-sum table with pfx[a] <= item < pfx[a + 1] (pfx[0] = 0, item < pfx[count])
+__device__ __forceinline__ int bj_slot(const int32_t* pfx, int count, int item) {
+  int lo = 0, hi = count;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (pfx[mid] <= item) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// blocks (I, J) of pair i in round r of nb blocks (circle method, nb even)
+__device__ __forceinline__ void bj_pair(int nb, int r, int i, int& I, int& J) {
+  const int M = nb - 1;
+  if (i == 0) {
+    I = M;
+    J = r;
+  } else {
+    I = (r + i) % M;
+    J = (r - i + M) % M;
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_bj_init(BJArgs g, const int32_t* sel) {
+  const int m = sel[blockIdx.x];
+  const int n = g.ndim[m];
+  const double* A = g.A + g.moff[m];
+  double* VT = g.VT + g.moff[m];
+  __shared__ double red[1024];
+  const int64_t nn = (int64_t)n * n;
+  double s2 = 0.0;
+  for (int64_t e = threadIdx.x; e < nn; e += 1024) {
+    VT[e] = ((e / n) == (e % n)) ? 1.0 : 0.0;
+    s2 += A[e] * A[e];
+  }
+  const double normF = sqrt(block_sum<1024>(s2, red));
+  if (threadIdx.x == 0) g.tiny[m] = 1e-16 * normF;
+}
+
+__global__ __launch_bounds__(256) void k_bj_pairs(BJArgs g) {
+  __shared__ double S[32][33];
+  __shared__ double Qs[32][33];
+  __shared__ double rc[16], rs[16];
+  __shared__ int rp[16], rq[16];
+  __shared__ int rot;
+  const int item = blockIdx.x;
+  const int a = bj_slot(g.pfx_pairs, g.count, item);
+  const int m = g.mat[a];
+  const int i = item - g.pfx_pairs[a];
+  const int n = g.ndim[m];
+  int I, J;
+  bj_pair(n >> 4, g.round, i, I, J);
+  const double* A = g.A + g.moff[m];
+  const int tid = threadIdx.x;
+  if (tid == 0) rot = 0;
+  for (int e = tid; e < 1024; e += 256) {
+    const int x = e >> 5, y = e & 31;
+    const int gx = (x < 16 ? I : J) * 16 + (x & 15), gy = (y < 16 ? I : J) * 16 + (y & 15);
+    S[x][y] = A[(int64_t)gx * n + gy];
+    Qs[x][y] = (x == y) ? 1.0 : 0.0;
+  }
+  const double tiny = g.tiny[m];
+  __syncthreads();
+  for (int r = 0; r < 31; ++r) {
+    if (tid < 16) {
+      const int p = (tid == 0) ? 31 : (r + tid) % 31;
+      const int q = (tid == 0) ? r : (r - tid + 31) % 31;
+      const double app = S[p][p], aqq = S[q][q], apq = S[p][q];
+      double c = 1.0, sn = 0.0;
+      if (fabs(apq) > 1e-16 * sqrt(fabs(app * aqq)) + tiny) {
+        const double th = (aqq - app) / (2.0 * apq);
+        const double t = (fabs(th) > 1e150) ? 0.5 / th
+                                            : ((th >= 0.0) ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+        c = 1.0 / sqrt(t * t + 1.0);
+        sn = t * c;
+        rot = 1;
+      }
+      rc[tid] = c;
+      rs[tid] = sn;
+      rp[tid] = p;
+      rq[tid] = q;
+    }
+    __syncthreads();
+    {
+      // S <- J^T S J one 2x2 block per thread: rows (p_bi, q_bi), columns (p_bj, q_bj)
+      const int bi = tid >> 4, bj = tid & 15;
+      const double ci = rc[bi], si = rs[bi], cj = rc[bj], sj = rs[bj];
+      if (si != 0.0 || sj != 0.0) {
+        const int p = rp[bi], q = rq[bi], p2 = rp[bj], q2 = rq[bj];
+        const double a0 = S[p][p2], b0 = S[p][q2], c0 = S[q][p2], d0 = S[q][q2];
+        const double a1 = ci * a0 - si * c0, b1 = ci * b0 - si * d0;
+        const double c1 = si * a0 + ci * c0, d1 = si * b0 + ci * d0;
+        double a2 = cj * a1 - sj * b1, b2 = sj * a1 + cj * b1;
+        double c2 = cj * c1 - sj * d1, d2 = sj * c1 + cj * d1;
+        if (bi == bj) {
+          b2 = 0.0;
+          c2 = 0.0;
+        }
+        S[p][p2] = a2;
+        S[p][q2] = b2;
+        S[q][p2] = c2;
+        S[q][q2] = d2;
+      }
+      // Q <- Q J: columns (p_k, q_k) of rows x and x + 16
+      const int k = tid & 15, x0 = tid >> 4;
+      const double c = rc[k], sn = rs[k];
+      if (sn != 0.0) {
+        const int p = rp[k], q = rq[k];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int x = x0 + 16 * h;
+          const double u = Qs[x][p], v = Qs[x][q];
+          Qs[x][p] = c * u - sn * v;
+          Qs[x][q] = sn * u + c * v;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  double* Qo = g.Q + ((int64_t)g.pfx_pairs[a] + i) * 1024;
+  for (int e = tid; e < 1024; e += 256) Qo[e] = Qs[e >> 5][e & 31];
+  if (tid == 0 && rot) g.flag[m] = 1;
+}
+
+// One wave per 32x32 tile, four tiles per workgroup.  v_mfma_f64_16x16x4f64 takes A as lane l =
+// A[l % 16][l / 16] and B as B[l / 16][l % 16] of a 16x4 / 4x16 step and leaves C[4 r + l / 16]
+// [l % 16] in element r, so the accumulators of X = A_t Q_P' are, element for element, the B
+// operands of the second product Q_P^T X.
+__global__ __launch_bounds__(256) void k_bj_tiles(BJArgs g, int total) {
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int item = blockIdx.x * 4 + wv;
+  if (item >= total) return;
+  const int a = bj_slot(g.pfx_tiles, g.count, item);
+  const int m = g.mat[a];
+  const int t = item - g.pfx_tiles[a];
+  const int n = g.ndim[m], nb = n >> 4, np = nb >> 1;
+  const int li = lane & 15, lk = lane >> 4;
+  const double* Qb = g.Q + (int64_t)g.pfx_pairs[a] * 1024;
+  const v4d zero4 = {0.0, 0.0, 0.0, 0.0};
+  v4d T[2][2] = {{zero4, zero4}, {zero4, zero4}};
+  if (t < np * np) {
+    const int P = t / np, P2 = t - (t / np) * np;
+    int I, J, I2, J2;
+    bj_pair(nb, g.round, P, I, J);
+    bj_pair(nb, g.round, P2, I2, J2);
+    double* A = g.A + g.moff[m];
+    const double* Q1 = Qb + (int64_t)P * 1024;
+    const double* Q2 = Qb + (int64_t)P2 * 1024;
+    v4d X[2][2] = {{zero4, zero4}, {zero4, zero4}};
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int k = 4 * s + lk;
+      const int gc = (k < 16 ? I2 : J2) * 16 + (k & 15);
+      const double a0 = A[(int64_t)(I * 16 + li) * n + gc];
+      const double a1 = A[(int64_t)(J * 16 + li) * n + gc];
+      const double b0 = Q2[k * 32 + li], b1 = Q2[k * 32 + 16 + li];
+      X[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, X[0][0], 0, 0, 0);
+      X[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, X[0][1], 0, 0, 0);
+      X[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, X[1][0], 0, 0, 0);
+      X[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, X[1][1], 0, 0, 0);
+    }
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int k = 4 * s + lk;
+      const double q0 = Q1[k * 32 + li], q1 = Q1[k * 32 + 16 + li];
+      const double x0 = X[s >> 2][0][s & 3], x1 = X[s >> 2][1][s & 3];
+      T[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(q0, x0, T[0][0], 0, 0, 0);
+      T[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(q0, x1, T[0][1], 0, 0, 0);
+      T[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(q1, x0, T[1][0], 0, 0, 0);
+      T[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(q1, x1, T[1][1], 0, 0, 0);
+    }
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          A[(int64_t)((bi ? J : I) * 16 + 4 * r + lk) * n + (bj ? J2 : I2) * 16 + li] = T[bi][bj][r];
+  } else {
+    const int tv = t - np * np;
+    const int P = tv / np, R = tv - (tv / np) * np;
+    int I, J;
+    bj_pair(nb, g.round, P, I, J);
+    double* VT = g.VT + g.moff[m];
+    const double* Q1 = Qb + (int64_t)P * 1024;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int k = 4 * s + lk;
+      const int64_t gk = (int64_t)((k < 16 ? I : J) * 16 + (k & 15)) * n + R * 32;
+      const double q0 = Q1[k * 32 + li], q1 = Q1[k * 32 + 16 + li];
+      const double v0 = VT[gk + li], v1 = VT[gk + 16 + li];
+      T[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(q0, v0, T[0][0], 0, 0, 0);
+      T[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(q0, v1, T[0][1], 0, 0, 0);
+      T[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(q1, v0, T[1][0], 0, 0, 0);
+      T[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(q1, v1, T[1][1], 0, 0, 0);
+    }
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          VT[(int64_t)((bi ? J : I) * 16 + 4 * r + lk) * n + R * 32 + 16 * bj + li] = T[bi][bj][r];
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_bj_finish(BJArgs g, const int32_t* sel, double* lam, const int64_t* loff) {
+  const int m = sel[blockIdx.x];
+  const int n = g.ndim[m];
+  jacobi_finish<1024>(g.A + g.moff[m], g.VT + g.moff[m], n, lam + loff[m]);
+}
+
+hipError_t launch_bj_init(hipStream_t s, int nsel, const int32_t* sel, const BJArgs& g) {
+  if (nsel == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_bj_init, dim3(nsel), dim3(1024), 0, s, g, sel);
+  return hipGetLastError();
+}
+
+hipError_t launch_bj_round(hipStream_t s, int npairs, int ntiles, const BJArgs& g) {
+  if (npairs == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_bj_pairs, dim3(npairs), dim3(256), 0, s, g);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_bj_tiles, dim3((ntiles + 3) / 4), dim3(256), 0, s, g, ntiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_bj_finish(hipStream_t s, int nsel, const int32_t* sel, const BJArgs& g, double* lam,
+                            const int64_t* loff) {
+  if (nsel == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_bj_finish, dim3(nsel), dim3(1024), 0, s, g, sel, lam, loff);
+  return hipGetLastError();
 }
 
 // f(lambda) = g + i h of one sub-step of length t for each eigenvalue:
@@ -1313,14 +1566,16 @@ hipError_t launch_assemble(hipStream_t s, int nb, const int32_t* fid, const int3
 }
 
 hipError_t launch_jacobi(hipStream_t s, int nf, int maxn, double* A, double* VT, const int64_t* moff,
-                         const int32_t* ndim, double* lam, const int64_t* loff, int32_t* info, int maxsweeps) {
+                         const int32_t* ndim, double* lam, const int64_t* loff, int32_t* info, int maxsweeps,
+                         const int32_t* sel) {
+  if (nf == 0) return hipSuccess;
   const size_t shm = (size_t)(maxn / 2) * (2 * sizeof(double) + 2 * sizeof(int));
   if (maxn > 256)
     hipLaunchKernelGGL(k_jacobi<1024>, dim3(nf), dim3(1024), shm, s, A, VT, moff, ndim, lam, loff, info,
-                       maxsweeps);
+                       maxsweeps, sel);
   else
     hipLaunchKernelGGL(k_jacobi<256>, dim3(nf), dim3(256), shm, s, A, VT, moff, ndim, lam, loff, info,
-                       maxsweeps);
+                       maxsweeps, sel);
   return hipGetLastError();
 }
 
