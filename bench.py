@@ -105,9 +105,14 @@ def batch_workload(args):
     Systems (seeded PCG64): `--batch-1d` 1D+1D chains with period ratio drawn from
     {golden mean, sqrt 2, sqrt 3} and Ec log-uniform in [1e3, 2e4], plus `--batch-2d`
     twisted triangular bilayers with twist uniform in [1, 6] deg and N log-uniform in
-    [1e5, 4e5] (Ec = 6500 sqrt(N / 398821)); 16 wavepackets each; kappa = 1 (potential-only
-    fibre windows, shared propagators), Strang, tau = 1e-3 (1D) / 5e-3 (2D), `--paths`
-    first entry as precision.
+    [1e5, 4e5] (Ec = 6500 sqrt(N / 398821)); 16 wavepackets each; kinetic share `--kappa`
+    (0: the paper's split, every fibre its own Bloch-shifted Hamiltonian, propagators shared
+    over the point symmetries; 1: potential-only windows shared by translation), Strang,
+    tau = 1e-3 (1D) / 5e-3 (2D), `--paths` first entry as precision.
+
+    Roofline of each layer's grouped pass (time from the batch tuner's measurement): bytes =
+    every system's state read and written (2 N W 16) plus its distinct propagators (and the FP64
+    diagonal, 16 N, on the mixed paths); flops = 8 W sum L^2 over every fibre.
     """
     import math
     import torch
@@ -127,11 +132,25 @@ def batch_workload(args):
     items = []
     for spec, tau in specs:
         S = lsx.System.from_spec(spec)
-        P = lsx.Plan(S, tau, "strang", 1.0, prec, stream)
+        P = lsx.Plan(S, tau, "strang", args.kappa, prec, stream)
         st = lsx.State(P, 16)
         st.upload(wl.random_state(S.N, 16, seed=len(items)), stream)
         items.append((S, P, st))
     pre = time.perf_counter() - t0
+    print(f"[bench] batch: {len(items)} systems built in {pre:.1f} s", file=sys.stderr, flush=True)
+    # algorithmic work of one grouped pass per layer, over all systems
+    work = {1: [0.0, 0.0], 2: [0.0, 0.0]}
+    distinct = {1: 0, 2: 0}
+    for S, P, st in items:
+        for j in (1, 2):
+            L = np.diff(S.fibres(j)[0]).astype(np.int64)
+            nd = P.sharing(j)[0]
+            distinct[j] += nd
+            # distinct propagators: each orbit or window class stores one, of its members' length
+            frac = nd / max(1, S.nfibres[j])
+            work[j][0] += 8.0 * 16 * float((L ** 2).sum())
+            work[j][1] += 2.0 * S.N * 16 * 16 + PROP_BYTES[prec] * float((L ** 2).sum()) * frac + \
+                (16.0 * S.N if prec != "fp64" else 0.0)
     B = lsx.Batch([it[2] for it in items])
     coeffs = sum(it[0].N * 16 for it in items)
     B.step(args.warmup, stream)
@@ -148,17 +167,36 @@ def batch_workload(args):
     e1.record(stream)
     e1.synchronize()
     ms_seq = e0.elapsed_time(e1)
+    roof = {}
+    for j in (1, 2):
+        us = B.tuning(j)[2]
+        if us > 0:
+            gbs = work[j][1] / (us * 1e-6) / 1e9
+            tfs = work[j][0] / (us * 1e-6) / 1e12
+            roof[f"layer{j}"] = {"pass_us": us, "GB/s": gbs, "hbm_frac": gbs * 1e9 / HBM_PEAK, "TFLOP/s": tfs,
+                                 "mfma_frac": tfs * 1e12 / PEAK[prec], "algorithmic_bytes": work[j][1],
+                                 "algorithmic_flops": work[j][0], "distinct_propagators": distinct[j]}
+    j = max(roof, key=lambda k: roof[k]["pass_us"]) if roof else None
+    if j is not None:
+        r = roof[j]
+        hbm = r["algorithmic_bytes"] / HBM_PEAK >= r["algorithmic_flops"] / PEAK[prec]
+        top = {"bound": "hbm" if hbm else "mfma", "achieved": r["GB/s"] if hbm else r["TFLOP/s"],
+               "peak": HBM_PEAK / 1e9 if hbm else PEAK[prec] / 1e12, "unit": "GB/s" if hbm else "TFLOP/s",
+               "frac": r["hbm_frac"] if hbm else r["mfma_frac"], "traffic": None,
+               "kernel": f"grouped fibre pass, {j} ({prec}), all systems"}
+    else:
+        top = None
     out = {"metric": METRIC + " (batched systems)", "value": coeffs * args.steps / (ms_batch * 1e-3),
            "unit": "coeff*steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": ms_batch / args.steps, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": DTYPE[prec], "data": "synthetic",
-           "config": {"workload": f"batch_{args.batch_1d}x1d_{args.batch_2d}x2d_W16_kappa1",
+           "config": {"workload": f"batch_{args.batch_1d}x1d_{args.batch_2d}x2d_W16_kappa{args.kappa:g}",
                       "systems": len(items), "total_coefficients": coeffs,
                       "N_range": [min(it[0].N for it in items), max(it[0].N for it in items)],
                       "tiles": {"layer1": B.tuning(1)[:2], "layer2": B.tuning(2)[:2]},
                       "launch_mode": {"layer1": B.tuning(1)[3], "layer2": B.tuning(2)[3]}},
            "sequential_value": coeffs * args.steps / (ms_seq * 1e-3), "sequential_ms_per_step": ms_seq / args.steps,
-           "precompute_s": pre}
+           "precompute_s": pre, "roofline": top, "passes": roof}
     print(json.dumps(out))
     B.destroy()
     for S, P, st in items:
