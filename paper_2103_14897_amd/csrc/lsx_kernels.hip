@@ -990,9 +990,16 @@ __global__ __launch_bounds__(64 * MS) void k_pass_f32m(PassArgs a) {
   for (int nb = 0; nb < NB; ++nb) k1[nb] = k2[nb] = k3[nb] = (v4f){0.f, 0.f, 0.f, 0.f};
   double2 sv[SM::PER];
   float2 Ac[KC], An[KC];
-  stage_load_f32<SM::PER, SM::RSTEP, SM::CR, GATHER>(sv, a, 0, r0, L, sw, sok, rr0);
+  // chunks in the order c0, c0 + 1, ... (mod nch), with the workgroup's own rows last: the
+  // epilogue's FP64 reload of those rows then finds them in this XCD's L2, just staged
+  const int c0 = ((t0.rb + 1) * MS * 16 / SM::CR) % nch;
+  auto chunk = [&](int i) { return i + c0 < nch ? i + c0 : i + c0 - nch; };
+  stage_load_f32<SM::PER, SM::RSTEP, SM::CR, GATHER>(sv, a, chunk(0), r0, L, sw, sok, rr0);
 #pragma unroll
-  for (int u = 0; u < KC; ++u) Ac[u] = (act && u < nks) ? P[u * 64] : *zp;
+  for (int u = 0; u < KC; ++u) {
+    const int ks = KC * chunk(0) + u;
+    Ac[u] = (act && ks < nks) ? P[(int64_t)ks * 64] : *zp;
+  }
 #pragma unroll
   for (int j = 0; j < SM::PER; ++j) {
     const float xr = (float)sv[j].x, xi = (float)sv[j].y;
@@ -1003,10 +1010,10 @@ __global__ __launch_bounds__(64 * MS) void k_pass_f32m(PassArgs a) {
     const int buf = ch & 1;
     const bool more = ch + 1 < nch;
     if (more) {
-      stage_load_f32<SM::PER, SM::RSTEP, SM::CR, GATHER>(sv, a, ch + 1, r0, L, sw, sok, rr0);
+      stage_load_f32<SM::PER, SM::RSTEP, SM::CR, GATHER>(sv, a, chunk(ch + 1), r0, L, sw, sok, rr0);
 #pragma unroll
       for (int u = 0; u < KC; ++u) {
-        const int ks = KC * (ch + 1) + u;
+        const int ks = KC * chunk(ch + 1) + u;
         An[u] = (act && ks < nks) ? P[(int64_t)ks * 64] : *zp;
       }
     }
