@@ -43,6 +43,20 @@ __device__ __forceinline__ void split3(double x, unsigned short& t0, unsigned sh
   r = r - (double)bf2f(t1);
   t2 = f2bf((float)r);
 }
+// exact three-term bf16 split of an fp32 value: t0 is x with the low 16 bits cleared, t1 the
+// same for the remainder x - t0 (exact in fp32, at most 16 significant bits), and the second
+// remainder has at most 8 significant bits, so it is a bf16 itself: t0 + t1 + t2 = x exactly.
+// Three masks and two subtractions, against three roundings for split3f.
+__device__ __forceinline__ void split3x(float x, unsigned short& t0, unsigned short& t1, unsigned short& t2) {
+  const unsigned u = __float_as_uint(x);
+  const float r1 = x - __uint_as_float(u & 0xFFFF0000u);
+  const unsigned v = __float_as_uint(r1);
+  const float r2 = r1 - __uint_as_float(v & 0xFFFF0000u);
+  t0 = (unsigned short)(u >> 16);
+  t1 = (unsigned short)(v >> 16);
+  t2 = (unsigned short)(__float_as_uint(r2) >> 16);
+}
+
 // same split from an fp32 value (all residuals exact in fp32)
 __device__ __forceinline__ void split3f(float x, unsigned short& t0, unsigned short& t1, unsigned short& t2) {
   t0 = f2bf(x);
@@ -1201,9 +1215,9 @@ __global__ __launch_bounds__(64 * MS) void k_pass_bf16m(PassArgs a) {
   TileDesc t = t0;
   t.rb = t0.rb * MS + kw;
   const bool act = t.rb < ((L + 15) >> 4);
-  const v8u16* zp = reinterpret_cast<const v8u16*>(a.zero);
-  const v8u16* P = reinterpret_cast<const v8u16*>(reinterpret_cast<const char*>(a.P) + t.poff) +
-                   (int64_t)(act ? t.rb : 0) * nkc * 6 * 64 + lane;
+  const v8bf* zb = reinterpret_cast<const v8bf*>(a.zero);
+  const v8bf* P = reinterpret_cast<const v8bf*>(reinterpret_cast<const char*>(a.P) + t.poff) +
+                  (int64_t)(act ? t.rb : 0) * nkc * 6 * 64 + lane;
   int wc[NB];
   bool wok[NB];
   tile_cols<NB>(a, t, li, wc, wok);
@@ -1221,22 +1235,28 @@ __global__ __launch_bounds__(64 * MS) void k_pass_bf16m(PassArgs a) {
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) rr[nb] = ii[nb] = ri[nb] = ir[nb] = (v4f){0.f, 0.f, 0.f, 0.f};
   double2 sv[PER];
-  v8u16 Ac[6], An[6];
+  // State operands of chunk kc (rows past the fibre read the zero buffer).  The offset is
+  // computed unconditionally and pinned by an empty asm operand, so the pointer select stays a
+  // select: a load under a branch makes the compiler wait for every outstanding load at the
+  // join, including the next chunk's prefetch.  (Pinning the pointer itself would lose its
+  // address space and turn the loads into flat loads, which LDS waits also wait for.)
   auto load_state = [&](int kc) {
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
       const int k = 32 * kc + rr0 + j * RSTEP;
       const bool ok = sok && k < L;
-      const int64_t row = xrow<GATHER>(a, r0 + (ok ? k : 0));
-      sv[j] = *(ok ? a.X + row * a.W + sw : zx);
+      int64_t off = xrow<GATHER>(a, r0 + (ok ? k : 0)) * a.W + sw;
+      asm volatile("" : "+v"(off));
+      sv[j] = *(ok ? a.X + off : zx);
     }
   };
+  // fp32(x) split exactly into three bf16 terms, six planes [term re/im][column][k]
   auto store_state = [&](int buf) {
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
       unsigned short q0, q1, q2, q3, q4, q5;
-      split3f((float)sv[j].x, q0, q1, q2);
-      split3f((float)sv[j].y, q3, q4, q5);
+      split3x((float)sv[j].x, q0, q1, q2);
+      split3x((float)sv[j].y, q3, q4, q5);
       const int k = rr0 + j * RSTEP;
       xb[buf][0][c][k] = q0;
       xb[buf][1][c][k] = q1;
@@ -1246,43 +1266,58 @@ __global__ __launch_bounds__(64 * MS) void k_pass_bf16m(PassArgs a) {
       xb[buf][5][c][k] = q5;
     }
   };
-  load_state(0);
+  // this wave's propagator planes of chunk kc (E re/im terms 0..2), zeros past the fibre
+  auto load_e = [&](v8bf (&E)[6], int kc) {
+    const bool in = act && kc < nkc;
 #pragma unroll
-  for (int pl = 0; pl < 6; ++pl) Ac[pl] = act ? P[pl * 64] : *zp;
+    for (int pl = 0; pl < 6; ++pl) {
+      int64_t off = ((int64_t)kc * 6 + pl) * 64;
+      asm volatile("" : "+v"(off));
+      E[pl] = *(in ? P + off : zb);
+    }
+  };
+  auto mma = [&](const v8bf (&E)[6], int buf) {
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      // one column block's operands at a time (keeps the next block's LDS reads from being
+      // hoisted, which would hold twice the registers)
+      if (nb > 0) __builtin_amdgcn_sched_barrier(0);
+      const int col = nb * 16 + li;
+      const v8bf Xr0 = *reinterpret_cast<const v8bf*>(&xb[buf][0][col][8 * lk]);
+      const v8bf Xr1 = *reinterpret_cast<const v8bf*>(&xb[buf][1][col][8 * lk]);
+      const v8bf Xr2 = *reinterpret_cast<const v8bf*>(&xb[buf][2][col][8 * lk]);
+      const v8bf Xi0 = *reinterpret_cast<const v8bf*>(&xb[buf][3][col][8 * lk]);
+      const v8bf Xi1 = *reinterpret_cast<const v8bf*>(&xb[buf][4][col][8 * lk]);
+      const v8bf Xi2 = *reinterpret_cast<const v8bf*>(&xb[buf][5][col][8 * lk]);
+      rr[nb] = mma3(rr[nb], E[0], E[2], E[4], Xr0, Xr1, Xr2);
+      ii[nb] = mma3(ii[nb], E[1], E[3], E[5], Xi0, Xi1, Xi2);
+      ri[nb] = mma3(ri[nb], E[0], E[2], E[4], Xi0, Xi1, Xi2);
+      ir[nb] = mma3(ir[nb], E[1], E[3], E[5], Xr0, Xr1, Xr2);
+    }
+  };
+  // Ping-pong operand buffers over pairs of chunks: chunk kc multiplies EA (or EB) while the
+  // next chunk's state values and planes load into sv and EB (or EA); no register copies.
+  v8bf EA[6], EB[6];
+  load_state(0);
+  load_e(EA, 0);
   store_state(0);
   __syncthreads();
-  for (int kc = 0; kc < nkc; ++kc) {
-    const int buf = kc & 1;
-    const bool more = kc + 1 < nkc;
-    if (more) {
-      load_state(kc + 1);
-#pragma unroll
-      for (int pl = 0; pl < 6; ++pl) An[pl] = act ? P[((int64_t)(kc + 1) * 6 + pl) * 64] : *zp;
-    }
+  for (int kc = 0; kc < nkc; kc += 2) {
+    load_state(kc + 1);
+    load_e(EB, kc + 1);
     __builtin_amdgcn_sched_barrier(0);
-    if (act) {
-      const v8bf er0 = as_bf(Ac[0]), ei0 = as_bf(Ac[1]), er1 = as_bf(Ac[2]);
-      const v8bf ei1 = as_bf(Ac[3]), er2 = as_bf(Ac[4]), ei2 = as_bf(Ac[5]);
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        const int col = nb * 16 + li;
-        const v8bf Xr0 = as_bf(*reinterpret_cast<const v8u16*>(&xb[buf][0][col][8 * lk]));
-        const v8bf Xr1 = as_bf(*reinterpret_cast<const v8u16*>(&xb[buf][1][col][8 * lk]));
-        const v8bf Xr2 = as_bf(*reinterpret_cast<const v8u16*>(&xb[buf][2][col][8 * lk]));
-        const v8bf Xi0 = as_bf(*reinterpret_cast<const v8u16*>(&xb[buf][3][col][8 * lk]));
-        const v8bf Xi1 = as_bf(*reinterpret_cast<const v8u16*>(&xb[buf][4][col][8 * lk]));
-        const v8bf Xi2 = as_bf(*reinterpret_cast<const v8u16*>(&xb[buf][5][col][8 * lk]));
-        rr[nb] = mma3(rr[nb], er0, er1, er2, Xr0, Xr1, Xr2);
-        ii[nb] = mma3(ii[nb], ei0, ei1, ei2, Xi0, Xi1, Xi2);
-        ri[nb] = mma3(ri[nb], er0, er1, er2, Xi0, Xi1, Xi2);
-        ir[nb] = mma3(ir[nb], ei0, ei1, ei2, Xr0, Xr1, Xr2);
-      }
-    }
-    if (more) {
-      store_state(buf ^ 1);
-#pragma unroll
-      for (int pl = 0; pl < 6; ++pl) Ac[pl] = An[pl];
-    }
+    if (act) mma(EA, 0);
+    __builtin_amdgcn_sched_barrier(0);
+    if (kc + 1 >= nkc) break;
+    store_state(1);
+    __syncthreads();
+    load_state(kc + 2);
+    load_e(EA, kc + 2);
+    __builtin_amdgcn_sched_barrier(0);
+    if (act) mma(EB, 1);
+    __builtin_amdgcn_sched_barrier(0);
+    if (kc + 2 >= nkc) break;
+    store_state(0);
     __syncthreads();
   }
   if (!act) return;

@@ -16,10 +16,12 @@ k1 = (a + b) c, k2 = a (d - c), k3 = b (c + d), FP32 accumulation over the fibre
   * the final subtraction of two such sums in FP32                                 -> 2u sqrt 2
   per element |y - y*|_a <= c_L (|E| |x|)_a with c_L = 2u + 4 sqrt(2) u + 4 gamma_{L+8},
   times sqrt 2 for combining the real and imaginary parts.
-BF16x3 path (E and x each split into three bf16 terms, round-to-nearest-even with 8
-significant bits, so each residual shrinks by 2^-8 and the dropped remainder is below
-2^-24 |.|; six of the nine cross products kept, the three dropped ones each below
-2^-24 |E| |x|; four real products per complex product, FP32 accumulation over 6 L terms):
+BF16x3 path (E split into three bf16 terms by round-to-nearest-even with 8 significant bits,
+remainder below 2^-24 |E|, |E1| <= 2^-9 |E|, |E2| <= 2^-18 |E|; x rounded to FP32 and then split
+exactly into three bf16 terms by truncation, |x1| < 2^-7 |x|, |x2| < 2^-14 |x| (the row-split
+kernel; the others split x by rounding, which is tighter); six of the nine cross products
+kept, the dropped E1 x2, E2 x1, E2 x2 together below (2^-23 + 2^-25 + 2^-32) |E| |x| < 3u;
+four real products per complex product, FP32 accumulation over 6 L terms):
   c_L = 2u + 3u + 2 gamma_{6L+8}, times sqrt 2.
 In the 2-norm: ||y - y*|| <= sqrt(2) c_Lmax || |E| ||_2 ||x||, with |E| the entrywise modulus.
 
