@@ -271,6 +271,28 @@ lsx_status lsx_plan_propagator(const lsx_plan* plan, int32_t layer, int32_t half
  */
 lsx_status lsx_plan_sharing(const lsx_plan* plan, int32_t layer, int32_t* ndistinct, int32_t* nsym);
 
+/*
+ * Band-limited products.  Over one step an entry P_ab of a fibre propagator arises only from
+ * chains of potential couplings linking rows a and b (eq. 3.6), each link of order t|v|, so
+ * the entries fall off fast away from the diagonal.  At plan creation the library records,
+ * for every block of 16 propagator rows, the range of column chunks (4 columns; 32 for
+ * LSX_MIX_BF16X3) that hold an entry with |Re| + |Im| >= tol in any of the plan's slots, and
+ * the fibre passes multiply only those chunks.  The entries left out change a pass by at most
+ * L tol relative to the state (L the fibre length).  Default tol: 2^-64 for LSX_FP64 (below the
+ * rounding of the products themselves), 2^-44 for the mixed precisions (far below their FP32
+ * rounding); lsx_plan_desc.band_tol chooses another, and the environment variable
+ * LSX_BAND_TOL overrides the default of lsx_plan_create (0: dense products).
+ * lsx_plan_band: *tol = the tolerance in use (0: dense), *kept = complex multiply-adds per state
+ * column of one pass of `layer` over all its fibres (rows times band width, inside the fibres),
+ * *dense = the same for dense products (sum of L^2).  Outputs may be NULL.  Host only.
+ */
+lsx_status lsx_plan_band(const lsx_plan* plan, int32_t layer, double* tol, int64_t* kept, int64_t* dense);
+/* The band of each 16-row block rb of one fibre (fibre order of lsx_fibre_get): lo_hi[2 rb] and
+ * lo_hi[2 rb + 1] = first and one past the last fibre position whose column the pass multiplies
+ * for those rows (multiples of 4, or of 32 for LSX_MIX_BF16X3; the padded fibre length at most).
+ * lo_hi holds 2 ceil(L / 16) int32.  Host only. */
+lsx_status lsx_plan_fibre_band(const lsx_plan* plan, int32_t layer, int32_t fibre, int32_t* lo_hi);
+
 /* Frees the plan.  LSX_E_STATE if states built on it are still alive. */
 lsx_status lsx_plan_destroy(lsx_plan* plan);
 
@@ -430,7 +452,9 @@ lsx_status lsx_observables_noalloc(lsx_plan* plan, const void* dev_c, int32_t W,
  *     cutoff (LSX_CUTOFF_BALL / LSX_CUTOFF_PRODUCT); per layer j = 0, 1: nv[j] coefficients,
  *     v_idx[j] (nv[j]*d int32), v_re[j], v_im[j].
  *   lsx_plan_desc: tau, scheme, kappa, precision as for lsx_plan_create; max_wavepackets > 0
- *     makes lsx_state_create / lsx_state_wrap refuse W above it (LSX_E_INVALID); 0: no limit.
+ *     makes lsx_state_create / lsx_state_wrap refuse W above it (LSX_E_INVALID); 0: no limit;
+ *     band_tol (see lsx_plan_band): 0 the default for the precision, < 0 dense products,
+ *     > 0 this tolerance; NaN is LSX_E_INVALID.
  * lsx_system_create_desc = lsx_system_create (host only).
  * lsx_index_size: *N = |I| (as lsx_system_size's N).
  * lsx_fibre_info: number of fibres of `layer` (1 .. nlayers) and, if `lengths` is not NULL,
@@ -457,6 +481,7 @@ typedef struct {
   double kappa;
   int32_t precision;
   int32_t max_wavepackets;
+  double band_tol;
 } lsx_plan_desc;
 lsx_status lsx_system_create_desc(const lsx_system_desc* desc, lsx_system** out);
 lsx_status lsx_index_size(const lsx_system* sys, int64_t* N);

@@ -33,6 +33,11 @@ static int env_int(const char* name, int dflt) {
   return v ? std::atoi(v) : dflt;
 }
 
+static double env_double(const char* name, double dflt) {
+  const char* v = std::getenv(name);
+  return (v && *v) ? std::atof(v) : dflt;
+}
+
 // ---------------------------------------------------------------- failure injection (tests)
 // LSX_TEST_FAIL_ALLOC=k makes the k-th device allocation counted from when the variable was
 // set (or last changed) report LSX_E_OOM; LSX_TEST_FAIL_EIG=1 makes the fibre eigensolver
@@ -618,11 +623,38 @@ struct LayerDev {
   DBuf<int32_t> nbr;
   DBuf<double2> v;  // stencil values (for the energy)
   PropSet prop[3];  // sub-step slots, times per scheme in scheme_times()
+  // Band of every 16-row block of every stored propagator, as fibre positions [lo, hi): row
+  // block rb of distinct propagator b is entry h_boff[b] + rb; the union over the layer's slots.
+  std::vector<int64_t> h_boff;
+  std::vector<int32_t> band_lo, band_hi;
 };
+
+// Band of row blocks [rb0, rb0 + n) of fibre f (those inside the fibre) as fibre positions
+// [k0, k1): the union of the blocks' bands.
+static void fibre_band(const LayerDev& ld, int f, int rb0, int n, int32_t& k0, int32_t& k1) {
+  const int L = ld.h_ptr[f + 1] - ld.h_ptr[f];
+  const int nrb = (L + 15) / 16;
+  k0 = kBandEnd;
+  k1 = 0;
+  if (!ld.h_boff.empty()) {
+    const int64_t base = ld.h_boff[ld.rep[f]];
+    for (int rb = rb0; rb < std::min(nrb, rb0 + n); ++rb) {
+      k0 = std::min(k0, ld.band_lo[base + rb]);
+      k1 = std::max(k1, ld.band_hi[base + rb]);
+    }
+  }
+  if (k1 <= k0) {
+    k0 = 0;
+    k1 = kBandEnd;
+  }
+}
 
 struct lsx_plan {
   lsx_system* sys = nullptr;
   double tau = 0.0, kappa = 0.0;
+  // propagator entries with |Re| + |Im| below band_tol are left out of the products, at the
+  // granularity of the storage's column chunks (0: every chunk is multiplied)
+  double band_tol = 0.0;
   int scheme = LSX_STRANG, precision = LSX_FP64, fmt = PF_F64;
   DBuf<double> K2;
   DBuf<double2> diag;  // mixed formats: per fibre-row diagonal, [layer*3+slot] blocks of N
@@ -1077,6 +1109,23 @@ static lsx_status precompute_layer(lsx_plan* pl, int layer, hipStream_t s) {
     ld.h_poff[f] = uoff[ld.rep[f]];
     ld.h_d0[f] = ft.ptr[uniq[ld.rep[f]]];
   }
+  // bands of the stored propagators, one entry per 16-row block, united over the slots
+  std::vector<int64_t> boff(nu + 1, 0);
+  for (int b = 0; b < nu; ++b) boff[b + 1] = boff[b] + (ft.ptr[uniq[b] + 1] - ft.ptr[uniq[b]] + 15) / 16;
+  const int64_t nband = boff[nu];
+  ld.h_boff = boff;
+  const bool banded = pl->band_tol > 0.0;
+  const int cw = band_chunk(pl->fmt);
+  ld.band_lo.assign(nband, banded ? kBandEnd : 0);
+  ld.band_hi.assign(nband, banded ? 0 : kBandEnd);
+  DBuf<int64_t> d_boff;
+  DBuf<int32_t> d_band;
+  std::vector<int32_t> hband;
+  if (banded) {
+    LSX_TRY(d_boff.upload(boff, s));
+    LSX_TRY(d_band.alloc((size_t)2 * nband));
+    hband.resize((size_t)2 * nband);
+  }
   const int flow = scheme_flow(pl->scheme);
   const SchemeTimes times = scheme_times(pl->scheme, pl->tau, sys->nl);
   for (int h = 0; h < 3; ++h) {
@@ -1092,13 +1141,25 @@ static lsx_status precompute_layer(lsx_plan* pl, int layer, hipStream_t s) {
     LSX_HIP_TRY(launch_form(s, pl->fmt, nu, maxL, d_fid.p, ld.ptr.p, VT.p, d_moff.p, d_ndim.p, d_emb.p, gh.p,
                             d_loff.p, ps.data.p, ps.off.p, dg));
     ps.present = true;
+    if (banded && nband > 0) {
+      LSX_HIP_TRY(launch_band(s, pl->fmt, nu, d_fid.p, ld.ptr.p, ps.data.p, ps.off.p, d_boff.p, pl->band_tol,
+                              d_band.p));
+      LSX_HIP_TRY(hipMemcpyAsync(hband.data(), d_band.p, hband.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      LSX_HIP_TRY(hipStreamSynchronize(s));
+      for (int64_t i = 0; i < nband; ++i) {
+        ld.band_lo[i] = std::min(ld.band_lo[i], hband[2 * i] * cw);
+        ld.band_hi[i] = std::max(ld.band_hi[i], hband[2 * i + 1] * cw);
+      }
+    }
   }
   LSX_HIP_TRY(hipStreamSynchronize(s));
   return LSX_OK;
 }
 
-extern "C" lsx_status lsx_plan_create(lsx_system* sys, double tau, int32_t scheme, double kappa,
-                                      int32_t precision, void* stream, lsx_plan** out) {
+// band_req: 0 the default tolerance for the precision (LSX_BAND_TOL overrides it), < 0 dense
+// products, > 0 that tolerance.
+static lsx_status plan_create(lsx_system* sys, double tau, int32_t scheme, double kappa, int32_t precision,
+                              double band_req, void* stream, lsx_plan** out) {
   if (!sys || !out) return fail(LSX_E_INVALID, "null argument");
   if (!std::isfinite(tau) || tau == 0.0) return fail(LSX_E_INVALID, "tau must be finite and nonzero");
   if (scheme != LSX_LIE && scheme != LSX_STRANG && scheme != LSX_LIE_BE && scheme != LSX_STRANG_CN &&
@@ -1116,6 +1177,15 @@ extern "C" lsx_status lsx_plan_create(lsx_system* sys, double tau, int32_t schem
   pl->scheme = scheme;
   pl->precision = precision;
   pl->fmt = precision == LSX_FP64 ? PF_F64 : (precision == LSX_MIX_FP32 ? PF_F32 : PF_BF16X3);
+  // Band tolerance: for FP64, 2^-64, so the entries left out change a pass by at most L 2^-64
+  // relative (below the rounding of the products themselves); for the mixed paths, 2^-44, at
+  // most L 2^-44 per pass (about 5e-11 for fibres of 900 rows), far below the FP32 rounding of
+  // the entries that are kept.  LSX_BAND_TOL overrides it (0: dense products).
+  if (band_req > 0.0)
+    pl->band_tol = band_req;
+  else if (band_req == 0.0)
+    pl->band_tol = env_double("LSX_BAND_TOL", pl->fmt == PF_F64 ? std::ldexp(1.0, -64) : std::ldexp(1.0, -44));
+  if (!(pl->band_tol >= 0.0)) pl->band_tol = 0.0;
   auto cleanup = [&](lsx_status st) {
     delete pl;
     return st;
@@ -1182,12 +1252,18 @@ extern "C" lsx_status lsx_plan_create(lsx_system* sys, double tau, int32_t schem
   return LSX_OK;
 }
 
+extern "C" lsx_status lsx_plan_create(lsx_system* sys, double tau, int32_t scheme, double kappa,
+                                      int32_t precision, void* stream, lsx_plan** out) {
+  return plan_create(sys, tau, scheme, kappa, precision, 0.0, stream, out);
+}
+
 extern "C" lsx_status lsx_plan_create_desc(lsx_system* sys, const lsx_plan_desc* desc, void* stream,
                                            lsx_plan** out) {
   if (!desc) return fail(LSX_E_INVALID, "null descriptor");
   if (desc->max_wavepackets < 0) return fail(LSX_E_INVALID, "max_wavepackets must be >= 0");
+  if (std::isnan(desc->band_tol)) return fail(LSX_E_INVALID, "band_tol must not be NaN");
   lsx_plan* pl = nullptr;
-  LSX_TRY(lsx_plan_create(sys, desc->tau, desc->scheme, desc->kappa, desc->precision, stream, &pl));
+  LSX_TRY(plan_create(sys, desc->tau, desc->scheme, desc->kappa, desc->precision, desc->band_tol, stream, &pl));
   pl->max_w = desc->max_wavepackets;
   *out = pl;
   return LSX_OK;
@@ -1273,6 +1349,42 @@ extern "C" lsx_status lsx_plan_sharing(const lsx_plan* pl, int32_t layer, int32_
   return LSX_OK;
 }
 
+extern "C" lsx_status lsx_plan_band(const lsx_plan* pl, int32_t layer, double* tol, int64_t* kept,
+                                    int64_t* dense) {
+  if (!pl) return fail(LSX_E_INVALID, "null plan");
+  if (layer < 1 || layer > pl->sys->nl) return fail(LSX_E_INVALID, "layer out of range");
+  const LayerDev& ld = pl->L[layer - 1];
+  int64_t k = 0, d = 0;
+  for (int f = 0; f < ld.nf; ++f) {
+    const int L = ld.h_ptr[f + 1] - ld.h_ptr[f];
+    d += (int64_t)L * L;
+    for (int rb = 0; rb < (L + 15) / 16; ++rb) {
+      int32_t k0, k1;
+      fibre_band(ld, f, rb, 1, k0, k1);
+      k += (int64_t)std::min(16, L - 16 * rb) * (std::min(k1, L) - k0);
+    }
+  }
+  if (tol) *tol = pl->band_tol;
+  if (kept) *kept = k;
+  if (dense) *dense = d;
+  return LSX_OK;
+}
+
+extern "C" lsx_status lsx_plan_fibre_band(const lsx_plan* pl, int32_t layer, int32_t fibre, int32_t* lo_hi) {
+  if (!pl || !lo_hi) return fail(LSX_E_INVALID, "null argument");
+  if (layer < 1 || layer > pl->sys->nl) return fail(LSX_E_INVALID, "layer out of range");
+  const LayerDev& ld = pl->L[layer - 1];
+  if (fibre < 0 || fibre >= ld.nf) return fail(LSX_E_INVALID, "fibre out of range");
+  const int L = ld.h_ptr[fibre + 1] - ld.h_ptr[fibre];
+  for (int rb = 0; rb < (L + 15) / 16; ++rb) {
+    int32_t k0, k1;
+    fibre_band(ld, fibre, rb, 1, k0, k1);
+    lo_hi[2 * rb] = k0;
+    lo_hi[2 * rb + 1] = std::min(k1, round_up(L, prop_pad(pl->fmt)));
+  }
+  return LSX_OK;
+}
+
 extern "C" lsx_status lsx_plan_destroy(lsx_plan* pl) {
   if (!pl) return LSX_OK;
   if (pl->nstates > 0) return fail(LSX_E_STATE, "plan still has live states");
@@ -1335,8 +1447,10 @@ static void build_tiles(const lsx_plan* pl, int layer, int W, int nb, int wb0, i
     for (int y = 1; y < NX; ++y)
       if (count[y] < count[x] || (count[y] == count[x] && load[y] < load[x])) x = y;
     count[x] += (int64_t)nrb * wt;
-    load[x] += (double)nrb * wt * (L + 8);
-    for (int rb = 0; rb < nrb; ++rb)
+    for (int rb = 0; rb < nrb; ++rb) {
+      int32_t k0, k1;
+      fibre_band(ld, f, rb * ms, ms, k0, k1);
+      load[x] += (double)wt * (std::min(k1, L) - k0 + 8);
       for (int wb = wb0; wb < wb1; ++wb) {
         TileDesc t;
         t.r0 = ld.h_ptr[f];
@@ -1346,8 +1460,11 @@ static void build_tiles(const lsx_plan* pl, int layer, int W, int nb, int wb0, i
         t.poff = ld.h_poff.empty() ? 0 : ld.h_poff[f];
         t.f = f;
         t.d0 = ld.h_d0.empty() ? ld.h_ptr[f] : ld.h_d0[f];
+        t.k0 = k0;
+        t.k1 = k1;
         bins[x].push_back(t);
       }
+    }
   }
   TileDesc empty{};
   empty.f = -1;
@@ -2211,8 +2328,10 @@ static void batch_tiles(const lsx_batch* b, int layer, int nb, std::vector<TileD
     for (int y = 1; y < NX; ++y)
       if (count[y] < count[x] || (count[y] == count[x] && load[y] < load[x])) x = y;
     count[x] += (int64_t)nrb * wt;
-    load[x] += (double)nrb * wt * (it.L + 8);
-    for (int rb = 0; rb < nrb; ++rb)
+    for (int rb = 0; rb < nrb; ++rb) {
+      int32_t k0, k1;
+      fibre_band(ld, it.f, rb, 1, k0, k1);
+      load[x] += (double)wt * (std::min(k1, it.L) - k0 + 8);
       for (int wb = 0; wb < wt; ++wb) {
         TileDesc t;
         t.r0 = ld.h_ptr[it.f];
@@ -2222,8 +2341,11 @@ static void batch_tiles(const lsx_batch* b, int layer, int nb, std::vector<TileD
         t.poff = ld.h_poff[it.f];
         t.f = it.sys;
         t.d0 = ld.h_d0[it.f];
+        t.k0 = k0;
+        t.k1 = k1;
         bins[x].push_back(t);
       }
+    }
   }
   TileDesc empty{};
   empty.f = -1;

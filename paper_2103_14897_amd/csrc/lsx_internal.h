@@ -47,15 +47,22 @@ inline int64_t prop_bytes(int fmt, int L) {
   }
 }
 
-// Tile of a fibre pass (32 bytes, read with one scalar load): fibre f starting at
-// fibre position r0 with length L, output rows 16*rb.., columns 16*NB*wb.., the byte
-// offset of the fibre's propagator and of its diagonal.  f < 0 marks a padding tile.
+// Tile of a fibre pass (40 bytes, read with scalar loads): fibre f starting at fibre
+// position r0 with length L, output rows 16*rb.., columns 16*NB*wb.., the byte offset of
+// the fibre's propagator and of its diagonal, and the band [k0, k1) of fibre positions
+// whose propagator columns hold an entry above the plan's band tolerance for any of the
+// tile's rows (multiples of the format's column chunk; the kernels clamp k1 to the padded
+// fibre length, so k1 = INT32_MAX means "to the end").  f < 0 marks a padding tile.
 struct TileDesc {
   int32_t r0, L, rb, wb;
   int64_t poff;
   int32_t f;
   int32_t d0;  // mixed formats: position of this propagator's diagonal (fibres may share one)
+  int32_t k0, k1;
 };
+constexpr int32_t kBandEnd = 0x7fffffff;
+// columns per propagator chunk of a format (the unit of the band)
+inline int band_chunk(int fmt) { return fmt == PF_BF16X3 ? 32 : 4; }
 
 struct PassArgs;
 // Arguments of every fibre-pass kernel.  Element k of fibre f (fibre position
@@ -134,6 +141,11 @@ hipError_t launch_eig_fn(hipStream_t s, int64_t nlam, const double* lam, double 
 hipError_t launch_form(hipStream_t s, int fmt, int nb, int maxL, const int32_t* fid, const int32_t* ptr,
                        const double* VT, const int64_t* moff, const int32_t* ndim, const int32_t* embed,
                        const double2* gh, const int64_t* loff, void* P, const int64_t* poff, double2* diag);
+// Band of every 16-row block of every stored propagator (k_band): band[2 (boff[b] + rb)] and
+// band[2 (boff[b] + rb) + 1] = first and one past the last column chunk with an entry whose
+// |Re| + |Im| >= tol (a block with none keeps its diagonal chunk).
+hipError_t launch_band(hipStream_t s, int fmt, int nb, const int32_t* fid, const int32_t* ptr, const void* P,
+                       const int64_t* poff, const int64_t* boff, double tol, int32_t* band);
 hipError_t launch_phase_table(hipStream_t s, int64_t N, const double* K2, double theta_scale, double2* ph);
 hipError_t launch_phase_apply(hipStream_t s, int64_t N, int W, const double2* ph, double2* c);
 hipError_t launch_pass(hipStream_t s, int fmt, int W, int ntiles, int nb, int ksplit, const PassArgs& a,

@@ -578,6 +578,67 @@ __global__ void k_form(const int32_t* fid, const int32_t* ptr, const double* VTa
   }
 }
 
+// ---------------------------------------------------------------- propagator bands
+// Over one short step an entry P_ab of a fibre propagator is reached only through chains of
+// potential couplings from a to b, each link carrying a factor of order t|v|, so the entries
+// fall off quickly away from the diagonal and most column chunks of a row block hold nothing
+// a product could feel.  For every 16-row block of every stored propagator this records the
+// first and one past the last column chunk (4 columns; 32 for the BF16x3 format) that holds an
+// entry with |Re| + |Im| >= tol (for BF16x3 the sum over the three terms' magnitudes bounds
+// the entry); a block with no such entry keeps its diagonal chunk.  One workgroup per stored
+// propagator; wave w takes row blocks w, w + 4, ...
+template <int FMT>
+__global__ __launch_bounds__(256) void k_band(const int32_t* fid, const int32_t* ptr, const void* Pall,
+                                              const int64_t* poff, const int64_t* boff, double tol,
+                                              int32_t* band) {
+  constexpr int CW = FMT == PF_BF16X3 ? 32 : 4;
+  const int b = blockIdx.x;
+  const int f = fid[b];
+  const int L = ptr[f + 1] - ptr[f];
+  const int Lp = FMT == PF_BF16X3 ? (L + 31) & ~31 : (L + 15) & ~15;
+  const int nc = Lp / CW, nrb = (L + 15) >> 4;
+  const int lane = threadIdx.x & 63;
+  const char* P = reinterpret_cast<const char*>(Pall) + poff[b];
+  for (int rb = threadIdx.x >> 6; rb < nrb; rb += blockDim.x >> 6) {
+    int lo = -1, hi = -1;
+    for (int kc = 0; kc < nc; ++kc) {
+      const int64_t ch = (int64_t)rb * nc + kc;
+      bool big = false;
+      if (FMT == PF_F64) {
+        const double2 v = reinterpret_cast<const double2*>(P)[ch * 64 + lane];
+        big = fabs(v.x) + fabs(v.y) >= tol;
+      } else if (FMT == PF_F32) {
+        const float2 v = reinterpret_cast<const float2*>(P)[ch * 64 + lane];
+        big = (double)fabsf(v.x) + (double)fabsf(v.y) >= tol;
+      } else {
+        const v8u16* Q = reinterpret_cast<const v8u16*>(P) + ch * 6 * 64 + lane;
+        v8u16 pl[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) pl[k] = Q[k * 64];
+#pragma unroll
+        for (int el = 0; el < 8; ++el) {
+          double m = 0.0;
+#pragma unroll
+          for (int k = 0; k < 6; ++k) m += fabs((double)bf2f(pl[k][el]));
+          big = big || m >= tol;
+        }
+      }
+      if (__any(big)) {
+        if (lo < 0) lo = kc;
+        hi = kc + 1;
+      }
+    }
+    if (lo < 0) {
+      lo = (16 * rb) / CW;
+      hi = lo + 1;
+    }
+    if (lane == 0) {
+      band[2 * (boff[b] + rb)] = lo;
+      band[2 * (boff[b] + rb) + 1] = hi;
+    }
+  }
+}
+
 // ---------------------------------------------------------------- kinetic phase
 __global__ void k_phase_table(int64_t N, const double* K2, double scale, double2* ph) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -712,6 +773,13 @@ __device__ __forceinline__ void pass_epilogue(const PassArgs& a, const TileDesc&
 
 __device__ __forceinline__ int64_t in_row(const PassArgs& a, int p) { return a.in_pos ? a.in_pos[p] : p; }
 
+// Band of a tile in units of `unit` fibre positions (4 for a k-step of the FP64 / FP32
+// products, 32 for a BF16x3 chunk): [lo, hi), clamped to the padded fibre length Lp.
+__device__ __forceinline__ void tile_band(const TileDesc& t, int Lp, int unit, int& lo, int& hi) {
+  lo = t.k0 / unit;
+  hi = (min(t.k1, Lp) + unit - 1) / unit;
+}
+
 // Operand loads of one group of U k-steps (4 fibre positions each) for the FP64/FP32
 // kernels: propagator chunk per k-step (A operand) and NB state values (B operand).
 template <typename PT, int NB, int U>
@@ -720,8 +788,8 @@ struct Group4 {
   double2 x[U][NB];
 };
 
-// All operand loads are unconditional: an out-of-range operand (k-step past the
-// fibre, column past W) is read from a zeroed buffer instead, so the address is
+// All operand loads are unconditional: an out-of-range operand (k-step past the tile's
+// band end kend, column past W) is read from a zeroed buffer instead, so the address is
 // selected, not the value, and no loaded value is consumed before the MFMAs that need
 // it -- the loads of the next group stay in flight during the current group.
 // GATHER: element k of the fibre is row in_pos[r0 + k] of X, else row r0 + k.
@@ -731,15 +799,15 @@ __device__ __forceinline__ int64_t xrow(const PassArgs& a, int p) {
 }
 
 template <bool GATHER, typename PT, int NB, int U>
-__device__ __forceinline__ void load_group4(Group4<PT, NB, U>& G, const PassArgs& a, const PT* P, int g, int nks,
+__device__ __forceinline__ void load_group4(Group4<PT, NB, U>& G, const PassArgs& a, const PT* P, int g, int kend,
                                             int r0, int L, int lk, const int (&wc)[NB], const bool (&wok)[NB]) {
   const PT* zp = reinterpret_cast<const PT*>(a.zero);
   const double2* zx = reinterpret_cast<const double2*>(a.zero);
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const int ks = g + u, k = 4 * ks + lk;
-    G.p[u] = *((ks < nks) ? P + (int64_t)ks * 64 : zp);
-    const bool ok = ks < nks && k < L;
+    G.p[u] = *((ks < kend) ? P + (int64_t)ks * 64 : zp);
+    const bool ok = ks < kend && k < L;
     const int64_t row = xrow<GATHER>(a, r0 + (ok ? k : 0));
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) G.x[u][nb] = *((ok && wok[nb]) ? a.X + row * a.W + wc[nb] : zx);
@@ -843,14 +911,16 @@ __device__ __forceinline__ void k_pass_f64_tile(const PassArgs& a0, int ti, doub
   // two register buffers in ping-pong: B is loaded while A is consumed and vice versa
   Group4<double2, NB, U> A, B;
   const int stride = KS * U;
-  int g = kw * U;
-  load_group4<GATHER>(A, a, P, g, nks, r0, L, lk, wc, wok);
-  for (; g < nks; g += 2 * stride) {
-    load_group4<GATHER>(B, a, P, g + stride, nks, r0, L, lk, wc, wok);  // past the end: zeros
+  int klo, khi;
+  tile_band(t, 4 * nks, 4, klo, khi);
+  int g = klo + kw * U;
+  load_group4<GATHER>(A, a, P, g, khi, r0, L, lk, wc, wok);
+  for (; g < khi; g += 2 * stride) {
+    load_group4<GATHER>(B, a, P, g + stride, khi, r0, L, lk, wc, wok);  // past the band: zeros
     __builtin_amdgcn_sched_barrier(0);
     mma_group_f64(k1, k2, k3, A);
-    if (g + stride >= nks) break;
-    load_group4<GATHER>(A, a, P, g + 2 * stride, nks, r0, L, lk, wc, wok);
+    if (g + stride >= khi) break;
+    load_group4<GATHER>(A, a, P, g + 2 * stride, khi, r0, L, lk, wc, wok);
     __builtin_amdgcn_sched_barrier(0);
     mma_group_f64(k1, k2, k3, B);
   }
@@ -900,14 +970,16 @@ __device__ __forceinline__ void k_pass_f32_tile(const PassArgs& a0, int ti, doub
   for (int nb = 0; nb < NB; ++nb) k1[nb] = k2[nb] = k3[nb] = (v4f){0.f, 0.f, 0.f, 0.f};
   Group4<float2, NB, U> A, B;
   const int stride = KS * U;
-  int g = kw * U;
-  load_group4<GATHER>(A, a, P, g, nks, r0, L, lk, wc, wok);
-  for (; g < nks; g += 2 * stride) {
-    load_group4<GATHER>(B, a, P, g + stride, nks, r0, L, lk, wc, wok);  // past the end: zeros
+  int klo, khi;
+  tile_band(t, 4 * nks, 4, klo, khi);
+  int g = klo + kw * U;
+  load_group4<GATHER>(A, a, P, g, khi, r0, L, lk, wc, wok);
+  for (; g < khi; g += 2 * stride) {
+    load_group4<GATHER>(B, a, P, g + stride, khi, r0, L, lk, wc, wok);  // past the band: zeros
     __builtin_amdgcn_sched_barrier(0);
     mma_group_f32(k1, k2, k3, A);
-    if (g + stride >= nks) break;
-    load_group4<GATHER>(A, a, P, g + 2 * stride, nks, r0, L, lk, wc, wok);
+    if (g + stride >= khi) break;
+    load_group4<GATHER>(A, a, P, g + 2 * stride, khi, r0, L, lk, wc, wok);
     __builtin_amdgcn_sched_barrier(0);
     mma_group_f32(k1, k2, k3, B);
   }
@@ -977,7 +1049,10 @@ __global__ __launch_bounds__(64 * MS) void k_pass_f32m(PassArgs a) {
   if (t0.f < 0) return;
   const int r0 = t0.r0, L = t0.L;
   const int nks = ((L + 15) & ~15) >> 2;
-  const int nch = (nks + KC - 1) / KC;  // k-steps past nks read zeros
+  // chunks [clo, clo + nch) cover the tile's band; k-steps past nks read zeros
+  int clo, nch;
+  tile_band(t0, 4 * nks, SM::CR, clo, nch);
+  nch -= clo;
   const int lane = threadIdx.x & 63, kw = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int li = lane & 15, lk = lane >> 4;
   TileDesc t = t0;
@@ -1004,10 +1079,11 @@ __global__ __launch_bounds__(64 * MS) void k_pass_f32m(PassArgs a) {
   for (int nb = 0; nb < NB; ++nb) k1[nb] = k2[nb] = k3[nb] = (v4f){0.f, 0.f, 0.f, 0.f};
   double2 sv[SM::PER];
   float2 Ac[KC], An[KC];
-  // chunks in the order c0, c0 + 1, ... (mod nch), with the workgroup's own rows last: the
-  // epilogue's FP64 reload of those rows then finds them in this XCD's L2, just staged
-  const int c0 = ((t0.rb + 1) * MS * 16 / SM::CR) % nch;
-  auto chunk = [&](int i) { return i + c0 < nch ? i + c0 : i + c0 - nch; };
+  // chunks of the band in the order c0, c0 + 1, ... (cyclically), with the workgroup's own
+  // rows last: the epilogue's FP64 reload of those rows then finds them in this XCD's L2,
+  // just staged
+  const int c0 = (((t0.rb + 1) * MS * 16 / SM::CR - clo) % nch + nch) % nch;
+  auto chunk = [&](int i) { return clo + (i + c0 < nch ? i + c0 : i + c0 - nch); };
   stage_load_f32<SM::PER, SM::RSTEP, SM::CR, GATHER>(sv, a, chunk(0), r0, L, sw, sok, rr0);
 #pragma unroll
   for (int u = 0; u < KC; ++u) {
@@ -1081,9 +1157,9 @@ struct ChunkBF {
 };
 
 template <bool GATHER, int NB>
-__device__ __forceinline__ void load_chunk_bf(ChunkBF<NB>& C, const PassArgs& a, const v8u16* P, int kc, int nkc,
+__device__ __forceinline__ void load_chunk_bf(ChunkBF<NB>& C, const PassArgs& a, const v8u16* P, int kc, int kend,
                                               int r0, int L, int lk, const int (&wc)[NB], const bool (&wok)[NB]) {
-  const bool kin = kc < nkc;
+  const bool kin = kc < kend;
   const v8u16* zp = reinterpret_cast<const v8u16*>(a.zero);
   const double2* zx = reinterpret_cast<const double2*>(a.zero);
 #pragma unroll
@@ -1154,14 +1230,16 @@ __device__ __forceinline__ void k_pass_bf16x3_tile(const PassArgs& a0, int ti, d
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) rr[nb] = ii[nb] = ri[nb] = ir[nb] = (v4f){0.f, 0.f, 0.f, 0.f};
   ChunkBF<NB> A, B;
-  int kc = kw;
-  load_chunk_bf<GATHER>(A, a, P, kc, nkc, r0, L, lk, wc, wok);
-  for (; kc < nkc; kc += 2 * KS) {
-    load_chunk_bf<GATHER>(B, a, P, kc + KS, nkc, r0, L, lk, wc, wok);  // past the end: zeros
+  int klo, khi;
+  tile_band(t, 32 * nkc, 32, klo, khi);
+  int kc = klo + kw;
+  load_chunk_bf<GATHER>(A, a, P, kc, khi, r0, L, lk, wc, wok);
+  for (; kc < khi; kc += 2 * KS) {
+    load_chunk_bf<GATHER>(B, a, P, kc + KS, khi, r0, L, lk, wc, wok);  // past the band: zeros
     __builtin_amdgcn_sched_barrier(0);
     mma_chunk_bf(rr, ii, ri, ir, A);
-    if (kc + KS >= nkc) break;
-    load_chunk_bf<GATHER>(A, a, P, kc + 2 * KS, nkc, r0, L, lk, wc, wok);
+    if (kc + KS >= khi) break;
+    load_chunk_bf<GATHER>(A, a, P, kc + 2 * KS, khi, r0, L, lk, wc, wok);
     __builtin_amdgcn_sched_barrier(0);
     mma_chunk_bf(rr, ii, ri, ir, B);
   }
@@ -1266,9 +1344,12 @@ __global__ __launch_bounds__(64 * MS) void k_pass_bf16m(PassArgs a) {
       xb[buf][5][c][k] = q5;
     }
   };
-  // this wave's propagator planes of chunk kc (E re/im terms 0..2), zeros past the fibre
+  // the tile's band of chunks [klo, khi)
+  int klo, khi;
+  tile_band(t0, 32 * nkc, 32, klo, khi);
+  // this wave's propagator planes of chunk kc (E re/im terms 0..2), zeros past the band
   auto load_e = [&](v8bf (&E)[6], int kc) {
-    const bool in = act && kc < nkc;
+    const bool in = act && kc < khi;
 #pragma unroll
     for (int pl = 0; pl < 6; ++pl) {
       int64_t off = ((int64_t)kc * 6 + pl) * 64;
@@ -1298,17 +1379,17 @@ __global__ __launch_bounds__(64 * MS) void k_pass_bf16m(PassArgs a) {
   // Ping-pong operand buffers over pairs of chunks: chunk kc multiplies EA (or EB) while the
   // next chunk's state values and planes load into sv and EB (or EA); no register copies.
   v8bf EA[6], EB[6];
-  load_state(0);
-  load_e(EA, 0);
+  load_state(klo);
+  load_e(EA, klo);
   store_state(0);
   __syncthreads();
-  for (int kc = 0; kc < nkc; kc += 2) {
+  for (int kc = klo; kc < khi; kc += 2) {
     load_state(kc + 1);
     load_e(EB, kc + 1);
     __builtin_amdgcn_sched_barrier(0);
     if (act) mma(EA, 0);
     __builtin_amdgcn_sched_barrier(0);
-    if (kc + 1 >= nkc) break;
+    if (kc + 1 >= khi) break;
     store_state(1);
     __syncthreads();
     load_state(kc + 2);
@@ -1316,7 +1397,7 @@ __global__ __launch_bounds__(64 * MS) void k_pass_bf16m(PassArgs a) {
     __builtin_amdgcn_sched_barrier(0);
     if (act) mma(EB, 1);
     __builtin_amdgcn_sched_barrier(0);
-    if (kc + 2 >= nkc) break;
+    if (kc + 2 >= khi) break;
     store_state(0);
     __syncthreads();
   }
@@ -1356,7 +1437,9 @@ __device__ __forceinline__ void k_gemv_tile(const PassArgs& a0, int ti, double* 
     const int rb = t.rb;
     const int nkc = ((L + 31) & ~31) >> 5;
     const v8u16* P = reinterpret_cast<const v8u16*>(Pb) + (int64_t)rb * nkc * 6 * 64 + lane;
-    for (int kc = kw; kc < nkc; kc += KS) {
+    int klo, khi;
+    tile_band(t, 32 * nkc, 32, klo, khi);
+    for (int kc = klo + kw; kc < khi; kc += KS) {
       const v8u16* Pc = P + (int64_t)kc * 6 * 64;
       const v8u16 r0v = Pc[0], i0v = Pc[64], r1v = Pc[128], i1v = Pc[192], r2v = Pc[256], i2v = Pc[320];
 #pragma unroll
@@ -1390,8 +1473,10 @@ __device__ __forceinline__ void k_gemv_tile(const PassArgs& a0, int ti, double* 
       const int rbj = t.rb * RB + j;
       Pj[j] = (j == 0 || rbj < nrb) ? reinterpret_cast<const PT*>(Pb) + (int64_t)rbj * nks * 64 + lane : nullptr;
     }
-    int ks = kw;
-    for (; ks + (G - 1) * KS < nks; ks += G * KS) {
+    int klo, khi;
+    tile_band(t, 4 * nks, 4, klo, khi);
+    int ks = klo + kw;
+    for (; ks + (G - 1) * KS < khi; ks += G * KS) {
       PT p[RB][G];
       double2 x[G];
 #pragma unroll
@@ -1411,7 +1496,7 @@ __device__ __forceinline__ void k_gemv_tile(const PassArgs& a0, int ti, double* 
           yi[j] += pr * x[g].y + pi * x[g].x;
         }
     }
-    for (; ks < nks; ks += KS) {
+    for (; ks < khi; ks += KS) {
       const int k = 4 * ks + lk;
       const bool ok = k < L;
       const double2 x = *(ok ? a.X + in_row(a, r0 + (ok ? k : 0)) : zx);
@@ -1624,6 +1709,18 @@ hipError_t launch_jacobi(hipStream_t s, int nf, int maxn, double* A, double* VT,
 hipError_t launch_eig_fn(hipStream_t s, int64_t nlam, const double* lam, double t, int flow, double2* gh) {
   if (nlam == 0) return hipSuccess;
   hipLaunchKernelGGL(k_eig_fn, dim3((unsigned)((nlam + 255) / 256)), dim3(256), 0, s, nlam, lam, t, flow, gh);
+  return hipGetLastError();
+}
+
+hipError_t launch_band(hipStream_t s, int fmt, int nb, const int32_t* fid, const int32_t* ptr, const void* P,
+                       const int64_t* poff, const int64_t* boff, double tol, int32_t* band) {
+  if (nb == 0) return hipSuccess;
+  if (fmt == PF_F64)
+    hipLaunchKernelGGL(k_band<PF_F64>, dim3(nb), dim3(256), 0, s, fid, ptr, P, poff, boff, tol, band);
+  else if (fmt == PF_F32)
+    hipLaunchKernelGGL(k_band<PF_F32>, dim3(nb), dim3(256), 0, s, fid, ptr, P, poff, boff, tol, band);
+  else
+    hipLaunchKernelGGL(k_band<PF_BF16X3>, dim3(nb), dim3(256), 0, s, fid, ptr, P, poff, boff, tol, band);
   return hipGetLastError();
 }
 

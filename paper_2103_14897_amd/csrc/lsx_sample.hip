@@ -261,6 +261,8 @@ __global__ __launch_bounds__(256) void k_emit_tiles(int NB, const int32_t* ptr, 
     t.poff = poff ? poff[f] : 0;
     t.f = f;
     t.d0 = d0 ? d0[f] : r0;
+    t.k0 = 0;  // the whole fibre: sampled passes take no band
+    t.k1 = kBandEnd;
     out[off[f] + k] = t;
   }
 }

@@ -90,6 +90,8 @@ _SIGS = {
     "lsx_mlp_destroy": (C.c_int, [_p]),
     "lsx_live_buffers": (C.c_int, [_i64p, _i64p]),
     "lsx_plan_sharing": (C.c_int, [_p, C.c_int32, _i32p, _i32p]),
+    "lsx_plan_band": (C.c_int, [_p, C.c_int32, _dp, _i64p, _i64p]),
+    "lsx_plan_fibre_band": (C.c_int, [_p, C.c_int32, C.c_int32, _i32p]),
     "lsx_system_symmetries": (C.c_int, [_p, _i32p, _i32p]),
     "lsx_observables_noalloc": (C.c_int, [_p, _p, C.c_int32, C.c_uint32, _p, _p]),
     "lsx_state_set_tuning": (C.c_int, [_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
@@ -112,7 +114,7 @@ class SystemDesc(C.Structure):
 class PlanDesc(C.Structure):
     """lsx_plan_desc of include/lsx.h."""
     _fields_ = [("tau", C.c_double), ("scheme", C.c_int32), ("kappa", C.c_double), ("precision", C.c_int32),
-                ("max_wavepackets", C.c_int32)]
+                ("max_wavepackets", C.c_int32), ("band_tol", C.c_double)]
 
 
 def live_buffers():
@@ -338,17 +340,33 @@ class Plan:
     """lsx_plan: one-time fibre eigendecomposition and propagators on the GPU."""
 
     def __init__(self, system, tau, scheme="strang", kappa=0.0, precision="fp64", stream=None,
-                 max_wavepackets=None):
+                 max_wavepackets=None, band_tol=None):
+        """band_tol: None or 0 the library's default, < 0 dense products, > 0 that tolerance."""
         self.system = system
         self.tau, self.scheme, self.kappa, self.precision = float(tau), scheme, float(kappa), precision
         h = _p()
-        if max_wavepackets is None:
+        if max_wavepackets is None and band_tol is None:
             _check(lib().lsx_plan_create(system.h, self.tau, SCHEME[scheme], self.kappa, PRECISION[precision],
                                          _stream(stream), C.byref(h)))
         else:
-            desc = PlanDesc(self.tau, SCHEME[scheme], self.kappa, PRECISION[precision], int(max_wavepackets))
+            desc = PlanDesc(self.tau, SCHEME[scheme], self.kappa, PRECISION[precision], int(max_wavepackets or 0),
+                            float(band_tol or 0.0))
             _check(lib().lsx_plan_create_desc(system.h, C.byref(desc), _stream(stream), C.byref(h)))
         self.h = h
+
+    def band(self, layer):
+        """(tolerance in use, complex multiply-adds per column of one layer pass, the dense count)."""
+        tol, kept, dense = C.c_double(), C.c_int64(), C.c_int64()
+        _check(lib().lsx_plan_band(self.h, int(layer), C.byref(tol), C.byref(kept), C.byref(dense)))
+        return tol.value, kept.value, dense.value
+
+    def fibre_band(self, layer, fibre):
+        """[nrb, 2] int32: first and one past the last multiplied fibre position per 16-row block."""
+        ptr, _ = self.system.fibres(layer)
+        L = int(ptr[fibre + 1] - ptr[fibre])
+        out = np.zeros(((L + 15) // 16, 2), dtype=np.int32)
+        _check(lib().lsx_plan_fibre_band(self.h, int(layer), int(fibre), out.ctypes.data_as(_i32p)))
+        return out
 
     def sharing(self, layer):
         """(distinct propagators stored for `layer`, point symmetries shared over)."""

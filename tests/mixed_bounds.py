@@ -25,6 +25,11 @@ four real products per complex product, FP32 accumulation over 6 L terms):
   c_L = 2u + 3u + 2 gamma_{6L+8}, times sqrt 2.
 In the 2-norm: ||y - y*|| <= sqrt(2) c_Lmax || |E| ||_2 ||x||, with |E| the entrywise modulus.
 
+Band-limited products (lsx_plan_band): the passes leave out propagator chunks whose entries
+all have |Re| + |Im| < tol (2^-44 by default on the mixed paths).  The left-out part B of a
+fibre's E has at most L^2 entries below tol, so ||B||_2 <= ||B||_F <= L tol, which adds
+Lmax tol to the relative bound of a pass.
+
 Every pass is otherwise unitary (exact flows, FP64 diagonal and phase), so an error made in
 one pass is carried by the later passes without growth: after a sequence of passes the
 relative error against FP64 arithmetic is at most the sum of the per-pass bounds.  The FP64
@@ -35,14 +40,16 @@ import math
 import numpy as np
 
 U32 = 2.0 ** -24
+BAND_TOL_MIXED = 2.0 ** -44  # the library's default band tolerance of the mixed paths
 
 
 def gamma(n):
     return n * U32 / (1.0 - n * U32)
 
 
-def pass_bound(props, precision):
-    """Relative 2-norm error bound of one mixed pass with the fibre propagators ``props``."""
+def pass_bound(props, precision, band_tol=BAND_TOL_MIXED):
+    """Relative 2-norm error bound of one mixed pass with the fibre propagators ``props``,
+    including the left-out band chunks (band_tol; 0 for dense products)."""
     worst = 0.0
     for P in props:
         L = P.shape[0]
@@ -55,7 +62,7 @@ def pass_bound(props, precision):
             c = 5 * U32 + 2 * gamma(6 * L + 8)
         else:
             raise ValueError(precision)
-        worst = max(worst, math.sqrt(2.0) * c * np.linalg.norm(np.abs(E), 2))
+        worst = max(worst, math.sqrt(2.0) * c * np.linalg.norm(np.abs(E), 2) + L * band_tol)
     return worst
 
 
