@@ -146,13 +146,11 @@ def batch_workload(args):
             L = np.diff(S.fibres(j)[0]).astype(np.int64)
             nd = P.sharing(j)[0]
             distinct[j] += nd
-            # distinct propagators: each orbit or window class stores one, of its members' length;
-            # band-limited products: the entries inside the bands (lsx_plan_band)
-            frac = nd / max(1, S.nfibres[j])
-            kept = float(P.band(j)[1])
+            # band-limited products (lsx_plan_band): the entries inside the bands; bytes count the
+            # stored propagators once (each orbit or window class stores one) and their diagonals
+            _, kept, _, skept, srows = P.band(j, stored=True)
             work[j][0] += 8.0 * 16 * kept
-            work[j][1] += 2.0 * S.N * 16 * 16 + PROP_BYTES[prec] * kept * frac + \
-                (16.0 * S.N if prec != "fp64" else 0.0)
+            work[j][1] += 2.0 * S.N * 16 * 16 + PROP_BYTES[prec] * skept + (16.0 * srows if prec != "fp64" else 0.0)
     B = lsx.Batch([it[2] for it in items])
     coeffs = sum(it[0].N * 16 for it in items)
     B.step(args.warmup, stream)
@@ -467,7 +465,7 @@ def layered_bench(args, S, W, tau, slot, what, workload):
                      "pass_us": passes, "tiles": {j: st.tuning(j)[:2] + (st.prefetch(j),) for j in layers},
                      "nontemporal_stores": st.store_mode()[0],
                      "band_kept": {j: P.band(j)[1] / max(P.band(j)[2], 1) for j in layers},
-                     "_kept": {j: P.band(j)[1] for j in layers}}
+                     "_kept": {j: P.band(j, stored=True) for j in layers}}
         st.destroy()
         P.destroy()
     ref = finals.get("fp64")
@@ -478,9 +476,9 @@ def layered_bench(args, S, W, tau, slot, what, workload):
     best = max(ok, key=lambda p: res[p]["coeff_steps_per_s"])
     r = res[best]
     j = max(r["pass_us"], key=lambda k: r["pass_us"][k])  # dominant pass
-    kept = r["_kept"][j]  # band-limited products (lsx_plan_band)
+    _, kept, _, skept, srows = r["_kept"][j]  # band-limited products (lsx_plan_band)
     flops = 8.0 * W * kept
-    nbytes = 2.0 * N * W * 16 + PROP_BYTES[best] * kept + (16.0 * N if best != "fp64" else 0.0)
+    nbytes = 2.0 * N * W * 16 + PROP_BYTES[best] * skept + (16.0 * srows if best != "fp64" else 0.0)
     t = r["pass_us"][j] * 1e-6
     bound = "mfma" if flops / PEAK[best] >= nbytes / HBM_PEAK else "hbm"
     if bound == "mfma":
@@ -560,7 +558,7 @@ def time_paths(S, w, c0, paths, scheme, kappa, steps, warmup, reps, stream):
             k1.record(stream)
             k1.synchronize()
             phase_us = k0.elapsed_time(k1) * 1e3 / reps
-        band = {j: P.band(j) for j in (1, 2)}
+        band = {j: P.band(j, stored=True) for j in (1, 2)}
         res[path] = {"coeff_steps_per_s": N * W * steps / (ms * 1e-3), "ms_per_step": ms / steps,
                      "wall_ms": wall * 1e3, "precompute_s": pre, "layer2_pass_us": kus, "layer1_pass_us": kus1,
                      "tiles": {"layer1": st.tuning(1)[:2] + (st.prefetch(1),),
@@ -568,7 +566,8 @@ def time_paths(S, w, c0, paths, scheme, kappa, steps, warmup, reps, stream):
                      "nontemporal_stores": st.store_mode()[0], "rel_change_after_T": moved,
                      "band_tol": band[1][0],
                      "band_kept": {f"layer{j}": band[j][1] / max(band[j][2], 1) for j in (1, 2)},
-                     "_kept": {j: band[j][1] for j in (1, 2)}}
+                     "_kept": {j: band[j][1] for j in (1, 2)},
+                     "_stored": {j: band[j][3:] for j in (1, 2)}}
         if phase_us is not None:
             res[path]["phase_us"] = phase_us
             res[path]["phase_GBps"] = (2.0 * N * W * 16 + 16.0 * N) / (phase_us * 1e-6) / 1e9
@@ -687,11 +686,13 @@ def main():
     r = res[best]
     # dominant kernel: the layer-2 fibre pass.  Algorithmic work per launch: the band-limited
     # complex products, 8 W flops per propagator entry inside the band (lsx_plan_band; the
-    # dense count would be sum L^2 entries); bytes: read + write the state (2 N W 16) plus those
-    # propagator entries (and the FP64 diagonal, N 16, on the mixed paths).
+    # dense count would be sum L^2 entries); bytes: read + write the state (2 N W 16) plus the
+    # band entries of the stored propagators, each read once (fibres that share a propagator
+    # through a point symmetry count it once), and on the mixed paths their FP64 diagonals.
     kept = r["_kept"][2]
+    skept, srows = r["_stored"][2]
     flops = 8.0 * W * kept
-    nbytes = 2.0 * N * W * 16 + PROP_BYTES[best] * kept + (16.0 * N if best != "fp64" else 0.0)
+    nbytes = 2.0 * N * W * 16 + PROP_BYTES[best] * skept + (16.0 * srows if best != "fp64" else 0.0)
     t = r["layer2_pass_us"] * 1e-6
     bound = "mfma" if flops / PEAK[best] >= nbytes / HBM_PEAK else "hbm"
     if bound == "mfma":
@@ -710,6 +711,7 @@ def main():
                  "other_roof_frac": (nbytes / t / HBM_PEAK) if bound == "mfma" else (flops / t / PEAK[best])})
     for q in res.values():
         q.pop("_kept", None)
+        q.pop("_stored", None)
     out = {
         "metric": METRIC,
         "value": r["coeff_steps_per_s"],

@@ -278,15 +278,21 @@ lsx_status lsx_plan_sharing(const lsx_plan* plan, int32_t layer, int32_t* ndisti
  * for every block of 16 propagator rows, the range of column chunks (4 columns; 32 for
  * LSX_MIX_BF16X3) that hold an entry with |Re| + |Im| >= tol in any of the plan's slots, and
  * the fibre passes multiply only those chunks.  The entries left out change a pass by at most
- * L tol relative to the state (L the fibre length).  Default tol: 2^-64 for LSX_FP64 (below the
- * rounding of the products themselves), 2^-44 for the mixed precisions (far below their FP32
+ * L tol relative to the state (L the fibre length).  Default tol: 2^-53 for LSX_FP64 (the unit
+ * roundoff: a change of the order of the pass's own rounding bound and of the accuracy of the
+ * computed propagator entries), 2^-44 for the mixed precisions (far below their FP32
  * rounding); lsx_plan_desc.band_tol chooses another, and the environment variable
  * LSX_BAND_TOL overrides the default of lsx_plan_create (0: dense products).
  * lsx_plan_band: *tol = the tolerance in use (0: dense), *kept = complex multiply-adds per state
  * column of one pass of `layer` over all its fibres (rows times band width, inside the fibres),
- * *dense = the same for dense products (sum of L^2).  Outputs may be NULL.  Host only.
+ * *dense = the same for dense products (sum of L^2), *stored_kept = the propagator entries
+ * inside the bands of the propagators the plan stores (fibres that share a propagator, see
+ * lsx_plan_sharing, count once: the entries a pass must read at least once), *stored_rows = the
+ * rows of the stored propagators (the diagonals a mixed pass reads).  Outputs may be NULL.
+ * Host only.
  */
-lsx_status lsx_plan_band(const lsx_plan* plan, int32_t layer, double* tol, int64_t* kept, int64_t* dense);
+lsx_status lsx_plan_band(const lsx_plan* plan, int32_t layer, double* tol, int64_t* kept, int64_t* dense,
+                         int64_t* stored_kept, int64_t* stored_rows);
 /* The band of each 16-row block rb of one fibre (fibre order of lsx_fibre_get): lo_hi[2 rb] and
  * lo_hi[2 rb + 1] = first and one past the last fibre position whose column the pass multiplies
  * for those rows (multiples of 4, or of 32 for LSX_MIX_BF16X3; the padded fibre length at most).

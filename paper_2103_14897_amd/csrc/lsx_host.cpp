@@ -1177,14 +1177,15 @@ static lsx_status plan_create(lsx_system* sys, double tau, int32_t scheme, doubl
   pl->scheme = scheme;
   pl->precision = precision;
   pl->fmt = precision == LSX_FP64 ? PF_F64 : (precision == LSX_MIX_FP32 ? PF_F32 : PF_BF16X3);
-  // Band tolerance: for FP64, 2^-64, so the entries left out change a pass by at most L 2^-64
-  // relative (below the rounding of the products themselves); for the mixed paths, 2^-44, at
-  // most L 2^-44 per pass (about 5e-11 for fibres of 900 rows), far below the FP32 rounding of
-  // the entries that are kept.  LSX_BAND_TOL overrides it (0: dense products).
+  // Band tolerance: for FP64 the unit roundoff u = 2^-53, so the entries left out change a pass
+  // by at most L u relative, the order of the pass's own rounding bound (and of the accuracy of
+  // the computed propagator entries); for the mixed paths 2^-44, at most L 2^-44 per pass
+  // (about 5e-11 for fibres of 900 rows), far below the FP32 rounding of the entries that are
+  // kept.  LSX_BAND_TOL overrides it (0: dense products).
   if (band_req > 0.0)
     pl->band_tol = band_req;
   else if (band_req == 0.0)
-    pl->band_tol = env_double("LSX_BAND_TOL", pl->fmt == PF_F64 ? std::ldexp(1.0, -64) : std::ldexp(1.0, -44));
+    pl->band_tol = env_double("LSX_BAND_TOL", pl->fmt == PF_F64 ? std::ldexp(1.0, -53) : std::ldexp(1.0, -44));
   if (!(pl->band_tol >= 0.0)) pl->band_tol = 0.0;
   auto cleanup = [&](lsx_status st) {
     delete pl;
@@ -1350,23 +1351,31 @@ extern "C" lsx_status lsx_plan_sharing(const lsx_plan* pl, int32_t layer, int32_
 }
 
 extern "C" lsx_status lsx_plan_band(const lsx_plan* pl, int32_t layer, double* tol, int64_t* kept,
-                                    int64_t* dense) {
+                                    int64_t* dense, int64_t* stored_kept, int64_t* stored_rows) {
   if (!pl) return fail(LSX_E_INVALID, "null plan");
   if (layer < 1 || layer > pl->sys->nl) return fail(LSX_E_INVALID, "layer out of range");
   const LayerDev& ld = pl->L[layer - 1];
-  int64_t k = 0, d = 0;
+  int64_t k = 0, d = 0, sk = 0, sr = 0;
+  std::vector<char> seen(ld.nunique, 0);
   for (int f = 0; f < ld.nf; ++f) {
     const int L = ld.h_ptr[f + 1] - ld.h_ptr[f];
+    const bool first = !seen[ld.rep[f]];
+    seen[ld.rep[f]] = 1;
     d += (int64_t)L * L;
+    if (first) sr += L;
     for (int rb = 0; rb < (L + 15) / 16; ++rb) {
       int32_t k0, k1;
       fibre_band(ld, f, rb, 1, k0, k1);
-      k += (int64_t)std::min(16, L - 16 * rb) * (std::min(k1, L) - k0);
+      const int64_t e = (int64_t)std::min(16, L - 16 * rb) * (std::min(k1, L) - k0);
+      k += e;
+      if (first) sk += e;
     }
   }
   if (tol) *tol = pl->band_tol;
   if (kept) *kept = k;
   if (dense) *dense = d;
+  if (stored_kept) *stored_kept = sk;
+  if (stored_rows) *stored_rows = sr;
   return LSX_OK;
 }
 
@@ -2807,6 +2816,8 @@ struct lsx_sampler {
   DBuf<TileDesc> tiles[2];  // tiles of the sampled (fibre, column) pairs, built per sub-step
   DBuf<int32_t> cols[2], ncols[2], off[2], fid[2], d0[2];
   DBuf<int64_t> poff[2];
+  // band of every (fibre, 16-row block): [2 (bptr[f] + rb)] = k0, [.. + 1] = k1 (fibre positions)
+  DBuf<int32_t> bptr[2], band[2];
   DBuf<int32_t> count;
   DBuf<double> wt[2], mass, sfeat[2];
   DBuf<float> X, z;
@@ -2860,6 +2871,21 @@ extern "C" lsx_status lsx_sampler_create(lsx_plan* pl, lsx_state* st, int32_t p1
     }
     LSX_TRY(sm->poff[j].upload(poff, nullptr));
     LSX_TRY(sm->d0[j].upload(d0, nullptr));
+    {
+      std::vector<int32_t> bp(std::max(nf, 1), 0), bd;
+      for (int f = 0; f < nf; ++f) {
+        bp[f] = (int32_t)(bd.size() / 2);
+        for (int rb = 0; rb < (ld.h_ptr[f + 1] - ld.h_ptr[f] + 15) / 16; ++rb) {
+          int32_t k0, k1;
+          fibre_band(ld, f, rb, 1, k0, k1);
+          bd.push_back(k0);
+          bd.push_back(k1);
+        }
+      }
+      if (bd.empty()) bd.assign(2, 0);
+      LSX_TRY(sm->bptr[j].upload(bp, nullptr));
+      LSX_TRY(sm->band[j].upload(bd, nullptr));
+    }
     // fibre of every canonical row, and the per-fibre shift features
     std::vector<int32_t> fid((size_t)sys->N, 0);
     std::vector<double> sf((size_t)nf * (d + 1), 0.0);
@@ -2962,7 +2988,8 @@ lsx_status sampled_substep(lsx_sampler* sm, int layer, int half, const double* u
   LSX_HIP_TRY(launch_sample_weights(s, nf, W, sm->p[j], ustride, u, z, sm->eps, sm->wt[j].p));
   const LayerDev& ld = pl->L[j];
   LSX_HIP_TRY(launch_sampled_tiles(s, nf, W, kSampledNB, sm->wt[j].p, ld.ptr.p, sm->poff[j].p, sm->d0[j].p,
-                                   sm->cols[j].p, sm->ncols[j].p, sm->off[j].p, sm->tiles[j].p, sm->count.p + j));
+                                   sm->bptr[j].p, sm->band[j].p, sm->cols[j].p, sm->ncols[j].p, sm->off[j].p,
+                                   sm->tiles[j].p, sm->count.p + j));
   PassArgs a = canon_pass_args(pl, st, layer, half);
   a.tiles = sm->tiles[j].p;
   a.tcount = sm->count.p + j;

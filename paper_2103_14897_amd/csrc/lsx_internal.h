@@ -174,9 +174,10 @@ hipError_t launch_subset_weights(hipStream_t s, int nf, int W, int p, int ustrid
 hipError_t launch_sample_weights(hipStream_t s, int nf, int W, int p, int ustride, const double* u, const float* z,
                                  double eps, double* wt);
 // column lists of the sampled fibres and their tiles (16 NB column slots per tile)
+// bptr, band (nullable): band of fibre f's row block rb at band[2 (bptr[f] + rb)] (k0, then k1)
 hipError_t launch_sampled_tiles(hipStream_t s, int nf, int W, int NB, const double* wt, const int32_t* ptr,
-                                const int64_t* poff, const int32_t* d0, int32_t* cols, int32_t* ncols, int32_t* off,
-                                TileDesc* tiles, int32_t* count);
+                                const int64_t* poff, const int32_t* d0, const int32_t* bptr, const int32_t* band,
+                                int32_t* cols, int32_t* ncols, int32_t* off, TileDesc* tiles, int32_t* count);
 hipError_t launch_copy_cols(hipStream_t s, int ntiles, const TileDesc* tiles, const int32_t* count, int NB,
                             const int32_t* pos, int W, const int32_t* cols, const int32_t* ncols, const double2* src,
                             double2* dst);

@@ -243,10 +243,11 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(int nf, int NB, const int32
   if (t == 1023) *count = scan[1023];
 }
 
-// Tiles of fibre f = blockIdx.x at off[f]: (row block rb, column-slot block cb), rb major.
+// Tiles of fibre f = blockIdx.x at off[f]: (row block rb, column-slot block cb), rb major, each with
+// its row block's band when the band table is given (else the whole fibre).
 __global__ __launch_bounds__(256) void k_emit_tiles(int NB, const int32_t* ptr, const int64_t* poff,
-                                                    const int32_t* d0, const int32_t* ncols, const int32_t* off,
-                                                    TileDesc* out) {
+                                                    const int32_t* d0, const int32_t* bptr, const int32_t* band,
+                                                    const int32_t* ncols, const int32_t* off, TileDesc* out) {
   const int f = blockIdx.x;
   const int r0 = ptr[f], L = ptr[f + 1] - r0;
   const int cw = 16 * NB;
@@ -261,8 +262,8 @@ __global__ __launch_bounds__(256) void k_emit_tiles(int NB, const int32_t* ptr, 
     t.poff = poff ? poff[f] : 0;
     t.f = f;
     t.d0 = d0 ? d0[f] : r0;
-    t.k0 = 0;  // the whole fibre: sampled passes take no band
-    t.k1 = kBandEnd;
+    t.k0 = band ? band[2 * (bptr[f] + t.rb)] : 0;
+    t.k1 = band ? band[2 * (bptr[f] + t.rb) + 1] : kBandEnd;
     out[off[f] + k] = t;
   }
 }
@@ -684,8 +685,8 @@ hipError_t launch_sample_weights(hipStream_t s, int nf, int W, int p, int ustrid
 }
 
 hipError_t launch_sampled_tiles(hipStream_t s, int nf, int W, int NB, const double* wt, const int32_t* ptr,
-                                const int64_t* poff, const int32_t* d0, int32_t* cols, int32_t* ncols, int32_t* off,
-                                TileDesc* tiles, int32_t* count) {
+                                const int64_t* poff, const int32_t* d0, const int32_t* bptr, const int32_t* band,
+                                int32_t* cols, int32_t* ncols, int32_t* off, TileDesc* tiles, int32_t* count) {
   if (nf == 0) return hipSuccess;
   hipLaunchKernelGGL(k_fibre_cols, dim3((nf + 3) / 4), dim3(256), 0, s, nf, W, wt, cols, ncols);
   hipError_t e = hipGetLastError();
@@ -693,7 +694,7 @@ hipError_t launch_sampled_tiles(hipStream_t s, int nf, int W, int NB, const doub
   hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, s, nf, NB, ptr, ncols, off, count);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_emit_tiles, dim3(nf), dim3(256), 0, s, NB, ptr, poff, d0, ncols, off, tiles);
+  hipLaunchKernelGGL(k_emit_tiles, dim3(nf), dim3(256), 0, s, NB, ptr, poff, d0, bptr, band, ncols, off, tiles);
   return hipGetLastError();
 }
 

@@ -90,7 +90,7 @@ _SIGS = {
     "lsx_mlp_destroy": (C.c_int, [_p]),
     "lsx_live_buffers": (C.c_int, [_i64p, _i64p]),
     "lsx_plan_sharing": (C.c_int, [_p, C.c_int32, _i32p, _i32p]),
-    "lsx_plan_band": (C.c_int, [_p, C.c_int32, _dp, _i64p, _i64p]),
+    "lsx_plan_band": (C.c_int, [_p, C.c_int32, _dp, _i64p, _i64p, _i64p, _i64p]),
     "lsx_plan_fibre_band": (C.c_int, [_p, C.c_int32, C.c_int32, _i32p]),
     "lsx_system_symmetries": (C.c_int, [_p, _i32p, _i32p]),
     "lsx_observables_noalloc": (C.c_int, [_p, _p, C.c_int32, C.c_uint32, _p, _p]),
@@ -354,10 +354,14 @@ class Plan:
             _check(lib().lsx_plan_create_desc(system.h, C.byref(desc), _stream(stream), C.byref(h)))
         self.h = h
 
-    def band(self, layer):
-        """(tolerance in use, complex multiply-adds per column of one layer pass, the dense count)."""
-        tol, kept, dense = C.c_double(), C.c_int64(), C.c_int64()
-        _check(lib().lsx_plan_band(self.h, int(layer), C.byref(tol), C.byref(kept), C.byref(dense)))
+    def band(self, layer, stored=False):
+        """(tolerance in use, complex multiply-adds per column of one layer pass, the dense count),
+        and with stored=True also (band entries of the stored propagators, their rows)."""
+        tol, kept, dense, sk, sr = C.c_double(), C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()
+        _check(lib().lsx_plan_band(self.h, int(layer), C.byref(tol), C.byref(kept), C.byref(dense), C.byref(sk),
+                                   C.byref(sr)))
+        if stored:
+            return tol.value, kept.value, dense.value, sk.value, sr.value
         return tol.value, kept.value, dense.value
 
     def fibre_band(self, layer, fibre):

@@ -8,8 +8,9 @@ column chunks holding an entry with |Re| + |Im| >= tol, and the passes multiply 
 * the recorded bands against the oracle's propagators (eigh, FP64), for every slot the plan
   holds: every chunk whose largest entry reaches 2 tol lies inside the band, and the band's
   first and last chunks reach tol / 2, so the band is also tight;
-* banded trajectories against dense ones (band_tol < 0): FP64 at rounding level, the mixed
-  paths within the sum of both runs' derived bounds (tests/mixed_bounds.py); the oracle
+* banded trajectories against dense ones (band_tol < 0): FP64 within the left-out entries'
+  bound (Lmax tol per pass) plus rounding, the mixed paths within the sum of both runs' derived
+  bounds (tests/mixed_bounds.py); the oracle
   comparisons of every other GPU test run on the default, banded plans;
 * the bands of the default tolerances leave out most of the products on the 1D chain (the
   BF16x3 format's 32-column chunks less so on its short layer-1 fibres).
@@ -102,14 +103,17 @@ def test_banded_steps_equal_dense_steps(which, precision):
     sb, sd = lsx.State(Pb, w.W), lsx.State(Pd, w.W)
     try:
         assert Pd.band(1)[0] == 0.0 and Pd.band(1)[1] == Pd.band(1)[2]
-        assert Pb.band(1)[0] == (2.0 ** -64 if precision == "fp64" else 2.0 ** -44)
+        tol = 2.0 ** -53 if precision == "fp64" else 2.0 ** -44
+        assert Pb.band(1)[0] == tol
         sb.upload(c0)
         sd.upload(c0)
         sb.step(nsteps)
         sd.step(nsteps)
         err = colrel(sb.download(), sd.download())
         if precision == "fp64":
-            bound = 1e-13
+            # left-out entries: at most Lmax tol per pass; the rest is rounding order
+            Lmax = max(len(r) for l in (1, 2) for _, r in O.fib[l])
+            bound = 2 * nsteps * Lmax * tol + 1e-13
         else:
             oplan = splitting.SplitPlan(O, 0.0)
             passes = mixed_bounds.strang_passes(w.tau, nsteps)
@@ -130,8 +134,11 @@ def test_default_bands_skip_most_chain_products(precision):
     P = lsx.Plan(S, w.tau, "strang", 0.0, precision)
     try:
         for layer in (1, 2):
-            tol, kept, dense = P.band(layer)
-            print(f"[case] chain band {precision} layer {layer}: tol {tol:.1e}, kept {kept / dense:.3f}", flush=True)
+            tol, kept, dense, skept, srows = P.band(layer, stored=True)
+            print(f"[case] chain band {precision} layer {layer}: tol {tol:.1e}, kept {kept / dense:.3f}, "
+                  f"stored {skept / kept:.3f} of it ({P.sharing(layer)[0]} of {S.nfibres[layer]} fibres)", flush=True)
+            # x -> -x maps the chain onto itself, so mirror fibres share one stored propagator
+            assert 0 < skept < kept and 0 < srows < S.N
             # BF16x3 chunks are 32 columns wide, coarse against the chain's short layer-1 fibres
             assert 0 < kept < (0.9 if precision == "mix_bf16x3" and layer == 1 else 0.7) * dense
     finally:
