@@ -1429,49 +1429,70 @@ struct lsx_state {
 };
 
 
-// Tile order of one fibre pass.  Workgroup i of a launch runs on XCD i % 8, and each
-// XCD has its own L2, so whole fibres are assigned to XCDs (longest first, to the
-// least-loaded XCD) and the XCD queues are interleaved; every queue lists its largest
-// tiles first.  Shorter queues are padded with empty tiles (f = -1).
-// ms > 1: tiles of the row-split kernels, rb counts groups of ms 16-row blocks.
+// Tile order of one fibre pass.  Workgroup i of a launch runs on XCD i % 8, and each XCD has
+// its own L2, so fibres are assigned to XCDs whole (longest first, to the least-loaded XCD) and
+// the XCD queues are interleaved; every queue lists its largest tiles first.  Fibres that share
+// one stored propagator (point-symmetry orbits, kappa = 1 windows) go to the same XCD in groups
+// of up to kShareGroup, with the tiles of a group's fibres for the same rows and columns listed
+// back to back, so each propagator block is fetched into that L2 once for the whole group
+// (LSX_GROUP_TILES=0 assigns every fibre on its own).  Shorter queues are padded with empty
+// tiles (f = -1).  ms > 1: tiles of the row-split kernels, rb counts groups of ms 16-row blocks.
+static constexpr int kShareGroup = 8;
 static void build_tiles(const lsx_plan* pl, int layer, int W, int nb, int wb0, int wb1, std::vector<TileDesc>& out,
                         int ms = 1) {
   const LayerDev& ld = pl->L[layer - 1];
   const int wt = wb1 - wb0;
   (void)W;
+  (void)nb;
   const int NX = std::max(1, env_int("LSX_XCDS", 8));
-  std::vector<int> order(ld.nf);
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-    return (ld.h_ptr[x + 1] - ld.h_ptr[x]) > (ld.h_ptr[y + 1] - ld.h_ptr[y]);
-  });
+  const bool share = env_int("LSX_GROUP_TILES", 1) != 0 && (int)ld.rep.size() == ld.nf;
+  // groups of fibres with one stored propagator, in fibre order, split into kShareGroup chunks
+  std::vector<std::vector<int>> groups;
+  {
+    std::map<int, int> open;  // propagator slot -> index of its group being filled
+    for (int f = 0; f < ld.nf; ++f) {
+      const int key = share ? ld.rep[f] : f;
+      auto it = open.find(key);
+      if (it == open.end() || (int)groups[it->second].size() >= kShareGroup) {
+        open[key] = (int)groups.size();
+        groups.push_back({f});
+      } else {
+        groups[it->second].push_back(f);
+      }
+    }
+  }
+  auto glen = [&](const std::vector<int>& g) { return ld.h_ptr[g[0] + 1] - ld.h_ptr[g[0]]; };
+  std::stable_sort(groups.begin(), groups.end(),
+                   [&](const std::vector<int>& x, const std::vector<int>& y) { return glen(x) > glen(y); });
   // balance the bins by tile count (equal counts need no padding tiles), ties by cost
   std::vector<double> load(NX, 0.0);
   std::vector<int64_t> count(NX, 0);
   std::vector<std::vector<TileDesc>> bins(NX);
-  for (int f : order) {
-    const int L = ld.h_ptr[f + 1] - ld.h_ptr[f];
+  for (const std::vector<int>& g : groups) {
+    const int L = glen(g);
     const int nrb = ((L + 15) / 16 + ms - 1) / ms;
     int x = 0;
     for (int y = 1; y < NX; ++y)
       if (count[y] < count[x] || (count[y] == count[x] && load[y] < load[x])) x = y;
-    count[x] += (int64_t)nrb * wt;
+    count[x] += (int64_t)nrb * wt * (int64_t)g.size();
     for (int rb = 0; rb < nrb; ++rb) {
-      int32_t k0, k1;
-      fibre_band(ld, f, rb * ms, ms, k0, k1);
-      load[x] += (double)wt * (std::min(k1, L) - k0 + 8);
       for (int wb = wb0; wb < wb1; ++wb) {
-        TileDesc t;
-        t.r0 = ld.h_ptr[f];
-        t.L = L;
-        t.rb = rb;
-        t.wb = wb;
-        t.poff = ld.h_poff.empty() ? 0 : ld.h_poff[f];
-        t.f = f;
-        t.d0 = ld.h_d0.empty() ? ld.h_ptr[f] : ld.h_d0[f];
-        t.k0 = k0;
-        t.k1 = k1;
-        bins[x].push_back(t);
+        for (int f : g) {
+          int32_t k0, k1;
+          fibre_band(ld, f, rb * ms, ms, k0, k1);
+          if (wb == wb0) load[x] += (double)wt * (std::min(k1, L) - k0 + 8);
+          TileDesc t;
+          t.r0 = ld.h_ptr[f];
+          t.L = L;
+          t.rb = rb;
+          t.wb = wb;
+          t.poff = ld.h_poff.empty() ? 0 : ld.h_poff[f];
+          t.f = f;
+          t.d0 = ld.h_d0.empty() ? ld.h_ptr[f] : ld.h_d0[f];
+          t.k0 = k0;
+          t.k1 = k1;
+          bins[x].push_back(t);
+        }
       }
     }
   }
