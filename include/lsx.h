@@ -326,8 +326,9 @@ lsx_status lsx_state_device_ptr(const lsx_state* st, void** dev_ptr);
 /*
  * Tile shape chosen for the fibre passes of `layer` (1 .. nlayers) of this state: each
  * workgroup covers 16*nb columns and either 16 output rows with ks > 0 waves splitting the
- * fibre length, or (ks < 0, mixed FP32) -ks consecutive 16-row blocks, one per wave, that
- * share the state operand staged once per workgroup in LDS.  For W = 1 (matrix-vector
+ * fibre length, or (ks = -2, -4 or -8, mixed paths) -ks consecutive 16-row blocks, one per wave,
+ * that share the state operand staged once per workgroup in LDS (each wave multiplies only its
+ * own row block's band, see lsx_plan_band; FP32 needs -ks <= 4 nb, BF16x3 nb <= 2).  For W = 1 (matrix-vector
  * passes) ks < 0 means 32 output rows (two row blocks) with -ks waves splitting the fibre
  * length (FP64 and mixed FP32).  At creation every candidate shape is timed on the state's own size
  * (LSX_AUTOTUNE=0 disables, LSX_NB / LSX_KS force a shape); pass_us is the measured
@@ -374,8 +375,9 @@ lsx_status lsx_state_store_mode(const lsx_state* st, int32_t* nontemporal, doubl
  *   library default) of `layer`'s passes; the tile list is rebuilt on the host and uploaded
  *   (synchronous).  Available shapes: W = 1: nb = 1 and ks in {1, 2, 4}, or {-1, -2, -4} except
  *   for LSX_MIX_BF16X3, groups = 0.  W > 1: nb in {1, 2, 4} with 16 nb <= W rounded up to 16;
- *   ks in {1, 2, 4} with groups 0, or 1 or 2 for LSX_FP64 / LSX_MIX_FP32; or ks in {-2, -4} for
- *   the mixed paths (nb <= 2 for LSX_MIX_BF16X3), groups 0.  Anything else is LSX_E_INVALID
+ *   ks in {1, 2, 4} with groups 0, or 1 or 2 for LSX_FP64 / LSX_MIX_FP32; or ks in {-2, -4, -8}
+ *   for the mixed paths (-ks <= 4 nb for LSX_MIX_FP32, nb <= 2 for LSX_MIX_BF16X3), groups 0.
+ *   Anything else is LSX_E_INVALID
  *   and leaves the state unchanged.  lsx_state_tuning then reports pass_us = 0.
  * lsx_state_set_store_mode: 0 ordinary, 1 non-temporal output stores (LSX_E_INVALID otherwise).
  * Neither call touches the state's values.  Not while a step on the state is in flight.

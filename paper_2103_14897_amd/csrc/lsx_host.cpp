@@ -627,6 +627,7 @@ struct LayerDev {
   // block rb of distinct propagator b is entry h_boff[b] + rb; the union over the layer's slots.
   std::vector<int64_t> h_boff;
   std::vector<int32_t> band_lo, band_hi;
+  DBuf<int32_t> d_band;  // the same bands on the device, (lo, hi) pairs (empty: dense products)
 };
 
 // Band of row blocks [rb0, rb0 + n) of fibre f (those inside the fibre) as fibre positions
@@ -1152,6 +1153,13 @@ static lsx_status precompute_layer(lsx_plan* pl, int layer, hipStream_t s) {
       }
     }
   }
+  if (banded && nband > 0) {
+    for (int64_t i = 0; i < nband; ++i) {
+      hband[2 * i] = ld.band_lo[i];
+      hband[2 * i + 1] = ld.band_hi[i];
+    }
+    LSX_TRY(ld.d_band.upload(hband, s));
+  }
   LSX_HIP_TRY(hipStreamSynchronize(s));
   return LSX_OK;
 }
@@ -1491,6 +1499,8 @@ static void build_tiles(const lsx_plan* pl, int layer, int W, int nb, int wb0, i
           t.d0 = ld.h_d0.empty() ? ld.h_ptr[f] : ld.h_d0[f];
           t.k0 = k0;
           t.k1 = k1;
+          t.bb = ld.h_boff.empty() ? -1 : (int32_t)ld.h_boff[ld.rep[f]];
+          t.pad_ = 0;
           bins[x].push_back(t);
         }
       }
@@ -1535,6 +1545,7 @@ static lsx_status choose_cycle(lsx_plan* pl, lsx_state* st, bool tune_store) {
     x.P = ld.prop[slot].data.p;
     x.diag = pl->diag.p ? pl->diag.p + (size_t)((layer - 1) * 3 + slot) * N : nullptr;
     x.zero = pl->zero.p;
+    x.rb_band = ld.d_band.p;
     x.W = W;
   }
   // per layer: option 0 the single-pass winner, 1 the winner at the other depth, 2 the runner-up
@@ -1639,6 +1650,14 @@ static lsx_status choose_cycle(lsx_plan* pl, lsx_state* st, bool tune_store) {
 // LSX_AUTOTUNE=0, every candidate shape is timed on this state's own size (reading the
 // state array, writing only the work array, so the state is not modified) and the
 // fastest one per layer is kept.
+// Row-split shapes the kernels are built for: m waves on consecutive row blocks sharing the
+// staged state of 16 nb columns (mixed formats; FP32 needs m <= 4 nb, BF16x3 nb <= 2).
+static bool rowsplit_shape(int fmt, int nb, int m) {
+  if (fmt == PF_F64 || !(m == 2 || m == 4 || m == 8)) return false;
+  if (fmt == PF_BF16X3) return nb == 1 || nb == 2;
+  return (nb == 1 || nb == 2 || nb == 4) && m <= 4 * nb;
+}
+
 static lsx_status choose_tiles(lsx_plan* pl, lsx_state* st) {
   const int W = st->W;
   // ks > 0: ks waves split the fibre length; ks < 0: -ks waves take consecutive row blocks
@@ -1666,12 +1685,11 @@ static lsx_status choose_tiles(lsx_plan* pl, lsx_state* st) {
         }
     if (pl->fmt == PF_F32 || pl->fmt == PF_BF16X3)
       for (int nb : {1, 2, 4})
-        for (int m : {2, 4})
-          if (16 * nb <= round_up(W, 16) && !(pl->fmt == PF_BF16X3 && nb == 4)) cands.push_back({nb, -m, 0});
+        for (int m : {2, 4, 8})
+          if (16 * nb <= round_up(W, 16) && rowsplit_shape(pl->fmt, nb, m)) cands.push_back({nb, -m, 0});
   }
   if (fnb > 0 || fks != 0) {
-    const bool rowsplit = fks < 0 && ((W > 1 && pl->fmt != PF_F64 && (fks == -2 || fks == -4) &&
-                                       !(pl->fmt == PF_BF16X3 && fnb == 4)) ||
+    const bool rowsplit = fks < 0 && ((W > 1 && rowsplit_shape(pl->fmt, fnb > 0 ? fnb : 1, -fks)) ||
                                       (W == 1 && pl->fmt != PF_BF16X3 && (fks == -1 || fks == -2 || fks == -4)));
     const Shape f{(fnb == 1 || fnb == 2 || fnb == 4) ? fnb : 1,
                   rowsplit ? fks : ((fks == 1 || fks == 2 || fks == 4) ? fks : 2), 0};
@@ -1719,6 +1737,7 @@ static lsx_status choose_tiles(lsx_plan* pl, lsx_state* st) {
         a.X = st->buf[0];
         a.Y = st->buf[1];
         a.zero = pl->zero.p;
+        a.rb_band = ld.d_band.p;
         a.W = W;
         a.u = c.u;
         // two timed passes (enough for passes of a millisecond or more), then, for shorter
@@ -1893,7 +1912,7 @@ static bool shape_valid(int fmt, int W, int nb, int ks, int u) {
   if (!(nb == 1 || nb == 2 || nb == 4) || 16 * nb > round_up(W, 16)) return false;
   if (ks == 1 || ks == 2 || ks == 4)
     return u == 0 || ((fmt == PF_F64 || fmt == PF_F32) && (u == 1 || u == 2));
-  if (ks == -2 || ks == -4) return u == 0 && fmt != PF_F64 && !(fmt == PF_BF16X3 && nb == 4);
+  if (ks < 0) return u == 0 && rowsplit_shape(fmt, nb, -ks);
   return false;
 }
 
@@ -1974,6 +1993,7 @@ struct Runner {
     a.X = st->buf[cur];
     a.Y = st->buf[1 - cur];
     a.zero = pl->zero.p;
+    a.rb_band = ld.d_band.p;
     a.W = st->W;
     a.nt = st->nt;
     a.u = st->u[layer - 1];
@@ -2373,6 +2393,8 @@ static void batch_tiles(const lsx_batch* b, int layer, int nb, std::vector<TileD
         t.d0 = ld.h_d0[it.f];
         t.k0 = k0;
         t.k1 = k1;
+        t.bb = -1;
+        t.pad_ = 0;
         bins[x].push_back(t);
       }
     }

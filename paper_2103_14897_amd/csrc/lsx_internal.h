@@ -47,18 +47,21 @@ inline int64_t prop_bytes(int fmt, int L) {
   }
 }
 
-// Tile of a fibre pass (40 bytes, read with scalar loads): fibre f starting at fibre
+// Tile of a fibre pass (48 bytes, read with scalar loads): fibre f starting at fibre
 // position r0 with length L, output rows 16*rb.., columns 16*NB*wb.., the byte offset of
 // the fibre's propagator and of its diagonal, and the band [k0, k1) of fibre positions
 // whose propagator columns hold an entry above the plan's band tolerance for any of the
 // tile's rows (multiples of the format's column chunk; the kernels clamp k1 to the padded
-// fibre length, so k1 = INT32_MAX means "to the end").  f < 0 marks a padding tile.
+// fibre length, so k1 = INT32_MAX means "to the end").  bb: entry of the propagator's first
+// 16-row block in the per-block band table (PassArgs::rb_band), -1 when the tile has none.
+// f < 0 marks a padding tile.
 struct TileDesc {
   int32_t r0, L, rb, wb;
   int64_t poff;
   int32_t f;
   int32_t d0;  // mixed formats: position of this propagator's diagonal (fibres may share one)
   int32_t k0, k1;
+  int32_t bb, pad_;
 };
 constexpr int32_t kBandEnd = 0x7fffffff;
 // columns per propagator chunk of a format (the unit of the band)
@@ -88,6 +91,10 @@ struct PassArgs {
   // s < ncols[f] (TileDesc::wb then counts blocks of 16 NB slots, not of columns)
   const int32_t* cols = nullptr;
   const int32_t* ncols = nullptr;
+  // row-split passes: band of every 16-row block of the layer's stored propagators, (k0, k1)
+  // fibre positions at [2 (TileDesc::bb + block)]; each wave of a tile then skips the chunks
+  // outside its own block's band (null: the tile's band for every wave)
+  const int32_t* rb_band = nullptr;
   // persistent batched launches: mode (0 none, 1 per-XCD tile queues on device counters,
   // 2 static stride), 9 device counters that are zero between launches (mode 1) and the
   // number of tiles in `tiles`

@@ -1015,11 +1015,14 @@ __global__ __launch_bounds__(64 * KS) void k_pass_f32_persist(PassArgs a0) {
 // each state row is fetched once per row-block group instead of once per row block.  Each
 // wave streams its own propagator rows, one chunk ahead in registers.  No cross-wave
 // reduction: every wave owns its output rows.  Needs MS <= 4 NB.  Chunks are KC k-steps
-// (4 KC fibre positions); four-wave groups take 32-row chunks, which halves the barriers and
-// doubles the work that hides each chunk's loads without costing occupancy.
+// (4 KC fibre positions); four- and eight-wave groups take 32-row chunks, which halves the
+// barriers and doubles the work that hides each chunk's loads without costing occupancy.
+// With band-limited products the staged chunks cover the union of the group's bands, and
+// each wave multiplies only the chunks of its own row block's band (PassArgs::rb_band), so
+// larger groups read the state operand fewer times without adding products.
 template <int NB, int MS>
 struct StageMap {
-  static constexpr int KC = MS == 4 ? 8 : 4;   // k-steps per chunk
+  static constexpr int KC = MS >= 4 ? 8 : 4;   // k-steps per chunk
   static constexpr int CR = 4 * KC;            // rows of a chunk
   static constexpr int CW = 16 * NB;           // columns of a chunk
   static constexpr int PER = CR * CW / (64 * MS);  // elements per thread per chunk
@@ -1084,11 +1087,22 @@ __global__ __launch_bounds__(64 * MS) void k_pass_f32m(PassArgs a) {
   // just staged
   const int c0 = (((t0.rb + 1) * MS * 16 / SM::CR - clo) % nch + nch) % nch;
   auto chunk = [&](int i) { return clo + (i + c0 < nch ? i + c0 : i + c0 - nch); };
+  // this wave's own band [wlo, whi) of chunks (its row block's), inside the staged ones
+  int wlo = clo, whi = clo + nch;
+  if (a.rb_band && t0.bb >= 0 && act) {
+    const int2 wb = reinterpret_cast<const int2*>(a.rb_band)[t0.bb + t.rb];
+    wlo = wb.x / SM::CR;
+    whi = (min(wb.y, 4 * nks) + SM::CR - 1) / SM::CR;
+  }
+  auto mine = [&](int cc) { return act && cc >= wlo && cc < whi; };
   stage_load_f32<SM::PER, SM::RSTEP, SM::CR, GATHER>(sv, a, chunk(0), r0, L, sw, sok, rr0);
+  {
+    const bool in = mine(chunk(0));
 #pragma unroll
-  for (int u = 0; u < KC; ++u) {
-    const int ks = KC * chunk(0) + u;
-    Ac[u] = (act && ks < nks) ? P[(int64_t)ks * 64] : *zp;
+    for (int u = 0; u < KC; ++u) {
+      const int ks = KC * chunk(0) + u;
+      Ac[u] = (in && ks < nks) ? P[(int64_t)ks * 64] : *zp;
+    }
   }
 #pragma unroll
   for (int j = 0; j < SM::PER; ++j) {
@@ -1101,14 +1115,15 @@ __global__ __launch_bounds__(64 * MS) void k_pass_f32m(PassArgs a) {
     const bool more = ch + 1 < nch;
     if (more) {
       stage_load_f32<SM::PER, SM::RSTEP, SM::CR, GATHER>(sv, a, chunk(ch + 1), r0, L, sw, sok, rr0);
+      const bool in = mine(chunk(ch + 1));
 #pragma unroll
       for (int u = 0; u < KC; ++u) {
         const int ks = KC * chunk(ch + 1) + u;
-        An[u] = (act && ks < nks) ? P[(int64_t)ks * 64] : *zp;
+        An[u] = (in && ks < nks) ? P[(int64_t)ks * 64] : *zp;
       }
     }
     __builtin_amdgcn_sched_barrier(0);
-    if (act) {
+    if (mine(chunk(ch))) {
 #pragma unroll
       for (int u = 0; u < KC; ++u) {
         const float ps = Ac[u].x + Ac[u].y;
@@ -1344,12 +1359,20 @@ __global__ __launch_bounds__(64 * MS) void k_pass_bf16m(PassArgs a) {
       xb[buf][5][c][k] = q5;
     }
   };
-  // the tile's band of chunks [klo, khi)
+  // the tile's band of chunks [klo, khi), and this wave's own [wlo, whi) inside it (its row
+  // block's band; the staged chunks cover the union)
   int klo, khi;
   tile_band(t0, 32 * nkc, 32, klo, khi);
-  // this wave's propagator planes of chunk kc (E re/im terms 0..2), zeros past the band
+  int wlo = klo, whi = khi;
+  if (a.rb_band && t0.bb >= 0 && act) {
+    const int2 wb = reinterpret_cast<const int2*>(a.rb_band)[t0.bb + t.rb];
+    wlo = wb.x / 32;
+    whi = (min(wb.y, 32 * nkc) + 31) / 32;
+  }
+  auto mine = [&](int kc) { return act && kc >= wlo && kc < whi; };
+  // this wave's propagator planes of chunk kc (E re/im terms 0..2), zeros outside its band
   auto load_e = [&](v8bf (&E)[6], int kc) {
-    const bool in = act && kc < khi;
+    const bool in = mine(kc);
 #pragma unroll
     for (int pl = 0; pl < 6; ++pl) {
       int64_t off = ((int64_t)kc * 6 + pl) * 64;
@@ -1387,7 +1410,7 @@ __global__ __launch_bounds__(64 * MS) void k_pass_bf16m(PassArgs a) {
     load_state(kc + 1);
     load_e(EB, kc + 1);
     __builtin_amdgcn_sched_barrier(0);
-    if (act) mma(EA, 0);
+    if (mine(kc)) mma(EA, 0);
     __builtin_amdgcn_sched_barrier(0);
     if (kc + 1 >= khi) break;
     store_state(1);
@@ -1395,7 +1418,7 @@ __global__ __launch_bounds__(64 * MS) void k_pass_bf16m(PassArgs a) {
     load_state(kc + 2);
     load_e(EA, kc + 2);
     __builtin_amdgcn_sched_barrier(0);
-    if (act) mma(EB, 1);
+    if (mine(kc + 1)) mma(EB, 1);
     __builtin_amdgcn_sched_barrier(0);
     if (kc + 2 >= khi) break;
     store_state(0);
@@ -1918,8 +1941,10 @@ hipError_t launch_pass(hipStream_t s, int fmt, int W, int ntiles, int nb, int ks
   }
       LSX_ROWSPLIT_BF(1, 2)
       LSX_ROWSPLIT_BF(1, 4)
+      LSX_ROWSPLIT_BF(1, 8)
       LSX_ROWSPLIT_BF(2, 2)
       LSX_ROWSPLIT_BF(2, 4)
+      LSX_ROWSPLIT_BF(2, 8)
 #undef LSX_ROWSPLIT_BF
       return hipErrorInvalidValue;
     }
@@ -1935,8 +1960,10 @@ hipError_t launch_pass(hipStream_t s, int fmt, int W, int ntiles, int nb, int ks
     LSX_ROWSPLIT_CASE(1, 4)
     LSX_ROWSPLIT_CASE(2, 2)
     LSX_ROWSPLIT_CASE(2, 4)
+    LSX_ROWSPLIT_CASE(2, 8)
     LSX_ROWSPLIT_CASE(4, 2)
     LSX_ROWSPLIT_CASE(4, 4)
+    LSX_ROWSPLIT_CASE(4, 8)
 #undef LSX_ROWSPLIT_CASE
     return hipErrorInvalidValue;
   }

@@ -264,6 +264,8 @@ __global__ __launch_bounds__(256) void k_emit_tiles(int NB, const int32_t* ptr, 
     t.d0 = d0 ? d0[f] : r0;
     t.k0 = band ? band[2 * (bptr[f] + t.rb)] : 0;
     t.k1 = band ? band[2 * (bptr[f] + t.rb) + 1] : kBandEnd;
+    t.bb = -1;
+    t.pad_ = 0;
     out[off[f] + k] = t;
   }
 }
