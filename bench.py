@@ -339,9 +339,10 @@ def learned_workload(args):
            "heldout_objective": obj,
            "expected_work_per_draw": {"learned": sum(cost_l) / 2, "uniform": sum(cost_u) / 2},
            "runs": runs,
-           "roofline": {"bound": "alu", "achieved": train_tf, "peak": 157.3, "unit": "TFLOP/s",
+           "roofline": {"bound": "mfma", "achieved": train_tf, "peak": 157.3, "unit": "TFLOP/s",
                         "frac": train_tf / 157.3, "traffic": None,
-                        "kernel": "proposal network train step (forward + objective + backward + Adam), FP32 VALU"}}
+                        "kernel": "proposal network train step (forward + objective + backward + Adam); "
+                                  "hidden-layer products on FP32 MFMA, first layer and tanh on the VALU"}}
     print(json.dumps(out))
     net.destroy()
     P.destroy()

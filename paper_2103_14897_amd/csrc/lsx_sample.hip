@@ -336,14 +336,9 @@ __global__ __launch_bounds__(256) void k_features(int nf, int W, int d, const do
 
 // ---------------------------------------------------------------- proposal network
 // Flat FP32 parameters: W1 [nin][64], b1 [64], W2 [64][64], b2 [64], w3 [64], b3.
-// z = w3 . tanh(W2^T tanh(W1^T x + b1) + b2) + b3.  Rows are processed in blocks of 32
-// by 256 threads: thread (r = tid / 8, q = tid % 8) owns row r and hidden units
-// 8q..8q+7 of both layers; activations are exchanged through LDS (row stride 65).
+// z = w3 . tanh(W2^T tanh(W1^T x + b1) + b2) + b3.
 constexpr int MLP_H = 64;
 constexpr int MLP_NIN_MAX = 8;
-constexpr int MLP_LD = 65;
-constexpr int MLP_ROWS = 32;
-constexpr int MLP_UPT = 8;  // hidden units per thread
 
 struct MlpOff {
   int W1, b1, W2, b2, w3, b3, n;
@@ -364,180 +359,247 @@ __device__ __forceinline__ void mlp_stage(const float* theta, int n, float* sp) 
   for (int k = threadIdx.x; k < n; k += blockDim.x) sp[k] = theta[k];
 }
 
-// first layer for row r, units 8q..: H1[r][j] = tanh(b1 + x . W1[:, j])
-__device__ __forceinline__ void mlp_layer1(const float* sp, const MlpOff& o, int nin, const float (&x)[MLP_NIN_MAX],
-                                           int r, int q, float* H1) {
-#pragma unroll
-  for (int jj = 0; jj < MLP_UPT; ++jj) {
-    const int j = MLP_UPT * q + jj;
-    float a = sp[o.b1 + j];
-    for (int i = 0; i < nin; ++i) a += x[i] * sp[o.W1 + i * MLP_H + j];
-    H1[r * MLP_LD + j] = tanhf(a);
-  }
-}
-
-// second layer for row r, units 8q..: h2[k] = tanh(b2 + sum_j H1[r][j] W2[j][k])
-__device__ __forceinline__ void mlp_layer2(const float* sp, const MlpOff& o, int r, int q, const float* H1,
-                                           float (&h2)[MLP_UPT]) {
-#pragma unroll
-  for (int kk = 0; kk < MLP_UPT; ++kk) h2[kk] = sp[o.b2 + MLP_UPT * q + kk];
-#pragma unroll 4
-  for (int j = 0; j < MLP_H; ++j) {
-    const float hj = H1[r * MLP_LD + j];
-    const float* w2 = sp + o.W2 + j * MLP_H + MLP_UPT * q;
-#pragma unroll
-    for (int kk = 0; kk < MLP_UPT; ++kk) h2[kk] += hj * w2[kk];
-  }
-#pragma unroll
-  for (int kk = 0; kk < MLP_UPT; ++kk) h2[kk] = tanhf(h2[kk]);
-}
-
 __device__ __forceinline__ void mlp_load_row(const float* X, int64_t M, int nin, int64_t m, float (&x)[MLP_NIN_MAX]) {
 #pragma unroll
   for (int i = 0; i < MLP_NIN_MAX; ++i) x[i] = (m < M && i < nin) ? X[m * nin + i] : 0.f;
 }
 
-__global__ __launch_bounds__(256) void k_mlp_fwd(const float* theta, int nin, const float* X, int64_t M, float* z) {
-  extern __shared__ float sp[];
-  const MlpOff o(nin);
-  float* H1 = sp + ((o.n + 3) & ~3);
-  mlp_stage(theta, o.n, sp);
-  __syncthreads();
-  const int r = threadIdx.x >> 3, q = threadIdx.x & 7;
-  const int64_t nblk = (M + MLP_ROWS - 1) / MLP_ROWS;
-  for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
-    const int64_t m = blk * MLP_ROWS + r;
-    float x[MLP_NIN_MAX];
-    mlp_load_row(X, M, nin, m, x);
-    mlp_layer1(sp, o, nin, x, r, q, H1);
-    __syncthreads();
-    float h2[MLP_UPT];
-    mlp_layer2(sp, o, r, q, H1, h2);
-    float zp = 0.f;
+// The hidden-layer products are dense contractions over 64 units: H1 (rows x 64) W2, and in the
+// backward pass D2 W2^T and H1^T D2.  Each wave takes chunks of 16 rows and forms them on the
+// matrix cores with v_mfma_f32_16x16x4f32 (FP32 operands and accumulation, the network's own
+// precision); the first layer (nin inputs), the tanh and the output layer stay on the VALU.
+// Operand layouts of the instruction: A (16 x 4): lane l holds A[l % 16][l / 16]; B (4 x 16):
+// lane l holds B[l / 16][l % 16]; C (16 x 16): element r of lane l is C[4 (l / 16) + r][l % 16].
+typedef float mlp_v4f __attribute__((ext_vector_type(4)));
+constexpr int MLP_CH = 16;    // rows per wave chunk
+constexpr int MLP_LDT = 68;   // LDS row stride of a chunk's 64-wide tiles (floats)
+constexpr int MLP_WTILE = 2 * MLP_CH * MLP_LDT + MLP_CH * MLP_NIN_MAX;  // per-wave LDS (H1, D, X)
+
+// W2 in the B layout: w2[kk][ct] = W2[4 kk + lk][16 ct + li]
+__device__ __forceinline__ void mlp_w2_frag(const float* sp, const MlpOff& o, int li, int lk, float (&w2)[16][4]) {
 #pragma unroll
-    for (int kk = 0; kk < MLP_UPT; ++kk) zp += h2[kk] * sp[o.w3 + MLP_UPT * q + kk];
-    zp += __shfl_xor(zp, 1);
-    zp += __shfl_xor(zp, 2);
-    zp += __shfl_xor(zp, 4);
-    if (q == 0 && m < M) z[m] = zp + sp[o.b3];
-    __syncthreads();
+  for (int kk = 0; kk < 16; ++kk)
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) w2[kk][ct] = sp[o.W2 + (4 * kk + lk) * MLP_H + 16 * ct + li];
+}
+
+// H1[li][4 kk + lk] for kk = 0..15 (the A layout of the layer-2 product), fed straight into it:
+// acc[ct] = pre-activation of layer 2, rows 4 lk + r, units 16 ct + li.  H1 (may be null) gets
+// the chunk's first-layer activations at [row][unit].  W2 operands from registers (w2, REG) or
+// from the staged parameters in LDS.
+template <bool REG>
+__device__ __forceinline__ void mlp_hidden(const float* sp, const MlpOff& o, int nin, const float (&x)[MLP_NIN_MAX],
+                                           int li, int lk, const float (*w2)[4], mlp_v4f (&acc)[4], float* H1) {
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) acc[ct] = (mlp_v4f){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int kk = 0; kk < 16; ++kk) {
+    const int j = 4 * kk + lk;
+    float a = sp[o.b1 + j];
+#pragma unroll
+    for (int i = 0; i < MLP_NIN_MAX; ++i)
+      if (i < nin) a += x[i] * sp[o.W1 + i * MLP_H + j];
+    const float h = tanhf(a);
+    if (H1) H1[li * MLP_LDT + j] = h;
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+      const float b = REG ? w2[kk][ct] : sp[o.W2 + (4 * kk + lk) * MLP_H + 16 * ct + li];
+      acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(h, b, acc[ct], 0, 0, 0);
+    }
   }
 }
 
-// Backward of sum_m g_m z_m, g_m = dz[m] * (*gscale when set).  Per row block: delta2 =
-// g w3 (1 - h2^2), delta1 = (W2 delta2)(1 - h1^2); thread (j = tid/4, part) accumulates
-// dW2[j][16 part..] = sum_r H1[r][j] D2[r][k], the row-owning threads accumulate the bias
-// and w3 terms, and the workgroup's partial gradient is written to partial[blockIdx.x][:].
+__global__ __launch_bounds__(256) void k_mlp_fwd(const float* theta, int nin, const float* X, int64_t M, float* z) {
+  extern __shared__ float sp[];
+  const MlpOff o(nin);
+  mlp_stage(theta, o.n, sp);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4, wave = threadIdx.x >> 6;
+  float w2[16][4], b2[4], w3[4];
+  mlp_w2_frag(sp, o, li, lk, w2);
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) {
+    b2[ct] = sp[o.b2 + 16 * ct + li];
+    w3[ct] = sp[o.w3 + 16 * ct + li];
+  }
+  const float b3 = sp[o.b3];
+  const int64_t nch = (M + MLP_CH - 1) / MLP_CH;
+  for (int64_t c = (int64_t)blockIdx.x * 4 + wave; c < nch; c += (int64_t)gridDim.x * 4) {
+    float x[MLP_NIN_MAX];
+    mlp_load_row(X, M, nin, c * MLP_CH + li, x);
+    mlp_v4f acc[4];
+    mlp_hidden<true>(sp, o, nin, x, li, lk, w2, acc, nullptr);
+    float zr[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      zr[r] = 0.f;
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) zr[r] += tanhf(acc[ct][r] + b2[ct]) * w3[ct];
+#pragma unroll
+      for (int off = 1; off < 16; off <<= 1) zr[r] += __shfl_xor(zr[r], off);
+    }
+    if (li == 0)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t m = c * MLP_CH + 4 * lk + r;
+        if (m < M) z[m] = zr[r] + b3;
+      }
+  }
+}
+
+// Backward of sum_m g_m z_m, g_m = dz[m] * (*gscale when set):
+//   d2 = g w3 (1 - h2^2),  d1 = (d2 W2^T)(1 - h1^2),
+//   grad W2 = H1^T d2 (matrix cores, accumulated in registers over the wave's chunks),
+//   grad W1 = X^T d1, b1, b2, w3, b3: sums over rows.
+// Each wave stages its chunk's H1, d2 (then d1) and inputs in its own LDS tiles; the waves'
+// sums are added in wave order at the end and the workgroup writes partial[blockIdx.x][:].
 __global__ __launch_bounds__(256) void k_mlp_bwd(const float* theta, int nin, const float* X, int64_t M,
                                                  const float* dz, const double* gscale, float* partial) {
   extern __shared__ float sp[];
   const MlpOff o(nin);
-  float* H1 = sp + ((o.n + 3) & ~3);
-  float* D2 = H1 + MLP_ROWS * MLP_LD;
-  float* D1 = D2 + MLP_ROWS * MLP_LD;
-  float* XS = D1 + MLP_ROWS * MLP_LD;  // [MLP_ROWS][MLP_NIN_MAX]
-  float* G = XS + MLP_ROWS * MLP_NIN_MAX;
+  const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4, wave = threadIdx.x >> 6;
+  float* H1 = sp + ((o.n + 3) & ~3) + wave * MLP_WTILE;
+  float* D = H1 + MLP_CH * MLP_LDT;
+  float* XS = D + MLP_CH * MLP_LDT;
   mlp_stage(theta, o.n, sp);
   __syncthreads();
-  const int tid = threadIdx.x;
-  const int r = tid >> 3, q = tid & 7;
   const float gs = gscale ? (float)*gscale : 1.f;
-  float accW2[16], accw3[MLP_UPT], accb2[MLP_UPT], accb1[MLP_UPT], accW1[2], accb3 = 0.f;
+  float b2[4], w3[4];
 #pragma unroll
-  for (int k = 0; k < 16; ++k) accW2[k] = 0.f;
+  for (int ct = 0; ct < 4; ++ct) {
+    b2[ct] = sp[o.b2 + 16 * ct + li];
+    w3[ct] = sp[o.w3 + 16 * ct + li];
+  }
+  mlp_v4f gW2[4][4];  // [jt][kt]: grad W2[16 jt + 4 lk + r][16 kt + li]
 #pragma unroll
-  for (int k = 0; k < MLP_UPT; ++k) accw3[k] = accb2[k] = accb1[k] = 0.f;
-  accW1[0] = accW1[1] = 0.f;
-  const int64_t nblk = (M + MLP_ROWS - 1) / MLP_ROWS;
-  for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
-    const int64_t m = blk * MLP_ROWS + r;
+  for (int jt = 0; jt < 4; ++jt)
+#pragma unroll
+    for (int kt = 0; kt < 4; ++kt) gW2[jt][kt] = (mlp_v4f){0.f, 0.f, 0.f, 0.f};
+  float gb2[4] = {0.f, 0.f, 0.f, 0.f}, gw3[4] = {0.f, 0.f, 0.f, 0.f};  // units 16 ct + li, rows 4 lk + r
+  float gW1[MLP_NIN_MAX], gb1 = 0.f, gb3 = 0.f;                          // unit = lane
+#pragma unroll
+  for (int i = 0; i < MLP_NIN_MAX; ++i) gW1[i] = 0.f;
+  const int64_t nch = (M + MLP_CH - 1) / MLP_CH;
+  for (int64_t c = (int64_t)blockIdx.x * 4 + wave; c < nch; c += (int64_t)gridDim.x * 4) {
     float x[MLP_NIN_MAX];
-    mlp_load_row(X, M, nin, m, x);
-    const float g = (m < M) ? dz[m] * gs : 0.f;
-    if (q == 0) {
+    mlp_load_row(X, M, nin, c * MLP_CH + li, x);
+    if (lk == 0)
 #pragma unroll
-      for (int i = 0; i < MLP_NIN_MAX; ++i) XS[r * MLP_NIN_MAX + i] = x[i];
-      accb3 += g;
-    }
-    mlp_layer1(sp, o, nin, x, r, q, H1);
-    __syncthreads();
-    float h2[MLP_UPT];
-    mlp_layer2(sp, o, r, q, H1, h2);
+      for (int i = 0; i < MLP_NIN_MAX; ++i) XS[li * MLP_NIN_MAX + i] = x[i];
+    mlp_v4f acc[4];
+    mlp_hidden<false>(sp, o, nin, x, li, lk, nullptr, acc, H1);
+    float g[4];
 #pragma unroll
-    for (int kk = 0; kk < MLP_UPT; ++kk) {
-      const int k = MLP_UPT * q + kk;
-      const float d2 = g * sp[o.w3 + k] * (1.f - h2[kk] * h2[kk]);
-      D2[r * MLP_LD + k] = d2;
-      accw3[kk] += g * h2[kk];
-      accb2[kk] += d2;
+    for (int r = 0; r < 4; ++r) {
+      const int64_t m = c * MLP_CH + 4 * lk + r;
+      g[r] = (m < M) ? dz[m] * gs : 0.f;
     }
-    __syncthreads();
-#pragma unroll 1
-    for (int jj = 0; jj < MLP_UPT; ++jj) {
-      const int j = MLP_UPT * q + jj;
-      float s = 0.f;
-      const float* w2 = sp + o.W2 + j * MLP_H;
-#pragma unroll 4
-      for (int k = 0; k < MLP_H; ++k) s += w2[k] * D2[r * MLP_LD + k];
-      const float h = H1[r * MLP_LD + j];
-      const float d1 = s * (1.f - h * h);
-      D1[r * MLP_LD + j] = d1;
-      accb1[jj] += d1;
-    }
-    __syncthreads();
-    {  // outer products over the rows of the block
-      const int j = tid >> 2, k0 = 16 * (tid & 3);
-#pragma unroll 2
-      for (int rr = 0; rr < MLP_ROWS; ++rr) {
-        const float h = H1[rr * MLP_LD + j];
+    if (li == 0) gb3 += (g[0] + g[1]) + (g[2] + g[3]);
 #pragma unroll
-        for (int kk = 0; kk < 16; ++kk) accW2[kk] += h * D2[rr * MLP_LD + k0 + kk];
+    for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float h2 = tanhf(acc[ct][r] + b2[ct]);
+        const float d2 = g[r] * w3[ct] * (1.f - h2 * h2);
+        D[(4 * lk + r) * MLP_LDT + 16 * ct + li] = d2;
+        gb2[ct] += d2;
+        gw3[ct] += g[r] * h2;
+      }
+    // the chunk's tiles are written by other lanes of this wave
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // grad W2 += H1^T d2 (k-steps over the chunk's rows)
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+      const int row = 4 * s4 + lk;
+      float a[4], b[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        a[t] = H1[row * MLP_LDT + 16 * t + li];
+        b[t] = D[row * MLP_LDT + 16 * t + li];
       }
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const int e = tid + 256 * u;
-        if (e < nin * MLP_H) {
-          const int i = e / MLP_H, jj = e % MLP_H;
-          float s = 0.f;
+      for (int jt = 0; jt < 4; ++jt)
+#pragma unroll
+        for (int kt = 0; kt < 4; ++kt)
+          gW2[jt][kt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[jt], b[kt], gW2[jt][kt], 0, 0, 0);
+    }
+    // e = d2 W2^T: rows 4 lk + r, units 16 jt + li
+    mlp_v4f e[4];
+#pragma unroll
+    for (int jt = 0; jt < 4; ++jt) e[jt] = (mlp_v4f){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      const float a = D[li * MLP_LDT + 4 * kk + lk];
+#pragma unroll
+      for (int jt = 0; jt < 4; ++jt)
+        e[jt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, sp[o.W2 + (16 * jt + li) * MLP_H + 4 * kk + lk], e[jt], 0,
+                                                     0, 0);
+    }
+    // d1 = e (1 - h1^2), written over d2 (every lane has read its d2 operands above)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int jt = 0; jt < 4; ++jt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 4 * lk + r, j = 16 * jt + li;
+        const float h = H1[row * MLP_LDT + j];
+        D[row * MLP_LDT + j] = e[jt][r] * (1.f - h * h);
+      }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // grad W1, b1 for unit j = lane over the chunk's rows
 #pragma unroll 4
-          for (int rr = 0; rr < MLP_ROWS; ++rr) s += XS[rr * MLP_NIN_MAX + i] * D1[rr * MLP_LD + jj];
-          accW1[u] += s;
+    for (int row = 0; row < MLP_CH; ++row) {
+      const float d1 = D[row * MLP_LDT + lane];
+      gb1 += d1;
+#pragma unroll
+      for (int i = 0; i < MLP_NIN_MAX; ++i) gW1[i] += XS[row * MLP_NIN_MAX + i] * d1;
+    }
+    // the tiles are rewritten by the next chunk
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  // sums over the lane groups lk (rows) of the unit-per-lane-group terms
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) {
+    gb2[ct] += __shfl_xor(gb2[ct], 16);
+    gb2[ct] += __shfl_xor(gb2[ct], 32);
+    gw3[ct] += __shfl_xor(gw3[ct], 16);
+    gw3[ct] += __shfl_xor(gw3[ct], 32);
+  }
+  gb3 += __shfl_xor(gb3, 16);
+  gb3 += __shfl_xor(gb3, 32);
+  // the waves' sums, added in wave order into sp (theta is no longer needed)
+  __syncthreads();
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
+      auto put = [&](int idx, float v) { sp[idx] = (w == 0) ? v : sp[idx] + v; };
+#pragma unroll
+      for (int jt = 0; jt < 4; ++jt)
+#pragma unroll
+        for (int kt = 0; kt < 4; ++kt)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) put(o.W2 + (16 * jt + 4 * lk + r) * MLP_H + 16 * kt + li, gW2[jt][kt][r]);
+      for (int i = 0; i < nin; ++i) put(o.W1 + i * MLP_H + lane, gW1[i]);
+      put(o.b1 + lane, gb1);
+      if (lk == 0)
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) {
+          put(o.b2 + 16 * ct + li, gb2[ct]);
+          put(o.w3 + 16 * ct + li, gw3[ct]);
         }
-      }
+      if (lane == 0) put(o.b3, gb3);
     }
     __syncthreads();
   }
   float* out = partial + (int64_t)blockIdx.x * o.n;
-  {
-    const int j = tid >> 2, k0 = 16 * (tid & 3);
-#pragma unroll
-    for (int kk = 0; kk < 16; ++kk) out[o.W2 + j * MLP_H + k0 + kk] = accW2[kk];
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int e = tid + 256 * u;
-      if (e < nin * MLP_H) out[o.W1 + e] = accW1[u];
-    }
-  }
-  // row-owned sums: reduce over the block's rows (fixed order) through LDS
-#pragma unroll
-  for (int kk = 0; kk < MLP_UPT; ++kk) {
-    H1[r * MLP_LD + MLP_UPT * q + kk] = accb1[kk];
-    D2[r * MLP_LD + MLP_UPT * q + kk] = accb2[kk];
-    D1[r * MLP_LD + MLP_UPT * q + kk] = accw3[kk];
-  }
-  if (q == 0) G[r] = accb3;
-  __syncthreads();
-  if (tid < 3 * MLP_H) {
-    const int which = tid / MLP_H, k = tid % MLP_H;
-    const float* buf = which == 0 ? H1 : (which == 1 ? D2 : D1);
-    float s = 0.f;
-    for (int rr = 0; rr < MLP_ROWS; ++rr) s += buf[rr * MLP_LD + k];
-    out[(which == 0 ? o.b1 : (which == 1 ? o.b2 : o.w3)) + k] = s;
-  } else if (tid == 3 * MLP_H) {
-    float s = 0.f;
-    for (int rr = 0; rr < MLP_ROWS; ++rr) s += G[rr];
-    out[o.b3] = s;
-  }
+  for (int k = threadIdx.x; k < o.n; k += blockDim.x) out[k] = sp[k];
 }
 
 // grad[e] = sum over workgroups of partial[b][e] (FP64, fixed order)
@@ -724,22 +786,20 @@ hipError_t launch_features(hipStream_t s, int nf, int W, int d, const double* sf
   return hipGetLastError();
 }
 
-static size_t mlp_lds_fwd(int nin) {
-  return (size_t)(((MlpOff(nin).n + 3) & ~3) + MLP_ROWS * MLP_LD) * sizeof(float);
-}
+static size_t mlp_lds_fwd(int nin) { return (size_t)((MlpOff(nin).n + 3) & ~3) * sizeof(float); }
 static size_t mlp_lds_bwd(int nin) {
-  return (size_t)(((MlpOff(nin).n + 3) & ~3) + 3 * MLP_ROWS * MLP_LD + MLP_ROWS * MLP_NIN_MAX + MLP_ROWS) *
-         sizeof(float);
+  return (size_t)(((MlpOff(nin).n + 3) & ~3) + 4 * MLP_WTILE) * sizeof(float);
 }
 
+// workgroups of the backward pass (4 waves of 16-row chunks each): one partial gradient each
 int mlp_bwd_blocks(int64_t M) {
-  const int64_t nblk = (M + MLP_ROWS - 1) / MLP_ROWS;
+  const int64_t nblk = (M + 4 * MLP_CH - 1) / (4 * MLP_CH);
   return (int)(nblk < 1 ? 1 : (nblk > 512 ? 512 : nblk));
 }
 
 hipError_t launch_mlp_fwd(hipStream_t s, const float* theta, int nin, const float* X, int64_t M, float* z) {
   if (M == 0) return hipSuccess;
-  const int64_t nblk = (M + MLP_ROWS - 1) / MLP_ROWS;
+  const int64_t nblk = (M + 4 * MLP_CH - 1) / (4 * MLP_CH);
   const unsigned grid = (unsigned)(nblk > 2048 ? 2048 : nblk);
   hipLaunchKernelGGL(k_mlp_fwd, dim3(grid), dim3(256), mlp_lds_fwd(nin), s, theta, nin, X, M, z);
   return hipGetLastError();
