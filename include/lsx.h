@@ -374,11 +374,14 @@ lsx_status lsx_state_store_mode(const lsx_state* st, int32_t* nontemporal, doubl
  * lsx_state_set_tuning: tile shape (nb, ks) and k-step groups in flight (`groups`, 0 for the
  *   library default) of `layer`'s passes; the tile list is rebuilt on the host and uploaded
  *   (synchronous).  Available shapes: W = 1: nb = 1 and ks in {1, 2, 4}, or {-1, -2, -4} except
- *   for LSX_MIX_BF16X3, groups = 0.  W > 1: nb in {1, 2, 4} with 16 nb <= W rounded up to 16;
- *   ks in {1, 2, 4} with groups 0, or 1 or 2 for LSX_FP64 / LSX_MIX_FP32; or ks in {-2, -4, -8}
- *   for the mixed paths (-ks <= 4 nb for LSX_MIX_FP32, nb <= 2 for LSX_MIX_BF16X3), groups 0.
- *   Anything else is LSX_E_INVALID
- *   and leaves the state unchanged.  lsx_state_tuning then reports pass_us = 0.
+ *   for LSX_MIX_BF16X3, groups = 0; nb = 8 with the same ks: orbit tiles, which multiply up to
+ *   eight fibres that share one stored propagator (lsx_plan_sharing) with one load of each
+ *   propagator chunk and give the same result as nb = 1 with that ks (LSX_E_INVALID on a layer
+ *   where no fibre shares).  W > 1: nb in {1, 2, 4} with 16 nb <= W rounded up to 16; ks in
+ *   {1, 2, 4} with groups 0, or 1 or 2 for LSX_FP64 / LSX_MIX_FP32; or ks in {-2, -4, -8} for
+ *   the mixed paths (-ks <= 4 nb for LSX_MIX_FP32, nb <= 2 for LSX_MIX_BF16X3), groups 0.
+ *   Anything else is LSX_E_INVALID and leaves the state unchanged.  lsx_state_tuning then
+ *   reports pass_us = 0.
  * lsx_state_set_store_mode: 0 ordinary, 1 non-temporal output stores (LSX_E_INVALID otherwise).
  * Neither call touches the state's values.  Not while a step on the state is in flight.
  */

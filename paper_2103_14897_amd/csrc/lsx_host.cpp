@@ -628,6 +628,13 @@ struct LayerDev {
   std::vector<int64_t> h_boff;
   std::vector<int32_t> band_lo, band_hi;
   DBuf<int32_t> d_band;  // the same bands on the device, (lo, hi) pairs (empty: dense products)
+  // Fibres that share a stored propagator, in groups of up to kOrbitMax in fibre order (a
+  // fibre without partners is a group of one), and the device table of the groups for the
+  // single-state orbit passes (PassArgs::orbit; empty when no fibre shares); orbit_max: the
+  // largest group
+  std::vector<std::vector<int>> groups;
+  DBuf<int32_t> d_orbit;
+  int orbit_max = 0;
 };
 
 // Band of row blocks [rb0, rb0 + n) of fibre f (those inside the fibre) as fibre positions
@@ -1110,6 +1117,30 @@ static lsx_status precompute_layer(lsx_plan* pl, int layer, hipStream_t s) {
     ld.h_poff[f] = uoff[ld.rep[f]];
     ld.h_d0[f] = ft.ptr[uniq[ld.rep[f]]];
   }
+  {
+    ld.groups.clear();
+    ld.orbit_max = 0;
+    std::vector<int> open(nu, -1);  // propagator slot -> its group being filled
+    for (int f = 0; f < nf; ++f) {
+      int& g = open[ld.rep[f]];
+      if (g < 0 || (int)ld.groups[g].size() >= kOrbitMax) {
+        g = (int)ld.groups.size();
+        ld.groups.emplace_back();
+      }
+      ld.groups[g].push_back(f);
+    }
+    for (const std::vector<int>& g : ld.groups) ld.orbit_max = std::max(ld.orbit_max, (int)g.size());
+    ld.d_orbit.release();
+    if (ld.orbit_max > 1) {
+      std::vector<int32_t> tab((size_t)kOrbitStride * ld.groups.size());
+      for (size_t g = 0; g < ld.groups.size(); ++g) {
+        const std::vector<int>& mem = ld.groups[g];
+        tab[g * kOrbitStride] = (int32_t)mem.size();
+        for (int m = 0; m < kOrbitMax; ++m) tab[g * kOrbitStride + 1 + m] = ft.ptr[mem[m < (int)mem.size() ? m : 0]];
+      }
+      LSX_TRY(ld.d_orbit.upload(tab, s));
+    }
+  }
   // bands of the stored propagators, one entry per 16-row block, united over the slots
   std::vector<int64_t> boff(nu + 1, 0);
   for (int b = 0; b < nu; ++b) boff[b + 1] = boff[b] + (ft.ptr[uniq[b] + 1] - ft.ptr[uniq[b]] + 15) / 16;
@@ -1441,61 +1472,57 @@ struct lsx_state {
 // its own L2, so fibres are assigned to XCDs whole (longest first, to the least-loaded XCD) and
 // the XCD queues are interleaved; every queue lists its largest tiles first.  Fibres that share
 // one stored propagator (point-symmetry orbits, kappa = 1 windows) go to the same XCD in groups
-// of up to kShareGroup, with the tiles of a group's fibres for the same rows and columns listed
+// of up to kOrbitMax, with the tiles of a group's fibres for the same rows and columns listed
 // back to back, so each propagator block is fetched into that L2 once for the whole group
-// (LSX_GROUP_TILES=0 assigns every fibre on its own).  Shorter queues are padded with empty
-// tiles (f = -1).  ms > 1: tiles of the row-split kernels, rb counts groups of ms 16-row blocks.
-static constexpr int kShareGroup = 8;
+// (LSX_GROUP_TILES=0 assigns every fibre on its own).  orbit: single-state orbit tiles, one per
+// group and row block (f = the group's entry in the layer's orbit table), which multiply the
+// group's states together.  Shorter queues are padded with empty tiles (f = -1).  ms > 1:
+// tiles of the row-split kernels, rb counts groups of ms 16-row blocks.
 static void build_tiles(const lsx_plan* pl, int layer, int W, int nb, int wb0, int wb1, std::vector<TileDesc>& out,
-                        int ms = 1) {
+                        int ms = 1, bool orbit = false) {
   const LayerDev& ld = pl->L[layer - 1];
   const int wt = wb1 - wb0;
   (void)W;
   (void)nb;
   const int NX = std::max(1, env_int("LSX_XCDS", 8));
-  const bool share = env_int("LSX_GROUP_TILES", 1) != 0 && (int)ld.rep.size() == ld.nf;
-  // groups of fibres with one stored propagator, in fibre order, split into kShareGroup chunks
-  std::vector<std::vector<int>> groups;
-  {
-    std::map<int, int> open;  // propagator slot -> index of its group being filled
-    for (int f = 0; f < ld.nf; ++f) {
-      const int key = share ? ld.rep[f] : f;
-      auto it = open.find(key);
-      if (it == open.end() || (int)groups[it->second].size() >= kShareGroup) {
-        open[key] = (int)groups.size();
-        groups.push_back({f});
-      } else {
-        groups[it->second].push_back(f);
-      }
-    }
+  const bool share = orbit || (env_int("LSX_GROUP_TILES", 1) != 0 && (int)ld.groups.size() > 0);
+  std::vector<std::vector<int>> single;
+  if (!share) {
+    single.resize(ld.nf);
+    for (int f = 0; f < ld.nf; ++f) single[f] = {f};
   }
+  const std::vector<std::vector<int>>& groups = share ? ld.groups : single;
   auto glen = [&](const std::vector<int>& g) { return ld.h_ptr[g[0] + 1] - ld.h_ptr[g[0]]; };
-  std::stable_sort(groups.begin(), groups.end(),
-                   [&](const std::vector<int>& x, const std::vector<int>& y) { return glen(x) > glen(y); });
+  std::vector<int> order(groups.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return glen(groups[x]) > glen(groups[y]); });
   // balance the bins by tile count (equal counts need no padding tiles), ties by cost
   std::vector<double> load(NX, 0.0);
   std::vector<int64_t> count(NX, 0);
   std::vector<std::vector<TileDesc>> bins(NX);
-  for (const std::vector<int>& g : groups) {
+  for (int gi : order) {
+    const std::vector<int>& g = groups[gi];
     const int L = glen(g);
     const int nrb = ((L + 15) / 16 + ms - 1) / ms;
+    const int ntg = orbit ? 1 : (int)g.size();  // tiles per row block and column block
     int x = 0;
     for (int y = 1; y < NX; ++y)
       if (count[y] < count[x] || (count[y] == count[x] && load[y] < load[x])) x = y;
-    count[x] += (int64_t)nrb * wt * (int64_t)g.size();
+    count[x] += (int64_t)nrb * wt * ntg;
     for (int rb = 0; rb < nrb; ++rb) {
       for (int wb = wb0; wb < wb1; ++wb) {
-        for (int f : g) {
+        for (int i = 0; i < ntg; ++i) {
+          const int f = g[i];
           int32_t k0, k1;
           fibre_band(ld, f, rb * ms, ms, k0, k1);
-          if (wb == wb0) load[x] += (double)wt * (std::min(k1, L) - k0 + 8);
+          if (wb == wb0) load[x] += (double)wt * (std::min(k1, L) - k0 + 8) * (orbit ? (double)g.size() : 1.0);
           TileDesc t;
           t.r0 = ld.h_ptr[f];
           t.L = L;
           t.rb = rb;
           t.wb = wb;
           t.poff = ld.h_poff.empty() ? 0 : ld.h_poff[f];
-          t.f = f;
+          t.f = orbit ? gi : f;
           t.d0 = ld.h_d0.empty() ? ld.h_ptr[f] : ld.h_d0[f];
           t.k0 = k0;
           t.k1 = k1;
@@ -1546,6 +1573,8 @@ static lsx_status choose_cycle(lsx_plan* pl, lsx_state* st, bool tune_store) {
     x.diag = pl->diag.p ? pl->diag.p + (size_t)((layer - 1) * 3 + slot) * N : nullptr;
     x.zero = pl->zero.p;
     x.rb_band = ld.d_band.p;
+    x.orbit = ld.d_orbit.p;
+    x.orbit_max = ld.orbit_max;
     x.W = W;
   }
   // per layer: option 0 the single-pass winner, 1 the winner at the other depth, 2 the runner-up
@@ -1671,11 +1700,13 @@ static lsx_status choose_tiles(lsx_plan* pl, lsx_state* st) {
   const int fnb = env_int("LSX_NB", 0), fks = env_int("LSX_KS", 0);
   const bool tune_u = (pl->fmt == PF_F64 || pl->fmt == PF_F32) && std::getenv("LSX_PREFETCH") == nullptr;
   if (W == 1) {
-    // ks < 0: FP64 / FP32 tiles of two row blocks with -ks waves
-    for (int k : {1, 2, 4}) {
-      cands.push_back({1, k, 0});
-      if (pl->fmt != PF_BF16X3) cands.push_back({1, -k, 0});
-    }
+    // ks < 0: FP64 / FP32 tiles of two row blocks with -ks waves; nb = kOrbitNB: orbit tiles
+    // (layers whose fibres share propagators)
+    for (int nb : {1, kOrbitNB})
+      for (int k : {1, 2, 4}) {
+        cands.push_back({nb, k, 0});
+        if (pl->fmt != PF_BF16X3) cands.push_back({nb, -k, 0});
+      }
   } else {
     for (int nb : {1, 2, 4})
       for (int k : {1, 2, 4})
@@ -1691,7 +1722,7 @@ static lsx_status choose_tiles(lsx_plan* pl, lsx_state* st) {
   if (fnb > 0 || fks != 0) {
     const bool rowsplit = fks < 0 && ((W > 1 && rowsplit_shape(pl->fmt, fnb > 0 ? fnb : 1, -fks)) ||
                                       (W == 1 && pl->fmt != PF_BF16X3 && (fks == -1 || fks == -2 || fks == -4)));
-    const Shape f{(fnb == 1 || fnb == 2 || fnb == 4) ? fnb : 1,
+    const Shape f{(fnb == 1 || fnb == 2 || fnb == 4 || (W == 1 && fnb == kOrbitNB)) ? fnb : 1,
                   rowsplit ? fks : ((fks == 1 || fks == 2 || fks == 4) ? fks : 2), 0};
     cands.assign(1, f);
   } else if (env_int("LSX_AUTOTUNE", 1) == 0 || pl->sys->N == 0) {
@@ -1708,11 +1739,15 @@ static lsx_status choose_tiles(lsx_plan* pl, lsx_state* st) {
   for (int layer = 1; layer <= nl && err == LSX_OK; ++layer) {
     float best = -1.f, second = -1.f;
     st->alt_nb[layer - 1] = 0;
-    for (const Shape& c : cands) {
+    for (Shape c : cands) {
+      if (W == 1 && c.nb == kOrbitNB && pl->L[layer - 1].orbit_max < 2) {
+        if (cands.size() > 1) continue;  // no fibre of this layer shares its propagator
+        c.nb = 1;
+      }
       std::vector<TileDesc> t;
       const int wt = (W == 1) ? 1 : (W + 16 * c.nb - 1) / (16 * c.nb);
       // row blocks per tile: W = 1 pairs for ks < 0, else -ks for the row-split shapes
-      build_tiles(pl, layer, W, c.nb, 0, wt, t, c.ks < 0 ? (W == 1 ? 2 : -c.ks) : 1);
+      build_tiles(pl, layer, W, c.nb, 0, wt, t, c.ks < 0 ? (W == 1 ? 2 : -c.ks) : 1, W == 1 && c.nb == kOrbitNB);
       DBuf<TileDesc> d;
       if ((err = d.upload(t, nullptr)) != LSX_OK) break;
       float ms = 0.f;
@@ -1738,6 +1773,8 @@ static lsx_status choose_tiles(lsx_plan* pl, lsx_state* st) {
         a.Y = st->buf[1];
         a.zero = pl->zero.p;
         a.rb_band = ld.d_band.p;
+        a.orbit = ld.d_orbit.p;
+        a.orbit_max = ld.orbit_max;
         a.W = W;
         a.u = c.u;
         // two timed passes (enough for passes of a millisecond or more), then, for shorter
@@ -1905,7 +1942,7 @@ extern "C" lsx_status lsx_state_store_mode(const lsx_state* st, int32_t* nontemp
 // Tile shapes the pass kernels are built for (see choose_tiles and launch_pass).
 static bool shape_valid(int fmt, int W, int nb, int ks, int u) {
   if (W == 1) {
-    if (nb != 1 || u != 0) return false;
+    if ((nb != 1 && nb != kOrbitNB) || u != 0) return false;
     if (ks == 1 || ks == 2 || ks == 4) return true;
     return fmt != PF_BF16X3 && (ks == -1 || ks == -2 || ks == -4);
   }
@@ -1923,9 +1960,12 @@ extern "C" lsx_status lsx_state_set_tuning(lsx_state* st, int32_t layer, int32_t
   if (!shape_valid(pl->fmt, st->W, nb, ks, groups))
     return fail(LSX_E_INVALID, "tile shape not available for this precision and W");
   const int W = st->W;
+  const bool orbit = W == 1 && nb == kOrbitNB;
+  if (orbit && pl->L[layer - 1].orbit_max < 2)
+    return fail(LSX_E_INVALID, "orbit tiles need fibres that share a stored propagator");
   const int wt = (W == 1) ? 1 : (W + 16 * nb - 1) / (16 * nb);
   std::vector<TileDesc> t;
-  build_tiles(pl, layer, W, nb, 0, wt, t, ks < 0 ? (W == 1 ? 2 : -ks) : 1);
+  build_tiles(pl, layer, W, nb, 0, wt, t, ks < 0 ? (W == 1 ? 2 : -ks) : 1, orbit);
   DBuf<TileDesc> d;
   LSX_TRY(d.upload(t, nullptr));
   const int l = layer - 1;
@@ -1994,6 +2034,8 @@ struct Runner {
     a.Y = st->buf[1 - cur];
     a.zero = pl->zero.p;
     a.rb_band = ld.d_band.p;
+    a.orbit = ld.d_orbit.p;
+    a.orbit_max = ld.orbit_max;
     a.W = st->W;
     a.nt = st->nt;
     a.u = st->u[layer - 1];
@@ -2994,6 +3036,8 @@ PassArgs canon_pass_args(const lsx_plan* pl, const lsx_state* st, int layer, int
   a.X = st->buf[0];
   a.Y = st->buf[1];
   a.zero = pl->zero.p;
+  a.orbit = ld.d_orbit.p;
+  a.orbit_max = ld.orbit_max;
   a.W = st->W;
   return a;
 }

@@ -66,6 +66,11 @@ struct TileDesc {
 constexpr int32_t kBandEnd = 0x7fffffff;
 // columns per propagator chunk of a format (the unit of the band)
 inline int band_chunk(int fmt) { return fmt == PF_BF16X3 ? 32 : 4; }
+// Fibres sharing a stored propagator are grouped by up to kOrbitMax; single-state passes
+// over such groups use the tile shape nb = kOrbitNB (PassArgs::orbit).
+constexpr int kOrbitMax = 8;
+constexpr int kOrbitStride = 1 + kOrbitMax;
+constexpr int kOrbitNB = 8;
 
 struct PassArgs;
 // Arguments of every fibre-pass kernel.  Element k of fibre f (fibre position
@@ -108,6 +113,12 @@ struct PassArgs {
   // K-split FP64 / FP32 passes: groups of k-steps each wave keeps in flight (1, 2 or 4; 0: the
   // library default), chosen per state by the tile tuner
   int32_t u = 0;
+  // single-state orbit passes (W = 1, tile shape nb = kOrbitNB): TileDesc::f indexes this
+  // table of fibre groups that share one stored propagator, kOrbitStride entries per group:
+  // the member count, then the fibre position of every member's first row (entries past the
+  // count repeat the first member's); orbit_max is the largest group of the layer
+  const int32_t* orbit = nullptr;
+  int32_t orbit_max = 0;
 };
 
 // ---------------------------------------------------------------- kernel launchers (lsx_kernels.hip)

@@ -1437,6 +1437,19 @@ __global__ __launch_bounds__(64 * MS) void k_pass_bf16m(PassArgs a) {
 }
 
 // ---------------------------------------------------------------- single-state fibre pass (W = 1)
+// y += p x and (sr, si) <- h (sr, si) for complex operands as explicit fused multiply-adds in
+// a fixed order, so the per-fibre and the orbit single-state kernels round alike
+__device__ __forceinline__ void cmac(double& yr, double& yi, double pr, double pi, double2 x) {
+  yr = __builtin_fma(pr, x.x, yr);
+  yr = __builtin_fma(-pi, x.y, yr);
+  yi = __builtin_fma(pr, x.y, yi);
+  yi = __builtin_fma(pi, x.x, yi);
+}
+__device__ __forceinline__ void cscale(double& sr, double& si, double2 h) {
+  const double zr = __builtin_fma(h.x, sr, -(h.y * si));
+  si = __builtin_fma(h.x, si, h.y * sr);
+  sr = zr;
+}
 // HBM-bound GEMV: each propagator entry is read once per pass.  Lane (li, lk) of chunk
 // (rb, k) multiplies entry (16rb+li, col) by x[col]; the four k-lanes and the KS waves
 // are summed in fixed order.  Mixed formats: E entries (rounded to their storage
@@ -1472,8 +1485,7 @@ __device__ __forceinline__ void k_gemv_tile(const PassArgs& a0, int ti, double* 
           const double2 x = a.X[in_row(a, r0 + k)];
           const double er = (double)(bf2f(r0v[e]) + bf2f(r1v[e]) + bf2f(r2v[e]));
           const double ei = (double)(bf2f(i0v[e]) + bf2f(i1v[e]) + bf2f(i2v[e]));
-          yr[0] += er * x.x - ei * x.y;
-          yi[0] += er * x.y + ei * x.x;
+          cmac(yr[0], yi[0], er, ei, x);
         }
       }
     }
@@ -1515,8 +1527,7 @@ __device__ __forceinline__ void k_gemv_tile(const PassArgs& a0, int ti, double* 
 #pragma unroll
         for (int j = 0; j < RB; ++j) {
           const double pr = p[j][g].x, pi = p[j][g].y;
-          yr[j] += pr * x[g].x - pi * x[g].y;
-          yi[j] += pr * x[g].y + pi * x[g].x;
+          cmac(yr[j], yi[j], pr, pi, x[g]);
         }
     }
     for (; ks < khi; ks += KS) {
@@ -1527,8 +1538,7 @@ __device__ __forceinline__ void k_gemv_tile(const PassArgs& a0, int ti, double* 
       for (int j = 0; j < RB; ++j) {
         const PT pe = *((j == 0 || Pj[j]) ? Pj[j] + (int64_t)ks * 64 : zp);
         const double pr = pe.x, pi = pe.y;
-        yr[j] += pr * x.x - pi * x.y;
-        yi[j] += pr * x.y + pi * x.x;
+        cmac(yr[j], yi[j], pr, pi, x);
       }
     }
   }
@@ -1559,8 +1569,7 @@ __device__ __forceinline__ void k_gemv_tile(const PassArgs& a0, int ti, double* 
         const double2 x = a.X[in_row(a, p)];
         if (FMT != PF_F64) {
           const double2 dg = a.diag[t.d0 + arow];
-          sr += dg.x * x.x - dg.y * x.y;
-          si += dg.x * x.y + dg.y * x.x;
+          cmac(sr, si, dg.x, dg.y, x);
         }
         if (a.wt) {
           const double g = a.wt[t.f];
@@ -1569,10 +1578,7 @@ __device__ __forceinline__ void k_gemv_tile(const PassArgs& a0, int ti, double* 
         }
       }
       if (a.ph) {
-        const double2 ph = a.ph[a.ph_idx ? a.ph_idx[p] : p];
-        const double zr = ph.x * sr - ph.y * si;
-        si = ph.x * si + ph.y * sr;
-        sr = zr;
+        cscale(sr, si, a.ph[a.ph_idx ? a.ph_idx[p] : p]);
       }
       a.Y[a.out_pos ? a.out_pos[p] : p] = make_double2(sr, si);
     }
@@ -1590,6 +1596,151 @@ template <int KS, int FMT>
 __global__ __launch_bounds__(64 * KS) void k_gemv_persist(PassArgs a0) {
   __shared__ double red[2 * KS * 16];
   persistent_tiles(a0, [&](int ti) { k_gemv_tile<KS, FMT, true>(a0, ti, red); });
+}
+
+// ---------------------------------------------------------------- single-state orbit pass (W = 1)
+// Fibres with one stored propagator (point-symmetry orbits, kappa = 1 translation classes)
+// are multiplied together: a tile covers RB row blocks of the shared propagator for the
+// states of up to M fibres of a group (PassArgs::orbit), so every propagator chunk is loaded
+// once for the whole group instead of once per fibre.  Each fibre's products are summed in
+// the order k_gemv_tile sums them for the same KS and RB (k-steps in order per lane, then the
+// four k-lanes, then the waves), so the two kernels give identical results.
+template <int KS, int FMT, int RB, int M>
+__global__ __launch_bounds__(64 * KS) void k_gemv_orbit(PassArgs a) {
+  static_assert(RB == 1 || FMT != PF_BF16X3, "BF16x3 single-state tiles cover one row block");
+  __shared__ double red[KS * RB * M * 2 * 16];
+  const TileDesc t = a.tiles[blockIdx.x];
+  if (t.f < 0) return;
+  const int32_t* og = a.orbit + (int64_t)t.f * kOrbitStride;
+  const int nm = og[0];
+  int r0[M];
+#pragma unroll
+  for (int m = 0; m < M; ++m) r0[m] = og[1 + m];
+  const int L = t.L;
+  const int lane = threadIdx.x & 63, kw = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int li = lane & 15, lk = lane >> 4;
+  const char* Pb = reinterpret_cast<const char*>(a.P) + t.poff;
+  double yr[RB][M], yi[RB][M];
+#pragma unroll
+  for (int j = 0; j < RB; ++j)
+#pragma unroll
+    for (int m = 0; m < M; ++m) yr[j][m] = yi[j][m] = 0.0;
+  if constexpr (FMT == PF_BF16X3) {
+    const int nkc = ((L + 31) & ~31) >> 5;
+    const v8u16* P = reinterpret_cast<const v8u16*>(Pb) + (int64_t)t.rb * nkc * 6 * 64 + lane;
+    int klo, khi;
+    tile_band(t, 32 * nkc, 32, klo, khi);
+    for (int kc = klo + kw; kc < khi; kc += KS) {
+      const v8u16* Pc = P + (int64_t)kc * 6 * 64;
+      const v8u16 r0v = Pc[0], i0v = Pc[64], r1v = Pc[128], i1v = Pc[192], r2v = Pc[256], i2v = Pc[320];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int k = 32 * kc + 8 * lk + e;
+        if (k < L) {
+          const double er = (double)(bf2f(r0v[e]) + bf2f(r1v[e]) + bf2f(r2v[e]));
+          const double ei = (double)(bf2f(i0v[e]) + bf2f(i1v[e]) + bf2f(i2v[e]));
+#pragma unroll
+          for (int m = 0; m < M; ++m) {
+            const double2 x = a.X[in_row(a, r0[m] + k)];
+            cmac(yr[0][m], yi[0][m], er, ei, x);
+          }
+        }
+      }
+    }
+  } else {
+    // groups of G k-steps, every load of a group issued before its products (state operands
+    // past the fibre and a missing second row block read the zero buffer, as in k_gemv_tile)
+    using PT = typename std::conditional<FMT == PF_F64, double2, float2>::type;
+    constexpr int G = M <= 2 ? 4 : (M <= 4 ? 2 : 1);
+    const int nks = ((L + 15) & ~15) >> 2;
+    const int nrb = (L + 15) >> 4;
+    const PT* zp = reinterpret_cast<const PT*>(a.zero);
+    const double2* zx = reinterpret_cast<const double2*>(a.zero);
+    const PT* Pj[RB];
+#pragma unroll
+    for (int j = 0; j < RB; ++j) {
+      const int rbj = t.rb * RB + j;
+      Pj[j] = (j == 0 || rbj < nrb) ? reinterpret_cast<const PT*>(Pb) + (int64_t)rbj * nks * 64 + lane : nullptr;
+    }
+    int klo, khi;
+    tile_band(t, 4 * nks, 4, klo, khi);
+    int ks = klo + kw;
+    for (; ks + (G - 1) * KS < khi; ks += G * KS) {
+      PT p[RB][G];
+      double2 x[G][M];
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const int kk = ks + g * KS, k = 4 * kk + lk;
+        const bool ok = k < L;
+#pragma unroll
+        for (int j = 0; j < RB; ++j) p[j][g] = *((j == 0 || Pj[j]) ? Pj[j] + (int64_t)kk * 64 : zp);
+#pragma unroll
+        for (int m = 0; m < M; ++m) x[g][m] = *(ok ? a.X + in_row(a, r0[m] + (ok ? k : 0)) : zx);
+      }
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int j = 0; j < RB; ++j) {
+          const double pr = p[j][g].x, pi = p[j][g].y;
+#pragma unroll
+          for (int m = 0; m < M; ++m) {
+            cmac(yr[j][m], yi[j][m], pr, pi, x[g][m]);
+          }
+        }
+    }
+    for (; ks < khi; ks += KS) {
+      const int k = 4 * ks + lk;
+      const bool ok = k < L;
+      double2 x[M];
+#pragma unroll
+      for (int m = 0; m < M; ++m) x[m] = *(ok ? a.X + in_row(a, r0[m] + (ok ? k : 0)) : zx);
+#pragma unroll
+      for (int j = 0; j < RB; ++j) {
+        const PT pe = *((j == 0 || Pj[j]) ? Pj[j] + (int64_t)ks * 64 : zp);
+        const double pr = pe.x, pi = pe.y;
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+          cmac(yr[j][m], yi[j][m], pr, pi, x[m]);
+        }
+      }
+    }
+  }
+  // sum the four k-lanes of each row, then the waves in order
+#pragma unroll
+  for (int j = 0; j < RB; ++j)
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      double vr = yr[j][m], vi = yi[j][m];
+      vr += __shfl_xor(vr, 16);
+      vi += __shfl_xor(vi, 16);
+      vr += __shfl_xor(vr, 32);
+      vi += __shfl_xor(vi, 32);
+      if (lk == 0) {
+        red[(((kw * RB + j) * M + m) * 2 + 0) * 16 + li] = vr;
+        red[(((kw * RB + j) * M + m) * 2 + 1) * 16 + li] = vi;
+      }
+    }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < 16 * RB * M; idx += 64 * KS) {
+    const int lr = idx & 15, m = (idx >> 4) % M, j = idx / (16 * M);
+    const int arow = 16 * (t.rb * RB + j) + lr;
+    if (m >= nm || arow >= L) continue;
+    double sr = 0.0, si = 0.0;
+    for (int w = 0; w < KS; ++w) {
+      sr += red[(((w * RB + j) * M + m) * 2 + 0) * 16 + lr];
+      si += red[(((w * RB + j) * M + m) * 2 + 1) * 16 + lr];
+    }
+    const int p = og[1 + m] + arow;
+    if (FMT != PF_F64) {
+      const double2 x = a.X[in_row(a, p)];
+      const double2 dg = a.diag[t.d0 + arow];
+      cmac(sr, si, dg.x, dg.y, x);
+    }
+    if (a.ph) {
+      cscale(sr, si, a.ph[a.ph_idx ? a.ph_idx[p] : p]);
+    }
+    a.Y[a.out_pos ? a.out_pos[p] : p] = make_double2(sr, si);
+  }
 }
 
 // ---------------------------------------------------------------- FP64 reductions
@@ -1906,6 +2057,44 @@ static hipError_t launch_gemv_rb2(hipStream_t s, int fmt, int ntiles, const Pass
   return hipGetLastError();
 }
 
+// single-state orbit tiles: KS waves, RB row blocks per tile (ks < 0: two), M the layer's
+// largest group rounded up to an instantiated size
+template <int KS, int RB>
+static hipError_t launch_gemv_orbit_m(hipStream_t s, int fmt, int ntiles, const PassArgs& a) {
+  const int gm = a.orbit_max;
+#define LSX_ORBIT_M(M_)                                                                          \
+  if (gm <= M_) {                                                                                \
+    if (fmt == PF_F64)                                                                           \
+      hipLaunchKernelGGL((k_gemv_orbit<KS, PF_F64, RB, M_>), dim3(ntiles), dim3(64 * KS), 0, s, a); \
+    else if (fmt == PF_F32)                                                                      \
+      hipLaunchKernelGGL((k_gemv_orbit<KS, PF_F32, RB, M_>), dim3(ntiles), dim3(64 * KS), 0, s, a); \
+    else if constexpr (RB == 1)                                                                  \
+      hipLaunchKernelGGL((k_gemv_orbit<KS, PF_BF16X3, 1, M_>), dim3(ntiles), dim3(64 * KS), 0, s, a); \
+    else                                                                                         \
+      return hipErrorInvalidValue;                                                               \
+    return hipGetLastError();                                                                    \
+  }
+  LSX_ORBIT_M(2)
+  LSX_ORBIT_M(4)
+  LSX_ORBIT_M(6)
+  LSX_ORBIT_M(8)
+#undef LSX_ORBIT_M
+  return hipErrorInvalidValue;
+}
+
+static hipError_t launch_gemv_orbit(hipStream_t s, int fmt, int ntiles, int ksplit, const PassArgs& a) {
+  if (!a.orbit || a.orbit_max < 1 || a.orbit_max > kOrbitMax || a.wt || a.tcount) return hipErrorInvalidValue;
+  switch (ksplit) {
+    case 1: return launch_gemv_orbit_m<1, 1>(s, fmt, ntiles, a);
+    case 2: return launch_gemv_orbit_m<2, 1>(s, fmt, ntiles, a);
+    case 4: return launch_gemv_orbit_m<4, 1>(s, fmt, ntiles, a);
+    case -1: return launch_gemv_orbit_m<1, 2>(s, fmt, ntiles, a);
+    case -2: return launch_gemv_orbit_m<2, 2>(s, fmt, ntiles, a);
+    case -4: return launch_gemv_orbit_m<4, 2>(s, fmt, ntiles, a);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 // batched: tile.f is a system index into a.batch and every system has its own W; the
 // caller passes gather = whether the systems' in_pos tables are set (uniform per pass)
 hipError_t launch_pass(hipStream_t s, int fmt, int W, int ntiles, int nb, int ksplit, const PassArgs& a,
@@ -1914,6 +2103,7 @@ hipError_t launch_pass(hipStream_t s, int fmt, int W, int ntiles, int nb, int ks
   const bool gather = a.in_pos != nullptr;
   if (W == 1) {
     if (batched) return launch_gemv<4, true>(s, fmt, ntiles, a);
+    if (nb == kOrbitNB) return launch_gemv_orbit(s, fmt, ntiles, ksplit, a);
     if (ksplit < 0) {  // tiles of two row blocks, -ksplit waves
       if (fmt == PF_BF16X3) return hipErrorInvalidValue;
       switch (-ksplit) {
