@@ -1450,15 +1450,12 @@ __device__ __forceinline__ void cscale(double& sr, double& si, double2 h) {
   si = __builtin_fma(h.x, si, h.y * sr);
   sr = zr;
 }
-// HBM-bound GEMV: each propagator entry is read once per pass.  Lane (li, lk) of chunk
-// (rb, k) multiplies entry (16rb+li, col) by x[col]; the four k-lanes and the KS waves
-// are summed in fixed order.  Mixed formats: E entries (rounded to their storage
-// precision) times the FP64 state, FP64 accumulation, plus the FP64 diagonal term.
-// FP64 / FP32 tiles may cover RB = 2 consecutive row blocks (tile rb counts pairs): each
-// state load then serves two propagator loads, which halves the state loads per entry.
-template <int KS, int FMT, bool BATCH, int RB = 1>
+// Single-state GEMV, one 16-row block per tile: each propagator entry is read once per pass.
+// Lane (li, lk) of chunk (rb, k) multiplies entry (16rb+li, col) by x[col]; the four k-lanes
+// and the KS waves are summed in fixed order.  Mixed formats: E entries (rounded to their
+// storage precision) times the FP64 state, FP64 accumulation, plus the FP64 diagonal term.
+template <int KS, int FMT, bool BATCH>
 __device__ __forceinline__ void k_gemv_tile(const PassArgs& a0, int ti, double* red) {
-  static_assert(RB == 1 || FMT != PF_BF16X3, "BF16x3 single-state tiles cover one row block");
   const TileDesc t = a0.tiles[ti];
   if (t.f < 0) return;
   const PassArgs a = BATCH ? a0.batch[t.f] : a0;
@@ -1466,13 +1463,10 @@ __device__ __forceinline__ void k_gemv_tile(const PassArgs& a0, int ti, double* 
   const int lane = threadIdx.x & 63, kw = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int li = lane & 15, lk = lane >> 4;
   const char* Pb = reinterpret_cast<const char*>(a.P) + t.poff;
-  double yr[RB], yi[RB];
-#pragma unroll
-  for (int j = 0; j < RB; ++j) yr[j] = yi[j] = 0.0;
+  double yr = 0.0, yi = 0.0;
   if constexpr (FMT == PF_BF16X3) {
-    const int rb = t.rb;
     const int nkc = ((L + 31) & ~31) >> 5;
-    const v8u16* P = reinterpret_cast<const v8u16*>(Pb) + (int64_t)rb * nkc * 6 * 64 + lane;
+    const v8u16* P = reinterpret_cast<const v8u16*>(Pb) + (int64_t)t.rb * nkc * 6 * 64 + lane;
     int klo, khi;
     tile_band(t, 32 * nkc, 32, klo, khi);
     for (int kc = klo + kw; kc < khi; kc += KS) {
@@ -1485,84 +1479,62 @@ __device__ __forceinline__ void k_gemv_tile(const PassArgs& a0, int ti, double* 
           const double2 x = a.X[in_row(a, r0 + k)];
           const double er = (double)(bf2f(r0v[e]) + bf2f(r1v[e]) + bf2f(r2v[e]));
           const double ei = (double)(bf2f(i0v[e]) + bf2f(i1v[e]) + bf2f(i2v[e]));
-          cmac(yr[0], yi[0], er, ei, x);
+          cmac(yr, yi, er, ei, x);
         }
       }
     }
   } else {
     // Groups of G k-steps: all loads of a group are issued before its products, with the
     // state operand of positions past the fibre read from the zero buffer (their propagator
-    // entries are zero padding) and a missing second row block's entries from the zero buffer
-    // too, so the loads stay branch-free; the products are summed in k-step order as one at a
-    // time.
+    // entries are zero padding), so the loads stay branch-free; the products are summed in
+    // k-step order as one at a time.
     using PT = typename std::conditional<FMT == PF_F64, double2, float2>::type;
     constexpr int G = 8;
     const int nks = ((L + 15) & ~15) >> 2;
-    const int nrb = (L + 15) >> 4;
-    const PT* zp = reinterpret_cast<const PT*>(a.zero);
     const double2* zx = reinterpret_cast<const double2*>(a.zero);
-    // a tile's first row block always exists; the second (RB = 2) may lie past the fibre
-    const PT* Pj[RB];
-#pragma unroll
-    for (int j = 0; j < RB; ++j) {
-      const int rbj = t.rb * RB + j;
-      Pj[j] = (j == 0 || rbj < nrb) ? reinterpret_cast<const PT*>(Pb) + (int64_t)rbj * nks * 64 + lane : nullptr;
-    }
+    const PT* P = reinterpret_cast<const PT*>(Pb) + (int64_t)t.rb * nks * 64 + lane;
     int klo, khi;
     tile_band(t, 4 * nks, 4, klo, khi);
     int ks = klo + kw;
     for (; ks + (G - 1) * KS < khi; ks += G * KS) {
-      PT p[RB][G];
+      PT p[G];
       double2 x[G];
 #pragma unroll
       for (int g = 0; g < G; ++g) {
         const int kk = ks + g * KS, k = 4 * kk + lk;
         const bool ok = k < L;
-#pragma unroll
-        for (int j = 0; j < RB; ++j) p[j][g] = *((j == 0 || Pj[j]) ? Pj[j] + (int64_t)kk * 64 : zp);
+        p[g] = P[(int64_t)kk * 64];
         x[g] = *(ok ? a.X + in_row(a, r0 + (ok ? k : 0)) : zx);
       }
 #pragma unroll
-      for (int g = 0; g < G; ++g)
-#pragma unroll
-        for (int j = 0; j < RB; ++j) {
-          const double pr = p[j][g].x, pi = p[j][g].y;
-          cmac(yr[j], yi[j], pr, pi, x[g]);
-        }
+      for (int g = 0; g < G; ++g) cmac(yr, yi, p[g].x, p[g].y, x[g]);
     }
     for (; ks < khi; ks += KS) {
       const int k = 4 * ks + lk;
       const bool ok = k < L;
       const double2 x = *(ok ? a.X + in_row(a, r0 + (ok ? k : 0)) : zx);
-#pragma unroll
-      for (int j = 0; j < RB; ++j) {
-        const PT pe = *((j == 0 || Pj[j]) ? Pj[j] + (int64_t)ks * 64 : zp);
-        const double pr = pe.x, pi = pe.y;
-        cmac(yr[j], yi[j], pr, pi, x);
-      }
+      const PT pe = P[(int64_t)ks * 64];
+      cmac(yr, yi, pe.x, pe.y, x);
     }
   }
   // sum the four k-lanes of each row (lanes li, li+16, li+32, li+48)
-#pragma unroll
-  for (int j = 0; j < RB; ++j) {
-    yr[j] += __shfl_xor(yr[j], 16);
-    yi[j] += __shfl_xor(yi[j], 16);
-    yr[j] += __shfl_xor(yr[j], 32);
-    yi[j] += __shfl_xor(yi[j], 32);
-    if (lk == 0) {
-      red[((kw * RB + j) * 2 + 0) * 16 + li] = yr[j];
-      red[((kw * RB + j) * 2 + 1) * 16 + li] = yi[j];
-    }
+  yr += __shfl_xor(yr, 16);
+  yi += __shfl_xor(yi, 16);
+  yr += __shfl_xor(yr, 32);
+  yi += __shfl_xor(yi, 32);
+  if (lk == 0) {
+    red[(kw * 2 + 0) * 16 + li] = yr;
+    red[(kw * 2 + 1) * 16 + li] = yi;
   }
   __syncthreads();
-  if (threadIdx.x < 16 * RB) {
-    const int j = threadIdx.x >> 4, lr = threadIdx.x & 15;
-    const int arow = 16 * (t.rb * RB + j) + lr;
+  if (threadIdx.x < 16) {
+    const int lr = threadIdx.x;
+    const int arow = 16 * t.rb + lr;
     if (arow < L) {
       double sr = 0.0, si = 0.0;
       for (int w = 0; w < KS; ++w) {
-        sr += red[((w * RB + j) * 2 + 0) * 16 + lr];
-        si += red[((w * RB + j) * 2 + 1) * 16 + lr];
+        sr += red[(w * 2 + 0) * 16 + lr];
+        si += red[(w * 2 + 1) * 16 + lr];
       }
       const int p = r0 + arow;
       if (FMT != PF_F64 || a.wt) {
@@ -1577,19 +1549,17 @@ __device__ __forceinline__ void k_gemv_tile(const PassArgs& a0, int ti, double* 
           si = x.y + g * (si - x.y);
         }
       }
-      if (a.ph) {
-        cscale(sr, si, a.ph[a.ph_idx ? a.ph_idx[p] : p]);
-      }
+      if (a.ph) cscale(sr, si, a.ph[a.ph_idx ? a.ph_idx[p] : p]);
       a.Y[a.out_pos ? a.out_pos[p] : p] = make_double2(sr, si);
     }
   }
 }
 
-template <int KS, int FMT, bool BATCH, int RB = 1>
+template <int KS, int FMT, bool BATCH>
 __global__ __launch_bounds__(64 * KS) void k_gemv(PassArgs a0) {
-  __shared__ double red[2 * KS * 16 * RB];
+  __shared__ double red[2 * KS * 16];
   if (a0.tcount && (int)blockIdx.x >= *a0.tcount) return;
-  k_gemv_tile<KS, FMT, BATCH, RB>(a0, blockIdx.x, red);
+  k_gemv_tile<KS, FMT, BATCH>(a0, blockIdx.x, red);
 }
 
 template <int KS, int FMT>
@@ -1600,15 +1570,14 @@ __global__ __launch_bounds__(64 * KS) void k_gemv_persist(PassArgs a0) {
 
 // ---------------------------------------------------------------- single-state orbit pass (W = 1)
 // Fibres with one stored propagator (point-symmetry orbits, kappa = 1 translation classes)
-// are multiplied together: a tile covers RB row blocks of the shared propagator for the
+// are multiplied together: a tile covers a 16-row block of the shared propagator for the
 // states of up to M fibres of a group (PassArgs::orbit), so every propagator chunk is loaded
 // once for the whole group instead of once per fibre.  Each fibre's products are summed in
-// the order k_gemv_tile sums them for the same KS and RB (k-steps in order per lane, then the
-// four k-lanes, then the waves), so the two kernels give identical results.
-template <int KS, int FMT, int RB, int M>
+// the order k_gemv_tile sums them for the same KS (k-steps in order per lane, then the four
+// k-lanes, then the waves), so the two kernels give identical results.
+template <int KS, int FMT, int M>
 __global__ __launch_bounds__(64 * KS) void k_gemv_orbit(PassArgs a) {
-  static_assert(RB == 1 || FMT != PF_BF16X3, "BF16x3 single-state tiles cover one row block");
-  __shared__ double red[KS * RB * M * 2 * 16];
+  __shared__ double red[KS * M * 2 * 16];
   const TileDesc t = a.tiles[blockIdx.x];
   if (t.f < 0) return;
   const int32_t* og = a.orbit + (int64_t)t.f * kOrbitStride;
@@ -1620,11 +1589,9 @@ __global__ __launch_bounds__(64 * KS) void k_gemv_orbit(PassArgs a) {
   const int lane = threadIdx.x & 63, kw = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int li = lane & 15, lk = lane >> 4;
   const char* Pb = reinterpret_cast<const char*>(a.P) + t.poff;
-  double yr[RB][M], yi[RB][M];
+  double yr[M], yi[M];
 #pragma unroll
-  for (int j = 0; j < RB; ++j)
-#pragma unroll
-    for (int m = 0; m < M; ++m) yr[j][m] = yi[j][m] = 0.0;
+  for (int m = 0; m < M; ++m) yr[m] = yi[m] = 0.0;
   if constexpr (FMT == PF_BF16X3) {
     const int nkc = ((L + 31) & ~31) >> 5;
     const v8u16* P = reinterpret_cast<const v8u16*>(Pb) + (int64_t)t.rb * nkc * 6 * 64 + lane;
@@ -1642,51 +1609,37 @@ __global__ __launch_bounds__(64 * KS) void k_gemv_orbit(PassArgs a) {
 #pragma unroll
           for (int m = 0; m < M; ++m) {
             const double2 x = a.X[in_row(a, r0[m] + k)];
-            cmac(yr[0][m], yi[0][m], er, ei, x);
+            cmac(yr[m], yi[m], er, ei, x);
           }
         }
       }
     }
   } else {
     // groups of G k-steps, every load of a group issued before its products (state operands
-    // past the fibre and a missing second row block read the zero buffer, as in k_gemv_tile)
+    // past the fibre read the zero buffer, as in k_gemv_tile)
     using PT = typename std::conditional<FMT == PF_F64, double2, float2>::type;
     constexpr int G = M <= 2 ? 4 : (M <= 4 ? 2 : 1);
     const int nks = ((L + 15) & ~15) >> 2;
-    const int nrb = (L + 15) >> 4;
-    const PT* zp = reinterpret_cast<const PT*>(a.zero);
     const double2* zx = reinterpret_cast<const double2*>(a.zero);
-    const PT* Pj[RB];
-#pragma unroll
-    for (int j = 0; j < RB; ++j) {
-      const int rbj = t.rb * RB + j;
-      Pj[j] = (j == 0 || rbj < nrb) ? reinterpret_cast<const PT*>(Pb) + (int64_t)rbj * nks * 64 + lane : nullptr;
-    }
+    const PT* P = reinterpret_cast<const PT*>(Pb) + (int64_t)t.rb * nks * 64 + lane;
     int klo, khi;
     tile_band(t, 4 * nks, 4, klo, khi);
     int ks = klo + kw;
     for (; ks + (G - 1) * KS < khi; ks += G * KS) {
-      PT p[RB][G];
+      PT p[G];
       double2 x[G][M];
 #pragma unroll
       for (int g = 0; g < G; ++g) {
         const int kk = ks + g * KS, k = 4 * kk + lk;
         const bool ok = k < L;
-#pragma unroll
-        for (int j = 0; j < RB; ++j) p[j][g] = *((j == 0 || Pj[j]) ? Pj[j] + (int64_t)kk * 64 : zp);
+        p[g] = P[(int64_t)kk * 64];
 #pragma unroll
         for (int m = 0; m < M; ++m) x[g][m] = *(ok ? a.X + in_row(a, r0[m] + (ok ? k : 0)) : zx);
       }
 #pragma unroll
       for (int g = 0; g < G; ++g)
 #pragma unroll
-        for (int j = 0; j < RB; ++j) {
-          const double pr = p[j][g].x, pi = p[j][g].y;
-#pragma unroll
-          for (int m = 0; m < M; ++m) {
-            cmac(yr[j][m], yi[j][m], pr, pi, x[g][m]);
-          }
-        }
+        for (int m = 0; m < M; ++m) cmac(yr[m], yi[m], p[g].x, p[g].y, x[g][m]);
     }
     for (; ks < khi; ks += KS) {
       const int k = 4 * ks + lk;
@@ -1694,41 +1647,33 @@ __global__ __launch_bounds__(64 * KS) void k_gemv_orbit(PassArgs a) {
       double2 x[M];
 #pragma unroll
       for (int m = 0; m < M; ++m) x[m] = *(ok ? a.X + in_row(a, r0[m] + (ok ? k : 0)) : zx);
+      const PT pe = P[(int64_t)ks * 64];
 #pragma unroll
-      for (int j = 0; j < RB; ++j) {
-        const PT pe = *((j == 0 || Pj[j]) ? Pj[j] + (int64_t)ks * 64 : zp);
-        const double pr = pe.x, pi = pe.y;
-#pragma unroll
-        for (int m = 0; m < M; ++m) {
-          cmac(yr[j][m], yi[j][m], pr, pi, x[m]);
-        }
-      }
+      for (int m = 0; m < M; ++m) cmac(yr[m], yi[m], pe.x, pe.y, x[m]);
     }
   }
   // sum the four k-lanes of each row, then the waves in order
 #pragma unroll
-  for (int j = 0; j < RB; ++j)
-#pragma unroll
-    for (int m = 0; m < M; ++m) {
-      double vr = yr[j][m], vi = yi[j][m];
-      vr += __shfl_xor(vr, 16);
-      vi += __shfl_xor(vi, 16);
-      vr += __shfl_xor(vr, 32);
-      vi += __shfl_xor(vi, 32);
-      if (lk == 0) {
-        red[(((kw * RB + j) * M + m) * 2 + 0) * 16 + li] = vr;
-        red[(((kw * RB + j) * M + m) * 2 + 1) * 16 + li] = vi;
-      }
+  for (int m = 0; m < M; ++m) {
+    double vr = yr[m], vi = yi[m];
+    vr += __shfl_xor(vr, 16);
+    vi += __shfl_xor(vi, 16);
+    vr += __shfl_xor(vr, 32);
+    vi += __shfl_xor(vi, 32);
+    if (lk == 0) {
+      red[((kw * M + m) * 2 + 0) * 16 + li] = vr;
+      red[((kw * M + m) * 2 + 1) * 16 + li] = vi;
     }
+  }
   __syncthreads();
-  for (int idx = threadIdx.x; idx < 16 * RB * M; idx += 64 * KS) {
-    const int lr = idx & 15, m = (idx >> 4) % M, j = idx / (16 * M);
-    const int arow = 16 * (t.rb * RB + j) + lr;
+  for (int idx = threadIdx.x; idx < 16 * M; idx += 64 * KS) {
+    const int lr = idx & 15, m = idx >> 4;
+    const int arow = 16 * t.rb + lr;
     if (m >= nm || arow >= L) continue;
     double sr = 0.0, si = 0.0;
     for (int w = 0; w < KS; ++w) {
-      sr += red[(((w * RB + j) * M + m) * 2 + 0) * 16 + lr];
-      si += red[(((w * RB + j) * M + m) * 2 + 1) * 16 + lr];
+      sr += red[((w * M + m) * 2 + 0) * 16 + lr];
+      si += red[((w * M + m) * 2 + 1) * 16 + lr];
     }
     const int p = og[1 + m] + arow;
     if (FMT != PF_F64) {
@@ -1736,9 +1681,122 @@ __global__ __launch_bounds__(64 * KS) void k_gemv_orbit(PassArgs a) {
       const double2 dg = a.diag[t.d0 + arow];
       cmac(sr, si, dg.x, dg.y, x);
     }
-    if (a.ph) {
-      cscale(sr, si, a.ph[a.ph_idx ? a.ph_idx[p] : p]);
+    if (a.ph) cscale(sr, si, a.ph[a.ph_idx ? a.ph_idx[p] : p]);
+    a.Y[a.out_pos ? a.out_pos[p] : p] = make_double2(sr, si);
+  }
+}
+
+// ---------------------------------------------------------------- single-state passes, one row per lane
+// A wave covers four 16-row blocks of a propagator (lane l: block l / 16 of the tile, row
+// l % 16) and reads, for each k-step, the four columns of its row from the four lanes' slots
+// of the stored chunk, so the state operand of a k-step is the same for the whole wave: it is
+// read once per wave through the scalar cache instead of once per lane.  ORB: the tile
+// multiplies up to M fibres of a group with one propagator (PassArgs::orbit), else the tile's
+// own fibre.  Per fibre and row the products are summed in column order, then the KS waves in
+// order, so orbit and per-fibre tiles give identical results.  The k-steps run over the union
+// of the four blocks' bands, and each block's lanes take zeros outside their own block's band.
+template <int KS, int FMT, int M, bool ORB, bool GATHER>
+__global__ __launch_bounds__(64 * KS) void k_gemv_rows(PassArgs a) {
+  static_assert(FMT != PF_BF16X3, "FP64 / FP32 storage");
+  static_assert(ORB || M == 1, "a per-fibre tile has one fibre");
+  using PT = typename std::conditional<FMT == PF_F64, double2, float2>::type;
+  __shared__ double red[KS * M * 2 * 64];
+  const TileDesc t = a.tiles[blockIdx.x];
+  if (t.f < 0) return;
+  int nm = 1, r0[M];
+  if constexpr (ORB) {
+    const int32_t* og = a.orbit + (int64_t)t.f * kOrbitStride;
+    nm = og[0];
+#pragma unroll
+    for (int m = 0; m < M; ++m) r0[m] = og[1 + m];
+  } else {
+    r0[0] = t.r0;
+  }
+  const int L = t.L;
+  const int lane = threadIdx.x & 63, kw = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int li = lane & 15, q = lane >> 4;
+  const int nks = ((L + 15) & ~15) >> 2, nrb = (L + 15) >> 4;
+  const int rbq = 4 * t.rb + q;
+  const bool rowok = rbq < nrb;
+  const PT* zp = reinterpret_cast<const PT*>(a.zero);
+  const PT* Pq = reinterpret_cast<const PT*>(reinterpret_cast<const char*>(a.P) + t.poff) +
+                 (int64_t)(rowok ? rbq : 0) * nks * 64 + li;
+  int klo, khi;
+  tile_band(t, 4 * nks, 4, klo, khi);
+  // each row block's own band (fibre positions): its lanes read the zero buffer outside it
+  int qlo = 0, qhi = kBandEnd;
+  if (a.rb_band && t.bb >= 0 && rowok) {
+    const int2 b = reinterpret_cast<const int2*>(a.rb_band)[t.bb + rbq];
+    qlo = b.x;
+    qhi = b.y;
+  }
+  auto src = [&](int kk, int c) { return (rowok && 4 * kk >= qlo && 4 * kk < qhi) ? Pq + (int64_t)kk * 64 + 16 * c : zp; };
+  double yr[M], yi[M];
+#pragma unroll
+  for (int m = 0; m < M; ++m) yr[m] = yi[m] = 0.0;
+  constexpr int G = 2;
+  // The state operand of a k-step: four consecutive rows of every fibre, one 64-byte read per
+  // fibre where its rows are contiguous (no gather, k-step inside the fibre); columns past the
+  // fibre multiply zero padding and read the fibre's last row instead.
+  struct X4 {
+    double2 v[4];
+  };
+  auto step = [&](const PT (&e)[4], int kk) {
+    if (!GATHER && 4 * kk + 3 < L) {
+#pragma unroll
+      for (int m = 0; m < M; ++m) {
+        const X4 x = *reinterpret_cast<const X4*>(a.X + r0[m] + 4 * kk);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) cmac(yr[m], yi[m], e[c].x, e[c].y, x.v[c]);
+      }
+    } else {
+#pragma unroll
+      for (int m = 0; m < M; ++m)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const double2 x = a.X[xrow<GATHER>(a, r0[m] + min(4 * kk + c, L - 1))];
+          cmac(yr[m], yi[m], e[c].x, e[c].y, x);
+        }
     }
+  };
+  int kk = klo + kw;
+  for (; kk + (G - 1) * KS < khi; kk += G * KS) {
+    PT e[G][4];
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) e[g][c] = *src(kk + g * KS, c);
+#pragma unroll
+    for (int g = 0; g < G; ++g) step(e[g], kk + g * KS);
+  }
+  for (; kk < khi; kk += KS) {
+    PT e[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) e[c] = *src(kk, c);
+    step(e, kk);
+  }
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    red[((kw * M + m) * 2 + 0) * 64 + lane] = yr[m];
+    red[((kw * M + m) * 2 + 1) * 64 + lane] = yi[m];
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < 64 * M; idx += 64 * KS) {
+    const int ln = idx & 63, m = idx >> 6;
+    const int arow = 16 * (4 * t.rb + (ln >> 4)) + (ln & 15);
+    if (m >= nm || arow >= L) continue;
+    double sr = 0.0, si = 0.0;
+    for (int w = 0; w < KS; ++w) {
+      sr += red[((w * M + m) * 2 + 0) * 64 + ln];
+      si += red[((w * M + m) * 2 + 1) * 64 + ln];
+    }
+    const int p = (ORB ? a.orbit[(int64_t)t.f * kOrbitStride + 1 + m] : t.r0) + arow;
+    if (FMT != PF_F64) {
+      const double2 x = a.X[in_row(a, p)];
+      const double2 dg = a.diag[t.d0 + arow];
+      cmac(sr, si, dg.x, dg.y, x);
+    }
+    if (a.ph) cscale(sr, si, a.ph[a.ph_idx ? a.ph_idx[p] : p]);
     a.Y[a.out_pos ? a.out_pos[p] : p] = make_double2(sr, si);
   }
 }
@@ -2045,34 +2103,20 @@ static hipError_t launch_gemv(hipStream_t s, int fmt, int ntiles, const PassArgs
   return hipGetLastError();
 }
 
-// single-state FP64 / FP32 tiles of two row blocks (tile rb counts pairs)
+// single-state orbit tiles of one row block: KS waves, M the layer's largest group rounded up
+// to an instantiated size
 template <int KS>
-static hipError_t launch_gemv_rb2(hipStream_t s, int fmt, int ntiles, const PassArgs& a) {
-  if (fmt == PF_F64)
-    hipLaunchKernelGGL((k_gemv<KS, PF_F64, false, 2>), dim3(ntiles), dim3(64 * KS), 0, s, a);
-  else if (fmt == PF_F32)
-    hipLaunchKernelGGL((k_gemv<KS, PF_F32, false, 2>), dim3(ntiles), dim3(64 * KS), 0, s, a);
-  else
-    return hipErrorInvalidValue;
-  return hipGetLastError();
-}
-
-// single-state orbit tiles: KS waves, RB row blocks per tile (ks < 0: two), M the layer's
-// largest group rounded up to an instantiated size
-template <int KS, int RB>
 static hipError_t launch_gemv_orbit_m(hipStream_t s, int fmt, int ntiles, const PassArgs& a) {
   const int gm = a.orbit_max;
-#define LSX_ORBIT_M(M_)                                                                          \
-  if (gm <= M_) {                                                                                \
-    if (fmt == PF_F64)                                                                           \
-      hipLaunchKernelGGL((k_gemv_orbit<KS, PF_F64, RB, M_>), dim3(ntiles), dim3(64 * KS), 0, s, a); \
-    else if (fmt == PF_F32)                                                                      \
-      hipLaunchKernelGGL((k_gemv_orbit<KS, PF_F32, RB, M_>), dim3(ntiles), dim3(64 * KS), 0, s, a); \
-    else if constexpr (RB == 1)                                                                  \
-      hipLaunchKernelGGL((k_gemv_orbit<KS, PF_BF16X3, 1, M_>), dim3(ntiles), dim3(64 * KS), 0, s, a); \
-    else                                                                                         \
-      return hipErrorInvalidValue;                                                               \
-    return hipGetLastError();                                                                    \
+#define LSX_ORBIT_M(M_)                                                                           \
+  if (gm <= M_) {                                                                                 \
+    if (fmt == PF_F64)                                                                            \
+      hipLaunchKernelGGL((k_gemv_orbit<KS, PF_F64, M_>), dim3(ntiles), dim3(64 * KS), 0, s, a);    \
+    else if (fmt == PF_F32)                                                                       \
+      hipLaunchKernelGGL((k_gemv_orbit<KS, PF_F32, M_>), dim3(ntiles), dim3(64 * KS), 0, s, a);    \
+    else                                                                                          \
+      hipLaunchKernelGGL((k_gemv_orbit<KS, PF_BF16X3, M_>), dim3(ntiles), dim3(64 * KS), 0, s, a); \
+    return hipGetLastError();                                                                     \
   }
   LSX_ORBIT_M(2)
   LSX_ORBIT_M(4)
@@ -2082,15 +2126,44 @@ static hipError_t launch_gemv_orbit_m(hipStream_t s, int fmt, int ntiles, const 
   return hipErrorInvalidValue;
 }
 
+// single-state tiles of four row blocks, one row per lane (FP64 / FP32 storage): per-fibre
+// tiles (orbit = false) or orbit tiles with M the layer's largest group rounded up
+template <int KS, int M, bool ORB>
+static hipError_t launch_gemv_rows_m(hipStream_t s, bool f64, int ntiles, const PassArgs& a) {
+  const dim3 grid(ntiles), block(64 * KS);
+  if (a.in_pos) {
+    if (f64)
+      hipLaunchKernelGGL((k_gemv_rows<KS, PF_F64, M, ORB, true>), grid, block, 0, s, a);
+    else
+      hipLaunchKernelGGL((k_gemv_rows<KS, PF_F32, M, ORB, true>), grid, block, 0, s, a);
+  } else {
+    if (f64)
+      hipLaunchKernelGGL((k_gemv_rows<KS, PF_F64, M, ORB, false>), grid, block, 0, s, a);
+    else
+      hipLaunchKernelGGL((k_gemv_rows<KS, PF_F32, M, ORB, false>), grid, block, 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+template <int KS>
+static hipError_t launch_gemv_rows(hipStream_t s, int fmt, int ntiles, bool orbit, const PassArgs& a) {
+  if (fmt == PF_BF16X3) return hipErrorInvalidValue;
+  const bool f64 = fmt == PF_F64;
+  if (!orbit) return launch_gemv_rows_m<KS, 1, false>(s, f64, ntiles, a);
+  if (!a.orbit || a.orbit_max < 1 || a.orbit_max > kOrbitMax || a.wt || a.tcount) return hipErrorInvalidValue;
+  const int gm = a.orbit_max;
+  if (gm <= 2) return launch_gemv_rows_m<KS, 2, true>(s, f64, ntiles, a);
+  if (gm <= 4) return launch_gemv_rows_m<KS, 4, true>(s, f64, ntiles, a);
+  if (gm <= 6) return launch_gemv_rows_m<KS, 6, true>(s, f64, ntiles, a);
+  return launch_gemv_rows_m<KS, 8, true>(s, f64, ntiles, a);
+}
+
 static hipError_t launch_gemv_orbit(hipStream_t s, int fmt, int ntiles, int ksplit, const PassArgs& a) {
   if (!a.orbit || a.orbit_max < 1 || a.orbit_max > kOrbitMax || a.wt || a.tcount) return hipErrorInvalidValue;
   switch (ksplit) {
-    case 1: return launch_gemv_orbit_m<1, 1>(s, fmt, ntiles, a);
-    case 2: return launch_gemv_orbit_m<2, 1>(s, fmt, ntiles, a);
-    case 4: return launch_gemv_orbit_m<4, 1>(s, fmt, ntiles, a);
-    case -1: return launch_gemv_orbit_m<1, 2>(s, fmt, ntiles, a);
-    case -2: return launch_gemv_orbit_m<2, 2>(s, fmt, ntiles, a);
-    case -4: return launch_gemv_orbit_m<4, 2>(s, fmt, ntiles, a);
+    case 1: return launch_gemv_orbit_m<1>(s, fmt, ntiles, a);
+    case 2: return launch_gemv_orbit_m<2>(s, fmt, ntiles, a);
+    case 4: return launch_gemv_orbit_m<4>(s, fmt, ntiles, a);
     default: return hipErrorInvalidValue;
   }
 }
@@ -2103,15 +2176,17 @@ hipError_t launch_pass(hipStream_t s, int fmt, int W, int ntiles, int nb, int ks
   const bool gather = a.in_pos != nullptr;
   if (W == 1) {
     if (batched) return launch_gemv<4, true>(s, fmt, ntiles, a);
-    if (nb == kOrbitNB) return launch_gemv_orbit(s, fmt, ntiles, ksplit, a);
-    if (ksplit < 0) {  // tiles of two row blocks, -ksplit waves
-      if (fmt == PF_BF16X3) return hipErrorInvalidValue;
+    if (ksplit < 0) {  // tiles of four row blocks, one row per lane, -ksplit waves
+      const bool orbit = nb == kOrbitNB;
       switch (-ksplit) {
-        case 1: return launch_gemv_rb2<1>(s, fmt, ntiles, a);
-        case 2: return launch_gemv_rb2<2>(s, fmt, ntiles, a);
-        default: return launch_gemv_rb2<4>(s, fmt, ntiles, a);
+        case 1: return launch_gemv_rows<1>(s, fmt, ntiles, orbit, a);
+        case 2: return launch_gemv_rows<2>(s, fmt, ntiles, orbit, a);
+        case 4: return launch_gemv_rows<4>(s, fmt, ntiles, orbit, a);
+        case 8: return launch_gemv_rows<8>(s, fmt, ntiles, orbit, a);
+        default: return hipErrorInvalidValue;
       }
     }
+    if (nb == kOrbitNB) return launch_gemv_orbit(s, fmt, ntiles, ksplit, a);
     switch (ksplit) {
       case 1: return launch_gemv<1, false>(s, fmt, ntiles, a);
       case 2: return launch_gemv<2, false>(s, fmt, ntiles, a);

@@ -61,28 +61,30 @@ def test_rowsplit_shapes(prec, nb, ms, which, monkeypatch):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mix_fp32"])
-@pytest.mark.parametrize("ks", [-1, -2, -4])
+@pytest.mark.parametrize("ks", [-1, -2, -4, -8])
 @pytest.mark.parametrize("which", ["chain", "twisted"])
-def test_single_state_pair_tiles(prec, ks, which, monkeypatch):
-    """W = 1 tiles of two row blocks (ks < 0): single passes of both layers against the oracle
-    and Strang trajectories (kappa 0 and 0.5, the latter with the phase fused into the pass)
-    against the one-row-block tiles of the same precision."""
+def test_single_state_row_lane_tiles(prec, ks, which, monkeypatch):
+    """W = 1 tiles of four row blocks with one output row per lane (ks < 0), whose state operand
+    is read once per wave: single passes of both layers against the oracle and Strang
+    trajectories (kappa 0 and 0.5, the latter with the phase fused into the pass) against the
+    one-row-block tiles of the same precision."""
     spec = wl.chain_system(2.0e4) if which == "chain" else wl.twisted_system(1500.0)
     S = lsx.System.from_spec(spec)
     O = splitting.Lifted.from_spec(spec)
     plan = splitting.SplitPlan(O, 0.0)
     tau = 1e-3
-    print(f"[case] single-state pair tiles {which} {prec} ks={ks}", flush=True)
+    print(f"[case] single-state row-per-lane tiles {which} {prec} ks={ks}", flush=True)
     P = lsx.Plan(S, tau, "strang", 0.0, prec)
     monkeypatch.setenv("LSX_NB", "1")
     monkeypatch.setenv("LSX_KS", str(ks))
     st = lsx.State(P, 1)
-    monkeypatch.setenv("LSX_KS", str(-ks))
+    kref = min(-ks, 4)  # the one-row-block tiles take up to four waves
+    monkeypatch.setenv("LSX_KS", str(kref))
     ref = lsx.State(P, 1)
     monkeypatch.delenv("LSX_NB")
     monkeypatch.delenv("LSX_KS")
     try:
-        assert st.tuning(1)[:2] == (1, ks) and ref.tuning(1)[:2] == (1, -ks)
+        assert st.tuning(1)[:2] == (1, ks) and ref.tuning(1)[:2] == (1, kref)
         c = wl.random_state(S.N, 1, seed=-ks)
         tol = 1e-12 if prec == "fp64" else 1e-7
         for layer, half, t in ((1, 0, tau), (1, 1, tau / 2), (2, 0, tau)):
@@ -93,17 +95,19 @@ def test_single_state_pair_tiles(prec, ks, which, monkeypatch):
         ref.upload(c)
         st.step(20)
         ref.step(20)
-        assert colrel(st.download(), ref.download()) < 1e-13
+        # the same FP64 products summed in another order (one running sum per row against four
+        # per row combined at the end): FP64 rounding of 40 passes over fibres of up to ~400
+        assert colrel(st.download(), ref.download()) < 1e-12
     finally:
         st.destroy()
         ref.destroy()
         P.destroy()
-    # a kinetic share: the phase fused into the pair tiles' epilogue
+    # a kinetic share: the phase fused into the row-per-lane tiles' epilogue
     P = lsx.Plan(S, tau, "strang", 0.5, prec)
     monkeypatch.setenv("LSX_NB", "1")
     monkeypatch.setenv("LSX_KS", str(ks))
     st = lsx.State(P, 1)
-    monkeypatch.setenv("LSX_KS", str(-ks))
+    monkeypatch.setenv("LSX_KS", str(kref))
     ref = lsx.State(P, 1)
     monkeypatch.delenv("LSX_NB")
     monkeypatch.delenv("LSX_KS")
@@ -113,7 +117,7 @@ def test_single_state_pair_tiles(prec, ks, which, monkeypatch):
         ref.upload(c)
         st.step(20)
         ref.step(20)
-        assert colrel(st.download(), ref.download()) < 1e-13
+        assert colrel(st.download(), ref.download()) < 1e-12
     finally:
         st.destroy()
         ref.destroy()
