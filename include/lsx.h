@@ -330,7 +330,7 @@ lsx_status lsx_state_device_ptr(const lsx_state* st, void** dev_ptr);
  * that share the state operand staged once per workgroup in LDS (each wave multiplies only its
  * own row block's band, see lsx_plan_band; FP32 needs -ks <= 4 nb, BF16x3 nb <= 2).  For W = 1
  * (matrix-vector passes) ks < 0 means 64 output rows, one per lane, with -ks waves splitting
- * the fibre length (FP64 and mixed FP32), and nb = 8 tiles that multiply the fibres sharing a
+ * the fibre length, and nb = 8 tiles that multiply the fibres sharing a
  * stored propagator together (lsx_state_set_tuning).  At creation every candidate shape is
  * timed on the state's own size
  * (LSX_AUTOTUNE=0 disables, LSX_NB / LSX_KS force a shape); pass_us is the measured
@@ -376,8 +376,7 @@ lsx_status lsx_state_store_mode(const lsx_state* st, int32_t* nontemporal, doubl
  * lsx_state_set_tuning: tile shape (nb, ks) and k-step groups in flight (`groups`, 0 for the
  *   library default) of `layer`'s passes; the tile list is rebuilt on the host and uploaded
  *   (synchronous).  Available shapes: W = 1: nb = 1 and ks in {1, 2, 4}, or {-1, -2, -4, -8}
- *   (tiles of 64 rows, one row per lane) except for LSX_MIX_BF16X3, groups = 0; nb = 8 with the
- *   same ks: orbit tiles, which multiply up to
+ *   (tiles of 64 rows, one row per lane), groups = 0; nb = 8 with the same ks: orbit tiles, which multiply up to
  *   eight fibres that share one stored propagator (lsx_plan_sharing) with one load of each
  *   propagator chunk and give the same result as nb = 1 with that ks (LSX_E_INVALID on a layer
  *   where no fibre shares).  W > 1: nb in {1, 2, 4} with 16 nb <= W rounded up to 16; ks in

@@ -1700,12 +1700,12 @@ static lsx_status choose_tiles(lsx_plan* pl, lsx_state* st) {
   const int fnb = env_int("LSX_NB", 0), fks = env_int("LSX_KS", 0);
   const bool tune_u = (pl->fmt == PF_F64 || pl->fmt == PF_F32) && std::getenv("LSX_PREFETCH") == nullptr;
   if (W == 1) {
-    // ks < 0: FP64 / FP32 tiles of four row blocks, one row per lane, -ks waves; nb = kOrbitNB: orbit tiles
+    // ks < 0: tiles of four row blocks, one row per lane, -ks waves; nb = kOrbitNB: orbit tiles
     // (layers whose fibres share propagators)
     for (int nb : {1, kOrbitNB})
       for (int k : {1, 2, 4, 8}) {
         if (k < 8) cands.push_back({nb, k, 0});
-        if (pl->fmt != PF_BF16X3) cands.push_back({nb, -k, 0});
+        cands.push_back({nb, -k, 0});
       }
   } else {
     for (int nb : {1, 2, 4})
@@ -1721,7 +1721,7 @@ static lsx_status choose_tiles(lsx_plan* pl, lsx_state* st) {
   }
   if (fnb > 0 || fks != 0) {
     const bool rowsplit = fks < 0 && ((W > 1 && rowsplit_shape(pl->fmt, fnb > 0 ? fnb : 1, -fks)) ||
-                                      (W == 1 && pl->fmt != PF_BF16X3 && (fks == -1 || fks == -2 || fks == -4 || fks == -8)));
+                                      (W == 1 && (fks == -1 || fks == -2 || fks == -4 || fks == -8)));
     const Shape f{(fnb == 1 || fnb == 2 || fnb == 4 || (W == 1 && fnb == kOrbitNB)) ? fnb : 1,
                   rowsplit ? fks : ((fks == 1 || fks == 2 || fks == 4) ? fks : 2), 0};
     cands.assign(1, f);
@@ -1944,7 +1944,7 @@ static bool shape_valid(int fmt, int W, int nb, int ks, int u) {
   if (W == 1) {
     if ((nb != 1 && nb != kOrbitNB) || u != 0) return false;
     if (ks == 1 || ks == 2 || ks == 4) return true;
-    return fmt != PF_BF16X3 && (ks == -1 || ks == -2 || ks == -4 || ks == -8);
+    return ks == -1 || ks == -2 || ks == -4 || ks == -8;
   }
   if (!(nb == 1 || nb == 2 || nb == 4) || 16 * nb > round_up(W, 16)) return false;
   if (ks == 1 || ks == 2 || ks == 4)

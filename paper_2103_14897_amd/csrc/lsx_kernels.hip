@@ -1688,18 +1688,17 @@ __global__ __launch_bounds__(64 * KS) void k_gemv_orbit(PassArgs a) {
 
 // ---------------------------------------------------------------- single-state passes, one row per lane
 // A wave covers four 16-row blocks of a propagator (lane l: block l / 16 of the tile, row
-// l % 16) and reads, for each k-step, the four columns of its row from the four lanes' slots
-// of the stored chunk, so the state operand of a k-step is the same for the whole wave: it is
-// read once per wave through the scalar cache instead of once per lane.  ORB: the tile
+// l % 16) and reads, for each k-step, all columns of its row from the lane slots of the
+// stored chunk (four slots of one column for FP64 / FP32, four slots of eight columns for
+// BF16x3), so the state operand of a k-step is the same for the whole wave: it is read once
+// per wave through the scalar cache instead of once per lane.  ORB: the tile
 // multiplies up to M fibres of a group with one propagator (PassArgs::orbit), else the tile's
 // own fibre.  Per fibre and row the products are summed in column order, then the KS waves in
 // order, so orbit and per-fibre tiles give identical results.  The k-steps run over the union
 // of the four blocks' bands, and each block's lanes take zeros outside their own block's band.
 template <int KS, int FMT, int M, bool ORB, bool GATHER>
 __global__ __launch_bounds__(64 * KS) void k_gemv_rows(PassArgs a) {
-  static_assert(FMT != PF_BF16X3, "FP64 / FP32 storage");
   static_assert(ORB || M == 1, "a per-fibre tile has one fibre");
-  using PT = typename std::conditional<FMT == PF_F64, double2, float2>::type;
   __shared__ double red[KS * M * 2 * 64];
   const TileDesc t = a.tiles[blockIdx.x];
   if (t.f < 0) return;
@@ -1715,14 +1714,10 @@ __global__ __launch_bounds__(64 * KS) void k_gemv_rows(PassArgs a) {
   const int L = t.L;
   const int lane = threadIdx.x & 63, kw = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int li = lane & 15, q = lane >> 4;
-  const int nks = ((L + 15) & ~15) >> 2, nrb = (L + 15) >> 4;
+  const int nrb = (L + 15) >> 4;
   const int rbq = 4 * t.rb + q;
   const bool rowok = rbq < nrb;
-  const PT* zp = reinterpret_cast<const PT*>(a.zero);
-  const PT* Pq = reinterpret_cast<const PT*>(reinterpret_cast<const char*>(a.P) + t.poff) +
-                 (int64_t)(rowok ? rbq : 0) * nks * 64 + li;
-  int klo, khi;
-  tile_band(t, 4 * nks, 4, klo, khi);
+  const char* Pb = reinterpret_cast<const char*>(a.P) + t.poff;
   // each row block's own band (fibre positions): its lanes read the zero buffer outside it
   int qlo = 0, qhi = kBandEnd;
   if (a.rb_band && t.bb >= 0 && rowok) {
@@ -1730,50 +1725,103 @@ __global__ __launch_bounds__(64 * KS) void k_gemv_rows(PassArgs a) {
     qlo = b.x;
     qhi = b.y;
   }
-  auto src = [&](int kk, int c) { return (rowok && 4 * kk >= qlo && 4 * kk < qhi) ? Pq + (int64_t)kk * 64 + 16 * c : zp; };
   double yr[M], yi[M];
 #pragma unroll
   for (int m = 0; m < M; ++m) yr[m] = yi[m] = 0.0;
-  constexpr int G = 2;
-  // The state operand of a k-step: four consecutive rows of every fibre, one 64-byte read per
-  // fibre where its rows are contiguous (no gather, k-step inside the fibre); columns past the
-  // fibre multiply zero padding and read the fibre's last row instead.
-  struct X4 {
-    double2 v[4];
-  };
-  auto step = [&](const PT (&e)[4], int kk) {
-    if (!GATHER && 4 * kk + 3 < L) {
+  if constexpr (FMT == PF_BF16X3) {
+    // BF16x3 chunks of 32 columns: the row's four lane slots hold 8 consecutive columns each
+    // (six planes of 8 bf16 per slot); per slot, the state operand is 8 consecutive rows of
+    // every fibre (two 64-byte reads where contiguous)
+    const int nkc = ((L + 31) & ~31) >> 5;
+    const v8u16* zp = reinterpret_cast<const v8u16*>(a.zero);
+    const v8u16* Pq = reinterpret_cast<const v8u16*>(Pb) + (int64_t)(rowok ? rbq : 0) * nkc * 6 * 64 + li;
+    int klo, khi;
+    tile_band(t, 32 * nkc, 32, klo, khi);
+    struct X8 {
+      double2 v[8];
+    };
+    for (int kc = klo + kw; kc < khi; kc += KS) {
+      const bool in = rowok && 32 * kc >= qlo && 32 * kc < qhi;
+      const v8u16* Pc = Pq + (int64_t)kc * 6 * 64;
 #pragma unroll
-      for (int m = 0; m < M; ++m) {
-        const X4 x = *reinterpret_cast<const X4*>(a.X + r0[m] + 4 * kk);
+      for (int j = 0; j < 4; ++j) {
+        v8u16 pl[6];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) cmac(yr[m], yi[m], e[c].x, e[c].y, x.v[c]);
-      }
-    } else {
+        for (int k = 0; k < 6; ++k) pl[k] = *(in ? Pc + 64 * k + 16 * j : zp);
+        double er[8], ei[8];
 #pragma unroll
-      for (int m = 0; m < M; ++m)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const double2 x = a.X[xrow<GATHER>(a, r0[m] + min(4 * kk + c, L - 1))];
-          cmac(yr[m], yi[m], e[c].x, e[c].y, x);
+        for (int e = 0; e < 8; ++e) {
+          er[e] = (double)(bf2f(pl[0][e]) + bf2f(pl[2][e]) + bf2f(pl[4][e]));
+          ei[e] = (double)(bf2f(pl[1][e]) + bf2f(pl[3][e]) + bf2f(pl[5][e]));
         }
+        const int c0 = 32 * kc + 8 * j;
+        if (!GATHER && c0 + 7 < L) {
+#pragma unroll
+          for (int m = 0; m < M; ++m) {
+            const X8 x = *reinterpret_cast<const X8*>(a.X + r0[m] + c0);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) cmac(yr[m], yi[m], er[e], ei[e], x.v[e]);
+          }
+        } else {
+#pragma unroll
+          for (int m = 0; m < M; ++m)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+              const double2 x = a.X[xrow<GATHER>(a, r0[m] + min(c0 + e, L - 1))];
+              cmac(yr[m], yi[m], er[e], ei[e], x);
+            }
+        }
+      }
     }
-  };
-  int kk = klo + kw;
-  for (; kk + (G - 1) * KS < khi; kk += G * KS) {
-    PT e[G][4];
+  } else {
+    using PT = typename std::conditional<FMT == PF_F64, double2, float2>::type;
+    const int nks = ((L + 15) & ~15) >> 2;
+    const PT* zp = reinterpret_cast<const PT*>(a.zero);
+    const PT* Pq = reinterpret_cast<const PT*>(Pb) + (int64_t)(rowok ? rbq : 0) * nks * 64 + li;
+    int klo, khi;
+    tile_band(t, 4 * nks, 4, klo, khi);
+    auto src = [&](int kk, int c) { return (rowok && 4 * kk >= qlo && 4 * kk < qhi) ? Pq + (int64_t)kk * 64 + 16 * c : zp; };
+    constexpr int G = 2;
+    // The state operand of a k-step: four consecutive rows of every fibre, one 64-byte read per
+    // fibre where its rows are contiguous (no gather, k-step inside the fibre); columns past the
+    // fibre multiply zero padding and read the fibre's last row instead.
+    struct X4 {
+      double2 v[4];
+    };
+    auto step = [&](const PT (&e)[4], int kk) {
+      if (!GATHER && 4 * kk + 3 < L) {
 #pragma unroll
-    for (int g = 0; g < G; ++g)
+        for (int m = 0; m < M; ++m) {
+          const X4 x = *reinterpret_cast<const X4*>(a.X + r0[m] + 4 * kk);
 #pragma unroll
-      for (int c = 0; c < 4; ++c) e[g][c] = *src(kk + g * KS, c);
+          for (int c = 0; c < 4; ++c) cmac(yr[m], yi[m], e[c].x, e[c].y, x.v[c]);
+        }
+      } else {
 #pragma unroll
-    for (int g = 0; g < G; ++g) step(e[g], kk + g * KS);
-  }
-  for (; kk < khi; kk += KS) {
-    PT e[4];
+        for (int m = 0; m < M; ++m)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) e[c] = *src(kk, c);
-    step(e, kk);
+          for (int c = 0; c < 4; ++c) {
+            const double2 x = a.X[xrow<GATHER>(a, r0[m] + min(4 * kk + c, L - 1))];
+            cmac(yr[m], yi[m], e[c].x, e[c].y, x);
+          }
+      }
+    };
+    int kk = klo + kw;
+    for (; kk + (G - 1) * KS < khi; kk += G * KS) {
+      PT e[G][4];
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) e[g][c] = *src(kk + g * KS, c);
+#pragma unroll
+      for (int g = 0; g < G; ++g) step(e[g], kk + g * KS);
+    }
+    for (; kk < khi; kk += KS) {
+      PT e[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) e[c] = *src(kk, c);
+      step(e, kk);
+    }
   }
 #pragma unroll
   for (int m = 0; m < M; ++m) {
@@ -2126,36 +2174,33 @@ static hipError_t launch_gemv_orbit_m(hipStream_t s, int fmt, int ntiles, const 
   return hipErrorInvalidValue;
 }
 
-// single-state tiles of four row blocks, one row per lane (FP64 / FP32 storage): per-fibre
+// single-state tiles of four row blocks, one row per lane (every storage format): per-fibre
 // tiles (orbit = false) or orbit tiles with M the layer's largest group rounded up
-template <int KS, int M, bool ORB>
-static hipError_t launch_gemv_rows_m(hipStream_t s, bool f64, int ntiles, const PassArgs& a) {
-  const dim3 grid(ntiles), block(64 * KS);
-  if (a.in_pos) {
-    if (f64)
-      hipLaunchKernelGGL((k_gemv_rows<KS, PF_F64, M, ORB, true>), grid, block, 0, s, a);
-    else
-      hipLaunchKernelGGL((k_gemv_rows<KS, PF_F32, M, ORB, true>), grid, block, 0, s, a);
-  } else {
-    if (f64)
-      hipLaunchKernelGGL((k_gemv_rows<KS, PF_F64, M, ORB, false>), grid, block, 0, s, a);
-    else
-      hipLaunchKernelGGL((k_gemv_rows<KS, PF_F32, M, ORB, false>), grid, block, 0, s, a);
-  }
+template <int KS, int FMT, int M, bool ORB>
+static hipError_t launch_gemv_rows_g(hipStream_t s, int ntiles, const PassArgs& a) {
+  if (a.in_pos)
+    hipLaunchKernelGGL((k_gemv_rows<KS, FMT, M, ORB, true>), dim3(ntiles), dim3(64 * KS), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_gemv_rows<KS, FMT, M, ORB, false>), dim3(ntiles), dim3(64 * KS), 0, s, a);
   return hipGetLastError();
+}
+
+template <int KS, int M, bool ORB>
+static hipError_t launch_gemv_rows_m(hipStream_t s, int fmt, int ntiles, const PassArgs& a) {
+  if (fmt == PF_F64) return launch_gemv_rows_g<KS, PF_F64, M, ORB>(s, ntiles, a);
+  if (fmt == PF_F32) return launch_gemv_rows_g<KS, PF_F32, M, ORB>(s, ntiles, a);
+  return launch_gemv_rows_g<KS, PF_BF16X3, M, ORB>(s, ntiles, a);
 }
 
 template <int KS>
 static hipError_t launch_gemv_rows(hipStream_t s, int fmt, int ntiles, bool orbit, const PassArgs& a) {
-  if (fmt == PF_BF16X3) return hipErrorInvalidValue;
-  const bool f64 = fmt == PF_F64;
-  if (!orbit) return launch_gemv_rows_m<KS, 1, false>(s, f64, ntiles, a);
+  if (!orbit) return launch_gemv_rows_m<KS, 1, false>(s, fmt, ntiles, a);
   if (!a.orbit || a.orbit_max < 1 || a.orbit_max > kOrbitMax || a.wt || a.tcount) return hipErrorInvalidValue;
   const int gm = a.orbit_max;
-  if (gm <= 2) return launch_gemv_rows_m<KS, 2, true>(s, f64, ntiles, a);
-  if (gm <= 4) return launch_gemv_rows_m<KS, 4, true>(s, f64, ntiles, a);
-  if (gm <= 6) return launch_gemv_rows_m<KS, 6, true>(s, f64, ntiles, a);
-  return launch_gemv_rows_m<KS, 8, true>(s, f64, ntiles, a);
+  if (gm <= 2) return launch_gemv_rows_m<KS, 2, true>(s, fmt, ntiles, a);
+  if (gm <= 4) return launch_gemv_rows_m<KS, 4, true>(s, fmt, ntiles, a);
+  if (gm <= 6) return launch_gemv_rows_m<KS, 6, true>(s, fmt, ntiles, a);
+  return launch_gemv_rows_m<KS, 8, true>(s, fmt, ntiles, a);
 }
 
 static hipError_t launch_gemv_orbit(hipStream_t s, int fmt, int ntiles, int ksplit, const PassArgs& a) {

@@ -5,7 +5,7 @@ of the chain, the translation classes of the kappa = 1 windows) are multiplied t
 tile holds row blocks of the shared propagator and the states of up to eight such fibres, so
 each propagator chunk is loaded once for the group instead of once per fibre.
 
-* every shape (ks in 1, 2, 4; four-row-block tiles with one row per lane -1, -2, -4, -8 except BF16x3) of every precision
+* every shape (ks in 1, 2, 4; four-row-block tiles with one row per lane -1, -2, -4, -8) of every precision
   on the chain (groups of two), the twisted bilayer (groups of six and the fixed fibre) and the
   kappa = 1 chain windows (groups of up to eight): single passes of both layers equal the
   per-fibre kernel of the same shape bit for bit (the same products summed in the same order)
@@ -33,7 +33,7 @@ def colrel(a, b):
 
 
 def shapes(precision):
-    return [1, 2, 4] if precision == "mix_bf16x3" else [1, 2, 4, -1, -2, -4, -8]
+    return [1, 2, 4, -1, -2, -4, -8]
 
 
 def untuned_states(P, n, monkeypatch):
@@ -98,7 +98,7 @@ def test_orbit_trajectories_with_fused_phase(which, precision, monkeypatch):
     P = lsx.Plan(S, 1e-3, "strang", 0.5, precision)
     orb, ref = untuned_states(P, 2, monkeypatch)
     try:
-        ks = 2 if precision == "mix_bf16x3" else -2
+        ks = -2
         for layer in (1, 2):
             orb.set_tuning(layer, ORBIT_NB, ks)
             ref.set_tuning(layer, 1, ks)

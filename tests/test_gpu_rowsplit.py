@@ -60,7 +60,7 @@ def test_rowsplit_shapes(prec, nb, ms, which, monkeypatch):
         S.destroy()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mix_fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "mix_fp32", "mix_bf16x3"])
 @pytest.mark.parametrize("ks", [-1, -2, -4, -8])
 @pytest.mark.parametrize("which", ["chain", "twisted"])
 def test_single_state_row_lane_tiles(prec, ks, which, monkeypatch):
