@@ -397,7 +397,13 @@ lsx_status lsx_state_destroy(lsx_state* st);
  * (App. A compositions; with exact flows the Strang half-steps of consecutive steps inside
  * one call are merged, F1(tau/2) F1(tau/2) = F1(tau), and so are the adjacent F1 sub-steps
  * of the Yoshida scheme; Crank-Nicolson steps are applied unmerged).  nsteps >= 0.
- * Stream-ordered.
+ * Stream-ordered.  Where the passes are launch-bound (every layer's tuned pass at most
+ * 20 us) and a call repeats the step body often enough, the library captures about 128 of
+ * its passes once into a HIP graph (kept with the state, one per arrangement of its two
+ * arrays, rebuilt after lsx_state_set_tuning / lsx_state_set_store_mode) and replays it;
+ * the launches and results are the same as without.  LSX_GRAPH=1 / 0 forces graphs on / off.
+ * While the caller's stream is itself being captured, every pass is launched on it
+ * directly.
  */
 lsx_status lsx_step(lsx_plan* plan, lsx_state* st, int64_t nsteps, void* stream);
 
@@ -505,8 +511,10 @@ lsx_status lsx_state_wrap(lsx_plan* plan, int32_t W, void* dev_ptr, lsx_state** 
 /*
  * Batched systems -- several independent (plan, state) pairs advanced together: every
  * fibre pass of the batch is ONE grouped kernel launch over the tiles of all systems
- * (fibres of uneven lengths, systems of different cutoffs, lattices, W), and the
- * repeated part of the step sequence is captured once in a HIP graph and replayed.
+ * (fibres of uneven lengths, systems of different cutoffs, lattices, W); where the grouped
+ * passes are launch-bound (as for lsx_step), the repeated part of the step sequence is
+ * captured once in a HIP graph (about 128 passes, repetitions short of a whole graph run
+ * directly) and replayed.
  *
  * lsx_batch_create: plans[i] and states[i] (i < n) must match (states[i] created on
  *   plans[i]); all plans must share the scheme, the precision and the number of layers;

@@ -1465,7 +1465,49 @@ struct lsx_state {
   int nred = 0;
   int nbatches = 0;                    // batches that reference this state
   int nsamplers = 0;                   // samplers that reference this state
+  // lsx_step: captured graphs of the repeated step body (StepGraph::k repetitions each), one per
+  // arrangement of the two arrays (an owned state's arrays swap roles after an odd number of
+  // passes); dropped whenever the tile shapes or the store mode change
+  struct StepGraph {
+    double2* b0 = nullptr;
+    int cur = 0, lay = 0;
+    int64_t k = 0;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t e = nullptr;
+  };
+  StepGraph sg[2];
+  hipStream_t cap = nullptr;
+  void drop_graphs() {
+    for (StepGraph& x : sg) {
+      if (x.e) (void)hipGraphExecDestroy(x.e);
+      if (x.g) (void)hipGraphDestroy(x.g);
+      x = StepGraph{};
+    }
+  }
+  ~lsx_state() {
+    drop_graphs();
+    if (cap) (void)hipStreamDestroy(cap);
+  }
 };
+
+// Passes per captured step graph: a graph launch costs about as much as a dozen kernel
+// launches, and kernels inside one graph follow each other faster than host-issued launches,
+// so a graph holds many repetitions of the step body (LSX_GRAPH_PASSES overrides the size).
+static constexpr int kGraphPasses = 128;
+static int64_t graph_passes() { return std::max(1, env_int("LSX_GRAPH_PASSES", kGraphPasses)); }
+// Graph replay pays where the passes are launch-bound: a captured graph starts consecutive
+// kernels sooner than host launches do, which matters for passes of a few microseconds, while
+// on passes of tens of microseconds and more it measured equal or slower.  By default
+// (LSX_GRAPH unset) graphs are used when every layer's tuned pass takes at most kGraphMaxUs;
+// LSX_GRAPH=1 always uses them, LSX_GRAPH=0 never.
+static constexpr float kGraphMaxUs = 20.f;
+static bool use_step_graphs(const float* tuned_us, int nl) {
+  const int mode = env_int("LSX_GRAPH", -1);
+  if (mode >= 0) return mode != 0;
+  for (int l = 0; l < nl; ++l)
+    if (!(tuned_us[l] > 0.f && tuned_us[l] <= kGraphMaxUs)) return false;
+  return true;
+}
 
 
 // Tile order of one fibre pass.  Workgroup i of a launch runs on XCD i % 8, and each XCD has
@@ -1977,6 +2019,7 @@ extern "C" lsx_status lsx_state_set_tuning(lsx_state* st, int32_t layer, int32_t
   st->ks[l] = ks;
   st->u[l] = groups;
   st->tuned_us[l] = 0.f;
+  st->drop_graphs();
   return LSX_OK;
 }
 
@@ -1984,6 +2027,7 @@ extern "C" lsx_status lsx_state_set_store_mode(lsx_state* st, int32_t nontempora
   if (!st) return fail(LSX_E_INVALID, "null state");
   if (nontemporal != 0 && nontemporal != 1) return fail(LSX_E_INVALID, "store mode must be 0 or 1");
   st->nt = nontemporal;
+  st->drop_graphs();
   return LSX_OK;
 }
 
@@ -2182,9 +2226,62 @@ extern "C" lsx_status lsx_step(lsx_plan* pl, lsx_state* st, int64_t nsteps, void
   std::vector<PassSpec> head, body, tail;
   int64_t reps = 0;
   step_sequence(pl->scheme, pl->sys->nl, nsteps, head, body, tail, reps);
-  return run_passes(pl, st, reinterpret_cast<hipStream_t>(stream), [&](Runner& r) -> lsx_status {
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  // body repetitions per captured graph: about kGraphPasses passes, an even number of them so
+  // that a replay ends in the arrays and layout it starts from
+  int64_t k = std::max<int64_t>(1, graph_passes() / std::max<int64_t>(1, (int64_t)body.size()));
+  if ((k * (int64_t)body.size()) % 2) ++k;
+  // no captured graph inside a caller's own capture of this stream (its launches are captured
+  // as they are)
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  LSX_HIP_TRY(hipStreamIsCapturing(s, &cs));
+  const bool graphs = use_step_graphs(st->tuned_us, pl->sys->nl) && cs == hipStreamCaptureStatusNone && !body.empty() &&
+                      reps >= k;
+  return run_passes(pl, st, s, [&](Runner& r) -> lsx_status {
     for (const PassSpec& p : head) LSX_TRY(r.pass(p.layer, p.half, p.next, p.phase_half));
-    for (int64_t k = 0; k < reps; ++k)
+    int64_t left = reps;
+    if (graphs) {
+      lsx_state::StepGraph* g = nullptr;
+      for (lsx_state::StepGraph& x : st->sg)
+        if (x.e && x.b0 == st->buf[0] && x.cur == r.cur && x.lay == r.lay && x.k == k) g = &x;
+      if (!g) {
+        g = !st->sg[0].e ? &st->sg[0] : (!st->sg[1].e ? &st->sg[1] : &st->sg[0]);
+        if (g->e) (void)hipGraphExecDestroy(g->e);
+        if (g->g) (void)hipGraphDestroy(g->g);
+        *g = lsx_state::StepGraph{};
+        if (!st->cap) LSX_HIP_TRY(hipStreamCreateWithFlags(&st->cap, hipStreamNonBlocking));
+        Runner rc{pl, st, st->cap};
+        rc.cur = r.cur;
+        rc.lay = r.lay;
+        LSX_HIP_TRY(hipStreamBeginCapture(st->cap, hipStreamCaptureModeThreadLocal));
+        lsx_status cap_err = LSX_OK;
+        for (int64_t i = 0; i < k && cap_err == LSX_OK; ++i)
+          for (const PassSpec& p : body)
+            if ((cap_err = rc.pass(p.layer, p.half, p.next, p.phase_half)) != LSX_OK) break;
+        hipGraph_t gg = nullptr;
+        const hipError_t ee = hipStreamEndCapture(st->cap, &gg);
+        if (cap_err == LSX_OK && ee == hipSuccess && (rc.cur != r.cur || rc.lay != r.lay))
+          cap_err = fail(LSX_E_STATE, "internal: captured step body does not return to its arrays");
+        if (cap_err != LSX_OK || ee != hipSuccess) {
+          if (gg) (void)hipGraphDestroy(gg);
+          if (cap_err != LSX_OK) return cap_err;
+          LSX_HIP_TRY(ee);
+        }
+        g->g = gg;
+        const hipError_t ie = hipGraphInstantiate(&g->e, g->g, nullptr, nullptr, 0);
+        if (ie != hipSuccess) {
+          (void)hipGraphDestroy(g->g);
+          *g = lsx_state::StepGraph{};
+          LSX_HIP_TRY(ie);
+        }
+        g->b0 = st->buf[0];
+        g->cur = r.cur;
+        g->lay = r.lay;
+        g->k = k;
+      }
+      for (; left >= k; left -= k) LSX_HIP_TRY(hipGraphLaunch(g->e, s));
+    }
+    for (; left > 0; --left)
       for (const PassSpec& p : body) LSX_TRY(r.pass(p.layer, p.half, p.next, p.phase_half));
     for (const PassSpec& p : tail) LSX_TRY(r.pass(p.layer, p.half, p.next, p.phase_half));
     return LSX_OK;
@@ -2329,6 +2426,7 @@ struct lsx_batch {
   hipStream_t cap = nullptr;
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
+  int64_t graph_k = 0;  // body repetitions the graph holds
   ~lsx_batch() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -2658,15 +2756,18 @@ extern "C" lsx_status lsx_batch_step(lsx_batch* b, int64_t nsteps, void* stream)
     greps = reps / 2;
     extra = reps % 2;
   }
-  if (greps > 0) {
+  // one graph holds kb repetitions of the (even) body, about kGraphPasses passes; the
+  // repetitions short of a whole graph run eagerly
+  const int64_t kb = std::max<int64_t>(1, graph_passes() / std::max<int64_t>(1, (int64_t)gbody.size()));
+  const bool use_graph = use_step_graphs(b->tuned_us, b->nl) && !gbody.empty() && greps >= kb;
+  int64_t eager = use_graph ? greps % kb : greps;
+  if (use_graph) {
     // the body returns to the same (array, layout) state, so one captured graph serves
     // every repetition; it is built on first use and kept with the batch
     const int cur0 = cur, lay0 = lay;
-    if (!b->exec || env_int("LSX_GRAPH", 1) == 0) {
-      if (env_int("LSX_GRAPH", 1) == 0) {
-        for (int64_t r = 0; r < greps; ++r)
-          for (const PassSpec& p : gbody) LSX_TRY(batch_pass(b, s, p, cur, lay));
-      } else {
+    if (b->exec && b->graph_k != kb) batch_drop_graph(b);
+    if (!b->exec) {
+      {
         // build every argument array first: capture must not do synchronous copies
         int c2 = cur, l2 = lay;
         for (const PassSpec& p : gbody) {
@@ -2679,8 +2780,9 @@ extern "C" lsx_status lsx_batch_step(lsx_batch* b, int64_t nsteps, void* stream)
         if (!b->cap) LSX_HIP_TRY(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
         LSX_HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
         lsx_status cap_err = LSX_OK;
-        for (const PassSpec& p : gbody)
-          if ((cap_err = batch_pass(b, b->cap, p, cur, lay)) != LSX_OK) break;
+        for (int64_t i = 0; i < kb && cap_err == LSX_OK; ++i)
+          for (const PassSpec& p : gbody)
+            if ((cap_err = batch_pass(b, b->cap, p, cur, lay)) != LSX_OK) break;
         hipGraph_t g = nullptr;
         const hipError_t ee = hipStreamEndCapture(b->cap, &g);
         if (cap_err != LSX_OK) {
@@ -2690,17 +2792,18 @@ extern "C" lsx_status lsx_batch_step(lsx_batch* b, int64_t nsteps, void* stream)
         LSX_HIP_TRY(ee);
         b->graph = g;
         LSX_HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+        b->graph_k = kb;
         cur = cur0;
         lay = lay0;
       }
     }
-    if (b->exec && env_int("LSX_GRAPH", 1) != 0) {
-      for (int64_t r = 0; r < greps; ++r) LSX_HIP_TRY(hipGraphLaunch(b->exec, s));
-      // the captured body has an even number of passes and ends in the layout it started from
-      cur = cur0;
-      lay = lay0;
-    }
+    for (int64_t r = 0; r < greps / kb; ++r) LSX_HIP_TRY(hipGraphLaunch(b->exec, s));
+    // the captured body has an even number of passes and ends in the layout it started from
+    cur = cur0;
+    lay = lay0;
   }
+  for (int64_t r = 0; r < eager; ++r)
+    for (const PassSpec& p : gbody) LSX_TRY(batch_pass(b, s, p, cur, lay));
   for (int64_t r = 0; r < extra; ++r)
     for (const PassSpec& p : body) LSX_TRY(batch_pass(b, s, p, cur, lay));
   for (const PassSpec& p : tail) LSX_TRY(batch_pass(b, s, p, cur, lay));

@@ -5,7 +5,9 @@ system (FP64: <= 1e-12 per step; mixed: the rounding bound derived in mixed_boun
 the same system stepped on its own (up to the summation order of a different tile shape),
 for every scheme and precision, with systems of different lattices, cutoffs, dimensions and
 wavepacket counts; the replayed HIP graph of the step body must give the same result on
-every call.
+every call.  The short runs here set LSX_GRAPH_PASSES=2 (graphs of one body repetition), so
+that they replay graphs (LSX_GRAPH=1: whatever the pass times); test_default_graphs_equal_eager_launches
+runs the default graph size.
 """
 import math
 
@@ -24,6 +26,12 @@ pytestmark = pytest.mark.gpu
 
 def colrel(a, b):
     return (np.linalg.norm(a - b, axis=0) / np.linalg.norm(b, axis=0)).max()
+
+
+@pytest.fixture(autouse=True)
+def one_body_graphs(monkeypatch):
+    monkeypatch.setenv("LSX_GRAPH", "1")
+    monkeypatch.setenv("LSX_GRAPH_PASSES", "2")
 
 
 def systems():
@@ -240,3 +248,35 @@ def test_example3_batch_and_mixed_layer_counts():
             ref.destroy()
             P.destroy()
             S.destroy()
+
+
+@pytest.mark.parametrize("scheme", ["strang", "lie"])
+def test_default_graphs_equal_eager_launches(monkeypatch, scheme):
+    """Graphs of the default size (about 128 passes of the step body each, repetitions short of
+    a whole graph launched directly): 150 and then 70 steps of a batch equal the same batch
+    stepped with every pass launched directly (LSX_GRAPH=0), bit for bit."""
+    print(f"[case] batch default graphs {scheme}", flush=True)
+    monkeypatch.delenv("LSX_GRAPH_PASSES")
+    monkeypatch.setenv("LSX_NB", "1")
+    monkeypatch.setenv("LSX_KS", "2")
+    out = {}
+    for graph in ("1", "0"):
+        monkeypatch.setenv("LSX_GRAPH", graph)
+        made = []
+        for k, (spec, W) in enumerate(systems()[:3]):
+            S = lsx.System.from_spec(spec)
+            P = lsx.Plan(S, 0.004, scheme, 0.5, "mix_fp32")
+            st = lsx.State(P, W)
+            st.upload(wl.random_state(S.N, W, seed=k))
+            made.append((S, P, st))
+        B = lsx.Batch([m[2] for m in made])
+        B.step(150)
+        B.step(70)
+        out[graph] = [st.download() for _, _, st in made]
+        B.destroy()
+        for S, P, st in made:
+            st.destroy()
+            P.destroy()
+            S.destroy()
+    for a, b in zip(out["1"], out["0"]):
+        assert np.array_equal(a, b)

@@ -99,7 +99,9 @@ def test_yoshida_wavepackets(which):
         S.destroy()
 
 
-def test_yoshida_batch_equals_individual():
+def test_yoshida_batch_equals_individual(monkeypatch):
+    monkeypatch.setenv("LSX_GRAPH", "1")
+    monkeypatch.setenv("LSX_GRAPH_PASSES", "2")  # graphs of one body repetition: the second call replays one
     systems = [wl.chain_system(2000.0), wl.chain_system(5000.0, L2=np.sqrt(2.0)), wl.twisted_system(300.0)]
     Ss, Ps, sts, refs = [], [], [], []
     try:
