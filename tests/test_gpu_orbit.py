@@ -13,7 +13,9 @@ each propagator chunk is loaded once for the group instead of once per fibre.
   derived bounds, tests/mixed_bounds.py);
 * Strang trajectories, whose first pass gathers through the layout tables and whose passes
   apply the kinetic phase (kappa = 0.5) in their epilogue, equal the per-fibre kernel's;
-* a plan without shared propagators (LSX_SYMMETRY=0) refuses the shape.
+* a plan without shared propagators (LSX_SYMMETRY=0) refuses the shape;
+* three layers (the chain trilayer at kappa 0 and 1): every layer's orbit tiles equal the
+  per-fibre tiles and agree with the three-layer oracle's fibre flows.
 """
 import numpy as np
 import pytest
@@ -136,5 +138,43 @@ def test_orbit_shape_needs_shared_propagators(monkeypatch):
         st2.destroy()
     finally:
         st.destroy()
+        P.destroy()
+        S.destroy()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mix_fp32", "mix_bf16x3"])
+@pytest.mark.parametrize("kappa", [0.0, 1.0])
+def test_three_layer_orbit_passes(kappa, precision, monkeypatch):
+    """Three-layer chain (x -> -x orbits at kappa 0, translation classes at kappa 1): every layer's
+    orbit tiles equal the per-fibre tiles of the same shape bit for bit and agree with the
+    three-layer oracle's fibre flows."""
+    from oracle import multilayer as ml
+    spec = wl.chain_layers(2000.0)
+    print(f"[case] three-layer orbit passes kappa={kappa} {precision}", flush=True)
+    S = lsx.System.layers(spec.d, spec.As, spec.Ec, spec.cutoff, spec.pots)
+    O = ml.MultiLifted(spec.d, spec.As, spec.Ec, spec.cutoff, spec.pots)
+    oplan = ml.MultiSplitPlan(O, kappa)
+    tau = 0.01
+    P = lsx.Plan(S, tau, "strang", kappa, precision)
+    orb, ref = untuned_states(P, 2, monkeypatch)
+    try:
+        c = wl.random_state(S.N, 1, seed=13)
+        for layer, half, t in ((1, 1, tau / 2), (2, 1, tau / 2), (3, 0, tau)):
+            assert P.sharing(layer)[0] < S.nfibres[layer]
+            want = oplan.apply_fibres(c, layer, t)
+            tol = 1e-12 if precision == "fp64" else 1e-7
+            for ks in (2, -4):
+                orb.set_tuning(layer, ORBIT_NB, ks)
+                ref.set_tuning(layer, 1, ks)
+                orb.upload(c)
+                ref.upload(c)
+                orb.fibre_pass(layer, half)
+                ref.fibre_pass(layer, half)
+                got = orb.download()
+                assert np.array_equal(got, ref.download()), (layer, ks)
+                assert colrel(got, want) < tol, (layer, ks)
+    finally:
+        orb.destroy()
+        ref.destroy()
         P.destroy()
         S.destroy()
