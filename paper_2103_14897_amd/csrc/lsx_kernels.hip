@@ -1781,14 +1781,17 @@ __global__ __launch_bounds__(64 * KS) void k_gemv_rows(PassArgs a) {
     int klo, khi;
     tile_band(t, 4 * nks, 4, klo, khi);
     auto src = [&](int kk, int c) { return (rowok && 4 * kk >= qlo && 4 * kk < qhi) ? Pq + (int64_t)kk * 64 + 16 * c : zp; };
-    constexpr int G = 2;
     // The state operand of a k-step: four consecutive rows of every fibre, one 64-byte read per
     // fibre where its rows are contiguous (no gather, k-step inside the fibre); columns past the
-    // fibre multiply zero padding and read the fibre's last row instead.
+    // fibre multiply zero padding and read the fibre's last row instead.  One k-step's loads in
+    // flight per wave (two measured slower: fewer waves fit).
     struct X4 {
       double2 v[4];
     };
-    auto step = [&](const PT (&e)[4], int kk) {
+    for (int kk = klo + kw; kk < khi; kk += KS) {
+      PT e[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) e[c] = *src(kk, c);
       if (!GATHER && 4 * kk + 3 < L) {
 #pragma unroll
         for (int m = 0; m < M; ++m) {
@@ -1805,22 +1808,6 @@ __global__ __launch_bounds__(64 * KS) void k_gemv_rows(PassArgs a) {
             cmac(yr[m], yi[m], e[c].x, e[c].y, x);
           }
       }
-    };
-    int kk = klo + kw;
-    for (; kk + (G - 1) * KS < khi; kk += G * KS) {
-      PT e[G][4];
-#pragma unroll
-      for (int g = 0; g < G; ++g)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) e[g][c] = *src(kk + g * KS, c);
-#pragma unroll
-      for (int g = 0; g < G; ++g) step(e[g], kk + g * KS);
-    }
-    for (; kk < khi; kk += KS) {
-      PT e[4];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) e[c] = *src(kk, c);
-      step(e, kk);
     }
   }
 #pragma unroll
