@@ -398,10 +398,14 @@ lsx_status lsx_state_destroy(lsx_state* st);
  * one call are merged, F1(tau/2) F1(tau/2) = F1(tau), and so are the adjacent F1 sub-steps
  * of the Yoshida scheme; Crank-Nicolson steps are applied unmerged).  nsteps >= 0.
  * Stream-ordered.  Where the passes are launch-bound (every layer's tuned pass at most
- * 20 us) and a call repeats the step body often enough, the library captures about 128 of
- * its passes once into a HIP graph (kept with the state, one per arrangement of its two
- * arrays, rebuilt after lsx_state_set_tuning / lsx_state_set_store_mode) and replays it;
- * the launches and results are the same as without.  LSX_GRAPH=1 / 0 forces graphs on / off.
+ * 20 us) and a call repeats the step body often enough, the library captures its passes
+ * once into HIP graphs and replays them: graphs of about 512 passes for the bulk of the
+ * call, then halved sizes down to about 32 passes for the remainder (LSX_GRAPH_PASSES,
+ * LSX_GRAPH_MIN_PASSES), the passes short of the smallest launched directly.  The graphs are
+ * kept with the state, one per size and arrangement of its two arrays, up to 16 (the least
+ * recently used is replaced, after a device synchronisation), and rebuilt after
+ * lsx_state_set_tuning / lsx_state_set_store_mode; the launches and results are the same as
+ * without.  LSX_GRAPH=1 / 0 forces graphs on / off.
  * While the caller's stream is itself being captured, every pass is launched on it
  * directly.
  */

@@ -1468,21 +1468,27 @@ struct lsx_state {
   // lsx_step: captured graphs of the repeated step body (StepGraph::k repetitions each), one per
   // arrangement of the two arrays (an owned state's arrays swap roles after an odd number of
   // passes); dropped whenever the tile shapes or the store mode change
+  // captured step graphs, one per (arrangement of the two arrays, body repetitions): the sizes
+  // of one call's ladder for each of the arrangements a call can start from
   struct StepGraph {
     double2* b0 = nullptr;
     int cur = 0, lay = 0;
     int64_t k = 0;
+    uint64_t used = 0;  // last use (the least recently used one is replaced when all are taken)
     hipGraph_t g = nullptr;
     hipGraphExec_t e = nullptr;
   };
-  StepGraph sg[2];
+  static constexpr int kMaxStepGraphs = 16;
+  StepGraph sg[kMaxStepGraphs];
+  uint64_t graph_clock = 0;
   hipStream_t cap = nullptr;
+  static void release(StepGraph& x) {
+    if (x.e) (void)hipGraphExecDestroy(x.e);
+    if (x.g) (void)hipGraphDestroy(x.g);
+    x = StepGraph{};
+  }
   void drop_graphs() {
-    for (StepGraph& x : sg) {
-      if (x.e) (void)hipGraphExecDestroy(x.e);
-      if (x.g) (void)hipGraphDestroy(x.g);
-      x = StepGraph{};
-    }
+    for (StepGraph& x : sg) release(x);
   }
   ~lsx_state() {
     drop_graphs();
@@ -1493,8 +1499,14 @@ struct lsx_state {
 // Passes per captured step graph: a graph launch costs about as much as a dozen kernel
 // launches, and kernels inside one graph follow each other faster than host-issued launches,
 // so a graph holds many repetitions of the step body (LSX_GRAPH_PASSES overrides the size).
-static constexpr int kGraphPasses = 128;
-static int64_t graph_passes() { return std::max(1, env_int("LSX_GRAPH_PASSES", kGraphPasses)); }
+// A single state's call replays graphs of kGraphPasses passes for its bulk and halved sizes
+// down to kGraphMinPasses (LSX_GRAPH_MIN_PASSES) for the remainder; a batch replays graphs of
+// kBatchGraphPasses.
+static constexpr int kGraphPasses = 512;
+static constexpr int kGraphMinPasses = 32;
+static constexpr int kBatchGraphPasses = 128;
+static int64_t graph_passes(int dflt) { return std::max(1, env_int("LSX_GRAPH_PASSES", dflt)); }
+static int64_t graph_min_passes() { return std::max(1, env_int("LSX_GRAPH_MIN_PASSES", kGraphMinPasses)); }
 // Graph replay pays where the passes are launch-bound: a captured graph starts consecutive
 // kernels sooner than host launches do, which matters for passes of a few microseconds, while
 // on passes of tens of microseconds and more it measured equal or slower.  By default
@@ -2227,28 +2239,40 @@ extern "C" lsx_status lsx_step(lsx_plan* pl, lsx_state* st, int64_t nsteps, void
   int64_t reps = 0;
   step_sequence(pl->scheme, pl->sys->nl, nsteps, head, body, tail, reps);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  // body repetitions per captured graph: about kGraphPasses passes, an even number of them so
-  // that a replay ends in the arrays and layout it starts from
-  int64_t k = std::max<int64_t>(1, graph_passes() / std::max<int64_t>(1, (int64_t)body.size()));
-  if ((k * (int64_t)body.size()) % 2) ++k;
+  // body repetitions per captured graph (the ladder): about graph_passes() passes for the bulk
+  // of the call, then halved sizes down to about graph_min_passes() passes for its remainder,
+  // each an even number of passes so that a replay ends in the arrays and layout it starts from
+  const int64_t nb = std::max<int64_t>(1, (int64_t)body.size());
+  auto even = [nb](int64_t k) { return (k * nb) % 2 ? k + 1 : k; };
+  std::vector<int64_t> ladder{even(std::max<int64_t>(1, graph_passes(kGraphPasses) / nb))};
+  for (int64_t k = ladder[0] / 2; k >= 1; k /= 2) {
+    const int64_t ke = even(k);
+    if (ke >= ladder.back() || ke * nb < graph_min_passes()) break;
+    ladder.push_back(ke);
+  }
   // no captured graph inside a caller's own capture of this stream (its launches are captured
   // as they are)
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   LSX_HIP_TRY(hipStreamIsCapturing(s, &cs));
   const bool graphs = use_step_graphs(st->tuned_us, pl->sys->nl) && cs == hipStreamCaptureStatusNone && !body.empty() &&
-                      reps >= k;
+                      reps >= ladder.back();
   return run_passes(pl, st, s, [&](Runner& r) -> lsx_status {
     for (const PassSpec& p : head) LSX_TRY(r.pass(p.layer, p.half, p.next, p.phase_half));
     int64_t left = reps;
-    if (graphs) {
+    for (const int64_t k : ladder) {
+      if (!graphs || left < k) continue;
       lsx_state::StepGraph* g = nullptr;
       for (lsx_state::StepGraph& x : st->sg)
         if (x.e && x.b0 == st->buf[0] && x.cur == r.cur && x.lay == r.lay && x.k == k) g = &x;
       if (!g) {
-        g = !st->sg[0].e ? &st->sg[0] : (!st->sg[1].e ? &st->sg[1] : &st->sg[0]);
-        if (g->e) (void)hipGraphExecDestroy(g->e);
-        if (g->g) (void)hipGraphDestroy(g->g);
-        *g = lsx_state::StepGraph{};
+        // an empty slot, else the least recently used graph (its launches have finished first)
+        g = &st->sg[0];
+        for (lsx_state::StepGraph& x : st->sg)
+          if (!x.e || (g->e && x.used < g->used)) g = &x;
+        if (g->e) {
+          LSX_HIP_TRY(hipDeviceSynchronize());
+          lsx_state::release(*g);
+        }
         if (!st->cap) LSX_HIP_TRY(hipStreamCreateWithFlags(&st->cap, hipStreamNonBlocking));
         Runner rc{pl, st, st->cap};
         rc.cur = r.cur;
@@ -2279,6 +2303,7 @@ extern "C" lsx_status lsx_step(lsx_plan* pl, lsx_state* st, int64_t nsteps, void
         g->lay = r.lay;
         g->k = k;
       }
+      g->used = ++st->graph_clock;
       for (; left >= k; left -= k) LSX_HIP_TRY(hipGraphLaunch(g->e, s));
     }
     for (; left > 0; --left)
@@ -2758,7 +2783,7 @@ extern "C" lsx_status lsx_batch_step(lsx_batch* b, int64_t nsteps, void* stream)
   }
   // one graph holds kb repetitions of the (even) body, about kGraphPasses passes; the
   // repetitions short of a whole graph run eagerly
-  const int64_t kb = std::max<int64_t>(1, graph_passes() / std::max<int64_t>(1, (int64_t)gbody.size()));
+  const int64_t kb = std::max<int64_t>(1, graph_passes(kBatchGraphPasses) / std::max<int64_t>(1, (int64_t)gbody.size()));
   const bool use_graph = use_step_graphs(b->tuned_us, b->nl) && !gbody.empty() && greps >= kb;
   int64_t eager = use_graph ? greps % kb : greps;
   if (use_graph) {

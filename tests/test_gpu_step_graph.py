@@ -1,16 +1,21 @@
 """Captured step graphs of lsx_step.
 
-A call that repeats the step body often enough replays a HIP graph of many body repetitions
-(about 128 passes; LSX_GRAPH_PASSES sets the size) instead of launching every pass from the
-host.  The graph is kept with the state, one per arrangement of its two arrays (an owned
-state's arrays swap roles after a call with an odd number of passes), and rebuilt after the
-tile shape or the store mode changes.  The launches are the same, so the results must be
-bit-identical to launching every pass directly (LSX_GRAPH=0):
+A call that repeats the step body often enough replays HIP graphs of many body repetitions
+instead of launching every pass from the host: graphs of about 512 passes (LSX_GRAPH_PASSES)
+for the bulk of the call, then halved sizes down to about 32 passes (LSX_GRAPH_MIN_PASSES) for
+its remainder.  The graphs are kept with the state, one per size and arrangement of its two
+arrays (an owned state's arrays swap roles after a call with an odd number of passes), up to
+16 of them (the least recently used is replaced), and rebuilt after the tile shape or the
+store mode changes.  The launches are the same, so the results must be bit-identical to
+launching every pass directly (LSX_GRAPH=0):
 
 * every scheme (three-layer Lie has an odd body), kappa 0 and 0.5 (phase sub-steps inside the
   body), FP64 and mixed FP32, over a sequence of calls of different lengths: shorter than one
   graph, several graphs with a remainder, odd and even pass counts;
-* the default graph size over long calls, an owned state and a wrapped state;
+* ladders of graph sizes down to one or two body repetitions, every scheme, over calls whose
+  remainders take different sizes;
+* the default sizes over long calls, an owned state and a wrapped state;
+* more graphs than the state keeps (sizes changed between calls), so that graphs are replaced;
 * a changed tile shape and store mode between calls;
 * a caller's own stream capture of lsx_step (the library then launches every pass into it):
   one replay equals direct stepping.
@@ -27,12 +32,17 @@ pytestmark = pytest.mark.gpu
 CALLS = [1, 9, 2, 30, 5, 17]
 
 
-def run(monkeypatch, make, scheme, kappa, precision, W, calls, graph, passes=None, change=None, wrap=False):
+def run(monkeypatch, make, scheme, kappa, precision, W, calls, graph, passes=None, change=None, wrap=False,
+        min_passes=None, sizes=None):
     monkeypatch.setenv("LSX_GRAPH", graph)
     if passes is None:
         monkeypatch.delenv("LSX_GRAPH_PASSES", raising=False)
     else:
         monkeypatch.setenv("LSX_GRAPH_PASSES", str(passes))
+    if min_passes is None:
+        monkeypatch.delenv("LSX_GRAPH_MIN_PASSES", raising=False)
+    else:
+        monkeypatch.setenv("LSX_GRAPH_MIN_PASSES", str(min_passes))
     monkeypatch.setenv("LSX_NB", "1")
     monkeypatch.setenv("LSX_KS", "2")
     S = make()
@@ -50,6 +60,8 @@ def run(monkeypatch, make, scheme, kappa, precision, W, calls, graph, passes=Non
         for i, n in enumerate(calls):
             if change is not None and i == 2:
                 change(st)
+            if sizes is not None:
+                monkeypatch.setenv("LSX_GRAPH_PASSES", str(sizes[i % len(sizes)]))
             st.step(n)
         return st.download()
     finally:
@@ -82,6 +94,36 @@ def test_three_layer_graphs_equal_direct_launches(monkeypatch, scheme):
     print(f"[case] step graphs three layers {scheme}", flush=True)
     a = run(monkeypatch, three_layer, scheme, 0.0, "fp64", 4, CALLS, "1", passes=3)
     b = run(monkeypatch, three_layer, scheme, 0.0, "fp64", 4, CALLS, "0")
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mix_fp32"])
+@pytest.mark.parametrize("scheme", ["strang", "lie", "yoshida4", "strang_cn", "lie_be"])
+def test_graph_ladder_equals_direct_launches(monkeypatch, scheme, precision):
+    print(f"[case] step graph ladder {scheme} {precision}", flush=True)
+    calls = [40, 3, 23, 17, 9, 64]
+    a = run(monkeypatch, two_layer, scheme, 0.5, precision, 8, calls, "1", passes=32, min_passes=2)
+    b = run(monkeypatch, two_layer, scheme, 0.5, precision, 8, calls, "0")
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("scheme", ["lie", "strang"])
+def test_three_layer_graph_ladder_equals_direct_launches(monkeypatch, scheme):
+    print(f"[case] step graph ladder three layers {scheme}", flush=True)
+    calls = [30, 7, 19, 12]
+    a = run(monkeypatch, three_layer, scheme, 0.0, "fp64", 4, calls, "1", passes=24, min_passes=3)
+    b = run(monkeypatch, three_layer, scheme, 0.0, "fp64", 4, calls, "0")
+    assert np.array_equal(a, b)
+
+
+def test_graph_cache_replacement(monkeypatch):
+    """Twenty graph sizes over forty calls (both arrangements of the arrays): more graphs than the
+    state keeps, so the least recently used ones are replaced and rebuilt."""
+    print("[case] step graph cache replacement", flush=True)
+    calls = [25, 26] * 20
+    sizes = [2 * (i // 2 + 1) for i in range(40)]
+    a = run(monkeypatch, two_layer, "strang", 0.0, "mix_fp32", 8, calls, "1", min_passes=2, sizes=sizes)
+    b = run(monkeypatch, two_layer, "strang", 0.0, "mix_fp32", 8, calls, "0")
     assert np.array_equal(a, b)
 
 
