@@ -1487,7 +1487,11 @@ struct lsx_state {
     if (x.g) (void)hipGraphDestroy(x.g);
     x = StepGraph{};
   }
+  // replays still running finish first (the graphs are released on the host's order)
   void drop_graphs() {
+    bool any = false;
+    for (const StepGraph& x : sg) any = any || x.e;
+    if (any) (void)hipDeviceSynchronize();
     for (StepGraph& x : sg) release(x);
   }
   ~lsx_state() {
@@ -2265,7 +2269,7 @@ extern "C" lsx_status lsx_step(lsx_plan* pl, lsx_state* st, int64_t nsteps, void
       for (lsx_state::StepGraph& x : st->sg)
         if (x.e && x.b0 == st->buf[0] && x.cur == r.cur && x.lay == r.lay && x.k == k) g = &x;
       if (!g) {
-        // an empty slot, else the least recently used graph (its launches have finished first)
+        // an empty slot, else the least recently used graph (its replays finish first)
         g = &st->sg[0];
         for (lsx_state::StepGraph& x : st->sg)
           if (!x.e || (g->e && x.used < g->used)) g = &x;
@@ -2464,7 +2468,9 @@ static const int32_t* layout_table(const lsx_plan* pl, int layer, int layout) {
   return layout_map(pl, layer, layout);
 }
 
+// replays still running finish first
 static void batch_drop_graph(lsx_batch* b) {
+  if (b->exec) (void)hipDeviceSynchronize();
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   b->exec = nullptr;
