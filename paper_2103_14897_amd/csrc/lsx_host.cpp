@@ -1613,10 +1613,7 @@ static void build_tiles(const lsx_plan* pl, int layer, int W, int nb, int wb0, i
 // winner with the other depth (where a depth was tuned) and the single-pass runner-up.  The
 // cycle runs between the work array and a scratch array of the same size, so the state is not
 // modified.  Without room for the scratch array everything stays as the single passes chose.
-// With tune_store false the store mode stays as set (ordinary or forced).  Where the step will
-// replay captured graphs (the rule of lsx_step), the cycles are timed as a captured graph as
-// well: a graph starts consecutive kernels sooner than host launches do, which can reorder
-// shapes whose passes take a few microseconds.
+// With tune_store false the store mode stays as set (ordinary or forced).
 static lsx_status choose_cycle(lsx_plan* pl, lsx_state* st, bool tune_store) {
   const int nl = pl->sys->nl, W = st->W;
   const int64_t N = pl->sys->N;
@@ -1656,11 +1653,8 @@ static lsx_status choose_cycle(lsx_plan* pl, lsx_state* st, bool tune_store) {
     return fail(LSX_E_HIP, "event creation failed");
   }
   hipError_t he = hipSuccess;
-  hipStream_t gs = nullptr;
-  if (use_step_graphs(st->tuned_us, nl) && hipStreamCreateWithFlags(&gs, hipStreamNonBlocking) != hipSuccess)
-    gs = nullptr;
   int pick[kMaxLayers] = {0, 0, 0};
-  auto cycle = [&](int nt, hipStream_t s) {
+  auto cycle = [&](int nt) {
     double2* src = st->buf[1];
     double2* dst = tmp.p;
     for (int l = 0; l < nl && he == hipSuccess; ++l) {
@@ -1671,37 +1665,14 @@ static lsx_status choose_cycle(lsx_plan* pl, lsx_state* st, bool tune_store) {
       x.Y = dst;
       x.nt = nt;
       x.u = o.u;
-      he = launch_pass(s, pl->fmt, W, o.ntiles, o.nb, o.ks, x);
+      he = launch_pass(nullptr, pl->fmt, W, o.ntiles, o.nb, o.ks, x);
       std::swap(src, dst);
     }
   };
   auto timed = [&](int nt, int reps) {
     float ms = 0.f;
-    if (gs) {
-      // reps cycles captured once, replayed once untimed and once timed
-      hipGraph_t g = nullptr;
-      hipGraphExec_t ge = nullptr;
-      if (he == hipSuccess) {
-        he = hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal);
-        if (he == hipSuccess) {
-          for (int r = 0; r < reps && he == hipSuccess; ++r) cycle(nt, gs);
-          const hipError_t ee = hipStreamEndCapture(gs, &g);
-          if (he == hipSuccess) he = ee;
-        }
-      }
-      if (he == hipSuccess) he = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-      if (he == hipSuccess) he = hipGraphLaunch(ge, gs);
-      if (he == hipSuccess) he = hipEventRecord(e0, gs);
-      if (he == hipSuccess) he = hipGraphLaunch(ge, gs);
-      if (he == hipSuccess) he = hipEventRecord(e1, gs);
-      if (he == hipSuccess) he = hipEventSynchronize(e1);
-      if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
-      if (ge) (void)hipGraphExecDestroy(ge);
-      if (g) (void)hipGraphDestroy(g);
-      return ms * 1e3f / reps;
-    }
     if (he == hipSuccess) he = hipEventRecord(e0, nullptr);
-    for (int r = 0; r < reps && he == hipSuccess; ++r) cycle(nt, nullptr);
+    for (int r = 0; r < reps && he == hipSuccess; ++r) cycle(nt);
     if (he == hipSuccess) he = hipEventRecord(e1, nullptr);
     if (he == hipSuccess) he = hipEventSynchronize(e1);
     if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
@@ -1744,7 +1715,6 @@ static lsx_status choose_cycle(lsx_plan* pl, lsx_state* st, bool tune_store) {
     }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  if (gs) (void)hipStreamDestroy(gs);
   if (he != hipSuccess) return fail(LSX_E_HIP, std::string("step-cycle tuning: ") + hipGetErrorString(he));
   st->nt = best_nt;
   for (int l = 0; l < nl; ++l) {
