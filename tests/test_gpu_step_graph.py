@@ -16,6 +16,8 @@ launching every pass directly (LSX_GRAPH=0):
   remainders take different sizes;
 * the default sizes over long calls, an owned state and a wrapped state;
 * more graphs than the state keeps (sizes changed between calls), so that graphs are replaced;
+* the configuration the benchmark times (the Ec = 2e4 chain, 64 wavepackets, tuned shapes,
+  2000 steps in one call), FP64 and mixed FP32;
 * a changed tile shape and store mode between calls;
 * a caller's own stream capture of lsx_step (the library then launches every pass into it):
   one replay equals direct stepping.
@@ -176,5 +178,35 @@ def test_caller_capture_of_step(monkeypatch):
     finally:
         st.destroy()
         ref.destroy()
+        P.destroy()
+        S.destroy()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mix_fp32"])
+def test_headline_chain_graphs_equal_direct_launches(monkeypatch, precision):
+    """The configuration the benchmark times: the Ec = 2e4 chain (N = 5149), 64 wavepackets,
+    Strang tau = 1e-3, the tuner's own tile shapes and store mode, 2000 steps in one call
+    (graph ladder from the default sizes) against the same state stepped with every pass
+    launched directly."""
+    print(f"[case] headline chain, 2000 steps, graphs vs direct, {precision}", flush=True)
+    monkeypatch.delenv("LSX_GRAPH_PASSES", raising=False)
+    monkeypatch.delenv("LSX_GRAPH_MIN_PASSES", raising=False)
+    monkeypatch.delenv("LSX_GRAPH", raising=False)
+    w = wl.chain(2.0e4, 64)
+    S = lsx.System.from_spec(w.spec)
+    P = lsx.Plan(S, w.tau, "strang", 0.0, precision)
+    st = lsx.State(P, 64)
+    try:
+        c0 = w.initial_state(S.index())
+        out = {}
+        for graph in ("1", "0"):
+            monkeypatch.setenv("LSX_GRAPH", graph)
+            st.upload(c0)
+            st.step(2000)
+            out[graph] = st.download()
+        assert np.array_equal(out["1"], out["0"])
+        assert np.isfinite(out["1"]).all()
+    finally:
+        st.destroy()
         P.destroy()
         S.destroy()
