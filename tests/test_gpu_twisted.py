@@ -2,10 +2,10 @@
 
 * reduced cutoff (Ec = 1500, N = 21421, 199 + 199 fibres): whole trajectories against the
   oracle, FP64 per step <= 1e-12;
-* full size (Ec = 6500, N = 398821, 889 + 889 fibres of length 7-889, W = 128): the oracle
-  cannot step the whole system in test time, so it checks sampled fibres one by one
-  (propagators and single passes, which are exact per fibre) and the invariants that hold at
-  any size (unitarity, Strang reversibility).
+* full size (Ec = 6500, N = 398821, 889 + 889 fibres of length 7-889, W = 128, and W = 1 in
+  the single-state configuration): the oracle cannot step the whole system in test time, so
+  it checks sampled fibres one by one (propagators and single passes, which are exact per
+  fibre) and the invariants that hold at any size (unitarity, Strang reversibility).
 """
 import numpy as np
 import pytest
@@ -173,3 +173,32 @@ def test_twisted_full_size_to_T_mixed_within_1e6_of_fp64(full_twisted):
         assert err <= 1e-6, (prec, err)
         # the mixed paths round differently from FP64 (their error is not zero)
         assert err > 0.0, prec
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mix_fp32", "mix_bf16x3"])
+def test_twisted_full_size_single_state_sampled(full_twisted, precision):
+    """One wavepacket (W = 1) at full size, in the tuned launch configuration (single-state
+    tiles, most of them multiplying every fibre of a symmetry orbit with one stored propagator):
+    single passes of both layers on sampled fibres (the longest, the shortest and random ones,
+    mostly orbit members other than the stored representative) against the oracle's propagator
+    of each fibre applied to its rows."""
+    w, S, O = full_twisted
+    print(f"[case] twisted full size W=1 {precision}", flush=True)
+    P = lsx.Plan(S, w.tau, "strang", 0.0, precision)
+    st = lsx.State(P, 1)
+    tol = 1e-12 if precision == "fp64" else 1e-7
+    try:
+        c = wl.random_state(S.N, 1, seed=13)
+        for layer in (1, 2):
+            ptr, rows = _oracle_fibres(O, layer)
+            st.upload(c)
+            st.fibre_pass(layer, 0)
+            got = st.download()
+            for f in _sample_fibres(ptr, k=5, seed=20 + layer):
+                r = rows[f]
+                Pf = splitting.propagator_from_hamiltonian(O.fibre_hamiltonian(layer, r, 0.0), w.tau)
+                err = colrel(got[r], Pf @ c[r])
+                assert err < tol, (precision, layer, f, len(r), err, st.tuning(layer))
+    finally:
+        st.destroy()
+        P.destroy()
