@@ -114,19 +114,9 @@ def batch_workload(args):
     every system's state read and written (2 N W 16) plus its distinct propagators (and the FP64
     diagonal, 16 N, on the mixed paths); flops = 8 W sum L^2 over every fibre.
     """
-    import math
     import torch
-    rng = np.random.default_rng(0)
     prec = args.paths.split(",")[0]
-    specs = []
-    for _ in range(args.batch_1d):
-        ratio = [wl.GOLDEN, math.sqrt(2.0), math.sqrt(3.0)][rng.integers(3)]
-        Ec = float(np.exp(rng.uniform(np.log(1e3), np.log(2e4))))
-        specs.append((wl.chain_system(Ec, L2=ratio), 1e-3))
-    for _ in range(args.batch_2d):
-        theta = float(rng.uniform(1.0, 6.0))
-        Ntarget = float(np.exp(rng.uniform(np.log(1e5), np.log(4e5))))
-        specs.append((wl.twisted_system(6500.0 * math.sqrt(Ntarget / 398821.0), theta_deg=theta), 5e-3))
+    specs = wl.batch_specs(args.batch_1d, args.batch_2d)
     stream = torch.cuda.current_stream()
     t0 = time.perf_counter()
     items = []

@@ -233,6 +233,24 @@ def random_state(N: int, W: int, seed: int = 0) -> np.ndarray:
     return c.astype(np.complex128)
 
 
+def batch_specs(n1d: int = 240, n2d: int = 16, seed: int = 0):
+    """The batched uneven systems (seeded PCG64), as (spec, tau) pairs: n1d 1D+1D chains with
+    period ratio drawn from {golden mean, sqrt 2, sqrt 3} and Ec log-uniform in [1e3, 2e4]
+    (tau = 1e-3), then n2d twisted triangular bilayers with twist uniform in [1, 6] deg and N
+    log-uniform in [1e5, 4e5] (Ec = 6500 sqrt(N / 398821); tau = 5e-3)."""
+    rng = np.random.default_rng(seed)
+    specs = []
+    for _ in range(n1d):
+        ratio = [GOLDEN, math.sqrt(2.0), math.sqrt(3.0)][rng.integers(3)]
+        Ec = float(np.exp(rng.uniform(np.log(1e3), np.log(2e4))))
+        specs.append((chain_system(Ec, L2=ratio), 1e-3))
+    for _ in range(n2d):
+        theta = float(rng.uniform(1.0, 6.0))
+        Ntarget = float(np.exp(rng.uniform(np.log(1e5), np.log(4e5))))
+        specs.append((twisted_system(6500.0 * math.sqrt(Ntarget / 398821.0), theta_deg=theta), 5e-3))
+    return specs
+
+
 @dataclass
 class Workload:
     """A system, a wavepacket batch recipe and a time grid."""

@@ -280,3 +280,51 @@ def test_default_graphs_equal_eager_launches(monkeypatch, scheme):
             S.destroy()
     for a, b in zip(out["1"], out["0"]):
         assert np.array_equal(a, b)
+
+
+def test_full_size_batch_members_match_oracle(monkeypatch):
+    """The batched workload at full size, in the launch configuration the benchmark times
+    (240 chains and 16 twisted bilayers of N up to 4e5, 16 wavepackets each, kappa = 0, Strang,
+    mixed FP32, the batch tuner's own shapes and launch mode, graphs by the default rule): three
+    chain members (the smallest, the largest and one between) against the oracle's unmerged
+    evolution within the derived mixed bound, and every member's mass against its start."""
+    print("[case] full-size batch (240 chains + 16 bilayers), mixed FP32", flush=True)
+    monkeypatch.delenv("LSX_GRAPH", raising=False)
+    monkeypatch.delenv("LSX_GRAPH_PASSES", raising=False)
+    specs = wl.batch_specs()
+    nsteps, W = 3, 16
+    made = []
+    try:
+        for i, (spec, tau) in enumerate(specs):
+            S = lsx.System.from_spec(spec)
+            P = lsx.Plan(S, tau, "strang", 0.0, "mix_fp32")
+            st = lsx.State(P, W)
+            c0 = wl.random_state(S.N, W, seed=i)
+            st.upload(c0)
+            made.append((S, P, st, c0, spec, tau))
+        B = lsx.Batch([m[2] for m in made])
+        try:
+            B.step(nsteps)
+        finally:
+            B.destroy()
+        Ns = [m[0].N for m in made[:240]]
+        picks = sorted({int(np.argmin(Ns)), int(np.argmax(Ns)), int(np.argsort(Ns)[len(Ns) // 2])})
+        for i in picks:
+            S, P, st, c0, spec, tau = made[i]
+            O = splitting.Lifted.from_spec(spec)
+            assert np.array_equal(S.index(), O.mn)
+            plan = splitting.SplitPlan(O, 0.0)
+            oref = plan.evolve(c0, tau, nsteps, "strang")
+            bound = mixed_bounds.sequence_bound(plan, mixed_bounds.strang_passes(tau, nsteps, merged=True), "mix_fp32")
+            err = colrel(st.download(), oref)
+            print(f"  chain {i} N={S.N}: rel err {err:.2e} (bound {bound:.2e})")
+            assert err <= bound + 1e-12 * nsteps, (i, S.N, err, bound)
+        for i, (S, P, st, c0, spec, tau) in enumerate(made):
+            m = st.observables(lsx.OBS_MASS)["mass"]
+            m0 = np.sum(np.abs(c0) ** 2, axis=0)
+            assert np.abs(m - m0).max() < 1e-6, (i, S.N)
+    finally:
+        for S, P, st, *_ in made:
+            st.destroy()
+            P.destroy()
+            S.destroy()
