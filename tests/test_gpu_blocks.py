@@ -2,13 +2,14 @@
 periodic for both layers, lifted by (m, p, n)) against the block oracle: propagators of both
 layers, Lie / Strang / Yoshida / BE-Lie / CN-Strang trajectories (FP64 <= 2e-12 relative L2
 per step, Yoshida 6e-12), kappa in {0, 0.5, 1}, single passes in every precision at ragged W,
-mixed precision after many steps, mass, energy and fibre masses, and the entry points that
-reject these systems."""
+single passes at the benchmark's full size on sampled fibres, mixed precision after many steps,
+mass, energy and fibre masses, and the entry points that reject these systems."""
 import numpy as np
 import pytest
 
 from oracle import blocks
 from oracle import multilayer as ml
+from oracle import splitting
 from paper_2103_14897_amd import lsx
 from paper_2103_14897_amd import workloads as wl
 
@@ -137,4 +138,38 @@ def test_example3_rejections():
             st.destroy()
             P.destroy()
     finally:
+        S.destroy()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mix_fp32", "mix_bf16x3"])
+def test_example3_full_size_sampled_passes(precision):
+    """Example 3 at the size the benchmark runs (Ec = 1000, N = 74037, fibres up to 2117 rows,
+    W = 128, tau = 5e-3) in the tuned launch configuration: single passes of both layers on
+    sampled fibres (the longest, the shortest and one at random) against the oracle's
+    propagator of each fibre, built from the oracle's own row lists."""
+    print(f"[case] example3 full size sampled passes {precision}", flush=True)
+    S, O = build(1000.0)
+    assert S.N == 74037
+    tau, W = 5e-3, 128
+    P = lsx.Plan(S, tau, "strang", 0.0, precision)
+    st = lsx.State(P, W)
+    rng = np.random.default_rng(4)
+    tol = 1e-12 if precision == "fp64" else 1e-7
+    try:
+        c = wl.random_state(S.N, W, seed=17)
+        for layer in (1, 2):
+            rows_all = [rows for _, rows in O.fib[layer]]
+            L = np.array([len(r) for r in rows_all])
+            picks = sorted({int(np.argmax(L)), int(np.argmin(L)), int(rng.integers(len(L)))})
+            st.upload(c)
+            st.fibre_pass(layer, 0)
+            got = st.download()
+            for f in picks:
+                r = rows_all[f]
+                Pf = splitting.propagator_from_hamiltonian(O.fibre_hamiltonian(layer, r, 0.0), tau)
+                err = colrel(got[r], Pf @ c[r])
+                assert err < tol, (precision, layer, f, len(r), err, st.tuning(layer))
+    finally:
+        st.destroy()
+        P.destroy()
         S.destroy()
