@@ -2,6 +2,7 @@
 every layer and slot, Lie, Strang and Yoshida trajectories (FP64 <= 2e-12 relative L2 per
 step; Yoshida 6e-12 per step for its three Strang steps), the
 fused kinetic phase for kappa in {0, 0.4, 1}, single passes at ragged W in every precision,
+single passes of the twisted trilayer at the benchmark's full size on sampled fibres,
 mixed precision after many steps, mass, energy and per-layer fibre masses, two layers through
 the layered constructor, and the entry points that take two-layer systems only (samplers and
 the semi-implicit step)."""
@@ -9,6 +10,7 @@ import numpy as np
 import pytest
 
 from oracle import multilayer as ml
+from oracle import splitting
 from paper_2103_14897_amd import lsx
 from paper_2103_14897_amd import workloads as wl
 
@@ -251,4 +253,40 @@ def test_three_layer_rejections():
             st.destroy()
             P.destroy()
     finally:
+        S.destroy()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mix_fp32", "mix_bf16x3"])
+def test_trilayer_full_size_sampled_passes(precision):
+    """The twisted trilayer at the size the benchmark runs (Ec = 1000, N = 415135, 9061 fibres
+    per layer, W = 128, tau = 5e-3, Strang) in the tuned launch configuration: single passes
+    of every layer (the slots the Strang step uses: tau for layers 1 and 3, tau / 2 for layer
+    2) on sampled fibres (the longest, the shortest and two at random) against the oracle's
+    propagator of each fibre, built from the oracle's own row lists."""
+    print(f"[case] trilayer full size sampled passes {precision}", flush=True)
+    S, O = build(wl.twisted_layers(1000.0))
+    assert S.N == 415135 and np.array_equal(S.index(), O.mn)
+    tau, W = 5e-3, 128
+    P = lsx.Plan(S, tau, "strang", 0.0, precision)
+    st = lsx.State(P, W)
+    rng = np.random.default_rng(6)
+    tol = 1e-12 if precision == "fp64" else 1e-7
+    try:
+        c = wl.random_state(S.N, W, seed=23)
+        for layer, slot in ((1, 0), (2, 1), (3, 0)):
+            t = tau if slot == 0 else tau / 2
+            rows_all = [rows for _, rows in O.fib[layer]]
+            L = np.array([len(r) for r in rows_all])
+            picks = sorted({int(np.argmax(L)), int(np.argmin(L))} | {int(x) for x in rng.integers(len(L), size=2)})
+            st.upload(c)
+            st.fibre_pass(layer, slot)
+            got = st.download()
+            for f in picks:
+                r = rows_all[f]
+                Pf = splitting.propagator_from_hamiltonian(O.fibre_hamiltonian(layer, r, 0.0), t)
+                err = colrel(got[r], Pf @ c[r])
+                assert err < tol, (precision, layer, f, len(r), err, st.tuning(layer))
+    finally:
+        st.destroy()
+        P.destroy()
         S.destroy()
