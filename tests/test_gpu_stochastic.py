@@ -449,3 +449,39 @@ def test_learned_proposal_beats_uniform(twisted_sys):
         net.destroy()
         st.destroy()
         P.destroy()
+
+
+def test_semi_implicit_full_size_sampled_rows():
+    """Alg. 1 on the full twisted bilayer (Ec = 6500, N = 398821) with the 128 wavepackets the
+    benchmark steps: sampled output rows against the oracle.  The oracle's step with per-fibre
+    weights (the Alg. 4 form) set to one on the layer-1 and layer-2 fibres that hold the sampled
+    rows and zero elsewhere gives Alg. 1's output exactly at those rows, from a few dozen fibre
+    blocks instead of all 1778."""
+    spec = wl.twisted_system(6500.0)
+    S = lsx.System.from_spec(spec)
+    O = splitting.Lifted.from_spec(spec)
+    print(f"[case] semi-implicit full size N={S.N} W=128", flush=True)
+    assert S.N == 398821 and np.array_equal(S.index(), O.mn)
+    W, tau = 128, 5e-3
+    P, st = _pair(S, tau, "strang", 0.0, "fp64", W)
+    try:
+        c = wl.random_state(S.N, W, seed=12)
+        st.upload(c)
+        st.si_step(1)
+        got = st.download()
+        rng = np.random.default_rng(8)
+        R = np.unique(np.concatenate([[0, S.N - 1], rng.choice(S.N, size=24, replace=False)]))
+        weights = []
+        for layer in (1, 2):
+            owner = np.empty(S.N, dtype=np.int64)
+            for f, (_, rows) in enumerate(O.fib[layer]):
+                owner[rows] = f
+            a = np.zeros((len(O.fib[layer]), W))
+            a[np.unique(owner[R])] = 1.0
+            weights.append(a)
+        ref = sto.semi_implicit_step(O, c, tau, weights[0], weights[1])
+        assert colrel(got[R], ref[R]) < 3e-12
+    finally:
+        st.destroy()
+        P.destroy()
+        S.destroy()
