@@ -138,20 +138,25 @@ def test_twisted_full_size_sampled_mixed(full_twisted, precision):
         P.destroy()
 
 
-def test_twisted_full_size_to_T_mixed_within_1e6_of_fp64(full_twisted):
-    """The accuracy bar of the mixed paths on the full twisted bilayer (Ec = 6500, W = 128,
-    Strang tau = 5e-3 to T = 1, 200 steps): after T every wavepacket of the FP32 and BF16x3
-    paths is within 1e-6 relative L2 of the FP64 path (max over wavepackets), and the FP64
-    path keeps every mass to 1e-13 per step (unitary sub-flows, Thm 4.4's exact analogue)."""
+@pytest.mark.parametrize("W", [128, 1])
+def test_twisted_full_size_to_T_mixed_within_1e6_of_fp64(full_twisted, W):
+    """The accuracy bar of the mixed paths on the full twisted bilayer (Ec = 6500, Strang
+    tau = 5e-3 to T = 1, 200 steps), with the 128 wavepackets of the batch configuration and
+    with the single wavepacket of the single-state one: after T every wavepacket of the FP32 and
+    BF16x3 paths is within 1e-6 relative L2 of the FP64 path (max over wavepackets), and the
+    FP64 path keeps every mass to 1e-13 per step (unitary sub-flows, Thm 4.4's exact analogue)."""
     w, S, O = full_twisted
+    if W != w.W:
+        w = wl.twisted(W=W)
     nsteps = int(round(w.T / w.tau))
     assert nsteps == 200
     c0 = w.initial_state(O.mn)
+    assert c0.shape == (S.N, W)
     out = {}
     for prec in ("fp64", "mix_fp32", "mix_bf16x3"):
-        print(f"[case] twisted full size to T, {prec}", flush=True)
+        print(f"[case] twisted full size to T, W={W}, {prec}", flush=True)
         P = lsx.Plan(S, w.tau, "strang", 0.0, prec)
-        st = lsx.State(P, w.W)
+        st = lsx.State(P, W)
         try:
             st.upload(c0)
             st.step(nsteps)
