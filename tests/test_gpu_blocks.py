@@ -173,3 +173,33 @@ def test_example3_full_size_sampled_passes(precision):
         st.destroy()
         P.destroy()
         S.destroy()
+
+
+def test_example3_full_size_mixed_within_1e6_of_fp64():
+    """Example 3 at the benchmark's size (Ec = 1000, N = 74037, W = 128, Strang tau = 5e-3):
+    after 50 steps from the same random unit wavepackets, the FP32 and BF16x3 paths are within
+    1e-6 relative L2 of the FP64 path (max over wavepackets), and every mass stays within the
+    paths' bounds."""
+    S, O = build(1000.0)
+    c0 = wl.random_state(S.N, 128, seed=0)
+    out = {}
+    try:
+        for prec in ("fp64", "mix_fp32", "mix_bf16x3"):
+            print(f"[case] example3 full size 50 steps {prec}", flush=True)
+            P = lsx.Plan(S, 5e-3, "strang", 0.0, prec)
+            st = lsx.State(P, 128)
+            try:
+                st.upload(c0)
+                st.step(50)
+                out[prec] = st.download()
+                m = st.observables(lsx.OBS_MASS)["mass"]
+                assert np.abs(m - 1.0).max() < (1e-13 * 50 if prec == "fp64" else 1e-6), prec
+            finally:
+                st.destroy()
+                P.destroy()
+        for prec in ("mix_fp32", "mix_bf16x3"):
+            err = colrel(out[prec], out["fp64"])
+            print(f"  {prec}: rel L2 vs FP64 after 50 steps {err:.2e}", flush=True)
+            assert err <= 1e-6, (prec, err)
+    finally:
+        S.destroy()
